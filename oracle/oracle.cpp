@@ -1,0 +1,714 @@
+// TIMEST reference oracle -- TEST INFRASTRUCTURE ONLY (see timest_oracle.h).
+//
+// Plain single-threaded C++ written from the paper (arXiv 2507.20441):
+// every step is the definition or the algorithm written out, with no blocking,
+// fusion or reordering beyond what the paper states.  Exact integers
+// (unsigned __int128) throughout; overflow is reported, never wrapped.
+
+#include "timest_oracle.h"
+#include "graph_internal.h"
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <utility>
+#include <vector>
+
+typedef unsigned __int128 u128;
+
+static or_u128 to_or(u128 x) { return or_u128{(uint64_t)x, (uint64_t)(x >> 64)}; }
+static u128 from_or(or_u128 x) { return ((u128)x.hi << 64) | x.lo; }
+
+// Checked arithmetic: returns false on overflow.
+static bool add_ok(u128 a, u128 b, u128* r) { *r = a + b; return *r >= a; }
+static bool mul_ok(u128 a, u128 b, u128* r) { return !__builtin_mul_overflow(a, b, r); }
+
+static const int64_t kMaxSpan = (int64_t)1 << 62;
+
+// ------------------------------------------------------------------------
+// Graph construction (container in graph_internal.h).
+// ------------------------------------------------------------------------
+extern "C" int or_graph_create(const int32_t* src, const int32_t* dst, const int64_t* t,
+                               int64_t m, int32_t n, or_graph** out) {
+    if (!out || m < 0 || n < 0 || (m > 0 && (!src || !dst || !t)) || m >= ((int64_t)1 << 31))
+        return OR_EINVAL;
+    // First failing check wins, in this order: id range, self loop, span, duplicate.
+    for (int64_t i = 0; i < m; ++i)
+        if (src[i] < 0 || src[i] >= n || dst[i] < 0 || dst[i] >= n) return OR_EINVAL;
+    for (int64_t i = 0; i < m; ++i)
+        if (src[i] == dst[i]) return OR_ESELFLOOP;
+    int64_t tmin = 0, tmax = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        if (i == 0 || t[i] < tmin) tmin = t[i];
+        if (i == 0 || t[i] > tmax) tmax = t[i];
+    }
+    if (m > 0 && ((__int128)tmax - (__int128)tmin) >= kMaxSpan) return OR_ERANGE;
+
+    or_graph* g = new or_graph();
+    g->n = n;
+    g->m = m;
+    g->shift = tmin;
+    g->T = tmax - tmin;
+    g->e.resize(m);
+    for (int64_t i = 0; i < m; ++i) g->e[i] = OEdge{src[i], dst[i], t[i] - tmin};
+    std::sort(g->e.begin(), g->e.end(), [](const OEdge& a, const OEdge& b) {
+        if (a.t != b.t) return a.t < b.t;
+        if (a.u != b.u) return a.u < b.u;
+        return a.v < b.v;
+    });
+    // Each tuple (u,v,t) may appear only once (Sec. 1.1).
+    for (int64_t i = 1; i < m; ++i) {
+        const OEdge& a = g->e[i - 1];
+        const OEdge& b = g->e[i];
+        if (a.t == b.t && a.u == b.u && a.v == b.v) {
+            delete g;
+            return OR_EDUP;
+        }
+    }
+    g->out.resize(n);
+    g->in.resize(n);
+    for (int64_t id = 0; id < m; ++id) {
+        const OEdge& x = g->e[id];
+        g->out[x.u].push_back((int32_t)id);
+        g->in[x.v].push_back((int32_t)id);
+        g->el[{x.u, x.v}].push_back((int32_t)id);
+    }
+    *out = g;
+    return OR_OK;
+}
+
+extern "C" void or_graph_destroy(or_graph* g) { delete g; }
+
+extern "C" void or_graph_edges(const or_graph* g, int32_t* src, int32_t* dst, int64_t* t) {
+    for (int64_t i = 0; i < g->m; ++i) {
+        if (src) src[i] = g->e[i].u;
+        if (dst) dst[i] = g->e[i].v;
+        if (t) t[i] = g->e[i].t;
+    }
+}
+
+extern "C" int64_t or_graph_shift(const or_graph* g) { return g->shift; }
+
+extern "C" int64_t or_graph_list(const or_graph* g, int32_t vertex, int dir, int32_t* eids,
+                                 int64_t cap) {
+    if (vertex < 0 || vertex >= g->n) return -1;
+    const std::vector<int32_t>& L = dir > 0 ? g->out[vertex] : g->in[vertex];
+    for (int64_t i = 0; i < (int64_t)L.size() && i < cap; ++i) eids[i] = L[i];
+    return (int64_t)L.size();
+}
+
+// First position in an eid list (sorted by time) whose edge time is >= t0.
+static size_t first_at_or_after(const or_graph& g, const std::vector<int32_t>& L, int64_t t0) {
+    size_t lo = 0, hi = L.size();
+    while (lo < hi) {
+        size_t mid = (lo + hi) / 2;
+        if (g.e[L[mid]].t < t0) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------------
+// Motif and spanning tree (Def. "temporal motif", Def. "dependency list",
+// Def. "spanning tree of a temporal motif").
+// ------------------------------------------------------------------------
+static bool motif_ok(const or_motif* mo) {
+    if (!mo || mo->k < 2 || mo->k > 8 || mo->l < 1 || mo->l > 16) return false;
+    if (mo->delta < 1 || mo->delta >= kMaxSpan) return false;
+    for (int p = 0; p < mo->l; ++p) {
+        if (mo->src[p] < 0 || mo->src[p] >= mo->k || mo->dst[p] < 0 || mo->dst[p] >= mo->k) return false;
+        if (mo->src[p] == mo->dst[p]) return false;
+    }
+    // weakly connected: every vertex reachable from vertex 0 ignoring direction
+    bool seen[8] = {false};
+    seen[0] = true;
+    for (int pass = 0; pass < mo->k; ++pass)
+        for (int p = 0; p < mo->l; ++p)
+            if (seen[mo->src[p]] || seen[mo->dst[p]]) seen[mo->src[p]] = seen[mo->dst[p]] = true;
+    for (int x = 0; x < mo->k; ++x)
+        if (!seen[x]) return false;
+    return true;
+}
+
+// A set of k-1 motif edges is a spanning tree iff adding them one by one
+// never joins two already-connected vertices.
+static bool is_spanning_tree(const or_motif* mo, const int32_t* edges, int cnt) {
+    if (cnt != mo->k - 1) return false;
+    int comp[8];
+    for (int x = 0; x < mo->k; ++x) comp[x] = x;
+    for (int j = 0; j < cnt; ++j) {
+        int p = edges[j];
+        if (p < 0 || p >= mo->l) return false;
+        for (int j2 = 0; j2 < j; ++j2)
+            if (edges[j2] == p) return false;
+        int a = comp[mo->src[p]], b = comp[mo->dst[p]];
+        if (a == b) return false;
+        for (int x = 0; x < mo->k; ++x)
+            if (comp[x] == b) comp[x] = a;
+    }
+    return true;
+}
+
+static bool tree_ok(const or_motif* mo, const or_tree* tr) {
+    if (!tr || !is_spanning_tree(mo, tr->edge, tr->n_edges)) return false;
+    for (int j = 0; j < tr->n_edges; ++j)
+        if (tr->edge[j] == tr->center) return true;
+    return false;
+}
+
+struct Plan {
+    or_motif mo;
+    int center = -1;
+    bool in_tree[16] = {false};
+    int parent[16];
+    int attach[16];      // motif vertex shared with the parent edge
+    int lower[16];       // v_s: the endpoint of s further from the center
+    int alpha[16];       // +1: child leaves the attach vertex; -1: enters it
+    int beta[16];        // -1: child precedes its parent in pi ('<'); +1: follows ('>')
+    int height[16];
+    int H = 0;
+    std::vector<int> children[16];
+    std::vector<int> preorder;     // center first, then children subtree by subtree
+    std::vector<int> tree_sorted;  // tree edges by increasing pi index
+};
+
+static void attach_children(Plan& P, int s, int z) {
+    // Every tree edge other than s touching z hangs below s at z.
+    for (int p = 0; p < P.mo.l; ++p) {
+        if (!P.in_tree[p] || p == s || p == P.parent[s]) continue;
+        if (P.mo.src[p] != z && P.mo.dst[p] != z) continue;
+        if (P.parent[p] != -2) continue;  // already placed
+        P.parent[p] = s;
+        P.attach[p] = z;
+        P.lower[p] = (P.mo.src[p] == z) ? P.mo.dst[p] : P.mo.src[p];
+        P.alpha[p] = (P.mo.src[p] == z) ? +1 : -1;
+        P.beta[p] = (p < s) ? -1 : +1;
+        P.children[s].push_back(p);
+        attach_children(P, p, P.lower[p]);
+    }
+}
+
+static int compute_height(Plan& P, int s) {
+    int h = 0;
+    for (int c : P.children[s]) h = std::max(h, 1 + compute_height(P, c));
+    P.height[s] = h;
+    return h;
+}
+
+static void build_preorder(Plan& P, int s) {
+    P.preorder.push_back(s);
+    for (int c : P.children[s]) build_preorder(P, c);
+}
+
+static void make_plan(const or_motif* mo, const or_tree* tr, Plan& P) {
+    P.mo = *mo;
+    P.center = tr->center;
+    for (int p = 0; p < 16; ++p) {
+        P.parent[p] = -2;
+        P.attach[p] = P.lower[p] = -1;
+        P.alpha[p] = P.beta[p] = 0;
+        P.height[p] = 0;
+    }
+    for (int j = 0; j < tr->n_edges; ++j) P.in_tree[tr->edge[j]] = true;
+    int c = tr->center;
+    P.parent[c] = -1;
+    attach_children(P, c, mo->src[c]);
+    attach_children(P, c, mo->dst[c]);
+    for (int p = 0; p < 16; ++p) std::sort(P.children[p].begin(), P.children[p].end());
+    P.H = compute_height(P, c);
+    build_preorder(P, c);
+    for (int p = 0; p < mo->l; ++p)
+        if (P.in_tree[p]) P.tree_sorted.push_back(p);
+}
+
+// Default tree: the spanning tree with the smallest constraint looseness
+// (Alg. 8, read per tree vertex over pairs of incident tree edges as
+// |pi(e1) - pi(e2)| - 1), ties to the lexicographically smallest edge set;
+// center: the tree edge giving the smallest rooted height, ties to the
+// smallest pi index.
+extern "C" int or_default_tree(const or_motif* mo, or_tree* out) {
+    if (!motif_ok(mo) || !out) return OR_EINVAL;
+    int need = mo->k - 1;
+    long best = -1;
+    int best_set[8] = {0};
+    int cur[8];
+    // enumerate subsets of size need in lexicographic order
+    std::vector<int> idx(need);
+    for (int j = 0; j < need; ++j) idx[j] = j;
+    while (true) {
+        for (int j = 0; j < need; ++j) cur[j] = idx[j];
+        if (is_spanning_tree(mo, cur, need)) {
+            long loose = 0;
+            for (int x = 0; x < mo->k; ++x)
+                for (int a = 0; a < need; ++a)
+                    for (int b = a + 1; b < need; ++b) {
+                        int pa = cur[a], pb = cur[b];
+                        bool ia = mo->src[pa] == x || mo->dst[pa] == x;
+                        bool ib = mo->src[pb] == x || mo->dst[pb] == x;
+                        if (ia && ib) loose += std::abs(pa - pb) - 1;
+                    }
+            if (best < 0 || loose < best) {
+                best = loose;
+                for (int j = 0; j < need; ++j) best_set[j] = cur[j];
+            }
+        }
+        int j = need - 1;
+        while (j >= 0 && idx[j] == mo->l - need + j) --j;
+        if (j < 0) break;
+        ++idx[j];
+        for (int j2 = j + 1; j2 < need; ++j2) idx[j2] = idx[j2 - 1] + 1;
+    }
+    if (best < 0) return OR_EINVAL;
+    or_tree t;
+    std::memset(&t, 0, sizeof t);
+    t.n_edges = need;
+    for (int j = 0; j < need; ++j) t.edge[j] = best_set[j];
+    int best_h = 1 << 30;
+    for (int j = 0; j < need; ++j) {
+        t.center = best_set[j];
+        Plan P;
+        make_plan(mo, &t, P);
+        if (P.H < best_h) {
+            best_h = P.H;
+            out->center = best_set[j];
+        }
+    }
+    out->n_edges = need;
+    for (int j = 0; j < 8; ++j) out->edge[j] = j < need ? best_set[j] : 0;
+    return OR_OK;
+}
+
+// ------------------------------------------------------------------------
+// Preprocessing: Alg. 1 (intervals) and Alg. 2 (bottom-up s-weights).
+// ------------------------------------------------------------------------
+struct or_prep {
+    const or_graph* g = nullptr;
+    Plan P;
+    int64_t delta = 0;
+    int64_t q = 0;
+    std::vector<int64_t> lo, hi;       // eid range of G_i: edges with t in I_i
+    std::vector<int64_t> base;         // offset of G_i's block in the weight tables
+    std::vector<u128> w[16];           // w_i(s,e) at base[i] + (e - lo[i]); non-leaf s only
+    std::vector<u128> Wi;              // W_i
+    std::vector<u128> cumW;            // cumW[i] = sum_{i'<i} W_i', q+1 entries
+    std::vector<std::vector<u128>> root_cum;  // per interval: prefix of w_i(c,e) over G_i
+    u128 W = 0;
+};
+
+static bool in_interval(int64_t t, int64_t i, int64_t delta) {
+    return t >= i * delta && t < (i + 2) * delta;
+}
+
+// s-weight lookup: a leaf edge has weight 1 (Alg. 2 skips height 0).
+static u128 weight(const or_prep& R, int64_t i, int s, int32_t e) {
+    if (R.P.children[s].empty()) return 1;
+    return R.w[s][R.base[i] + (e - R.lo[i])];
+}
+
+// Candidate matches for child c of tree edge s, when s is matched to edge e
+// inside G_i (Claim "matching-edges-set"): the edges at the image g of the
+// attach vertex, leaving it (alpha=+) or entering it (alpha=-), whose time lies
+// in [t-delta, t] (beta '<') or [t, t+delta] (beta '>'), that lie in G_i, and
+// whose far endpoint is not the image o of s's other endpoint.  In eid order.
+static void candidates(const or_prep& R, int64_t i, int s, int32_t e, int c,
+                       std::vector<int32_t>& cand) {
+    const or_graph& G = *R.g;
+    const Plan& P = R.P;
+    const OEdge& E = G.e[e];
+    int32_t g = (P.attach[c] == P.mo.src[s]) ? E.u : E.v;
+    int32_t o = (P.attach[c] == P.mo.src[s]) ? E.v : E.u;
+    int64_t wlo = P.beta[c] < 0 ? E.t - R.delta : E.t;
+    int64_t whi = P.beta[c] < 0 ? E.t : E.t + R.delta;
+    const std::vector<int32_t>& L = P.alpha[c] > 0 ? G.out[g] : G.in[g];
+    cand.clear();
+    for (size_t x = first_at_or_after(G, L, wlo); x < L.size(); ++x) {
+        const OEdge& F = G.e[L[x]];
+        if (F.t > whi) break;
+        if (!in_interval(F.t, i, R.delta)) continue;
+        int32_t far = P.alpha[c] > 0 ? F.v : F.u;
+        if (far == o) continue;
+        cand.push_back(L[x]);
+    }
+}
+
+extern "C" int or_prepare(const or_graph* g, const or_motif* mo, const or_tree* tr, or_prep** out) {
+    if (!g || !out || !motif_ok(mo)) return OR_EINVAL;
+    or_tree def;
+    if (!tr) {
+        if (or_default_tree(mo, &def) != OR_OK) return OR_EINVAL;
+        tr = &def;
+    }
+    if (!tree_ok(mo, tr)) return OR_EINVAL;
+    or_prep* R = new or_prep();
+    R->g = g;
+    make_plan(mo, tr, R->P);
+    R->delta = mo->delta;
+    const int64_t d = R->delta;
+    // Alg. 1: q overlapping 2*delta intervals cover every match.
+    R->q = g->m > 0 ? g->T / d + 1 : 0;
+    R->lo.resize(R->q);
+    R->hi.resize(R->q);
+    R->base.resize(R->q + 1);
+    R->base[0] = 0;
+    for (int64_t i = 0; i < R->q; ++i) {
+        int64_t a = 0, b = g->m;  // first eid with t >= i*d
+        while (a < b) { int64_t mid = (a + b) / 2; if (g->e[mid].t < i * d) a = mid + 1; else b = mid; }
+        R->lo[i] = a;
+        b = g->m;                 // first eid with t >= (i+2)*d
+        while (a < b) { int64_t mid = (a + b) / 2; if (g->e[mid].t < (i + 2) * d) a = mid + 1; else b = mid; }
+        R->hi[i] = a;
+        R->base[i + 1] = R->base[i] + (R->hi[i] - R->lo[i]);
+    }
+    const Plan& P = R->P;
+    for (int p = 0; p < mo->l; ++p)
+        if (P.in_tree[p] && !P.children[p].empty()) R->w[p].assign(R->base[R->q], 0);
+
+    std::vector<int32_t> cand;
+    R->Wi.assign(R->q, 0);
+    for (int64_t i = 0; i < R->q; ++i) {                 // Alg. 1: each subgraph G_i
+        for (int h = 1; h <= P.H; ++h) {                 // Alg. 2: heights bottom-up
+            for (int64_t e = R->lo[i]; e < R->hi[i]; ++e) {
+                for (int s = 0; s < mo->l; ++s) {
+                    if (!P.in_tree[s] || P.height[s] != h) continue;
+                    // Claim "overall-num-matches": product over the dependency
+                    // list of the summed child weights over the candidate list.
+                    u128 prod = 1;
+                    for (int c : P.children[s]) {
+                        candidates(*R, i, s, (int32_t)e, c, cand);
+                        u128 sum = 0;
+                        for (int32_t f : cand)
+                            if (!add_ok(sum, weight(*R, i, c, f), &sum)) { delete R; return OR_EOVERFLOW; }
+                        if (!mul_ok(prod, sum, &prod)) { delete R; return OR_EOVERFLOW; }
+                    }
+                    R->w[s][R->base[i] + (e - R->lo[i])] = prod;
+                }
+            }
+        }
+        // Claim "num-matches-entire-tree": W_i sums the center weights.
+        u128 Wi = 0;
+        for (int64_t e = R->lo[i]; e < R->hi[i]; ++e)
+            if (!add_ok(Wi, weight(*R, i, P.center, (int32_t)e), &Wi)) { delete R; return OR_EOVERFLOW; }
+        R->Wi[i] = Wi;
+    }
+    R->cumW.assign(R->q + 1, 0);
+    for (int64_t i = 0; i < R->q; ++i)
+        if (!add_ok(R->cumW[i], R->Wi[i], &R->cumW[i + 1])) { delete R; return OR_EOVERFLOW; }
+    R->W = R->cumW[R->q];
+    R->root_cum.resize(R->q);
+    for (int64_t i = 0; i < R->q; ++i) {
+        std::vector<u128>& rc = R->root_cum[i];
+        rc.assign(R->hi[i] - R->lo[i] + 1, 0);
+        for (int64_t e = R->lo[i]; e < R->hi[i]; ++e)
+            rc[e - R->lo[i] + 1] = rc[e - R->lo[i]] + weight(*R, i, P.center, (int32_t)e);
+    }
+    *out = R;
+    return OR_OK;
+}
+
+extern "C" void or_prep_destroy(or_prep* p) { delete p; }
+extern "C" or_u128 or_prep_W(const or_prep* p) { return to_or(p->W); }
+extern "C" int64_t or_prep_q(const or_prep* p) { return p->q; }
+
+extern "C" void or_prep_interval_weights(const or_prep* p, or_u128* wi) {
+    for (int64_t i = 0; i < p->q; ++i) wi[i] = to_or(p->Wi[i]);
+}
+
+extern "C" int or_prep_weights(const or_prep* p, int32_t s, int slot, or_u128* out) {
+    if (s < 0 || s >= p->P.mo.l || !p->P.in_tree[s] || slot < 0 || slot > 1) return OR_EINVAL;
+    const or_graph& G = *p->g;
+    for (int64_t e = 0; e < G.m; ++e) {
+        int64_t i = G.e[e].t / p->delta - slot;
+        if (i < 0 || i >= p->q) { out[e] = to_or(0); continue; }
+        out[e] = to_or(weight(*p, i, s, (int32_t)e));
+    }
+    return OR_OK;
+}
+
+// ------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
+// multiply-xor S-box on a 4x32 counter with a 2x32 key bumped by the Weyl
+// constants between rounds.
+// ------------------------------------------------------------------------
+extern "C" void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += W0; k1 += W1; }
+        uint64_t p0 = (uint64_t)M0 * c0;
+        uint64_t p1 = (uint64_t)M1 * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// floor(X * n / 2^128) by schoolbook multiplication in 64-bit limbs.
+static u128 scale_to_range(u128 X, u128 n) {
+    uint64_t x0 = (uint64_t)X, x1 = (uint64_t)(X >> 64);
+    uint64_t n0 = (uint64_t)n, n1 = (uint64_t)(n >> 64);
+    u128 p00 = (u128)x0 * n0, p01 = (u128)x0 * n1, p10 = (u128)x1 * n0, p11 = (u128)x1 * n1;
+    u128 mid = (p00 >> 64) + (uint64_t)p01 + (uint64_t)p10;
+    return p11 + (p01 >> 64) + (p10 >> 64) + (mid >> 64);
+}
+
+static u128 draw(uint64_t seed, uint64_t j, uint32_t d, u128 n) {
+    uint32_t ctr[4] = {(uint32_t)j, (uint32_t)(j >> 32), d, 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    or_philox4x32_10(ctr, key, x);
+    u128 X = (u128)x[0] | ((u128)x[1] << 32) | ((u128)x[2] << 64) | ((u128)x[3] << 96);
+    return scale_to_range(X, n);
+}
+
+extern "C" or_u128 or_draw(uint64_t seed, uint64_t j, uint32_t d, or_u128 n) {
+    return to_or(draw(seed, j, d, from_or(n)));
+}
+
+// ------------------------------------------------------------------------
+// Alg. 4 (ValidateAndDeriveCnt) and Alg. 5 (DeriveCnt).
+// ------------------------------------------------------------------------
+
+// ListCount: number of chains (x_1, ..., x_r), x_j in lists[j], with
+// after < t(x_1) < t(x_2) < ... < t(x_r) <= upto.  Dynamic programming over the
+// lists with a pointer traversal: cnt_j(x) = sum of cnt_{j-1}(y) over y with
+// t(y) < t(x).  Returns false on overflow.
+static bool list_count(const or_graph& G, const std::vector<std::vector<int32_t>>& lists,
+                       size_t first, int64_t after, int64_t upto, u128* result) {
+    if (first == lists.size()) { *result = 1; return true; }
+    std::vector<int64_t> pt, ct;
+    std::vector<u128> pc, cc;
+    for (size_t j = first; j < lists.size(); ++j) {
+        ct.clear();
+        cc.clear();
+        for (int32_t x : lists[j]) {
+            int64_t tx = G.e[x].t;
+            if (tx > after && tx <= upto) ct.push_back(tx);
+        }
+        cc.assign(ct.size(), 0);
+        if (j == first) {
+            for (size_t a = 0; a < ct.size(); ++a) cc[a] = 1;
+        } else {
+            u128 acc = 0;
+            size_t y = 0;
+            for (size_t a = 0; a < ct.size(); ++a) {
+                while (y < pt.size() && pt[y] < ct[a]) {
+                    if (!add_ok(acc, pc[y], &acc)) return false;
+                    ++y;
+                }
+                cc[a] = acc;
+            }
+        }
+        pt.swap(ct);
+        pc.swap(cc);
+    }
+    u128 total = 0;
+    for (u128 v : pc)
+        if (!add_ok(total, v, &total)) return false;
+    *result = total;
+    return true;
+}
+
+// Validate the image of the tree edges (Alg. 4: 1-1 vertex map, delta range,
+// edge order; the first failing check is the recorded cause), then count the
+// motif instances that extend it (Alg. 5).
+static int validate_and_derive(const or_prep& R, const int32_t* img_e /* indexed by motif edge */,
+                               uint32_t* status, uint32_t* n_phi, u128* m_phi) {
+    const or_graph& G = *R.g;
+    const Plan& P = R.P;
+    const or_motif& M = P.mo;
+    *status = 0; *n_phi = 0; *m_phi = 0;
+    int32_t img_v[8];
+    for (int x = 0; x < M.k; ++x) img_v[x] = -1;
+    for (int p : P.tree_sorted) {
+        img_v[M.src[p]] = G.e[img_e[p]].u;
+        img_v[M.dst[p]] = G.e[img_e[p]].v;
+    }
+    for (int x = 0; x < M.k; ++x)
+        for (int y = x + 1; y < M.k; ++y)
+            if (img_v[x] == img_v[y]) { *status = 1; return OR_OK; }
+    int64_t tmin = 0, tmax = 0;
+    bool firstt = true;
+    for (int p : P.tree_sorted) {
+        int64_t t = G.e[img_e[p]].t;
+        if (firstt || t < tmin) tmin = t;
+        if (firstt || t > tmax) tmax = t;
+        firstt = false;
+    }
+    if (tmax - tmin > R.delta) { *status = 2; return OR_OK; }
+    for (size_t a = 1; a < P.tree_sorted.size(); ++a)
+        if (!(G.e[img_e[P.tree_sorted[a - 1]]].t < G.e[img_e[P.tree_sorted[a]]].t)) {
+            *status = 3;
+            return OR_OK;
+        }
+    // N_phi: the number of intervals that contain every tree edge.  Only the
+    // intervals starting at or before t_min and after t_min - 2*delta can.
+    uint32_t cnt = 0;
+    for (int64_t i = std::max<int64_t>(0, tmin / R.delta - 1); i <= tmin / R.delta + 1 && i < R.q; ++i)
+        if (i * R.delta <= tmin && tmax < (i + 2) * R.delta) ++cnt;
+    *n_phi = cnt;
+    // Alg. 5: for each non-tree motif edge, the edges of G that can match it
+    // (binary search on the multi-edge list to the times any completion can
+    // use); tree edges are fixed single-element lists.  Lists are numbered in
+    // pi order; ListCount counts strictly increasing chains.  The delta window
+    // is enforced by fixing the first edge of the chain.
+    std::vector<std::vector<int32_t>> lists(M.l);
+    for (int p = 0; p < M.l; ++p) {
+        if (P.in_tree[p]) { lists[p].push_back(img_e[p]); continue; }
+        auto it = G.el.find({img_v[M.src[p]], img_v[M.dst[p]]});
+        if (it == G.el.end()) return OR_OK;  // no edge can match p: M_phi = 0
+        const std::vector<int32_t>& L = it->second;
+        for (size_t x = first_at_or_after(G, L, tmax - R.delta); x < L.size(); ++x) {
+            if (G.e[L[x]].t > tmin + R.delta) break;
+            lists[p].push_back(L[x]);
+        }
+    }
+    u128 total = 0;
+    for (int32_t f : lists[0]) {
+        u128 c;
+        if (!list_count(G, lists, 1, G.e[f].t, G.e[f].t + R.delta, &c)) return OR_EOVERFLOW;
+        if (!add_ok(total, c, &total)) return OR_EOVERFLOW;
+    }
+    *m_phi = total;
+    return OR_OK;
+}
+
+extern "C" int or_derive_cnt(const or_prep* p, const int32_t* eids, or_u128* m_phi) {
+    const Plan& P = p->P;
+    int32_t img_e[16];
+    for (int x = 0; x < 16; ++x) img_e[x] = -1;
+    int32_t img_v[8];
+    for (int x = 0; x < 8; ++x) img_v[x] = -1;
+    for (size_t a = 0; a < P.tree_sorted.size(); ++a) {
+        if (eids[a] < 0 || eids[a] >= p->g->m) return OR_EINVAL;
+        int q = P.tree_sorted[a];
+        img_e[q] = eids[a];
+        // the tree edges must agree on the image of every shared vertex
+        const int32_t ends[2] = {p->g->e[eids[a]].u, p->g->e[eids[a]].v};
+        const int vs[2] = {P.mo.src[q], P.mo.dst[q]};
+        for (int b = 0; b < 2; ++b) {
+            if (img_v[vs[b]] >= 0 && img_v[vs[b]] != ends[b]) return OR_EINVAL;
+            img_v[vs[b]] = ends[b];
+        }
+    }
+    uint32_t st, np;
+    u128 mp;
+    int rc = validate_and_derive(*p, img_e, &st, &np, &mp);
+    if (rc != OR_OK) return rc;
+    if (st != 0) return OR_EINVAL;
+    *m_phi = to_or(mp);
+    return OR_OK;
+}
+
+// ------------------------------------------------------------------------
+// Alg. 3 (SampleSubg) and Alg. 6 (Estimate).
+// ------------------------------------------------------------------------
+
+// Inverse CDF: the unique index x with sum(w[0..x)) <= r < sum(w[0..x]).
+static size_t pick(const std::vector<u128>& wts, u128 r) {
+    u128 cum = 0;
+    for (size_t x = 0; x < wts.size(); ++x) {
+        if (r < cum + wts[x]) return x;
+        cum += wts[x];
+    }
+    return wts.size();  // unreachable when r < total
+}
+
+extern "C" int or_sample(const or_prep* p, uint64_t seed, uint64_t j0, uint64_t count,
+                         uint64_t k_total, or_result* res, or_rec* recs) {
+    if (!p || !res) return OR_EINVAL;
+    const or_prep& R = *p;
+    const Plan& P = R.P;
+    std::memset(res, 0, sizeof *res);
+    res->W = to_or(R.W);
+    res->k = k_total;
+    res->q = R.q;
+    if (R.W == 0) {
+        res->flags |= 1u;
+        res->estimate = 0.0;
+        for (uint64_t a = 0; recs && a < count; ++a) {
+            std::memset(&recs[a], 0, sizeof(or_rec));
+            recs[a].status = 4;  // not drawn: there is nothing to sample
+            for (int x = 0; x < 8; ++x) recs[a].eid[x] = -1;
+        }
+        return OR_OK;
+    }
+    u128 acc2 = 0, acc2_sq = 0;
+    std::vector<int32_t> cand;
+    std::vector<u128> wts;
+    for (uint64_t a = 0; a < count; ++a) {
+        uint64_t j = j0 + a;
+        int32_t img_e[16];
+        for (int x = 0; x < 16; ++x) img_e[x] = -1;
+        // Alg. 6: pick G_i with probability W_i / W; Alg. 3: pick the center
+        // edge with probability w_{c,e} / W_i -- one draw, split in two stages.
+        u128 r0 = draw(seed, j, 0, R.W);
+        int64_t i = (int64_t)(std::upper_bound(R.cumW.begin(), R.cumW.end(), r0) - R.cumW.begin()) - 1;
+        u128 r = r0 - R.cumW[i];
+        const std::vector<u128>& rc = R.root_cum[i];
+        int64_t x = (int64_t)(std::upper_bound(rc.begin(), rc.end(), r) - rc.begin()) - 1;
+        img_e[P.center] = (int32_t)(R.lo[i] + x);
+        // Alg. 3: top-down, each child with probability proportional to its
+        // weight over its candidate list.
+        uint32_t d = 1;
+        for (size_t step = 1; step < P.preorder.size(); ++step) {
+            int c = P.preorder[step];
+            int s = P.parent[c];
+            candidates(R, i, s, img_e[s], c, cand);
+            wts.clear();
+            u128 Wx = 0;
+            for (int32_t f : cand) {
+                wts.push_back(weight(R, i, c, f));
+                Wx += wts.back();
+            }
+            // A child of an edge with positive weight always has positive
+            // candidate weight (the parent's weight is their product).
+            if (Wx == 0) return OR_EINVAL;
+            u128 rr = draw(seed, j, d++, Wx);
+            img_e[c] = cand[pick(wts, rr)];
+        }
+        uint32_t status, n_phi;
+        u128 m_phi;
+        int rcode = validate_and_derive(R, img_e, &status, &n_phi, &m_phi);
+        if (rcode != OR_OK) return rcode;
+        if (status == 0) {
+            ++res->n_valid;
+            if (m_phi != 0) ++res->n_nonzero;
+            // 2 * M_phi / N_phi with N_phi in {1, 2} stays an integer.
+            u128 term;
+            if (!mul_ok(m_phi, (u128)(2 / n_phi), &term)) return OR_EOVERFLOW;
+            if (!add_ok(acc2, term, &acc2)) return OR_EOVERFLOW;
+            u128 sq;
+            if (!mul_ok(term, term, &sq) || !add_ok(acc2_sq, sq, &acc2_sq)) {
+                acc2_sq = ~(u128)0;
+                res->flags |= 2u;
+            }
+        } else if (status == 1) {
+            ++res->n_bad_vertex;
+        } else if (status == 2) {
+            ++res->n_bad_delta;
+        } else {
+            ++res->n_bad_order;
+        }
+        if (recs) {
+            or_rec& out = recs[a];
+            std::memset(&out, 0, sizeof out);
+            out.interval = (uint32_t)i;
+            out.status = status;
+            out.n_phi = status == 0 ? n_phi : 0;
+            for (int y = 0; y < 8; ++y) out.eid[y] = -1;
+            for (size_t y = 0; y < P.tree_sorted.size(); ++y) out.eid[y] = img_e[P.tree_sorted[y]];
+            out.m_phi = to_or(status == 0 ? m_phi : 0);
+        }
+    }
+    res->acc2 = to_or(acc2);
+    res->acc2_sq = to_or(acc2_sq);
+    // Alg. 6: C^ = (cnt / k) * W with cnt = acc2 / 2.
+    res->estimate = k_total ? (double)R.W * ((double)acc2 / (2.0 * (double)k_total)) : 0.0;
+    return OR_OK;
+}

@@ -1,0 +1,198 @@
+"""Seeded synthetic temporal graphs and motifs shaped like TIMEST's workloads.
+
+The paper evaluates on wiki-talk, stackoverflow, bitcoin and reddit-reply
+(Tab. "dataset"): power-law degree distributions, bursty activity, spans of
+years, delta of hours to weeks.  Those datasets are not available here, so
+these seeded generators stand in for them at matching scale and shape.  This
+module only draws inputs; it holds none of the estimator's arithmetic and is
+the one piece of code shared by the GPU path's tests and the oracle's.
+
+Graph recipe (per config):
+  * Chung-Lu: vertex r has weight (r+1)^(-1/(gamma-1)); ids are a seeded
+    permutation; source and destination are drawn independently in
+    proportion to weight; self loops are redrawn.
+  * Times: uniform integers, or bursty per-source renewal processes with
+    Pareto(alpha=1.5) gaps (mean span S per source, wrapped modulo S).
+  * Duplicate (u, v, t) tuples get a fresh time until every tuple is unique
+    (Sec. 1.1: each tuple appears once).
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Motifs as ordered edge lists: edge p is the p-th edge in time (the order pi
+# of Def. "temporal motif").  The paper's own motif figures are not recoverable,
+# so these are the shapes the workloads name.
+MOTIFS = {
+    # a->b, b->c, c->a
+    "3cycle": ((0, 1), (1, 2), (2, 0)),
+    # a->b, b->c, c->d, d->a
+    "4cycle": ((0, 1), (1, 2), (2, 3), (3, 0)),
+    # 4-leaf out-star a->b < a->c < a->d < a->e
+    "4star": ((0, 1), (0, 2), (0, 3), (0, 4)),
+    # fan-out then fan-in: a->b < a->c < a->d < b->e < c->e < d->e
+    "scatter_gather": ((0, 1), (0, 2), (0, 3), (1, 4), (2, 4), (3, 4)),
+    # a->b->c->d->e->f
+    "6chain": ((0, 1), (1, 2), (2, 3), (3, 4), (4, 5)),
+}
+
+
+def motif_vertices(edges) -> int:
+    return 1 + max(max(e) for e in edges)
+
+
+@dataclass
+class TemporalGraph:
+    src: np.ndarray          # int32
+    dst: np.ndarray          # int32
+    t: np.ndarray            # int64
+    n: int
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def m(self) -> int:
+        return int(self.src.shape[0])
+
+
+def _chung_lu_pairs(rng, n, m, gamma):
+    w = (np.arange(n, dtype=np.float64) + 1.0) ** (-1.0 / (gamma - 1.0))
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    ids = rng.permutation(n).astype(np.int32)
+
+    def draw(size):
+        r = np.searchsorted(cdf, rng.random(size), side="right")
+        return ids[np.minimum(r, n - 1)]
+
+    u = draw(m)
+    v = draw(m)
+    bad = np.nonzero(u == v)[0]
+    while bad.size:
+        u[bad] = draw(bad.size)
+        v[bad] = draw(bad.size)
+        bad = bad[u[bad] == v[bad]]
+    return u, v
+
+
+def _bursty_times(rng, u, span, alpha=1.5):
+    """Per-source renewal process: start s_u ~ U[0, span), gaps x_u * U^(-1/alpha)
+    with x_u = span / (3 d_u) (mean gap 3 x_u), times wrapped modulo span."""
+    m = u.shape[0]
+    order = np.argsort(u, kind="stable")
+    us = u[order]
+    starts = np.flatnonzero(np.r_[True, us[1:] != us[:-1]])
+    counts = np.diff(np.r_[starts, m])
+    group = np.repeat(np.arange(starts.size), counts)
+    x = span / (3.0 * counts.astype(np.float64))
+    gaps = x[group] * rng.random(m) ** (-1.0 / alpha)
+    c = np.cumsum(gaps)
+    before = np.r_[0.0, c[starts[1:] - 1]]
+    within = c - before[group]
+    s0 = rng.random(starts.size) * span
+    ts = np.floor(s0[group] + within) % span
+    t = np.empty(m, np.int64)
+    t[order] = ts.astype(np.int64)
+    return t
+
+
+def _dedup(rng, u, v, t, redraw):
+    """Give a fresh time to every repeated (u, v, t) until all are unique."""
+    while True:
+        key_order = np.lexsort((t, v, u))
+        us, vs, ts = u[key_order], v[key_order], t[key_order]
+        dup = np.nonzero((us[1:] == us[:-1]) & (vs[1:] == vs[:-1]) & (ts[1:] == ts[:-1]))[0] + 1
+        if dup.size == 0:
+            return t
+        idx = key_order[dup]
+        t[idx] = redraw(idx.size)
+
+
+def chung_lu_graph(n, m, gamma, seed, times="uniform", tmax=100_000, span=10_000_000,
+                   reciprocal=0, recip_gap=600, name="") -> TemporalGraph:
+    rng = np.random.default_rng(seed)
+    base = m - reciprocal
+    u, v = _chung_lu_pairs(rng, n, base, gamma)
+    if times == "uniform":
+        t = rng.integers(0, tmax + 1, size=base, dtype=np.int64)
+        redraw = lambda k: rng.integers(0, tmax + 1, size=k, dtype=np.int64)  # noqa: E731
+    elif times == "bursty":
+        t = _bursty_times(rng, u, float(span))
+        redraw = lambda k: rng.integers(0, span, size=k, dtype=np.int64)  # noqa: E731
+    else:
+        raise ValueError(times)
+    t = _dedup(rng, u, v, t, redraw)
+    if reciprocal:
+        pick = rng.choice(base, size=reciprocal, replace=False)
+        ru, rv = v[pick].copy(), u[pick].copy()
+        rt = t[pick] + rng.integers(1, recip_gap + 1, size=reciprocal, dtype=np.int64)
+        u = np.concatenate([u, ru])
+        v = np.concatenate([v, rv])
+        t = _dedup(rng, u, v, np.concatenate([t, rt]), redraw)
+    meta = dict(n=n, m=m, gamma=gamma, seed=seed, times=times, tmax=tmax, span=span,
+                reciprocal=reciprocal)
+    return TemporalGraph(u.astype(np.int32), v.astype(np.int32), t.astype(np.int64), n, name, meta)
+
+
+# ---------------------------------------------------------------------------
+# The named workloads.
+# ---------------------------------------------------------------------------
+def tiny_graph() -> TemporalGraph:
+    """1,000 vertices, 20,000 edges, Chung-Lu gamma=2.3, times U{0..100000}."""
+    return chung_lu_graph(1000, 20_000, 2.3, seed=101, times="uniform", tmax=100_000, name="tiny")
+
+
+TINY = dict(motifs=(("3cycle", 1000),), k=100_000, seed=1)
+
+
+def medium_graph() -> TemporalGraph:
+    """100,000 vertices, 2,000,000 edges, gamma=2.1, bursty times over 1e7 s."""
+    return chung_lu_graph(100_000, 2_000_000, 2.1, seed=102, times="bursty", span=10_000_000,
+                          name="medium")
+
+
+MEDIUM = dict(motifs=(("4cycle", 3600), ("4star", 3600)), k=10_000_000, seed=1)
+
+
+def large_graph() -> TemporalGraph:
+    """2,000,000 vertices, 100,000,000 edges (90M Chung-Lu gamma=2.0 plus 10M
+    reciprocated at +U{1..600} s), bursty times over 3e7 s."""
+    return chung_lu_graph(2_000_000, 100_000_000, 2.0, seed=103, times="bursty",
+                          span=30_000_000, reciprocal=10_000_000, name="large")
+
+
+LARGE = dict(motifs=(("scatter_gather", 86400), ("6chain", 86400)), k=100_000_000, seed=1)
+
+
+def small_graph(m, seed, n=None, gamma=2.1, times="bursty", span=None) -> TemporalGraph:
+    """A graph of the medium shape scaled down to m edges (tests)."""
+    n = n if n is not None else max(50, m // 20)
+    span = span if span is not None else max(1000, 5 * m)
+    return chung_lu_graph(n, m, gamma, seed=seed, times=times, span=span, tmax=span,
+                          name=f"small{m}")
+
+
+def batched_jobs(n_jobs=64, seed=1000, m_lo=1e4, m_hi=5e6):
+    """The batched workload: graph sizes log-uniform in [1e4, 5e6] edges (medium
+    shape, span 1e7 s), motifs uniform over MOTIFS, delta log-uniform in
+    [600, 86400], sample budgets log-uniform in [1e5, 1e7]."""
+    rng = np.random.default_rng(seed)
+    names = list(MOTIFS)
+    jobs = []
+    for j in range(n_jobs):
+        m = int(round(10 ** rng.uniform(np.log10(m_lo), np.log10(m_hi))))
+        jobs.append(dict(
+            graph_seed=seed + j,
+            m=m,
+            n=max(50, m // 20),
+            motif=names[int(rng.integers(len(names)))],
+            delta=int(round(10 ** rng.uniform(np.log10(600), np.log10(86400)))),
+            k=int(round(10 ** rng.uniform(5, 7))),
+            seed=int(rng.integers(1, 2**63 - 1)),
+        ))
+    return jobs
+
+
+def batched_graph(job) -> TemporalGraph:
+    return chung_lu_graph(job["n"], job["m"], 2.1, seed=job["graph_seed"], times="bursty",
+                          span=10_000_000, name=f"job{job['graph_seed']}")
