@@ -1,0 +1,212 @@
+/*
+ * timest.h -- C ABI of the MI355X (gfx950) TIMEST hot path.
+ *
+ * TIMEST (arXiv 2507.20441) estimates the number of temporal motif matches
+ * in a temporal multigraph by sampling weighted temporal spanning-tree
+ * matches.  This library runs its data-parallel hot path on one AMD Instinct
+ * MI355X: CSR build of the time-sorted edge lists, the bottom-up spanning-tree
+ * weights, the weighted tree sampler, validation and completion counting of
+ * each sample, and the reduction into the estimate.  Every stage is a HIP
+ * kernel written for CDNA4; the host code here only plans and launches.
+ *
+ * Conventions shared by every call:
+ *   - Return value: TM_OK (0) or a negative TM_E* code; tm_last_error() then
+ *     holds a message for the calling thread.  A failed call leaves its
+ *     output handles untouched and the library usable.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *     on it; calls that return values to host memory synchronise it first.
+ *   - Device memory is allocated by the library (hipMalloc) and owned by the
+ *     handle that holds it until its destroy call.
+ *   - Sizes: at most 2^31 - 1 edges and 2^31 - 1 vertices; the time span
+ *     max(t) - min(t) and delta must stay below 2^62, and the number of bits
+ *     of (n - 1) plus the number of bits of the time span must not exceed 64
+ *     (the per-vertex neighbour lists are searched on a packed 64-bit key).
+ */
+#ifndef TIMEST_H
+#define TIMEST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TM_MAX_K 8   /* motif vertices */
+#define TM_MAX_L 16  /* motif edges */
+
+enum tm_error {
+    TM_OK = 0,
+    TM_EINVAL = -1,      /* NULL or malformed argument, vertex id out of range,
+                            bad motif or tree */
+    TM_ESELFLOOP = -2,   /* an edge (u, u, t) */
+    TM_EDUP = -3,        /* a tuple (u, v, t) given twice (Sec. 1.1 forbids it) */
+    TM_EOVERFLOW = -4,   /* a weight, W or a completion count reaches 2^128 */
+    TM_ERANGE = -5,      /* time span or delta too large for the limits above */
+    TM_ENOMEM = -6,      /* device allocation failed */
+    TM_EDEVICE = -7      /* HIP runtime error */
+};
+
+enum tm_ptr_kind { TM_PTR_HOST = 0, TM_PTR_DEVICE = 1 };
+
+/* result flags */
+#define TM_F_W_ZERO 1u        /* no partial match exists: estimate is 0 */
+#define TM_F_SQ_SATURATED 2u  /* acc2_sq reached 2^128 - 1 and stopped */
+#define TM_F_WIDE 4u          /* weights needed 128 bits (else 64) */
+
+typedef struct { uint64_t lo, hi; } tm_u128;
+
+typedef struct tm_graph tm_graph;
+typedef struct tm_weights tm_weights;
+
+/* Temporal motif M = (H, pi, delta) (Def. "temporal motif"): l directed edges
+ * src[p] -> dst[p] over vertices 0..k-1, listed in pi order (edge p must be
+ * the p-th in time).  2 <= k <= 8, 1 <= l <= 16, no self loop, weakly
+ * connected, 1 <= delta < 2^62.  Parallel motif edges are allowed. */
+typedef struct {
+    int32_t k;
+    int32_t l;
+    int32_t src[TM_MAX_L];
+    int32_t dst[TM_MAX_L];
+    int64_t delta;
+} tm_motif;
+
+/* Spanning tree S of the motif (Def. "spanning tree of a temporal motif"):
+ * k - 1 distinct motif edge indices forming a tree of the underlying
+ * undirected graph, and the center (root) edge, one of them (Sec. 4.1). */
+typedef struct {
+    int32_t n_edges;
+    int32_t edge[8];
+    int32_t center;
+} tm_tree;
+
+/* Outcome of an estimate (Alg. 6).  acc2 is the exact sum over samples of
+ * 2 * M_phi / N_phi (M_phi: motif matches completing the sampled tree match,
+ * N_phi in {1, 2}: intervals holding it); estimate = W * acc2 / (2 k), each
+ * 128-bit integer converted to double with round-to-nearest-even.
+ * std_error = (W / 2) * sd(2 M_phi / N_phi) / sqrt(k). */
+typedef struct {
+    double estimate;
+    double std_error;
+    tm_u128 W;           /* total sampling weight (Claim "num-matches-entire-tree") */
+    tm_u128 acc2;
+    tm_u128 acc2_sq;     /* sum of squares of the same terms */
+    uint64_t k;
+    uint64_t n_valid;     /* samples passing Alg. 4 */
+    uint64_t n_bad_vertex;/* vertex map not 1-1 */
+    uint64_t n_bad_delta; /* tree edges not within delta */
+    uint64_t n_bad_order; /* tree edges not in pi order */
+    uint64_t n_nonzero;   /* valid samples with M_phi > 0 */
+    int64_t q;            /* number of 2*delta intervals */
+    uint32_t flags;       /* TM_F_* */
+    int32_t status;       /* TM_OK, or the error of this job in batched calls */
+} tm_result;
+
+/* One per sample: the interval drawn, the validation outcome (0 valid,
+ * 1 vertex map not 1-1, 2 outside delta, 3 out of order, 4 not drawn because
+ * W = 0), N_phi and M_phi (0 unless valid), and the eids matched to the tree
+ * edges listed in increasing pi index (-1 past the last tree edge).  An eid
+ * is the rank of an edge under the key (time, src, dst). */
+typedef struct {
+    uint32_t interval;
+    uint32_t status;
+    uint32_t n_phi;
+    uint32_t pad;
+    int32_t eid[8];
+    tm_u128 m_phi;
+} tm_sample_rec;
+
+/* Message of a TM_E* code; static storage. */
+const char* tm_strerror(int code);
+/* Detail of the last failed call on this thread; static thread-local storage. */
+const char* tm_last_error(void);
+
+/* Build the graph (Sec. 4, storage): validate the m edges (src[i], dst[i],
+ * t[i]), shift times so the earliest is 0, order edges by (time, src, dst)
+ * (that rank is the eid), and build per-vertex out- and in-lists in time
+ * order plus the same lists ordered by (neighbour, time), which hold every
+ * multi-edge list El_{u,v} (Def. "multi-edge list") as a contiguous run.
+ * src, dst, t: m entries each, host or device memory per ptr_kind; the caller
+ * keeps ownership and may free them once the call returns.  n: vertex count,
+ * ids in [0, n).  m = 0 gives an empty graph.  Errors: TM_EINVAL (NULL,
+ * m or n out of range, id out of range), TM_ESELFLOOP, TM_ERANGE, TM_EDUP --
+ * the first failing check in that order -- TM_ENOMEM, TM_EDEVICE. */
+int tm_graph_create(const int32_t* src, const int32_t* dst, const int64_t* t, int64_t m,
+                    int32_t n, int ptr_kind, void* stream, tm_graph** out);
+
+/* Frees the graph's device memory.  Weights built on it must be destroyed
+ * first.  NULL is ignored. */
+void tm_graph_destroy(tm_graph* g);
+
+/* Sizes of a graph; any output pointer may be NULL. */
+int tm_graph_info(const tm_graph* g, int64_t* m, int32_t* n, int64_t* t_shift,
+                  int64_t* t_span, uint64_t* device_bytes);
+
+/* Arrays of the built graph, copied to host memory for inspection. */
+enum tm_graph_array {
+    TM_ARR_SRC = 0,      /* int32[m]  source by eid */
+    TM_ARR_DST = 1,      /* int32[m]  destination by eid */
+    TM_ARR_T = 2,        /* int64[m]  shifted time by eid */
+    TM_ARR_OUT_OFF = 3,  /* int32[n+1] offsets of each vertex's out-lists */
+    TM_ARR_IN_OFF = 4,   /* int32[n+1] offsets of each vertex's in-lists */
+    TM_ARR_OUT_EID = 5,  /* int32[m]  out-lists in time order (eids) */
+    TM_ARR_IN_EID = 6,   /* int32[m]  in-lists in time order (eids) */
+    TM_ARR_OUTN_EID = 7, /* int32[m]  out-lists in (destination, time) order */
+    TM_ARR_INN_EID = 8   /* int32[m]  in-lists in (source, time) order */
+};
+int tm_graph_export(const tm_graph* g, int which, void* host_out, void* stream);
+
+/* Default spanning tree and center: the tree with the smallest constraint
+ * looseness (Alg. 8, taken per tree vertex over pairs of incident tree edges
+ * as |pi(e1) - pi(e2)| - 1), ties to the lexicographically smallest edge set;
+ * the center minimises the rooted height, ties to the smallest pi index. */
+int tm_default_tree(const tm_motif* mo, tm_tree* out);
+
+/* Preprocess (Alg. 1, Alg. 2): for every edge e, every non-leaf tree edge s
+ * and both 2*delta intervals I_i = [i delta, (i+2) delta) holding e, the
+ * s-weight w_i(s, e) (Def. "s-weight", Claim "overall-num-matches"), exact;
+ * then W_i and W (Claim "num-matches-entire-tree").  The tables stay resident
+ * in device memory for any number of tm_sample calls.  tr = NULL takes
+ * tm_default_tree.  Weights are computed in 64 bits and recomputed in 128
+ * bits when any value or prefix sum would reach 2^64.  Errors: TM_EINVAL,
+ * TM_ERANGE (bit limits above), TM_EOVERFLOW, TM_ENOMEM, TM_EDEVICE. */
+int tm_weights_create(tm_graph* g, const tm_motif* mo, const tm_tree* tr, void* stream,
+                      tm_weights** out);
+void tm_weights_destroy(tm_weights* w);
+
+/* W, the interval count q, whether 128-bit weights were needed, the device
+ * bytes held and the tree used; any output pointer may be NULL. */
+int tm_weights_info(const tm_weights* w, tm_u128* W, int64_t* q, int32_t* wide,
+                    uint64_t* device_bytes, tm_tree* tree);
+
+/* w_i(s, e) for every eid e, with i = floor(t(e) / delta) - slot (slot 0 or 1;
+ * entries with i < 0 are 0); s is a tree edge's motif index.  Leaf edges give 1.
+ * host_out: m entries. */
+int tm_weights_export(const tm_weights* w, int32_t s, int32_t slot, tm_u128* host_out,
+                      void* stream);
+
+/* W_i for i = 0 .. q-1 into host memory. */
+int tm_weights_intervals(const tm_weights* w, tm_u128* host_out, void* stream);
+
+/* Draw samples j = j0 .. j0 + count - 1 (Alg. 3 SampleSubg, Alg. 4, Alg. 5)
+ * and reduce them (Alg. 6).  Draw d of sample j is the Philox4x32-10 block
+ * for counter (j mod 2^32, j >> 32, d, 0) and key (seed mod 2^32, seed >> 32)
+ * read as a 128-bit X; it selects floor(X * n / 2^128) among n.  Draw 0 picks
+ * the (interval, center edge) pair by inverse CDF over pairs in (interval,
+ * eid) order weighted by w_i(c, e); draw d >= 1 picks the d-th tree edge in
+ * pre-order (children in increasing pi index) by inverse CDF over its
+ * candidate list (Claim "matching-edges-set") in eid order.  k_total is the k
+ * of the estimate formula (count for a whole run).  recs: NULL, or device
+ * memory for count records.  Synchronises the stream.  Results for a given
+ * (weights, seed, j) never depend on how samples are split across calls. */
+int tm_sample(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count, uint64_t k_total,
+              void* stream, tm_result* out, tm_sample_rec* recs);
+
+/* One whole estimate: tm_weights_create, tm_sample(j0 = 0, count = k_total =
+ * k), tm_weights_destroy. */
+int tm_estimate(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint64_t k,
+                uint64_t seed, void* stream, tm_result* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

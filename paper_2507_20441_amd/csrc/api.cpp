@@ -1,0 +1,481 @@
+// C ABI of the TIMEST GPU library: argument checks, the motif plan, handle
+// lifetimes and the host side of each entry point.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "tm_internal.h"
+
+static thread_local char g_last_error[512] = "";
+
+int tm_fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int DevArena::alloc(void** p, size_t nbytes) {
+    *p = nullptr;
+    if (nbytes == 0) nbytes = 16;
+    hipError_t e = hipMalloc(p, nbytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return tm_fail(e == hipErrorOutOfMemory ? TM_ENOMEM : TM_EDEVICE,
+                       "hipMalloc(%zu bytes): %s", nbytes, hipGetErrorString(e));
+    }
+    blocks.push_back(*p);
+    bytes += nbytes;
+    return TM_OK;
+}
+
+void DevArena::release() {
+    for (void* p : blocks) (void)hipFree(p);
+    blocks.clear();
+    bytes = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Motif and tree checks, and the rooted plan.
+// ---------------------------------------------------------------------------
+int motif_check(const tm_motif* mo) {
+    if (!mo) return tm_fail(TM_EINVAL, "motif: NULL");
+    if (mo->k < 2 || mo->k > TM_MAX_K) return tm_fail(TM_EINVAL, "motif: k = %d outside [2, 8]", mo->k);
+    if (mo->l < 1 || mo->l > TM_MAX_L) return tm_fail(TM_EINVAL, "motif: l = %d outside [1, 16]", mo->l);
+    if (mo->delta < 1 || mo->delta >= ((int64_t)1 << 62))
+        return tm_fail(TM_EINVAL, "motif: delta = %lld outside [1, 2^62)", (long long)mo->delta);
+    int root[TM_MAX_K];
+    for (int x = 0; x < mo->k; ++x) root[x] = x;
+    auto find = [&](int x) {
+        while (root[x] != x) x = root[x];
+        return x;
+    };
+    for (int p = 0; p < mo->l; ++p) {
+        const int a = mo->src[p], b = mo->dst[p];
+        if (a < 0 || a >= mo->k || b < 0 || b >= mo->k)
+            return tm_fail(TM_EINVAL, "motif: edge %d has an endpoint outside [0, k)", p);
+        if (a == b) return tm_fail(TM_EINVAL, "motif: edge %d is a self loop", p);
+        root[find(a)] = find(b);
+    }
+    for (int x = 1; x < mo->k; ++x)
+        if (find(x) != find(0)) return tm_fail(TM_EINVAL, "motif: not weakly connected");
+    return TM_OK;
+}
+
+static bool spanning_tree_of(const tm_motif* mo, const int32_t* e, int cnt) {
+    if (cnt != mo->k - 1) return false;
+    int root[TM_MAX_K];
+    for (int x = 0; x < mo->k; ++x) root[x] = x;
+    auto find = [&](int x) {
+        while (root[x] != x) x = root[x];
+        return x;
+    };
+    for (int j = 0; j < cnt; ++j) {
+        if (e[j] < 0 || e[j] >= mo->l) return false;
+        const int a = find(mo->src[e[j]]), b = find(mo->dst[e[j]]);
+        if (a == b) return false;  // repeated edge or cycle
+        root[a] = b;
+    }
+    return true;
+}
+
+int plan_build(const tm_motif* mo, const tm_tree* tr, HostPlan* P) {
+    TM_TRY(motif_check(mo));
+    if (!tr) return tm_fail(TM_EINVAL, "tree: NULL");
+    if (!spanning_tree_of(mo, tr->edge, tr->n_edges))
+        return tm_fail(TM_EINVAL, "tree: not a spanning tree of the motif");
+    bool in_tree[TM_MAX_L] = {false};
+    for (int j = 0; j < tr->n_edges; ++j) in_tree[tr->edge[j]] = true;
+    if (tr->center < 0 || tr->center >= mo->l || !in_tree[tr->center])
+        return tm_fail(TM_EINVAL, "tree: center %d is not a tree edge", tr->center);
+    HostPlan& H = *P;
+    H = HostPlan();
+    H.mo = *mo;
+    H.tree = *tr;
+    H.nt = tr->n_edges;
+    for (int p = 0; p < TM_MAX_L; ++p) H.slot_of_edge[p] = -1;
+    for (int s = 0; s < kMaxSlots; ++s) {
+        H.n_children[s] = 0;
+        H.height[s] = 0;
+    }
+    // Pre-order placement from the center.  The center meets its children at
+    // both endpoints; any other edge at its new (lower) endpoint only.
+    int n_slots = 0;
+    auto place = [&](auto&& self, int s) -> void {
+        const int e = H.edge[s];
+        int cand[TM_MAX_L], nc = 0;
+        for (int p = 0; p < mo->l; ++p) {
+            if (!in_tree[p] || H.slot_of_edge[p] != -1) continue;  // placed or reserved
+            const bool at_src = s == 0 ? (mo->src[p] == mo->src[e] || mo->dst[p] == mo->src[e])
+                                       : false;
+            const bool at_dst = s == 0 ? (mo->src[p] == mo->dst[e] || mo->dst[p] == mo->dst[e])
+                                       : false;
+            const bool at_low = s != 0 && (mo->src[p] == H.new_vertex[s] || mo->dst[p] == H.new_vertex[s]);
+            if (at_src || at_dst || at_low) cand[nc++] = p;
+        }
+        for (int j = 0; j < nc; ++j) H.slot_of_edge[cand[j]] = -2;  // reserved
+        for (int j = 0; j < nc; ++j) {
+            const int p = cand[j];
+            const int c = n_slots++;
+            H.edge[c] = p;
+            H.slot_of_edge[p] = c;
+            H.parent[c] = s;
+            int z;
+            if (s == 0) z = (mo->src[p] == mo->src[e] || mo->dst[p] == mo->src[e]) ? mo->src[e] : mo->dst[e];
+            else z = H.new_vertex[s];
+            H.side[c] = z == mo->src[e] ? 0 : 1;
+            H.alpha[c] = mo->src[p] == z ? +1 : -1;
+            H.beta[c] = p < e ? -1 : +1;
+            H.new_vertex[c] = mo->src[p] == z ? mo->dst[p] : mo->src[p];
+            H.children[s][H.n_children[s]++] = c;
+            self(self, c);
+        }
+    };
+    H.edge[0] = tr->center;
+    H.slot_of_edge[tr->center] = 0;
+    H.parent[0] = -1;
+    H.side[0] = 0;
+    H.alpha[0] = 0;
+    H.beta[0] = 0;
+    H.new_vertex[0] = -1;
+    n_slots = 1;
+    place(place, 0);
+    if (n_slots != H.nt) return tm_fail(TM_EINVAL, "tree: not connected through its center");
+    // heights, children before parents: slots are in pre-order, so walk back
+    for (int s = H.nt - 1; s >= 0; --s) {
+        int h = 0;
+        for (int j = 0; j < H.n_children[s]; ++j) h = std::max(h, 1 + H.height[H.children[s][j]]);
+        H.height[s] = h;
+    }
+    H.H = H.height[0];
+    int r = 0;
+    for (int p = 0; p < mo->l; ++p)
+        if (H.slot_of_edge[p] >= 0) H.by_pi[r++] = H.slot_of_edge[p];
+    // non-tree edges and their runs between tree positions
+    H.n_free = 0;
+    H.n_runs = 0;
+    int last_tree_slot = -1;
+    for (int p = 0; p < mo->l;) {
+        if (H.slot_of_edge[p] >= 0) {
+            last_tree_slot = H.slot_of_edge[p];
+            ++p;
+            continue;
+        }
+        const int first = H.n_free;
+        while (p < mo->l && H.slot_of_edge[p] < 0) {
+            H.free_src[H.n_free] = mo->src[p];
+            H.free_dst[H.n_free] = mo->dst[p];
+            ++H.n_free;
+            ++p;
+        }
+        H.run_first[H.n_runs] = first;
+        H.run_len[H.n_runs] = H.n_free - first;
+        H.run_prev[H.n_runs] = last_tree_slot;
+        H.run_next[H.n_runs] = p < mo->l ? H.slot_of_edge[p] : -1;
+        ++H.n_runs;
+    }
+    return TM_OK;
+}
+
+extern "C" int tm_default_tree(const tm_motif* mo, tm_tree* out) {
+    TM_TRY(motif_check(mo));
+    if (!out) return tm_fail(TM_EINVAL, "tree: NULL output");
+    const int need = mo->k - 1;
+    long best_loose = -1;
+    int32_t best[8] = {0};
+    for (uint32_t mask = 0; mask < (1u << mo->l); ++mask) {
+        if (__builtin_popcount(mask) != need) continue;
+        int32_t e[8];
+        int c = 0;
+        for (int p = 0; p < mo->l; ++p)
+            if (mask >> p & 1) e[c++] = p;
+        if (!spanning_tree_of(mo, e, c)) continue;
+        long loose = 0;
+        for (int x = 0; x < mo->k; ++x) {
+            int inc[8], ni = 0;
+            for (int j = 0; j < c; ++j)
+                if (mo->src[e[j]] == x || mo->dst[e[j]] == x) inc[ni++] = e[j];
+            for (int a = 0; a < ni; ++a)
+                for (int b = a + 1; b < ni; ++b) loose += std::abs(inc[a] - inc[b]) - 1;
+        }
+        const bool better = best_loose < 0 || loose < best_loose ||
+                            (loose == best_loose && std::lexicographical_compare(e, e + c, best, best + c));
+        if (better) {
+            best_loose = loose;
+            std::memcpy(best, e, sizeof(int32_t) * c);
+        }
+    }
+    if (best_loose < 0) return tm_fail(TM_EINVAL, "motif: no spanning tree");
+    tm_tree t;
+    std::memset(&t, 0, sizeof t);
+    t.n_edges = need;
+    std::memcpy(t.edge, best, sizeof(int32_t) * need);
+    int best_h = 1 << 30;
+    int center = best[0];
+    for (int j = 0; j < need; ++j) {  // best[] is increasing: ties keep the smaller index
+        t.center = best[j];
+        HostPlan P;
+        TM_TRY(plan_build(mo, &t, &P));
+        if (P.H < best_h) {
+            best_h = P.H;
+            center = best[j];
+        }
+    }
+    t.center = center;
+    *out = t;
+    return TM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Entry points.
+// ---------------------------------------------------------------------------
+extern "C" const char* tm_strerror(int code) {
+    switch (code) {
+        case TM_OK: return "ok";
+        case TM_EINVAL: return "invalid argument";
+        case TM_ESELFLOOP: return "self loop in the graph";
+        case TM_EDUP: return "duplicate (u, v, t) tuple";
+        case TM_EOVERFLOW: return "count reaches 2^128";
+        case TM_ERANGE: return "value outside the supported range";
+        case TM_ENOMEM: return "out of device memory";
+        case TM_EDEVICE: return "HIP runtime error";
+        default: return "unknown error";
+    }
+}
+
+extern "C" const char* tm_last_error(void) { return g_last_error; }
+
+static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+extern "C" int tm_graph_create(const int32_t* src, const int32_t* dst, const int64_t* t, int64_t m,
+                               int32_t n, int ptr_kind, void* stream, tm_graph** out) {
+    if (!out) return tm_fail(TM_EINVAL, "graph: NULL output");
+    if (m < 0 || m >= ((int64_t)1 << 31) || n < 0 || n == INT32_MAX)
+        return tm_fail(TM_EINVAL, "graph: m = %lld or n = %d out of range", (long long)m, n);
+    if (m > 0 && (!src || !dst || !t)) return tm_fail(TM_EINVAL, "graph: NULL edge array");
+    if (ptr_kind != TM_PTR_HOST && ptr_kind != TM_PTR_DEVICE)
+        return tm_fail(TM_EINVAL, "graph: bad ptr_kind %d", ptr_kind);
+    hipStream_t st = as_stream(stream);
+    tm_graph* g = new (std::nothrow) tm_graph();
+    if (!g) return tm_fail(TM_ENOMEM, "graph: host allocation");
+    g->m = m;
+    g->n = n;
+    (void)hipGetDevice(&g->device);
+    const int32_t *ds = src, *dd = dst;
+    const int64_t* dt = t;
+    void* staged[3] = {nullptr, nullptr, nullptr};
+    int rc = TM_OK;
+    if (ptr_kind == TM_PTR_HOST && m > 0) {
+        const size_t sz[3] = {m * sizeof(int32_t), m * sizeof(int32_t), m * sizeof(int64_t)};
+        const void* hp[3] = {src, dst, t};
+        for (int a = 0; a < 3 && rc == TM_OK; ++a) {
+            hipError_t e = hipMallocAsync(&staged[a], sz[a], st);
+            if (e == hipSuccess) e = hipMemcpyAsync(staged[a], hp[a], sz[a], hipMemcpyHostToDevice, st);
+            if (e != hipSuccess)
+                rc = tm_fail(e == hipErrorOutOfMemory ? TM_ENOMEM : TM_EDEVICE, "graph: staging: %s",
+                             hipGetErrorString(e));
+        }
+        ds = static_cast<const int32_t*>(staged[0]);
+        dd = static_cast<const int32_t*>(staged[1]);
+        dt = static_cast<const int64_t*>(staged[2]);
+    }
+    if (rc == TM_OK) rc = graph_build(g, ds, dd, dt, st);
+    for (void* p : staged)
+        if (p) (void)hipFreeAsync(p, st);
+    (void)hipStreamSynchronize(st);
+    if (rc != TM_OK) {
+        g->arena.release();
+        delete g;
+        return rc;
+    }
+    *out = g;
+    return TM_OK;
+}
+
+extern "C" void tm_graph_destroy(tm_graph* g) {
+    if (!g) return;
+    g->arena.release();
+    delete g;
+}
+
+extern "C" int tm_graph_info(const tm_graph* g, int64_t* m, int32_t* n, int64_t* t_shift,
+                             int64_t* t_span, uint64_t* device_bytes) {
+    if (!g) return tm_fail(TM_EINVAL, "graph: NULL");
+    if (m) *m = g->m;
+    if (n) *n = g->n;
+    if (t_shift) *t_shift = g->shift;
+    if (t_span) *t_span = g->T;
+    if (device_bytes) *device_bytes = g->arena.bytes;
+    return TM_OK;
+}
+
+extern "C" int tm_graph_export(const tm_graph* g, int which, void* host_out, void* stream) {
+    if (!g || !host_out) return tm_fail(TM_EINVAL, "graph_export: NULL");
+    const DevGraph& D = g->d;
+    const void* p = nullptr;
+    size_t bytes = 0;
+    const size_t m = (size_t)g->m, n1 = (size_t)g->n + 1;
+    switch (which) {
+        case TM_ARR_SRC: p = D.src; bytes = m * 4; break;
+        case TM_ARR_DST: p = D.dst; bytes = m * 4; break;
+        case TM_ARR_T: p = D.t; bytes = m * 8; break;
+        case TM_ARR_OUT_OFF: p = D.off[0]; bytes = n1 * 4; break;
+        case TM_ARR_IN_OFF: p = D.off[1]; bytes = n1 * 4; break;
+        case TM_ARR_OUT_EID: p = D.leid[0]; bytes = m * 4; break;
+        case TM_ARR_IN_EID: p = D.leid[1]; bytes = m * 4; break;
+        case TM_ARR_OUTN_EID: p = D.neid[0]; bytes = m * 4; break;
+        case TM_ARR_INN_EID: p = D.neid[1]; bytes = m * 4; break;
+        default: return tm_fail(TM_EINVAL, "graph_export: unknown array %d", which);
+    }
+    if (bytes == 0 || !p) return TM_OK;
+    hipStream_t st = as_stream(stream);
+    TM_HIP(hipMemcpyAsync(host_out, p, bytes, hipMemcpyDeviceToHost, st));
+    TM_HIP(hipStreamSynchronize(st));
+    return TM_OK;
+}
+
+extern "C" int tm_weights_create(tm_graph* g, const tm_motif* mo, const tm_tree* tr, void* stream,
+                                 tm_weights** out) {
+    if (!g || !out) return tm_fail(TM_EINVAL, "weights: NULL argument");
+    TM_TRY(motif_check(mo));
+    tm_tree def;
+    if (!tr) {
+        TM_TRY(tm_default_tree(mo, &def));
+        tr = &def;
+    }
+    tm_weights* w = new (std::nothrow) tm_weights();
+    if (!w) return tm_fail(TM_ENOMEM, "weights: host allocation");
+    w->g = g;
+    int rc = plan_build(mo, tr, &w->plan);
+    if (rc == TM_OK) rc = weights_build(w, as_stream(stream));
+    if (rc != TM_OK) {
+        w->arena.release();
+        delete w;
+        return rc;
+    }
+    *out = w;
+    return TM_OK;
+}
+
+extern "C" void tm_weights_destroy(tm_weights* w) {
+    if (!w) return;
+    w->arena.release();
+    delete w;
+}
+
+extern "C" int tm_weights_info(const tm_weights* w, tm_u128* W, int64_t* q, int32_t* wide,
+                               uint64_t* device_bytes, tm_tree* tree) {
+    if (!w) return tm_fail(TM_EINVAL, "weights: NULL");
+    if (W) {
+        W->lo = (u64)w->W;
+        W->hi = (u64)(w->W >> 64);
+    }
+    if (q) *q = w->q;
+    if (wide) *wide = w->wide ? 1 : 0;
+    if (device_bytes) *device_bytes = w->arena.bytes;
+    if (tree) *tree = w->plan.tree;
+    return TM_OK;
+}
+
+extern "C" int tm_weights_export(const tm_weights* w, int32_t s, int32_t slot, tm_u128* host_out,
+                                 void* stream) {
+    if (!w || !host_out) return tm_fail(TM_EINVAL, "weights_export: NULL");
+    const HostPlan& P = w->plan;
+    if (s < 0 || s >= P.mo.l || P.slot_of_edge[s] < 0 || slot < 0 || slot > 1)
+        return tm_fail(TM_EINVAL, "weights_export: edge %d / slot %d", s, slot);
+    const int sl = P.slot_of_edge[s];
+    const int64_t m = w->g->m;
+    if (m == 0) return TM_OK;
+    hipStream_t st = as_stream(stream);
+    std::vector<int64_t> t(m);
+    TM_HIP(hipMemcpyAsync(t.data(), w->g->d.t, m * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    const bool leaf = P.n_children[sl] == 0;
+    const size_t wsz = w->wide ? 16 : 8;
+    std::vector<unsigned char> v[2];
+    if (!leaf)
+        for (int par = 0; par < 2; ++par) {
+            v[par].resize(m * wsz);
+            TM_HIP(hipMemcpyAsync(v[par].data(), w->vals[sl][par], m * wsz, hipMemcpyDeviceToHost, st));
+        }
+    TM_HIP(hipStreamSynchronize(st));
+    for (int64_t e = 0; e < m; ++e) {
+        const int64_t i = t[e] / P.mo.delta - slot;
+        tm_u128 x = {0, 0};
+        if (i >= 0 && i < w->q) {
+            if (leaf) {
+                x.lo = 1;
+            } else {
+                const unsigned char* b = v[i & 1].data() + e * wsz;
+                std::memcpy(&x.lo, b, 8);
+                if (w->wide) std::memcpy(&x.hi, b + 8, 8);
+            }
+        }
+        host_out[e] = x;
+    }
+    return TM_OK;
+}
+
+extern "C" int tm_weights_intervals(const tm_weights* w, tm_u128* host_out, void* stream) {
+    if (!w || !host_out) return tm_fail(TM_EINVAL, "weights_intervals: NULL");
+    if (w->q == 0) return TM_OK;
+    hipStream_t st = as_stream(stream);
+    const size_t wsz = w->wide ? 16 : 8;
+    std::vector<unsigned char> c((w->q + 1) * wsz);
+    TM_HIP(hipMemcpyAsync(c.data(), w->cumW, c.size(), hipMemcpyDeviceToHost, st));
+    TM_HIP(hipStreamSynchronize(st));
+    auto at = [&](int64_t i) {
+        u128 x = 0;
+        u64 lo = 0, hi = 0;
+        std::memcpy(&lo, c.data() + i * wsz, 8);
+        if (w->wide) std::memcpy(&hi, c.data() + i * wsz + 8, 8);
+        x = ((u128)hi << 64) | lo;
+        return x;
+    };
+    for (int64_t i = 0; i < w->q; ++i) {
+        const u128 d = at(i + 1) - at(i);
+        host_out[i].lo = (u64)d;
+        host_out[i].hi = (u64)(d >> 64);
+    }
+    return TM_OK;
+}
+
+static double u128_to_double(tm_u128 x) { return (double)(((u128)x.hi << 64) | x.lo); }
+
+static void finish_result(tm_result* r) {
+    const double W = u128_to_double(r->W);
+    const double acc2 = u128_to_double(r->acc2);
+    const double k = (double)r->k;
+    r->estimate = r->k ? W * (acc2 / (2.0 * k)) : 0.0;
+    r->std_error = 0.0;
+    if (r->k > 1 && !(r->flags & TM_F_SQ_SATURATED)) {
+        const double mean = acc2 / k;
+        double var = (u128_to_double(r->acc2_sq) - k * mean * mean) / (k - 1.0);
+        if (var < 0) var = 0;
+        r->std_error = (W / 2.0) * __builtin_sqrt(var / k);
+    }
+}
+
+extern "C" int tm_sample(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count,
+                         uint64_t k_total, void* stream, tm_result* out, tm_sample_rec* recs) {
+    if (!w || !out) return tm_fail(TM_EINVAL, "sample: NULL argument");
+    if (count > 0 && j0 + count < j0) return tm_fail(TM_EINVAL, "sample: id range wraps");
+    TM_TRY(sample_run(w, seed, j0, count, k_total, as_stream(stream), out, recs));
+    finish_result(out);
+    out->status = TM_OK;
+    return TM_OK;
+}
+
+extern "C" int tm_estimate(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint64_t k,
+                           uint64_t seed, void* stream, tm_result* out) {
+    if (!out) return tm_fail(TM_EINVAL, "estimate: NULL output");
+    tm_weights* w = nullptr;
+    TM_TRY(tm_weights_create(g, mo, tr, stream, &w));
+    const int rc = tm_sample(w, seed, 0, k, k, stream, out, nullptr);
+    tm_weights_destroy(w);
+    return rc;
+}

@@ -1,0 +1,41 @@
+// Scan of tile sums for the device-wide exclusive scan (tm_primitives.h).
+#include "tm_primitives.h"
+
+namespace {
+
+// One block scans up to kScanTile values in place: a[0..n] (a[n] = total).
+__global__ void __launch_bounds__(kBlock) scan_single_kernel(u128* a, int64_t n, int* ovf) {
+    const int64_t first = (int64_t)threadIdx.x * kScanItems;
+    u128 v[kScanItems];
+    u128 s = 0;
+    bool carry = false;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = first + k;
+        v[k] = i < n ? a[i] : (u128)0;
+        u128 y = s + v[k];
+        if (y < s) carry = true;
+        s = y;
+    }
+    u128 tot;
+    u128 run = block_exclusive(s, &tot, &carry);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = first + k;
+        if (i < n) a[i] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) a[n] = tot;
+    if (carry) atomicOr(ovf, 1);
+}
+
+}  // namespace
+
+int scan_parts(u128* part, int64_t nb, int* ovf, hipStream_t st) {
+    if (nb <= kScanTile) {
+        hipLaunchKernelGGL(scan_single_kernel, dim3(1), dim3(kBlock), 0, st, part, nb, ovf);
+        TM_HIP(hipGetLastError());
+        return TM_OK;
+    }
+    return device_exclusive_scan<u128>(ArrayReader128{part}, nb, part, ovf, st);
+}

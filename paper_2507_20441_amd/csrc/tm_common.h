@@ -1,0 +1,168 @@
+// Shared definitions of the TIMEST GPU library: plain structs handed to the
+// kernels, exact-integer helpers, the Philox4x32-10 generator and searches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef unsigned __int128 u128;
+typedef unsigned long long u64;
+
+#define TM_HD __host__ __device__ __forceinline__
+
+// Block shape used by every kernel: 256 lanes = 4 wave64.
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+
+// ---------------------------------------------------------------------------
+// Graph in device memory.  Edges are indexed by eid (rank under (t, src, dst)).
+// Per vertex g, out-lists occupy positions [out_off[g], out_off[g+1]) of two
+// arrays: the T order (time, then destination: eid order restricted to g) and
+// the N order (destination, then time), which holds El_{g,v} as a contiguous
+// run.  In-lists likewise with the source as neighbour.  N-order entries carry
+// a packed key (neighbour << bt | time) and the position of the same edge in
+// the T order (xref).
+// ---------------------------------------------------------------------------
+struct DevGraph {
+    int64_t m;
+    int32_t n;
+    int32_t bt;          // bits of the time field in the packed key
+    int64_t T;           // largest shifted time
+    const int32_t* src;  // [m]
+    const int32_t* dst;  // [m]
+    const int64_t* t;    // [m]
+    const int32_t* off[2];     // [2][n+1]: 0 = out, 1 = in
+    const int64_t* lt[2];      // T order: time
+    const int32_t* leid[2];    // T order: eid
+    const int32_t* lnbr[2];    // T order: neighbour
+    const u64* nkey[2];        // N order: neighbour << bt | time
+    const int32_t* nxref[2];   // N order: position of the edge in the T order
+    const int32_t* neid[2];    // N order: eid
+};
+
+// ---------------------------------------------------------------------------
+// Exact integers.
+// ---------------------------------------------------------------------------
+TM_HD bool add_ok(u64 a, u64 b, u64* r) { *r = a + b; return *r >= a; }
+TM_HD bool add_ok(u128 a, u128 b, u128* r) { *r = a + b; return *r >= a; }
+TM_HD bool mul_ok(u64 a, u64 b, u64* r) { return !__builtin_mul_overflow(a, b, r); }
+TM_HD bool mul_ok(u128 a, u128 b, u128* r) { return !__builtin_mul_overflow(a, b, r); }
+
+template <typename T>
+TM_HD u128 to_u128(T x) { return (u128)x; }
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds, each multiplying words 0
+// and 2 by the two round multipliers and mixing the high halves with the other
+// words and the key; the key advances by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+struct Block4 {
+    uint32_t x[4];
+};
+
+__device__ __forceinline__ Block4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                           uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Block4 b;
+    b.x[0] = c0;
+    b.x[1] = c1;
+    b.x[2] = c2;
+    b.x[3] = c3;
+    return b;
+}
+
+// 128-bit block of draw d of sample j: words x0 + x1 2^32 + x2 2^64 + x3 2^96.
+struct X128 {
+    u64 lo, hi;
+};
+
+__device__ __forceinline__ X128 draw_block(u64 seed, u64 j, uint32_t d) {
+    Block4 b = philox10((uint32_t)j, (uint32_t)(j >> 32), d, 0u, (uint32_t)seed,
+                        (uint32_t)(seed >> 32));
+    X128 x;
+    x.lo = (u64)b.x[0] | ((u64)b.x[1] << 32);
+    x.hi = (u64)b.x[2] | ((u64)b.x[3] << 32);
+    return x;
+}
+
+// floor(X * n / 2^128): the position selected among n.
+__device__ __forceinline__ u64 scale(X128 X, u64 n) {
+    // X * n = hi*n * 2^64 + lo*n; the floor by 2^128 is the top word of
+    // hi*n + floor(lo*n / 2^64), which cannot carry past 128 bits.
+    u128 s = (u128)X.hi * n + (u128)__umul64hi(X.lo, n);
+    return (u64)(s >> 64);
+}
+
+__device__ __forceinline__ u128 scale(X128 X, u128 n) {
+    const u64 n0 = (u64)n, n1 = (u64)(n >> 64);
+    const u128 a = (u128)X.lo * n0;   // 2^0
+    const u128 b = (u128)X.lo * n1;   // 2^64
+    const u128 c = (u128)X.hi * n0;   // 2^64
+    const u128 d = (u128)X.hi * n1;   // 2^128
+    const u128 mid = (a >> 64) + (u64)b + (u64)c;
+    return d + (b >> 64) + (c >> 64) + (mid >> 64);
+}
+
+// ---------------------------------------------------------------------------
+// Searches over sorted ranges [lo, hi) of positions (int32 positions).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ int32_t lower_bound_pos(const T* a, int32_t lo, int32_t hi, T key) {
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+template <typename T>
+__device__ __forceinline__ int32_t upper_bound_pos(const T* a, int32_t lo, int32_t hi, T key) {
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if (key < a[mid]) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// The candidate window of a child edge (Claim "matching-edges-set"):
+// the child's edges at the vertex g (out-list when alpha = +, in-list when
+// alpha = -) with time in [t - delta, t] (beta '<') or [t, t + delta]
+// (beta '>'), clipped to I_i = [i delta, (i+2) delta) and to [0, T]; minus
+// the edges whose far endpoint is o (a contiguous run of the N order).
+// ---------------------------------------------------------------------------
+struct Window {
+    int32_t p0, p1;  // T-order positions of the window
+    int32_t q0, q1;  // N-order positions of the excluded run
+};
+
+__device__ __forceinline__ Window find_window(const DevGraph& G, int dir, int32_t g, int32_t o,
+                                              int64_t wlo, int64_t whi) {
+    Window w;
+    const int32_t a = G.off[dir][g], b = G.off[dir][g + 1];
+    if (wlo < 0) wlo = 0;
+    if (whi > G.T) whi = G.T;
+    if (wlo > whi) {
+        w.p0 = w.p1 = a;
+        w.q0 = w.q1 = a;
+        return w;
+    }
+    w.p0 = lower_bound_pos<int64_t>(G.lt[dir], a, b, wlo);
+    w.p1 = upper_bound_pos<int64_t>(G.lt[dir], w.p0, b, whi);
+    const u64 base = (u64)o << G.bt;
+    w.q0 = lower_bound_pos<u64>(G.nkey[dir], a, b, base | (u64)wlo);
+    w.q1 = upper_bound_pos<u64>(G.nkey[dir], w.q0, b, base | (u64)whi);
+    return w;
+}

@@ -1,0 +1,122 @@
+// Host-side internals of the TIMEST GPU library: handles, the motif plan,
+// error plumbing and the launchers each translation unit provides.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/timest.h"
+#include "tm_common.h"
+
+// ---------------------------------------------------------------------------
+// Errors: every failing call records a message for its thread.
+// ---------------------------------------------------------------------------
+int tm_fail(int code, const char* fmt, ...);
+
+#define TM_HIP(expr)                                                              \
+    do {                                                                          \
+        hipError_t _e = (expr);                                                   \
+        if (_e != hipSuccess)                                                     \
+            return tm_fail(_e == hipErrorOutOfMemory ? TM_ENOMEM : TM_EDEVICE,    \
+                           "%s: %s (%s:%d)", #expr, hipGetErrorString(_e),        \
+                           __FILE__, __LINE__);                                   \
+    } while (0)
+
+#define TM_TRY(expr)                    \
+    do {                                \
+        int _rc = (expr);               \
+        if (_rc != TM_OK) return _rc;   \
+    } while (0)
+
+// Device allocations owned by a handle; released together.
+struct DevArena {
+    std::vector<void*> blocks;
+    uint64_t bytes = 0;
+    int alloc(void** p, size_t nbytes);
+    void release();
+};
+
+template <typename T>
+int arena_alloc(DevArena& A, T** p, size_t count) {
+    return A.alloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+// ---------------------------------------------------------------------------
+// Graph handle.
+// ---------------------------------------------------------------------------
+struct tm_graph {
+    DevGraph d{};
+    int64_t m = 0;
+    int32_t n = 0;
+    int64_t shift = 0;
+    int64_t T = 0;
+    int device = 0;
+    DevArena arena;
+};
+
+// ---------------------------------------------------------------------------
+// Motif plan: the spanning tree rooted at its center edge (Sec. 4.1), listed
+// in pre-order (center first, children in increasing pi index, each child's
+// subtree before the next sibling).  Slots index that pre-order.
+// ---------------------------------------------------------------------------
+constexpr int kMaxSlots = 8;
+
+struct HostPlan {
+    tm_motif mo{};
+    tm_tree tree{};
+    int nt = 0;                    // tree edges (k - 1)
+    int H = 0;                     // height of the center
+    int slot_of_edge[TM_MAX_L];    // pre-order slot of a motif edge, -1 if not in the tree
+    int edge[kMaxSlots];           // motif edge of a slot
+    int parent[kMaxSlots];         // parent slot, -1 for the center
+    int side[kMaxSlots];           // 0: attaches at the parent's source, 1: at its destination
+    int alpha[kMaxSlots];          // +1: child leaves the shared vertex; -1: enters it
+    int beta[kMaxSlots];           // -1: child precedes its parent in pi; +1: follows
+    int height[kMaxSlots];
+    int new_vertex[kMaxSlots];     // motif vertex first reached through this slot
+    int children[kMaxSlots][kMaxSlots];
+    int n_children[kMaxSlots];
+    int by_pi[kMaxSlots];          // slots in increasing pi index
+    // non-tree edges in pi order, and maximal runs of consecutive ones
+    int n_free = 0;
+    int free_src[TM_MAX_L], free_dst[TM_MAX_L];
+    int n_runs = 0;
+    int run_first[TM_MAX_L], run_len[TM_MAX_L];
+    int run_prev[TM_MAX_L], run_next[TM_MAX_L];  // tree slots around a run, -1 at the ends
+};
+
+int plan_build(const tm_motif* mo, const tm_tree* tr, HostPlan* out);
+int motif_check(const tm_motif* mo);
+
+// ---------------------------------------------------------------------------
+// Per-slot tables of a weight set.  For a non-leaf slot s, vals[s][par] holds,
+// per eid e, w_i(s, e) for the interval i of parity par that holds e (each
+// edge lies in at most one interval of each parity).  Non-leaf, non-center
+// slots also keep exclusive prefix sums of those values along the lists in
+// which their parent looks them up (qt: T order, qn: N order, per parity);
+// the center keeps them along eid order (qc).
+// ---------------------------------------------------------------------------
+struct tm_weights {
+    tm_graph* g = nullptr;
+    HostPlan plan;
+    bool wide = false;
+    int64_t q = 0;
+    u128 W = 0;
+    void* vals[kMaxSlots][2] = {};
+    void* qt[kMaxSlots][2] = {};
+    void* qn[kMaxSlots][2] = {};
+    void* qc[2] = {};
+    int32_t* ilo = nullptr;  // [q] first eid of I_i
+    int32_t* ihi = nullptr;  // [q] one past the last eid of I_i
+    void* cumW = nullptr;    // [q+1] prefix of W_i
+    DevArena arena;
+};
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64_t* t,
+                hipStream_t st);
+int weights_build(tm_weights* w, hipStream_t st);
+int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStream_t st,
+               tm_result* out, tm_sample_rec* recs);

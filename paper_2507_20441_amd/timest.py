@@ -1,0 +1,249 @@
+"""Python binding of the TIMEST GPU library (libtimest.so, include/timest.h).
+
+Argument marshalling only: every step of the estimator runs in the library's
+HIP kernels.  PyTorch supplies device memory (for inputs and per-sample
+records) and the current HIP stream.  Loading fails loudly when the library
+is missing; there is no CPU fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtimest.so")
+
+TM_OK, TM_EINVAL, TM_ESELFLOOP, TM_EDUP, TM_EOVERFLOW, TM_ERANGE, TM_ENOMEM, TM_EDEVICE = \
+    0, -1, -2, -3, -4, -5, -6, -7
+TM_PTR_HOST, TM_PTR_DEVICE = 0, 1
+TM_F_W_ZERO, TM_F_SQ_SATURATED, TM_F_WIDE = 1, 2, 4
+ARRAYS = dict(src=0, dst=1, t=2, out_off=3, in_off=4, out_eid=5, in_eid=6, outn_eid=7, inn_eid=8)
+
+
+class U128(C.Structure):
+    _fields_ = [("lo", C.c_uint64), ("hi", C.c_uint64)]
+
+    @property
+    def value(self) -> int:
+        return int(self.lo) | (int(self.hi) << 64)
+
+
+class Motif(C.Structure):
+    _fields_ = [("k", C.c_int32), ("l", C.c_int32), ("src", C.c_int32 * 16),
+                ("dst", C.c_int32 * 16), ("delta", C.c_int64)]
+
+
+class Tree(C.Structure):
+    _fields_ = [("n_edges", C.c_int32), ("edge", C.c_int32 * 8), ("center", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("estimate", C.c_double), ("std_error", C.c_double), ("W", U128), ("acc2", U128),
+                ("acc2_sq", U128), ("k", C.c_uint64), ("n_valid", C.c_uint64),
+                ("n_bad_vertex", C.c_uint64), ("n_bad_delta", C.c_uint64),
+                ("n_bad_order", C.c_uint64), ("n_nonzero", C.c_uint64), ("q", C.c_int64),
+                ("flags", C.c_uint32), ("status", C.c_int32)]
+
+
+REC_DTYPE = np.dtype([("interval", "<u4"), ("status", "<u4"), ("n_phi", "<u4"), ("pad", "<u4"),
+                      ("eid", "<i4", (8,)), ("m_lo", "<u8"), ("m_hi", "<u8")])
+U128_DTYPE = np.dtype([("lo", "<u8"), ("hi", "<u8")])
+
+
+class TimestError(RuntimeError):
+    def __init__(self, code, what, detail):
+        super().__init__(f"{what}: {detail} (code {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() or "
+                               "python paper_2507_20441_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+        L.tm_strerror.restype = C.c_char_p
+        L.tm_strerror.argtypes = [C.c_int]
+        L.tm_last_error.restype = C.c_char_p
+        L.tm_graph_create.argtypes = [vp, vp, vp, i64, i32, C.c_int, vp, C.POINTER(vp)]
+        L.tm_graph_destroy.argtypes = [vp]
+        L.tm_graph_destroy.restype = None
+        L.tm_graph_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i64),
+                                    C.POINTER(i64), C.POINTER(u64)]
+        L.tm_graph_export.argtypes = [vp, C.c_int, vp, vp]
+        L.tm_default_tree.argtypes = [C.POINTER(Motif), C.POINTER(Tree)]
+        L.tm_weights_create.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), vp, C.POINTER(vp)]
+        L.tm_weights_destroy.argtypes = [vp]
+        L.tm_weights_destroy.restype = None
+        L.tm_weights_info.argtypes = [vp, C.POINTER(U128), C.POINTER(i64), C.POINTER(i32),
+                                      C.POINTER(u64), C.POINTER(Tree)]
+        L.tm_weights_export.argtypes = [vp, i32, i32, vp, vp]
+        L.tm_weights_intervals.argtypes = [vp, vp, vp]
+        L.tm_sample.argtypes = [vp, u64, u64, u64, u64, vp, C.POINTER(Result), vp]
+        L.tm_estimate.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), u64, u64, vp,
+                                  C.POINTER(Result)]
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != TM_OK:
+        raise TimestError(rc, what, lib().tm_last_error().decode())
+
+
+def _stream():
+    import torch
+    if torch.cuda.is_available():
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(0)
+
+
+def make_motif(edges, delta, k=None) -> Motif:
+    mo = Motif()
+    mo.l = len(edges)
+    mo.k = k if k is not None else 1 + max(max(e) for e in edges)
+    for p, (a, b) in enumerate(edges):
+        mo.src[p], mo.dst[p] = a, b
+    mo.delta = int(delta)
+    return mo
+
+
+def make_tree(edges, center) -> Tree:
+    tr = Tree()
+    tr.n_edges = len(edges)
+    for j, p in enumerate(edges):
+        tr.edge[j] = p
+    tr.center = center
+    return tr
+
+
+def default_tree(mo: Motif) -> Tree:
+    tr = Tree()
+    _check(lib().tm_default_tree(C.byref(mo), C.byref(tr)), "default_tree")
+    return tr
+
+
+def u128_ints(a):
+    return [int(x["lo"]) | (int(x["hi"]) << 64) for x in a]
+
+
+class Graph:
+    """A temporal graph resident in device memory.
+
+    src, dst, t: numpy arrays (copied from host memory) or torch tensors on
+    the GPU (read in place on the current stream)."""
+
+    def __init__(self, src, dst, t, n):
+        import torch
+        self.n = int(n)
+        h = C.c_void_p()
+        if isinstance(src, torch.Tensor) and src.is_cuda:
+            s = src.to(torch.int32).contiguous()
+            d = dst.to(torch.int32).contiguous()
+            tt = t.to(torch.int64).contiguous()
+            self.m = int(s.numel())
+            rc = lib().tm_graph_create(C.c_void_p(s.data_ptr()), C.c_void_p(d.data_ptr()),
+                                       C.c_void_p(tt.data_ptr()), self.m, self.n, TM_PTR_DEVICE,
+                                       _stream(), C.byref(h))
+        else:
+            s = np.ascontiguousarray(np.asarray(src), dtype=np.int32)
+            d = np.ascontiguousarray(np.asarray(dst), dtype=np.int32)
+            tt = np.ascontiguousarray(np.asarray(t), dtype=np.int64)
+            self.m = int(s.shape[0])
+            rc = lib().tm_graph_create(s.ctypes.data_as(C.c_void_p), d.ctypes.data_as(C.c_void_p),
+                                       tt.ctypes.data_as(C.c_void_p), self.m, self.n, TM_PTR_HOST,
+                                       _stream(), C.byref(h))
+        _check(rc, "graph_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tm_graph_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def info(self):
+        m, n, sh, sp, b = C.c_int64(), C.c_int32(), C.c_int64(), C.c_int64(), C.c_uint64()
+        _check(lib().tm_graph_info(self.h, C.byref(m), C.byref(n), C.byref(sh), C.byref(sp),
+                                   C.byref(b)), "graph_info")
+        return dict(m=m.value, n=n.value, t_shift=sh.value, t_span=sp.value, bytes=b.value)
+
+    def export(self, name):
+        which = ARRAYS[name]
+        size = self.n + 1 if name.endswith("_off") else self.m
+        out = np.empty(size, np.int64 if name == "t" else np.int32)
+        _check(lib().tm_graph_export(self.h, which, out.ctypes.data_as(C.c_void_p), _stream()),
+               "graph_export")
+        return out
+
+
+class Weights:
+    """Resident s-weight tables of one (graph, motif, tree) (Alg. 1, Alg. 2)."""
+
+    def __init__(self, g: Graph, mo: Motif, tr: Tree = None):
+        self.g, self.mo = g, mo
+        h = C.c_void_p()
+        _check(lib().tm_weights_create(g.h, C.byref(mo), C.byref(tr) if tr is not None else None,
+                                       _stream(), C.byref(h)), "weights_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tm_weights_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def info(self):
+        W, q, wide, b, tr = U128(), C.c_int64(), C.c_int32(), C.c_uint64(), Tree()
+        _check(lib().tm_weights_info(self.h, C.byref(W), C.byref(q), C.byref(wide), C.byref(b),
+                                     C.byref(tr)), "weights_info")
+        return dict(W=W.value, q=q.value, wide=bool(wide.value), bytes=b.value, tree=tr)
+
+    @property
+    def W(self) -> int:
+        return self.info()["W"]
+
+    def weights(self, s, slot):
+        out = np.empty(self.g.m, U128_DTYPE)
+        _check(lib().tm_weights_export(self.h, int(s), int(slot), out.ctypes.data_as(C.c_void_p),
+                                       _stream()), "weights_export")
+        return out
+
+    def interval_weights(self):
+        q = self.info()["q"]
+        out = np.empty(q, U128_DTYPE)
+        _check(lib().tm_weights_intervals(self.h, out.ctypes.data_as(C.c_void_p), _stream()),
+               "weights_intervals")
+        return u128_ints(out)
+
+    def sample(self, seed, k, j0=0, count=None, k_total=None, records=False):
+        import torch
+        count = k if count is None else count
+        k_total = k if k_total is None else k_total
+        res = Result()
+        recs_dev = None
+        ptr = None
+        if records and count > 0:
+            recs_dev = torch.empty(count * REC_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+            ptr = C.c_void_p(recs_dev.data_ptr())
+        _check(lib().tm_sample(self.h, int(seed), int(j0), int(count), int(k_total), _stream(),
+                               C.byref(res), ptr), "sample")
+        recs = None
+        if records:
+            recs = (recs_dev.cpu().numpy().view(REC_DTYPE) if recs_dev is not None
+                    else np.zeros(0, REC_DTYPE))
+        return res, recs
+
+
+def estimate(g: Graph, mo: Motif, k, seed, tr: Tree = None) -> Result:
+    res = Result()
+    _check(lib().tm_estimate(g.h, C.byref(mo), C.byref(tr) if tr is not None else None, int(k),
+                             int(seed), _stream(), C.byref(res)), "estimate")
+    return res

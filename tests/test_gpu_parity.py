@@ -1,0 +1,271 @@
+"""GPU parity: the HIP path, called through the C ABI, against the oracle.
+
+Integers are compared bit for bit: the CSR arrays, every s-weight, W and
+every W_i, every per-sample record, the exact accumulators; the FP64
+estimate is the same formula on the same integers and must be identical.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle_helpers import all_tree_choices
+from paper_2507_20441_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-parity]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available(), "no HIP device"
+    from paper_2507_20441_amd import timest
+    timest.lib()
+    return timest
+
+
+def pair(T, g):
+    return O.Graph(g.src, g.dst, g.t, g.n), T.Graph(g.src, g.dst, g.t, g.n)
+
+
+def motifs_for(T, edges, delta):
+    return O.make_motif(edges, delta), T.make_motif(edges, delta)
+
+
+def trees_for(T, otr):
+    return otr, T.make_tree(list(otr.edge)[: otr.n_edges], otr.center)
+
+
+def rec_equal(a, b):
+    return bool((a == b).all())
+
+
+# ---------------------------------------------------------------------------
+# CSR build
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("m,seed,n,span", [(1, 1, 2, 10), (777, 2, 40, 300), (5000, 3, 300, 20000),
+                                           (40000, 4, 2000, 10**6)])
+def test_csr_matches_oracle(T, m, seed, n, span):
+    say("csr", m, seed)
+    g = W.small_graph(m, seed, n=n, span=span)
+    og, tg = pair(T, g)
+    s, d, t = og.edges()
+    assert (tg.export("src") == s).all() and (tg.export("dst") == d).all()
+    assert (tg.export("t") == t).all()
+    assert tg.info()["t_shift"] == og.shift
+    for name, direction, nbr in (("out", +1, d), ("in", -1, s)):
+        off = tg.export(f"{name}_off")
+        teid = tg.export(f"{name}_eid")
+        neid = tg.export(f"{name}n_eid")
+        assert off[0] == 0 and off[-1] == g.m
+        for v in range(g.n):
+            want = og.vertex_list(v, direction)
+            got = teid[off[v]:off[v + 1]]
+            assert (got == want).all(), (name, v)
+            # N order: the same edges by (neighbour, eid)
+            order = np.lexsort((want, nbr[want]))
+            assert (neid[off[v]:off[v + 1]] == want[order]).all(), (name, v)
+
+
+def test_graph_from_device_tensors(T):
+    import torch
+    g = W.small_graph(3000, 5, n=200, span=5000)
+    a = T.Graph(g.src, g.dst, g.t, g.n)
+    b = T.Graph(torch.from_numpy(g.src).cuda(), torch.from_numpy(g.dst).cuda(),
+                torch.from_numpy(g.t).cuda(), g.n)
+    for name in ("src", "dst", "t", "out_off", "in_off", "out_eid", "in_eid", "outn_eid", "inn_eid"):
+        assert (a.export(name) == b.export(name)).all(), name
+
+
+def test_graph_errors_match_oracle(T):
+    cases = [
+        ([0, 1], [1, 1], [5, 6], 3),          # self loop
+        ([0, 0], [1, 1], [5, 5], 3),          # duplicate tuple
+        ([0, 4], [1, 2], [5, 6], 3),          # id out of range
+        ([0, 1], [1, 2], [-(2**62), 2**62], 3),  # span too large
+    ]
+    for s, d, t, n in cases:
+        say("graph error case", s, d, t)
+        with pytest.raises(O.OracleError) as eo:
+            O.Graph(np.array(s), np.array(d), np.array(t), n)
+        with pytest.raises(T.TimestError) as eg:
+            T.Graph(np.array(s), np.array(d), np.array(t), n)
+        assert eo.value.code == eg.value.code
+
+
+# ---------------------------------------------------------------------------
+# Weights and samples
+# ---------------------------------------------------------------------------
+def check_prep(T, og, tg, edges, delta, otr, seeds=(1, 2), k=3000, g=None):
+    omo, tmo = motifs_for(T, edges, delta)
+    otr, ttr = trees_for(T, otr)
+    P = O.Prep(og, omo, otr)
+    Wt = T.Weights(tg, tmo, ttr)
+    info = Wt.info()
+    assert info["W"] == P.W
+    assert info["q"] == P.q
+    assert Wt.interval_weights() == P.interval_weights()
+    for s in list(otr.edge)[: otr.n_edges]:
+        for slot in (0, 1):
+            a = P.weights(s, slot)
+            b = Wt.weights(s, slot)
+            assert (a["lo"] == b["lo"]).all() and (a["hi"] == b["hi"]).all(), (s, slot)
+    for seed in seeds:
+        ro, reco = P.sample(seed, k, records=True)
+        rg, recg = Wt.sample(seed, k, records=True)
+        assert rec_equal(reco, recg), seed
+        assert rg.acc2.value == ro.acc2.value and rg.acc2_sq.value == ro.acc2_sq.value
+        assert (rg.n_valid, rg.n_bad_vertex, rg.n_bad_delta, rg.n_bad_order, rg.n_nonzero) == \
+               (ro.n_valid, ro.n_bad_vertex, ro.n_bad_delta, ro.n_bad_order, ro.n_nonzero)
+        assert rg.estimate == ro.estimate
+    return P, Wt
+
+
+MOTIF_CASES = [
+    ("3cycle", W.MOTIFS["3cycle"], 50),
+    ("4cycle", W.MOTIFS["4cycle"], 70),
+    ("4star", W.MOTIFS["4star"], 40),
+    ("scatter_gather", W.MOTIFS["scatter_gather"], 90),
+    ("6chain", W.MOTIFS["6chain"], 70),
+    ("lead_trail", ((0, 1), (1, 2), (2, 3), (3, 0), (0, 2)), 90),
+    ("parallel", ((0, 1), (1, 0), (0, 1)), 40),
+    ("in_star", ((1, 0), (2, 0), (0, 3)), 40),
+    ("single_edge", ((0, 1),), 30),
+]
+
+
+@pytest.mark.parametrize("name,edges,delta", MOTIF_CASES, ids=[c[0] for c in MOTIF_CASES])
+def test_every_tree_and_center_small_graph(T, name, edges, delta):
+    g = W.small_graph(300, 11, n=12, span=600)
+    og, tg = pair(T, g)
+    for j, otr in enumerate(all_tree_choices(edges)):
+        if j >= 10:
+            break
+        say(name, "tree", list(otr.edge)[: otr.n_edges], "center", otr.center)
+        check_prep(T, og, tg, edges, delta, otr, seeds=(3,), k=2000)
+
+
+@pytest.mark.parametrize("name,edges,delta", MOTIF_CASES[:6], ids=[c[0] for c in MOTIF_CASES[:6]])
+def test_default_tree_multi_tile_graph(T, name, edges, delta):
+    """Several scan and sort tiles with a ragged tail."""
+    g = W.small_graph(20011, 12, n=600, span=200000)
+    og, tg = pair(T, g)
+    say(name, "multi-tile")
+    check_prep(T, og, tg, edges, delta * 20, O.default_tree(O.make_motif(edges, 1)), seeds=(1, 9),
+               k=20000)
+
+
+def test_tiny_workload_full_run_is_bit_identical(T):
+    """The small workload in full: 1,000 vertices, 20,000 edges, 3-cycle at
+    delta = 1,000, 100,000 samples, seed 1."""
+    g = W.tiny_graph()
+    og, tg = pair(T, g)
+    (name, delta), = W.TINY["motifs"]
+    omo, tmo = motifs_for(T, W.MOTIFS[name], delta)
+    P = O.Prep(og, omo)
+    Wt = T.Weights(tg, tmo)
+    say("tiny full run")
+    ro, reco = P.sample(W.TINY["seed"], W.TINY["k"], records=True)
+    rg, recg = Wt.sample(W.TINY["seed"], W.TINY["k"], records=True)
+    assert rec_equal(reco, recg)
+    assert rg.estimate == ro.estimate and rg.acc2.value == ro.acc2.value
+    C = og.brute_count(omo)
+    assert abs(rg.estimate - C) <= 0.05 * C, (rg.estimate, C)
+
+
+def test_wide_weights_beyond_64_bits(T):
+    """An 8-vertex out-star on a hub with 1,500 out-edges inside one window:
+    every center weight is about 1500^6 > 2^64, so the 128-bit path runs."""
+    rng = np.random.default_rng(3)
+    hub_n = 1500
+    src = np.zeros(hub_n, np.int32)
+    dst = np.arange(1, hub_n + 1, dtype=np.int32)
+    t = rng.integers(0, 50, hub_n).astype(np.int64)
+    g = W.TemporalGraph(src, dst, t, hub_n + 1)
+    og, tg = pair(T, g)
+    edges = tuple((0, j) for j in range(1, 8))
+    omo, tmo = motifs_for(T, edges, 100)
+    say("wide")
+    P, Wt = check_prep(T, og, tg, edges, 100, O.default_tree(omo), seeds=(1,), k=4000)
+    assert P.W >= 2**64 and Wt.info()["wide"]
+
+
+def test_zero_weight_and_empty_graph(T):
+    # no 2-path can exist: every edge leaves vertex 0
+    g = W.TemporalGraph(np.zeros(5, np.int32), np.arange(1, 6, dtype=np.int32),
+                        np.arange(5, dtype=np.int64), 6)
+    og, tg = pair(T, g)
+    omo, tmo = motifs_for(T, W.MOTIFS["3cycle"], 10)
+    P, Wt = O.Prep(og, omo), T.Weights(tg, tmo)
+    ro, reco = P.sample(1, 50, records=True)
+    rg, recg = Wt.sample(1, 50, records=True)
+    assert P.W == 0 and Wt.W == 0 and rg.flags & T.TM_F_W_ZERO and rg.estimate == 0.0
+    assert rec_equal(reco, recg)
+    e = np.zeros(0, np.int64)
+    eg = T.Graph(e.astype(np.int32), e.astype(np.int32), e, 4)
+    res = T.estimate(eg, tmo, 100, 1)
+    assert res.W.value == 0 and res.estimate == 0.0
+
+
+def test_sample_ranges_compose(T):
+    g = W.small_graph(20000, 13, n=500, span=100000)
+    tg = T.Graph(g.src, g.dst, g.t, g.n)
+    Wt = T.Weights(tg, T.make_motif(W.MOTIFS["4cycle"], 2000))
+    say("ranges")
+    whole, rw = Wt.sample(7, 100000, records=True)
+    parts = [Wt.sample(7, 100000, j0=a, count=b - a, records=True)
+             for a, b in ((0, 1), (1, 40000), (40000, 99999), (99999, 100000))]
+    assert sum(p[0].acc2.value for p in parts) == whole.acc2.value
+    assert rec_equal(np.concatenate([p[1] for p in parts]), rw)
+    again, _ = Wt.sample(7, 100000)
+    assert again.acc2.value == whole.acc2.value and again.estimate == whole.estimate
+
+
+# ---------------------------------------------------------------------------
+# The benchmark workload at full size
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def medium(T):
+    g = W.medium_graph()
+    og, tg = pair(T, g)
+    return g, og, tg
+
+
+@pytest.mark.parametrize("name", ["4cycle", "4star"])
+def test_medium_workload_full_size(T, medium, name):
+    """100,000 vertices, 2,000,000 edges; 10^7 samples in the launch shape the
+    benchmark times; every weight, W_i, the first 200,000 samples' sum and
+    records of four sampled windows against the oracle."""
+    g, og, tg = medium
+    delta = dict(W.MEDIUM["motifs"])[name]
+    omo, tmo = motifs_for(T, W.MOTIFS[name], delta)
+    P = O.Prep(og, omo)
+    Wt = T.Weights(tg, tmo)
+    say("medium", name, "W", P.W)
+    assert Wt.W == P.W
+    assert Wt.interval_weights() == P.interval_weights()
+    for s in list(P.tr.edge)[: P.tr.n_edges]:
+        for slot in (0, 1):
+            a, b = P.weights(s, slot), Wt.weights(s, slot)
+            assert (a["lo"] == b["lo"]).all() and (a["hi"] == b["hi"]).all()
+    k, seed = W.MEDIUM["k"], W.MEDIUM["seed"]
+    full, _ = Wt.sample(seed, k)
+    head_o, _ = P.sample(seed, k, j0=0, count=200_000)
+    head_g, _ = Wt.sample(seed, k, j0=0, count=200_000)
+    assert head_o.acc2.value == head_g.acc2.value and head_o.n_valid == head_g.n_valid
+    for j0 in (0, 3_333_331, 7_000_000, k - 5000):
+        ro, reco = P.sample(seed, k, j0=j0, count=5000, records=True)
+        rg, recg = Wt.sample(seed, k, j0=j0, count=5000, records=True)
+        assert rec_equal(reco, recg), j0
+    # the whole run is the sum of its pieces
+    pieces = [Wt.sample(seed, k, j0=a, count=b - a)[0] for a, b in
+              ((0, 2_500_000), (2_500_000, 6_000_001), (6_000_001, k))]
+    assert sum(p.acc2.value for p in pieces) == full.acc2.value
+    assert sum(p.n_valid for p in pieces) == full.n_valid
+    assert full.estimate == float(P.W) * (float(full.acc2.value) / (2.0 * k))
