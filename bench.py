@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Throughput of the TIMEST hot path on one MI355X.
+
+One step is one pass of the whole path over the medium workload, starting
+from edge arrays already resident in device memory:
+  graph build (sort + lists) -> for each motif: weights -> 10^7 samples
+  (draw, validate, complete) -> reduction to the estimate.
+Workload: 100,000 vertices, 2,000,000 edges (Chung-Lu gamma = 2.1, bursty
+Pareto(1.5) per-source times over 1e7 s); 4-cycle and 4-leaf out-star at
+delta = 3,600 s; 10^7 samples per motif, seed 1.
+
+Prints one JSON line: samples/s over the timed steps, the roofline of the
+dominant kernel (bytes of its access model per launch over its average
+duration from HIP events on its stream) and the oracle's single-thread CPU
+throughput on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+STAGES = ["graph", "weights", "sample", "reduce"]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-samples", type=int, default=1_000_000,
+                    help="oracle samples per motif in the CPU baseline (0: skip it)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="before timing, run a plain device copy of BYTES (3 times) so that "
+                         "hardware counters can be scaled by a kernel of known traffic")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "sample_kernel_medium_traffic.json"),
+                    help="HBM bytes per launch from rocprofv3 counters (JSON), if present")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "this build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import ctypes as C
+
+    import torch
+
+    from paper_2507_20441_amd import timest as T
+    from paper_2507_20441_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    torch.cuda.set_device(0)
+    L = T.lib()
+    L.tm_profile_enable.argtypes = [C.c_int]
+    L.tm_profile_enable.restype = None
+
+    class Profile(C.Structure):
+        _fields_ = [("ms", C.c_double * 4), ("launches", C.c_uint64 * 4)]
+
+    L.tm_profile_read.argtypes = [C.POINTER(Profile), C.c_int]
+    L.tm_sample_model_bytes.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64,
+                                        C.c_void_p, C.POINTER(C.c_uint64)]
+
+    log("generating the medium workload")
+    g = W.medium_graph()
+    cfg = W.MEDIUM
+    k, seed = cfg["k"], cfg["seed"]
+    motifs = [(name, T.make_motif(W.MOTIFS[name], delta)) for name, delta in cfg["motifs"]]
+    src = torch.from_numpy(g.src).cuda()
+    dst = torch.from_numpy(g.dst).cuda()
+    tt = torch.from_numpy(g.t).cuda()
+    torch.cuda.synchronize()
+
+    def step():
+        G = T.Graph(src, dst, tt, g.n)
+        out = []
+        for _, mo in motifs:
+            Wt = T.Weights(G, mo)
+            res, _ = Wt.sample(seed, k)
+            out.append((res.estimate, res.std_error, res.n_valid, res.W.value))
+            Wt.close()
+        G.close()
+        return out
+
+    if args.copy_calibration > 0:
+        a = torch.empty(args.copy_calibration, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    log(f"warmup x{args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    prof = Profile()
+    L.tm_profile_read(C.byref(prof), 1)
+    L.tm_profile_enable(1)
+    log(f"timing x{args.steps}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        results = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    L.tm_profile_enable(0)
+    L.tm_profile_read(C.byref(prof), 1)
+    samples = len(motifs) * k * args.steps
+    value = samples / elapsed
+    stage_ms = {STAGES[i]: prof.ms[i] / args.steps for i in range(4)}
+    stage_launch = {STAGES[i]: prof.launches[i] for i in range(4)}
+    log("stage ms per step", stage_ms)
+
+    # Access-model bytes of the sampling kernel's launches in one step
+    # (counting pass, outside the timed region: same draws).
+    Gm = T.Graph(src, dst, tt, g.n)
+    model_bytes = 0
+    per_motif = []
+    for (name, mo), r in zip(motifs, results):
+        Wt = T.Weights(Gm, mo)
+        b = C.c_uint64()
+        rc = L.tm_sample_model_bytes(Wt.h, seed, 0, k, T._stream(), C.byref(b))
+        assert rc == 0, L.tm_last_error()
+        model_bytes += b.value
+        est, se, nvalid, Wv = r
+        per_motif.append(dict(motif=name, estimate=est, std_error=se,
+                              rel_ci95=(1.96 * se / est) if est else None, valid=nvalid, W=Wv,
+                              model_bytes=b.value))
+        Wt.close()
+    Gm.close()
+    sample_launches = stage_launch["sample"] / args.steps
+    sample_ms = stage_ms["sample"]
+    achieved = model_bytes / (sample_ms * 1e-3) / 1e9 if sample_ms > 0 else 0.0
+    traffic = None
+    if os.path.exists(args.traffic):
+        try:
+            tr = json.load(open(args.traffic))
+            traffic = tr.get("hbm_bytes_per_launch")
+        except (OSError, ValueError):
+            traffic = None
+    roofline = dict(bound="hbm", kernel="sample_kernel", achieved=round(achieved, 2),
+                    peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 5),
+                    traffic=traffic, bytes_per_launch=model_bytes / sample_launches,
+                    avg_launch_ms=sample_ms / sample_launches)
+
+    cpu = None
+    if args.cpu_samples > 0:
+        cpu = cpu_baseline(g, cfg, args.cpu_samples)
+
+    line = {
+        "metric": "samples/s at <=5% rel. err; batched-queue vs one-job-per-launch; p99 latency",
+        "value": round(value, 1),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": "medium: 100000 vertices, 2000000 edges (Chung-Lu 2.1, bursty Pareto 1.5 "
+                        "times over 1e7 s), 4-cycle and 4-star at delta 3600, 1e7 samples each, "
+                        "seed 1; graph build + weights + sampling + reduction per step",
+            "m": g.m, "n": g.n, "k_per_motif": k,
+        },
+        "stages_ms_per_step": {s: round(v, 3) for s, v in stage_ms.items()},
+        "estimates": per_motif,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(g, cfg, n_samples):
+    """The oracle, single-threaded, on the same workload: full graph build and
+    weights, then n_samples of the k samples per motif; the sampling time is
+    scaled linearly to k (samples are independent)."""
+    import oracle as O
+    from paper_2507_20441_amd import workloads as W
+    log(f"cpu baseline: oracle, {n_samples} samples per motif")
+    t0 = time.perf_counter()
+    og = O.Graph(g.src, g.dst, g.t, g.n)
+    t_graph = time.perf_counter() - t0
+    total = t_graph
+    k = cfg["k"]
+    for name, delta in cfg["motifs"]:
+        t1 = time.perf_counter()
+        P = O.Prep(og, O.make_motif(W.MOTIFS[name], delta))
+        t2 = time.perf_counter()
+        P.sample(cfg["seed"], k, j0=0, count=n_samples)
+        t3 = time.perf_counter()
+        total += (t2 - t1) + (t3 - t2) * (k / n_samples)
+    value = len(cfg["motifs"]) * k / total
+    return dict(value=round(value, 1), unit="samples/s", cores=1, kind="oracle",
+                sample=f"full graph build and weights for both motifs, {n_samples} of {k} samples "
+                       f"per motif; sampling time scaled linearly to {k}")
+
+
+if __name__ == "__main__":
+    main()

@@ -206,6 +206,35 @@ int tm_sample(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count, uint64_
 int tm_estimate(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint64_t k,
                 uint64_t seed, void* stream, tm_result* out);
 
+/* ---- measurement --------------------------------------------------------
+ * Device time of the library's stages, measured with HIP events recorded on
+ * the caller's stream around each stage's kernels (no extra synchronisation:
+ * the events are read when the call synchronises anyway). */
+enum tm_stage {
+    TM_STAGE_GRAPH = 0,    /* tm_graph_create: validation, sorts, lists */
+    TM_STAGE_WEIGHTS = 1,  /* tm_weights_create: all levels, prefix tables, intervals */
+    TM_STAGE_SAMPLE = 2,   /* the sampling kernel of tm_sample (draw, validate, complete) */
+    TM_STAGE_REDUCE = 3,   /* the final reduction of tm_sample */
+    TM_N_STAGES = 4
+};
+typedef struct {
+    double ms[TM_N_STAGES];          /* accumulated device milliseconds */
+    uint64_t launches[TM_N_STAGES];  /* timed stage executions */
+} tm_profile;
+
+/* Turn stage timing on (1) or off (0, the default); process-wide. */
+void tm_profile_enable(int on);
+/* Copy the accumulated times; reset = 1 clears them afterwards. */
+int tm_profile_read(tm_profile* out, int reset);
+
+/* Bytes the sampling kernel's access model requests for samples j0 ..
+ * j0 + count - 1 (a counting pass, not timed, same draws as tm_sample): every
+ * binary search over a range of L entries is charged ceil(log2(L + 1)) reads
+ * of its element size, every other read its element size; writes of records
+ * are not counted.  Used as the numerator of the sampler's roofline. */
+int tm_sample_model_bytes(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count,
+                          void* stream, uint64_t* bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -17,6 +18,35 @@ int tm_fail(int code, const char* fmt, ...) {
     vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
     va_end(ap);
     return code;
+}
+
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static tm_profile g_prof = {};
+
+bool prof_enabled() {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    return g_prof_on;
+}
+
+void prof_add(int stage, double ms) {
+    if (stage < 0 || stage >= TM_N_STAGES) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.ms[stage] += ms;
+    g_prof.launches[stage] += 1;
+}
+
+extern "C" void tm_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+}
+
+extern "C" int tm_profile_read(tm_profile* out, int reset) {
+    if (!out) return tm_fail(TM_EINVAL, "profile_read: NULL");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    *out = g_prof;
+    if (reset) g_prof = tm_profile{};
+    return TM_OK;
 }
 
 int DevArena::alloc(void** p, size_t nbytes) {
@@ -464,10 +494,18 @@ extern "C" int tm_sample(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t cou
                          uint64_t k_total, void* stream, tm_result* out, tm_sample_rec* recs) {
     if (!w || !out) return tm_fail(TM_EINVAL, "sample: NULL argument");
     if (count > 0 && j0 + count < j0) return tm_fail(TM_EINVAL, "sample: id range wraps");
-    TM_TRY(sample_run(w, seed, j0, count, k_total, as_stream(stream), out, recs));
+    TM_TRY(sample_run(w, seed, j0, count, k_total, as_stream(stream), out, recs, nullptr));
     finish_result(out);
     out->status = TM_OK;
     return TM_OK;
+}
+
+extern "C" int tm_sample_model_bytes(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count,
+                                     void* stream, uint64_t* bytes) {
+    if (!w || !bytes) return tm_fail(TM_EINVAL, "sample_model_bytes: NULL argument");
+    tm_result r;
+    return sample_run(w, seed, j0, count, count, as_stream(stream), &r, nullptr,
+                      reinterpret_cast<u64*>(bytes));
 }
 
 extern "C" int tm_estimate(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint64_t k,

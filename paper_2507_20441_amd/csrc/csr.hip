@@ -157,6 +157,8 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
         return TM_OK;
     }
 
+    StageTimer timer;
+    timer.start(TM_STAGE_GRAPH, st);
     // --- validation: ids, self loops, time span -------------------------
     int* flags = nullptr;
     u64* tbounds = nullptr;
@@ -302,7 +304,9 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
     TM_HIP(hipMemcpyAsync(hflags, flags, sizeof hflags, hipMemcpyDeviceToHost, st));
     TM_HIP(hipFreeAsync(flags, st));
     TM_HIP(hipFreeAsync(tbounds, st));
+    timer.stop();
     TM_HIP(hipStreamSynchronize(st));
+    timer.finish();
     if (hflags[1]) return tm_fail(TM_EDEVICE, "graph: internal scan overflow");
     return TM_OK;
 }

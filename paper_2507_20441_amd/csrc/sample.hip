@@ -47,7 +47,11 @@ struct Partial {
     u128 acc2, acc2_sq;
     u64 n_valid, n_vertex, n_delta, n_order, n_nonzero;
     u64 flags;  // bit 0: acc2 wrapped, bit 1: acc2_sq saturated
+    u64 bytes;  // access-model bytes (counting pass only)
 };
+
+// Reads charged to one binary search over L entries: ceil(log2(L + 1)).
+__device__ __forceinline__ u64 probes(int64_t L) { return L <= 0 ? 0 : (u64)(64 - __clzll((u64)L)); }
 
 // --------------------------------------------------------------------------
 // Completion counting (Alg. 5).  Chains over the multi-edge lists of
@@ -63,9 +67,10 @@ struct Run {
     int n;
 };
 
+template <bool kCount>
 __device__ __forceinline__ void run_bounds(const DevGraph& G, const int32_t* img_v, const int* fs,
                                            const int* fd, int first, int len, int64_t lo, int64_t hi,
-                                           Run& R) {
+                                           Run& R, u64& nb) {
     R.n = len;
     if (lo < 0) lo = 0;
     if (hi > G.T) hi = G.T;
@@ -79,12 +84,16 @@ __device__ __forceinline__ void run_bounds(const DevGraph& G, const int32_t* img
         const u64 base = (u64)y << G.bt;
         R.a[j] = lower_bound_pos<u64>(G.nkey[0], a, b, base | (u64)lo);
         R.b[j] = upper_bound_pos<u64>(G.nkey[0], R.a[j], b, base | (u64)hi);
+        if constexpr (kCount) nb += 8 + (probes(b - a) + probes(b - R.a[j])) * 8;
     }
 }
 
-__device__ __forceinline__ u128 chain_count(const DevGraph& G, const Run& R, bool* ovf) {
+template <bool kCount>
+__device__ __forceinline__ u128 chain_count(const DevGraph& G, const Run& R, bool* ovf, u64& nb) {
     if (R.n == 0) return 1;
     if (R.n == 1) return (u128)(R.b[0] - R.a[0]);
+    if constexpr (kCount)
+        for (int j = 0; j < R.n; ++j) nb += (u64)(R.b[j] - R.a[j]) * 8;
     const u64 tmask = (G.bt >= 64) ? ~0ull : ((1ull << G.bt) - 1);
     u128 S[TM_MAX_L];
     int32_t p[TM_MAX_L];
@@ -118,7 +127,7 @@ __device__ __forceinline__ W child_mass(const Window& w, bool leaf, const W* qt,
     return (qt[w.p1] - qt[w.p0]) - (qn[w.q1] - qn[w.q0]);
 }
 
-template <typename W>
+template <typename W, bool kCount>
 __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
     const DevGraph& G = a.G;
     const W Wtot = (W)(((u128)a.W_hi << 64) | a.W_lo);
@@ -128,6 +137,8 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
     acc.acc2_sq = 0;
     acc.n_valid = acc.n_vertex = acc.n_delta = acc.n_order = acc.n_nonzero = 0;
     acc.flags = 0;
+    acc.bytes = 0;
+    u64 nb = 0;
     bool ovf = false;
     bool bad = false;
     const u64 stride = (u64)gridDim.x * kBlock;
@@ -149,6 +160,8 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
         // an interval with positive W_i holds edges; positions stay inside it
         if (hi <= lo) { bad = true; break; }
         e0 = e0 < lo ? lo : (e0 >= hi ? hi - 1 : e0);
+        if constexpr (kCount)
+            nb += (probes(a.q + 1) + 2 + probes(hi - lo)) * sizeof(W) + 8 + 16;
         img_e[0] = e0;
         te[0] = G.t[e0];
         eu[0] = G.src[e0];
@@ -194,6 +207,13 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
                 pos = upper_bound_pos<W>(qt, w.p0 + 1, w.p1 + 1, tgt) - 1;
             }
             pos = pos < w.p0 ? w.p0 : (pos >= w.p1 ? w.p1 - 1 : pos);
+            if constexpr (kCount) {
+                const int32_t la = G.off[d][g], lb = G.off[d][g + 1];
+                nb += 8 + (2 * probes(lb - la) + probes(lb - w.p0) + probes(lb - w.q0)) * 8;
+                nb += probes(w.q1 - w.q0) * (4 + (leaf ? 0 : 2 * sizeof(W)));
+                if (!leaf) nb += (5 + probes(w.p1 - w.p0)) * sizeof(W);
+                nb += 16;
+            }
             const int32_t e = G.leid[d][pos];
             const int32_t nb = G.lnbr[d][pos];
             img_e[s] = e;
@@ -233,40 +253,40 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
                 const int pv = a.run_prev[rr], nx = a.run_next[rr];
                 if (pv < 0) { lead = rr; continue; }
                 if (nx < 0) { trail = rr; continue; }
-                run_bounds(G, img_v, a.free_src, a.free_dst, a.run_first[rr], a.run_len[rr],
-                           te[pv] + 1, te[nx] - 1, R);
-                const u128 c = chain_count(G, R, &ovf);
+                run_bounds<kCount>(G, img_v, a.free_src, a.free_dst, a.run_first[rr], a.run_len[rr],
+                           te[pv] + 1, te[nx] - 1, R, nb);
+                const u128 c = chain_count<kCount>(G, R, &ovf, nb);
                 if (!mul_ok(m_phi, c, &m_phi)) ovf = true;
             }
             if (m_phi != 0 && lead >= 0 && trail < 0) {
-                run_bounds(G, img_v, a.free_src, a.free_dst, a.run_first[lead], a.run_len[lead],
-                           tlast - a.delta, tfirst - 1, R);
-                if (!mul_ok(m_phi, chain_count(G, R, &ovf), &m_phi)) ovf = true;
+                run_bounds<kCount>(G, img_v, a.free_src, a.free_dst, a.run_first[lead], a.run_len[lead],
+                           tlast - a.delta, tfirst - 1, R, nb);
+                if (!mul_ok(m_phi, chain_count<kCount>(G, R, &ovf, nb), &m_phi)) ovf = true;
             } else if (m_phi != 0 && trail >= 0 && lead < 0) {
-                run_bounds(G, img_v, a.free_src, a.free_dst, a.run_first[trail], a.run_len[trail],
-                           tlast + 1, tfirst + a.delta, R);
-                if (!mul_ok(m_phi, chain_count(G, R, &ovf), &m_phi)) ovf = true;
+                run_bounds<kCount>(G, img_v, a.free_src, a.free_dst, a.run_first[trail], a.run_len[trail],
+                           tlast + 1, tfirst + a.delta, R, nb);
+                if (!mul_ok(m_phi, chain_count<kCount>(G, R, &ovf, nb), &m_phi)) ovf = true;
             } else if (m_phi != 0 && trail >= 0 && lead >= 0) {
                 // the first edge f of the leading chain fixes the window end
                 // t(f) + delta of the trailing chain
                 Run F;
-                run_bounds(G, img_v, a.free_src, a.free_dst, a.run_first[lead], 1,
-                           tlast - a.delta, tfirst - 1, F);
+                run_bounds<kCount>(G, img_v, a.free_src, a.free_dst, a.run_first[lead], 1,
+                           tlast - a.delta, tfirst - 1, F, nb);
                 const u64 tmask = (G.bt >= 64) ? ~0ull : ((1ull << G.bt) - 1);
                 u128 sum = 0;
                 for (int32_t x = F.a[0]; x < F.b[0]; ++x) {
                     const int64_t tf = (int64_t)(G.nkey[0][x] & tmask);
                     u128 lc = 1;
                     if (a.run_len[lead] > 1) {
-                        run_bounds(G, img_v, a.free_src, a.free_dst, a.run_first[lead] + 1,
-                                   a.run_len[lead] - 1, tf + 1, tfirst - 1, R);
-                        lc = chain_count(G, R, &ovf);
+                        run_bounds<kCount>(G, img_v, a.free_src, a.free_dst, a.run_first[lead] + 1,
+                                   a.run_len[lead] - 1, tf + 1, tfirst - 1, R, nb);
+                        lc = chain_count<kCount>(G, R, &ovf, nb);
                     }
                     if (lc == 0) continue;
-                    run_bounds(G, img_v, a.free_src, a.free_dst, a.run_first[trail],
-                               a.run_len[trail], tlast + 1, tf + a.delta, R);
+                    run_bounds<kCount>(G, img_v, a.free_src, a.free_dst, a.run_first[trail],
+                               a.run_len[trail], tlast + 1, tf + a.delta, R, nb);
                     u128 prod;
-                    if (!mul_ok(lc, chain_count(G, R, &ovf), &prod)) ovf = true;
+                    if (!mul_ok(lc, chain_count<kCount>(G, R, &ovf, nb), &prod)) ovf = true;
                     if (!add_ok(sum, prod, &sum)) ovf = true;
                 }
                 if (!mul_ok(m_phi, sum, &m_phi)) ovf = true;
@@ -299,6 +319,7 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
             out.m_phi.hi = (u64)(m_phi >> 64);
         }
     }
+    acc.bytes = nb;
     // block reduction into one partial
     __shared__ Partial red[kBlock];
     red[threadIdx.x] = acc;
@@ -315,6 +336,7 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
             x.n_order += y.n_order;
             x.n_nonzero += y.n_nonzero;
             x.flags |= y.flags;
+            x.bytes += y.bytes;
         }
         __syncthreads();
     }
@@ -330,6 +352,7 @@ __global__ void __launch_bounds__(kBlock) reduce_kernel(const Partial* parts, in
     acc.acc2_sq = 0;
     acc.n_valid = acc.n_vertex = acc.n_delta = acc.n_order = acc.n_nonzero = 0;
     acc.flags = 0;
+    acc.bytes = 0;
     for (int b = threadIdx.x; b < n; b += kBlock) {
         const Partial& y = parts[b];
         if (!add_ok(acc.acc2, y.acc2, &acc.acc2)) acc.flags |= 1;
@@ -340,6 +363,7 @@ __global__ void __launch_bounds__(kBlock) reduce_kernel(const Partial* parts, in
         acc.n_order += y.n_order;
         acc.n_nonzero += y.n_nonzero;
         acc.flags |= y.flags;
+        acc.bytes += y.bytes;
     }
     __shared__ Partial red[kBlock];
     red[threadIdx.x] = acc;
@@ -356,6 +380,7 @@ __global__ void __launch_bounds__(kBlock) reduce_kernel(const Partial* parts, in
             x.n_order += y.n_order;
             x.n_nonzero += y.n_nonzero;
             x.flags |= y.flags;
+            x.bytes += y.bytes;
         }
         __syncthreads();
     }
@@ -377,7 +402,11 @@ __global__ void fill_undrawn_kernel(tm_sample_rec* recs, u64 count) {
 }  // namespace
 
 int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStream_t st,
-               tm_result* out, tm_sample_rec* recs) {
+               tm_result* out, tm_sample_rec* recs, u64* model_bytes) {
+    if (model_bytes) {
+        *model_bytes = 0;
+        recs = nullptr;
+    }
     const HostPlan& P = w->plan;
     std::memset(out, 0, sizeof *out);
     out->k = k_total;
@@ -450,14 +479,25 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
     TM_HIP(hipMemsetAsync(ovf, 0, sizeof(int), st));
     a.parts = parts;
     a.ovf = ovf;
-    if (w->wide)
-        hipLaunchKernelGGL((sample_kernel<u128>), dim3(blocks), dim3(kBlock), 0, st, a);
-    else
-        hipLaunchKernelGGL((sample_kernel<u64>), dim3(blocks), dim3(kBlock), 0, st, a);
+    StageTimer t_sample, t_reduce;
+    if (!model_bytes) t_sample.start(TM_STAGE_SAMPLE, st);
+    if (model_bytes) {
+        if (w->wide)
+            hipLaunchKernelGGL((sample_kernel<u128, true>), dim3(blocks), dim3(kBlock), 0, st, a);
+        else
+            hipLaunchKernelGGL((sample_kernel<u64, true>), dim3(blocks), dim3(kBlock), 0, st, a);
+    } else if (w->wide) {
+        hipLaunchKernelGGL((sample_kernel<u128, false>), dim3(blocks), dim3(kBlock), 0, st, a);
+    } else {
+        hipLaunchKernelGGL((sample_kernel<u64, false>), dim3(blocks), dim3(kBlock), 0, st, a);
+    }
     TM_HIP(hipGetLastError());
+    t_sample.stop();
+    if (!model_bytes) t_reduce.start(TM_STAGE_REDUCE, st);
     hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const Partial*)parts, blocks,
                        parts + blocks);
     TM_HIP(hipGetLastError());
+    t_reduce.stop();
     Partial h;
     int hovf = 0;
     TM_HIP(hipMemcpyAsync(&h, parts + blocks, sizeof h, hipMemcpyDeviceToHost, st));
@@ -465,6 +505,9 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
     TM_HIP(hipFreeAsync(parts, st));
     TM_HIP(hipFreeAsync(ovf, st));
     TM_HIP(hipStreamSynchronize(st));
+    t_sample.finish();
+    t_reduce.finish();
+    if (model_bytes) *model_bytes = h.bytes;
     if (hovf & 2) return tm_fail(TM_EDEVICE, "sample: inconsistent weight tables");
     if (hovf || (h.flags & 1)) return tm_fail(TM_EOVERFLOW, "sample: a count reaches 2^128");
     out->acc2.lo = (u64)h.acc2;

@@ -119,4 +119,42 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
                 hipStream_t st);
 int weights_build(tm_weights* w, hipStream_t st);
 int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStream_t st,
-               tm_result* out, tm_sample_rec* recs);
+               tm_result* out, tm_sample_rec* recs, u64* model_bytes);
+
+// ---------------------------------------------------------------------------
+// Stage timing with HIP events on the call's stream (tm_profile_enable).
+// ---------------------------------------------------------------------------
+bool prof_enabled();
+void prof_add(int stage, double ms);
+
+struct StageTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t st = nullptr;
+    int stage = 0;
+    bool on = false;
+    void start(int stage_, hipStream_t st_) {
+        stage = stage_;
+        st = st_;
+        on = prof_enabled() && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
+        if (on) (void)hipEventRecord(a, st);
+    }
+    void stop() {
+        if (on) (void)hipEventRecord(b, st);
+    }
+    // after the stream has been synchronised
+    void finish() {
+        if (!on) return;
+        float ms = 0.f;
+        if (hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess)
+            prof_add(stage, ms);
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        on = false;
+    }
+    ~StageTimer() {
+        if (on) {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    }
+};

@@ -223,6 +223,8 @@ int weights_build(tm_weights* w, hipStream_t st) {
         return TM_OK;
     }
     if (w->q >= ((int64_t)1 << 31)) return tm_fail(TM_ERANGE, "weights: too many intervals");
+    StageTimer timer;
+    timer.start(TM_STAGE_WEIGHTS, st);
     int* ovf = nullptr;
     TM_HIP(hipMallocAsync((void**)&ovf, sizeof(int), st));
     int h = 0;
@@ -239,7 +241,9 @@ int weights_build(tm_weights* w, hipStream_t st) {
         if (wide) rc = tm_fail(TM_EOVERFLOW, "weights: a weight or W reaches 2^128");
     }
     TM_HIP(hipFreeAsync(ovf, st));
+    timer.stop();
     TM_HIP(hipStreamSynchronize(st));
+    timer.finish();
     if (rc != TM_OK) clear_tables(w);
     return rc;
 }
