@@ -145,11 +145,13 @@ def main():
     sample_launches = stage_launch["sample"] / args.steps
     sample_ms = stage_ms["sample"]
     achieved = model_bytes / (sample_ms * 1e-3) / 1e9 if sample_ms > 0 else 0.0
+    # counter-measured bytes, valid only for the kernel source they were taken on
     traffic = None
     if os.path.exists(args.traffic):
         try:
             tr = json.load(open(args.traffic))
-            traffic = tr.get("hbm_bytes_per_launch")
+            if tr.get("source_sha") == kernel_source_sha():
+                traffic = tr.get("hbm_bytes_per_launch")
         except (OSError, ValueError):
             traffic = None
     roofline = dict(bound="hbm", kernel="sample_kernel", achieved=round(achieved, 2),
@@ -186,6 +188,16 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def kernel_source_sha():
+    """Hash of the sampling kernel's sources (the counters' validity key)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("sample.hip", "tm_common.h", "tm_primitives.h", "tm_internal.h"):
+        with open(os.path.join(ROOT, "paper_2507_20441_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(g, cfg, n_samples):
