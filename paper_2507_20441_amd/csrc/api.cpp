@@ -49,10 +49,26 @@ extern "C" int tm_profile_read(tm_profile* out, int reset) {
     return TM_OK;
 }
 
+void pool_setup() {
+    static std::mutex mu;
+    static bool done[64] = {false};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+    std::lock_guard<std::mutex> lk(mu);
+    if (done[dev]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t keep = ~0ull;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    done[dev] = true;
+}
+
 int DevArena::alloc(void** p, size_t nbytes) {
     *p = nullptr;
     if (nbytes == 0) nbytes = 16;
-    hipError_t e = hipMalloc(p, nbytes);
+    nbytes = (nbytes + 255) & ~(size_t)255;
+    hipError_t e = hipMallocAsync(p, nbytes, stream);
     if (e != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
@@ -65,7 +81,8 @@ int DevArena::alloc(void** p, size_t nbytes) {
 }
 
 void DevArena::release() {
-    for (void* p : blocks) (void)hipFree(p);
+    for (void* p : blocks) (void)hipFreeAsync(p, stream);
+    if (!blocks.empty()) (void)hipStreamSynchronize(stream);
     blocks.clear();
     bytes = 0;
 }
@@ -183,6 +200,9 @@ int plan_build(const tm_motif* mo, const tm_tree* tr, HostPlan* P) {
         H.height[s] = h;
     }
     H.H = H.height[0];
+    for (int s = 0; s < H.nt; ++s)
+        H.same_window[s] = s > 1 && H.parent[s] == H.parent[s - 1] && H.side[s] == H.side[s - 1] &&
+                           H.alpha[s] == H.alpha[s - 1] && H.beta[s] == H.beta[s - 1];
     int r = 0;
     for (int p = 0; p < mo->l; ++p)
         if (H.slot_of_edge[p] >= 0) H.by_pi[r++] = H.slot_of_edge[p];
@@ -296,6 +316,8 @@ extern "C" int tm_graph_create(const int32_t* src, const int32_t* dst, const int
     g->m = m;
     g->n = n;
     (void)hipGetDevice(&g->device);
+    pool_setup();
+    g->arena.stream = st;
     const int32_t *ds = src, *dd = dst;
     const int64_t* dt = t;
     void* staged[3] = {nullptr, nullptr, nullptr};
@@ -381,6 +403,8 @@ extern "C" int tm_weights_create(tm_graph* g, const tm_motif* mo, const tm_tree*
     tm_weights* w = new (std::nothrow) tm_weights();
     if (!w) return tm_fail(TM_ENOMEM, "weights: host allocation");
     w->g = g;
+    w->arena.stream = as_stream(stream);
+    pool_setup();
     int rc = plan_build(mo, tr, &w->plan);
     if (rc == TM_OK) rc = weights_build(w, as_stream(stream));
     if (rc != TM_OK) {

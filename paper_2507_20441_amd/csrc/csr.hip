@@ -36,7 +36,22 @@ validate_kernel(const int32_t* src, const int32_t* dst, const int64_t* t, int64_
         hi = b > hi ? b : hi;
         f |= __shfl_xor(f, d, 64);
     }
+    // one atomic per block: the waves meet in LDS first
+    __shared__ u64 slo[kWaves], shi[kWaves];
+    __shared__ int sf[kWaves];
+    const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
+        slo[wave] = lo;
+        shi[wave] = hi;
+        sf[wave] = f;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kWaves; ++w) {
+            lo = slo[w] < lo ? slo[w] : lo;
+            hi = shi[w] > hi ? shi[w] : hi;
+            f |= sf[w];
+        }
         atomicMin(tmin, lo);
         atomicMax(tmax, hi);
         if (f) atomicOr(flags, f);
@@ -168,7 +183,7 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
     TM_HIP(hipMemsetAsync(flags, 0, sizeof(int) * 2, st));
     TM_HIP(hipMemcpyAsync(tbounds, init, sizeof init, hipMemcpyHostToDevice, st));
     {
-        const unsigned blocks = (unsigned)std::min<int64_t>(grid_for(m), 4096);
+        const unsigned blocks = (unsigned)std::min<int64_t>(grid_for(m), 1024);
         hipLaunchKernelGGL(validate_kernel, dim3(blocks), dim3(kBlock), 0, st, src, dst, t, m, n,
                            flags, tbounds, tbounds + 1);
         TM_HIP(hipGetLastError());

@@ -2,15 +2,24 @@
 //
 // One lane per sample.  Draw 0 picks (interval, center edge) by inverse CDF
 // over the pairs in (interval, eid) order: a search of the interval prefix
-// W_i, then of the center's prefix array inside the interval.  Each further
-// tree edge, in pre-order, is drawn by inverse CDF over its candidate list:
-// the window of the shared vertex's list minus the run of edges to the
-// excluded vertex.  The excluded entries sit at known T-order positions
-// (xref), so the number J of excluded entries before the answer is found by a
-// search over the excluded run, and the answer by one more search of the
-// window's prefix array at the target shifted by their weight.
+// W_i (staged in LDS when it fits), then of the center's prefix array inside
+// the interval.  Each further tree edge, in pre-order, is drawn by inverse CDF
+// over its candidate list: the window of the shared vertex's list minus the
+// run of edges to the excluded vertex.  The excluded entries sit at known
+// T-order positions (xref), so the number J of excluded entries before the
+// answer is found by a search over the excluded run, and the answer by one
+// more search of the window's prefix array at the target shifted by their
+// weight.
+//
+// Each sample's state (matched eid, endpoints and time per tree slot, image
+// per motif vertex) stays in registers: loops over tree slots are unrolled to
+// the largest tree, and slot and vertex indices from the plan are uniform
+// kernel arguments, resolved by selects rather than indexed memory.  Runs of
+// three or more non-tree edges, or a leading and a trailing run coupled by
+// delta, take a separate kernel variant with the general chain counter.
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include "tm_primitives.h"
 
@@ -26,17 +35,21 @@ struct SampleArgs {
     int parent[kMaxSlots], side[kMaxSlots], dir[kMaxSlots], beta[kMaxSlots], leaf[kMaxSlots];
     int new_vertex[kMaxSlots];
     int by_pi[kMaxSlots];
+    int same_window[kMaxSlots];
     const void* qt[kMaxSlots][2];
     const void* qn[kMaxSlots][2];
     const void* qc[2];
     const int32_t* ilo;
     const int32_t* ihi;
     const void* cumW;
+    int cum_in_lds;  // the q+1 interval prefix fits the block's LDS
     u64 W_lo, W_hi;
     int n_free;
     int free_src[TM_MAX_L], free_dst[TM_MAX_L];
     int n_runs;
     int run_first[TM_MAX_L], run_len[TM_MAX_L], run_prev[TM_MAX_L], run_next[TM_MAX_L];
+    int general_runs;  // some run needs the general chain counter (3+ lists, or a
+                       // leading and a trailing run coupled by delta)
     u64 seed, j0, count;
     tm_sample_rec* recs;
     struct Partial* parts;
@@ -50,65 +63,186 @@ struct Partial {
     u64 bytes;  // access-model bytes (counting pass only)
 };
 
+constexpr int kCumLdsBytes = 24 * 1024;
+
 // Reads charged to one binary search over L entries: ceil(log2(L + 1)).
 __device__ __forceinline__ u64 probes(int64_t L) { return L <= 0 ? 0 : (u64)(64 - __clzll((u64)L)); }
 
-// --------------------------------------------------------------------------
-// Completion counting (Alg. 5).  Chains over the multi-edge lists of
-// consecutive non-tree motif edges: every list is a run of the source's
-// out-list in (destination, time) order, restricted to [lo, hi]; a chain
-// takes one edge per list with strictly increasing times.  Merge-sweep over
-// the lists in time order; S[j] counts chains ending in list j so far.  On
-// equal times the later list goes first, so it never extends an edge of the
-// same time.
-// --------------------------------------------------------------------------
-struct Run {
-    int32_t a[TM_MAX_L], b[TM_MAX_L];  // [a, b) in the out-list N order
-    int n;
-};
-
-template <bool kCount>
-__device__ __forceinline__ void run_bounds(const DevGraph& G, const int32_t* img_v, const int* fs,
-                                           const int* fd, int first, int len, int64_t lo, int64_t hi,
-                                           Run& R, u64& nb) {
-    R.n = len;
-    if (lo < 0) lo = 0;
-    if (hi > G.T) hi = G.T;
-    for (int j = 0; j < len; ++j) {
-        const int32_t x = img_v[fs[first + j]], y = img_v[fd[first + j]];
-        const int32_t a = G.off[0][x], b = G.off[0][x + 1];
-        if (lo > hi) {
-            R.a[j] = R.b[j] = a;
-            continue;
-        }
-        const u64 base = (u64)y << G.bt;
-        R.a[j] = lower_bound_pos<u64>(G.nkey[0], a, b, base | (u64)lo);
-        R.b[j] = upper_bound_pos<u64>(G.nkey[0], R.a[j], b, base | (u64)hi);
-        if constexpr (kCount) nb += 8 + (probes(b - a) + probes(b - R.a[j])) * 8;
+// Compile-time loop: f(integral_constant<I>) for I in [B, E).  Register
+// arrays are only ever indexed by these constants, so they never become
+// stack memory.
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(static_cast<F&&>(f));
     }
 }
 
-template <bool kCount>
-__device__ __forceinline__ u128 chain_count(const DevGraph& G, const Run& R, bool* ovf, u64& nb) {
-    if (R.n == 0) return 1;
-    if (R.n == 1) return (u128)(R.b[0] - R.a[0]);
-    if constexpr (kCount)
-        for (int j = 0; j < R.n; ++j) nb += (u64)(R.b[j] - R.a[j]) * 8;
-    const u64 tmask = (G.bt >= 64) ? ~0ull : ((1ull << G.bt) - 1);
-    u128 S[TM_MAX_L];
-    int32_t p[TM_MAX_L];
-    for (int j = 0; j < R.n; ++j) {
-        S[j] = 0;
-        p[j] = R.a[j];
+template <int N, typename T>
+__device__ __forceinline__ T pick(const T (&v)[N], int idx) {
+    T r = v[0];
+    sfor<1, N>([&](auto j) { r = (idx == decltype(j)::value) ? v[decltype(j)::value] : r; });
+    return r;
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void put(T (&v)[N], int idx, T x) {
+    sfor<0, N>([&](auto j) { v[decltype(j)::value] = (idx == decltype(j)::value) ? x : v[decltype(j)::value]; });
+}
+
+// ---------------------------------------------------------------------------
+// Branchless searches.  Each step halves the candidate range; the final step
+// settles the last element.  Several searches over the same range run in
+// lockstep so that their loads are independent.
+// ---------------------------------------------------------------------------
+struct Bounds {
+    int32_t p0, p1;  // T-order window [p0, p1)
+    int32_t q0, q1;  // N-order excluded run [q0, q1)
+    int32_t a, b;    // the vertex's list
+};
+
+// The child window of Claim "matching-edges-set" in list dir of vertex g with
+// time in [wlo, whi], and the run of edges whose far endpoint is o.
+__device__ __forceinline__ Bounds window_bounds(const DevGraph& G, int dir, int32_t g, int32_t o,
+                                                int64_t wlo, int64_t whi) {
+    Bounds r;
+    r.a = G.off[dir][g];
+    r.b = G.off[dir][g + 1];
+    if (wlo < 0) wlo = 0;
+    if (whi > G.T) whi = G.T;
+    if (wlo > whi || r.a == r.b) {
+        r.p0 = r.p1 = r.q0 = r.q1 = r.a;
+        return r;
     }
+    const int64_t* lt = G.lt[dir];
+    const u64* nk = G.nkey[dir];
+    const u64 base = (u64)o << G.bt;
+    const u64 klo = base | (u64)wlo, khi = base | (u64)whi;
+    int32_t b0 = r.a, b1 = r.a, b2 = r.a, b3 = r.a;
+    int32_t n = r.b - r.a;
+    while (n > 1) {
+        const int32_t h = n >> 1;
+        const int64_t x0 = lt[b0 + h], x1 = lt[b1 + h];
+        const u64 x2 = nk[b2 + h], x3 = nk[b3 + h];
+        b0 = x0 < wlo ? b0 + h : b0;
+        b1 = x1 <= whi ? b1 + h : b1;
+        b2 = x2 < klo ? b2 + h : b2;
+        b3 = x3 <= khi ? b3 + h : b3;
+        n -= h;
+    }
+    r.p0 = b0 + (lt[b0] < wlo ? 1 : 0);
+    r.p1 = b1 + (lt[b1] <= whi ? 1 : 0);
+    r.q0 = b2 + (nk[b2] < klo ? 1 : 0);
+    r.q1 = b3 + (nk[b3] <= khi ? 1 : 0);
+    return r;
+}
+
+// First index in [lo, hi) with a[idx] > key (hi if none).
+template <typename T>
+__device__ __forceinline__ int32_t upper_bound_bl(const T* a, int32_t lo, int32_t hi, T key) {
+    int32_t n = hi - lo;
+    if (n <= 0) return lo;
+    int32_t b = lo;
+    while (n > 1) {
+        const int32_t h = n >> 1;
+        b = a[b + h] <= key ? b + h : b;
+        n -= h;
+    }
+    return b + (a[b] <= key ? 1 : 0);
+}
+
+// The multi-edge run El_{x,y} restricted to times [lo, hi]: a contiguous run
+// of x's out-list in (destination, time) order.
+__device__ __forceinline__ void el_run(const DevGraph& G, int32_t x, int32_t y, int64_t lo, int64_t hi,
+                                       int32_t& ra, int32_t& rb, int32_t& la, int32_t& lb) {
+    la = G.off[0][x];
+    lb = G.off[0][x + 1];
+    if (lo < 0) lo = 0;
+    if (hi > G.T) hi = G.T;
+    if (lo > hi || la == lb) {
+        ra = rb = la;
+        return;
+    }
+    const u64* nk = G.nkey[0];
+    const u64 base = (u64)y << G.bt;
+    const u64 klo = base | (u64)lo, khi = base | (u64)hi;
+    int32_t b0 = la, b1 = la;
+    int32_t n = lb - la;
+    while (n > 1) {
+        const int32_t h = n >> 1;
+        const u64 x0 = nk[b0 + h], x1 = nk[b1 + h];
+        b0 = x0 < klo ? b0 + h : b0;
+        b1 = x1 <= khi ? b1 + h : b1;
+        n -= h;
+    }
+    ra = b0 + (nk[b0] < klo ? 1 : 0);
+    rb = b1 + (nk[b1] <= khi ? 1 : 0);
+}
+
+__device__ __forceinline__ u64 tmask_of(const DevGraph& G) {
+    return G.bt >= 64 ? ~0ull : ((1ull << G.bt) - 1);
+}
+
+// ---------------------------------------------------------------------------
+// Completion counting (Alg. 5).  A run of consecutive non-tree motif edges
+// takes one edge from each of its multi-edge lists with strictly increasing
+// times inside [lo, hi].  One list: its length.  Two lists: a two-pointer
+// merge.  More lists, or a leading and a trailing run coupled by delta: the
+// general counter below (a merge-sweep with one counter per list).
+// ---------------------------------------------------------------------------
+template <bool kCount>
+__device__ __forceinline__ u128 run_count_short(const DevGraph& G, int32_t x0, int32_t y0, int32_t x1,
+                                                int32_t y1, int len, int64_t lo, int64_t hi, u64& nb) {
+    int32_t a0, b0, la0, lb0;
+    el_run(G, x0, y0, lo, hi, a0, b0, la0, lb0);
+    if constexpr (kCount) nb += 8 + 2 * probes(lb0 - la0) * 8;
+    if (len == 1) return (u128)(b0 - a0);
+    int32_t a1, b1, la1, lb1;
+    el_run(G, x1, y1, lo, hi, a1, b1, la1, lb1);
+    if constexpr (kCount) nb += 8 + 2 * probes(lb1 - la1) * 8 + (u64)(b0 - a0 + b1 - a1) * 8;
+    // pairs (e, f), e in the first list, f in the second, t(e) < t(f)
+    const u64* nk = G.nkey[0];
+    const u64 m = tmask_of(G);
+    u128 total = 0;
+    int32_t p = a0;
+    for (int32_t f = a1; f < b1; ++f) {
+        const u64 tf = nk[f] & m;
+        while (p < b0 && (nk[p] & m) < tf) ++p;
+        total += (u128)(p - a0);
+    }
+    return total;
+}
+
+struct V8 {
+    int32_t v[TM_MAX_K];
+};
+
+// Chains through the lists of free edges first .. first+len-1 with times in
+// [lo, hi]; merge-sweep in time order, later lists first on equal times.
+template <bool kCount>
+__device__ u128 chain_count_general(const DevGraph& G, const V8& img, const int* fs, const int* fd,
+                                    int first, int len, int64_t lo, int64_t hi, bool* ovf, u64& nb) {
+    if (len == 0) return 1;
+    int32_t ra[TM_MAX_L], rb[TM_MAX_L];
+    for (int j = 0; j < len; ++j) {
+        int32_t la, lb;
+        el_run(G, img.v[fs[first + j]], img.v[fd[first + j]], lo, hi, ra[j], rb[j], la, lb);
+        if constexpr (kCount) nb += 8 + 2 * probes(lb - la) * 8 + (u64)(rb[j] - ra[j]) * 8;
+    }
+    if (len == 1) return (u128)(rb[0] - ra[0]);
+    const u64* nk = G.nkey[0];
+    const u64 m = tmask_of(G);
+    u128 S[TM_MAX_L];
+    for (int j = 0; j < len; ++j) S[j] = 0;
     while (true) {
         int best = -1;
-        u64 bt = 0;
-        for (int j = R.n - 1; j >= 0; --j) {
-            if (p[j] < R.b[j]) {
-                const u64 tj = G.nkey[0][p[j]] & tmask;
-                if (best < 0 || tj < bt) {
-                    bt = tj;
+        u64 tb = 0;
+        for (int j = len - 1; j >= 0; --j) {
+            if (ra[j] < rb[j]) {
+                const u64 tj = nk[ra[j]] & m;
+                if (best < 0 || tj < tb) {
+                    tb = tj;
                     best = j;
                 }
             }
@@ -116,197 +250,311 @@ __device__ __forceinline__ u128 chain_count(const DevGraph& G, const Run& R, boo
         if (best < 0) break;
         const u128 c = best == 0 ? (u128)1 : S[best - 1];
         if (!add_ok(S[best], c, &S[best])) *ovf = true;
-        ++p[best];
+        ++ra[best];
     }
-    return S[R.n - 1];
+    return S[len - 1];
 }
 
-template <typename W>
-__device__ __forceinline__ W child_mass(const Window& w, bool leaf, const W* qt, const W* qn) {
-    if (leaf) return (W)((w.p1 - w.p0) - (w.q1 - w.q0));
-    return (qt[w.p1] - qt[w.p0]) - (qn[w.q1] - qn[w.q0]);
+// All runs of a valid sample when some run needs the general counter.
+template <bool kCount>
+__device__ __noinline__ u128 complete_general(const SampleArgs& a, const V8& img, int64_t tfirst,
+                                              int64_t tlast, const int64_t* tprev, const int64_t* tnext,
+                                              bool* ovf, u64* nbp) {
+    const DevGraph& G = a.G;
+    u64 nb = 0;
+    u128 m_phi = 1;
+    int lead = -1, trail = -1;
+    for (int r = 0; r < a.n_runs && m_phi != 0; ++r) {
+        if (a.run_prev[r] < 0) { lead = r; continue; }
+        if (a.run_next[r] < 0) { trail = r; continue; }
+        const u128 c = chain_count_general<kCount>(G, img, a.free_src, a.free_dst, a.run_first[r],
+                                                   a.run_len[r], tprev[r] + 1, tnext[r] - 1, ovf, nb);
+        if (!mul_ok(m_phi, c, &m_phi)) *ovf = true;
+    }
+    if (m_phi != 0 && lead >= 0 && trail < 0) {
+        const u128 c = chain_count_general<kCount>(G, img, a.free_src, a.free_dst, a.run_first[lead],
+                                                   a.run_len[lead], tlast - a.delta, tfirst - 1, ovf, nb);
+        if (!mul_ok(m_phi, c, &m_phi)) *ovf = true;
+    } else if (m_phi != 0 && trail >= 0 && lead < 0) {
+        const u128 c = chain_count_general<kCount>(G, img, a.free_src, a.free_dst, a.run_first[trail],
+                                                   a.run_len[trail], tlast + 1, tfirst + a.delta, ovf, nb);
+        if (!mul_ok(m_phi, c, &m_phi)) *ovf = true;
+    } else if (m_phi != 0 && trail >= 0 && lead >= 0) {
+        // the first edge f of the leading chain fixes the end t(f) + delta of
+        // the trailing chain
+        int32_t fa, fb, la, lb;
+        const int f0 = a.run_first[lead];
+        el_run(G, img.v[a.free_src[f0]], img.v[a.free_dst[f0]], tlast - a.delta, tfirst - 1, fa, fb, la, lb);
+        if constexpr (kCount) nb += 8 + 2 * probes(lb - la) * 8 + (u64)(fb - fa) * 8;
+        const u64 m = tmask_of(G);
+        u128 sum = 0;
+        for (int32_t x = fa; x < fb; ++x) {
+            const int64_t tf = (int64_t)(G.nkey[0][x] & m);
+            const u128 lc = chain_count_general<kCount>(G, img, a.free_src, a.free_dst, f0 + 1,
+                                                        a.run_len[lead] - 1, tf + 1, tfirst - 1, ovf, nb);
+            if (lc == 0) continue;
+            const u128 tc = chain_count_general<kCount>(G, img, a.free_src, a.free_dst, a.run_first[trail],
+                                                        a.run_len[trail], tlast + 1, tf + a.delta, ovf, nb);
+            u128 prod;
+            if (!mul_ok(lc, tc, &prod)) *ovf = true;
+            if (!add_ok(sum, prod, &sum)) *ovf = true;
+        }
+        if (!mul_ok(m_phi, sum, &m_phi)) *ovf = true;
+    }
+    *nbp += nb;
+    return m_phi;
 }
 
-template <typename W, bool kCount>
+// ---------------------------------------------------------------------------
+// Wave and block reduction of the per-lane partial sums.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ u128 shfl_xor_u128(u128 v, int m) {
+    const u64 lo = __shfl_xor((u64)v, m, 64), hi = __shfl_xor((u64)(v >> 64), m, 64);
+    return ((u128)hi << 64) | lo;
+}
+
+__device__ __forceinline__ void combine(Partial& x, const Partial& y) {
+    if (!add_ok(x.acc2, y.acc2, &x.acc2)) x.flags |= 1;
+    if (!add_ok(x.acc2_sq, y.acc2_sq, &x.acc2_sq)) {
+        x.acc2_sq = ~(u128)0;
+        x.flags |= 2;
+    }
+    x.n_valid += y.n_valid;
+    x.n_vertex += y.n_vertex;
+    x.n_delta += y.n_delta;
+    x.n_order += y.n_order;
+    x.n_nonzero += y.n_nonzero;
+    x.flags |= y.flags;
+    x.bytes += y.bytes;
+}
+
+__device__ __forceinline__ void block_reduce_write(Partial acc, Partial* out) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        Partial y;
+        y.acc2 = shfl_xor_u128(acc.acc2, m);
+        y.acc2_sq = shfl_xor_u128(acc.acc2_sq, m);
+        y.n_valid = __shfl_xor(acc.n_valid, m, 64);
+        y.n_vertex = __shfl_xor(acc.n_vertex, m, 64);
+        y.n_delta = __shfl_xor(acc.n_delta, m, 64);
+        y.n_order = __shfl_xor(acc.n_order, m, 64);
+        y.n_nonzero = __shfl_xor(acc.n_nonzero, m, 64);
+        y.flags = __shfl_xor(acc.flags, m, 64);
+        y.bytes = __shfl_xor(acc.bytes, m, 64);
+        combine(acc, y);
+    }
+    __shared__ Partial red[kWaves];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Partial s = red[0];
+        for (int w = 1; w < kWaves; ++w) combine(s, red[w]);
+        *out = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The sampling kernel.
+// ---------------------------------------------------------------------------
+template <typename W, bool kCount, bool kGeneral>
 __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
+    constexpr int NT = kMaxSlots - 1;  // register slots; a.nt of them are used
+    extern __shared__ unsigned char lds_raw[];
     const DevGraph& G = a.G;
     const W Wtot = (W)(((u128)a.W_hi << 64) | a.W_lo);
-    const W* cumW = static_cast<const W*>(a.cumW);
-    Partial acc;
-    acc.acc2 = 0;
-    acc.acc2_sq = 0;
-    acc.n_valid = acc.n_vertex = acc.n_delta = acc.n_order = acc.n_nonzero = 0;
-    acc.flags = 0;
-    acc.bytes = 0;
-    u64 nb = 0;
-    bool ovf = false;
-    bool bad = false;
+    const W* cumG = static_cast<const W*>(a.cumW);
+    const int32_t ncum = (int32_t)a.q + 1;
+    W* cumL = reinterpret_cast<W*>(lds_raw);
+    if (a.cum_in_lds) {
+        for (int32_t x = threadIdx.x; x < ncum; x += kBlock) cumL[x] = cumG[x];
+        __syncthreads();
+    }
+    const W* cum = a.cum_in_lds ? cumL : cumG;
+
+    u128 acc2 = 0, acc2_sq = 0;
+    uint32_t n_valid = 0, n_vertex = 0, n_delta = 0, n_order = 0, n_nonzero = 0;
+    u64 flags = 0, nb = 0;
+    bool ovf = false, bad = false;
     const u64 stride = (u64)gridDim.x * kBlock;
     for (u64 r = (u64)blockIdx.x * kBlock + threadIdx.x; r < a.count; r += stride) {
         const u64 j = a.j0 + r;
-        int32_t img_e[kMaxSlots];
-        int64_t te[kMaxSlots];
-        int32_t eu[kMaxSlots], ev[kMaxSlots];
-        int32_t img_v[TM_MAX_K];
+        int32_t ee[NT], eu[NT], ev[NT];
+        int64_t te[NT];
+        int32_t img[TM_MAX_K];
+        sfor<0, TM_MAX_K>([&](auto x) { img[decltype(x)::value] = -1 - decltype(x)::value; });
         // draw 0: interval, then center edge
         const W r0 = scale(draw_block(a.seed, j, 0), Wtot);
-        const int32_t i = upper_bound_pos<W>(cumW, 0, (int32_t)a.q + 1, r0) - 1;
+        const int32_t i = upper_bound_bl<W>(cum, 0, ncum, r0) - 1;
         if (i < 0 || i >= a.q) { bad = true; break; }
         const int par = i & 1;
         const W* qc = static_cast<const W*>(a.qc[par]);
         const int32_t lo = a.ilo[i], hi = a.ihi[i];
-        const W target0 = r0 - cumW[i] + qc[lo];
-        int32_t e0 = upper_bound_pos<W>(qc, lo + 1, hi + 1, target0) - 1;
-        // an interval with positive W_i holds edges; positions stay inside it
         if (hi <= lo) { bad = true; break; }
+        const W target0 = r0 - cum[i] + qc[lo];
+        int32_t e0 = upper_bound_bl<W>(qc, lo + 1, hi + 1, target0) - 1;
         e0 = e0 < lo ? lo : (e0 >= hi ? hi - 1 : e0);
         if constexpr (kCount)
             nb += (probes(a.q + 1) + 2 + probes(hi - lo)) * sizeof(W) + 8 + 16;
-        img_e[0] = e0;
+        ee[0] = e0;
         te[0] = G.t[e0];
         eu[0] = G.src[e0];
         ev[0] = G.dst[e0];
-        img_v[a.esrc[0]] = eu[0];
-        img_v[a.edst[0]] = ev[0];
+        put(img, a.esrc[0], eu[0]);
+        put(img, a.edst[0], ev[0]);
         const int64_t ilo_t = (int64_t)i * a.delta, ihi_t = ((int64_t)i + 2) * a.delta - 1;
-        // draws 1..: children in pre-order
-        for (int s = 1; s < a.nt; ++s) {
+        Bounds last;  // the previous child's window, reused by a leaf sibling with the same one
+        last.p0 = last.p1 = last.q0 = last.q1 = last.a = last.b = 0;
+        // draws 1..nt-1: children in pre-order
+        sfor<1, NT>([&](auto sc) {
+            constexpr int s = decltype(sc)::value;
+            if (s >= a.nt || bad) return;
             const int p = a.parent[s];
-            const int32_t g = a.side[s] ? ev[p] : eu[p];
-            const int32_t o = a.side[s] ? eu[p] : ev[p];
-            int64_t wlo = a.beta[s] < 0 ? te[p] - a.delta : te[p];
-            int64_t whi = a.beta[s] < 0 ? te[p] : te[p] + a.delta;
+            const int32_t pu = pick(eu, p), pv = pick(ev, p);
+            const int64_t pt = pick(te, p);
+            const int32_t g = a.side[s] ? pv : pu;
+            const int32_t o = a.side[s] ? pu : pv;
+            int64_t wlo = a.beta[s] < 0 ? pt - a.delta : pt;
+            int64_t whi = a.beta[s] < 0 ? pt : pt + a.delta;
             wlo = wlo > ilo_t ? wlo : ilo_t;
             whi = whi < ihi_t ? whi : ihi_t;
             const int d = a.dir[s];
-            const Window w = find_window(G, d, g, o, wlo, whi);
+            const Bounds w = a.same_window[s] ? last : window_bounds(G, d, g, o, wlo, whi);
+            last = w;
             const bool leaf = a.leaf[s] != 0;
             const W* qt = static_cast<const W*>(a.qt[s][par]);
             const W* qn = static_cast<const W*>(a.qn[s][par]);
-            const W mass = child_mass<W>(w, leaf, qt, qn);
+            W bt0 = 0, bn0 = 0, mass;
+            if (leaf) {
+                mass = (W)((w.p1 - w.p0) - (w.q1 - w.q0));
+            } else {
+                bt0 = qt[w.p0];
+                bn0 = qn[w.q0];
+                mass = (qt[w.p1] - bt0) - (qn[w.q1] - bn0);
+            }
             // a child of a positive-weight match always has positive mass
-            if (mass == 0 || w.p1 <= w.p0) { bad = true; break; }
+            if (mass == 0 || w.p1 <= w.p0) { bad = true; return; }
             const W rr = scale(draw_block(a.seed, j, (uint32_t)s), mass);
             // J: excluded entries whose preceding candidate mass is <= rr
-            int32_t lo_j = w.q0, hi_j = w.q1;
             const int32_t* xref = G.nxref[d];
-            while (lo_j < hi_j) {
-                const int32_t mid = lo_j + ((hi_j - lo_j) >> 1);
-                const int32_t pos = xref[mid];
-                W F;
-                if (leaf) F = (W)((pos - w.p0) - (mid - w.q0));
-                else F = (qt[pos] - qt[w.p0]) - (qn[mid] - qn[w.q0]);
-                if (F <= rr) lo_j = mid + 1; else hi_j = mid;
+            int32_t jb = w.q0, jn = w.q1 - w.q0;
+            if (jn > 0) {
+                while (jn > 1) {
+                    const int32_t h = jn >> 1;
+                    const int32_t mid = jb + h;
+                    const int32_t xp = xref[mid];
+                    const W F = leaf ? (W)((xp - w.p0) - (mid - w.q0)) : (qt[xp] - bt0) - (qn[mid] - bn0);
+                    jb = F <= rr ? mid : jb;
+                    jn -= h;
+                }
+                const int32_t xp = xref[jb];
+                const W F = leaf ? (W)((xp - w.p0) - (jb - w.q0)) : (qt[xp] - bt0) - (qn[jb] - bn0);
+                jb += F <= rr ? 1 : 0;
             }
-            const int32_t J = lo_j - w.q0;
+            const int32_t J = jb - w.q0;
             int32_t pos;
             if (leaf) {
                 pos = w.p0 + (int32_t)rr + J;
             } else {
-                const W tgt = qt[w.p0] + rr + (qn[w.q0 + J] - qn[w.q0]);
-                pos = upper_bound_pos<W>(qt, w.p0 + 1, w.p1 + 1, tgt) - 1;
+                const W tgt = bt0 + rr + (qn[w.q0 + J] - bn0);
+                pos = upper_bound_bl<W>(qt, w.p0 + 1, w.p1 + 1, tgt) - 1;
             }
             pos = pos < w.p0 ? w.p0 : (pos >= w.p1 ? w.p1 - 1 : pos);
             if constexpr (kCount) {
-                const int32_t la = G.off[d][g], lb = G.off[d][g + 1];
-                nb += 8 + (2 * probes(lb - la) + probes(lb - w.p0) + probes(lb - w.q0)) * 8;
+                if (!a.same_window[s])
+                    nb += 8 + (2 * probes(w.b - w.a) + probes(w.b - w.p0) + probes(w.b - w.q0)) * 8;
                 nb += probes(w.q1 - w.q0) * (4 + (leaf ? 0 : 2 * sizeof(W)));
                 if (!leaf) nb += (5 + probes(w.p1 - w.p0)) * sizeof(W);
                 nb += 16;
             }
-            const int32_t e = G.leid[d][pos];
-            const int32_t nb = G.lnbr[d][pos];
-            img_e[s] = e;
+            const int32_t nbv = G.lnbr[d][pos];
+            ee[s] = G.leid[d][pos];
             te[s] = G.lt[d][pos];
-            eu[s] = d == 0 ? g : nb;
-            ev[s] = d == 0 ? nb : g;
-            img_v[a.new_vertex[s]] = nb;
-        }
+            eu[s] = d == 0 ? g : nbv;
+            ev[s] = d == 0 ? nbv : g;
+            put(img, a.new_vertex[s], nbv);
+        });
         if (bad) break;
         // Alg. 4: vertex map 1-1, then delta range, then edge order
         uint32_t status = 0;
-        for (int x = 0; x < a.k && status == 0; ++x)
-            for (int y = x + 1; y < a.k; ++y)
-                if (img_v[x] == img_v[y]) { status = 1; break; }
+        sfor<0, TM_MAX_K>([&](auto xc) {
+            constexpr int x = decltype(xc)::value;
+            sfor<x + 1, TM_MAX_K>([&](auto yc) {
+                constexpr int y = decltype(yc)::value;
+                if (y < a.k && img[x] == img[y]) status = 1;
+            });
+        });
         int64_t tmin = te[0], tmax = te[0];
-        for (int s = 1; s < a.nt; ++s) {
-            tmin = te[s] < tmin ? te[s] : tmin;
-            tmax = te[s] > tmax ? te[s] : tmax;
-        }
+        sfor<1, NT>([&](auto sc) {
+            constexpr int s = decltype(sc)::value;
+            if (s < a.nt) {
+                tmin = te[s] < tmin ? te[s] : tmin;
+                tmax = te[s] > tmax ? te[s] : tmax;
+            }
+        });
         if (status == 0 && tmax - tmin > a.delta) status = 2;
-        if (status == 0)
-            for (int x = 1; x < a.nt; ++x)
-                if (!(te[a.by_pi[x - 1]] < te[a.by_pi[x]])) { status = 3; break; }
+        if (status == 0) {
+            sfor<1, NT>([&](auto xc) {
+                constexpr int x = decltype(xc)::value;
+                if (x < a.nt && !(pick(te, a.by_pi[x - 1]) < pick(te, a.by_pi[x]))) status = 3;
+            });
+        }
         uint32_t n_phi = 0;
         u128 m_phi = 0;
         if (status == 0) {
-            // N_phi: intervals holding every tree edge
+            // N_phi: intervals holding every tree edge (I_b always; I_{b-1}
+            // when the last time is still below (b+1) delta)
             const int64_t b = tmin / a.delta;
-            for (int64_t ii = b - 1; ii <= b; ++ii)
-                if (ii >= 0 && ii < a.q && ii * a.delta <= tmin && tmax < (ii + 2) * a.delta) ++n_phi;
+            n_phi = (b < a.q ? 1u : 0u) + ((b >= 1 && tmax < (b + 1) * a.delta) ? 1u : 0u);
             // Alg. 5: completions over the non-tree edges
-            m_phi = 1;
-            const int64_t tfirst = te[a.by_pi[0]], tlast = te[a.by_pi[a.nt - 1]];
-            int lead = -1, trail = -1;
-            Run R;
-            for (int rr = 0; rr < a.n_runs && m_phi != 0; ++rr) {
-                const int pv = a.run_prev[rr], nx = a.run_next[rr];
-                if (pv < 0) { lead = rr; continue; }
-                if (nx < 0) { trail = rr; continue; }
-                run_bounds<kCount>(G, img_v, a.free_src, a.free_dst, a.run_first[rr], a.run_len[rr],
-                           te[pv] + 1, te[nx] - 1, R, nb);
-                const u128 c = chain_count<kCount>(G, R, &ovf, nb);
-                if (!mul_ok(m_phi, c, &m_phi)) ovf = true;
-            }
-            if (m_phi != 0 && lead >= 0 && trail < 0) {
-                run_bounds<kCount>(G, img_v, a.free_src, a.free_dst, a.run_first[lead], a.run_len[lead],
-                           tlast - a.delta, tfirst - 1, R, nb);
-                if (!mul_ok(m_phi, chain_count<kCount>(G, R, &ovf, nb), &m_phi)) ovf = true;
-            } else if (m_phi != 0 && trail >= 0 && lead < 0) {
-                run_bounds<kCount>(G, img_v, a.free_src, a.free_dst, a.run_first[trail], a.run_len[trail],
-                           tlast + 1, tfirst + a.delta, R, nb);
-                if (!mul_ok(m_phi, chain_count<kCount>(G, R, &ovf, nb), &m_phi)) ovf = true;
-            } else if (m_phi != 0 && trail >= 0 && lead >= 0) {
-                // the first edge f of the leading chain fixes the window end
-                // t(f) + delta of the trailing chain
-                Run F;
-                run_bounds<kCount>(G, img_v, a.free_src, a.free_dst, a.run_first[lead], 1,
-                           tlast - a.delta, tfirst - 1, F, nb);
-                const u64 tmask = (G.bt >= 64) ? ~0ull : ((1ull << G.bt) - 1);
-                u128 sum = 0;
-                for (int32_t x = F.a[0]; x < F.b[0]; ++x) {
-                    const int64_t tf = (int64_t)(G.nkey[0][x] & tmask);
-                    u128 lc = 1;
-                    if (a.run_len[lead] > 1) {
-                        run_bounds<kCount>(G, img_v, a.free_src, a.free_dst, a.run_first[lead] + 1,
-                                   a.run_len[lead] - 1, tf + 1, tfirst - 1, R, nb);
-                        lc = chain_count<kCount>(G, R, &ovf, nb);
-                    }
-                    if (lc == 0) continue;
-                    run_bounds<kCount>(G, img_v, a.free_src, a.free_dst, a.run_first[trail],
-                               a.run_len[trail], tlast + 1, tf + a.delta, R, nb);
-                    u128 prod;
-                    if (!mul_ok(lc, chain_count<kCount>(G, R, &ovf, nb), &prod)) ovf = true;
-                    if (!add_ok(sum, prod, &sum)) ovf = true;
+            const int64_t tfirst = pick(te, a.by_pi[0]), tlast = pick(te, a.by_pi[a.nt - 1]);
+            if constexpr (kGeneral) {
+                V8 iv;
+                sfor<0, TM_MAX_K>([&](auto x) { iv.v[decltype(x)::value] = img[decltype(x)::value]; });
+                int64_t tp[TM_MAX_L], tn[TM_MAX_L];
+                for (int r2 = 0; r2 < a.n_runs; ++r2) {
+                    tp[r2] = a.run_prev[r2] >= 0 ? pick(te, a.run_prev[r2]) : 0;
+                    tn[r2] = a.run_next[r2] >= 0 ? pick(te, a.run_next[r2]) : 0;
                 }
-                if (!mul_ok(m_phi, sum, &m_phi)) ovf = true;
+                m_phi = complete_general<kCount>(a, iv, tfirst, tlast, tp, tn, &ovf, &nb);
+            } else {
+                m_phi = 1;
+                for (int r2 = 0; r2 < a.n_runs && m_phi != 0; ++r2) {
+                    const int pv = a.run_prev[r2], nx = a.run_next[r2];
+                    const int f0 = a.run_first[r2], len = a.run_len[r2];
+                    int64_t lo_t, hi_t;
+                    if (pv >= 0 && nx >= 0) {
+                        lo_t = pick(te, pv) + 1;
+                        hi_t = pick(te, nx) - 1;
+                    } else if (nx >= 0) {  // leading run only
+                        lo_t = tlast - a.delta;
+                        hi_t = tfirst - 1;
+                    } else {  // trailing run only
+                        lo_t = tlast + 1;
+                        hi_t = tfirst + a.delta;
+                    }
+                    const int32_t x0 = pick(img, a.free_src[f0]), y0 = pick(img, a.free_dst[f0]);
+                    const int32_t x1 = len > 1 ? pick(img, a.free_src[f0 + 1]) : 0;
+                    const int32_t y1 = len > 1 ? pick(img, a.free_dst[f0 + 1]) : 0;
+                    const u128 c = run_count_short<kCount>(G, x0, y0, x1, y1, len, lo_t, hi_t, nb);
+                    if (!mul_ok(m_phi, c, &m_phi)) ovf = true;
+                }
             }
-            ++acc.n_valid;
-            if (m_phi != 0) ++acc.n_nonzero;
+            ++n_valid;
+            if (m_phi != 0) ++n_nonzero;
             u128 term;
             if (!mul_ok(m_phi, (u128)(2 / n_phi), &term)) ovf = true;
-            if (!add_ok(acc.acc2, term, &acc.acc2)) acc.flags |= 1;
+            if (!add_ok(acc2, term, &acc2)) flags |= 1;
             u128 sq;
-            if (!mul_ok(term, term, &sq) || !add_ok(acc.acc2_sq, sq, &acc.acc2_sq)) {
-                acc.acc2_sq = ~(u128)0;
-                acc.flags |= 2;
+            if (!mul_ok(term, term, &sq) || !add_ok(acc2_sq, sq, &acc2_sq)) {
+                acc2_sq = ~(u128)0;
+                flags |= 2;
             }
         } else if (status == 1) {
-            ++acc.n_vertex;
+            ++n_vertex;
         } else if (status == 2) {
-            ++acc.n_delta;
+            ++n_delta;
         } else {
-            ++acc.n_order;
+            ++n_order;
         }
         if (a.recs) {
             tm_sample_rec& out = a.recs[r];
@@ -314,33 +562,25 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
             out.status = status;
             out.n_phi = n_phi;
             out.pad = 0;
-            for (int x = 0; x < 8; ++x) out.eid[x] = x < a.nt ? img_e[a.by_pi[x]] : -1;
+            sfor<0, 8>([&](auto xc) {
+                constexpr int x = decltype(xc)::value;
+                out.eid[x] = x < a.nt ? pick(ee, a.by_pi[x < NT ? x : 0]) : -1;
+            });
             out.m_phi.lo = (u64)m_phi;
             out.m_phi.hi = (u64)(m_phi >> 64);
         }
     }
+    Partial acc;
+    acc.acc2 = acc2;
+    acc.acc2_sq = acc2_sq;
+    acc.n_valid = n_valid;
+    acc.n_vertex = n_vertex;
+    acc.n_delta = n_delta;
+    acc.n_order = n_order;
+    acc.n_nonzero = n_nonzero;
+    acc.flags = flags;
     acc.bytes = nb;
-    // block reduction into one partial
-    __shared__ Partial red[kBlock];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int h = kBlock / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-            Partial& x = red[threadIdx.x];
-            const Partial& y = red[threadIdx.x + h];
-            if (!add_ok(x.acc2, y.acc2, &x.acc2)) x.flags |= 1;
-            if (!add_ok(x.acc2_sq, y.acc2_sq, &x.acc2_sq)) { x.acc2_sq = ~(u128)0; x.flags |= 2; }
-            x.n_valid += y.n_valid;
-            x.n_vertex += y.n_vertex;
-            x.n_delta += y.n_delta;
-            x.n_order += y.n_order;
-            x.n_nonzero += y.n_nonzero;
-            x.flags |= y.flags;
-            x.bytes += y.bytes;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) a.parts[blockIdx.x] = red[0];
+    block_reduce_write(acc, &a.parts[blockIdx.x]);
     if (ovf) atomicOr(a.ovf, 1);
     if (bad) atomicOr(a.ovf, 2);
 }
@@ -353,38 +593,8 @@ __global__ void __launch_bounds__(kBlock) reduce_kernel(const Partial* parts, in
     acc.n_valid = acc.n_vertex = acc.n_delta = acc.n_order = acc.n_nonzero = 0;
     acc.flags = 0;
     acc.bytes = 0;
-    for (int b = threadIdx.x; b < n; b += kBlock) {
-        const Partial& y = parts[b];
-        if (!add_ok(acc.acc2, y.acc2, &acc.acc2)) acc.flags |= 1;
-        if (!add_ok(acc.acc2_sq, y.acc2_sq, &acc.acc2_sq)) { acc.acc2_sq = ~(u128)0; acc.flags |= 2; }
-        acc.n_valid += y.n_valid;
-        acc.n_vertex += y.n_vertex;
-        acc.n_delta += y.n_delta;
-        acc.n_order += y.n_order;
-        acc.n_nonzero += y.n_nonzero;
-        acc.flags |= y.flags;
-        acc.bytes += y.bytes;
-    }
-    __shared__ Partial red[kBlock];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int h = kBlock / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-            Partial& x = red[threadIdx.x];
-            const Partial& y = red[threadIdx.x + h];
-            if (!add_ok(x.acc2, y.acc2, &x.acc2)) x.flags |= 1;
-            if (!add_ok(x.acc2_sq, y.acc2_sq, &x.acc2_sq)) { x.acc2_sq = ~(u128)0; x.flags |= 2; }
-            x.n_valid += y.n_valid;
-            x.n_vertex += y.n_vertex;
-            x.n_delta += y.n_delta;
-            x.n_order += y.n_order;
-            x.n_nonzero += y.n_nonzero;
-            x.flags |= y.flags;
-            x.bytes += y.bytes;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *out = red[0];
+    for (int b = threadIdx.x; b < n; b += kBlock) combine(acc, parts[b]);
+    block_reduce_write(acc, out);
 }
 
 __global__ void fill_undrawn_kernel(tm_sample_rec* recs, u64 count) {
@@ -397,6 +607,14 @@ __global__ void fill_undrawn_kernel(tm_sample_rec* recs, u64 count) {
     out.pad = 0;
     for (int x = 0; x < 8; ++x) out.eid[x] = -1;
     out.m_phi.lo = out.m_phi.hi = 0;
+}
+
+template <typename W, bool kCount>
+void launch_sample(dim3 grid, size_t lds, hipStream_t st, const SampleArgs& a) {
+    if (a.general_runs)
+        hipLaunchKernelGGL((sample_kernel<W, kCount, true>), grid, dim3(kBlock), lds, st, a);
+    else
+        hipLaunchKernelGGL((sample_kernel<W, kCount, false>), grid, dim3(kBlock), lds, st, a);
 }
 
 }  // namespace
@@ -424,6 +642,7 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
         }
         return TM_OK;
     }
+    if (P.nt < 1 || P.nt > 7) return tm_fail(TM_EINVAL, "sample: tree with %d edges", P.nt);
     SampleArgs a;
     std::memset(&a, 0, sizeof a);
     a.G = w->g->d;
@@ -442,6 +661,7 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
         a.leaf[s] = P.n_children[s] == 0;
         a.new_vertex[s] = P.new_vertex[s];
         a.by_pi[s] = P.by_pi[s];
+        a.same_window[s] = P.same_window[s];
         for (int par = 0; par < 2; ++par) {
             a.qt[s][par] = w->qt[s][par];
             a.qn[s][par] = w->qn[s][par];
@@ -452,6 +672,10 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
     a.ilo = w->ilo;
     a.ihi = w->ihi;
     a.cumW = w->cumW;
+    const size_t wsz = w->wide ? 16 : 8;
+    const size_t cum_bytes = (size_t)(w->q + 1) * wsz;
+    a.cum_in_lds = cum_bytes <= (size_t)kCumLdsBytes;
+    const size_t lds = a.cum_in_lds ? cum_bytes : 0;
     a.W_lo = (u64)w->W;
     a.W_hi = (u64)(w->W >> 64);
     a.n_free = P.n_free;
@@ -460,18 +684,23 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
         a.free_dst[f] = P.free_dst[f];
     }
     a.n_runs = P.n_runs;
+    bool has_lead = false, has_trail = false;
     for (int r = 0; r < P.n_runs; ++r) {
         a.run_first[r] = P.run_first[r];
         a.run_len[r] = P.run_len[r];
         a.run_prev[r] = P.run_prev[r];
         a.run_next[r] = P.run_next[r];
+        if (P.run_len[r] > 2) a.general_runs = 1;
+        if (P.run_prev[r] < 0) has_lead = true;
+        if (P.run_next[r] < 0) has_trail = true;
     }
+    if (has_lead && has_trail) a.general_runs = 1;
     a.seed = seed;
     a.j0 = j0;
     a.count = count;
     a.recs = recs;
     const u64 want = (count + kBlock - 1) / kBlock;
-    const int blocks = (int)std::min<u64>(want, 4096);
+    const int blocks = (int)std::min<u64>(want, 8192);
     Partial* parts = nullptr;
     int* ovf = nullptr;
     TM_HIP(hipMallocAsync((void**)&parts, (size_t)(blocks + 1) * sizeof(Partial), st));
@@ -481,15 +710,14 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
     a.ovf = ovf;
     StageTimer t_sample, t_reduce;
     if (!model_bytes) t_sample.start(TM_STAGE_SAMPLE, st);
+    const dim3 grid(blocks);
     if (model_bytes) {
-        if (w->wide)
-            hipLaunchKernelGGL((sample_kernel<u128, true>), dim3(blocks), dim3(kBlock), 0, st, a);
-        else
-            hipLaunchKernelGGL((sample_kernel<u64, true>), dim3(blocks), dim3(kBlock), 0, st, a);
+        if (w->wide) launch_sample<u128, true>(grid, lds, st, a);
+        else launch_sample<u64, true>(grid, lds, st, a);
     } else if (w->wide) {
-        hipLaunchKernelGGL((sample_kernel<u128, false>), dim3(blocks), dim3(kBlock), 0, st, a);
+        launch_sample<u128, false>(grid, lds, st, a);
     } else {
-        hipLaunchKernelGGL((sample_kernel<u64, false>), dim3(blocks), dim3(kBlock), 0, st, a);
+        launch_sample<u64, false>(grid, lds, st, a);
     }
     TM_HIP(hipGetLastError());
     t_sample.stop();

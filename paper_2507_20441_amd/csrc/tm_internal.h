@@ -29,9 +29,13 @@ int tm_fail(int code, const char* fmt, ...);
     } while (0)
 
 // Device allocations owned by a handle; released together.
+// Allocation is stream-ordered from the device's memory pool, which keeps
+// freed memory cached (see pool_setup), so building and dropping tables per
+// call costs no device-wide synchronisation.
 struct DevArena {
     std::vector<void*> blocks;
     uint64_t bytes = 0;
+    hipStream_t stream = nullptr;
     int alloc(void** p, size_t nbytes);
     void release();
 };
@@ -40,6 +44,9 @@ template <typename T>
 int arena_alloc(DevArena& A, T** p, size_t count) {
     return A.alloc(reinterpret_cast<void**>(p), count * sizeof(T));
 }
+
+// Keep freed pool memory cached on the current device (once per device).
+void pool_setup();
 
 // ---------------------------------------------------------------------------
 // Graph handle.
@@ -77,6 +84,8 @@ struct HostPlan {
     int children[kMaxSlots][kMaxSlots];
     int n_children[kMaxSlots];
     int by_pi[kMaxSlots];          // slots in increasing pi index
+    int same_window[kMaxSlots];    // 1: same parent, side, direction and time side as
+                                   // the previous slot (a leaf sibling): same window
     // non-tree edges in pi order, and maximal runs of consecutive ones
     int n_free = 0;
     int free_src[TM_MAX_L], free_dst[TM_MAX_L];

@@ -17,16 +17,18 @@
 // parity i & 1 -- one prefix array per parity serves every interval.
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include "tm_primitives.h"
 
 namespace {
 
 struct ChildDesc {
-    int side;   // 0: attaches at the source endpoint of the parent's match, 1: destination
-    int dir;    // 0: child is an out-edge of the shared vertex, 1: an in-edge
-    int beta;   // -1: child precedes the parent in pi, +1: follows it
+    int side;     // 0: attaches at the source endpoint of the parent's match, 1: destination
+    int dir;      // 0: child is an out-edge of the shared vertex, 1: an in-edge
+    int beta;     // -1: child precedes the parent in pi, +1: follows it
     int leaf;
+    int same_as;  // an earlier leaf child with the same side, direction and time side, or -1
     const void* qt[2];
     const void* qn[2];
 };
@@ -36,49 +38,134 @@ struct LevelArgs {
     int64_t delta;
     int nc;
     ChildDesc c[kMaxSlots];
+    int walk;  // -1: eid order; 0 / 1: the T order of the out- / in-lists
     void* out[2];
     int* ovf;
 };
 
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(static_cast<F&&>(f));
+    }
+}
+
+// Two windows of the same vertex list in lockstep: for each, the T-order
+// range with time in [lo, hi] and the N-order run of neighbour o in it.
+// Eight independent loads per halving step.
+struct Win {
+    int32_t p0, p1, q0, q1;
+};
+
+__device__ __forceinline__ void two_windows(const DevGraph& G, int dir, int32_t g, int32_t o,
+                                            int64_t lo0, int64_t hi0, int64_t lo1, int64_t hi1,
+                                            Win& A, Win& B) {
+    const int32_t a = G.off[dir][g], b = G.off[dir][g + 1];
+    lo0 = lo0 < 0 ? 0 : lo0;
+    lo1 = lo1 < 0 ? 0 : lo1;
+    hi0 = hi0 > G.T ? G.T : hi0;
+    hi1 = hi1 > G.T ? G.T : hi1;
+    const bool e0 = lo0 > hi0 || a == b, e1 = lo1 > hi1 || a == b;
+    if (e0 && e1) {
+        A.p0 = A.p1 = A.q0 = A.q1 = a;
+        B = A;
+        return;
+    }
+    // an empty window searches harmless keys and is reset afterwards
+    if (e0) { lo0 = lo1; hi0 = hi1; }
+    if (e1) { lo1 = lo0; hi1 = hi0; }
+    const int64_t* lt = G.lt[dir];
+    const u64* nk = G.nkey[dir];
+    const u64 base = (u64)o << G.bt;
+    const u64 kl0 = base | (u64)lo0, kh0 = base | (u64)hi0;
+    const u64 kl1 = base | (u64)lo1, kh1 = base | (u64)hi1;
+    int32_t c0 = a, c1 = a, c2 = a, c3 = a, c4 = a, c5 = a, c6 = a, c7 = a;
+    int32_t n = b - a;
+    while (n > 1) {
+        const int32_t h = n >> 1;
+        const int64_t x0 = lt[c0 + h], x1 = lt[c1 + h], x2 = lt[c2 + h], x3 = lt[c3 + h];
+        const u64 y0 = nk[c4 + h], y1 = nk[c5 + h], y2 = nk[c6 + h], y3 = nk[c7 + h];
+        c0 = x0 < lo0 ? c0 + h : c0;
+        c1 = x1 <= hi0 ? c1 + h : c1;
+        c2 = x2 < lo1 ? c2 + h : c2;
+        c3 = x3 <= hi1 ? c3 + h : c3;
+        c4 = y0 < kl0 ? c4 + h : c4;
+        c5 = y1 <= kh0 ? c5 + h : c5;
+        c6 = y2 < kl1 ? c6 + h : c6;
+        c7 = y3 <= kh1 ? c7 + h : c7;
+        n -= h;
+    }
+    A.p0 = c0 + (lt[c0] < lo0 ? 1 : 0);
+    A.p1 = c1 + (lt[c1] <= hi0 ? 1 : 0);
+    B.p0 = c2 + (lt[c2] < lo1 ? 1 : 0);
+    B.p1 = c3 + (lt[c3] <= hi1 ? 1 : 0);
+    A.q0 = c4 + (nk[c4] < kl0 ? 1 : 0);
+    A.q1 = c5 + (nk[c5] <= kh0 ? 1 : 0);
+    B.q0 = c6 + (nk[c6] < kl1 ? 1 : 0);
+    B.q1 = c7 + (nk[c7] <= kh1 ? 1 : 0);
+    if (e0) A.p0 = A.p1 = A.q0 = A.q1 = a;
+    if (e1) B.p0 = B.p1 = B.q0 = B.q1 = a;
+}
+
+template <typename W>
+__device__ __forceinline__ W window_mass(const Win& w, bool leaf, const void* qt, const void* qn) {
+    if (leaf) return (W)((w.p1 - w.p0) - (w.q1 - w.q0));
+    const W* T = static_cast<const W*>(qt);
+    const W* N = static_cast<const W*>(qn);
+    return (T[w.p1] - T[w.p0]) - (N[w.q1] - N[w.q0]);
+}
+
+// One thread per edge e and both intervals holding it: slot A is
+// i = floor(t / delta), slot B is i - 1.  The two windows of a child differ
+// only where the interval clips them, so they are searched together.
 template <typename W>
 __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const DevGraph& G = a.G;
-    if (e >= G.m) return;
+    if (p >= G.m) return;
+    const int32_t e = a.walk < 0 ? (int32_t)p : G.leid[a.walk][p];
     const int32_t u = G.src[e], v = G.dst[e];
     const int64_t t = G.t[e];
     const int64_t blk = t / a.delta;
-    W val[2] = {0, 0};
+    const bool hasB = blk >= 1;
+    const int parA = (int)(blk & 1), parB = parA ^ 1;
+    const int64_t loA = blk * a.delta, hiA = (blk + 2) * a.delta - 1;
+    const int64_t loB = (blk - 1) * a.delta, hiB = (blk + 1) * a.delta - 1;
+    W prodA = 1, prodB = hasB ? (W)1 : (W)0;
+    W fA[kMaxSlots], fB[kMaxSlots];
     bool ovf = false;
-    for (int slot = 0; slot < 2; ++slot) {
-        const int64_t i = blk - slot;
-        if (i < 0) continue;
-        const int par = (int)(i & 1);
-        const int64_t ilo = i * a.delta, ihi = (i + 2) * a.delta - 1;
-        W prod = 1;
-        for (int c = 0; c < a.nc; ++c) {
-            const ChildDesc& d = a.c[c];
+    sfor<0, kMaxSlots>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        if (c >= a.nc) return;
+        const ChildDesc& d = a.c[c];
+        W xa = 0, xb = 0;
+        if (d.same_as >= 0) {
+            sfor<0, c>([&](auto kk) {
+                constexpr int k2 = decltype(kk)::value;
+                if (d.same_as == k2) {
+                    xa = fA[k2];
+                    xb = fB[k2];
+                }
+            });
+        } else {
             const int32_t g = d.side ? v : u;
             const int32_t o = d.side ? u : v;
-            int64_t wlo = d.beta < 0 ? t - a.delta : t;
-            int64_t whi = d.beta < 0 ? t : t + a.delta;
-            wlo = wlo > ilo ? wlo : ilo;
-            whi = whi < ihi ? whi : ihi;
-            const Window w = find_window(G, d.dir, g, o, wlo, whi);
-            W f;
-            if (d.leaf) {
-                f = (W)((w.p1 - w.p0) - (w.q1 - w.q0));
-            } else {
-                const W* qt = static_cast<const W*>(d.qt[par]);
-                const W* qn = static_cast<const W*>(d.qn[par]);
-                f = (qt[w.p1] - qt[w.p0]) - (qn[w.q1] - qn[w.q0]);
-            }
-            if (!mul_ok(prod, f, &prod)) ovf = true;
+            const int64_t wlo = d.beta < 0 ? t - a.delta : t;
+            const int64_t whi = d.beta < 0 ? t : t + a.delta;
+            Win A, B;
+            two_windows(G, d.dir, g, o, wlo > loA ? wlo : loA, whi < hiA ? whi : hiA,
+                        wlo > loB ? wlo : loB, whi < hiB ? whi : hiB, A, B);
+            xa = window_mass<W>(A, d.leaf, d.qt[parA], d.qn[parA]);
+            xb = hasB ? window_mass<W>(B, d.leaf, d.qt[parB], d.qn[parB]) : (W)0;
         }
-        val[par] = prod;
-    }
-    static_cast<W*>(a.out[0])[e] = val[0];
-    static_cast<W*>(a.out[1])[e] = val[1];
+        fA[c] = xa;
+        fB[c] = xb;
+        if (!mul_ok(prodA, xa, &prodA)) ovf = true;
+        if (!mul_ok(prodB, xb, &prodB)) ovf = true;
+    });
+    static_cast<W*>(a.out[parA])[e] = prodA;
+    static_cast<W*>(a.out[parB])[e] = hasB ? prodB : (W)0;
     if (ovf) atomicOr(a.ovf, 4);
 }
 
@@ -136,6 +223,7 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf) {
             a.G = g->d;
             a.delta = delta;
             a.nc = P.n_children[s];
+            int at_src = 0;
             for (int j = 0; j < a.nc; ++j) {
                 const int c = P.children[s][j];
                 ChildDesc& d = a.c[j];
@@ -143,11 +231,24 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf) {
                 d.dir = P.alpha[c] > 0 ? 0 : 1;
                 d.beta = P.beta[c];
                 d.leaf = P.n_children[c] == 0;
+                d.same_as = -1;
+                for (int j2 = 0; j2 < j && d.leaf; ++j2) {
+                    const ChildDesc& e2 = a.c[j2];
+                    if (e2.leaf && e2.same_as < 0 && e2.side == d.side && e2.dir == d.dir &&
+                        e2.beta == d.beta) {
+                        d.same_as = j2;
+                        break;
+                    }
+                }
                 for (int par = 0; par < 2; ++par) {
                     d.qt[par] = w->qt[c][par];
                     d.qn[par] = w->qn[c][par];
                 }
+                at_src += d.side == 0 ? 1 : -1;
             }
+            // walk edges grouped by the endpoint most children search from:
+            // neighbouring lanes then search the same list at nearby times
+            a.walk = a.nc == 0 ? -1 : (at_src >= 0 ? 0 : 1);
             for (int par = 0; par < 2; ++par) {
                 W* p;
                 TM_TRY(arena_alloc(w->arena, &p, (size_t)m));
