@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
-STAGES = ["graph", "weights", "sample", "reduce"]
+STAGES = ["graph", "weights", "sample", "reduce", "roots"]
 
 
 def log(*a):
@@ -68,7 +68,7 @@ def main():
     L.tm_profile_enable.restype = None
 
     class Profile(C.Structure):
-        _fields_ = [("ms", C.c_double * 4), ("launches", C.c_uint64 * 4)]
+        _fields_ = [("ms", C.c_double * 5), ("launches", C.c_uint64 * 5)]
 
     L.tm_profile_read.argtypes = [C.POINTER(Profile), C.c_int]
     L.tm_sample_model_bytes.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64,
@@ -121,8 +121,8 @@ def main():
     L.tm_profile_read(C.byref(prof), 1)
     samples = len(motifs) * k * args.steps
     value = samples / elapsed
-    stage_ms = {STAGES[i]: prof.ms[i] / args.steps for i in range(4)}
-    stage_launch = {STAGES[i]: prof.launches[i] for i in range(4)}
+    stage_ms = {STAGES[i]: prof.ms[i] / args.steps for i in range(5)}
+    stage_launch = {STAGES[i]: prof.launches[i] for i in range(5)}
     log("stage ms per step", stage_ms)
 
     # Access-model bytes of the sampling kernel's launches in one step

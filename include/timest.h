@@ -215,7 +215,8 @@ enum tm_stage {
     TM_STAGE_WEIGHTS = 1,  /* tm_weights_create: all levels, prefix tables, intervals */
     TM_STAGE_SAMPLE = 2,   /* the sampling kernel of tm_sample (draw, validate, complete) */
     TM_STAGE_REDUCE = 3,   /* the final reduction of tm_sample */
-    TM_N_STAGES = 4
+    TM_STAGE_ROOTS = 4,    /* tm_sample on large counts: root draws and their sort by root */
+    TM_N_STAGES = 5
 };
 typedef struct {
     double ms[TM_N_STAGES];          /* accumulated device milliseconds */
@@ -228,10 +229,12 @@ void tm_profile_enable(int on);
 int tm_profile_read(tm_profile* out, int reset);
 
 /* Bytes the sampling kernel's access model requests for samples j0 ..
- * j0 + count - 1 (a counting pass, not timed, same draws as tm_sample): every
- * binary search over a range of L entries is charged ceil(log2(L + 1)) reads
- * of its element size, every other read its element size; writes of records
- * are not counted.  Used as the numerator of the sampler's roofline. */
+ * j0 + count - 1 (a counting pass, not timed, same draws and the same kernel
+ * variant as tm_sample with that count): every binary search over a range of
+ * L entries is charged ceil(log2(L + 1)) reads of its element size, every
+ * other read its element size; writes of records are not counted, nor is the
+ * root-draw stage that large counts run first.  Used as the numerator of the
+ * sampling kernel's roofline. */
 int tm_sample_model_bytes(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count,
                           void* stream, uint64_t* bytes);
 

@@ -91,6 +91,20 @@ __global__ void gather_edges_kernel(const int32_t* src, const int32_t* dst, cons
     }
 }
 
+// Edge arrays straight from sorted packed keys t << 2bn | u << bn | v, and the
+// duplicate check on neighbours.
+__global__ void decode_edges_kernel(const u64* key, int64_t m, int bn, int32_t* osrc, int32_t* odst,
+                                    int64_t* ot, int* flags) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= m) return;
+    const u64 k = key[e];
+    const u64 mask = (1ull << bn) - 1;
+    osrc[e] = (int32_t)((k >> bn) & mask);
+    odst[e] = (int32_t)(k & mask);
+    ot[e] = (int64_t)(k >> (2 * bn));
+    if (e > 0 && key[e - 1] == k) atomicOr(flags, kDup);
+}
+
 __global__ void iota_key_kernel(const int32_t* key_by_eid, int64_t m, uint32_t* keys, uint32_t* vals) {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= m) return;
@@ -130,15 +144,18 @@ __global__ void fill_n_order_kernel(const uint32_t* eids, const int64_t* t, cons
     neid[p] = (int32_t)e;
 }
 
-__global__ void degree_kernel(const int32_t* v, int64_t m, int32_t* deg) {
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e < m) atomicAdd(&deg[v[e]], 1);
+// List offsets from the owner-sorted keys: off[v] is the first position whose
+// owner is >= v.  Position p writes the offsets of the owners in
+// (key[p-1], key[p]]; the last position also closes the owners after it.
+__global__ void offsets_kernel(const uint32_t* key, int64_t m, int32_t n, int32_t* off) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= m) return;
+    const int64_t cur = key[p];
+    const int64_t prev = p == 0 ? -1 : (int64_t)key[p - 1];
+    for (int64_t v = prev + 1; v <= cur; ++v) off[v] = (int32_t)p;
+    if (p == m - 1)
+        for (int64_t v = cur + 1; v <= n; ++v) off[v] = (int32_t)m;
 }
-
-struct DegReader {
-    const int32_t* d;
-    __device__ uint32_t operator()(int64_t i) const { return (uint32_t)d[i]; }
-};
 
 int bits_for(u64 x) {
     int b = 0;
@@ -239,12 +256,13 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
     TM_TRY(arena_alloc(g->arena, &esrc, m));
     TM_TRY(arena_alloc(g->arena, &edst, m));
     TM_TRY(arena_alloc(g->arena, &et, m));
-    hipLaunchKernelGGL(gather_edges_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, src, dst, t,
-                       (const uint32_t*)perm, m, tmin, esrc, edst, et, flags);
+    if (one_key && bn > 0)
+        hipLaunchKernelGGL(decode_edges_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
+                           (const u64*)kres, m, bn, esrc, edst, et, flags);
+    else
+        hipLaunchKernelGGL(gather_edges_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, src, dst, t,
+                           (const uint32_t*)perm, m, tmin, esrc, edst, et, flags);
     TM_HIP(hipGetLastError());
-    TM_HIP(hipMemcpyAsync(hflags, flags, sizeof hflags, hipMemcpyDeviceToHost, st));
-    TM_HIP(hipStreamSynchronize(st));
-    if (hflags[0] & kDup) return tm_fail(TM_EDUP, "graph: duplicate (u, v, t) tuple");
     D.src = esrc;
     D.dst = edst;
     D.t = et;
@@ -264,7 +282,7 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
         TM_TRY(arena_alloc(g->arena, &leid, m));
         TM_TRY(arena_alloc(g->arena, &lnbr, m));
         TM_TRY(arena_alloc(g->arena, &off, (size_t)n + 1));
-        TM_HIP(hipMallocAsync((void**)&tpos[dir], m * sizeof(int32_t), st));
+        TM_TRY(arena_alloc(g->arena, &tpos[dir], (size_t)m));
         // T order: stable sort of the eids by the list owner
         hipLaunchKernelGGL(iota_key_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, key_by_eid, m,
                            k32a, va);
@@ -275,12 +293,11 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
                            (const uint32_t*)vr, (const int64_t*)et, nbr_by_eid, m, lt, leid, lnbr,
                            tpos[dir]);
         TM_HIP(hipGetLastError());
-        // offsets from the owner's degree
-        TM_HIP(hipMemsetAsync(off, 0, ((size_t)n + 1) * sizeof(int32_t), st));
-        hipLaunchKernelGGL(degree_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, key_by_eid, m, off);
+        hipLaunchKernelGGL(offsets_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
+                           (const uint32_t*)kr, m, n, off);
         TM_HIP(hipGetLastError());
-        TM_TRY(device_exclusive_scan<int32_t>(DegReader{off}, n, off, flags + 1, st));
         D.off[dir] = off;
+        D.tpos[dir] = tpos[dir];
         D.lt[dir] = lt;
         D.leid[dir] = leid;
         D.lnbr[dir] = lnbr;
@@ -310,8 +327,6 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
         D.nxref[dir] = nxref;
         D.neid[dir] = neid;
     }
-    TM_HIP(hipFreeAsync(tpos[0], st));
-    TM_HIP(hipFreeAsync(tpos[1], st));
     TM_HIP(hipFreeAsync(ka, st));
     TM_HIP(hipFreeAsync(kb, st));
     TM_HIP(hipFreeAsync(va, st));
@@ -322,6 +337,7 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
     timer.stop();
     TM_HIP(hipStreamSynchronize(st));
     timer.finish();
+    if (hflags[0] & kDup) return tm_fail(TM_EDUP, "graph: duplicate (u, v, t) tuple");
     if (hflags[1]) return tm_fail(TM_EDEVICE, "graph: internal scan overflow");
     return TM_OK;
 }

@@ -54,6 +54,8 @@ struct SampleArgs {
     tm_sample_rec* recs;
     struct Partial* parts;
     int* ovf;
+    const uint32_t* skey;  // root-sorted order: T-order position of the root * 2 + interval parity
+    const uint32_t* sval;  // ... and the sample's offset in [0, count)
 };
 
 struct Partial {
@@ -356,9 +358,12 @@ __device__ __forceinline__ void block_reduce_write(Partial acc, Partial* out) {
 // ---------------------------------------------------------------------------
 // The sampling kernel.
 // ---------------------------------------------------------------------------
-template <typename W, bool kCount, bool kGeneral>
-__global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
-    constexpr int NT = kMaxSlots - 1;  // register slots; a.nt of them are used
+// Draw 0 of each sample (interval, then center edge), written as a sort key:
+// the root's position in the out-list T order (grouping samples by source
+// vertex and time) and the interval's parity.  The sort that follows changes
+// only the order in which samples are processed.
+template <typename W>
+__global__ void __launch_bounds__(kBlock) root_kernel(SampleArgs a, uint32_t* keys, uint32_t* vals) {
     extern __shared__ unsigned char lds_raw[];
     const DevGraph& G = a.G;
     const W Wtot = (W)(((u128)a.W_hi << 64) | a.W_lo);
@@ -370,35 +375,84 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
         __syncthreads();
     }
     const W* cum = a.cum_in_lds ? cumL : cumG;
+    bool bad = false;
+    const u64 stride = (u64)gridDim.x * kBlock;
+    for (u64 r = (u64)blockIdx.x * kBlock + threadIdx.x; r < a.count; r += stride) {
+        const W r0 = scale(draw_block(a.seed, a.j0 + r, 0), Wtot);
+        const int32_t i = upper_bound_bl<W>(cum, 0, ncum, r0) - 1;
+        if (i < 0 || i >= a.q) { bad = true; break; }
+        const W* qc = static_cast<const W*>(a.qc[i & 1]);
+        const int32_t lo = a.ilo[i], hi = a.ihi[i];
+        if (hi <= lo) { bad = true; break; }
+        int32_t e0 = upper_bound_bl<W>(qc, lo + 1, hi + 1, r0 - cum[i] + qc[lo]) - 1;
+        e0 = e0 < lo ? lo : (e0 >= hi ? hi - 1 : e0);
+        keys[r] = (uint32_t)G.tpos[0][e0] * 2u + (uint32_t)(i & 1);
+        vals[r] = (uint32_t)r;
+    }
+    if (bad) atomicOr(a.ovf, 2);
+}
+
+template <typename W, bool kCount, bool kGeneral, bool kSorted>
+__global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
+    constexpr int NT = kMaxSlots - 1;  // register slots; a.nt of them are used
+    extern __shared__ unsigned char lds_raw[];
+    const DevGraph& G = a.G;
+    const W Wtot = (W)(((u128)a.W_hi << 64) | a.W_lo);
+    const W* cumG = static_cast<const W*>(a.cumW);
+    const int32_t ncum = (int32_t)a.q + 1;
+    W* cumL = reinterpret_cast<W*>(lds_raw);
+    if (!kSorted && a.cum_in_lds) {
+        for (int32_t x = threadIdx.x; x < ncum; x += kBlock) cumL[x] = cumG[x];
+        __syncthreads();
+    }
+    const W* cum = a.cum_in_lds ? cumL : cumG;
 
     u128 acc2 = 0, acc2_sq = 0;
     uint32_t n_valid = 0, n_vertex = 0, n_delta = 0, n_order = 0, n_nonzero = 0;
     u64 flags = 0, nb = 0;
     bool ovf = false, bad = false;
     const u64 stride = (u64)gridDim.x * kBlock;
-    for (u64 r = (u64)blockIdx.x * kBlock + threadIdx.x; r < a.count; r += stride) {
-        const u64 j = a.j0 + r;
+    for (u64 x = (u64)blockIdx.x * kBlock + threadIdx.x; x < a.count; x += stride) {
         int32_t ee[NT], eu[NT], ev[NT];
         int64_t te[NT];
         int32_t img[TM_MAX_K];
-        sfor<0, TM_MAX_K>([&](auto x) { img[decltype(x)::value] = -1 - decltype(x)::value; });
-        // draw 0: interval, then center edge
-        const W r0 = scale(draw_block(a.seed, j, 0), Wtot);
-        const int32_t i = upper_bound_bl<W>(cum, 0, ncum, r0) - 1;
-        if (i < 0 || i >= a.q) { bad = true; break; }
+        sfor<0, TM_MAX_K>([&](auto xx) { img[decltype(xx)::value] = -1 - decltype(xx)::value; });
+        u64 r;
+        int32_t i;
+        if constexpr (kSorted) {
+            // the root was drawn by root_kernel; lanes follow the sorted order
+            const uint32_t key = a.skey[x];
+            r = a.sval[x];
+            const int32_t pos = (int32_t)(key >> 1);
+            const int32_t e0 = G.leid[0][pos];
+            ee[0] = e0;
+            te[0] = G.lt[0][pos];
+            ev[0] = G.lnbr[0][pos];
+            eu[0] = G.src[e0];
+            const int64_t blk = te[0] / a.delta;
+            i = (int32_t)(((blk & 1) == (int64_t)(key & 1)) ? blk : blk - 1);
+            if constexpr (kCount) nb += 8 + 20;
+        } else {
+            // draw 0: interval, then center edge
+            r = x;
+            const W r0 = scale(draw_block(a.seed, a.j0 + r, 0), Wtot);
+            i = upper_bound_bl<W>(cum, 0, ncum, r0) - 1;
+            if (i < 0 || i >= a.q) { bad = true; break; }
+            const W* qc = static_cast<const W*>(a.qc[i & 1]);
+            const int32_t lo = a.ilo[i], hi = a.ihi[i];
+            if (hi <= lo) { bad = true; break; }
+            const W target0 = r0 - cum[i] + qc[lo];
+            int32_t e0 = upper_bound_bl<W>(qc, lo + 1, hi + 1, target0) - 1;
+            e0 = e0 < lo ? lo : (e0 >= hi ? hi - 1 : e0);
+            if constexpr (kCount)
+                nb += (probes(a.q + 1) + 2 + probes(hi - lo)) * sizeof(W) + 8 + 16;
+            ee[0] = e0;
+            te[0] = G.t[e0];
+            eu[0] = G.src[e0];
+            ev[0] = G.dst[e0];
+        }
+        const u64 j = a.j0 + r;
         const int par = i & 1;
-        const W* qc = static_cast<const W*>(a.qc[par]);
-        const int32_t lo = a.ilo[i], hi = a.ihi[i];
-        if (hi <= lo) { bad = true; break; }
-        const W target0 = r0 - cum[i] + qc[lo];
-        int32_t e0 = upper_bound_bl<W>(qc, lo + 1, hi + 1, target0) - 1;
-        e0 = e0 < lo ? lo : (e0 >= hi ? hi - 1 : e0);
-        if constexpr (kCount)
-            nb += (probes(a.q + 1) + 2 + probes(hi - lo)) * sizeof(W) + 8 + 16;
-        ee[0] = e0;
-        te[0] = G.t[e0];
-        eu[0] = G.src[e0];
-        ev[0] = G.dst[e0];
         put(img, a.esrc[0], eu[0]);
         put(img, a.edst[0], ev[0]);
         const int64_t ilo_t = (int64_t)i * a.delta, ihi_t = ((int64_t)i + 2) * a.delta - 1;
@@ -609,12 +663,34 @@ __global__ void fill_undrawn_kernel(tm_sample_rec* recs, u64 count) {
     out.m_phi.lo = out.m_phi.hi = 0;
 }
 
-template <typename W, bool kCount>
+template <typename W, bool kCount, bool kSorted>
 void launch_sample(dim3 grid, size_t lds, hipStream_t st, const SampleArgs& a) {
     if (a.general_runs)
-        hipLaunchKernelGGL((sample_kernel<W, kCount, true>), grid, dim3(kBlock), lds, st, a);
+        hipLaunchKernelGGL((sample_kernel<W, kCount, true, kSorted>), grid, dim3(kBlock), lds, st, a);
     else
-        hipLaunchKernelGGL((sample_kernel<W, kCount, false>), grid, dim3(kBlock), lds, st, a);
+        hipLaunchKernelGGL((sample_kernel<W, kCount, false, kSorted>), grid, dim3(kBlock), lds, st, a);
+}
+
+template <bool kCount>
+void launch_any(bool wide, bool sorted, dim3 grid, size_t lds, hipStream_t st, const SampleArgs& a) {
+    if (wide) {
+        if (sorted) launch_sample<u128, kCount, true>(grid, lds, st, a);
+        else launch_sample<u128, kCount, false>(grid, lds, st, a);
+    } else {
+        if (sorted) launch_sample<u64, kCount, true>(grid, lds, st, a);
+        else launch_sample<u64, kCount, false>(grid, lds, st, a);
+    }
+}
+
+// Samples per chunk (sort keys and offsets are 32-bit), and the smallest
+// count for which sorting by root pays for itself.
+constexpr u64 kChunk = (u64)1 << 28;
+constexpr u64 kSortMin = (u64)1 << 16;
+
+int bits_of(u64 x) {
+    int b = 0;
+    while (x) { ++b; x >>= 1; }
+    return b;
 }
 
 }  // namespace
@@ -696,45 +772,87 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
     }
     if (has_lead && has_trail) a.general_runs = 1;
     a.seed = seed;
-    a.j0 = j0;
-    a.count = count;
-    a.recs = recs;
-    const u64 want = (count + kBlock - 1) / kBlock;
-    const int blocks = (int)std::min<u64>(want, 8192);
+    const bool sorted = count >= kSortMin;
+    const u64 chunk = std::min<u64>(count, kChunk);
+    const int blocks = (int)std::min<u64>((chunk + kBlock - 1) / kBlock, 8192);
+    const int key_bits = bits_of(2 * (u64)w->g->m - 1);
     Partial* parts = nullptr;
     int* ovf = nullptr;
+    uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
     TM_HIP(hipMallocAsync((void**)&parts, (size_t)(blocks + 1) * sizeof(Partial), st));
     TM_HIP(hipMallocAsync((void**)&ovf, sizeof(int), st));
     TM_HIP(hipMemsetAsync(ovf, 0, sizeof(int), st));
+    if (sorted) {
+        TM_HIP(hipMallocAsync((void**)&k0, chunk * sizeof(uint32_t), st));
+        TM_HIP(hipMallocAsync((void**)&v0, chunk * sizeof(uint32_t), st));
+        TM_HIP(hipMallocAsync((void**)&k1, chunk * sizeof(uint32_t), st));
+        TM_HIP(hipMallocAsync((void**)&v1, chunk * sizeof(uint32_t), st));
+    }
     a.parts = parts;
     a.ovf = ovf;
-    StageTimer t_sample, t_reduce;
-    if (!model_bytes) t_sample.start(TM_STAGE_SAMPLE, st);
-    const dim3 grid(blocks);
-    if (model_bytes) {
-        if (w->wide) launch_sample<u128, true>(grid, lds, st, a);
-        else launch_sample<u64, true>(grid, lds, st, a);
-    } else if (w->wide) {
-        launch_sample<u128, false>(grid, lds, st, a);
-    } else {
-        launch_sample<u64, false>(grid, lds, st, a);
-    }
-    TM_HIP(hipGetLastError());
-    t_sample.stop();
-    if (!model_bytes) t_reduce.start(TM_STAGE_REDUCE, st);
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const Partial*)parts, blocks,
-                       parts + blocks);
-    TM_HIP(hipGetLastError());
-    t_reduce.stop();
     Partial h;
+    std::memset(&h, 0, sizeof h);
     int hovf = 0;
-    TM_HIP(hipMemcpyAsync(&h, parts + blocks, sizeof h, hipMemcpyDeviceToHost, st));
-    TM_HIP(hipMemcpyAsync(&hovf, ovf, sizeof hovf, hipMemcpyDeviceToHost, st));
+    for (u64 c0 = 0; c0 < count; c0 += chunk) {
+        const u64 n = std::min<u64>(chunk, count - c0);
+        a.j0 = j0 + c0;
+        a.count = n;
+        a.recs = recs ? recs + c0 : nullptr;
+        const dim3 grid((unsigned)std::min<u64>((n + kBlock - 1) / kBlock, (u64)blocks));
+        StageTimer t_roots, t_sample, t_reduce;
+        if (sorted) {
+            if (!model_bytes) t_roots.start(TM_STAGE_ROOTS, st);
+            if (w->wide)
+                hipLaunchKernelGGL(root_kernel<u128>, grid, dim3(kBlock), lds, st, a, k0, v0);
+            else
+                hipLaunchKernelGGL(root_kernel<u64>, grid, dim3(kBlock), lds, st, a, k0, v0);
+            TM_HIP(hipGetLastError());
+            uint32_t *ks, *vs;
+            TM_TRY(radix_sort_pairs<uint32_t>(k0, v0, k1, v1, (int64_t)n, key_bits, &ks, &vs, ovf, st));
+            a.skey = ks;
+            a.sval = vs;
+            t_roots.stop();
+        }
+        if (!model_bytes) t_sample.start(TM_STAGE_SAMPLE, st);
+        // the sorted variant does not search the interval prefix
+        if (model_bytes) launch_any<true>(w->wide, sorted, grid, sorted ? 0 : lds, st, a);
+        else launch_any<false>(w->wide, sorted, grid, sorted ? 0 : lds, st, a);
+        TM_HIP(hipGetLastError());
+        t_sample.stop();
+        if (!model_bytes) t_reduce.start(TM_STAGE_REDUCE, st);
+        hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const Partial*)parts,
+                           (int)grid.x, parts + blocks);
+        TM_HIP(hipGetLastError());
+        t_reduce.stop();
+        Partial hc;
+        TM_HIP(hipMemcpyAsync(&hc, parts + blocks, sizeof hc, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipMemcpyAsync(&hovf, ovf, sizeof hovf, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipStreamSynchronize(st));
+        t_roots.finish();
+        t_sample.finish();
+        t_reduce.finish();
+        if (hovf) break;
+        if (!add_ok(h.acc2, hc.acc2, &h.acc2)) h.flags |= 1;
+        if (!add_ok(h.acc2_sq, hc.acc2_sq, &h.acc2_sq)) {
+            h.acc2_sq = ~(u128)0;
+            h.flags |= 2;
+        }
+        h.n_valid += hc.n_valid;
+        h.n_vertex += hc.n_vertex;
+        h.n_delta += hc.n_delta;
+        h.n_order += hc.n_order;
+        h.n_nonzero += hc.n_nonzero;
+        h.flags |= hc.flags;
+        h.bytes += hc.bytes;
+    }
     TM_HIP(hipFreeAsync(parts, st));
     TM_HIP(hipFreeAsync(ovf, st));
-    TM_HIP(hipStreamSynchronize(st));
-    t_sample.finish();
-    t_reduce.finish();
+    if (sorted) {
+        TM_HIP(hipFreeAsync(k0, st));
+        TM_HIP(hipFreeAsync(v0, st));
+        TM_HIP(hipFreeAsync(k1, st));
+        TM_HIP(hipFreeAsync(v1, st));
+    }
     if (model_bytes) *model_bytes = h.bytes;
     if (hovf & 2) return tm_fail(TM_EDEVICE, "sample: inconsistent weight tables");
     if (hovf || (h.flags & 1)) return tm_fail(TM_EOVERFLOW, "sample: a count reaches 2^128");

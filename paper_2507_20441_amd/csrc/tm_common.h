@@ -38,6 +38,7 @@ struct DevGraph {
     const u64* nkey[2];        // N order: neighbour << bt | time
     const int32_t* nxref[2];   // N order: position of the edge in the T order
     const int32_t* neid[2];    // N order: eid
+    const int32_t* tpos[2];    // by eid: the edge's position in the T order
 };
 
 // ---------------------------------------------------------------------------
