@@ -49,26 +49,11 @@ extern "C" int tm_profile_read(tm_profile* out, int reset) {
     return TM_OK;
 }
 
-void pool_setup() {
-    static std::mutex mu;
-    static bool done[64] = {false};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
-    std::lock_guard<std::mutex> lk(mu);
-    if (done[dev]) return;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t keep = ~0ull;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-    }
-    done[dev] = true;
-}
-
 int DevArena::alloc(void** p, size_t nbytes) {
     *p = nullptr;
     if (nbytes == 0) nbytes = 16;
     nbytes = (nbytes + 255) & ~(size_t)255;
-    hipError_t e = hipMallocAsync(p, nbytes, stream);
+    hipError_t e = dev_alloc(p, nbytes, stream);
     if (e != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
@@ -80,9 +65,11 @@ int DevArena::alloc(void** p, size_t nbytes) {
     return TM_OK;
 }
 
+// Called when no work of the library is in flight (every entry point
+// synchronises before it returns), so the blocks are free for any stream.
 void DevArena::release() {
-    for (void* p : blocks) (void)hipFreeAsync(p, stream);
-    if (!blocks.empty()) (void)hipStreamSynchronize(stream);
+    for (void* p : blocks) (void)dev_free(p, stream);
+    if (!blocks.empty()) dev_stream_synced(stream);
     blocks.clear();
     bytes = 0;
 }
@@ -316,7 +303,6 @@ extern "C" int tm_graph_create(const int32_t* src, const int32_t* dst, const int
     g->m = m;
     g->n = n;
     (void)hipGetDevice(&g->device);
-    pool_setup();
     g->arena.stream = st;
     const int32_t *ds = src, *dd = dst;
     const int64_t* dt = t;
@@ -326,7 +312,7 @@ extern "C" int tm_graph_create(const int32_t* src, const int32_t* dst, const int
         const size_t sz[3] = {m * sizeof(int32_t), m * sizeof(int32_t), m * sizeof(int64_t)};
         const void* hp[3] = {src, dst, t};
         for (int a = 0; a < 3 && rc == TM_OK; ++a) {
-            hipError_t e = hipMallocAsync(&staged[a], sz[a], st);
+            hipError_t e = dev_alloc(&staged[a], sz[a], st);
             if (e == hipSuccess) e = hipMemcpyAsync(staged[a], hp[a], sz[a], hipMemcpyHostToDevice, st);
             if (e != hipSuccess)
                 rc = tm_fail(e == hipErrorOutOfMemory ? TM_ENOMEM : TM_EDEVICE, "graph: staging: %s",
@@ -338,8 +324,8 @@ extern "C" int tm_graph_create(const int32_t* src, const int32_t* dst, const int
     }
     if (rc == TM_OK) rc = graph_build(g, ds, dd, dt, st);
     for (void* p : staged)
-        if (p) (void)hipFreeAsync(p, st);
-    (void)hipStreamSynchronize(st);
+        if (p) (void)dev_free(p, st);
+    (void)sync_stream(st);
     if (rc != TM_OK) {
         g->arena.release();
         delete g;
@@ -387,7 +373,7 @@ extern "C" int tm_graph_export(const tm_graph* g, int which, void* host_out, voi
     if (bytes == 0 || !p) return TM_OK;
     hipStream_t st = as_stream(stream);
     TM_HIP(hipMemcpyAsync(host_out, p, bytes, hipMemcpyDeviceToHost, st));
-    TM_HIP(hipStreamSynchronize(st));
+    TM_HIP(sync_stream(st));
     return TM_OK;
 }
 
@@ -404,7 +390,6 @@ extern "C" int tm_weights_create(tm_graph* g, const tm_motif* mo, const tm_tree*
     if (!w) return tm_fail(TM_ENOMEM, "weights: host allocation");
     w->g = g;
     w->arena.stream = as_stream(stream);
-    pool_setup();
     int rc = plan_build(mo, tr, &w->plan);
     if (rc == TM_OK) rc = weights_build(w, as_stream(stream));
     if (rc != TM_OK) {
@@ -456,7 +441,7 @@ extern "C" int tm_weights_export(const tm_weights* w, int32_t s, int32_t slot, t
             v[par].resize(m * wsz);
             TM_HIP(hipMemcpyAsync(v[par].data(), w->vals[sl][par], m * wsz, hipMemcpyDeviceToHost, st));
         }
-    TM_HIP(hipStreamSynchronize(st));
+    TM_HIP(sync_stream(st));
     for (int64_t e = 0; e < m; ++e) {
         const int64_t i = t[e] / P.mo.delta - slot;
         tm_u128 x = {0, 0};
@@ -481,7 +466,7 @@ extern "C" int tm_weights_intervals(const tm_weights* w, tm_u128* host_out, void
     const size_t wsz = w->wide ? 16 : 8;
     std::vector<unsigned char> c((w->q + 1) * wsz);
     TM_HIP(hipMemcpyAsync(c.data(), w->cumW, c.size(), hipMemcpyDeviceToHost, st));
-    TM_HIP(hipStreamSynchronize(st));
+    TM_HIP(sync_stream(st));
     auto at = [&](int64_t i) {
         u128 x = 0;
         u64 lo = 0, hi = 0;

@@ -185,7 +185,7 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
             TM_HIP(hipMemsetAsync(off, 0, ((size_t)n + 1) * sizeof(int32_t), st));
             D.off[dir] = off;
         }
-        TM_HIP(hipStreamSynchronize(st));
+        TM_HIP(sync_stream(st));
         return TM_OK;
     }
 
@@ -194,8 +194,8 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
     // --- validation: ids, self loops, time span -------------------------
     int* flags = nullptr;
     u64* tbounds = nullptr;
-    TM_HIP(hipMallocAsync((void**)&flags, sizeof(int) * 2, st));
-    TM_HIP(hipMallocAsync((void**)&tbounds, sizeof(u64) * 2, st));
+    TM_HIP(dev_alloc((void**)&flags, sizeof(int) * 2, st));
+    TM_HIP(dev_alloc((void**)&tbounds, sizeof(u64) * 2, st));
     const u64 init[2] = {~0ull, 0ull};
     TM_HIP(hipMemsetAsync(flags, 0, sizeof(int) * 2, st));
     TM_HIP(hipMemcpyAsync(tbounds, init, sizeof init, hipMemcpyHostToDevice, st));
@@ -209,7 +209,7 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
     u64 hb[2];
     TM_HIP(hipMemcpyAsync(hflags, flags, sizeof hflags, hipMemcpyDeviceToHost, st));
     TM_HIP(hipMemcpyAsync(hb, tbounds, sizeof hb, hipMemcpyDeviceToHost, st));
-    TM_HIP(hipStreamSynchronize(st));
+    TM_HIP(sync_stream(st));
     if (hflags[0] & kBadRange) return tm_fail(TM_EINVAL, "graph: vertex id outside [0, %d)", n);
     if (hflags[0] & kSelfLoop) return tm_fail(TM_ESELFLOOP, "graph: self loop");
     const int64_t tmin = (int64_t)(hb[0] ^ 0x8000000000000000ull);
@@ -229,10 +229,10 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
     // --- canonical order (t, u, v) ----------------------------------------
     u64 *ka = nullptr, *kb = nullptr;
     uint32_t *va = nullptr, *vb = nullptr;
-    TM_HIP(hipMallocAsync((void**)&ka, m * sizeof(u64), st));
-    TM_HIP(hipMallocAsync((void**)&kb, m * sizeof(u64), st));
-    TM_HIP(hipMallocAsync((void**)&va, m * sizeof(uint32_t), st));
-    TM_HIP(hipMallocAsync((void**)&vb, m * sizeof(uint32_t), st));
+    TM_HIP(dev_alloc((void**)&ka, m * sizeof(u64), st));
+    TM_HIP(dev_alloc((void**)&kb, m * sizeof(u64), st));
+    TM_HIP(dev_alloc((void**)&va, m * sizeof(uint32_t), st));
+    TM_HIP(dev_alloc((void**)&vb, m * sizeof(uint32_t), st));
     u64* kres;
     uint32_t* perm;
     const bool one_key = 2 * bn + D.bt <= 64;
@@ -327,15 +327,15 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
         D.nxref[dir] = nxref;
         D.neid[dir] = neid;
     }
-    TM_HIP(hipFreeAsync(ka, st));
-    TM_HIP(hipFreeAsync(kb, st));
-    TM_HIP(hipFreeAsync(va, st));
-    TM_HIP(hipFreeAsync(vb, st));
+    TM_HIP(dev_free(ka, st));
+    TM_HIP(dev_free(kb, st));
+    TM_HIP(dev_free(va, st));
+    TM_HIP(dev_free(vb, st));
     TM_HIP(hipMemcpyAsync(hflags, flags, sizeof hflags, hipMemcpyDeviceToHost, st));
-    TM_HIP(hipFreeAsync(flags, st));
-    TM_HIP(hipFreeAsync(tbounds, st));
+    TM_HIP(dev_free(flags, st));
+    TM_HIP(dev_free(tbounds, st));
     timer.stop();
-    TM_HIP(hipStreamSynchronize(st));
+    TM_HIP(sync_stream(st));
     timer.finish();
     if (hflags[0] & kDup) return tm_fail(TM_EDUP, "graph: duplicate (u, v, t) tuple");
     if (hflags[1]) return tm_fail(TM_EDEVICE, "graph: internal scan overflow");

@@ -1,0 +1,116 @@
+// Device block cache of the TIMEST GPU library.
+//
+// Tables and temporaries are allocated and released on every call; returning
+// them to HIP each time costs milliseconds per call.  Released blocks are kept
+// here instead.  A block released on stream S may serve a later allocation on
+// S at once (stream order makes that safe) and any other stream once S has
+// been synchronised by the library (every entry point synchronises its stream
+// before it returns).  Memory goes back to HIP only when an allocation fails.
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "tm_internal.h"
+
+namespace {
+
+struct Block {
+    void* p;
+    size_t cap;
+    hipStream_t st;
+    bool synced;
+};
+
+constexpr int kMaxDevices = 64;
+
+std::mutex g_mu;
+std::vector<Block> g_free[kMaxDevices];
+std::unordered_map<void*, size_t> g_used;
+
+size_t size_class(size_t bytes) {
+    if (bytes <= 4096) return (bytes + 255) & ~(size_t)255;
+    // steps of 1/8 of the enclosing power of two
+    size_t p2 = 1;
+    while (p2 < bytes) p2 <<= 1;
+    const size_t step = p2 >> 4 > 4096 ? p2 >> 4 : 4096;
+    return (bytes + step - 1) / step * step;
+}
+
+int device_index() {
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= kMaxDevices) return 0;
+    return d;
+}
+
+}  // namespace
+
+hipError_t dev_alloc(void** p, size_t bytes, hipStream_t st) {
+    *p = nullptr;
+    const size_t cls = size_class(bytes ? bytes : 1);
+    const int dev = device_index();
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        std::vector<Block>& fl = g_free[dev];
+        int best = -1;
+        for (int i = 0; i < (int)fl.size(); ++i) {
+            const Block& b = fl[i];
+            if (b.cap < cls || b.cap > 2 * cls) continue;
+            if (!b.synced && b.st != st) continue;
+            if (best < 0 || b.cap < fl[best].cap) best = i;
+        }
+        if (best >= 0) {
+            *p = fl[best].p;
+            g_used[*p] = fl[best].cap;
+            fl.erase(fl.begin() + best);
+            return hipSuccess;
+        }
+    }
+    hipError_t e = hipMalloc(p, cls);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        // give cached, synchronised blocks back and try once more
+        std::vector<void*> drop;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            std::vector<Block>& fl = g_free[dev];
+            for (int i = (int)fl.size() - 1; i >= 0; --i)
+                if (fl[i].synced) {
+                    drop.push_back(fl[i].p);
+                    fl.erase(fl.begin() + i);
+                }
+        }
+        for (void* q : drop) (void)hipFree(q);
+        e = hipMalloc(p, cls);
+        if (e != hipSuccess) {
+            *p = nullptr;
+            return e;
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_used[*p] = cls;
+    return hipSuccess;
+}
+
+hipError_t dev_free(void* p, hipStream_t st) {
+    if (!p) return hipSuccess;
+    const int dev = device_index();
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_used.find(p);
+    if (it == g_used.end()) return hipErrorInvalidValue;
+    g_free[dev].push_back(Block{p, it->second, st, false});
+    g_used.erase(it);
+    return hipSuccess;
+}
+
+void dev_stream_synced(hipStream_t st) {
+    const int dev = device_index();
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (Block& b : g_free[dev])
+        if (b.st == st) b.synced = true;
+}
+
+hipError_t sync_stream(hipStream_t st) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess) dev_stream_synced(st);
+    return e;
+}

@@ -714,7 +714,7 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
             hipLaunchKernelGGL(fill_undrawn_kernel, dim3((unsigned)((count + kBlock - 1) / kBlock)),
                                dim3(kBlock), 0, st, recs, count);
             TM_HIP(hipGetLastError());
-            TM_HIP(hipStreamSynchronize(st));
+            TM_HIP(sync_stream(st));
         }
         return TM_OK;
     }
@@ -779,14 +779,14 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
     Partial* parts = nullptr;
     int* ovf = nullptr;
     uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
-    TM_HIP(hipMallocAsync((void**)&parts, (size_t)(blocks + 1) * sizeof(Partial), st));
-    TM_HIP(hipMallocAsync((void**)&ovf, sizeof(int), st));
+    TM_HIP(dev_alloc((void**)&parts, (size_t)(blocks + 1) * sizeof(Partial), st));
+    TM_HIP(dev_alloc((void**)&ovf, sizeof(int), st));
     TM_HIP(hipMemsetAsync(ovf, 0, sizeof(int), st));
     if (sorted) {
-        TM_HIP(hipMallocAsync((void**)&k0, chunk * sizeof(uint32_t), st));
-        TM_HIP(hipMallocAsync((void**)&v0, chunk * sizeof(uint32_t), st));
-        TM_HIP(hipMallocAsync((void**)&k1, chunk * sizeof(uint32_t), st));
-        TM_HIP(hipMallocAsync((void**)&v1, chunk * sizeof(uint32_t), st));
+        TM_HIP(dev_alloc((void**)&k0, chunk * sizeof(uint32_t), st));
+        TM_HIP(dev_alloc((void**)&v0, chunk * sizeof(uint32_t), st));
+        TM_HIP(dev_alloc((void**)&k1, chunk * sizeof(uint32_t), st));
+        TM_HIP(dev_alloc((void**)&v1, chunk * sizeof(uint32_t), st));
     }
     a.parts = parts;
     a.ovf = ovf;
@@ -827,7 +827,7 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
         Partial hc;
         TM_HIP(hipMemcpyAsync(&hc, parts + blocks, sizeof hc, hipMemcpyDeviceToHost, st));
         TM_HIP(hipMemcpyAsync(&hovf, ovf, sizeof hovf, hipMemcpyDeviceToHost, st));
-        TM_HIP(hipStreamSynchronize(st));
+        TM_HIP(sync_stream(st));
         t_roots.finish();
         t_sample.finish();
         t_reduce.finish();
@@ -845,13 +845,13 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
         h.flags |= hc.flags;
         h.bytes += hc.bytes;
     }
-    TM_HIP(hipFreeAsync(parts, st));
-    TM_HIP(hipFreeAsync(ovf, st));
+    TM_HIP(dev_free(parts, st));
+    TM_HIP(dev_free(ovf, st));
     if (sorted) {
-        TM_HIP(hipFreeAsync(k0, st));
-        TM_HIP(hipFreeAsync(v0, st));
-        TM_HIP(hipFreeAsync(k1, st));
-        TM_HIP(hipFreeAsync(v1, st));
+        TM_HIP(dev_free(k0, st));
+        TM_HIP(dev_free(v0, st));
+        TM_HIP(dev_free(k1, st));
+        TM_HIP(dev_free(v1, st));
     }
     if (model_bytes) *model_bytes = h.bytes;
     if (hovf & 2) return tm_fail(TM_EDEVICE, "sample: inconsistent weight tables");

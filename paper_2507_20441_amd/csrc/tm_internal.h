@@ -29,9 +29,7 @@ int tm_fail(int code, const char* fmt, ...);
     } while (0)
 
 // Device allocations owned by a handle; released together.
-// Allocation is stream-ordered from the device's memory pool, which keeps
-// freed memory cached (see pool_setup), so building and dropping tables per
-// call costs no device-wide synchronisation.
+// Tables owned by a handle, allocated from the library's block cache.
 struct DevArena {
     std::vector<void*> blocks;
     uint64_t bytes = 0;
@@ -45,8 +43,13 @@ int arena_alloc(DevArena& A, T** p, size_t count) {
     return A.alloc(reinterpret_cast<void**>(p), count * sizeof(T));
 }
 
-// Keep freed pool memory cached on the current device (once per device).
-void pool_setup();
+// Device block cache (mem.cpp): stream-aware reuse of released blocks.
+hipError_t dev_alloc(void** p, size_t bytes, hipStream_t st);
+hipError_t dev_free(void* p, hipStream_t st);
+// Every block released on st becomes reusable by any stream.
+void dev_stream_synced(hipStream_t st);
+// hipStreamSynchronize, then dev_stream_synced.
+hipError_t sync_stream(hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Graph handle.

@@ -136,7 +136,7 @@ int device_exclusive_scan(F f, int64_t n, T* out, int* ovf, hipStream_t st) {
     }
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     u128* part = nullptr;
-    TM_HIP(hipMallocAsync((void**)&part, (nb + 1) * sizeof(u128), st));
+    TM_HIP(dev_alloc((void**)&part, (nb + 1) * sizeof(u128), st));
     hipLaunchKernelGGL((scan_tiles_kernel<F>), dim3((unsigned)nb), dim3(kBlock), 0, st, f, n, part,
                        ovf);
     TM_HIP(hipGetLastError());
@@ -146,7 +146,7 @@ int device_exclusive_scan(F f, int64_t n, T* out, int* ovf, hipStream_t st) {
                            n, (const u128*)part, out, ovf);
         TM_HIP(hipGetLastError());
     }
-    TM_HIP(hipFreeAsync(part, st));
+    TM_HIP(dev_free(part, st));
     return rc;
 }
 
@@ -249,7 +249,7 @@ int radix_sort_pairs(K* keys, uint32_t* vals, K* tkeys, uint32_t* tvals, int64_t
     if (n > 1 && nbits > 0) {
         const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
         uint32_t* hist = nullptr;
-        TM_HIP(hipMallocAsync((void**)&hist, (ntiles * kRadix + 1) * sizeof(uint32_t), st));
+        TM_HIP(dev_alloc((void**)&hist, (ntiles * kRadix + 1) * sizeof(uint32_t), st));
         for (int shift = 0; shift < nbits; shift += kRadixBits) {
             const int bits = nbits - shift < kRadixBits ? nbits - shift : kRadixBits;
             hipLaunchKernelGGL((radix_hist_kernel<K>), dim3((unsigned)ntiles), dim3(kBlock), 0, st,
@@ -264,7 +264,7 @@ int radix_sort_pairs(K* keys, uint32_t* vals, K* tkeys, uint32_t* tvals, int64_t
             K* tk = ka; ka = kb; kb = tk;
             uint32_t* tv = va; va = vb; vb = tv;
         }
-        TM_HIP(hipFreeAsync(hist, st));
+        TM_HIP(dev_free(hist, st));
     }
     *k_out = ka;
     *v_out = va;

@@ -297,7 +297,7 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf) {
     w->cumW = cum;
     W hW;
     TM_HIP(hipMemcpyAsync(&hW, cum + w->q, sizeof(W), hipMemcpyDeviceToHost, st));
-    TM_HIP(hipStreamSynchronize(st));
+    TM_HIP(sync_stream(st));
     w->W = to_u128(hW);
     return TM_OK;
 }
@@ -327,7 +327,7 @@ int weights_build(tm_weights* w, hipStream_t st) {
     StageTimer timer;
     timer.start(TM_STAGE_WEIGHTS, st);
     int* ovf = nullptr;
-    TM_HIP(hipMallocAsync((void**)&ovf, sizeof(int), st));
+    TM_HIP(dev_alloc((void**)&ovf, sizeof(int), st));
     int h = 0;
     int rc = TM_OK;
     for (int wide = 0; wide < 2; ++wide) {
@@ -337,13 +337,13 @@ int weights_build(tm_weights* w, hipStream_t st) {
         rc = wide ? build_typed<u128>(w, st, ovf) : build_typed<u64>(w, st, ovf);
         if (rc != TM_OK) break;
         TM_HIP(hipMemcpyAsync(&h, ovf, sizeof(int), hipMemcpyDeviceToHost, st));
-        TM_HIP(hipStreamSynchronize(st));
+        TM_HIP(sync_stream(st));
         if (h == 0) break;
         if (wide) rc = tm_fail(TM_EOVERFLOW, "weights: a weight or W reaches 2^128");
     }
-    TM_HIP(hipFreeAsync(ovf, st));
+    TM_HIP(dev_free(ovf, st));
     timer.stop();
-    TM_HIP(hipStreamSynchronize(st));
+    TM_HIP(sync_stream(st));
     timer.finish();
     if (rc != TM_OK) clear_tables(w);
     return rc;
