@@ -206,6 +206,35 @@ int tm_sample(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count, uint64_
 int tm_estimate(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint64_t k,
                 uint64_t seed, void* stream, tm_result* out);
 
+/* ---- batched estimation (many jobs in one pass) -------------------------
+ * Every job's samples are drawn exactly as tm_sample draws them (same seed,
+ * same sample ids 0 .. k-1), so each job's result is bit-identical to its
+ * own tm_sample / tm_estimate; only the schedule differs.  The root draws of
+ * all jobs run in one launch, one radix sort orders all samples by (job,
+ * root list position), and persistent kernels pull (job, sample range)
+ * tiles from a device counter, with one reduction per job.  Per-job errors
+ * go to out[i].status; the call fails only on a device or argument error. */
+
+/* Sample jobs i = 0 .. n_jobs-1 from resident weight sets: k[i] samples with
+ * seed seed[i] from w[i].  Synchronises the stream. */
+int tm_sample_batch(tm_weights* const* w, const uint64_t* k, const uint64_t* seed, int n_jobs,
+                    void* stream, tm_result* out);
+
+/* Whole estimates for n_jobs (graph, motif, tree, k, seed) jobs: the 64-bit
+ * weight builds of all jobs are enqueued back to back with a single
+ * synchronisation (jobs that overflow 64 bits are rebuilt in 128 bits), then
+ * tm_sample_batch.  tr may be NULL (default trees) or hold per-job pointers
+ * (NULL entries take the default).  Results equal tm_estimate's per job. */
+int tm_estimate_batch(tm_graph* const* g, const tm_motif* mo, const tm_tree* const* tr,
+                      const uint64_t* k, const uint64_t* seed, int n_jobs, void* stream,
+                      tm_result* out);
+
+/* Schedule of the batched kernels: samples per tile (>= 256) and the grid of
+ * the persistent kernels (0 = 8 workgroups per compute unit).  Process-wide;
+ * the autotuner in the Python package searches these.  Returns the previous
+ * values through prev_tile / prev_blocks when not NULL. */
+int tm_batch_config(int tile, int blocks, int* prev_tile, int* prev_blocks);
+
 /* ---- measurement --------------------------------------------------------
  * Device time of the library's stages, measured with HIP events recorded on
  * the caller's stream around each stage's kernels (no extra synchronisation:

@@ -526,3 +526,134 @@ extern "C" int tm_estimate(tm_graph* g, const tm_motif* mo, const tm_tree* tr, u
     tm_weights_destroy(w);
     return rc;
 }
+
+// ---------------------------------------------------------------------------
+// Batched estimation.
+// ---------------------------------------------------------------------------
+static std::mutex g_cfg_mu;
+
+extern "C" int tm_batch_config(int tile, int blocks, int* prev_tile, int* prev_blocks) {
+    if (tile < 256 || blocks < 0) return tm_fail(TM_EINVAL, "batch_config: tile %d, blocks %d", tile, blocks);
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    if (prev_tile) *prev_tile = g_batch_config.tile;
+    if (prev_blocks) *prev_blocks = g_batch_config.blocks;
+    g_batch_config.tile = tile;
+    g_batch_config.blocks = blocks;
+    return TM_OK;
+}
+
+static BatchConfig batch_config_now() {
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    return g_batch_config;
+}
+
+extern "C" int tm_sample_batch(tm_weights* const* w, const uint64_t* k, const uint64_t* seed, int n_jobs,
+                               void* stream, tm_result* out) {
+    if (n_jobs < 0 || (n_jobs > 0 && (!w || !k || !seed || !out)))
+        return tm_fail(TM_EINVAL, "sample_batch: bad arguments");
+    for (int i = 0; i < n_jobs; ++i)
+        if (!w[i]) return tm_fail(TM_EINVAL, "sample_batch: job %d has no weights", i);
+    if (n_jobs == 0) return TM_OK;
+    std::vector<u64> kk(k, k + n_jobs), ss(seed, seed + n_jobs);
+    TM_TRY(batch_sample_run(w, kk.data(), ss.data(), n_jobs, as_stream(stream), out, batch_config_now()));
+    for (int i = 0; i < n_jobs; ++i)
+        if (out[i].status == TM_OK) finish_result(&out[i]);
+    return TM_OK;
+}
+
+extern "C" int tm_estimate_batch(tm_graph* const* g, const tm_motif* mo, const tm_tree* const* tr,
+                                 const uint64_t* k, const uint64_t* seed, int n_jobs, void* stream,
+                                 tm_result* out) {
+    if (n_jobs < 0 || (n_jobs > 0 && (!g || !mo || !k || !seed || !out)))
+        return tm_fail(TM_EINVAL, "estimate_batch: bad arguments");
+    if (n_jobs == 0) return TM_OK;
+    hipStream_t st = as_stream(stream);
+    std::vector<tm_weights*> ws(n_jobs, nullptr);
+    std::vector<int> status(n_jobs, TM_OK);
+    int* flags = nullptr;
+    u64* wdev = nullptr;
+    TM_HIP(dev_alloc((void**)&flags, n_jobs * sizeof(int), st));
+    TM_HIP(dev_alloc((void**)&wdev, n_jobs * sizeof(u64), st));
+    TM_TRY(fill_u32(flags, n_jobs, 0u, st));
+    TM_TRY(fill_u32(wdev, 2 * n_jobs, 0u, st));
+    StageTimer timer;
+    timer.start(TM_STAGE_WEIGHTS, st);
+    // every job's 64-bit weight build, back to back, no synchronisation
+    for (int i = 0; i < n_jobs; ++i) {
+        if (!g[i]) { status[i] = tm_fail(TM_EINVAL, "estimate_batch: job %d has no graph", i); continue; }
+        tm_tree def;
+        const tm_tree* ti = tr ? tr[i] : nullptr;
+        if (!ti) {
+            const int rc = tm_default_tree(&mo[i], &def);
+            if (rc != TM_OK) { status[i] = rc; continue; }
+            ti = &def;
+        }
+        tm_weights* w = new (std::nothrow) tm_weights();
+        if (!w) { status[i] = tm_fail(TM_ENOMEM, "estimate_batch: host allocation"); continue; }
+        w->g = g[i];
+        w->arena.stream = st;
+        int rc = plan_build(&mo[i], ti, &w->plan);
+        if (rc == TM_OK) rc = weights_enqueue(w, st, flags + i);
+        if (rc == TM_OK && w->q > 0)
+            rc = hipMemcpyAsync(wdev + i, static_cast<const unsigned char*>(w->cumW) + w->q * 8, 8,
+                                hipMemcpyDeviceToDevice, st) == hipSuccess ? TM_OK : TM_EDEVICE;
+        if (rc != TM_OK) {
+            w->arena.release();
+            delete w;
+            status[i] = rc;
+            continue;
+        }
+        ws[i] = w;
+    }
+    std::vector<int> hflags(n_jobs, 0);
+    std::vector<u64> hW(n_jobs, 0);
+    TM_HIP(hipMemcpyAsync(hflags.data(), flags, n_jobs * sizeof(int), hipMemcpyDeviceToHost, st));
+    TM_HIP(hipMemcpyAsync(hW.data(), wdev, n_jobs * sizeof(u64), hipMemcpyDeviceToHost, st));
+    TM_HIP(dev_free(flags, st));
+    TM_HIP(dev_free(wdev, st));
+    TM_HIP(sync_stream(st));
+    // jobs whose 64-bit build overflowed are rebuilt with the widening path
+    for (int i = 0; i < n_jobs; ++i) {
+        if (!ws[i]) continue;
+        if (hflags[i]) {
+            const int rc = weights_build(ws[i], st);
+            if (rc != TM_OK) {
+                tm_weights_destroy(ws[i]);
+                ws[i] = nullptr;
+                status[i] = rc;
+            }
+        } else {
+            ws[i]->W = hW[i];
+        }
+    }
+    timer.stop();
+    TM_HIP(sync_stream(st));
+    timer.finish();
+    std::vector<tm_weights*> act;
+    std::vector<u64> kk, ss;
+    std::vector<int> idx;
+    for (int i = 0; i < n_jobs; ++i) {
+        if (!ws[i]) {
+            std::memset(&out[i], 0, sizeof(tm_result));
+            out[i].k = k[i];
+            out[i].status = status[i];
+            continue;
+        }
+        act.push_back(ws[i]);
+        kk.push_back(k[i]);
+        ss.push_back(seed[i]);
+        idx.push_back(i);
+    }
+    int rc = TM_OK;
+    if (!act.empty()) {
+        std::vector<tm_result> r(act.size());
+        rc = batch_sample_run(act.data(), kk.data(), ss.data(), (int)act.size(), st, r.data(),
+                              batch_config_now());
+        for (size_t a = 0; a < act.size() && rc == TM_OK; ++a) {
+            out[idx[a]] = r[a];
+            if (r[a].status == TM_OK) finish_result(&out[idx[a]]);
+        }
+    }
+    for (tm_weights* w : ws) tm_weights_destroy(w);
+    return rc;
+}

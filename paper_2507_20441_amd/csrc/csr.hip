@@ -240,15 +240,15 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
                        bn, one_key ? 1 : 0, ka, va);
     TM_HIP(hipGetLastError());
     if (one_key) {
-        TM_TRY(radix_sort_pairs<u64>(ka, va, kb, vb, m, 2 * bn + D.bt, &kres, &perm, flags + 1, st));
+        TM_TRY(radix_sort_pairs<u64>(ka, va, kb, vb, m, 0, 2 * bn + D.bt, &kres, &perm, flags + 1, st));
     } else {
-        TM_TRY(radix_sort_pairs<u64>(ka, va, kb, vb, m, 2 * bn, &kres, &perm, flags + 1, st));
+        TM_TRY(radix_sort_pairs<u64>(ka, va, kb, vb, m, 0, 2 * bn, &kres, &perm, flags + 1, st));
         u64* kother = kres == ka ? kb : ka;
         uint32_t* vother = perm == va ? vb : va;
         hipLaunchKernelGGL(key_time_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, t, perm, m,
                            tmin, kother);
         TM_HIP(hipGetLastError());
-        TM_TRY(radix_sort_pairs<u64>(kother, perm, kres, vother, m, D.bt, &kres, &perm, flags + 1,
+        TM_TRY(radix_sort_pairs<u64>(kother, perm, kres, vother, m, 0, D.bt, &kres, &perm, flags + 1,
                                      st));
     }
     int32_t *esrc, *edst;
@@ -288,7 +288,7 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
                            k32a, va);
         TM_HIP(hipGetLastError());
         uint32_t *kr, *vr;
-        TM_TRY(radix_sort_pairs<uint32_t>(k32a, va, k32b, vb, m, bn, &kr, &vr, flags + 1, st));
+        TM_TRY(radix_sort_pairs<uint32_t>(k32a, va, k32b, vb, m, 0, bn, &kr, &vr, flags + 1, st));
         hipLaunchKernelGGL(fill_t_order_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
                            (const uint32_t*)vr, (const int64_t*)et, nbr_by_eid, m, lt, leid, lnbr,
                            tpos[dir]);
@@ -318,7 +318,7 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
                            D.lnbr[other], D.leid[other], m, k32a, va);
         TM_HIP(hipGetLastError());
         uint32_t *kr, *vr;
-        TM_TRY(radix_sort_pairs<uint32_t>(k32a, va, k32b, vb, m, bn, &kr, &vr, flags + 1, st));
+        TM_TRY(radix_sort_pairs<uint32_t>(k32a, va, k32b, vb, m, 0, bn, &kr, &vr, flags + 1, st));
         hipLaunchKernelGGL(fill_n_order_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
                            (const uint32_t*)vr, (const int64_t*)et, nbr_by_eid,
                            (const int32_t*)tpos[dir], m, D.bt, nkey, nxref, neid);

@@ -56,6 +56,15 @@ struct SampleArgs {
     int* ovf;
     const uint32_t* skey;  // root-sorted order: T-order position of the root * 2 + interval parity
     const uint32_t* sval;  // ... and the sample's offset in [0, count)
+    uint32_t key_mask;     // bits of skey holding the root key (the rest name the job)
+};
+
+// Per-lane running sums of a sampling pass.
+struct LaneAcc {
+    u128 acc2, acc2_sq;
+    uint32_t n_valid, n_vertex, n_delta, n_order, n_nonzero;
+    u64 flags, nb;
+    bool ovf, bad;
 };
 
 struct Partial {
@@ -358,6 +367,25 @@ __device__ __forceinline__ void block_reduce_write(Partial acc, Partial* out) {
 // ---------------------------------------------------------------------------
 // The sampling kernel.
 // ---------------------------------------------------------------------------
+// Draw 0 of sample a.j0 + r: the interval, then the center edge; returned as
+// the root key (T-order position of the root * 2 + interval parity).
+// Inconsistent tables give a harmless key and set bad.
+template <typename W>
+__device__ __forceinline__ uint32_t root_key(const SampleArgs& a, const W* cum, W Wtot, int32_t ncum,
+                                             u64 r, bool& bad) {
+    const W r0 = scale(draw_block(a.seed, a.j0 + r, 0), Wtot);
+    const int32_t i = upper_bound_bl<W>(cum, 0, ncum, r0) - 1;
+    const int32_t lo = (i >= 0 && i < a.q) ? a.ilo[i] : 0, hi = (i >= 0 && i < a.q) ? a.ihi[i] : 0;
+    if (hi <= lo) {
+        bad = true;
+        return 0u;
+    }
+    const W* qc = static_cast<const W*>(a.qc[i & 1]);
+    int32_t e0 = upper_bound_bl<W>(qc, lo + 1, hi + 1, r0 - cum[i] + qc[lo]) - 1;
+    e0 = e0 < lo ? lo : (e0 >= hi ? hi - 1 : e0);
+    return (uint32_t)a.G.tpos[0][e0] * 2u + (uint32_t)(i & 1);
+}
+
 // Draw 0 of each sample (interval, then center edge), written as a sort key:
 // the root's position in the out-list T order (grouping samples by source
 // vertex and time) and the interval's parity.  The sort that follows changes
@@ -378,41 +406,27 @@ __global__ void __launch_bounds__(kBlock) root_kernel(SampleArgs a, uint32_t* ke
     bool bad = false;
     const u64 stride = (u64)gridDim.x * kBlock;
     for (u64 r = (u64)blockIdx.x * kBlock + threadIdx.x; r < a.count; r += stride) {
-        const W r0 = scale(draw_block(a.seed, a.j0 + r, 0), Wtot);
-        const int32_t i = upper_bound_bl<W>(cum, 0, ncum, r0) - 1;
-        if (i < 0 || i >= a.q) { bad = true; break; }
-        const W* qc = static_cast<const W*>(a.qc[i & 1]);
-        const int32_t lo = a.ilo[i], hi = a.ihi[i];
-        if (hi <= lo) { bad = true; break; }
-        int32_t e0 = upper_bound_bl<W>(qc, lo + 1, hi + 1, r0 - cum[i] + qc[lo]) - 1;
-        e0 = e0 < lo ? lo : (e0 >= hi ? hi - 1 : e0);
-        keys[r] = (uint32_t)G.tpos[0][e0] * 2u + (uint32_t)(i & 1);
+        keys[r] = root_key<W>(a, cum, Wtot, ncum, r, bad);
         vals[r] = (uint32_t)r;
     }
     if (bad) atomicOr(a.ovf, 2);
 }
 
+// Samples at positions x = x0, x0 + stride, ... < xend: sample offsets in
+// [0, count), or, in root-sorted order, positions of the sorted arrays.
 template <typename W, bool kCount, bool kGeneral, bool kSorted>
-__global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
+__device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* cum, u64 x0, u64 xend,
+                                                 u64 stride, LaneAcc& L) {
     constexpr int NT = kMaxSlots - 1;  // register slots; a.nt of them are used
-    extern __shared__ unsigned char lds_raw[];
     const DevGraph& G = a.G;
     const W Wtot = (W)(((u128)a.W_hi << 64) | a.W_lo);
-    const W* cumG = static_cast<const W*>(a.cumW);
     const int32_t ncum = (int32_t)a.q + 1;
-    W* cumL = reinterpret_cast<W*>(lds_raw);
-    if (!kSorted && a.cum_in_lds) {
-        for (int32_t x = threadIdx.x; x < ncum; x += kBlock) cumL[x] = cumG[x];
-        __syncthreads();
-    }
-    const W* cum = a.cum_in_lds ? cumL : cumG;
-
-    u128 acc2 = 0, acc2_sq = 0;
-    uint32_t n_valid = 0, n_vertex = 0, n_delta = 0, n_order = 0, n_nonzero = 0;
-    u64 flags = 0, nb = 0;
-    bool ovf = false, bad = false;
-    const u64 stride = (u64)gridDim.x * kBlock;
-    for (u64 x = (u64)blockIdx.x * kBlock + threadIdx.x; x < a.count; x += stride) {
+    u128 acc2 = L.acc2, acc2_sq = L.acc2_sq;
+    uint32_t n_valid = L.n_valid, n_vertex = L.n_vertex, n_delta = L.n_delta, n_order = L.n_order,
+             n_nonzero = L.n_nonzero;
+    u64 flags = L.flags, nb = L.nb;
+    bool ovf = L.ovf, bad = L.bad;
+    for (u64 x = x0; x < xend; x += stride) {
         int32_t ee[NT], eu[NT], ev[NT];
         int64_t te[NT];
         int32_t img[TM_MAX_K];
@@ -421,7 +435,7 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
         int32_t i;
         if constexpr (kSorted) {
             // the root was drawn by root_kernel; lanes follow the sorted order
-            const uint32_t key = a.skey[x];
+            const uint32_t key = a.skey[x] & a.key_mask;
             r = a.sval[x];
             const int32_t pos = (int32_t)(key >> 1);
             const int32_t e0 = G.leid[0][pos];
@@ -624,19 +638,61 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
             out.m_phi.hi = (u64)(m_phi >> 64);
         }
     }
+    L.acc2 = acc2;
+    L.acc2_sq = acc2_sq;
+    L.n_valid = n_valid;
+    L.n_vertex = n_vertex;
+    L.n_delta = n_delta;
+    L.n_order = n_order;
+    L.n_nonzero = n_nonzero;
+    L.flags = flags;
+    L.nb = nb;
+    L.ovf = ovf;
+    L.bad = bad;
+}
+
+__device__ __forceinline__ LaneAcc lane_zero() {
+    LaneAcc L;
+    L.acc2 = 0;
+    L.acc2_sq = 0;
+    L.n_valid = L.n_vertex = L.n_delta = L.n_order = L.n_nonzero = 0;
+    L.flags = L.nb = 0;
+    L.ovf = L.bad = false;
+    return L;
+}
+
+// Block-wide sum of the lanes' partials into *out; flags into *ovf.
+__device__ __forceinline__ void lanes_reduce(const LaneAcc& L, Partial* out, int* ovf) {
     Partial acc;
-    acc.acc2 = acc2;
-    acc.acc2_sq = acc2_sq;
-    acc.n_valid = n_valid;
-    acc.n_vertex = n_vertex;
-    acc.n_delta = n_delta;
-    acc.n_order = n_order;
-    acc.n_nonzero = n_nonzero;
-    acc.flags = flags;
-    acc.bytes = nb;
-    block_reduce_write(acc, &a.parts[blockIdx.x]);
-    if (ovf) atomicOr(a.ovf, 1);
-    if (bad) atomicOr(a.ovf, 2);
+    acc.acc2 = L.acc2;
+    acc.acc2_sq = L.acc2_sq;
+    acc.n_valid = L.n_valid;
+    acc.n_vertex = L.n_vertex;
+    acc.n_delta = L.n_delta;
+    acc.n_order = L.n_order;
+    acc.n_nonzero = L.n_nonzero;
+    acc.flags = L.flags;
+    acc.bytes = L.nb;
+    block_reduce_write(acc, out);
+    if (L.ovf) atomicOr(ovf, 1);
+    if (L.bad) atomicOr(ovf, 2);
+}
+
+template <typename W, bool kCount, bool kGeneral, bool kSorted>
+__global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
+    extern __shared__ unsigned char lds_raw[];
+    const W* cumG = static_cast<const W*>(a.cumW);
+    const int32_t ncum = (int32_t)a.q + 1;
+    W* cumL = reinterpret_cast<W*>(lds_raw);
+    if (!kSorted && a.cum_in_lds) {
+        for (int32_t x = threadIdx.x; x < ncum; x += kBlock) cumL[x] = cumG[x];
+        __syncthreads();
+    }
+    const W* cum = a.cum_in_lds ? cumL : cumG;
+    LaneAcc L = lane_zero();
+    sample_positions<W, kCount, kGeneral, kSorted>(a, cum, (u64)blockIdx.x * kBlock + threadIdx.x,
+                                                   a.count, (u64)gridDim.x * kBlock, L);
+    lanes_reduce(L, &a.parts[blockIdx.x], a.ovf);
 }
 
 // Sum of the block partials (integers: the order does not matter).
@@ -693,33 +749,10 @@ int bits_of(u64 x) {
     return b;
 }
 
-}  // namespace
-
-int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStream_t st,
-               tm_result* out, tm_sample_rec* recs, u64* model_bytes) {
-    if (model_bytes) {
-        *model_bytes = 0;
-        recs = nullptr;
-    }
+// Per-job kernel arguments from a weight set (everything but the sample range).
+void fill_args(const tm_weights* w, SampleArgs* out, size_t* lds_out) {
     const HostPlan& P = w->plan;
-    std::memset(out, 0, sizeof *out);
-    out->k = k_total;
-    out->q = w->q;
-    out->W.lo = (u64)w->W;
-    out->W.hi = (u64)(w->W >> 64);
-    if (w->wide) out->flags |= TM_F_WIDE;
-    if (w->W == 0 || count == 0) {
-        if (w->W == 0) out->flags |= TM_F_W_ZERO;
-        if (recs && count) {
-            hipLaunchKernelGGL(fill_undrawn_kernel, dim3((unsigned)((count + kBlock - 1) / kBlock)),
-                               dim3(kBlock), 0, st, recs, count);
-            TM_HIP(hipGetLastError());
-            TM_HIP(sync_stream(st));
-        }
-        return TM_OK;
-    }
-    if (P.nt < 1 || P.nt > 7) return tm_fail(TM_EINVAL, "sample: tree with %d edges", P.nt);
-    SampleArgs a;
+    SampleArgs& a = *out;
     std::memset(&a, 0, sizeof a);
     a.G = w->g->d;
     a.delta = P.mo.delta;
@@ -771,7 +804,117 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
         if (P.run_next[r] < 0) has_trail = true;
     }
     if (has_lead && has_trail) a.general_runs = 1;
+    *lds_out = lds;
+}
+
+// ---------------------------------------------------------------------------
+// Batched sampling: many jobs (weight sets) in one pass.  Every sample of
+// every job gets a root key prefixed by its job, one radix sort orders them
+// all, and persistent kernels pull (job, range) tiles from a device counter.
+// ---------------------------------------------------------------------------
+struct Tile {
+    int32_t job;
+    int32_t pad;
+    u64 begin, end;  // sample offsets (roots) or sorted positions (samples) of the job
+    u64 out;         // roots: where the job's keys start in the batch arrays
+};
+
+template <typename W>
+__global__ void __launch_bounds__(kBlock)
+batch_root_kernel(const SampleArgs* jobs, const Tile* tiles, int n_tiles, int* counter, uint32_t* keys,
+                  uint32_t* vals, int kb, int* ovf) {
+    extern __shared__ unsigned char lds_raw[];
+    __shared__ int s_tile;
+    bool bad = false;
+    while (true) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
+        __syncthreads();
+        const int t = s_tile;
+        if (t >= n_tiles) break;
+        const Tile T = tiles[t];
+        const SampleArgs& a = jobs[T.job];
+        const W* cumG = static_cast<const W*>(a.cumW);
+        const int32_t ncum = (int32_t)a.q + 1;
+        W* cumL = reinterpret_cast<W*>(lds_raw);
+        if (a.cum_in_lds) {
+            for (int32_t x = threadIdx.x; x < ncum; x += kBlock) cumL[x] = cumG[x];
+            __syncthreads();
+        }
+        const W* cum = a.cum_in_lds ? cumL : cumG;
+        const W Wtot = (W)(((u128)a.W_hi << 64) | a.W_lo);
+        for (u64 r = T.begin + threadIdx.x; r < T.end; r += kBlock) {
+            keys[T.out + r] = ((uint32_t)T.job << kb) | root_key<W>(a, cum, Wtot, ncum, r, bad);
+            vals[T.out + r] = (uint32_t)r;
+        }
+    }
+    if (bad) atomicOr(ovf, 2);
+}
+
+template <typename W, bool kGeneral>
+__global__ void __launch_bounds__(kBlock)
+batch_sample_kernel(const SampleArgs* jobs, const Tile* tiles, int n_tiles, int* counter,
+                    Partial* tile_parts, int* ovf) {
+    __shared__ int s_tile;
+    while (true) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
+        __syncthreads();
+        const int t = s_tile;
+        if (t >= n_tiles) break;
+        const Tile T = tiles[t];
+        LaneAcc L = lane_zero();
+        sample_positions<W, false, kGeneral, true>(jobs[T.job], nullptr, T.begin + threadIdx.x, T.end,
+                                                   kBlock, L);
+        lanes_reduce(L, &tile_parts[t], ovf);
+    }
+}
+
+// One block per job: the sum of the job's tile partials.
+__global__ void __launch_bounds__(kBlock)
+job_reduce_kernel(const Partial* tile_parts, const int* first, const int* count, Partial* out) {
+    Partial acc;
+    acc.acc2 = 0;
+    acc.acc2_sq = 0;
+    acc.n_valid = acc.n_vertex = acc.n_delta = acc.n_order = acc.n_nonzero = 0;
+    acc.flags = 0;
+    acc.bytes = 0;
+    const int f = first[blockIdx.x], c = count[blockIdx.x];
+    for (int b = threadIdx.x; b < c; b += kBlock) combine(acc, tile_parts[f + b]);
+    block_reduce_write(acc, &out[blockIdx.x]);
+}
+
+}  // namespace
+
+int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStream_t st,
+               tm_result* out, tm_sample_rec* recs, u64* model_bytes) {
+    if (model_bytes) {
+        *model_bytes = 0;
+        recs = nullptr;
+    }
+    const HostPlan& P = w->plan;
+    std::memset(out, 0, sizeof *out);
+    out->k = k_total;
+    out->q = w->q;
+    out->W.lo = (u64)w->W;
+    out->W.hi = (u64)(w->W >> 64);
+    if (w->wide) out->flags |= TM_F_WIDE;
+    if (w->W == 0 || count == 0) {
+        if (w->W == 0) out->flags |= TM_F_W_ZERO;
+        if (recs && count) {
+            hipLaunchKernelGGL(fill_undrawn_kernel, dim3((unsigned)((count + kBlock - 1) / kBlock)),
+                               dim3(kBlock), 0, st, recs, count);
+            TM_HIP(hipGetLastError());
+            TM_HIP(sync_stream(st));
+        }
+        return TM_OK;
+    }
+    if (P.nt < 1 || P.nt > 7) return tm_fail(TM_EINVAL, "sample: tree with %d edges", P.nt);
+    SampleArgs a;
+    size_t lds = 0;
+    fill_args(w, &a, &lds);
     a.seed = seed;
+    a.key_mask = ~0u;
     const bool sorted = count >= kSortMin;
     const u64 chunk = std::min<u64>(count, kChunk);
     const int blocks = (int)std::min<u64>((chunk + kBlock - 1) / kBlock, 8192);
@@ -781,7 +924,7 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
     uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
     TM_HIP(dev_alloc((void**)&parts, (size_t)(blocks + 1) * sizeof(Partial), st));
     TM_HIP(dev_alloc((void**)&ovf, sizeof(int), st));
-    TM_HIP(hipMemsetAsync(ovf, 0, sizeof(int), st));
+    TM_TRY(fill_u32(ovf, 1, 0u, st));
     if (sorted) {
         TM_HIP(dev_alloc((void**)&k0, chunk * sizeof(uint32_t), st));
         TM_HIP(dev_alloc((void**)&v0, chunk * sizeof(uint32_t), st));
@@ -808,7 +951,7 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
                 hipLaunchKernelGGL(root_kernel<u64>, grid, dim3(kBlock), lds, st, a, k0, v0);
             TM_HIP(hipGetLastError());
             uint32_t *ks, *vs;
-            TM_TRY(radix_sort_pairs<uint32_t>(k0, v0, k1, v1, (int64_t)n, key_bits, &ks, &vs, ovf, st));
+            TM_TRY(radix_sort_pairs<uint32_t>(k0, v0, k1, v1, (int64_t)n, 0, key_bits, &ks, &vs, ovf, st));
             a.skey = ks;
             a.sval = vs;
             t_roots.stop();
@@ -866,5 +1009,197 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
     out->n_bad_order = h.n_order;
     out->n_nonzero = h.n_nonzero;
     if (h.flags & 2) out->flags |= TM_F_SQ_SATURATED;
+    return TM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Host side of batched sampling.
+// ---------------------------------------------------------------------------
+BatchConfig g_batch_config = {8192, 0};
+
+int batch_sample_run(tm_weights* const* ws, const u64* ks, const u64* seeds, int n, hipStream_t st,
+                     tm_result* out, const BatchConfig& cfg) {
+    // results of jobs without samples, and the list of active jobs
+    std::vector<int> act;
+    for (int x = 0; x < n; ++x) {
+        tm_weights* w = ws[x];
+        tm_result& o = out[x];
+        std::memset(&o, 0, sizeof o);
+        o.k = ks[x];
+        o.q = w->q;
+        o.W.lo = (u64)w->W;
+        o.W.hi = (u64)(w->W >> 64);
+        if (w->wide) o.flags |= TM_F_WIDE;
+        if (w->W == 0) o.flags |= TM_F_W_ZERO;
+        if (w->W != 0 && ks[x] > 0) act.push_back(x);
+        if (w->plan.nt < 1 || w->plan.nt > 7) return tm_fail(TM_EINVAL, "batch: job %d tree size", x);
+    }
+    const int na = (int)act.size();
+    if (na == 0) return TM_OK;
+    int kb = 1;
+    u64 total = 0;
+    for (int x : act) {
+        kb = std::max(kb, bits_of(2 * (u64)ws[x]->g->m - 1));
+        total += ks[x];
+    }
+    const int jb = bits_of((u64)(na - 1));
+    if (kb + jb > 32 || total >= ((u64)1 << 32) || total < ks[act[0]]) {
+        // too large for one set of 32-bit keys: job by job
+        for (int x : act) {
+            tm_sample_rec* none = nullptr;
+            TM_TRY(sample_run(ws[x], seeds[x], 0, ks[x], ks[x], st, &out[x], none, nullptr));
+        }
+        return TM_OK;
+    }
+    const int tile = cfg.tile > 0 ? cfg.tile : 8192;
+    int cus = 256;
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            cus = prop.multiProcessorCount;
+    }
+    const int blocks = cfg.blocks > 0 ? cfg.blocks : 8 * cus;
+    // job arguments; groups by (wide, general) kernel variant
+    std::vector<SampleArgs> args(na);
+    std::vector<u64> base(na);
+    const int passes = (kb + jb + kRadixBits - 1) / kRadixBits;
+    u64 off = 0;
+    for (int y = 0; y < na; ++y) {
+        size_t lds;
+        fill_args(ws[act[y]], &args[y], &lds);
+        args[y].seed = seeds[act[y]];
+        args[y].j0 = 0;
+        args[y].count = ks[act[y]];
+        args[y].key_mask = (kb >= 32) ? ~0u : ((1u << kb) - 1);
+        base[y] = off;
+        off += ks[act[y]];
+    }
+    std::vector<Tile> rt, stt;
+    std::vector<int> g_rt_first(5, 0), g_st_first(5, 0), jfirst(na), jcount(na);
+    for (int grp = 0; grp < 4; ++grp) {
+        g_rt_first[grp] = (int)rt.size();
+        g_st_first[grp] = (int)stt.size();
+        for (int y = 0; y < na; ++y) {
+            const tm_weights* w = ws[act[y]];
+            const int gy = (w->wide ? 2 : 0) + (args[y].general_runs ? 1 : 0);
+            if (gy != grp) continue;
+            jfirst[y] = (int)stt.size();
+            for (u64 b = 0; b < ks[act[y]]; b += (u64)tile) {
+                const u64 e = std::min<u64>(ks[act[y]], b + (u64)tile);
+                rt.push_back(Tile{y, 0, b, e, base[y]});
+                stt.push_back(Tile{y, 0, base[y] + b, base[y] + e, 0});
+            }
+            jcount[y] = (int)stt.size() - jfirst[y];
+        }
+    }
+    g_rt_first[4] = (int)rt.size();
+    g_st_first[4] = (int)stt.size();
+    // device buffers
+    SampleArgs* djobs = nullptr;
+    Tile *drt = nullptr, *dst = nullptr;
+    uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
+    Partial *tparts = nullptr, *jparts = nullptr;
+    int *ctr = nullptr, *ovf = nullptr, *djf = nullptr, *djc = nullptr;
+    TM_HIP(dev_alloc((void**)&djobs, na * sizeof(SampleArgs), st));
+    TM_HIP(dev_alloc((void**)&drt, rt.size() * sizeof(Tile), st));
+    TM_HIP(dev_alloc((void**)&dst, stt.size() * sizeof(Tile), st));
+    TM_HIP(dev_alloc((void**)&k0, total * sizeof(uint32_t), st));
+    TM_HIP(dev_alloc((void**)&v0, total * sizeof(uint32_t), st));
+    TM_HIP(dev_alloc((void**)&k1, total * sizeof(uint32_t), st));
+    TM_HIP(dev_alloc((void**)&v1, total * sizeof(uint32_t), st));
+    TM_HIP(dev_alloc((void**)&tparts, stt.size() * sizeof(Partial), st));
+    TM_HIP(dev_alloc((void**)&jparts, na * sizeof(Partial), st));
+    TM_HIP(dev_alloc((void**)&ctr, 16 * sizeof(int), st));
+    TM_HIP(dev_alloc((void**)&ovf, sizeof(int), st));
+    TM_HIP(dev_alloc((void**)&djf, na * sizeof(int), st));
+    TM_HIP(dev_alloc((void**)&djc, na * sizeof(int), st));
+    // the sorted arrays end where an even number of passes leaves them
+    uint32_t* ks_sorted = passes % 2 == 0 ? k0 : k1;
+    uint32_t* vs_sorted = passes % 2 == 0 ? v0 : v1;
+    for (int y = 0; y < na; ++y) {
+        args[y].skey = ks_sorted;
+        args[y].sval = vs_sorted;
+    }
+    TM_HIP(hipMemcpyAsync(djobs, args.data(), na * sizeof(SampleArgs), hipMemcpyHostToDevice, st));
+    TM_HIP(hipMemcpyAsync(drt, rt.data(), rt.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
+    TM_HIP(hipMemcpyAsync(dst, stt.data(), stt.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
+    TM_HIP(hipMemcpyAsync(djf, jfirst.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
+    TM_HIP(hipMemcpyAsync(djc, jcount.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
+    TM_TRY(fill_u32(ctr, 16, 0u, st));
+    TM_TRY(fill_u32(ovf, 1, 0u, st));
+    StageTimer t_roots, t_sample, t_reduce;
+    t_roots.start(TM_STAGE_ROOTS, st);
+    for (int grp = 0; grp < 4; ++grp) {
+        const int nt = g_rt_first[grp + 1] - g_rt_first[grp];
+        if (nt == 0) continue;
+        const dim3 grid((unsigned)std::min(blocks, nt));
+        const Tile* tl = drt + g_rt_first[grp];
+        if (grp >= 2)
+            hipLaunchKernelGGL(batch_root_kernel<u128>, grid, dim3(kBlock), kCumLdsBytes, st, djobs, tl, nt,
+                               ctr + grp, k0, v0, kb, ovf);
+        else
+            hipLaunchKernelGGL(batch_root_kernel<u64>, grid, dim3(kBlock), kCumLdsBytes, st, djobs, tl, nt,
+                               ctr + grp, k0, v0, kb, ovf);
+        TM_HIP(hipGetLastError());
+    }
+    {
+        uint32_t *ksr, *vsr;
+        TM_TRY(radix_sort_pairs<uint32_t>(k0, v0, k1, v1, (int64_t)total, 0, kb + jb, &ksr, &vsr, ovf, st));
+        if (ksr != ks_sorted) return tm_fail(TM_EDEVICE, "batch: unexpected sort buffer");
+    }
+    t_roots.stop();
+    t_sample.start(TM_STAGE_SAMPLE, st);
+    for (int grp = 0; grp < 4; ++grp) {
+        const int nt = g_st_first[grp + 1] - g_st_first[grp];
+        if (nt == 0) continue;
+        const dim3 grid((unsigned)std::min(blocks, nt));
+        const Tile* tl = dst + g_st_first[grp];
+        Partial* tp = tparts + g_st_first[grp];
+        int* c = ctr + 4 + grp;
+        switch (grp) {
+            case 0: hipLaunchKernelGGL((batch_sample_kernel<u64, false>), grid, dim3(kBlock), 0, st, djobs, tl, nt, c, tp, ovf); break;
+            case 1: hipLaunchKernelGGL((batch_sample_kernel<u64, true>), grid, dim3(kBlock), 0, st, djobs, tl, nt, c, tp, ovf); break;
+            case 2: hipLaunchKernelGGL((batch_sample_kernel<u128, false>), grid, dim3(kBlock), 0, st, djobs, tl, nt, c, tp, ovf); break;
+            default: hipLaunchKernelGGL((batch_sample_kernel<u128, true>), grid, dim3(kBlock), 0, st, djobs, tl, nt, c, tp, ovf); break;
+        }
+        TM_HIP(hipGetLastError());
+    }
+    t_sample.stop();
+    t_reduce.start(TM_STAGE_REDUCE, st);
+    hipLaunchKernelGGL(job_reduce_kernel, dim3(na), dim3(kBlock), 0, st, (const Partial*)tparts,
+                       (const int*)djf, (const int*)djc, jparts);
+    TM_HIP(hipGetLastError());
+    t_reduce.stop();
+    std::vector<Partial> hp(na);
+    int hovf = 0;
+    TM_HIP(hipMemcpyAsync(hp.data(), jparts, na * sizeof(Partial), hipMemcpyDeviceToHost, st));
+    TM_HIP(hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, st));
+    for (void* q : {(void*)djobs, (void*)drt, (void*)dst, (void*)k0, (void*)v0, (void*)k1, (void*)v1,
+                    (void*)tparts, (void*)jparts, (void*)ctr, (void*)ovf, (void*)djf, (void*)djc})
+        TM_HIP(dev_free(q, st));
+    TM_HIP(sync_stream(st));
+    t_roots.finish();
+    t_sample.finish();
+    t_reduce.finish();
+    if (hovf & 2) return tm_fail(TM_EDEVICE, "batch: inconsistent weight tables");
+    for (int y = 0; y < na; ++y) {
+        const Partial& h = hp[y];
+        tm_result& o = out[act[y]];
+        if ((hovf & 1) || (h.flags & 1)) {
+            o.status = TM_EOVERFLOW;
+            continue;
+        }
+        o.acc2.lo = (u64)h.acc2;
+        o.acc2.hi = (u64)(h.acc2 >> 64);
+        o.acc2_sq.lo = (u64)h.acc2_sq;
+        o.acc2_sq.hi = (u64)(h.acc2_sq >> 64);
+        o.n_valid = h.n_valid;
+        o.n_bad_vertex = h.n_vertex;
+        o.n_bad_delta = h.n_delta;
+        o.n_bad_order = h.n_order;
+        o.n_nonzero = h.n_nonzero;
+        if (h.flags & 2) o.flags |= TM_F_SQ_SATURATED;
+    }
     return TM_OK;
 }

@@ -1,4 +1,6 @@
 // Scan of tile sums for the device-wide exclusive scan (tm_primitives.h).
+#include <algorithm>
+
 #include "tm_primitives.h"
 
 namespace {
@@ -30,6 +32,20 @@ __global__ void __launch_bounds__(kBlock) scan_single_kernel(u128* a, int64_t n,
 }
 
 }  // namespace
+
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        p[i] = v;
+}
+
+int fill_u32(void* p, int64_t n_words, uint32_t v, hipStream_t st) {
+    if (n_words <= 0) return TM_OK;
+    const int64_t blocks = std::min<int64_t>((n_words + kBlock - 1) / kBlock, 4096);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st,
+                       static_cast<uint32_t*>(p), n_words, v);
+    TM_HIP(hipGetLastError());
+    return TM_OK;
+}
 
 int scan_parts(u128* part, int64_t nb, int* ovf, hipStream_t st) {
     if (nb <= kScanTile) {

@@ -50,6 +50,8 @@ hipError_t dev_free(void* p, hipStream_t st);
 void dev_stream_synced(hipStream_t st);
 // hipStreamSynchronize, then dev_stream_synced.
 hipError_t sync_stream(hipStream_t st);
+// Set n_words 32-bit words to v with a kernel (capturable, unlike a memset).
+int fill_u32(void* p, int64_t n_words, uint32_t v, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Graph handle.
@@ -130,8 +132,22 @@ struct tm_weights {
 int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64_t* t,
                 hipStream_t st);
 int weights_build(tm_weights* w, hipStream_t st);
+// The 64-bit weight build enqueued on st with no host synchronisation; a
+// product or prefix that does not fit 64 bits sets *ovf (device).  The
+// caller reads W from cumW[q] afterwards, or rebuilds with weights_build.
+int weights_enqueue(tm_weights* w, hipStream_t st, int* ovf);
 int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStream_t st,
                tm_result* out, tm_sample_rec* recs, u64* model_bytes);
+
+// Batched sampling of several weight sets in one pass (tile: samples per work
+// item of the persistent kernels; blocks: their grid, 0 = 8 per CU).
+struct BatchConfig {
+    int tile;
+    int blocks;
+};
+extern BatchConfig g_batch_config;
+int batch_sample_run(tm_weights* const* ws, const u64* k, const u64* seeds, int n, hipStream_t st,
+                     tm_result* out, const BatchConfig& cfg);
 
 // ---------------------------------------------------------------------------
 // Stage timing with HIP events on the call's stream (tm_profile_enable).

@@ -12,6 +12,10 @@ constexpr int kSortTile = kBlock * kSortItems;     // 2048
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
+// Clearing device words with a kernel rather than a memset node, so that the
+// same code can be captured into a HIP graph.
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v);
+
 // ---------------------------------------------------------------------------
 // Wave and block scans of 128-bit values (two 64-bit shuffles per step).
 // ---------------------------------------------------------------------------
@@ -131,8 +135,8 @@ int scan_parts(u128* part, int64_t nb, int* ovf, hipStream_t st);
 template <typename T, typename F>
 int device_exclusive_scan(F f, int64_t n, T* out, int* ovf, hipStream_t st) {
     if (n == 0) {
-        TM_HIP(hipMemsetAsync(out, 0, sizeof(T), st));
-        return TM_OK;
+        static_assert(sizeof(T) % 4 == 0, "scan outputs are whole words");
+        return fill_u32(out, sizeof(T) / 4, 0u, st);
     }
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     u128* part = nullptr;
@@ -236,12 +240,12 @@ struct HistReader {
     __device__ uint32_t operator()(int64_t i) const { return h[i]; }
 };
 
-// Sorts (keys, vals) by bits [0, nbits) of the key, stably.  Buffers ping-pong
-// between (keys, vals) and (tkeys, tvals); on return *k_out / *v_out point to
-// whichever pair holds the result.
+// Sorts (keys, vals) by bits [lo_bit, nbits) of the key, stably.  Buffers
+// ping-pong between (keys, vals) and (tkeys, tvals); on return *k_out / *v_out
+// point to whichever pair holds the result.
 template <typename K>
-int radix_sort_pairs(K* keys, uint32_t* vals, K* tkeys, uint32_t* tvals, int64_t n, int nbits,
-                     K** k_out, uint32_t** v_out, int* ovf, hipStream_t st) {
+int radix_sort_pairs(K* keys, uint32_t* vals, K* tkeys, uint32_t* tvals, int64_t n, int lo_bit,
+                     int nbits, K** k_out, uint32_t** v_out, int* ovf, hipStream_t st) {
     K* ka = keys;
     uint32_t* va = vals;
     K* kb = tkeys;
@@ -250,7 +254,7 @@ int radix_sort_pairs(K* keys, uint32_t* vals, K* tkeys, uint32_t* tvals, int64_t
         const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
         uint32_t* hist = nullptr;
         TM_HIP(dev_alloc((void**)&hist, (ntiles * kRadix + 1) * sizeof(uint32_t), st));
-        for (int shift = 0; shift < nbits; shift += kRadixBits) {
+        for (int shift = lo_bit; shift < nbits; shift += kRadixBits) {
             const int bits = nbits - shift < kRadixBits ? nbits - shift : kRadixBits;
             hipLaunchKernelGGL((radix_hist_kernel<K>), dim3((unsigned)ntiles), dim3(kBlock), 0, st,
                                (const K*)ka, n, shift, bits, hist, ntiles);

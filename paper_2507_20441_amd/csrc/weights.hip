@@ -295,10 +295,6 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf) {
                           w->ihi},
         w->q, cum, ovf, st));
     w->cumW = cum;
-    W hW;
-    TM_HIP(hipMemcpyAsync(&hW, cum + w->q, sizeof(W), hipMemcpyDeviceToHost, st));
-    TM_HIP(sync_stream(st));
-    w->W = to_u128(hW);
     return TM_OK;
 }
 
@@ -332,12 +328,16 @@ int weights_build(tm_weights* w, hipStream_t st) {
     int rc = TM_OK;
     for (int wide = 0; wide < 2; ++wide) {
         clear_tables(w);
-        TM_HIP(hipMemsetAsync(ovf, 0, sizeof(int), st));
+        TM_TRY(fill_u32(ovf, 1, 0u, st));
         w->wide = wide != 0;
         rc = wide ? build_typed<u128>(w, st, ovf) : build_typed<u64>(w, st, ovf);
         if (rc != TM_OK) break;
+        u64 hW[2] = {0, 0};
         TM_HIP(hipMemcpyAsync(&h, ovf, sizeof(int), hipMemcpyDeviceToHost, st));
+        TM_HIP(hipMemcpyAsync(hW, static_cast<const unsigned char*>(w->cumW) + w->q * (wide ? 16 : 8),
+                              wide ? 16 : 8, hipMemcpyDeviceToHost, st));
         TM_HIP(sync_stream(st));
+        w->W = ((u128)hW[1] << 64) | hW[0];
         if (h == 0) break;
         if (wide) rc = tm_fail(TM_EOVERFLOW, "weights: a weight or W reaches 2^128");
     }
@@ -345,6 +345,19 @@ int weights_build(tm_weights* w, hipStream_t st) {
     timer.stop();
     TM_HIP(sync_stream(st));
     timer.finish();
+    if (rc != TM_OK) clear_tables(w);
+    return rc;
+}
+
+int weights_enqueue(tm_weights* w, hipStream_t st, int* ovf) {
+    tm_graph* g = w->g;
+    w->q = g->m > 0 ? g->T / w->plan.mo.delta + 1 : 0;
+    w->wide = false;
+    w->W = 0;
+    if (g->m == 0) return TM_OK;
+    if (w->q >= ((int64_t)1 << 31)) return tm_fail(TM_ERANGE, "weights: too many intervals");
+    clear_tables(w);
+    const int rc = build_typed<u64>(w, st, ovf);
     if (rc != TM_OK) clear_tables(w);
     return rc;
 }

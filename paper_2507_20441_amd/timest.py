@@ -87,6 +87,12 @@ def lib():
         L.tm_sample.argtypes = [vp, u64, u64, u64, u64, vp, C.POINTER(Result), vp]
         L.tm_estimate.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), u64, u64, vp,
                                   C.POINTER(Result)]
+        L.tm_sample_batch.argtypes = [C.POINTER(vp), C.POINTER(u64), C.POINTER(u64), C.c_int, vp,
+                                      C.POINTER(Result)]
+        L.tm_estimate_batch.argtypes = [C.POINTER(vp), C.POINTER(Motif), C.POINTER(C.POINTER(Tree)),
+                                        C.POINTER(u64), C.POINTER(u64), C.c_int, vp,
+                                        C.POINTER(Result)]
+        L.tm_batch_config.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         _lib = L
     return _lib
 
@@ -247,3 +253,37 @@ def estimate(g: Graph, mo: Motif, k, seed, tr: Tree = None) -> Result:
     _check(lib().tm_estimate(g.h, C.byref(mo), C.byref(tr) if tr is not None else None, int(k),
                              int(seed), _stream(), C.byref(res)), "estimate")
     return res
+
+
+def batch_config(tile, blocks=0):
+    """Set the batched kernels' schedule; returns the previous (tile, blocks)."""
+    pt, pb = C.c_int(), C.c_int()
+    _check(lib().tm_batch_config(int(tile), int(blocks), C.byref(pt), C.byref(pb)), "batch_config")
+    return pt.value, pb.value
+
+
+def sample_batch(weights, ks, seeds):
+    """tm_sample_batch over resident weight sets; one Result per job."""
+    n = len(weights)
+    hs = (C.c_void_p * n)(*[w.h for w in weights])
+    kk = (C.c_uint64 * n)(*[int(x) for x in ks])
+    ss = (C.c_uint64 * n)(*[int(x) for x in seeds])
+    out = (Result * n)()
+    _check(lib().tm_sample_batch(hs, kk, ss, n, _stream(), out), "sample_batch")
+    return list(out)
+
+
+def estimate_batch(graphs, motifs, ks, seeds, trees=None):
+    """tm_estimate_batch: whole estimates for (graph, motif, k, seed) jobs."""
+    n = len(graphs)
+    hs = (C.c_void_p * n)(*[g.h for g in graphs])
+    mo = (Motif * n)(*motifs)
+    kk = (C.c_uint64 * n)(*[int(x) for x in ks])
+    ss = (C.c_uint64 * n)(*[int(x) for x in seeds])
+    tr = None
+    if trees is not None:
+        keep = [C.pointer(t) if t is not None else None for t in trees]
+        tr = (C.POINTER(Tree) * n)(*keep)
+    out = (Result * n)()
+    _check(lib().tm_estimate_batch(hs, mo, tr, kk, ss, n, _stream(), out), "estimate_batch")
+    return list(out)

@@ -1,0 +1,97 @@
+"""Batched estimation: each job's result in a batch is bit-identical to the
+same job run alone (the draws are keyed by (seed, sample id); the batch only
+changes the schedule)."""
+import numpy as np
+import pytest
+
+from paper_2507_20441_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-batch]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2507_20441_amd import timest
+    timest.lib()
+    return timest
+
+
+def same(a, b):
+    return (a.acc2.value == b.acc2.value and a.acc2_sq.value == b.acc2_sq.value
+            and a.n_valid == b.n_valid and a.n_bad_vertex == b.n_bad_vertex
+            and a.n_bad_delta == b.n_bad_delta and a.n_bad_order == b.n_bad_order
+            and a.n_nonzero == b.n_nonzero and a.W.value == b.W.value
+            and a.estimate == b.estimate and a.flags == b.flags)
+
+
+@pytest.fixture(scope="module")
+def mix(T):
+    """Jobs over four graphs: every motif, a general-run motif, a 128-bit job,
+    a zero-weight job and a zero-sample job, uneven budgets."""
+    graphs = [W.small_graph(m, s, n=max(50, m // 20), span=20 * m)
+              for m, s in ((3000, 1), (20011, 2), (120000, 3), (700, 4))]
+    tg = [T.Graph(g.src, g.dst, g.t, g.n) for g in graphs]
+    rng = np.random.default_rng(5)
+    hub = 1500
+    star = W.TemporalGraph(np.zeros(hub, np.int32), np.arange(1, hub + 1, dtype=np.int32),
+                           rng.integers(0, 50, hub).astype(np.int64), hub + 1)
+    tg.append(T.Graph(star.src, star.dst, star.t, star.n))
+    zero = T.Graph(np.zeros(5, np.int32), np.arange(1, 6, dtype=np.int32), np.arange(5, dtype=np.int64), 6)
+    tg.append(zero)
+    jobs = []
+    names = list(W.MOTIFS)
+    for i in range(14):
+        gi = i % 4
+        name = names[i % len(names)]
+        delta = [400, 3000, 20000, 150][gi]
+        jobs.append((tg[gi], T.make_motif(W.MOTIFS[name], delta), int(rng.integers(1, 3)) * 10 ** int(rng.integers(3, 6)),
+                     int(rng.integers(1, 2 ** 62))))
+    jobs.append((tg[1], T.make_motif(((0, 1), (1, 2), (2, 3), (3, 0), (0, 2)), 5000), 30000, 77))
+    jobs.append((tg[4], T.make_motif(tuple((0, j) for j in range(1, 8)), 100), 20000, 5))
+    jobs.append((tg[5], T.make_motif(W.MOTIFS["3cycle"], 10), 1000, 3))
+    jobs.append((tg[0], T.make_motif(W.MOTIFS["4cycle"], 400), 0, 9))
+    return tg, jobs
+
+
+@pytest.mark.parametrize("tile,blocks", [(8192, 0), (256, 7), (1024, 64)])
+def test_sample_batch_matches_single_runs(T, mix, tile, blocks):
+    tg, jobs = mix
+    prev = T.batch_config(tile, blocks)
+    try:
+        ws = [T.Weights(g, mo) for g, mo, _, _ in jobs]
+        say("batch", tile, blocks, len(ws))
+        got = T.sample_batch(ws, [k for *_, k, _ in jobs], [s for *_, s in jobs])
+        for i, ((g, mo, k, seed), w) in enumerate(zip(jobs, ws)):
+            alone, _ = w.sample(seed, k)
+            assert got[i].status == 0 and same(got[i], alone), i
+        assert ws[15].info()["wide"] and got[16].flags & T.TM_F_W_ZERO
+    finally:
+        T.batch_config(*prev)
+
+
+def test_estimate_batch_matches_estimate(T, mix):
+    tg, jobs = mix
+    say("estimate_batch")
+    got = T.estimate_batch([g for g, *_ in jobs], [mo for _, mo, _, _ in jobs],
+                           [k for *_, k, _ in jobs], [s for *_, s in jobs])
+    for i, (g, mo, k, seed) in enumerate(jobs):
+        alone = T.estimate(g, mo, k, seed)
+        assert got[i].status == 0 and same(got[i], alone), i
+
+
+def test_batch_repeats_identically(T, mix):
+    tg, jobs = mix
+    ws = [T.Weights(g, mo) for g, mo, _, _ in jobs[:6]]
+    ks = [k for *_, k, _ in jobs[:6]]
+    ss = [s for *_, s in jobs[:6]]
+    first = T.sample_batch(ws, ks, ss)
+    for rep in range(3):
+        ws[0].sample(123, 5000)  # eager work in between
+        again = T.sample_batch(ws, ks, ss)
+        assert all(same(a, b) for a, b in zip(first, again)), rep
