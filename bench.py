@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="before timing, run a plain device copy of BYTES (3 times) so that "
                          "hardware counters can be scaled by a kernel of known traffic")
+    ap.add_argument("--workload", choices=["medium", "batched"], default="medium",
+                    help="medium: the single-job path (default); batched: 64 heterogeneous "
+                         "jobs, one launch per job against the batched pass")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "sample_kernel_medium_traffic.json"),
                     help="HBM bytes per launch from rocprofv3 counters (JSON), if present")
     return ap.parse_args()
@@ -53,6 +56,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
               "this build has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batched":
+        return batched(args)
 
     import ctypes as C
 
@@ -186,6 +192,94 @@ def main():
         "estimates": per_motif,
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def batched(args):
+    """64 estimation jobs of uneven graph size, motif, delta and budget, from
+    resident graphs: one launch per job (tm_estimate each, the job's whole
+    weights -> samples -> reduction) against one batched pass
+    (tm_estimate_batch) with the autotuned schedule.  Same results required."""
+    import torch
+
+    from paper_2507_20441_amd import autotune
+    from paper_2507_20441_amd import timest as T
+    from paper_2507_20441_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    torch.cuda.set_device(0)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    jobs = W.batched_jobs()
+    log(f"generating {len(jobs)} graphs")
+    graphs = []
+    for j in jobs:
+        g = W.batched_graph(j)
+        graphs.append(T.Graph(g.src, g.dst, g.t, g.n))
+    motifs = [T.make_motif(W.MOTIFS[j["motif"]], j["delta"]) for j in jobs]
+    ks = [j["k"] for j in jobs]
+    seeds = [j["seed"] for j in jobs]
+    total = sum(ks)
+
+    def per_job():
+        return [T.estimate(g, mo, k, s) for g, mo, k, s in zip(graphs, motifs, ks, seeds)]
+
+    def batch():
+        return T.estimate_batch(graphs, motifs, ks, seeds)
+
+    log("tuning the batched schedule")
+    ws = [T.Weights(g, mo) for g, mo in zip(graphs, motifs)]
+    choice, times = autotune.tune(ws, ks, seeds, cus)
+    for w in ws:
+        w.close()
+    log(f"schedule {choice}; timings ms {times}")
+    for _ in range(max(1, args.warmup)):
+        ref = per_job()
+        got = batch()
+    same = all(a.acc2.value == b.acc2.value and a.n_valid == b.n_valid and a.estimate == b.estimate
+               for a, b in zip(ref, got))
+    assert same, "batched results differ from one-job-per-launch results"
+    t_job, t_batch = [], []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        per_job()
+        torch.cuda.synchronize()
+        t_job.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        batch()
+        torch.cuda.synchronize()
+        t_batch.append(time.perf_counter() - t0)
+    tj, tb = min(t_job), min(t_batch)
+    wide = sum(1 for r in got if r.flags & T.TM_F_WIDE)
+    rel = [1.96 * r.std_error / r.estimate for r in got if r.estimate > 0]
+    line = {
+        "metric": "samples/s at <=5% rel. err; batched-queue vs one-job-per-launch; p99 latency",
+        "value": round(total / tb, 1),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(tb * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": "batched: 64 jobs, graphs log-uniform 1e4..5e6 edges (medium shape), "
+                        "motifs uniform over 5, delta log-uniform 600..86400, k log-uniform 1e5..1e7; "
+                        "resident graphs; weights + samples + reduction per job",
+            "jobs": len(jobs), "edges_total": sum(j["m"] for j in jobs), "samples_total": total,
+        },
+        "one_job_per_launch": {"ms": round(tj * 1e3, 3), "samples_per_s": round(total / tj, 1)},
+        "batched": {"ms": round(tb * 1e3, 3), "samples_per_s": round(total / tb, 1),
+                    "schedule": {"tile": choice[0], "blocks": choice[1]}},
+        "speedup": round(tj / tb, 3),
+        "bit_identical": same,
+        "jobs_128bit": wide,
+        "rel_ci95_max": max(rel) if rel else None,
+        "autotune_ms": {f"{t},{b}": round(v, 3) for (t, b), v in times.items()},
     }
     print(json.dumps(line), flush=True)
 
