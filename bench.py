@@ -41,9 +41,18 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="before timing, run a plain device copy of BYTES (3 times) so that "
                          "hardware counters can be scaled by a kernel of known traffic")
-    ap.add_argument("--workload", choices=["medium", "batched"], default="medium",
+    ap.add_argument("--workload", choices=["medium", "batched", "serving"], default="medium",
                     help="medium: the single-job path (default); batched: 64 heterogeneous "
-                         "jobs, one launch per job against the batched pass")
+                         "jobs, one launch per job against the batched pass; serving: a Poisson "
+                         "query stream against the server")
+    ap.add_argument("--serve-scale", type=float, default=1.0,
+                    help="serving: size of the large resident graph relative to 5e8 edges")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="queries per second")
+    ap.add_argument("--serve-budget-gb", type=float, default=0.0,
+                    help="server budget; 0: free device memory after the graphs, less 16 GB")
+    ap.add_argument("--serve-check", type=int, default=12,
+                    help="served queries re-run alone with tm_estimate and compared")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "sample_kernel_medium_traffic.json"),
                     help="HBM bytes per launch from rocprofv3 counters (JSON), if present")
     return ap.parse_args()
@@ -59,6 +68,8 @@ def main():
 
     if args.workload == "batched":
         return batched(args)
+    if args.workload == "serving":
+        return serving(args)
 
     import ctypes as C
 
@@ -282,6 +293,142 @@ def batched(args):
         "autotune_ms": {f"{t},{b}": round(v, 3) for (t, b), v in times.items()},
     }
     print(json.dumps(line), flush=True)
+
+
+def serving(args):
+    """Open-loop serving: Poisson arrivals submitted at their times to one
+    server holding every graph resident; latency is measured by the server
+    from submit to result.  A closed-loop pass over the first queries then
+    compares the server's saturated throughput with one tm_estimate per
+    query, and sampled served results are re-run alone for identity."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2507_20441_amd import timest as T
+    from paper_2507_20441_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    torch.cuda.set_device(0)
+    specs = W.serving_graph_specs(args.serve_scale)
+    graphs = []
+    t0 = time.perf_counter()
+    for sp in specs:
+        u, v, t = W.device_graph(sp["n"], sp["m"], 2.1, sp["seed"])
+        torch.cuda.synchronize()
+        graphs.append(T.Graph(u, v, t, sp["n"]))
+        del u, v, t
+        torch.cuda.empty_cache()
+        log(f"graph n={sp['n']} m={sp['m']} built, {time.perf_counter() - t0:.1f} s")
+    free = torch.cuda.mem_get_info()[0]
+    budget = int(args.serve_budget_gb * 2**30) if args.serve_budget_gb > 0 else int(free - 16 * 2**30)
+    queries = W.serving_queries(args.serve_seconds, args.serve_rate, len(graphs))
+    motifs = {(q["motif"], q["delta"]): T.make_motif(W.MOTIFS[q["motif"]], q["delta"]) for q in queries}
+    log(f"{len(queries)} queries over {args.serve_seconds} s; budget {budget / 2**30:.1f} GiB")
+
+    def run(qs, open_loop):
+        srv = T.Server(budget)
+        gids = [srv.add_graph(g) for g in graphs]
+        tickets = [None] * len(qs)
+        ready = threading.Semaphore(0)
+        res = [None] * len(qs)
+
+        def collect():
+            for i in range(len(qs)):
+                ready.acquire()
+                try:
+                    res[i] = srv.wait(tickets[i])
+                except T.TimestError as e:
+                    res[i] = (None, str(e))
+                if (i + 1) % 250 == 0:
+                    log(f"{i + 1} results")
+
+        th = threading.Thread(target=collect)
+        th.start()
+        start = time.perf_counter()
+        for i, q in enumerate(qs):
+            if open_loop:
+                delay = start + q["at"] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            tickets[i] = srv.submit(gids[q["graph"]], motifs[(q["motif"], q["delta"])], q["k"], q["seed"])
+            ready.release()
+        th.join()
+        wall = time.perf_counter() - start
+        st = srv.stats()
+        srv.close()
+        return res, st, wall
+
+    log("open loop")
+    res, st, wall = run(queries, True)
+    errors = sorted({info for r, info in res if r is None})
+    ok = [(r, info) for r, info in res if r is not None]
+    if errors:
+        log(f"{len(res) - len(ok)} queries failed: {errors[:3]}")
+    lat = np.array([info.latency_ms for _, info in ok])
+    qd = np.array([info.queued_ms for _, info in ok])
+    total = sum(q["k"] for q, (r, _) in zip(queries, res) if r is not None)
+    # closed loop: the same first queries all at once, then one tm_estimate each
+    n_cl = min(len(queries), 400)
+    cl = queries[:n_cl]
+    cl_res, cl_st, cl_wall = run(cl, False)
+    cl_total = sum(q["k"] for q in cl)
+    log("one tm_estimate per query")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    alone = [T.estimate(graphs[q["graph"]], motifs[(q["motif"], q["delta"])], q["k"], q["seed"]) for q in cl]
+    torch.cuda.synchronize()
+    seq_wall = time.perf_counter() - t1
+    same_cl = all(r is not None and a.acc2.value == r.acc2.value and a.n_valid == r.n_valid
+                  and a.estimate == r.estimate for a, (r, _) in zip(alone, cl_res))
+    rng = np.random.default_rng(7)
+    served = [i for i, (r, _) in enumerate(res) if r is not None]
+    pick = rng.choice(served, size=min(args.serve_check, len(served)), replace=False)
+    same_open = True
+    for i in pick:
+        q = queries[i]
+        a = T.estimate(graphs[q["graph"]], motifs[(q["motif"], q["delta"])], q["k"], q["seed"])
+        r = res[i][0]
+        same_open &= a.acc2.value == r.acc2.value and a.n_valid == r.n_valid and a.estimate == r.estimate
+    assert same_cl and same_open, "served results differ from tm_estimate alone"
+    rel = [1.96 * r.std_error / r.estimate for r, _ in ok if r.estimate > 0]
+    line = {
+        "metric": "samples/s at <=5% rel. err; batched-queue vs one-job-per-launch; p99 latency",
+        "value": round(total / wall, 1),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": round(wall * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"serving: resident graphs {[(sp['n'], sp['m']) for sp in specs]}; Poisson "
+                        f"{args.serve_rate}/s for {args.serve_seconds} s; motif uniform over 5, delta "
+                        "uniform over {3600, 86400} on the large graph and over 8 values 600..86400 "
+                        "on the others, k log-uniform 1e5..1e7",
+            "queries": len(queries), "samples_total": total, "budget_bytes": budget,
+        },
+        "failed_queries": len(res) - len(ok),
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "mean": float(lat.mean()), "max": float(lat.max())},
+        "queued_ms": {"p50": float(np.percentile(qd, 50)), "p99": float(np.percentile(qd, 99))},
+        "offered_samples_per_s": round(total / args.serve_seconds, 1),
+        "server": st,
+        "closed_loop": {"queries": n_cl, "served_samples_per_s": round(cl_total / cl_wall, 1),
+                        "one_job_per_launch_samples_per_s": round(cl_total / seq_wall, 1),
+                        "speedup": round(seq_wall / cl_wall, 3), "server": cl_st},
+        "identical_alone_vs_mix": bool(same_cl and same_open),
+        "rel_ci95_max": max(rel) if rel else None,
+        "rel_ci95_median": float(np.median(rel)) if rel else None,
+    }
+    print(json.dumps(line), flush=True)
+    for g in graphs:
+        g.close()
 
 
 def kernel_source_sha():

@@ -43,7 +43,10 @@ enum tm_error {
     TM_EOVERFLOW = -4,   /* a weight, W or a completion count reaches 2^128 */
     TM_ERANGE = -5,      /* time span or delta too large for the limits above */
     TM_ENOMEM = -6,      /* device allocation failed */
-    TM_EDEVICE = -7      /* HIP runtime error */
+    TM_EDEVICE = -7,     /* HIP runtime error */
+    TM_EADMIT = -8,      /* serving: the query's weight set alone exceeds the budget */
+    TM_EAGAIN = -9,      /* serving: the query has not finished yet */
+    TM_ECANCELED = -10   /* serving: the server shut down before the query finished */
 };
 
 enum tm_ptr_kind { TM_PTR_HOST = 0, TM_PTR_DEVICE = 1 };
@@ -234,6 +237,80 @@ int tm_estimate_batch(tm_graph* const* g, const tm_motif* mo, const tm_tree* con
  * the autotuner in the Python package searches these.  Returns the previous
  * values through prev_tile / prev_blocks when not NULL. */
 int tm_batch_config(int tile, int blocks, int* prev_tile, int* prev_blocks);
+
+/* Device bytes the weight tables of (g, mo, tr) take in 64-bit (wide = 0)
+ * or 128-bit (wide = 1) form: what tm_weights_info reports as device_bytes
+ * after tm_weights_create builds them in that form.  tr may be NULL (the
+ * default tree).  Errors: TM_EINVAL. */
+int tm_weights_footprint(const tm_graph* g, const tm_motif* mo, const tm_tree* tr, int32_t wide,
+                         uint64_t* bytes);
+
+/* ---- serving --------------------------------------------------------------
+ * A server answers estimation queries on resident graphs from a worker
+ * thread with a stream of its own (default priority).
+ *
+ * Weight sets are cached per (graph, motif, delta, tree) and shared by the
+ * queries that need them.  The budget bounds the server's device memory: the
+ * resident weight sets plus a reserve for one sampling pass (24 bytes per
+ * sample of pass_samples).  Admission: a query whose weight set is resident
+ * is admitted at once; otherwise, in arrival order, when the set's 64-bit
+ * footprint fits the budget after evicting idle sets, least recently used
+ * first.  A set that turns out to need 128 bits is kept if it fits alone.
+ *
+ * Continuous batching: each pass draws up to job_chunk samples of every
+ * admitted query (fewest remaining samples first, at most max_jobs queries
+ * and pass_samples samples in all) with one batched sampling pass, so a query
+ * arriving during a long one joins at the next pass.  A query's result is
+ * its exact integer sums over its passes, hence equal to tm_estimate's for
+ * the same (graph, motif, tree, k, seed), whatever else is in the mix. */
+typedef struct tm_server tm_server;
+
+typedef struct {
+    uint64_t pass_samples;  /* samples per pass over all queries (0: 2^24) */
+    uint64_t job_chunk;     /* samples one query adds to a pass (0: 2^22) */
+    int32_t max_jobs;       /* queries per pass (0: 256) */
+    int32_t fifo;           /* 1: oldest query first in a pass instead of fewest remaining */
+} tm_server_opts;
+
+typedef struct {
+    double queued_ms;      /* submit -> admitted (its weight set resident) */
+    double latency_ms;     /* submit -> result ready */
+    uint32_t weights_hit;  /* 1: the weight set was resident on admission */
+    uint32_t passes;       /* sampling passes the query took part in */
+} tm_query_info;
+
+typedef struct {
+    uint64_t submitted, completed, failed;
+    uint64_t passes, samples;
+    uint64_t weight_builds, weight_hits, evictions;
+    uint64_t admission_waits;  /* queries that waited for memory to be admitted */
+    uint64_t budget_bytes, resident_bytes, peak_bytes;
+    uint64_t cached_sets;
+    double build_ms;  /* worker time in weight builds */
+    double pass_ms;   /* worker time in sampling passes */
+} tm_server_stats;
+
+/* Start a server on the current device.  opts may be NULL (defaults).
+ * Errors: TM_EINVAL (budget below the pass reserve), TM_EDEVICE. */
+int tm_server_create(uint64_t budget_bytes, const tm_server_opts* opts, tm_server** out);
+/* Register a built graph; it stays owned by the caller and must outlive the
+ * server.  Its memory is not counted in the budget. */
+int tm_server_add_graph(tm_server* srv, tm_graph* g, int32_t* gid);
+/* Queue a query: k samples with the given seed of the motif on graph gid
+ * (tr NULL: default tree).  Errors, at once: TM_EINVAL (bad graph id,
+ * motif or tree), TM_EADMIT (its 64-bit weight set exceeds the budget). */
+int tm_server_submit(tm_server* srv, int32_t gid, const tm_motif* mo, const tm_tree* tr, uint64_t k,
+                     uint64_t seed, uint64_t* ticket);
+/* Result of a finished query: returns its status (TM_OK or its error) and
+ * forgets the ticket; TM_EAGAIN while it runs; TM_EINVAL for an unknown
+ * ticket.  info may be NULL. */
+int tm_server_poll(tm_server* srv, uint64_t ticket, tm_result* out, tm_query_info* info);
+/* As tm_server_poll, blocking until the query finishes. */
+int tm_server_wait(tm_server* srv, uint64_t ticket, tm_result* out, tm_query_info* info);
+int tm_server_read_stats(tm_server* srv, tm_server_stats* out);
+/* Stop the worker (queries not finished end with TM_ECANCELED) and free the
+ * weight cache.  Waiting threads must have returned first. */
+void tm_server_destroy(tm_server* srv);
 
 /* ---- measurement --------------------------------------------------------
  * Device time of the library's stages, measured with HIP events recorded on

@@ -16,7 +16,7 @@ OBJDIR = os.path.join(ROOT, "_build", "timest")
 LIB = os.path.join(HERE, "libtimest.so")
 ARCH = os.environ.get("TIMEST_ARCH", "gfx950")
 
-SOURCES = ["csr.hip", "weights.hip", "sample.hip", "scan.hip", "api.cpp", "mem.cpp"]
+SOURCES = ["csr.hip", "weights.hip", "sample.hip", "scan.hip", "api.cpp", "mem.cpp", "serve.cpp"]
 HEADERS = ["tm_common.h", "tm_internal.h", "tm_primitives.h"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

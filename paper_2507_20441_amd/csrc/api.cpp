@@ -281,6 +281,9 @@ extern "C" const char* tm_strerror(int code) {
         case TM_ERANGE: return "value outside the supported range";
         case TM_ENOMEM: return "out of device memory";
         case TM_EDEVICE: return "HIP runtime error";
+        case TM_EADMIT: return "query exceeds the server's memory budget";
+        case TM_EAGAIN: return "query not finished";
+        case TM_ECANCELED: return "server stopped before the query finished";
         default: return "unknown error";
     }
 }
@@ -401,6 +404,22 @@ extern "C" int tm_weights_create(tm_graph* g, const tm_motif* mo, const tm_tree*
     return TM_OK;
 }
 
+extern "C" int tm_weights_footprint(const tm_graph* g, const tm_motif* mo, const tm_tree* tr,
+                                    int32_t wide, uint64_t* bytes) {
+    if (!g || !bytes) return tm_fail(TM_EINVAL, "weights_footprint: NULL argument");
+    TM_TRY(motif_check(mo));
+    tm_tree def;
+    if (!tr) {
+        TM_TRY(tm_default_tree(mo, &def));
+        tr = &def;
+    }
+    HostPlan P;
+    TM_TRY(plan_build(mo, tr, &P));
+    const int64_t q = g->m > 0 ? g->T / mo->delta + 1 : 0;
+    *bytes = weights_footprint(P, g->m, q, wide != 0);
+    return TM_OK;
+}
+
 extern "C" void tm_weights_destroy(tm_weights* w) {
     if (!w) return;
     w->arena.release();
@@ -435,13 +454,31 @@ extern "C" int tm_weights_export(const tm_weights* w, int32_t s, int32_t slot, t
     TM_HIP(hipMemcpyAsync(t.data(), w->g->d.t, m * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     const bool leaf = P.n_children[sl] == 0;
     const size_t wsz = w->wide ? 16 : 8;
-    std::vector<unsigned char> v[2];
-    if (!leaf)
+    // values are differences of neighbouring prefix entries: along eid order
+    // for the center, along the T order of the slot's list otherwise
+    std::vector<unsigned char> pre[2];
+    std::vector<int32_t> pos;
+    const int dir = P.alpha[sl] > 0 ? 0 : 1;
+    if (!leaf) {
         for (int par = 0; par < 2; ++par) {
-            v[par].resize(m * wsz);
-            TM_HIP(hipMemcpyAsync(v[par].data(), w->vals[sl][par], m * wsz, hipMemcpyDeviceToHost, st));
+            pre[par].resize((m + 1) * wsz);
+            const void* src = sl == 0 ? w->qc[par] : w->qt[sl][par];
+            TM_HIP(hipMemcpyAsync(pre[par].data(), src, (m + 1) * wsz, hipMemcpyDeviceToHost, st));
         }
+        if (sl != 0) {
+            pos.resize(m);
+            TM_HIP(hipMemcpyAsync(pos.data(), w->g->d.tpos[dir], m * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        }
+    }
     TM_HIP(sync_stream(st));
+    auto at = [&](int par, int64_t p) {
+        const unsigned char* b = pre[par].data() + p * wsz;
+        u64 lo = 0, hi = 0;
+        std::memcpy(&lo, b, 8);
+        if (w->wide) std::memcpy(&hi, b + 8, 8);
+        const u128 v = ((u128)hi << 64) | lo;
+        return w->wide ? v : (u128)(u64)v;
+    };
     for (int64_t e = 0; e < m; ++e) {
         const int64_t i = t[e] / P.mo.delta - slot;
         tm_u128 x = {0, 0};
@@ -449,9 +486,12 @@ extern "C" int tm_weights_export(const tm_weights* w, int32_t s, int32_t slot, t
             if (leaf) {
                 x.lo = 1;
             } else {
-                const unsigned char* b = v[i & 1].data() + e * wsz;
-                std::memcpy(&x.lo, b, 8);
-                if (w->wide) std::memcpy(&x.hi, b + 8, 8);
+                const int par = (int)(i & 1);
+                const int64_t p = sl == 0 ? e : pos[e];
+                u128 d = at(par, p + 1) - at(par, p);
+                if (!w->wide) d = (u64)d;
+                x.lo = (u64)d;
+                x.hi = (u64)(d >> 64);
             }
         }
         host_out[e] = x;
@@ -485,7 +525,7 @@ extern "C" int tm_weights_intervals(const tm_weights* w, tm_u128* host_out, void
 
 static double u128_to_double(tm_u128 x) { return (double)(((u128)x.hi << 64) | x.lo); }
 
-static void finish_result(tm_result* r) {
+void finish_result(tm_result* r) {
     const double W = u128_to_double(r->W);
     const double acc2 = u128_to_double(r->acc2);
     const double k = (double)r->k;
@@ -542,9 +582,30 @@ extern "C" int tm_batch_config(int tile, int blocks, int* prev_tile, int* prev_b
     return TM_OK;
 }
 
-static BatchConfig batch_config_now() {
+BatchConfig batch_config_now() {
     std::lock_guard<std::mutex> lk(g_cfg_mu);
     return g_batch_config;
+}
+
+// Results of k[i] samples (ids 0 .. k[i] - 1) of every job, in one batched pass.
+int sample_batch_results(tm_weights* const* w, const uint64_t* k, const uint64_t* seed, int n_jobs,
+                         hipStream_t st, tm_result* out) {
+    std::vector<u64> j0(n_jobs, 0), kk(k, k + n_jobs), ss(seed, seed + n_jobs);
+    std::vector<JobSums> sums(n_jobs);
+    TM_TRY(batch_sample_pass(w, j0.data(), kk.data(), ss.data(), n_jobs, st, sums.data(), batch_config_now()));
+    for (int i = 0; i < n_jobs; ++i) {
+        tm_result& o = out[i];
+        std::memset(&o, 0, sizeof o);
+        o.k = kk[i];
+        o.q = w[i]->q;
+        o.W.lo = (u64)w[i]->W;
+        o.W.hi = (u64)(w[i]->W >> 64);
+        if (w[i]->wide) o.flags |= TM_F_WIDE;
+        if (w[i]->W == 0) o.flags |= TM_F_W_ZERO;
+        sums_to_result(sums[i], &o);
+        if (o.status == TM_OK) finish_result(&o);
+    }
+    return TM_OK;
 }
 
 extern "C" int tm_sample_batch(tm_weights* const* w, const uint64_t* k, const uint64_t* seed, int n_jobs,
@@ -554,10 +615,7 @@ extern "C" int tm_sample_batch(tm_weights* const* w, const uint64_t* k, const ui
     for (int i = 0; i < n_jobs; ++i)
         if (!w[i]) return tm_fail(TM_EINVAL, "sample_batch: job %d has no weights", i);
     if (n_jobs == 0) return TM_OK;
-    std::vector<u64> kk(k, k + n_jobs), ss(seed, seed + n_jobs);
-    TM_TRY(batch_sample_run(w, kk.data(), ss.data(), n_jobs, as_stream(stream), out, batch_config_now()));
-    for (int i = 0; i < n_jobs; ++i)
-        if (out[i].status == TM_OK) finish_result(&out[i]);
+    TM_TRY(sample_batch_results(w, k, seed, n_jobs, as_stream(stream), out));
     return TM_OK;
 }
 
@@ -647,12 +705,9 @@ extern "C" int tm_estimate_batch(tm_graph* const* g, const tm_motif* mo, const t
     int rc = TM_OK;
     if (!act.empty()) {
         std::vector<tm_result> r(act.size());
-        rc = batch_sample_run(act.data(), kk.data(), ss.data(), (int)act.size(), st, r.data(),
-                              batch_config_now());
-        for (size_t a = 0; a < act.size() && rc == TM_OK; ++a) {
-            out[idx[a]] = r[a];
-            if (r[a].status == TM_OK) finish_result(&out[idx[a]]);
-        }
+        rc = sample_batch_results(act.data(), reinterpret_cast<const uint64_t*>(kk.data()),
+                                  reinterpret_cast<const uint64_t*>(ss.data()), (int)act.size(), st, r.data());
+        for (size_t a = 0; a < act.size() && rc == TM_OK; ++a) out[idx[a]] = r[a];
     }
     for (tm_weights* w : ws) tm_weights_destroy(w);
     return rc;

@@ -5,7 +5,8 @@
 // here instead.  A block released on stream S may serve a later allocation on
 // S at once (stream order makes that safe) and any other stream once S has
 // been synchronised by the library (every entry point synchronises its stream
-// before it returns).  Memory goes back to HIP only when an allocation fails.
+// before it returns).  Memory goes back to HIP only when an allocation fails
+// (after a device synchronisation, so no queued work still uses it).
 #include <mutex>
 #include <unordered_map>
 #include <vector>
@@ -54,7 +55,10 @@ hipError_t dev_alloc(void** p, size_t bytes, hipStream_t st) {
         int best = -1;
         for (int i = 0; i < (int)fl.size(); ++i) {
             const Block& b = fl[i];
-            if (b.cap < cls || b.cap > 2 * cls) continue;
+            // small blocks may serve requests down to half their size;
+            // large ones only slightly smaller requests
+            const size_t slack = cls > ((size_t)64 << 20) ? cls >> 3 : cls;
+            if (b.cap < cls || b.cap > cls + slack) continue;
             if (!b.synced && b.st != st) continue;
             if (best < 0 || b.cap < fl[best].cap) best = i;
         }
@@ -68,18 +72,8 @@ hipError_t dev_alloc(void** p, size_t bytes, hipStream_t st) {
     hipError_t e = hipMalloc(p, cls);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        // give cached, synchronised blocks back and try once more
-        std::vector<void*> drop;
-        {
-            std::lock_guard<std::mutex> lk(g_mu);
-            std::vector<Block>& fl = g_free[dev];
-            for (int i = (int)fl.size() - 1; i >= 0; --i)
-                if (fl[i].synced) {
-                    drop.push_back(fl[i].p);
-                    fl.erase(fl.begin() + i);
-                }
-        }
-        for (void* q : drop) (void)hipFree(q);
+        // give every cached block back and try once more
+        dev_cache_trim();
         e = hipMalloc(p, cls);
         if (e != hipSuccess) {
             *p = nullptr;
@@ -89,6 +83,19 @@ hipError_t dev_alloc(void** p, size_t bytes, hipStream_t st) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_used[*p] = cls;
     return hipSuccess;
+}
+
+void dev_cache_trim() {
+    const int dev = device_index();
+    std::vector<Block> drop;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        drop.swap(g_free[dev]);
+    }
+    if (drop.empty()) return;
+    // blocks released on a stream may still be in use by its queued work
+    (void)hipDeviceSynchronize();
+    for (const Block& b : drop) (void)hipFree(b.p);
 }
 
 hipError_t dev_free(void* p, hipStream_t st) {

@@ -56,7 +56,7 @@ struct SampleArgs {
     int* ovf;
     const uint32_t* skey;  // root-sorted order: T-order position of the root * 2 + interval parity
     const uint32_t* sval;  // ... and the sample's offset in [0, count)
-    uint32_t key_mask;     // bits of skey holding the root key (the rest name the job)
+    uint32_t key_base;     // batched: skey of this job = key_base + its root key
 };
 
 // Per-lane running sums of a sampling pass.
@@ -435,7 +435,7 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
         int32_t i;
         if constexpr (kSorted) {
             // the root was drawn by root_kernel; lanes follow the sorted order
-            const uint32_t key = a.skey[x] & a.key_mask;
+            const uint32_t key = a.skey[x] - a.key_base;
             r = a.sval[x];
             const int32_t pos = (int32_t)(key >> 1);
             const int32_t e0 = G.leid[0][pos];
@@ -822,7 +822,7 @@ struct Tile {
 template <typename W>
 __global__ void __launch_bounds__(kBlock)
 batch_root_kernel(const SampleArgs* jobs, const Tile* tiles, int n_tiles, int* counter, uint32_t* keys,
-                  uint32_t* vals, int kb, int* ovf) {
+                  uint32_t* vals, int* ovf) {
     extern __shared__ unsigned char lds_raw[];
     __shared__ int s_tile;
     bool bad = false;
@@ -844,7 +844,7 @@ batch_root_kernel(const SampleArgs* jobs, const Tile* tiles, int n_tiles, int* c
         const W* cum = a.cum_in_lds ? cumL : cumG;
         const W Wtot = (W)(((u128)a.W_hi << 64) | a.W_lo);
         for (u64 r = T.begin + threadIdx.x; r < T.end; r += kBlock) {
-            keys[T.out + r] = ((uint32_t)T.job << kb) | root_key<W>(a, cum, Wtot, ncum, r, bad);
+            keys[T.out + r] = a.key_base + root_key<W>(a, cum, Wtot, ncum, r, bad);
             vals[T.out + r] = (uint32_t)r;
         }
     }
@@ -914,7 +914,7 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
     size_t lds = 0;
     fill_args(w, &a, &lds);
     a.seed = seed;
-    a.key_mask = ~0u;
+    a.key_base = 0;
     const bool sorted = count >= kSortMin;
     const u64 chunk = std::min<u64>(count, kChunk);
     const int blocks = (int)std::min<u64>((chunk + kBlock - 1) / kBlock, 8192);
@@ -1017,40 +1017,50 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
 // ---------------------------------------------------------------------------
 BatchConfig g_batch_config = {8192, 0};
 
-int batch_sample_run(tm_weights* const* ws, const u64* ks, const u64* seeds, int n, hipStream_t st,
-                     tm_result* out, const BatchConfig& cfg) {
-    // results of jobs without samples, and the list of active jobs
-    std::vector<int> act;
-    for (int x = 0; x < n; ++x) {
-        tm_weights* w = ws[x];
-        tm_result& o = out[x];
-        std::memset(&o, 0, sizeof o);
-        o.k = ks[x];
-        o.q = w->q;
-        o.W.lo = (u64)w->W;
-        o.W.hi = (u64)(w->W >> 64);
-        if (w->wide) o.flags |= TM_F_WIDE;
-        if (w->W == 0) o.flags |= TM_F_W_ZERO;
-        if (w->W != 0 && ks[x] > 0) act.push_back(x);
-        if (w->plan.nt < 1 || w->plan.nt > 7) return tm_fail(TM_EINVAL, "batch: job %d tree size", x);
+void sums_merge(JobSums& into, const JobSums& x) {
+    if (!add_ok(into.acc2, x.acc2, &into.acc2)) into.flags |= 1;
+    if (!add_ok(into.acc2_sq, x.acc2_sq, &into.acc2_sq)) {
+        into.acc2_sq = ~(u128)0;
+        into.flags |= 2;
     }
+    into.n_valid += x.n_valid;
+    into.n_vertex += x.n_vertex;
+    into.n_delta += x.n_delta;
+    into.n_order += x.n_order;
+    into.n_nonzero += x.n_nonzero;
+    into.flags |= x.flags;
+    if (into.status == TM_OK) into.status = x.status;
+}
+
+void sums_to_result(const JobSums& h, tm_result* o) {
+    o->acc2.lo = (u64)h.acc2;
+    o->acc2.hi = (u64)(h.acc2 >> 64);
+    o->acc2_sq.lo = (u64)h.acc2_sq;
+    o->acc2_sq.hi = (u64)(h.acc2_sq >> 64);
+    o->n_valid = h.n_valid;
+    o->n_bad_vertex = h.n_vertex;
+    o->n_bad_delta = h.n_delta;
+    o->n_bad_order = h.n_order;
+    o->n_nonzero = h.n_nonzero;
+    if (h.flags & 2) o->flags |= TM_F_SQ_SATURATED;
+    o->status = (h.flags & 1) ? TM_EOVERFLOW : h.status;
+}
+
+namespace {
+
+// One batched pass over jobs whose root-key ranges and sample offsets all fit
+// 32 bits together: job y's keys are key_base[y] + (its root key < 2 m_y).
+int batch_group(tm_weights* const* ws, const std::vector<int>& act, const u64* j0s, const u64* counts,
+                const u64* seeds, hipStream_t st, JobSums* out, const BatchConfig& cfg) {
     const int na = (int)act.size();
-    if (na == 0) return TM_OK;
-    int kb = 1;
-    u64 total = 0;
-    for (int x : act) {
-        kb = std::max(kb, bits_of(2 * (u64)ws[x]->g->m - 1));
-        total += ks[x];
+    u64 total = 0, key_space = 0;
+    std::vector<uint32_t> key_base(na);
+    for (int y = 0; y < na; ++y) {
+        key_base[y] = (uint32_t)key_space;
+        key_space += 2 * (u64)ws[act[y]]->g->m;
+        total += counts[act[y]];
     }
-    const int jb = bits_of((u64)(na - 1));
-    if (kb + jb > 32 || total >= ((u64)1 << 32) || total < ks[act[0]]) {
-        // too large for one set of 32-bit keys: job by job
-        for (int x : act) {
-            tm_sample_rec* none = nullptr;
-            TM_TRY(sample_run(ws[x], seeds[x], 0, ks[x], ks[x], st, &out[x], none, nullptr));
-        }
-        return TM_OK;
-    }
+    const int key_bits = std::max(1, bits_of(key_space - 1));
     const int tile = cfg.tile > 0 ? cfg.tile : 8192;
     int cus = 256;
     {
@@ -1063,17 +1073,17 @@ int batch_sample_run(tm_weights* const* ws, const u64* ks, const u64* seeds, int
     // job arguments; groups by (wide, general) kernel variant
     std::vector<SampleArgs> args(na);
     std::vector<u64> base(na);
-    const int passes = (kb + jb + kRadixBits - 1) / kRadixBits;
+    const int passes = (key_bits + kRadixBits - 1) / kRadixBits;
     u64 off = 0;
     for (int y = 0; y < na; ++y) {
         size_t lds;
         fill_args(ws[act[y]], &args[y], &lds);
         args[y].seed = seeds[act[y]];
-        args[y].j0 = 0;
-        args[y].count = ks[act[y]];
-        args[y].key_mask = (kb >= 32) ? ~0u : ((1u << kb) - 1);
+        args[y].j0 = j0s[act[y]];
+        args[y].count = counts[act[y]];
+        args[y].key_base = key_base[y];
         base[y] = off;
-        off += ks[act[y]];
+        off += counts[act[y]];
     }
     std::vector<Tile> rt, stt;
     std::vector<int> g_rt_first(5, 0), g_st_first(5, 0), jfirst(na), jcount(na);
@@ -1085,8 +1095,9 @@ int batch_sample_run(tm_weights* const* ws, const u64* ks, const u64* seeds, int
             const int gy = (w->wide ? 2 : 0) + (args[y].general_runs ? 1 : 0);
             if (gy != grp) continue;
             jfirst[y] = (int)stt.size();
-            for (u64 b = 0; b < ks[act[y]]; b += (u64)tile) {
-                const u64 e = std::min<u64>(ks[act[y]], b + (u64)tile);
+            const u64 cy = counts[act[y]];
+            for (u64 b = 0; b < cy; b += (u64)tile) {
+                const u64 e = std::min<u64>(cy, b + (u64)tile);
                 rt.push_back(Tile{y, 0, b, e, base[y]});
                 stt.push_back(Tile{y, 0, base[y] + b, base[y] + e, 0});
             }
@@ -1137,15 +1148,15 @@ int batch_sample_run(tm_weights* const* ws, const u64* ks, const u64* seeds, int
         const Tile* tl = drt + g_rt_first[grp];
         if (grp >= 2)
             hipLaunchKernelGGL(batch_root_kernel<u128>, grid, dim3(kBlock), kCumLdsBytes, st, djobs, tl, nt,
-                               ctr + grp, k0, v0, kb, ovf);
+                               ctr + grp, k0, v0, ovf);
         else
             hipLaunchKernelGGL(batch_root_kernel<u64>, grid, dim3(kBlock), kCumLdsBytes, st, djobs, tl, nt,
-                               ctr + grp, k0, v0, kb, ovf);
+                               ctr + grp, k0, v0, ovf);
         TM_HIP(hipGetLastError());
     }
     {
         uint32_t *ksr, *vsr;
-        TM_TRY(radix_sort_pairs<uint32_t>(k0, v0, k1, v1, (int64_t)total, 0, kb + jb, &ksr, &vsr, ovf, st));
+        TM_TRY(radix_sort_pairs<uint32_t>(k0, v0, k1, v1, (int64_t)total, 0, key_bits, &ksr, &vsr, ovf, st));
         if (ksr != ks_sorted) return tm_fail(TM_EDEVICE, "batch: unexpected sort buffer");
     }
     t_roots.stop();
@@ -1185,21 +1196,72 @@ int batch_sample_run(tm_weights* const* ws, const u64* ks, const u64* seeds, int
     if (hovf & 2) return tm_fail(TM_EDEVICE, "batch: inconsistent weight tables");
     for (int y = 0; y < na; ++y) {
         const Partial& h = hp[y];
-        tm_result& o = out[act[y]];
+        JobSums& o = out[act[y]];
         if ((hovf & 1) || (h.flags & 1)) {
             o.status = TM_EOVERFLOW;
             continue;
         }
-        o.acc2.lo = (u64)h.acc2;
-        o.acc2.hi = (u64)(h.acc2 >> 64);
-        o.acc2_sq.lo = (u64)h.acc2_sq;
-        o.acc2_sq.hi = (u64)(h.acc2_sq >> 64);
+        o.acc2 = h.acc2;
+        o.acc2_sq = h.acc2_sq;
         o.n_valid = h.n_valid;
-        o.n_bad_vertex = h.n_vertex;
-        o.n_bad_delta = h.n_delta;
-        o.n_bad_order = h.n_order;
+        o.n_vertex = h.n_vertex;
+        o.n_delta = h.n_delta;
+        o.n_order = h.n_order;
         o.n_nonzero = h.n_nonzero;
-        if (h.flags & 2) o.flags |= TM_F_SQ_SATURATED;
+        o.flags = h.flags & 2;
     }
     return TM_OK;
+}
+
+}  // namespace
+
+int batch_sample_pass(tm_weights* const* ws, const u64* j0s, const u64* counts, const u64* seeds, int n,
+                      hipStream_t st, JobSums* out, const BatchConfig& cfg) {
+    std::vector<int> act;
+    for (int x = 0; x < n; ++x) {
+        out[x] = JobSums{};
+        tm_weights* w = ws[x];
+        if (w->plan.nt < 1 || w->plan.nt > 7) return tm_fail(TM_EINVAL, "batch: job %d tree size", x);
+        if (w->W != 0 && counts[x] > 0) act.push_back(x);
+    }
+    // groups in job order whose key ranges (2 m per job) and sample counts
+    // each stay below 2^32; a job alone beyond that samples on its own
+    const u64 lim = (u64)1 << 32;
+    std::vector<int> grp;
+    u64 keys = 0, cnt = 0;
+    auto flush = [&]() -> int {
+        if (grp.empty()) return TM_OK;
+        const int rc = batch_group(ws, grp, j0s, counts, seeds, st, out, cfg);
+        grp.clear();
+        keys = cnt = 0;
+        return rc;
+    };
+    for (int x : act) {
+        const u64 kx = 2 * (u64)ws[x]->g->m;
+        if (counts[x] >= lim) {
+            tm_result r;
+            tm_sample_rec* none = nullptr;
+            const int rc = sample_run(ws[x], seeds[x], j0s[x], counts[x], counts[x], st, &r, none, nullptr);
+            if (rc == TM_EOVERFLOW) {
+                out[x].status = rc;
+                continue;
+            }
+            TM_TRY(rc);
+            JobSums& h = out[x];
+            h.acc2 = ((u128)r.acc2.hi << 64) | r.acc2.lo;
+            h.acc2_sq = ((u128)r.acc2_sq.hi << 64) | r.acc2_sq.lo;
+            h.n_valid = r.n_valid;
+            h.n_vertex = r.n_bad_vertex;
+            h.n_delta = r.n_bad_delta;
+            h.n_order = r.n_bad_order;
+            h.n_nonzero = r.n_nonzero;
+            h.flags = (r.flags & TM_F_SQ_SATURATED) ? 2 : 0;
+            continue;
+        }
+        if (keys + kx > lim || cnt + counts[x] >= lim) TM_TRY(flush());
+        grp.push_back(x);
+        keys += kx;
+        cnt += counts[x];
+    }
+    return flush();
 }

@@ -46,6 +46,8 @@ int arena_alloc(DevArena& A, T** p, size_t count) {
 // Device block cache (mem.cpp): stream-aware reuse of released blocks.
 hipError_t dev_alloc(void** p, size_t bytes, hipStream_t st);
 hipError_t dev_free(void* p, hipStream_t st);
+// Synchronise the device and return every cached block to HIP.
+void dev_cache_trim();
 // Every block released on st becomes reusable by any stream.
 void dev_stream_synced(hipStream_t st);
 // hipStreamSynchronize, then dev_stream_synced.
@@ -103,12 +105,13 @@ int plan_build(const tm_motif* mo, const tm_tree* tr, HostPlan* out);
 int motif_check(const tm_motif* mo);
 
 // ---------------------------------------------------------------------------
-// Per-slot tables of a weight set.  For a non-leaf slot s, vals[s][par] holds,
-// per eid e, w_i(s, e) for the interval i of parity par that holds e (each
-// edge lies in at most one interval of each parity).  Non-leaf, non-center
-// slots also keep exclusive prefix sums of those values along the lists in
-// which their parent looks them up (qt: T order, qn: N order, per parity);
-// the center keeps them along eid order (qc).
+// Per-slot tables of a weight set.  For a non-leaf slot s, the build computes
+// per eid e w_i(s, e) for the interval i of parity par that holds e (each
+// edge lies in at most one interval of each parity) into vals[s][par], a
+// temporary.  What stays are exclusive prefix sums of those values: for
+// non-leaf, non-center slots along the lists in which their parent looks them
+// up (qt: T order, qn: N order, per parity); for the center along eid order
+// (qc).  A value is the difference of two neighbouring prefix entries.
 // ---------------------------------------------------------------------------
 struct tm_weights {
     tm_graph* g = nullptr;
@@ -116,7 +119,7 @@ struct tm_weights {
     bool wide = false;
     int64_t q = 0;
     u128 W = 0;
-    void* vals[kMaxSlots][2] = {};
+    void* vals[kMaxSlots][2] = {};  // build temporaries, null afterwards
     void* qt[kMaxSlots][2] = {};
     void* qn[kMaxSlots][2] = {};
     void* qc[2] = {};
@@ -139,6 +142,25 @@ int weights_enqueue(tm_weights* w, hipStream_t st, int* ovf);
 int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStream_t st,
                tm_result* out, tm_sample_rec* recs, u64* model_bytes);
 
+// Device bytes of a weight set's tables (prefix arrays, intervals) for a
+// graph of m edges and q intervals, in 64-bit (wide = false) or 128-bit form,
+// and the temporaries a build holds on top of them at its peak (one slot's
+// values, per parity).
+u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide);
+u64 weights_build_extra(int64_t m, bool wide);
+
+// Exact sums over a range of samples of one job.  Sums over disjoint ranges
+// add up to the sums over their union, whatever the split.
+struct JobSums {
+    u128 acc2 = 0, acc2_sq = 0;
+    u64 n_valid = 0, n_vertex = 0, n_delta = 0, n_order = 0, n_nonzero = 0;
+    u64 flags = 0;  // bit 0: acc2 reached 2^128; bit 1: acc2_sq saturated
+    int status = TM_OK;
+};
+void sums_merge(JobSums& into, const JobSums& x);
+// Copy sums into a result (which already holds k, q, W and flags).
+void sums_to_result(const JobSums& s, tm_result* out);
+
 // Batched sampling of several weight sets in one pass (tile: samples per work
 // item of the persistent kernels; blocks: their grid, 0 = 8 per CU).
 struct BatchConfig {
@@ -146,8 +168,16 @@ struct BatchConfig {
     int blocks;
 };
 extern BatchConfig g_batch_config;
-int batch_sample_run(tm_weights* const* ws, const u64* k, const u64* seeds, int n, hipStream_t st,
-                     tm_result* out, const BatchConfig& cfg);
+// Samples j0[x] .. j0[x] + count[x] - 1 of every job x with W > 0; per-job
+// errors go to out[x].status.
+int batch_sample_pass(tm_weights* const* ws, const u64* j0, const u64* count, const u64* seeds, int n,
+                      hipStream_t st, JobSums* out, const BatchConfig& cfg);
+
+BatchConfig batch_config_now();
+int sample_batch_results(tm_weights* const* w, const uint64_t* k, const uint64_t* seed, int n_jobs,
+                         hipStream_t st, tm_result* out);
+// Estimate and standard error of a result whose W, k, acc2 and acc2_sq are set.
+void finish_result(tm_result* r);
 
 // ---------------------------------------------------------------------------
 // Stage timing with HIP events on the call's stream (tm_profile_enable).

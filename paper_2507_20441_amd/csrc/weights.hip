@@ -249,9 +249,11 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf) {
             // walk edges grouped by the endpoint most children search from:
             // neighbouring lanes then search the same list at nearby times
             a.walk = a.nc == 0 ? -1 : (at_src >= 0 ? 0 : 1);
+            // the values themselves are temporaries: the parent and the
+            // sampler read only the prefix arrays built from them below
             for (int par = 0; par < 2; ++par) {
                 W* p;
-                TM_TRY(arena_alloc(w->arena, &p, (size_t)m));
+                TM_HIP(dev_alloc((void**)&p, ((size_t)m * sizeof(W) + 255) & ~(size_t)255, st));
                 w->vals[s][par] = p;
                 a.out[par] = p;
             }
@@ -270,6 +272,8 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf) {
                     TM_TRY(device_exclusive_scan<W>(ListGather<W>{vp, g->d.neid[dir]}, m, qn, ovf, st));
                     w->qt[s][par] = qt;
                     w->qn[s][par] = qn;
+                    TM_HIP(dev_free(w->vals[s][par], st));
+                    w->vals[s][par] = nullptr;
                 }
             }
         }
@@ -281,6 +285,8 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf) {
         TM_TRY(device_exclusive_scan<W>(Plain<W>{static_cast<const W*>(w->vals[0][par])}, m, qc,
                                         ovf, st));
         w->qc[par] = qc;
+        TM_HIP(dev_free(w->vals[0][par], st));
+        w->vals[0][par] = nullptr;
     }
     // intervals and their weights
     TM_TRY(arena_alloc(w->arena, &w->ilo, (size_t)w->q));
@@ -300,6 +306,9 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf) {
 
 void clear_tables(tm_weights* w) {
     w->arena.release();
+    for (auto& vs : w->vals)
+        for (void* v : vs)
+            if (v) (void)dev_free(v, w->arena.stream);
     std::memset(w->vals, 0, sizeof w->vals);
     std::memset(w->qt, 0, sizeof w->qt);
     std::memset(w->qn, 0, sizeof w->qn);
@@ -347,6 +356,22 @@ int weights_build(tm_weights* w, hipStream_t st) {
     timer.finish();
     if (rc != TM_OK) clear_tables(w);
     return rc;
+}
+
+u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide) {
+    if (m <= 0) return 0;
+    const u64 wsz = wide ? 16 : 8;
+    auto blk = [](u64 bytes) { return ((bytes ? bytes : 16) + 255) & ~(u64)255; };
+    u64 b = 0;
+    for (int s = 1; s < P.nt; ++s)
+        if (P.n_children[s] > 0) b += 4 * blk((u64)(m + 1) * wsz);  // qt and qn, per parity
+    b += 2 * blk((u64)(m + 1) * wsz);                   // qc, per parity
+    b += 2 * blk((u64)q * 4) + blk((u64)(q + 1) * wsz); // ilo, ihi, cumW
+    return b;
+}
+
+u64 weights_build_extra(int64_t m, bool wide) {
+    return m <= 0 ? 0 : 2 * ((((u64)m * (wide ? 16 : 8)) + 255) & ~(u64)255);
 }
 
 int weights_enqueue(tm_weights* w, hipStream_t st, int* ovf) {

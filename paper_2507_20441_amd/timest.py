@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libtimest.so")
 
 TM_OK, TM_EINVAL, TM_ESELFLOOP, TM_EDUP, TM_EOVERFLOW, TM_ERANGE, TM_ENOMEM, TM_EDEVICE = \
     0, -1, -2, -3, -4, -5, -6, -7
+TM_EADMIT, TM_EAGAIN, TM_ECANCELED = -8, -9, -10
 TM_PTR_HOST, TM_PTR_DEVICE = 0, 1
 TM_F_W_ZERO, TM_F_SQ_SATURATED, TM_F_WIDE = 1, 2, 4
 ARRAYS = dict(src=0, dst=1, t=2, out_off=3, in_off=4, out_eid=5, in_eid=6, outn_eid=7, inn_eid=8)
@@ -43,6 +44,27 @@ class Result(C.Structure):
                 ("n_bad_vertex", C.c_uint64), ("n_bad_delta", C.c_uint64),
                 ("n_bad_order", C.c_uint64), ("n_nonzero", C.c_uint64), ("q", C.c_int64),
                 ("flags", C.c_uint32), ("status", C.c_int32)]
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("pass_samples", C.c_uint64), ("job_chunk", C.c_uint64), ("max_jobs", C.c_int32),
+                ("fifo", C.c_int32)]
+
+
+class QueryInfo(C.Structure):
+    _fields_ = [("queued_ms", C.c_double), ("latency_ms", C.c_double), ("weights_hit", C.c_uint32),
+                ("passes", C.c_uint32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(f, C.c_uint64) for f in (
+        "submitted", "completed", "failed", "passes", "samples", "weight_builds", "weight_hits",
+        "evictions", "admission_waits", "budget_bytes", "resident_bytes", "peak_bytes", "cached_sets")] + [
+        ("build_ms", C.c_double), ("pass_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: (round(getattr(self, f), 3) if t is C.c_double else int(getattr(self, f)))
+                for f, t in self._fields_}
 
 
 REC_DTYPE = np.dtype([("interval", "<u4"), ("status", "<u4"), ("n_phi", "<u4"), ("pad", "<u4"),
@@ -93,6 +115,16 @@ def lib():
                                         C.POINTER(u64), C.POINTER(u64), C.c_int, vp,
                                         C.POINTER(Result)]
         L.tm_batch_config.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.tm_weights_footprint.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), i32, C.POINTER(u64)]
+        L.tm_server_create.argtypes = [u64, C.POINTER(ServerOpts), C.POINTER(vp)]
+        L.tm_server_add_graph.argtypes = [vp, vp, C.POINTER(i32)]
+        L.tm_server_submit.argtypes = [vp, i32, C.POINTER(Motif), C.POINTER(Tree), u64, u64,
+                                       C.POINTER(u64)]
+        L.tm_server_poll.argtypes = [vp, u64, C.POINTER(Result), C.POINTER(QueryInfo)]
+        L.tm_server_wait.argtypes = [vp, u64, C.POINTER(Result), C.POINTER(QueryInfo)]
+        L.tm_server_read_stats.argtypes = [vp, C.POINTER(ServerStats)]
+        L.tm_server_destroy.argtypes = [vp]
+        L.tm_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -287,3 +319,65 @@ def estimate_batch(graphs, motifs, ks, seeds, trees=None):
     out = (Result * n)()
     _check(lib().tm_estimate_batch(hs, mo, tr, kk, ss, n, _stream(), out), "estimate_batch")
     return list(out)
+
+
+def weights_footprint(g: Graph, mo: Motif, tr: Tree = None, wide=False) -> int:
+    b = C.c_uint64()
+    _check(lib().tm_weights_footprint(g.h, C.byref(mo), C.byref(tr) if tr is not None else None,
+                                      1 if wide else 0, C.byref(b)), "weights_footprint")
+    return int(b.value)
+
+
+class Server:
+    """tm_server_*: resident graphs, a budgeted weight-set cache and
+    continuous batching, driven by the library's worker thread."""
+
+    def __init__(self, budget_bytes, pass_samples=0, job_chunk=0, max_jobs=0, fifo=False):
+        o = ServerOpts(int(pass_samples), int(job_chunk), int(max_jobs), 1 if fifo else 0)
+        h = C.c_void_p()
+        _check(lib().tm_server_create(int(budget_bytes), C.byref(o), C.byref(h)), "server_create")
+        self.h = h
+        self._graphs = []
+
+    def add_graph(self, g: Graph) -> int:
+        gid = C.c_int32()
+        _check(lib().tm_server_add_graph(self.h, g.h, C.byref(gid)), "server_add_graph")
+        self._graphs.append(g)
+        return gid.value
+
+    def submit(self, gid, mo: Motif, k, seed, tr: Tree = None) -> int:
+        t = C.c_uint64()
+        _check(lib().tm_server_submit(self.h, int(gid), C.byref(mo),
+                                      C.byref(tr) if tr is not None else None, int(k), int(seed),
+                                      C.byref(t)), "server_submit")
+        return t.value
+
+    def poll(self, ticket):
+        """(Result, QueryInfo) once finished, else None."""
+        r, i = Result(), QueryInfo()
+        rc = lib().tm_server_poll(self.h, int(ticket), C.byref(r), C.byref(i))
+        if rc == TM_EAGAIN:
+            return None
+        _check(rc, "server_poll")
+        return r, i
+
+    def wait(self, ticket):
+        r, i = Result(), QueryInfo()
+        _check(lib().tm_server_wait(self.h, int(ticket), C.byref(r), C.byref(i)), "server_wait")
+        return r, i
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().tm_server_read_stats(self.h, C.byref(st)), "server_stats")
+        return st.as_dict()
+
+    def close(self):
+        if self.h:
+            lib().tm_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

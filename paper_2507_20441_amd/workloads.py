@@ -196,3 +196,96 @@ def batched_jobs(n_jobs=64, seed=1000, m_lo=1e4, m_hi=5e6):
 def batched_graph(job) -> TemporalGraph:
     return chung_lu_graph(job["n"], job["m"], 2.1, seed=job["graph_seed"], times="bursty",
                           span=10_000_000, name=f"job{job['graph_seed']}")
+
+
+# ---------------------------------------------------------------------------
+# Serving: graphs too large to draw on the host in reasonable time are drawn
+# on the device with torch's seeded generator (same recipe, different random
+# stream from the numpy generator above).
+# ---------------------------------------------------------------------------
+SERVE_DELTAS = (600, 1800, 3600, 7200, 14400, 28800, 43200, 86400)
+# the large graph's weight sets take 7-40 GB each: an hour and a day keep its
+# ten (motif, delta) sets resident together
+SERVE_DELTAS_LARGE = (3600, 86400)
+
+
+def device_graph(n, m, gamma, seed, span=10_000_000, device="cuda"):
+    """Chung-Lu pairs with bursty per-source times, drawn on the device.
+    Returns (src int32, dst int32, t int64) device tensors with every
+    (u, v, t) unique."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    f64 = torch.float64
+    w = (torch.arange(n, device=device, dtype=f64) + 1.0) ** (-1.0 / (gamma - 1.0))
+    cdf = torch.cumsum(w, 0)
+    cdf /= cdf[-1].clone()
+    del w
+    ids = torch.randperm(n, generator=gen, device=device).to(torch.int32)
+
+    def draw(size):
+        r = torch.searchsorted(cdf, torch.rand(size, generator=gen, device=device, dtype=f64), right=True)
+        return ids[r.clamp_(max=n - 1)]
+
+    u, v = draw(m), draw(m)
+    while True:
+        bad = torch.nonzero(u == v).flatten()
+        if bad.numel() == 0:
+            break
+        u[bad], v[bad] = draw(bad.numel()), draw(bad.numel())
+    del cdf, ids
+    # bursty times: per-source renewal process, Pareto(1.5) gaps, mean span ~ span
+    order = torch.argsort(u, stable=True)
+    us = u[order].long()
+    counts = torch.bincount(us, minlength=n)
+    first = torch.cumsum(counts, 0) - counts
+    gaps = (span / (3.0 * counts[us].to(f64))) * torch.rand(m, generator=gen, device=device, dtype=f64) ** (-1.0 / 1.5)
+    c = torch.cumsum(gaps, 0)
+    before = (c - gaps)[first.clamp(max=m - 1)]
+    s0 = torch.rand(n, generator=gen, device=device, dtype=f64) * span
+    ts = torch.floor(s0[us] + (c - before[us])) % span
+    del gaps, c, before, counts, first, s0
+    t = torch.empty(m, dtype=torch.int64, device=device)
+    t[order] = ts.to(torch.int64)
+    del ts, us, order
+    # unique (u, v, t): redraw the time of every repeat
+    while True:
+        key = u.long() * n + v.long()
+        idx = torch.argsort(t, stable=True)
+        idx = idx[torch.argsort(key[idx], stable=True)]
+        ks, tsr = key[idx], t[idx]
+        dup = torch.nonzero((ks[1:] == ks[:-1]) & (tsr[1:] == tsr[:-1])).flatten() + 1
+        del key, ks, tsr
+        if dup.numel() == 0:
+            break
+        t[idx[dup]] = torch.randint(0, span, (dup.numel(),), generator=gen, device=device)
+        del idx, dup
+    return u, v, t
+
+
+def serving_graph_specs(scale=1.0):
+    """The resident graphs: one of 2e7 vertices and 5e8 edges, eight of 5e4
+    vertices and 1e6 edges (gamma 2.1, medium-style times over 1e7 s);
+    scale shrinks the large one for quick runs."""
+    big = dict(n=max(1000, int(2e7 * scale)), m=max(20_000, int(5e8 * scale)), seed=2000)
+    small = [dict(n=50_000, m=1_000_000, seed=2001 + g) for g in range(8)]
+    return [big] + small
+
+
+def serving_queries(seconds=60.0, rate=200.0, n_graphs=9, seed=3000):
+    """Poisson arrivals at `rate` per second for `seconds`: graph uniform over
+    the resident ones (graph 0 is the large one), motif uniform over MOTIFS,
+    delta uniform over SERVE_DELTAS_LARGE on graph 0 and over SERVE_DELTAS
+    elsewhere, sample budget log-uniform in [1e5, 1e7]."""
+    rng = np.random.default_rng(seed)
+    names = list(MOTIFS)
+    out, t = [], 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= seconds:
+            return out
+        g = int(rng.integers(n_graphs))
+        grid = SERVE_DELTAS_LARGE if g == 0 else SERVE_DELTAS
+        out.append(dict(at=t, graph=g, motif=names[int(rng.integers(len(names)))],
+                        delta=grid[int(rng.integers(len(grid)))],
+                        k=int(round(10 ** rng.uniform(5, 7))), seed=int(rng.integers(1, 2**63 - 1))))

@@ -1,0 +1,183 @@
+"""Serving loop: queries answered by the server are bit-identical to the same
+query run alone with tm_estimate, whatever else is in the mix, however the
+budget forces weight sets out and back in, and however a query's samples are
+split across passes; a few are also checked against the oracle."""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2507_20441_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-serve]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2507_20441_amd import timest
+    timest.lib()
+    return timest
+
+
+def same(a, b):
+    return (a.acc2.value == b.acc2.value and a.acc2_sq.value == b.acc2_sq.value
+            and a.n_valid == b.n_valid and a.n_bad_vertex == b.n_bad_vertex
+            and a.n_bad_delta == b.n_bad_delta and a.n_bad_order == b.n_bad_order
+            and a.n_nonzero == b.n_nonzero and a.W.value == b.W.value
+            and a.estimate == b.estimate and a.flags == b.flags and a.k == b.k)
+
+
+@pytest.fixture(scope="module")
+def world(T):
+    """Three resident graphs and 40 queries: every motif, several deltas,
+    repeated (graph, motif, delta) sets, uneven budgets, a zero-sample query."""
+    gs = [W.small_graph(m, s, n=max(50, m // 20), span=20 * m) for m, s in ((4000, 11), (30000, 12), (90000, 13))]
+    tg = [T.Graph(g.src, g.dst, g.t, g.n) for g in gs]
+    rng = np.random.default_rng(21)
+    names = list(W.MOTIFS)
+    deltas = [[300, 1500], [2000, 9000], [5000, 40000]]
+    qs = []
+    for i in range(40):
+        gi = int(rng.integers(3))
+        name = names[int(rng.integers(len(names)))]
+        delta = deltas[gi][int(rng.integers(2))]
+        k = int(10 ** rng.uniform(2, 5.3))
+        qs.append((gi, name, delta, k, int(rng.integers(1, 2 ** 62))))
+    qs.append((0, "4cycle", 300, 0, 5))
+    alone = []
+    for gi, name, delta, k, seed in qs:
+        alone.append(T.estimate(tg[gi], T.make_motif(W.MOTIFS[name], delta), k, seed))
+    return gs, tg, qs, alone
+
+
+def run_mix(T, tg, qs, **opts):
+    srv = T.Server(**opts)
+    try:
+        gids = [srv.add_graph(g) for g in tg]
+        tickets = [srv.submit(gids[gi], T.make_motif(W.MOTIFS[name], delta), k, seed)
+                   for gi, name, delta, k, seed in qs]
+        out = [srv.wait(t) for t in tickets]
+        return out, srv.stats()
+    finally:
+        srv.close()
+
+
+@pytest.mark.parametrize("fifo", [False, True])
+def test_mix_matches_alone(T, world, fifo):
+    gs, tg, qs, alone = world
+    say("mix fifo", fifo)
+    out, st = run_mix(T, tg, qs, budget_bytes=1 << 32, pass_samples=1 << 15, job_chunk=1 << 12, fifo=fifo)
+    for i, ((r, info), a) in enumerate(zip(out, alone)):
+        assert r.status == 0 and same(r, a), (i, qs[i])
+        assert info.latency_ms >= info.queued_ms >= 0
+    assert st["completed"] == len(qs) and st["failed"] == 0
+    assert st["passes"] > 1 and st["weight_hits"] > 0
+    assert max(info.passes for _, info in out) > 1
+
+
+def test_budget_forces_eviction(T, world):
+    gs, tg, qs, alone = world
+    # room for the largest single weight set and little more
+    wide = [bool(a.flags & T.TM_F_WIDE) for a in alone]
+    # a build holds one slot's 64-bit values per parity on top of the tables
+    extra = [2 * ((tg[gi].m * 8 + 255) & ~255) for gi, *_ in qs]
+    need = max(T.weights_footprint(tg[gi], T.make_motif(W.MOTIFS[name], delta), wide=wd) + x
+               for (gi, name, delta, _, _), wd, x in zip(qs, wide, extra))
+    budget = 24 * (1 << 14) + need + need // 4
+    say("evict budget", budget, "wide sets", sum(wide))
+    out, st = run_mix(T, tg, qs, budget_bytes=budget, pass_samples=1 << 14, job_chunk=1 << 11)
+    for i, ((r, _), a) in enumerate(zip(out, alone)):
+        assert r.status == 0 and same(r, a), (i, qs[i])
+    assert st["evictions"] > 0 and st["admission_waits"] > 0
+    if not any(wide):
+        # a 128-bit set can exceed its 64-bit admission estimate; otherwise
+        # the budget holds
+        assert st["peak_bytes"] <= budget
+
+
+def test_footprint_matches_build(T, world):
+    gs, tg, qs, alone = world
+    for gi, name, delta, _, _ in qs[:10]:
+        mo = T.make_motif(W.MOTIFS[name], delta)
+        w = T.Weights(tg[gi], mo)
+        info = w.info()
+        assert T.weights_footprint(tg[gi], mo, wide=info["wide"]) == info["bytes"]
+        w.close()
+
+
+def test_oracle_agrees(T, world):
+    gs, tg, qs, alone = world
+    g = gs[0]
+    og = O.Graph(g.src, g.dst, g.t, g.n)
+    srv = T.Server(1 << 30, pass_samples=1 << 13, job_chunk=1 << 10)
+    try:
+        gid = srv.add_graph(tg[0])
+        cases = [("3cycle", 300, 5000, 3), ("4cycle", 1500, 7000, 4), ("scatter_gather", 1500, 3000, 5)]
+        tickets = [srv.submit(gid, T.make_motif(W.MOTIFS[n], d), k, s) for n, d, k, s in cases]
+        for (n, d, k, s), t in zip(cases, tickets):
+            r, _ = srv.wait(t)
+            P = O.Prep(og, O.make_motif(W.MOTIFS[n], d))
+            o = P.sample(s, k)[0]
+            assert r.acc2.value == o.acc2.value and r.W.value == P.W and r.n_valid == o.n_valid, n
+            assert r.estimate == o.estimate
+    finally:
+        srv.close()
+
+
+def test_concurrent_submitters(T, world):
+    gs, tg, qs, alone = world
+    srv = T.Server(1 << 32, pass_samples=1 << 15, job_chunk=1 << 12)
+    gids = [srv.add_graph(g) for g in tg]
+    results = [None] * len(qs)
+
+    def client(part):
+        for i in range(part, len(qs), 4):
+            gi, name, delta, k, seed = qs[i]
+            t = srv.submit(gids[gi], T.make_motif(W.MOTIFS[name], delta), k, seed)
+            results[i] = srv.wait(t)
+
+    th = [threading.Thread(target=client, args=(p,)) for p in range(4)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    srv.close()
+    for i, (r, _) in enumerate(results):
+        assert same(r, alone[i]), i
+
+
+def test_errors(T, world):
+    gs, tg, qs, alone = world
+    with pytest.raises(T.TimestError) as e:
+        T.Server(1000, pass_samples=1 << 10)
+    assert e.value.code == T.TM_EINVAL
+    srv = T.Server(24 * (1 << 10) + 4096, pass_samples=1 << 10, job_chunk=1 << 10)
+    try:
+        gid = srv.add_graph(tg[2])
+        with pytest.raises(T.TimestError) as e:
+            srv.submit(gid, T.make_motif(W.MOTIFS["6chain"], 5000), 100, 1)
+        assert e.value.code == T.TM_EADMIT
+        with pytest.raises(T.TimestError) as e:
+            srv.submit(7, T.make_motif(W.MOTIFS["3cycle"], 5000), 100, 1)
+        assert e.value.code == T.TM_EINVAL
+        with pytest.raises(T.TimestError) as e:
+            srv.wait(12345)
+        assert e.value.code == T.TM_EINVAL
+    finally:
+        srv.close()
+
+
+def test_shutdown_with_pending(T, world):
+    gs, tg, qs, alone = world
+    srv = T.Server(1 << 32, pass_samples=1 << 12, job_chunk=1 << 10)
+    gid = srv.add_graph(tg[2])
+    for i in range(8):
+        srv.submit(gid, T.make_motif(W.MOTIFS["4star"], 40000), 200000, i + 1)
+    srv.close()
