@@ -41,16 +41,22 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="before timing, run a plain device copy of BYTES (3 times) so that "
                          "hardware counters can be scaled by a kernel of known traffic")
-    ap.add_argument("--workload", choices=["medium", "batched", "serving"], default="medium",
+    ap.add_argument("--workload", choices=["medium", "batched", "serving", "weights"], default="medium",
                     help="medium: the single-job path (default); batched: 64 heterogeneous "
                          "jobs, one launch per job against the batched pass; serving: a Poisson "
                          "query stream against the server")
+    ap.add_argument("--weights-graph", choices=["medium", "serving"], default="serving",
+                    help="weights: the medium graph, or the 5e8-edge serving graph")
+    ap.add_argument("--weights-deltas", default="3600,86400")
     ap.add_argument("--serve-scale", type=float, default=1.0,
                     help="serving: size of the large resident graph relative to 5e8 edges")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=200.0, help="queries per second")
     ap.add_argument("--serve-budget-gb", type=float, default=0.0,
-                    help="server budget; 0: free device memory after the graphs, less 16 GB")
+                    help="server budget; 0: free device memory after the graphs, less 4 GiB")
+    ap.add_argument("--serve-cold", action="store_true",
+                    help="serving: start the stream with an empty weight cache (default: every "
+                         "(graph, motif, delta) set the stream uses is built first)")
     ap.add_argument("--serve-check", type=int, default=12,
                     help="served queries re-run alone with tm_estimate and compared")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "sample_kernel_medium_traffic.json"),
@@ -70,6 +76,8 @@ def main():
         return batched(args)
     if args.workload == "serving":
         return serving(args)
+    if args.workload == "weights":
+        return weights_only(args)
 
     import ctypes as C
 
@@ -322,14 +330,23 @@ def serving(args):
         torch.cuda.empty_cache()
         log(f"graph n={sp['n']} m={sp['m']} built, {time.perf_counter() - t0:.1f} s")
     free = torch.cuda.mem_get_info()[0]
-    budget = int(args.serve_budget_gb * 2**30) if args.serve_budget_gb > 0 else int(free - 16 * 2**30)
+    budget = int(args.serve_budget_gb * 2**30) if args.serve_budget_gb > 0 else int(free - 4 * 2**30)
     queries = W.serving_queries(args.serve_seconds, args.serve_rate, len(graphs))
     motifs = {(q["motif"], q["delta"]): T.make_motif(W.MOTIFS[q["motif"]], q["delta"]) for q in queries}
     log(f"{len(queries)} queries over {args.serve_seconds} s; budget {budget / 2**30:.1f} GiB")
 
-    def run(qs, open_loop):
+    def run(qs, open_loop, warm=False):
         srv = T.Server(budget)
         gids = [srv.add_graph(g) for g in graphs]
+        warm_s = 0.0
+        if warm:
+            # resident weight tables: one zero-sample query per set the stream uses
+            t_w = time.perf_counter()
+            sets = sorted({(q["graph"], q["motif"], q["delta"]) for q in qs})
+            for gi, name, delta in sets:
+                srv.wait(srv.submit(gids[gi], motifs[(name, delta)], 0, 1))
+            warm_s = time.perf_counter() - t_w
+            log(f"{len(sets)} weight sets built in {warm_s:.1f} s")
         tickets = [None] * len(qs)
         ready = threading.Semaphore(0)
         res = [None] * len(qs)
@@ -357,11 +374,12 @@ def serving(args):
         th.join()
         wall = time.perf_counter() - start
         st = srv.stats()
+        st["warmup_s"] = round(warm_s, 3)
         srv.close()
         return res, st, wall
 
     log("open loop")
-    res, st, wall = run(queries, True)
+    res, st, wall = run(queries, True, warm=not args.serve_cold)
     errors = sorted({info for r, info in res if r is None})
     ok = [(r, info) for r, info in res if r is not None]
     if errors:
@@ -412,6 +430,7 @@ def serving(args):
                         "uniform over {3600, 86400} on the large graph and over 8 values 600..86400 "
                         "on the others, k log-uniform 1e5..1e7",
             "queries": len(queries), "samples_total": total, "budget_bytes": budget,
+            "weight_cache": "cold" if args.serve_cold else "warm (every set built before the stream)",
         },
         "failed_queries": len(res) - len(ok),
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
@@ -429,6 +448,47 @@ def serving(args):
     print(json.dumps(line), flush=True)
     for g in graphs:
         g.close()
+
+
+def weights_only(args):
+    """Weight builds alone (tm_weights_create) for every motif at each delta,
+    timed with the library's stage events, plus 1e6 samples each as a check."""
+    import torch
+
+    from paper_2507_20441_amd import timest as T
+    from paper_2507_20441_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    torch.cuda.set_device(0)
+    if args.weights_graph == "serving":
+        sp = W.serving_graph_specs(args.serve_scale)[0]
+        u, v, t = W.device_graph(sp["n"], sp["m"], 2.1, sp["seed"])
+        g = T.Graph(u, v, t, sp["n"])
+        del u, v, t
+        torch.cuda.empty_cache()
+    else:
+        mg = W.medium_graph()
+        g = T.Graph(mg.src, mg.dst, mg.t, mg.n)
+    T.profile_enable(True)
+    rows = []
+    for delta in [int(x) for x in args.weights_deltas.split(",")]:
+        for name in W.MOTIFS:
+            mo = T.make_motif(W.MOTIFS[name], delta)
+            best = None
+            for _ in range(max(1, args.steps)):
+                T.profile_read(reset=True)
+                w = T.Weights(g, mo)
+                ms = T.profile_read(reset=True)["ms"][1]
+                info = w.info()
+                r, _ = w.sample(1, 1_000_000)
+                w.close()
+                best = ms if best is None else min(best, ms)
+            rows.append(dict(motif=name, delta=delta, ms=round(best, 3), bytes=info["bytes"],
+                             wide=info["wide"], W=str(info["W"]), valid_of_1e6=int(r.n_valid)))
+            log(f"{name} delta={delta}: {best:.2f} ms, {info['bytes'] / 2**30:.2f} GiB, wide {info['wide']}")
+    print(json.dumps({"workload": f"weights on the {args.weights_graph} graph (m={g.m})", "builds": rows}),
+          flush=True)
+    g.close()
 
 
 def kernel_source_sha():

@@ -46,6 +46,13 @@ class Result(C.Structure):
                 ("flags", C.c_uint32), ("status", C.c_int32)]
 
 
+class Profile(C.Structure):
+    _fields_ = [("ms", C.c_double * 5), ("launches", C.c_uint64 * 5)]
+
+
+STAGES = ("graph", "weights", "sample", "reduce", "roots")
+
+
 class ServerOpts(C.Structure):
     _fields_ = [("pass_samples", C.c_uint64), ("job_chunk", C.c_uint64), ("max_jobs", C.c_int32),
                 ("fifo", C.c_int32)]
@@ -115,6 +122,10 @@ def lib():
                                         C.POINTER(u64), C.POINTER(u64), C.c_int, vp,
                                         C.POINTER(Result)]
         L.tm_batch_config.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.tm_profile_enable.argtypes = [C.c_int]
+        L.tm_profile_enable.restype = None
+        L.tm_profile_read.argtypes = [C.POINTER(Profile), C.c_int]
+        L.tm_sample_model_bytes.argtypes = [vp, u64, u64, u64, vp, C.POINTER(u64)]
         L.tm_weights_footprint.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), i32, C.POINTER(u64)]
         L.tm_server_create.argtypes = [u64, C.POINTER(ServerOpts), C.POINTER(vp)]
         L.tm_server_add_graph.argtypes = [vp, vp, C.POINTER(i32)]
@@ -381,3 +392,22 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def profile_enable(on=True):
+    """Stage timing with HIP events (tm_profile_enable)."""
+    lib().tm_profile_enable(1 if on else 0)
+
+
+def profile_read(reset=False) -> dict:
+    """Accumulated stage milliseconds and launch counts (tm_profile_read)."""
+    p = Profile()
+    _check(lib().tm_profile_read(C.byref(p), 1 if reset else 0), "profile_read")
+    return {"ms": list(p.ms), "launches": [int(x) for x in p.launches]}
+
+
+def sample_model_bytes(w: "Weights", seed, count, j0=0) -> int:
+    b = C.c_uint64()
+    _check(lib().tm_sample_model_bytes(w.h, int(seed), int(j0), int(count), _stream(), C.byref(b)),
+           "sample_model_bytes")
+    return int(b.value)
