@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cstring>
 #include <type_traits>
+#include <vector>
 
 #include "tm_primitives.h"
 
@@ -38,8 +39,10 @@ struct LevelArgs {
     int64_t delta;
     int nc;
     ChildDesc c[kMaxSlots];
-    int walk;  // -1: eid order; 0 / 1: the T order of the out- / in-lists
-    void* out[2];
+    int walk;          // -1: eid order; 0 / 1: the T order of the out- / in-lists
+    void* out[2];      // per parity: indexed by eid, or by in-list T position (out_by_pos)
+    int out_by_pos;    // first of two passes: write where the second pass walks
+    const void* in[2]; // second of two passes: the first pass's products, by walk position
     int* ovf;
 };
 
@@ -51,74 +54,76 @@ __device__ __forceinline__ void sfor(F&& f) {
     }
 }
 
-// Two windows of the same vertex list in lockstep: for each, the T-order
-// range with time in [lo, hi] and the N-order run of neighbour o in it.
-// Eight independent loads per halving step.
-struct Win {
-    int32_t p0, p1, q0, q1;
+// The first position of a vertex's list, in T order, whose time is >= x,
+// and, in N order, whose packed key is >= (o << bt) + x, for three x at once:
+// six independent loads per halving step.  x is clipped to [0, T + 1]; the
+// key for x = T + 1 (the end of o's run) is taken as "> (o << bt) + T", which
+// cannot wrap even when the id and time bits fill all 64.
+struct Bounds3 {
+    int32_t p[3], q[3];
 };
 
-__device__ __forceinline__ void two_windows(const DevGraph& G, int dir, int32_t g, int32_t o,
-                                            int64_t lo0, int64_t hi0, int64_t lo1, int64_t hi1,
-                                            Win& A, Win& B) {
+__device__ __forceinline__ Bounds3 three_bounds(const DevGraph& G, int dir, int32_t g, int32_t o,
+                                                const int64_t (&xs)[3]) {
     const int32_t a = G.off[dir][g], b = G.off[dir][g + 1];
-    lo0 = lo0 < 0 ? 0 : lo0;
-    lo1 = lo1 < 0 ? 0 : lo1;
-    hi0 = hi0 > G.T ? G.T : hi0;
-    hi1 = hi1 > G.T ? G.T : hi1;
-    const bool e0 = lo0 > hi0 || a == b, e1 = lo1 > hi1 || a == b;
-    if (e0 && e1) {
-        A.p0 = A.p1 = A.q0 = A.q1 = a;
-        B = A;
-        return;
-    }
-    // an empty window searches harmless keys and is reset afterwards
-    if (e0) { lo0 = lo1; hi0 = hi1; }
-    if (e1) { lo1 = lo0; hi1 = hi0; }
     const int64_t* lt = G.lt[dir];
     const u64* nk = G.nkey[dir];
     const u64 base = (u64)o << G.bt;
-    const u64 kl0 = base | (u64)lo0, kh0 = base | (u64)hi0;
-    const u64 kl1 = base | (u64)lo1, kh1 = base | (u64)hi1;
-    int32_t c0 = a, c1 = a, c2 = a, c3 = a, c4 = a, c5 = a, c6 = a, c7 = a;
+    int64_t x[3];
+    u64 kx[3];
+    bool le[3];
+    int32_t c[6];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        x[j] = xs[j] < 0 ? 0 : (xs[j] > G.T + 1 ? G.T + 1 : xs[j]);
+        le[j] = x[j] > G.T;
+        kx[j] = base + (u64)(le[j] ? G.T : x[j]);
+        c[j] = a;
+        c[3 + j] = a;
+    }
     int32_t n = b - a;
     while (n > 1) {
         const int32_t h = n >> 1;
-        const int64_t x0 = lt[c0 + h], x1 = lt[c1 + h], x2 = lt[c2 + h], x3 = lt[c3 + h];
-        const u64 y0 = nk[c4 + h], y1 = nk[c5 + h], y2 = nk[c6 + h], y3 = nk[c7 + h];
-        c0 = x0 < lo0 ? c0 + h : c0;
-        c1 = x1 <= hi0 ? c1 + h : c1;
-        c2 = x2 < lo1 ? c2 + h : c2;
-        c3 = x3 <= hi1 ? c3 + h : c3;
-        c4 = y0 < kl0 ? c4 + h : c4;
-        c5 = y1 <= kh0 ? c5 + h : c5;
-        c6 = y2 < kl1 ? c6 + h : c6;
-        c7 = y3 <= kh1 ? c7 + h : c7;
+        int64_t y[3];
+        u64 z[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            y[j] = lt[c[j] + h];
+            z[j] = nk[c[3 + j] + h];
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            c[j] = y[j] < x[j] ? c[j] + h : c[j];
+            c[3 + j] = (z[j] < kx[j] || (le[j] && z[j] == kx[j])) ? c[3 + j] + h : c[3 + j];
+        }
         n -= h;
     }
-    A.p0 = c0 + (lt[c0] < lo0 ? 1 : 0);
-    A.p1 = c1 + (lt[c1] <= hi0 ? 1 : 0);
-    B.p0 = c2 + (lt[c2] < lo1 ? 1 : 0);
-    B.p1 = c3 + (lt[c3] <= hi1 ? 1 : 0);
-    A.q0 = c4 + (nk[c4] < kl0 ? 1 : 0);
-    A.q1 = c5 + (nk[c5] <= kh0 ? 1 : 0);
-    B.q0 = c6 + (nk[c6] < kl1 ? 1 : 0);
-    B.q1 = c7 + (nk[c7] <= kh1 ? 1 : 0);
-    if (e0) A.p0 = A.p1 = A.q0 = A.q1 = a;
-    if (e1) B.p0 = B.p1 = B.q0 = B.q1 = a;
+    Bounds3 r;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        r.p[j] = a == b ? a : c[j] + (lt[c[j]] < x[j] ? 1 : 0);
+        const u64 zl = nk[c[3 + j]];
+        r.q[j] = a == b ? a : c[3 + j] + ((zl < kx[j] || (le[j] && zl == kx[j])) ? 1 : 0);
+    }
+    return r;
 }
 
+// Sum of the child's weights over T positions [p0, p1) minus the N run [q0, q1).
 template <typename W>
-__device__ __forceinline__ W window_mass(const Win& w, bool leaf, const void* qt, const void* qn) {
-    if (leaf) return (W)((w.p1 - w.p0) - (w.q1 - w.q0));
+__device__ __forceinline__ W window_mass(int32_t p0, int32_t p1, int32_t q0, int32_t q1, bool leaf,
+                                         const void* qt, const void* qn) {
+    if (p1 <= p0) return (W)0;
+    if (leaf) return (W)((p1 - p0) - (q1 - q0));
     const W* T = static_cast<const W*>(qt);
     const W* N = static_cast<const W*>(qn);
-    return (T[w.p1] - T[w.p0]) - (N[w.q1] - N[w.q0]);
+    return (T[p1] - T[p0]) - (N[q1] - N[q0]);
 }
 
 // One thread per edge e and both intervals holding it: slot A is
-// i = floor(t / delta), slot B is i - 1.  The two windows of a child differ
-// only where the interval clips them, so they are searched together.
+// i = floor(t / delta) = blk, slot B is i - 1.  Clipped to those intervals,
+// a child window [t - delta, t] becomes [blk delta, t] (A) and [t - delta, t]
+// (B), and [t, t + delta] becomes [t, t + delta] (A) and
+// [t, (blk + 1) delta - 1] (B): three distinct bounds per child.
 template <typename W>
 __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -130,9 +135,11 @@ __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
     const int64_t blk = t / a.delta;
     const bool hasB = blk >= 1;
     const int parA = (int)(blk & 1), parB = parA ^ 1;
-    const int64_t loA = blk * a.delta, hiA = (blk + 2) * a.delta - 1;
-    const int64_t loB = (blk - 1) * a.delta, hiB = (blk + 1) * a.delta - 1;
     W prodA = 1, prodB = hasB ? (W)1 : (W)0;
+    if (a.in[0]) {
+        prodA = static_cast<const W*>(a.in[parA])[p];
+        prodB = hasB ? static_cast<const W*>(a.in[parB])[p] : (W)0;
+    }
     W fA[kMaxSlots], fB[kMaxSlots];
     bool ovf = false;
     sfor<0, kMaxSlots>([&](auto cc) {
@@ -151,21 +158,36 @@ __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
         } else {
             const int32_t g = d.side ? v : u;
             const int32_t o = d.side ? u : v;
-            const int64_t wlo = d.beta < 0 ? t - a.delta : t;
-            const int64_t whi = d.beta < 0 ? t : t + a.delta;
-            Win A, B;
-            two_windows(G, d.dir, g, o, wlo > loA ? wlo : loA, whi < hiA ? whi : hiA,
-                        wlo > loB ? wlo : loB, whi < hiB ? whi : hiB, A, B);
-            xa = window_mass<W>(A, d.leaf, d.qt[parA], d.qn[parA]);
-            xb = hasB ? window_mass<W>(B, d.leaf, d.qt[parB], d.qn[parB]) : (W)0;
+            // x values (first position with time >= x):
+            //   before: A = [x0, x2), B = [x1, x2) with x0 = blk delta, x1 = t - delta, x2 = t + 1
+            //   after:  A = [x0, x1), B = [x0, x2) with x0 = t, x1 = t + delta + 1, x2 = (blk + 1) delta
+            int64_t xs[3];
+            if (d.beta < 0) {
+                xs[0] = blk * a.delta;
+                xs[1] = t - a.delta;
+                xs[2] = t + 1;
+            } else {
+                xs[0] = t;
+                xs[1] = t + a.delta + 1;
+                xs[2] = (blk + 1) * a.delta;
+            }
+            const Bounds3 r = three_bounds(G, d.dir, g, o, xs);
+            if (d.beta < 0) {
+                xa = window_mass<W>(r.p[0], r.p[2], r.q[0], r.q[2], d.leaf, d.qt[parA], d.qn[parA]);
+                xb = hasB ? window_mass<W>(r.p[1], r.p[2], r.q[1], r.q[2], d.leaf, d.qt[parB], d.qn[parB]) : (W)0;
+            } else {
+                xa = window_mass<W>(r.p[0], r.p[1], r.q[0], r.q[1], d.leaf, d.qt[parA], d.qn[parA]);
+                xb = hasB ? window_mass<W>(r.p[0], r.p[2], r.q[0], r.q[2], d.leaf, d.qt[parB], d.qn[parB]) : (W)0;
+            }
         }
         fA[c] = xa;
         fB[c] = xb;
         if (!mul_ok(prodA, xa, &prodA)) ovf = true;
         if (!mul_ok(prodB, xb, &prodB)) ovf = true;
     });
-    static_cast<W*>(a.out[parA])[e] = prodA;
-    static_cast<W*>(a.out[parB])[e] = hasB ? prodB : (W)0;
+    const int64_t at = a.out_by_pos ? (int64_t)G.tpos[1][e] : (int64_t)e;
+    static_cast<W*>(a.out[parA])[at] = prodA;
+    static_cast<W*>(a.out[parB])[at] = hasB ? prodB : (W)0;
     if (ovf) atomicOr(a.ovf, 4);
 }
 
@@ -218,48 +240,62 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf) {
     for (int h = 0; h <= P.H; ++h) {
         for (int s = 0; s < P.nt; ++s) {
             if (P.height[s] != h || (h == 0 && s != 0)) continue;
-            LevelArgs a;
-            std::memset(&a, 0, sizeof a);
-            a.G = g->d;
-            a.delta = delta;
-            a.nc = P.n_children[s];
-            int at_src = 0;
-            for (int j = 0; j < a.nc; ++j) {
-                const int c = P.children[s][j];
-                ChildDesc& d = a.c[j];
-                d.side = P.side[c];
-                d.dir = P.alpha[c] > 0 ? 0 : 1;
-                d.beta = P.beta[c];
-                d.leaf = P.n_children[c] == 0;
-                d.same_as = -1;
-                for (int j2 = 0; j2 < j && d.leaf; ++j2) {
-                    const ChildDesc& e2 = a.c[j2];
-                    if (e2.leaf && e2.same_as < 0 && e2.side == d.side && e2.dir == d.dir &&
-                        e2.beta == d.beta) {
-                        d.same_as = j2;
-                        break;
-                    }
-                }
-                for (int par = 0; par < 2; ++par) {
-                    d.qt[par] = w->qt[c][par];
-                    d.qn[par] = w->qn[c][par];
-                }
-                at_src += d.side == 0 ? 1 : -1;
-            }
-            // walk edges grouped by the endpoint most children search from:
-            // neighbouring lanes then search the same list at nearby times
-            a.walk = a.nc == 0 ? -1 : (at_src >= 0 ? 0 : 1);
-            // the values themselves are temporaries: the parent and the
-            // sampler read only the prefix arrays built from them below
+            // children grouped by the endpoint they attach at: each group
+            // walks the lists of that endpoint, so neighbouring lanes search
+            // the same list at nearby times; with children at both endpoints
+            // the first pass leaves its products where the second walks
+            std::vector<int> grp[2];
+            for (int j = 0; j < P.n_children[s]; ++j) grp[P.side[P.children[s][j]]].push_back(P.children[s][j]);
+            const bool two = !grp[0].empty() && !grp[1].empty();
             for (int par = 0; par < 2; ++par) {
                 W* p;
                 TM_HIP(dev_alloc((void**)&p, ((size_t)m * sizeof(W) + 255) & ~(size_t)255, st));
                 w->vals[s][par] = p;
-                a.out[par] = p;
             }
-            a.ovf = ovf;
-            hipLaunchKernelGGL((level_kernel<W>), dim3(grid_for(m)), dim3(kBlock), 0, st, a);
-            TM_HIP(hipGetLastError());
+            W* tmp[2] = {nullptr, nullptr};
+            if (two)
+                for (int par = 0; par < 2; ++par)
+                    TM_HIP(dev_alloc((void**)&tmp[par], ((size_t)m * sizeof(W) + 255) & ~(size_t)255, st));
+            for (int pass = 0; pass < (two ? 2 : 1); ++pass) {
+                const int side = two ? pass : (grp[0].empty() ? 1 : 0);
+                const std::vector<int>& cs = grp[side];
+                LevelArgs a;
+                std::memset(&a, 0, sizeof a);
+                a.G = g->d;
+                a.delta = delta;
+                a.nc = (int)cs.size();
+                for (int j = 0; j < a.nc; ++j) {
+                    const int c = cs[j];
+                    ChildDesc& d = a.c[j];
+                    d.side = P.side[c];
+                    d.dir = P.alpha[c] > 0 ? 0 : 1;
+                    d.beta = P.beta[c];
+                    d.leaf = P.n_children[c] == 0;
+                    d.same_as = -1;
+                    for (int j2 = 0; j2 < j && d.leaf; ++j2) {
+                        const ChildDesc& e2 = a.c[j2];
+                        if (e2.leaf && e2.same_as < 0 && e2.dir == d.dir && e2.beta == d.beta) {
+                            d.same_as = j2;
+                            break;
+                        }
+                    }
+                    for (int par = 0; par < 2; ++par) {
+                        d.qt[par] = w->qt[c][par];
+                        d.qn[par] = w->qn[c][par];
+                    }
+                }
+                a.walk = a.nc == 0 ? -1 : side;
+                for (int par = 0; par < 2; ++par) {
+                    a.out[par] = (two && pass == 0) ? (void*)tmp[par] : w->vals[s][par];
+                    a.in[par] = (two && pass == 1) ? (const void*)tmp[par] : nullptr;
+                }
+                a.out_by_pos = two && pass == 0;
+                a.ovf = ovf;
+                hipLaunchKernelGGL((level_kernel<W>), dim3(grid_for(m)), dim3(kBlock), 0, st, a);
+                TM_HIP(hipGetLastError());
+            }
+            if (two)
+                for (int par = 0; par < 2; ++par) TM_HIP(dev_free(tmp[par], st));
             // prefix sums along the lists the parent searches
             if (s != 0) {
                 const int dir = P.alpha[s] > 0 ? 0 : 1;
@@ -371,7 +407,8 @@ u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide) {
 }
 
 u64 weights_build_extra(int64_t m, bool wide) {
-    return m <= 0 ? 0 : 2 * ((((u64)m * (wide ? 16 : 8)) + 255) & ~(u64)255);
+    // one slot's values and a two-pass level's products, per parity
+    return m <= 0 ? 0 : 4 * ((((u64)m * (wide ? 16 : 8)) + 255) & ~(u64)255);
 }
 
 int weights_enqueue(tm_weights* w, hipStream_t st, int* ovf) {
