@@ -42,6 +42,8 @@ struct SampleArgs {
     const int32_t* ilo;
     const int32_t* ihi;
     const void* cumW;
+    const u64* guide;  // root pairs at 2^guide_bits + 1 evenly spaced draws (see weights)
+    int guide_bits;
     int cum_in_lds;  // the q+1 interval prefix fits the block's LDS
     u64 W_lo, W_hi;
     int n_free;
@@ -147,20 +149,6 @@ __device__ __forceinline__ Bounds window_bounds(const DevGraph& G, int dir, int3
     r.q0 = b2 + (nk[b2] < klo ? 1 : 0);
     r.q1 = b3 + (nk[b3] <= khi ? 1 : 0);
     return r;
-}
-
-// First index in [lo, hi) with a[idx] > key (hi if none).
-template <typename T>
-__device__ __forceinline__ int32_t upper_bound_bl(const T* a, int32_t lo, int32_t hi, T key) {
-    int32_t n = hi - lo;
-    if (n <= 0) return lo;
-    int32_t b = lo;
-    while (n > 1) {
-        const int32_t h = n >> 1;
-        b = a[b + h] <= key ? b + h : b;
-        n -= h;
-    }
-    return b + (a[b] <= key ? 1 : 0);
 }
 
 // The multi-edge run El_{x,y} restricted to times [lo, hi]: a contiguous run
@@ -371,18 +359,38 @@ __device__ __forceinline__ void block_reduce_write(Partial acc, Partial* out) {
 // the root key (T-order position of the root * 2 + interval parity).
 // Inconsistent tables give a harmless key and set bad.
 template <typename W>
+__device__ __forceinline__ bool draw_root(const SampleArgs& a, const W* cum, W Wtot, u64 j, int32_t& i,
+                                          int32_t& e0, u64* nb = nullptr) {
+    const X128 X = draw_block(a.seed, j, 0);
+    const W r0 = scale(X, Wtot);
+    int32_t i0 = 0, i1 = (int32_t)a.q - 1, ea = -1, eb = 0x7fffffff;
+    if (a.guide) {
+        // the guide bucket of X bounds the pair between two guide entries
+        const u64 b = X.hi >> (64 - a.guide_bits);
+        const u64 g0 = a.guide[b], g1 = a.guide[b + 1];
+        i0 = (int32_t)(g0 >> 32);
+        ea = (int32_t)(uint32_t)g0;
+        i1 = (int32_t)(g1 >> 32);
+        eb = (int32_t)(uint32_t)g1;
+    }
+    int32_t span = 0;
+    const bool ok = root_pair<W>(cum, a.qc, a.ilo, a.ihi, a.q, r0, i0, i1, ea, eb, i, e0, &span);
+    if (nb) *nb += (a.guide ? 16 : 0) + (probes(i1 - i0 + 1) + 2 + probes(span)) * sizeof(W) + 8;
+    return ok;
+}
+
+// Draw 0 of sample a.j0 + r: the interval, then the center edge; returned as
+// the root key (T-order position of the root * 2 + interval parity).
+// Inconsistent tables give a harmless key and set bad.
+template <typename W>
 __device__ __forceinline__ uint32_t root_key(const SampleArgs& a, const W* cum, W Wtot, int32_t ncum,
                                              u64 r, bool& bad) {
-    const W r0 = scale(draw_block(a.seed, a.j0 + r, 0), Wtot);
-    const int32_t i = upper_bound_bl<W>(cum, 0, ncum, r0) - 1;
-    const int32_t lo = (i >= 0 && i < a.q) ? a.ilo[i] : 0, hi = (i >= 0 && i < a.q) ? a.ihi[i] : 0;
-    if (hi <= lo) {
+    (void)ncum;
+    int32_t i, e0;
+    if (!draw_root<W>(a, cum, Wtot, a.j0 + r, i, e0)) {
         bad = true;
         return 0u;
     }
-    const W* qc = static_cast<const W*>(a.qc[i & 1]);
-    int32_t e0 = upper_bound_bl<W>(qc, lo + 1, hi + 1, r0 - cum[i] + qc[lo]) - 1;
-    e0 = e0 < lo ? lo : (e0 >= hi ? hi - 1 : e0);
     return (uint32_t)a.G.tpos[0][e0] * 2u + (uint32_t)(i & 1);
 }
 
@@ -449,17 +457,9 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
         } else {
             // draw 0: interval, then center edge
             r = x;
-            const W r0 = scale(draw_block(a.seed, a.j0 + r, 0), Wtot);
-            i = upper_bound_bl<W>(cum, 0, ncum, r0) - 1;
-            if (i < 0 || i >= a.q) { bad = true; break; }
-            const W* qc = static_cast<const W*>(a.qc[i & 1]);
-            const int32_t lo = a.ilo[i], hi = a.ihi[i];
-            if (hi <= lo) { bad = true; break; }
-            const W target0 = r0 - cum[i] + qc[lo];
-            int32_t e0 = upper_bound_bl<W>(qc, lo + 1, hi + 1, target0) - 1;
-            e0 = e0 < lo ? lo : (e0 >= hi ? hi - 1 : e0);
-            if constexpr (kCount)
-                nb += (probes(a.q + 1) + 2 + probes(hi - lo)) * sizeof(W) + 8 + 16;
+            int32_t e0;
+            if (!draw_root<W>(a, cum, Wtot, a.j0 + r, i, e0, kCount ? &nb : nullptr)) { bad = true; break; }
+            if constexpr (kCount) nb += 16;
             ee[0] = e0;
             te[0] = G.t[e0];
             eu[0] = G.src[e0];
@@ -781,9 +781,12 @@ void fill_args(const tm_weights* w, SampleArgs* out, size_t* lds_out) {
     a.ilo = w->ilo;
     a.ihi = w->ihi;
     a.cumW = w->cumW;
+    a.guide = w->guide;
+    a.guide_bits = w->guide_bits;
     const size_t wsz = w->wide ? 16 : 8;
     const size_t cum_bytes = (size_t)(w->q + 1) * wsz;
-    a.cum_in_lds = cum_bytes <= (size_t)kCumLdsBytes;
+    // with a guide a draw reads one or two prefix entries: no staging
+    a.cum_in_lds = !w->guide && cum_bytes <= (size_t)kCumLdsBytes;
     const size_t lds = a.cum_in_lds ? cum_bytes : 0;
     a.W_lo = (u64)w->W;
     a.W_hi = (u64)(w->W >> 64);
@@ -1139,6 +1142,9 @@ int batch_group(tm_weights* const* ws, const std::vector<int>& act, const u64* j
     TM_HIP(hipMemcpyAsync(djc, jcount.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
     TM_TRY(fill_u32(ctr, 16, 0u, st));
     TM_TRY(fill_u32(ovf, 1, 0u, st));
+    size_t root_lds = 0;
+    for (int y = 0; y < na; ++y)
+        if (args[y].cum_in_lds) root_lds = kCumLdsBytes;
     StageTimer t_roots, t_sample, t_reduce;
     t_roots.start(TM_STAGE_ROOTS, st);
     for (int grp = 0; grp < 4; ++grp) {
@@ -1147,10 +1153,10 @@ int batch_group(tm_weights* const* ws, const std::vector<int>& act, const u64* j
         const dim3 grid((unsigned)std::min(blocks, nt));
         const Tile* tl = drt + g_rt_first[grp];
         if (grp >= 2)
-            hipLaunchKernelGGL(batch_root_kernel<u128>, grid, dim3(kBlock), kCumLdsBytes, st, djobs, tl, nt,
+            hipLaunchKernelGGL(batch_root_kernel<u128>, grid, dim3(kBlock), root_lds, st, djobs, tl, nt,
                                ctr + grp, k0, v0, ovf);
         else
-            hipLaunchKernelGGL(batch_root_kernel<u64>, grid, dim3(kBlock), kCumLdsBytes, st, djobs, tl, nt,
+            hipLaunchKernelGGL(batch_root_kernel<u64>, grid, dim3(kBlock), root_lds, st, djobs, tl, nt,
                                ctr + grp, k0, v0, ovf);
         TM_HIP(hipGetLastError());
     }

@@ -116,6 +116,54 @@ __device__ __forceinline__ u128 scale(X128 X, u128 n) {
     return d + (b >> 64) + (c >> 64) + (mid >> 64);
 }
 
+// First index in [lo, hi) with a[idx] > key (hi if none); a fixed number of
+// halving steps with no branch on the data.
+template <typename T>
+__device__ __forceinline__ int32_t upper_bound_bl(const T* a, int32_t lo, int32_t hi, T key) {
+    int32_t n = hi - lo;
+    if (n <= 0) return lo;
+    int32_t b = lo;
+    while (n > 1) {
+        const int32_t h = n >> 1;
+        b = a[b + h] <= key ? b + h : b;
+        n -= h;
+    }
+    return b + (a[b] <= key ? 1 : 0);
+}
+
+// The root pair drawn by r in [0, W): over pairs (interval i, eid e in I_i)
+// in (i, eid) order weighted w_i(center, e), the pair whose cumulative range
+// holds r -- the last interval i with cum[i] <= r, then the last e of I_i
+// with qc[e] - qc[lo_i] <= r - cum[i] (qc: the center's prefix of the
+// interval's parity).  The search looks only at intervals [i0, i1], at eids
+// >= ea in i0 and <= eb in i1 (the range of a guide bucket; full ranges give
+// the plain search).  False on tables that cannot hold r.
+template <typename W>
+__device__ __forceinline__ bool root_pair(const W* cum, const void* const* qc, const int32_t* ilo,
+                                          const int32_t* ihi, int64_t q, W r, int32_t i0, int32_t i1,
+                                          int32_t ea, int32_t eb, int32_t& i_out, int32_t& e_out,
+                                          int32_t* span = nullptr) {
+    const int32_t i = upper_bound_bl<W>(cum, i0, i1 + 1, r) - 1;
+    if (i < 0 || i >= q) return false;
+    const int32_t lo = ilo[i], hi = ihi[i];
+    if (hi <= lo) return false;
+    const W* qq = static_cast<const W*>(qc[i & 1]);
+    const W target = r - cum[i] + qq[lo];
+    int32_t slo = lo, shi = hi;
+    if (i == i0 && ea > slo) slo = ea;
+    if (i == i1 && eb + 1 < shi) shi = eb + 1;
+    if (shi <= slo) {
+        slo = lo;
+        shi = hi;
+    }
+    int32_t e = upper_bound_bl<W>(qq, slo + 1, shi + 1, target) - 1;
+    e = e < lo ? lo : (e >= hi ? hi - 1 : e);
+    i_out = i;
+    e_out = e;
+    if (span) *span = shi - slo;
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // Searches over sorted ranges [lo, hi) of positions (int32 positions).
 // ---------------------------------------------------------------------------

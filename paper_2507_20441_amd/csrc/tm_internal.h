@@ -126,6 +126,11 @@ struct tm_weights {
     int32_t* ilo = nullptr;  // [q] first eid of I_i
     int32_t* ihi = nullptr;  // [q] one past the last eid of I_i
     void* cumW = nullptr;    // [q+1] prefix of W_i
+    // root pairs (interval << 32 | eid) at the draws X = b 2^(128 - guide_bits),
+    // b = 0 .. 2^guide_bits (the last at X = 2^128 - 1): a draw in bucket b
+    // picks a pair between entries b and b + 1
+    u64* guide = nullptr;
+    int guide_bits = 0;
     DevArena arena;
 };
 
@@ -148,6 +153,9 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
 // values, per parity).
 u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide);
 u64 weights_build_extra(int64_t m, bool wide);
+// Bits of the root guide for a graph of m edges: about four (interval, edge)
+// pairs per bucket, between 2^8 and 2^24 buckets.
+int guide_bits_for(int64_t m);
 
 // Exact sums over a range of samples of one job.  Sums over disjoint ranges
 // add up to the sums over their union, whatever the split.

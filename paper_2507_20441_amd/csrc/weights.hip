@@ -29,7 +29,8 @@ struct ChildDesc {
     int dir;      // 0: child is an out-edge of the shared vertex, 1: an in-edge
     int beta;     // -1: child precedes the parent in pi, +1: follows it
     int leaf;
-    int same_as;  // an earlier leaf child with the same side, direction and time side, or -1
+    int copies;   // leaf children with the same side, direction and time side share
+                  // one window: the factor is raised to this power (0: folded into another)
     const void* qt[2];
     const void* qn[2];
 };
@@ -140,22 +141,14 @@ __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
         prodA = static_cast<const W*>(a.in[parA])[p];
         prodB = hasB ? static_cast<const W*>(a.in[parB])[p] : (W)0;
     }
-    W fA[kMaxSlots], fB[kMaxSlots];
     bool ovf = false;
     sfor<0, kMaxSlots>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
         if (c >= a.nc) return;
         const ChildDesc& d = a.c[c];
+        if (d.copies == 0) return;
         W xa = 0, xb = 0;
-        if (d.same_as >= 0) {
-            sfor<0, c>([&](auto kk) {
-                constexpr int k2 = decltype(kk)::value;
-                if (d.same_as == k2) {
-                    xa = fA[k2];
-                    xb = fB[k2];
-                }
-            });
-        } else {
+        {
             const int32_t g = d.side ? v : u;
             const int32_t o = d.side ? u : v;
             // x values (first position with time >= x):
@@ -180,10 +173,10 @@ __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
                 xb = hasB ? window_mass<W>(r.p[0], r.p[2], r.q[0], r.q[2], d.leaf, d.qt[parB], d.qn[parB]) : (W)0;
             }
         }
-        fA[c] = xa;
-        fB[c] = xb;
-        if (!mul_ok(prodA, xa, &prodA)) ovf = true;
-        if (!mul_ok(prodB, xb, &prodB)) ovf = true;
+        for (int r = 0; r < d.copies; ++r) {
+            if (!mul_ok(prodA, xa, &prodA)) ovf = true;
+            if (!mul_ok(prodB, xb, &prodB)) ovf = true;
+        }
     });
     const int64_t at = a.out_by_pos ? (int64_t)G.tpos[1][e] : (int64_t)e;
     static_cast<W*>(a.out[parA])[at] = prodA;
@@ -227,10 +220,41 @@ struct IntervalWeight {
     }
 };
 
+// Guide entry b: the root pair of the draw X = b 2^(128 - gb) (X = 2^128 - 1
+// for the last), found by the plain search; W is read from the table.
+template <typename W>
+__global__ void __launch_bounds__(kBlock)
+guide_kernel(const W* cum, const void* qc0, const void* qc1, const int32_t* ilo, const int32_t* ihi, int64_t q,
+             int gb, u64* guide) {
+    const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t B = (int64_t)1 << gb;
+    if (b > B) return;
+    const W Wt = cum[q];
+    if (Wt == 0) {
+        guide[b] = 0;
+        return;
+    }
+    X128 X;
+    if (b == B) {
+        X.lo = ~0ull;
+        X.hi = ~0ull;
+    } else {
+        X.lo = 0;
+        X.hi = (u64)b << (64 - gb);
+    }
+    const W r = scale(X, Wt);
+    const void* qc[2] = {qc0, qc1};
+    int32_t i = 0, e = 0;
+    if (!root_pair<W>(cum, qc, ilo, ihi, q, r, 0, (int32_t)q - 1, -1, 0x7fffffff, i, e)) i = e = 0;
+    guide[b] = ((u64)(uint32_t)i << 32) | (uint32_t)e;
+}
+
 unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// check_each_level: read the overflow flag after every level and stop at the
+// first overflow (the synchronous build, which then restarts in 128 bits).
 template <typename W>
-int build_typed(tm_weights* w, hipStream_t st, int* ovf) {
+int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level = false) {
     tm_graph* g = w->g;
     const HostPlan& P = w->plan;
     const int64_t m = g->m;
@@ -271,11 +295,12 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf) {
                     d.dir = P.alpha[c] > 0 ? 0 : 1;
                     d.beta = P.beta[c];
                     d.leaf = P.n_children[c] == 0;
-                    d.same_as = -1;
+                    d.copies = 1;
                     for (int j2 = 0; j2 < j && d.leaf; ++j2) {
-                        const ChildDesc& e2 = a.c[j2];
-                        if (e2.leaf && e2.same_as < 0 && e2.dir == d.dir && e2.beta == d.beta) {
-                            d.same_as = j2;
+                        ChildDesc& e2 = a.c[j2];
+                        if (e2.leaf && e2.copies > 0 && e2.dir == d.dir && e2.beta == d.beta) {
+                            ++e2.copies;
+                            d.copies = 0;
                             break;
                         }
                     }
@@ -296,6 +321,12 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf) {
             }
             if (two)
                 for (int par = 0; par < 2; ++par) TM_HIP(dev_free(tmp[par], st));
+            if (check_each_level && sizeof(W) == 8) {
+                int h_ovf = 0;
+                TM_HIP(hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, st));
+                TM_HIP(sync_stream(st));
+                if (h_ovf) return TM_OK;  // the caller sees the flag and widens
+            }
             // prefix sums along the lists the parent searches
             if (s != 0) {
                 const int dir = P.alpha[s] > 0 ? 0 : 1;
@@ -337,6 +368,13 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf) {
                           w->ihi},
         w->q, cum, ovf, st));
     w->cumW = cum;
+    // the root guide
+    w->guide_bits = guide_bits_for(m);
+    const int64_t nb = ((int64_t)1 << w->guide_bits) + 1;
+    TM_TRY(arena_alloc(w->arena, &w->guide, (size_t)nb));
+    hipLaunchKernelGGL((guide_kernel<W>), dim3(grid_for(nb)), dim3(kBlock), 0, st, (const W*)cum, w->qc[0],
+                       w->qc[1], w->ilo, w->ihi, w->q, w->guide_bits, w->guide);
+    TM_HIP(hipGetLastError());
     return TM_OK;
 }
 
@@ -351,6 +389,7 @@ void clear_tables(tm_weights* w) {
     std::memset(w->qc, 0, sizeof w->qc);
     w->ilo = w->ihi = nullptr;
     w->cumW = nullptr;
+    w->guide = nullptr;
 }
 
 }  // namespace
@@ -375,12 +414,14 @@ int weights_build(tm_weights* w, hipStream_t st) {
         clear_tables(w);
         TM_TRY(fill_u32(ovf, 1, 0u, st));
         w->wide = wide != 0;
-        rc = wide ? build_typed<u128>(w, st, ovf) : build_typed<u64>(w, st, ovf);
+        rc = wide ? build_typed<u128>(w, st, ovf) : build_typed<u64>(w, st, ovf, true);
         if (rc != TM_OK) break;
         u64 hW[2] = {0, 0};
         TM_HIP(hipMemcpyAsync(&h, ovf, sizeof(int), hipMemcpyDeviceToHost, st));
-        TM_HIP(hipMemcpyAsync(hW, static_cast<const unsigned char*>(w->cumW) + w->q * (wide ? 16 : 8),
-                              wide ? 16 : 8, hipMemcpyDeviceToHost, st));
+        // a 64-bit build that stopped at an overflowing level has no W yet
+        if (w->cumW)
+            TM_HIP(hipMemcpyAsync(hW, static_cast<const unsigned char*>(w->cumW) + w->q * (wide ? 16 : 8),
+                                  wide ? 16 : 8, hipMemcpyDeviceToHost, st));
         TM_HIP(sync_stream(st));
         w->W = ((u128)hW[1] << 64) | hW[0];
         if (h == 0) break;
@@ -403,7 +444,15 @@ u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide) {
         if (P.n_children[s] > 0) b += 4 * blk((u64)(m + 1) * wsz);  // qt and qn, per parity
     b += 2 * blk((u64)(m + 1) * wsz);                   // qc, per parity
     b += 2 * blk((u64)q * 4) + blk((u64)(q + 1) * wsz); // ilo, ihi, cumW
+    b += blk((((u64)1 << guide_bits_for(m)) + 1) * 8);  // root guide
     return b;
+}
+
+int guide_bits_for(int64_t m) {
+    int b = 0;
+    while (b < 62 && ((int64_t)1 << (b + 1)) <= m) ++b;  // floor(log2 m)
+    b -= 1;                                                // ~2m pairs, ~4 per bucket
+    return b < 8 ? 8 : (b > 24 ? 24 : b);
 }
 
 u64 weights_build_extra(int64_t m, bool wide) {
