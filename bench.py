@@ -59,6 +59,9 @@ def parse():
                          "(graph, motif, delta) set the stream uses is built first)")
     ap.add_argument("--serve-check", type=int, default=12,
                     help="served queries re-run alone with tm_estimate and compared")
+    ap.add_argument("--traffic-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the traffic file (--traffic) from two rocprofv3 --pmc runs of this "
+                         "bench with --copy-calibration: FETCH_SIZE, then WRITE_SIZE")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "sample_kernel_medium_traffic.json"),
                     help="HBM bytes per launch from rocprofv3 counters (JSON), if present")
     return ap.parse_args()
@@ -72,6 +75,9 @@ def main():
               "this build has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
+    if args.traffic_summarize:
+        return summarize_traffic(args.traffic_summarize[0], args.traffic_summarize[1], args.traffic,
+                                 args.copy_calibration or (1 << 30))
     if args.workload == "batched":
         return batched(args)
     if args.workload == "serving":
@@ -489,6 +495,74 @@ def weights_only(args):
     print(json.dumps({"workload": f"weights on the {args.weights_graph} graph (m={g.m})", "builds": rows}),
           flush=True)
     g.close()
+
+
+TRAFFIC_KERNELS = {
+    "sample_kernel": "sample_kernel<unsigned long long, false, false, true>",
+    "root_kernel": "root_kernel<unsigned long long>",
+    "level_kernel": "level_kernel<unsigned long long>",
+}
+
+
+def summarize_traffic(fetch_dir, write_dir, out_path, calib_bytes):
+    """HBM bytes per launch of the main kernels from rocprofv3 counter CSVs:
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the same
+    counter reads for a device copy of calib_bytes in the same run."""
+    import csv
+    import glob
+    import statistics
+
+    def rows(d):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        assert f, f"no counter file under {d}"
+        return list(csv.DictReader(open(f[0])))
+
+    def per_kernel(rs):
+        out = {}
+        for r in rs:
+            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return out
+
+    fk, wk = per_kernel(rows(fetch_dir)), per_kernel(rows(write_dir))
+    copy = [n for n in fk if "copyBuffer" in n]
+    assert copy, "no copy kernel: run the bench with --copy-calibration"
+    # the calibration copies are the large ones (the library's own small
+    # device copies run the same kernel)
+    f_cal = statistics.median([v for v in fk[copy[0]] if v >= 0.5 * max(fk[copy[0]])])
+    w_cal = statistics.median([v for v in wk[copy[0]] if v >= 0.5 * max(wk[copy[0]])])
+    f_scale = calib_bytes / 1024.0 / f_cal
+    w_scale = calib_bytes / 1024.0 / w_cal
+    kernels = {}
+    for key, pat in TRAFFIC_KERNELS.items():
+        fn = [n for n in fk if pat in n]
+        wn = [n for n in wk if pat in n]
+        if not fn or not wn:
+            continue
+        fv, wv = fk[fn[0]], wk[wn[0]]
+        fb = statistics.mean(fv) * 1024 * f_scale
+        wb = statistics.mean(wv) * 1024 * w_scale
+        kernels[key] = dict(name=fn[0].split("(")[0] if "(anonymous" not in fn[0] else pat,
+                            launches=len(fv), fetch_kib_per_launch=fv, write_kib_per_launch=wv,
+                            fetch_bytes_per_launch=round(fb), write_bytes_per_launch=round(wb),
+                            hbm_bytes_per_launch=round(fb + wb))
+    doc = {
+        "workload": "medium (bench.py defaults, one step)",
+        "source_sha": kernel_source_sha(),
+        "copy_calibration": {"bytes": calib_bytes, "fetch_kib": f_cal, "write_kib": w_cal,
+                             "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4)},
+        "kernels": kernels,
+        "hbm_bytes_per_launch": kernels.get("sample_kernel", {}).get("hbm_bytes_per_launch"),
+        "commands": [
+            "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d <fetch> -o fetch "
+            "-- python3 <repo>/bench.py --steps 1 --warmup 0 --cpu-samples 0 --copy-calibration 1073741824",
+            "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d <write> -o write "
+            "-- python3 <repo>/bench.py --steps 1 --warmup 0 --cpu-samples 0 --copy-calibration 1073741824",
+            "python3 bench.py --traffic-summarize <fetch> <write>",
+        ],
+    }
+    with open(out_path, "w") as f:
+        json.dump(doc, f, indent=1)
+    print(json.dumps({k: v["hbm_bytes_per_launch"] for k, v in kernels.items()}))
 
 
 def kernel_source_sha():

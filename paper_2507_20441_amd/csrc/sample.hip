@@ -44,6 +44,7 @@ struct SampleArgs {
     const void* cumW;
     const u64* guide;  // root pairs at 2^guide_bits + 1 evenly spaced draws (see weights)
     int guide_bits;
+    const void* ioff;  // per interval: cum[i] - qc[lo_i]
     int cum_in_lds;  // the q+1 interval prefix fits the block's LDS
     u64 W_lo, W_hi;
     int n_free;
@@ -374,8 +375,12 @@ __device__ __forceinline__ bool draw_root(const SampleArgs& a, const W* cum, W W
         eb = (int32_t)(uint32_t)g1;
     }
     int32_t span = 0;
-    const bool ok = root_pair<W>(cum, a.qc, a.ilo, a.ihi, a.q, r0, i0, i1, ea, eb, i, e0, &span);
-    if (nb) *nb += (a.guide ? 16 : 0) + (probes(i1 - i0 + 1) + 2 + probes(span)) * sizeof(W) + 8;
+    const bool ok = root_pair<W>(cum, a.qc, a.ilo, a.ihi, a.q, r0, i0, i1, ea, eb, i, e0, &span,
+                                 static_cast<const W*>(a.ioff));
+    if (nb) {
+        if (a.ioff && i0 == i1) *nb += 16 + (1 + probes(span)) * sizeof(W);
+        else *nb += (a.guide ? 16 : 0) + (probes(i1 - i0 + 1) + 2 + probes(span)) * sizeof(W) + 8;
+    }
     return ok;
 }
 
@@ -783,6 +788,7 @@ void fill_args(const tm_weights* w, SampleArgs* out, size_t* lds_out) {
     a.cumW = w->cumW;
     a.guide = w->guide;
     a.guide_bits = w->guide_bits;
+    a.ioff = w->ioff;
     const size_t wsz = w->wide ? 16 : 8;
     const size_t cum_bytes = (size_t)(w->q + 1) * wsz;
     // with a guide a draw reads one or two prefix entries: no staging

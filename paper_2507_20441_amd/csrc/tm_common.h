@@ -138,11 +138,26 @@ __device__ __forceinline__ int32_t upper_bound_bl(const T* a, int32_t lo, int32_
 // interval's parity).  The search looks only at intervals [i0, i1], at eids
 // >= ea in i0 and <= eb in i1 (the range of a guide bucket; full ranges give
 // the plain search).  False on tables that cannot hold r.
+//
+// ioff (optional): per interval, cum[i] - qc[lo_i] (mod 2^bits).  With a
+// guide range inside one interval (i0 == i1, lo_i <= ea <= eb < hi_i), the
+// pair is found from ioff[i0] and the eids [ea, eb] alone: r - ioff[i] is
+// the target of the eid search, and the range already lies in the interval.
 template <typename W>
 __device__ __forceinline__ bool root_pair(const W* cum, const void* const* qc, const int32_t* ilo,
                                           const int32_t* ihi, int64_t q, W r, int32_t i0, int32_t i1,
                                           int32_t ea, int32_t eb, int32_t& i_out, int32_t& e_out,
-                                          int32_t* span = nullptr) {
+                                          int32_t* span = nullptr, const W* ioff = nullptr) {
+    if (ioff && i0 == i1 && i0 >= 0 && i0 < q && ea >= 0 && eb >= ea) {
+        const W* qq = static_cast<const W*>(qc[i0 & 1]);
+        const W target = r - ioff[i0];
+        int32_t e = upper_bound_bl<W>(qq, ea + 1, eb + 2, target) - 1;
+        e = e < ea ? ea : (e > eb ? eb : e);
+        i_out = i0;
+        e_out = e;
+        if (span) *span = eb - ea + 1;
+        return true;
+    }
     const int32_t i = upper_bound_bl<W>(cum, i0, i1 + 1, r) - 1;
     if (i < 0 || i >= q) return false;
     const int32_t lo = ilo[i], hi = ihi[i];

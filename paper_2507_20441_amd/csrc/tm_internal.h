@@ -131,6 +131,7 @@ struct tm_weights {
     // picks a pair between entries b and b + 1
     u64* guide = nullptr;
     int guide_bits = 0;
+    void* ioff = nullptr;    // [q] cum[i] - qc[lo_i] of the interval's parity
     DevArena arena;
 };
 

@@ -249,6 +249,16 @@ guide_kernel(const W* cum, const void* qc0, const void* qc1, const int32_t* ilo,
     guide[b] = ((u64)(uint32_t)i << 32) | (uint32_t)e;
 }
 
+// ioff[i] = cum[i] - qc_{i mod 2}[lo_i], modulo the word size.
+template <typename W>
+__global__ void __launch_bounds__(kBlock)
+ioff_kernel(const W* cum, const W* qc0, const W* qc1, const int32_t* ilo, int64_t q, W* ioff) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= q) return;
+    const W* qq = (i & 1) ? qc1 : qc0;
+    ioff[i] = cum[i] - qq[ilo[i]];
+}
+
 unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 // check_each_level: read the overflow flag after every level and stop at the
@@ -368,7 +378,13 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
                           w->ihi},
         w->q, cum, ovf, st));
     w->cumW = cum;
-    // the root guide
+    // per-interval offsets and the root guide
+    W* ioff;
+    TM_TRY(arena_alloc(w->arena, &ioff, (size_t)w->q));
+    hipLaunchKernelGGL((ioff_kernel<W>), dim3(grid_for(w->q)), dim3(kBlock), 0, st, (const W*)cum,
+                       (const W*)w->qc[0], (const W*)w->qc[1], (const int32_t*)w->ilo, w->q, ioff);
+    TM_HIP(hipGetLastError());
+    w->ioff = ioff;
     w->guide_bits = guide_bits_for(m);
     const int64_t nb = ((int64_t)1 << w->guide_bits) + 1;
     TM_TRY(arena_alloc(w->arena, &w->guide, (size_t)nb));
@@ -390,6 +406,7 @@ void clear_tables(tm_weights* w) {
     w->ilo = w->ihi = nullptr;
     w->cumW = nullptr;
     w->guide = nullptr;
+    w->ioff = nullptr;
 }
 
 }  // namespace
@@ -444,6 +461,7 @@ u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide) {
         if (P.n_children[s] > 0) b += 4 * blk((u64)(m + 1) * wsz);  // qt and qn, per parity
     b += 2 * blk((u64)(m + 1) * wsz);                   // qc, per parity
     b += 2 * blk((u64)q * 4) + blk((u64)(q + 1) * wsz); // ilo, ihi, cumW
+    b += blk((u64)q * wsz);                              // ioff
     b += blk((((u64)1 << guide_bits_for(m)) + 1) * 8);  // root guide
     return b;
 }
