@@ -225,7 +225,9 @@ def batched(args):
     """64 estimation jobs of uneven graph size, motif, delta and budget, from
     resident graphs: one launch per job (tm_estimate each, the job's whole
     weights -> samples -> reduction) against one batched pass
-    (tm_estimate_batch) with the autotuned schedule.  Same results required."""
+    (tm_estimate_batch) with the autotuned schedule, and against the same
+    pipeline recorded once into a HIP graph and replayed (tm_batch_plan_run,
+    the reported value).  Same results required."""
     import torch
 
     from paper_2507_20441_amd import autotune
@@ -258,13 +260,22 @@ def batched(args):
     for w in ws:
         w.close()
     log(f"schedule {choice}; timings ms {times}")
+    log("recording the pipeline into a graph")
+    t0 = time.perf_counter()
+    plan = T.BatchPlan(graphs, motifs, ks, seeds)
+    record_ms = (time.perf_counter() - t0) * 1e3
     for _ in range(max(1, args.warmup)):
         ref = per_job()
         got = batch()
-    same = all(a.acc2.value == b.acc2.value and a.n_valid == b.n_valid and a.estimate == b.estimate
-               for a, b in zip(ref, got))
-    assert same, "batched results differ from one-job-per-launch results"
-    t_job, t_batch = [], []
+        rep = plan.run()
+
+    def same_all(xs, ys):
+        return all(a.acc2.value == b.acc2.value and a.n_valid == b.n_valid and a.estimate == b.estimate
+                   for a, b in zip(xs, ys))
+
+    same = same_all(ref, got) and same_all(ref, rep)
+    assert same, "batched or replayed results differ from one-job-per-launch results"
+    t_job, t_batch, t_graph = [], [], []
     for _ in range(args.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -275,17 +286,23 @@ def batched(args):
         batch()
         torch.cuda.synchronize()
         t_batch.append(time.perf_counter() - t0)
-    tj, tb = min(t_job), min(t_batch)
+        t0 = time.perf_counter()
+        rep = plan.run()
+        torch.cuda.synchronize()
+        t_graph.append(time.perf_counter() - t0)
+        assert same_all(ref, rep), "a replay differs"
+    plan.close()
+    tj, tb, tgr = min(t_job), min(t_batch), min(t_graph)
     wide = sum(1 for r in got if r.flags & T.TM_F_WIDE)
     rel = [1.96 * r.std_error / r.estimate for r in got if r.estimate > 0]
     line = {
         "metric": "samples/s at <=5% rel. err; batched-queue vs one-job-per-launch; p99 latency",
-        "value": round(total / tb, 1),
+        "value": round(total / tgr, 1),
         "unit": "samples/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(tb * 1e3, 3),
+        "ms_per_step": round(tgr * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -300,7 +317,10 @@ def batched(args):
         "one_job_per_launch": {"ms": round(tj * 1e3, 3), "samples_per_s": round(total / tj, 1)},
         "batched": {"ms": round(tb * 1e3, 3), "samples_per_s": round(total / tb, 1),
                     "schedule": {"tile": choice[0], "blocks": choice[1]}},
-        "speedup": round(tj / tb, 3),
+        "graph_replay": {"ms": round(tgr * 1e3, 3), "samples_per_s": round(total / tgr, 1),
+                         "record_ms": round(record_ms, 1)},
+        "speedup": round(tj / tgr, 3),
+        "speedup_eager_batch": round(tj / tb, 3),
         "bit_identical": same,
         "jobs_128bit": wide,
         "rel_ci95_max": max(rel) if rel else None,

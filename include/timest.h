@@ -232,6 +232,26 @@ int tm_estimate_batch(tm_graph* const* g, const tm_motif* mo, const tm_tree* con
                       const uint64_t* k, const uint64_t* seed, int n_jobs, void* stream,
                       tm_result* out);
 
+/* A batch plan: the 64-bit pipeline of a fixed set of jobs -- every weight
+ * build, the root draws, the sort, the sampling and the per-job reductions --
+ * recorded once into a HIP graph on streams of the plan's own (the weight
+ * builds on four parallel branches, balanced by edge count, joined before
+ * the batched pass) and replayed by tm_batch_plan_run with no host work
+ * between the stages.  Jobs whose
+ * weights need 128 bits draw nothing in the graph and are re-run by
+ * tm_estimate after each replay.  The graphs must stay alive and unchanged;
+ * tr and its entries may be NULL (default trees).  Results equal
+ * tm_estimate's per job.  Errors: TM_EINVAL (as tm_estimate_batch, or a job
+ * of 2^32 samples or more), TM_ERANGE, TM_ENOMEM, TM_EDEVICE (recording). */
+typedef struct tm_batch_plan tm_batch_plan;
+int tm_batch_plan_create(tm_graph* const* g, const tm_motif* mo, const tm_tree* const* tr,
+                         const uint64_t* k, const uint64_t* seed, int n_jobs, void* stream,
+                         tm_batch_plan** out);
+/* Replay on `stream` and write one result per job; synchronises the stream.
+ * Replays may not overlap (they share the plan's buffers). */
+int tm_batch_plan_run(tm_batch_plan* p, void* stream, tm_result* out);
+void tm_batch_plan_destroy(tm_batch_plan* p);
+
 /* Schedule of the batched kernels: samples per tile (>= 256) and the grid of
  * the persistent kernels (0 = 8 workgroups per compute unit).  Process-wide;
  * the autotuner in the Python package searches these.  Returns the previous

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -24,7 +25,12 @@ static std::mutex g_prof_mu;
 static bool g_prof_on = false;
 static tm_profile g_prof = {};
 
+static thread_local bool t_prof_suspended = false;
+
+void prof_suspend(bool on) { t_prof_suspended = on; }
+
 bool prof_enabled() {
+    if (t_prof_suspended) return false;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     return g_prof_on;
 }
@@ -712,3 +718,195 @@ extern "C" int tm_estimate_batch(tm_graph* const* g, const tm_motif* mo, const t
     for (tm_weights* w : ws) tm_weights_destroy(w);
     return rc;
 }
+
+// ---------------------------------------------------------------------------
+// Batch plans: the 64-bit pipeline of a fixed job set recorded into a graph.
+// ---------------------------------------------------------------------------
+struct tm_batch_plan {
+    int n = 0;
+    std::vector<tm_graph*> g;
+    std::vector<tm_motif> mo;
+    std::vector<tm_tree> tr;
+    std::vector<u64> k, seed;
+    std::vector<tm_weights*> ws;
+    int* flags = nullptr;  // per job: its 64-bit build overflowed
+    u64* wdev = nullptr;   // per job: W (64-bit)
+    CapturedPass* pass = nullptr;
+    std::vector<std::pair<void*, hipStream_t>> kept;  // temporaries the graph reuses
+    hipStream_t cs = nullptr;                         // the stream recorded on
+    hipStream_t br[4] = {};                           // branches for the weight builds
+    hipEvent_t ev[5] = {};                            // fork and joins
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static void plan_release(tm_batch_plan* p) {
+    if (!p) return;
+    if (p->cs) (void)sync_stream(p->cs);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    (void)hipDeviceSynchronize();
+    if (p->pass) batch_capture_free(p->pass, p->cs);
+    for (tm_weights* w : p->ws) tm_weights_destroy(w);
+    for (auto& b : p->kept) (void)dev_free(b.first, b.second);
+    (void)dev_free(p->flags, p->cs);
+    (void)dev_free(p->wdev, p->cs);
+    for (hipStream_t b : p->br)
+        if (b) {
+            (void)sync_stream(b);
+            (void)hipStreamDestroy(b);
+        }
+    for (hipEvent_t e : p->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (p->cs) {
+        (void)sync_stream(p->cs);
+        (void)hipStreamDestroy(p->cs);
+    }
+    delete p;
+}
+
+extern "C" int tm_batch_plan_create(tm_graph* const* g, const tm_motif* mo, const tm_tree* const* tr,
+                                    const uint64_t* k, const uint64_t* seed, int n_jobs, void* stream,
+                                    tm_batch_plan** out) {
+    (void)stream;
+    if (!out || n_jobs < 1 || !g || !mo || !k || !seed) return tm_fail(TM_EINVAL, "batch_plan: bad arguments");
+    std::unique_ptr<tm_batch_plan> P(new (std::nothrow) tm_batch_plan());
+    if (!P) return tm_fail(TM_ENOMEM, "batch_plan: host allocation");
+    P->n = n_jobs;
+    std::vector<HostPlan> plans(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) {
+        if (!g[i]) return tm_fail(TM_EINVAL, "batch_plan: job %d has no graph", i);
+        TM_TRY(motif_check(&mo[i]));
+        tm_tree t;
+        if (tr && tr[i]) t = *tr[i];
+        else TM_TRY(tm_default_tree(&mo[i], &t));
+        TM_TRY(plan_build(&mo[i], &t, &plans[i]));
+        if (g[i]->m > 0 && g[i]->T / mo[i].delta + 1 >= ((int64_t)1 << 31))
+            return tm_fail(TM_ERANGE, "batch_plan: job %d has too many intervals", i);
+        P->g.push_back(g[i]);
+        P->mo.push_back(mo[i]);
+        P->tr.push_back(t);
+        P->k.push_back(k[i]);
+        P->seed.push_back(seed[i]);
+    }
+    TM_HIP(hipStreamCreateWithFlags(&P->cs, hipStreamNonBlocking));
+    tm_batch_plan* raw = P.release();
+    auto fail = [&](int rc) {
+        plan_release(raw);
+        return rc;
+    };
+    for (hipStream_t& b : raw->br)
+        if (hipStreamCreateWithFlags(&b, hipStreamNonBlocking) != hipSuccess)
+            return fail(tm_fail(TM_EDEVICE, "batch_plan: cannot create a stream"));
+    for (hipEvent_t& e : raw->ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return fail(tm_fail(TM_EDEVICE, "batch_plan: cannot create an event"));
+    if (dev_alloc((void**)&raw->flags, n_jobs * sizeof(int), raw->cs) != hipSuccess ||
+        dev_alloc((void**)&raw->wdev, n_jobs * sizeof(u64), raw->cs) != hipSuccess)
+        return fail(tm_fail(TM_ENOMEM, "batch_plan: device allocation"));
+    // weight builds go round-robin to the branches, largest graphs first
+    constexpr int kBranches = 4;
+    std::vector<int> order(n_jobs), branch(n_jobs, 0);
+    for (int i = 0; i < n_jobs; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return raw->g[a]->m > raw->g[b]->m; });
+    {
+        int64_t load[kBranches] = {};
+        for (int i : order) {
+            int b = 0;
+            for (int x = 1; x < kBranches; ++x)
+                if (load[x] < load[b]) b = x;
+            branch[i] = b;
+            load[b] += raw->g[i]->m;
+        }
+    }
+    raw->ws.assign(n_jobs, nullptr);
+    for (int i = 0; i < n_jobs; ++i) {
+        tm_weights* w = new (std::nothrow) tm_weights();
+        if (!w) return fail(tm_fail(TM_ENOMEM, "batch_plan: host allocation"));
+        w->g = raw->g[i];
+        w->arena.stream = raw->br[branch[i]];
+        w->plan = plans[i];
+        raw->ws[i] = w;
+    }
+    // record: every 64-bit weight build, W of each job, the batched pass
+    int rc = TM_OK;
+    dev_defer_begin(&raw->kept);
+    prof_suspend(true);
+    hipError_t e = hipStreamBeginCapture(raw->cs, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) rc = tm_fail(TM_EDEVICE, "batch_plan: begin capture: %s", hipGetErrorString(e));
+    if (rc == TM_OK) rc = fill_u32(raw->flags, n_jobs, 0u, raw->cs);
+    if (rc == TM_OK) rc = fill_u32(raw->wdev, 2 * n_jobs, 0u, raw->cs);
+    // fork: the branches start after the clears; join before the pass
+    if (rc == TM_OK && hipEventRecord(raw->ev[0], raw->cs) != hipSuccess)
+        rc = tm_fail(TM_EDEVICE, "batch_plan: fork");
+    for (int b = 0; b < kBranches && rc == TM_OK; ++b)
+        if (hipStreamWaitEvent(raw->br[b], raw->ev[0], 0) != hipSuccess) rc = tm_fail(TM_EDEVICE, "batch_plan: fork");
+    for (int i : order) {
+        if (rc != TM_OK) break;
+        tm_weights* w = raw->ws[i];
+        hipStream_t bs = raw->br[branch[i]];
+        rc = weights_enqueue(w, bs, raw->flags + i);
+        if (rc == TM_OK && w->q > 0 && w->cumW) {
+            e = hipMemcpyAsync(raw->wdev + i, static_cast<const unsigned char*>(w->cumW) + w->q * 8, 8,
+                               hipMemcpyDeviceToDevice, bs);
+            if (e != hipSuccess) rc = tm_fail(TM_EDEVICE, "batch_plan: copy: %s", hipGetErrorString(e));
+        }
+    }
+    for (int b = 0; b < kBranches && rc == TM_OK; ++b)
+        if (hipEventRecord(raw->ev[1 + b], raw->br[b]) != hipSuccess ||
+            hipStreamWaitEvent(raw->cs, raw->ev[1 + b], 0) != hipSuccess)
+            rc = tm_fail(TM_EDEVICE, "batch_plan: join");
+    if (rc == TM_OK) {
+        std::vector<const int*> wf(n_jobs);
+        for (int i = 0; i < n_jobs; ++i) wf[i] = raw->flags + i;
+        rc = batch_capture_enqueue(raw->ws.data(), wf.data(), raw->k.data(), raw->seed.data(), n_jobs, raw->cs,
+                                   batch_config_now(), &raw->pass);
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(raw->cs, &graph);
+    prof_suspend(false);
+    dev_defer_end();
+    raw->graph = graph;
+    if (rc == TM_OK && e != hipSuccess) rc = tm_fail(TM_EDEVICE, "batch_plan: end capture: %s", hipGetErrorString(e));
+    if (rc == TM_OK) {
+        e = hipGraphInstantiate(&raw->exec, raw->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = tm_fail(TM_EDEVICE, "batch_plan: instantiate: %s", hipGetErrorString(e));
+    }
+    if (rc != TM_OK) {
+        (void)hipGetLastError();
+        return fail(rc);
+    }
+    *out = raw;
+    return TM_OK;
+}
+
+extern "C" int tm_batch_plan_run(tm_batch_plan* p, void* stream, tm_result* out) {
+    if (!p || !out) return tm_fail(TM_EINVAL, "batch_plan_run: NULL argument");
+    hipStream_t st = as_stream(stream);
+    TM_HIP(hipGraphLaunch(p->exec, st));
+    std::vector<int> hflags(p->n);
+    std::vector<u64> hW(p->n);
+    TM_HIP(hipMemcpyAsync(hflags.data(), p->flags, p->n * sizeof(int), hipMemcpyDeviceToHost, st));
+    TM_HIP(hipMemcpyAsync(hW.data(), p->wdev, p->n * sizeof(u64), hipMemcpyDeviceToHost, st));
+    std::vector<JobSums> sums(p->n);
+    TM_TRY(batch_capture_read(p->pass, st, sums.data()));
+    for (int i = 0; i < p->n; ++i) {
+        tm_result& o = out[i];
+        if (hflags[i]) {
+            // 64 bits do not hold this job's weights: the 128-bit path, eagerly
+            TM_TRY(tm_estimate(p->g[i], &p->mo[i], &p->tr[i], p->k[i], p->seed[i], stream, &o));
+            continue;
+        }
+        std::memset(&o, 0, sizeof o);
+        o.k = p->k[i];
+        o.q = p->ws[i]->q;
+        o.W.lo = hW[i];
+        o.W.hi = 0;
+        if (hW[i] == 0) o.flags |= TM_F_W_ZERO;
+        sums_to_result(sums[i], &o);
+        if (o.status == TM_OK) finish_result(&o);
+    }
+    return TM_OK;
+}
+
+extern "C" void tm_batch_plan_destroy(tm_batch_plan* p) { plan_release(p); }

@@ -98,8 +98,19 @@ void dev_cache_trim() {
     for (const Block& b : drop) (void)hipFree(b.p);
 }
 
+// While a capture is being recorded on this thread, released blocks are kept
+// by the capture's owner: the recorded work reuses them at every replay.
+static thread_local std::vector<std::pair<void*, hipStream_t>>* t_defer = nullptr;
+
+void dev_defer_begin(std::vector<std::pair<void*, hipStream_t>>* keep) { t_defer = keep; }
+void dev_defer_end() { t_defer = nullptr; }
+
 hipError_t dev_free(void* p, hipStream_t st) {
     if (!p) return hipSuccess;
+    if (t_defer) {
+        t_defer->push_back({p, st});
+        return hipSuccess;
+    }
     const int dev = device_index();
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_used.find(p);

@@ -19,6 +19,7 @@
 // delta, take a separate kernel variant with the general chain counter.
 #include <algorithm>
 #include <cstring>
+#include <memory>
 #include <type_traits>
 
 #include "tm_primitives.h"
@@ -45,6 +46,10 @@ struct SampleArgs {
     const u64* guide;  // root pairs at 2^guide_bits + 1 evenly spaced draws (see weights)
     int guide_bits;
     const void* ioff;  // per interval: cum[i] - qc[lo_i]
+    // captured passes: W read from the job's table, and the job skipped when
+    // its 64-bit weight build overflowed (wflag set) or W = 0
+    const void* Wdev;
+    const int* wflag;
     int cum_in_lds;  // the q+1 interval prefix fits the block's LDS
     u64 W_lo, W_hi;
     int n_free;
@@ -843,6 +848,15 @@ batch_root_kernel(const SampleArgs* jobs, const Tile* tiles, int n_tiles, int* c
         if (t >= n_tiles) break;
         const Tile T = tiles[t];
         const SampleArgs& a = jobs[T.job];
+        const W Wtot = a.Wdev ? *static_cast<const W*>(a.Wdev) : (W)(((u128)a.W_hi << 64) | a.W_lo);
+        if ((a.wflag && *a.wflag != 0) || Wtot == 0) {
+            // a skipped job keeps valid keys; its samples are not drawn
+            for (u64 r = T.begin + threadIdx.x; r < T.end; r += kBlock) {
+                keys[T.out + r] = a.key_base;
+                vals[T.out + r] = (uint32_t)r;
+            }
+            continue;
+        }
         const W* cumG = static_cast<const W*>(a.cumW);
         const int32_t ncum = (int32_t)a.q + 1;
         W* cumL = reinterpret_cast<W*>(lds_raw);
@@ -851,7 +865,6 @@ batch_root_kernel(const SampleArgs* jobs, const Tile* tiles, int n_tiles, int* c
             __syncthreads();
         }
         const W* cum = a.cum_in_lds ? cumL : cumG;
-        const W Wtot = (W)(((u128)a.W_hi << 64) | a.W_lo);
         for (u64 r = T.begin + threadIdx.x; r < T.end; r += kBlock) {
             keys[T.out + r] = a.key_base + root_key<W>(a, cum, Wtot, ncum, r, bad);
             vals[T.out + r] = (uint32_t)r;
@@ -872,9 +885,11 @@ batch_sample_kernel(const SampleArgs* jobs, const Tile* tiles, int n_tiles, int*
         const int t = s_tile;
         if (t >= n_tiles) break;
         const Tile T = tiles[t];
+        const SampleArgs& a = jobs[T.job];
         LaneAcc L = lane_zero();
-        sample_positions<W, false, kGeneral, true>(jobs[T.job], nullptr, T.begin + threadIdx.x, T.end,
-                                                   kBlock, L);
+        const bool skip = (a.wflag && *a.wflag != 0) || (a.Wdev && *static_cast<const W*>(a.Wdev) == 0);
+        if (!skip)
+            sample_positions<W, false, kGeneral, true>(a, nullptr, T.begin + threadIdx.x, T.end, kBlock, L);
         lanes_reduce(L, &tile_parts[t], ovf);
     }
 }
@@ -1059,17 +1074,39 @@ namespace {
 
 // One batched pass over jobs whose root-key ranges and sample offsets all fit
 // 32 bits together: job y's keys are key_base[y] + (its root key < 2 m_y).
-int batch_group(tm_weights* const* ws, const std::vector<int>& act, const u64* j0s, const u64* counts,
-                const u64* seeds, hipStream_t st, JobSums* out, const BatchConfig& cfg) {
+// One batched pass over jobs act: host arrays, device buffers, launches.
+struct Group {
+    int na = 0;
+    u64 total = 0;
+    int key_bits = 1, passes = 1, blocks = 0;
+    size_t root_lds = 0;
+    std::vector<SampleArgs> args;
+    std::vector<Tile> rt, stt;
+    std::vector<int> g_rt_first, g_st_first, jfirst, jcount;
+    SampleArgs* djobs = nullptr;
+    Tile *drt = nullptr, *dst = nullptr;
+    uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
+    Partial *tparts = nullptr, *jparts = nullptr;
+    int *ctr = nullptr, *ovf = nullptr, *djf = nullptr, *djc = nullptr;
+    unsigned char* pinned = nullptr;  // captured passes: host staging of the uploads
+};
+
+// Host side: job arguments, tiles grouped by kernel variant.  Wdev / wflag
+// (per job in act, may be null) switch on the captured form.
+void group_prepare(tm_weights* const* ws, const std::vector<int>& act, const u64* j0s, const u64* counts,
+                   const u64* seeds, const BatchConfig& cfg, const void* const* Wdev, const int* const* wflag,
+                   Group& G) {
     const int na = (int)act.size();
-    u64 total = 0, key_space = 0;
+    G.na = na;
+    u64 key_space = 0;
     std::vector<uint32_t> key_base(na);
     for (int y = 0; y < na; ++y) {
         key_base[y] = (uint32_t)key_space;
         key_space += 2 * (u64)ws[act[y]]->g->m;
-        total += counts[act[y]];
+        G.total += counts[act[y]];
     }
-    const int key_bits = std::max(1, bits_of(key_space - 1));
+    G.key_bits = std::max(1, bits_of(key_space - 1));
+    G.passes = (G.key_bits + kRadixBits - 1) / kRadixBits;
     const int tile = cfg.tile > 0 ? cfg.tile : 8192;
     int cus = 256;
     {
@@ -1078,137 +1115,171 @@ int batch_group(tm_weights* const* ws, const std::vector<int>& act, const u64* j
         if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
             cus = prop.multiProcessorCount;
     }
-    const int blocks = cfg.blocks > 0 ? cfg.blocks : 8 * cus;
-    // job arguments; groups by (wide, general) kernel variant
-    std::vector<SampleArgs> args(na);
+    G.blocks = cfg.blocks > 0 ? cfg.blocks : 8 * cus;
+    G.args.resize(na);
     std::vector<u64> base(na);
-    const int passes = (key_bits + kRadixBits - 1) / kRadixBits;
     u64 off = 0;
     for (int y = 0; y < na; ++y) {
         size_t lds;
-        fill_args(ws[act[y]], &args[y], &lds);
-        args[y].seed = seeds[act[y]];
-        args[y].j0 = j0s[act[y]];
-        args[y].count = counts[act[y]];
-        args[y].key_base = key_base[y];
+        fill_args(ws[act[y]], &G.args[y], &lds);
+        G.args[y].seed = seeds[act[y]];
+        G.args[y].j0 = j0s[act[y]];
+        G.args[y].count = counts[act[y]];
+        G.args[y].key_base = key_base[y];
+        G.args[y].Wdev = Wdev ? Wdev[y] : nullptr;
+        G.args[y].wflag = wflag ? wflag[y] : nullptr;
+        if (G.args[y].cum_in_lds) G.root_lds = kCumLdsBytes;
         base[y] = off;
         off += counts[act[y]];
     }
-    std::vector<Tile> rt, stt;
-    std::vector<int> g_rt_first(5, 0), g_st_first(5, 0), jfirst(na), jcount(na);
+    G.g_rt_first.assign(5, 0);
+    G.g_st_first.assign(5, 0);
+    G.jfirst.assign(na, 0);
+    G.jcount.assign(na, 0);
     for (int grp = 0; grp < 4; ++grp) {
-        g_rt_first[grp] = (int)rt.size();
-        g_st_first[grp] = (int)stt.size();
+        G.g_rt_first[grp] = (int)G.rt.size();
+        G.g_st_first[grp] = (int)G.stt.size();
         for (int y = 0; y < na; ++y) {
             const tm_weights* w = ws[act[y]];
-            const int gy = (w->wide ? 2 : 0) + (args[y].general_runs ? 1 : 0);
+            const int gy = (w->wide ? 2 : 0) + (G.args[y].general_runs ? 1 : 0);
             if (gy != grp) continue;
-            jfirst[y] = (int)stt.size();
+            G.jfirst[y] = (int)G.stt.size();
             const u64 cy = counts[act[y]];
             for (u64 b = 0; b < cy; b += (u64)tile) {
                 const u64 e = std::min<u64>(cy, b + (u64)tile);
-                rt.push_back(Tile{y, 0, b, e, base[y]});
-                stt.push_back(Tile{y, 0, base[y] + b, base[y] + e, 0});
+                G.rt.push_back(Tile{y, 0, b, e, base[y]});
+                G.stt.push_back(Tile{y, 0, base[y] + b, base[y] + e, 0});
             }
-            jcount[y] = (int)stt.size() - jfirst[y];
+            G.jcount[y] = (int)G.stt.size() - G.jfirst[y];
         }
     }
-    g_rt_first[4] = (int)rt.size();
-    g_st_first[4] = (int)stt.size();
-    // device buffers
-    SampleArgs* djobs = nullptr;
-    Tile *drt = nullptr, *dst = nullptr;
-    uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
-    Partial *tparts = nullptr, *jparts = nullptr;
-    int *ctr = nullptr, *ovf = nullptr, *djf = nullptr, *djc = nullptr;
-    TM_HIP(dev_alloc((void**)&djobs, na * sizeof(SampleArgs), st));
-    TM_HIP(dev_alloc((void**)&drt, rt.size() * sizeof(Tile), st));
-    TM_HIP(dev_alloc((void**)&dst, stt.size() * sizeof(Tile), st));
-    TM_HIP(dev_alloc((void**)&k0, total * sizeof(uint32_t), st));
-    TM_HIP(dev_alloc((void**)&v0, total * sizeof(uint32_t), st));
-    TM_HIP(dev_alloc((void**)&k1, total * sizeof(uint32_t), st));
-    TM_HIP(dev_alloc((void**)&v1, total * sizeof(uint32_t), st));
-    TM_HIP(dev_alloc((void**)&tparts, stt.size() * sizeof(Partial), st));
-    TM_HIP(dev_alloc((void**)&jparts, na * sizeof(Partial), st));
-    TM_HIP(dev_alloc((void**)&ctr, 16 * sizeof(int), st));
-    TM_HIP(dev_alloc((void**)&ovf, sizeof(int), st));
-    TM_HIP(dev_alloc((void**)&djf, na * sizeof(int), st));
-    TM_HIP(dev_alloc((void**)&djc, na * sizeof(int), st));
+    G.g_rt_first[4] = (int)G.rt.size();
+    G.g_st_first[4] = (int)G.stt.size();
+}
+
+int group_alloc(Group& G, hipStream_t st) {
+    const int na = G.na;
+    TM_HIP(dev_alloc((void**)&G.djobs, na * sizeof(SampleArgs), st));
+    TM_HIP(dev_alloc((void**)&G.drt, G.rt.size() * sizeof(Tile), st));
+    TM_HIP(dev_alloc((void**)&G.dst, G.stt.size() * sizeof(Tile), st));
+    TM_HIP(dev_alloc((void**)&G.k0, G.total * sizeof(uint32_t), st));
+    TM_HIP(dev_alloc((void**)&G.v0, G.total * sizeof(uint32_t), st));
+    TM_HIP(dev_alloc((void**)&G.k1, G.total * sizeof(uint32_t), st));
+    TM_HIP(dev_alloc((void**)&G.v1, G.total * sizeof(uint32_t), st));
+    TM_HIP(dev_alloc((void**)&G.tparts, G.stt.size() * sizeof(Partial), st));
+    TM_HIP(dev_alloc((void**)&G.jparts, na * sizeof(Partial), st));
+    TM_HIP(dev_alloc((void**)&G.ctr, 16 * sizeof(int), st));
+    TM_HIP(dev_alloc((void**)&G.ovf, sizeof(int), st));
+    TM_HIP(dev_alloc((void**)&G.djf, na * sizeof(int), st));
+    TM_HIP(dev_alloc((void**)&G.djc, na * sizeof(int), st));
     // the sorted arrays end where an even number of passes leaves them
-    uint32_t* ks_sorted = passes % 2 == 0 ? k0 : k1;
-    uint32_t* vs_sorted = passes % 2 == 0 ? v0 : v1;
     for (int y = 0; y < na; ++y) {
-        args[y].skey = ks_sorted;
-        args[y].sval = vs_sorted;
+        G.args[y].skey = G.passes % 2 == 0 ? G.k0 : G.k1;
+        G.args[y].sval = G.passes % 2 == 0 ? G.v0 : G.v1;
     }
-    TM_HIP(hipMemcpyAsync(djobs, args.data(), na * sizeof(SampleArgs), hipMemcpyHostToDevice, st));
-    TM_HIP(hipMemcpyAsync(drt, rt.data(), rt.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
-    TM_HIP(hipMemcpyAsync(dst, stt.data(), stt.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
-    TM_HIP(hipMemcpyAsync(djf, jfirst.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
-    TM_HIP(hipMemcpyAsync(djc, jcount.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
-    TM_TRY(fill_u32(ctr, 16, 0u, st));
-    TM_TRY(fill_u32(ovf, 1, 0u, st));
-    size_t root_lds = 0;
-    for (int y = 0; y < na; ++y)
-        if (args[y].cum_in_lds) root_lds = kCumLdsBytes;
+    return TM_OK;
+}
+
+// Uploads of the host arrays; staged through pinned memory when `pinned`
+// (captured passes replay the copies from that buffer).
+int group_upload(Group& G, bool pinned, hipStream_t st) {
+    const size_t sz[5] = {G.na * sizeof(SampleArgs), G.rt.size() * sizeof(Tile), G.stt.size() * sizeof(Tile),
+                          G.na * sizeof(int), G.na * sizeof(int)};
+    const void* src[5] = {G.args.data(), G.rt.data(), G.stt.data(), G.jfirst.data(), G.jcount.data()};
+    void* dst[5] = {G.djobs, G.drt, G.dst, G.djf, G.djc};
+    if (pinned) {
+        size_t total = 0;
+        for (size_t b : sz) total += (b + 255) & ~(size_t)255;
+        TM_HIP(hipHostMalloc((void**)&G.pinned, total, hipHostMallocDefault));
+        size_t o = 0;
+        for (int x = 0; x < 5; ++x) {
+            std::memcpy(G.pinned + o, src[x], sz[x]);
+            src[x] = G.pinned + o;
+            o += (sz[x] + 255) & ~(size_t)255;
+        }
+    }
+    for (int x = 0; x < 5; ++x)
+        if (sz[x]) TM_HIP(hipMemcpyAsync(dst[x], src[x], sz[x], hipMemcpyHostToDevice, st));
+    return TM_OK;
+}
+
+// Counters, root draws, the sort, sampling and per-job sums into jparts.
+int group_launch(Group& G, hipStream_t st, bool timed) {
+    TM_TRY(fill_u32(G.ctr, 16, 0u, st));
+    TM_TRY(fill_u32(G.ovf, 1, 0u, st));
     StageTimer t_roots, t_sample, t_reduce;
-    t_roots.start(TM_STAGE_ROOTS, st);
+    if (timed) t_roots.start(TM_STAGE_ROOTS, st);
     for (int grp = 0; grp < 4; ++grp) {
-        const int nt = g_rt_first[grp + 1] - g_rt_first[grp];
+        const int nt = G.g_rt_first[grp + 1] - G.g_rt_first[grp];
         if (nt == 0) continue;
-        const dim3 grid((unsigned)std::min(blocks, nt));
-        const Tile* tl = drt + g_rt_first[grp];
+        const dim3 grid((unsigned)std::min(G.blocks, nt));
+        const Tile* tl = G.drt + G.g_rt_first[grp];
         if (grp >= 2)
-            hipLaunchKernelGGL(batch_root_kernel<u128>, grid, dim3(kBlock), root_lds, st, djobs, tl, nt,
-                               ctr + grp, k0, v0, ovf);
+            hipLaunchKernelGGL(batch_root_kernel<u128>, grid, dim3(kBlock), G.root_lds, st, G.djobs, tl, nt,
+                               G.ctr + grp, G.k0, G.v0, G.ovf);
         else
-            hipLaunchKernelGGL(batch_root_kernel<u64>, grid, dim3(kBlock), root_lds, st, djobs, tl, nt,
-                               ctr + grp, k0, v0, ovf);
+            hipLaunchKernelGGL(batch_root_kernel<u64>, grid, dim3(kBlock), G.root_lds, st, G.djobs, tl, nt,
+                               G.ctr + grp, G.k0, G.v0, G.ovf);
         TM_HIP(hipGetLastError());
     }
     {
         uint32_t *ksr, *vsr;
-        TM_TRY(radix_sort_pairs<uint32_t>(k0, v0, k1, v1, (int64_t)total, 0, key_bits, &ksr, &vsr, ovf, st));
-        if (ksr != ks_sorted) return tm_fail(TM_EDEVICE, "batch: unexpected sort buffer");
+        TM_TRY(radix_sort_pairs<uint32_t>(G.k0, G.v0, G.k1, G.v1, (int64_t)G.total, 0, G.key_bits, &ksr, &vsr,
+                                          G.ovf, st));
+        if (ksr != G.args[0].skey) return tm_fail(TM_EDEVICE, "batch: unexpected sort buffer");
     }
     t_roots.stop();
-    t_sample.start(TM_STAGE_SAMPLE, st);
+    if (timed) t_sample.start(TM_STAGE_SAMPLE, st);
     for (int grp = 0; grp < 4; ++grp) {
-        const int nt = g_st_first[grp + 1] - g_st_first[grp];
+        const int nt = G.g_st_first[grp + 1] - G.g_st_first[grp];
         if (nt == 0) continue;
-        const dim3 grid((unsigned)std::min(blocks, nt));
-        const Tile* tl = dst + g_st_first[grp];
-        Partial* tp = tparts + g_st_first[grp];
-        int* c = ctr + 4 + grp;
+        const dim3 grid((unsigned)std::min(G.blocks, nt));
+        const Tile* tl = G.dst + G.g_st_first[grp];
+        Partial* tp = G.tparts + G.g_st_first[grp];
+        int* c = G.ctr + 4 + grp;
         switch (grp) {
-            case 0: hipLaunchKernelGGL((batch_sample_kernel<u64, false>), grid, dim3(kBlock), 0, st, djobs, tl, nt, c, tp, ovf); break;
-            case 1: hipLaunchKernelGGL((batch_sample_kernel<u64, true>), grid, dim3(kBlock), 0, st, djobs, tl, nt, c, tp, ovf); break;
-            case 2: hipLaunchKernelGGL((batch_sample_kernel<u128, false>), grid, dim3(kBlock), 0, st, djobs, tl, nt, c, tp, ovf); break;
-            default: hipLaunchKernelGGL((batch_sample_kernel<u128, true>), grid, dim3(kBlock), 0, st, djobs, tl, nt, c, tp, ovf); break;
+            case 0: hipLaunchKernelGGL((batch_sample_kernel<u64, false>), grid, dim3(kBlock), 0, st, G.djobs, tl, nt, c, tp, G.ovf); break;
+            case 1: hipLaunchKernelGGL((batch_sample_kernel<u64, true>), grid, dim3(kBlock), 0, st, G.djobs, tl, nt, c, tp, G.ovf); break;
+            case 2: hipLaunchKernelGGL((batch_sample_kernel<u128, false>), grid, dim3(kBlock), 0, st, G.djobs, tl, nt, c, tp, G.ovf); break;
+            default: hipLaunchKernelGGL((batch_sample_kernel<u128, true>), grid, dim3(kBlock), 0, st, G.djobs, tl, nt, c, tp, G.ovf); break;
         }
         TM_HIP(hipGetLastError());
     }
     t_sample.stop();
-    t_reduce.start(TM_STAGE_REDUCE, st);
-    hipLaunchKernelGGL(job_reduce_kernel, dim3(na), dim3(kBlock), 0, st, (const Partial*)tparts,
-                       (const int*)djf, (const int*)djc, jparts);
+    if (timed) t_reduce.start(TM_STAGE_REDUCE, st);
+    hipLaunchKernelGGL(job_reduce_kernel, dim3(G.na), dim3(kBlock), 0, st, (const Partial*)G.tparts,
+                       (const int*)G.djf, (const int*)G.djc, G.jparts);
     TM_HIP(hipGetLastError());
     t_reduce.stop();
-    std::vector<Partial> hp(na);
+    if (timed) {
+        TM_HIP(sync_stream(st));
+        t_roots.finish();
+        t_sample.finish();
+        t_reduce.finish();
+    }
+    return TM_OK;
+}
+
+void group_free(Group& G, hipStream_t st) {
+    for (void* q : {(void*)G.djobs, (void*)G.drt, (void*)G.dst, (void*)G.k0, (void*)G.v0, (void*)G.k1, (void*)G.v1,
+                    (void*)G.tparts, (void*)G.jparts, (void*)G.ctr, (void*)G.ovf, (void*)G.djf, (void*)G.djc})
+        (void)dev_free(q, st);
+    if (G.pinned) (void)hipHostFree(G.pinned);
+    G.pinned = nullptr;
+}
+
+// Per-job sums from a finished group (stream synchronised).
+int group_read(Group& G, const std::vector<int>& act, hipStream_t st, JobSums* out) {
+    std::vector<Partial> hp(G.na);
     int hovf = 0;
-    TM_HIP(hipMemcpyAsync(hp.data(), jparts, na * sizeof(Partial), hipMemcpyDeviceToHost, st));
-    TM_HIP(hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, st));
-    for (void* q : {(void*)djobs, (void*)drt, (void*)dst, (void*)k0, (void*)v0, (void*)k1, (void*)v1,
-                    (void*)tparts, (void*)jparts, (void*)ctr, (void*)ovf, (void*)djf, (void*)djc})
-        TM_HIP(dev_free(q, st));
+    TM_HIP(hipMemcpyAsync(hp.data(), G.jparts, G.na * sizeof(Partial), hipMemcpyDeviceToHost, st));
+    TM_HIP(hipMemcpyAsync(&hovf, G.ovf, sizeof(int), hipMemcpyDeviceToHost, st));
     TM_HIP(sync_stream(st));
-    t_roots.finish();
-    t_sample.finish();
-    t_reduce.finish();
     if (hovf & 2) return tm_fail(TM_EDEVICE, "batch: inconsistent weight tables");
-    for (int y = 0; y < na; ++y) {
+    for (int y = 0; y < G.na; ++y) {
         const Partial& h = hp[y];
         JobSums& o = out[act[y]];
+        o = JobSums{};
         if ((hovf & 1) || (h.flags & 1)) {
             o.status = TM_EOVERFLOW;
             continue;
@@ -1223,6 +1294,21 @@ int batch_group(tm_weights* const* ws, const std::vector<int>& act, const u64* j
         o.flags = h.flags & 2;
     }
     return TM_OK;
+}
+
+// One batched pass over jobs whose root-key ranges and sample offsets all fit
+// 32 bits together: job y's keys are key_base[y] + (its root key < 2 m_y).
+int batch_group(tm_weights* const* ws, const std::vector<int>& act, const u64* j0s, const u64* counts,
+                const u64* seeds, hipStream_t st, JobSums* out, const BatchConfig& cfg) {
+    Group G;
+    group_prepare(ws, act, j0s, counts, seeds, cfg, nullptr, nullptr, G);
+    int rc = group_alloc(G, st);
+    if (rc == TM_OK) rc = group_upload(G, false, st);
+    if (rc == TM_OK) rc = group_launch(G, st, true);
+    if (rc == TM_OK) rc = group_read(G, act, st, out);
+    group_free(G, st);
+    (void)sync_stream(st);
+    return rc;
 }
 
 }  // namespace
@@ -1276,4 +1362,82 @@ int batch_sample_pass(tm_weights* const* ws, const u64* j0s, const u64* counts, 
         cnt += counts[x];
     }
     return flush();
+}
+
+// ---------------------------------------------------------------------------
+// Captured passes (recorded into a graph by the batch plan).
+// ---------------------------------------------------------------------------
+struct CapturedPass {
+    std::vector<Group> groups;
+    std::vector<std::vector<int>> acts;
+    int n = 0;
+};
+
+int batch_capture_enqueue(tm_weights* const* ws, const int* const* wflag, const u64* counts, const u64* seeds,
+                          int n, hipStream_t st, const BatchConfig& cfg, CapturedPass** out) {
+    std::unique_ptr<CapturedPass> P(new (std::nothrow) CapturedPass());
+    if (!P) return tm_fail(TM_ENOMEM, "capture: host allocation");
+    P->n = n;
+    const u64 lim = (u64)1 << 32;
+    std::vector<int> act;
+    u64 keys = 0, cnt = 0;
+    std::vector<u64> j0(n, 0);
+    auto flush = [&]() -> int {
+        if (act.empty()) return TM_OK;
+        std::vector<const void*> wd(act.size());
+        std::vector<const int*> wf(act.size());
+        for (size_t y = 0; y < act.size(); ++y) {
+            const tm_weights* w = ws[act[y]];
+            wd[y] = static_cast<const unsigned char*>(w->cumW) + w->q * 8;
+            wf[y] = wflag[act[y]];
+        }
+        P->groups.emplace_back();
+        P->acts.push_back(act);
+        Group& G = P->groups.back();
+        group_prepare(ws, act, j0.data(), counts, seeds, cfg, wd.data(), wf.data(), G);
+        TM_TRY(group_alloc(G, st));
+        TM_TRY(group_upload(G, true, st));
+        TM_TRY(group_launch(G, st, false));
+        act.clear();
+        keys = cnt = 0;
+        return TM_OK;
+    };
+    for (int x = 0; x < n; ++x) {
+        tm_weights* w = ws[x];
+        if (counts[x] == 0 || w->g->m == 0 || !w->cumW) continue;
+        if (w->wide) return tm_fail(TM_EINVAL, "capture: job %d has 128-bit weights", x);
+        if (w->plan.nt < 1 || w->plan.nt > 7) return tm_fail(TM_EINVAL, "capture: job %d tree size", x);
+        if (counts[x] >= lim) return tm_fail(TM_EINVAL, "capture: job %d draws 2^32 samples or more", x);
+        const u64 kx = 2 * (u64)w->g->m;
+        if (keys + kx > lim || cnt + counts[x] >= lim) {
+            const int rc = flush();
+            if (rc != TM_OK) {
+                batch_capture_free(P.release(), st);
+                return rc;
+            }
+        }
+        act.push_back(x);
+        keys += kx;
+        cnt += counts[x];
+    }
+    const int rc = flush();
+    if (rc != TM_OK) {
+        batch_capture_free(P.release(), st);
+        return rc;
+    }
+    *out = P.release();
+    return TM_OK;
+}
+
+int batch_capture_read(CapturedPass* P, hipStream_t st, JobSums* out) {
+    for (int x = 0; x < P->n; ++x) out[x] = JobSums{};
+    for (size_t g = 0; g < P->groups.size(); ++g) TM_TRY(group_read(P->groups[g], P->acts[g], st, out));
+    return TM_OK;
+}
+
+void batch_capture_free(CapturedPass* P, hipStream_t st) {
+    if (!P) return;
+    (void)sync_stream(st);
+    for (Group& G : P->groups) group_free(G, st);
+    delete P;
 }

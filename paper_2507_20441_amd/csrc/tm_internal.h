@@ -3,6 +3,7 @@
 #pragma once
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/timest.h"
@@ -48,6 +49,10 @@ hipError_t dev_alloc(void** p, size_t bytes, hipStream_t st);
 hipError_t dev_free(void* p, hipStream_t st);
 // Synchronise the device and return every cached block to HIP.
 void dev_cache_trim();
+// Between begin and end, dev_free on this thread appends to keep instead of
+// releasing (for work recorded into a graph, which replays on those blocks).
+void dev_defer_begin(std::vector<std::pair<void*, hipStream_t>>* keep);
+void dev_defer_end();
 // Every block released on st becomes reusable by any stream.
 void dev_stream_synced(hipStream_t st);
 // hipStreamSynchronize, then dev_stream_synced.
@@ -182,6 +187,19 @@ extern BatchConfig g_batch_config;
 int batch_sample_pass(tm_weights* const* ws, const u64* j0, const u64* count, const u64* seeds, int n,
                       hipStream_t st, JobSums* out, const BatchConfig& cfg);
 
+// The captured form of a batched pass over jobs whose 64-bit weights are
+// being built earlier on st: every launch and copy is enqueued with no host
+// synchronisation or read; W comes from each job's table and a job whose
+// wflag is set (overflow) or whose W is 0 draws nothing.  Jobs with
+// count[x] = 0 are left out.  The handle owns the buffers (and the pinned
+// staging the recorded uploads read) until batch_capture_free.
+struct CapturedPass;
+int batch_capture_enqueue(tm_weights* const* ws, const int* const* wflag, const u64* count, const u64* seeds,
+                          int n, hipStream_t st, const BatchConfig& cfg, CapturedPass** out);
+// Sums of every job after the recorded work ran (synchronises st).
+int batch_capture_read(CapturedPass* p, hipStream_t st, JobSums* out);
+void batch_capture_free(CapturedPass* p, hipStream_t st);
+
 BatchConfig batch_config_now();
 int sample_batch_results(tm_weights* const* w, const uint64_t* k, const uint64_t* seed, int n_jobs,
                          hipStream_t st, tm_result* out);
@@ -193,6 +211,8 @@ void finish_result(tm_result* r);
 // ---------------------------------------------------------------------------
 bool prof_enabled();
 void prof_add(int stage, double ms);
+// Stage timing off on this thread (while recording a graph).
+void prof_suspend(bool on);
 
 struct StageTimer {
     hipEvent_t a = nullptr, b = nullptr;

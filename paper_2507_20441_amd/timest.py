@@ -122,6 +122,11 @@ def lib():
                                         C.POINTER(u64), C.POINTER(u64), C.c_int, vp,
                                         C.POINTER(Result)]
         L.tm_batch_config.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.tm_batch_plan_create.argtypes = [C.POINTER(vp), C.POINTER(Motif), C.POINTER(C.POINTER(Tree)),
+                                           C.POINTER(u64), C.POINTER(u64), C.c_int, vp, C.POINTER(vp)]
+        L.tm_batch_plan_run.argtypes = [vp, vp, C.POINTER(Result)]
+        L.tm_batch_plan_destroy.argtypes = [vp]
+        L.tm_batch_plan_destroy.restype = None
         L.tm_profile_enable.argtypes = [C.c_int]
         L.tm_profile_enable.restype = None
         L.tm_profile_read.argtypes = [C.POINTER(Profile), C.c_int]
@@ -411,3 +416,37 @@ def sample_model_bytes(w: "Weights", seed, count, j0=0) -> int:
     _check(lib().tm_sample_model_bytes(w.h, int(seed), int(j0), int(count), _stream(), C.byref(b)),
            "sample_model_bytes")
     return int(b.value)
+
+
+class BatchPlan:
+    """tm_batch_plan_*: the 64-bit pipeline of a fixed job set recorded into
+    one HIP graph; run() replays it and returns one Result per job."""
+
+    def __init__(self, graphs, motifs, ks, seeds, trees=None):
+        n = len(graphs)
+        self._graphs = list(graphs)
+        hs = (C.c_void_p * n)(*[g.h for g in graphs])
+        mo = (Motif * n)(*motifs)
+        kk = (C.c_uint64 * n)(*[int(x) for x in ks])
+        ss = (C.c_uint64 * n)(*[int(x) for x in seeds])
+        tr = None
+        if trees is not None:
+            keep = [C.pointer(t) if t is not None else None for t in trees]
+            tr = (C.POINTER(Tree) * n)(*keep)
+        h = C.c_void_p()
+        _check(lib().tm_batch_plan_create(hs, mo, tr, kk, ss, n, _stream(), C.byref(h)), "batch_plan_create")
+        self.h = h
+        self.n = n
+
+    def run(self):
+        out = (Result * self.n)()
+        _check(lib().tm_batch_plan_run(self.h, _stream(), out), "batch_plan_run")
+        return list(out)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tm_batch_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

@@ -95,3 +95,30 @@ def test_batch_repeats_identically(T, mix):
         ws[0].sample(123, 5000)  # eager work in between
         again = T.sample_batch(ws, ks, ss)
         assert all(same(a, b) for a, b in zip(first, again)), rep
+
+
+def test_batch_plan_replays(T, mix):
+    """The recorded pipeline, replayed three times with other library work and
+    synchronisations between the replays, equals the eager batch every time;
+    the 128-bit job is re-run eagerly after each replay."""
+    import torch
+    tg, jobs = mix
+    gs = [g for g, *_ in jobs]
+    mos = [mo for _, mo, _, _ in jobs]
+    ks = [k for *_, k, _ in jobs]
+    ss = [s for *_, s in jobs]
+    ref = T.estimate_batch(gs, mos, ks, ss)
+    say("plan create")
+    plan = T.BatchPlan(gs, mos, ks, ss)
+    prev = T.batch_config(512, 3)  # a later schedule change does not touch the recording
+    try:
+        for rep in range(3):
+            say("replay", rep)
+            got = plan.run()
+            for i, (a, b) in enumerate(zip(got, ref)):
+                assert a.status == b.status and same(a, b), (rep, i)
+            T.estimate(gs[1], mos[1], 5000, 3 + rep)
+            torch.cuda.synchronize()
+    finally:
+        T.batch_config(*prev)
+        plan.close()
