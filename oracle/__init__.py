@@ -77,6 +77,8 @@ def lib():
         L.or_prep_weights.argtypes = [vp, i32, C.c_int, vp]
         L.or_sample.argtypes = [vp, u64, u64, u64, u64, C.POINTER(Result), vp]
         L.or_derive_cnt.argtypes = [vp, vp, C.POINTER(U128)]
+        L.or_prepare_light.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), C.POINTER(vp)]
+        L.or_edge_weight.argtypes = [vp, C.c_int64, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(U128)]
         L.or_philox4x32_10.argtypes = [vp, vp, vp]
         L.or_draw.argtypes = [u64, u64, C.c_uint32, U128]
         L.or_draw.restype = U128
@@ -206,16 +208,29 @@ class Graph:
 
 
 class Prep:
-    """Weights of one (graph, motif, tree) -- Alg. 1 / Alg. 2."""
+    """Weights of one (graph, motif, tree) -- Alg. 1 / Alg. 2.  light=True
+    builds no tables: only edge_weight and derive_cnt are then available."""
 
-    def __init__(self, g: Graph, mo: Motif, tr: Tree = None):
+    def __init__(self, g: Graph, mo: Motif, tr: Tree = None, light=False):
         self.g, self.mo = g, mo
         self.tr = tr if tr is not None else default_tree(mo)
         h = C.c_void_p()
-        rc = lib().or_prepare(g.h, C.byref(mo), C.byref(self.tr), C.byref(h))
+        fn = lib().or_prepare_light if light else lib().or_prepare
+        rc = fn(g.h, C.byref(mo), C.byref(self.tr), C.byref(h))
         if rc != OR_OK:
             raise OracleError(rc, "prepare")
         self.h = h
+
+    def edge_weight(self, interval, s, eid, work_limit=1 << 62):
+        """w_i(s, e) of one edge by the recursive rule (no tables); None when
+        the candidate lists exceed work_limit."""
+        out = U128()
+        rc = lib().or_edge_weight(self.h, int(interval), int(s), int(eid), int(work_limit), C.byref(out))
+        if rc == OR_ERANGE:
+            return None
+        if rc != OR_OK:
+            raise OracleError(rc, "edge_weight")
+        return out.value
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -404,6 +404,65 @@ extern "C" int or_prepare(const or_graph* g, const or_motif* mo, const or_tree* 
     return OR_OK;
 }
 
+extern "C" int or_prepare_light(const or_graph* g, const or_motif* mo, const or_tree* tr, or_prep** out) {
+    if (!g || !out || !motif_ok(mo)) return OR_EINVAL;
+    or_tree def;
+    if (!tr) {
+        if (or_default_tree(mo, &def) != OR_OK) return OR_EINVAL;
+        tr = &def;
+    }
+    if (!tree_ok(mo, tr)) return OR_EINVAL;
+    or_prep* R = new or_prep();
+    R->g = g;
+    make_plan(mo, tr, R->P);
+    R->delta = mo->delta;
+    R->q = g->m > 0 ? g->T / mo->delta + 1 : 0;
+    *out = R;
+    return OR_OK;
+}
+
+// Claim "overall-num-matches" for one edge: the product over s's children of
+// the summed child weights over the candidate list, each child weight again
+// by this rule (a leaf has weight 1).
+static int lazy_weight(const or_prep& R, int64_t i, int s, int32_t e, uint64_t& budget, u128* out) {
+    const Plan& P = R.P;
+    if (P.children[s].empty()) {
+        *out = 1;
+        return OR_OK;
+    }
+    u128 prod = 1;
+    std::vector<int32_t> cand;
+    for (int c : P.children[s]) {
+        candidates(R, i, s, e, c, cand);
+        if (cand.size() > budget) return OR_ERANGE;
+        budget -= cand.size();
+        const std::vector<int32_t> mine(cand);
+        u128 sum = 0;
+        for (int32_t f : mine) {
+            u128 x;
+            const int rc = lazy_weight(R, i, c, f, budget, &x);
+            if (rc != OR_OK) return rc;
+            if (!add_ok(sum, x, &sum)) return OR_EOVERFLOW;
+        }
+        if (!mul_ok(prod, sum, &prod)) return OR_EOVERFLOW;
+    }
+    *out = prod;
+    return OR_OK;
+}
+
+extern "C" int or_edge_weight(const or_prep* p, int64_t interval, int32_t s, int32_t eid, uint64_t work_limit,
+                              or_u128* w) {
+    if (!p || !w || eid < 0 || eid >= p->g->m || interval < 0 || interval >= p->q) return OR_EINVAL;
+    if (s < 0 || s >= p->P.mo.l || !p->P.in_tree[s]) return OR_EINVAL;
+    if (!in_interval(p->g->e[eid].t, interval, p->delta)) return OR_EINVAL;
+    uint64_t budget = work_limit;
+    u128 x;
+    const int rc = lazy_weight(*p, interval, s, eid, budget, &x);
+    if (rc != OR_OK) return rc;
+    *w = to_or(x);
+    return OR_OK;
+}
+
 extern "C" void or_prep_destroy(or_prep* p) { delete p; }
 extern "C" or_u128 or_prep_W(const or_prep* p) { return to_or(p->W); }
 extern "C" int64_t or_prep_q(const or_prep* p) { return p->q; }

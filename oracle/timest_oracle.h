@@ -111,6 +111,16 @@ void or_prep_interval_weights(const or_prep* p, or_u128* wi);
  * Leaf edges return 1 in every existing slot. */
 int or_prep_weights(const or_prep* p, int32_t s, int slot, or_u128* out);
 
+/* A preparation without weight tables: the plan, delta and the interval
+ * count only.  For graphs too large for or_prepare; serves or_edge_weight
+ * and or_derive_cnt (the table functions and or_sample need or_prepare). */
+int or_prepare_light(const or_graph* g, const or_motif* mo, const or_tree* tr, or_prep** out);
+/* w_i(s,e) for one edge, evaluated from Claim "overall-num-matches" by
+ * recursion over the candidate lists (no tables).  eid must lie in I_i.
+ * OR_ERANGE when more than work_limit candidates would be visited. */
+int or_edge_weight(const or_prep* p, int64_t interval, int32_t s, int32_t eid, uint64_t work_limit,
+                   or_u128* w);
+
 /* ---- sampling, validation, derivation, estimate (Alg. 3-6) ---------- */
 /* Samples ids j0 .. j0+count-1 with the given seed; k_total is the k used in
  * the estimate formula.  recs may be NULL. */

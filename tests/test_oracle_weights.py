@@ -89,3 +89,41 @@ def test_empty_graph_has_zero_weight():
     res, recs = P.sample(1, 10, records=True)
     assert res.flags & 1 and res.estimate == 0.0
     assert (recs["status"] == 4).all()
+
+
+@pytest.mark.parametrize("name,edges,delta,m,n,span", CASES[:6], ids=[c[0] for c in CASES[:6]])
+def test_single_edge_weight_equals_tables(name, edges, delta, m, n, span):
+    """The table-free single-edge weight (recursion over candidate lists) gives
+    every table entry of every tree edge, both slots, for every tree choice;
+    and a tight work limit is reported instead of a wrong value."""
+    g = W.small_graph(m, 7, n=n, span=span)
+    og = O.Graph(g.src, g.dst, g.t, g.n)
+    for tr in all_tree_choices(edges):
+        mo = O.make_motif(edges, delta)
+        P = O.Prep(og, mo, tr)
+        L = O.Prep(og, mo, tr, light=True)
+        t = og.edges()[2]
+        for s in tr.edge[:tr.n_edges]:
+            for slot in (0, 1):
+                ref = O.u128_array_to_int(P.weights(s, slot))
+                for e in range(og.m):
+                    i = int(t[e]) // delta - slot
+                    if i < 0 or i >= P.q:
+                        continue
+                    assert L.edge_weight(i, s, e) == ref[e], (s, slot, e)
+    # a limit smaller than the first candidate list: refused, not truncated
+    mo = O.make_motif(edges, delta)
+    L = O.Prep(og, mo, light=True)
+    c = L.tr.center
+    t = og.edges()[2]
+    seen = False
+    for e in range(og.m):
+        i = int(t[e]) // delta
+        if i >= L.q:
+            continue
+        full = L.edge_weight(i, c, e)
+        if full and full > 1:
+            assert L.edge_weight(i, c, e, work_limit=0) is None
+            seen = True
+            break
+    assert seen
