@@ -209,13 +209,27 @@ SERVE_DELTAS = (600, 1800, 3600, 7200, 14400, 28800, 43200, 86400)
 SERVE_DELTAS_LARGE = (3600, 86400)
 
 
-def device_graph(n, m, gamma, seed, span=10_000_000, device="cuda"):
-    """Chung-Lu pairs with bursty per-source times, drawn on the device.
+def device_graph(n, m, gamma, seed, span=10_000_000, device="cuda", reciprocal=0, recip_gap=600):
+    """Chung-Lu pairs with bursty per-source times, drawn on the device; the
+    last `reciprocal` edges reverse distinct earlier ones at +U{1..recip_gap} s.
     Returns (src int32, dst int32, t int64) device tensors with every
     (u, v, t) unique."""
     import torch
     gen = torch.Generator(device=device)
     gen.manual_seed(seed)
+    base = m - reciprocal
+    u, v, t = _device_base(n, base, gamma, gen, span, device)
+    if reciprocal:
+        pick = torch.randperm(base, generator=gen, device=device)[:reciprocal]
+        gap = torch.randint(1, recip_gap + 1, (reciprocal,), generator=gen, device=device)
+        u, v, t = torch.cat([u, v[pick]]), torch.cat([v, u[pick]]), torch.cat([t, t[pick] + gap])
+        del pick, gap
+        _device_dedup(u, v, t, n, span, gen, device)
+    return u, v, t
+
+
+def _device_base(n, m, gamma, gen, span, device):
+    import torch
     f64 = torch.float64
     w = (torch.arange(n, device=device, dtype=f64) + 1.0) ** (-1.0 / (gamma - 1.0))
     cdf = torch.cumsum(w, 0)
@@ -248,7 +262,13 @@ def device_graph(n, m, gamma, seed, span=10_000_000, device="cuda"):
     t = torch.empty(m, dtype=torch.int64, device=device)
     t[order] = ts.to(torch.int64)
     del ts, us, order
-    # unique (u, v, t): redraw the time of every repeat
+    _device_dedup(u, v, t, n, span, gen, device)
+    return u, v, t
+
+
+def _device_dedup(u, v, t, n, span, gen, device):
+    """Unique (u, v, t): redraw the time of every repeat, in place."""
+    import torch
     while True:
         key = u.long() * n + v.long()
         idx = torch.argsort(t, stable=True)
@@ -260,7 +280,13 @@ def device_graph(n, m, gamma, seed, span=10_000_000, device="cuda"):
             break
         t[idx[dup]] = torch.randint(0, span, (dup.numel(),), generator=gen, device=device)
         del idx, dup
-    return u, v, t
+
+
+def large_graph_device():
+    """The large workload drawn on the device (a host draw of 1e8 edges takes
+    minutes): 2,000,000 vertices, 100,000,000 edges = 90M Chung-Lu gamma 2.0
+    plus 10M reciprocated at +U{1..600} s, bursty times over 3e7 s."""
+    return device_graph(2_000_000, 100_000_000, 2.0, 103, span=30_000_000, reciprocal=10_000_000)
 
 
 def serving_graph_specs(scale=1.0):
