@@ -231,10 +231,13 @@ def device_graph(n, m, gamma, seed, span=10_000_000, device="cuda", reciprocal=0
 def _device_base(n, m, gamma, gen, span, device):
     import torch
     f64 = torch.float64
-    w = (torch.arange(n, device=device, dtype=f64) + 1.0) ** (-1.0 / (gamma - 1.0))
-    cdf = torch.cumsum(w, 0)
-    cdf /= cdf[-1].clone()
-    del w
+    # the vertex-weight distribution on the host: a device prefix sum of
+    # floats need not round the same way every run
+    w = (np.arange(n, dtype=np.float64) + 1.0) ** (-1.0 / (gamma - 1.0))
+    cdf_h = np.cumsum(w)
+    cdf_h /= cdf_h[-1]
+    cdf = torch.from_numpy(cdf_h).to(device)
+    del w, cdf_h
     ids = torch.randperm(n, generator=gen, device=device).to(torch.int32)
 
     def draw(size):
@@ -248,19 +251,25 @@ def _device_base(n, m, gamma, gen, span, device):
             break
         u[bad], v[bad] = draw(bad.numel()), draw(bad.numel())
     del cdf, ids
-    # bursty times: per-source renewal process, Pareto(1.5) gaps, mean span ~ span
+    # bursty times: per-source renewal process, Pareto(1.5) gaps, mean span ~
+    # span, wrapped modulo span.  Gaps are summed as exact fixed-point
+    # integers (1/1024 s), each reduced modulo the span first, so the sums do
+    # not depend on the order of a parallel scan.
+    q = 1024
     order = torch.argsort(u, stable=True)
     us = u[order].long()
     counts = torch.bincount(us, minlength=n)
     first = torch.cumsum(counts, 0) - counts
     gaps = (span / (3.0 * counts[us].to(f64))) * torch.rand(m, generator=gen, device=device, dtype=f64) ** (-1.0 / 1.5)
-    c = torch.cumsum(gaps, 0)
-    before = (c - gaps)[first.clamp(max=m - 1)]
-    s0 = torch.rand(n, generator=gen, device=device, dtype=f64) * span
-    ts = torch.floor(s0[us] + (c - before[us])) % span
-    del gaps, c, before, counts, first, s0
+    g = torch.floor(torch.fmod(gaps * q, float(span) * q)).to(torch.int64)
+    del gaps
+    c = torch.cumsum(g, 0)
+    before = (c - g)[first.clamp(max=m - 1)]
+    s0 = torch.floor(torch.rand(n, generator=gen, device=device, dtype=f64) * span * q).to(torch.int64)
+    ts = torch.div(s0[us] + (c - before[us]), q, rounding_mode="floor") % span
+    del g, c, before, counts, first, s0
     t = torch.empty(m, dtype=torch.int64, device=device)
-    t[order] = ts.to(torch.int64)
+    t[order] = ts
     del ts, us, order
     _device_dedup(u, v, t, n, span, gen, device)
     return u, v, t
