@@ -258,6 +258,23 @@ void tm_batch_plan_destroy(tm_batch_plan* p);
  * values through prev_tile / prev_blocks when not NULL. */
 int tm_batch_config(int tile, int blocks, int* prev_tile, int* prev_blocks);
 
+/* Spanning-tree candidates (Sec. "Choosing the Spanning Tree", Alg. 8):
+ * every (spanning tree, center) pair of the motif, ordered by constraint
+ * looseness -- per motif vertex, over unordered pairs of tree edges incident
+ * to it, |pi(e1) - pi(e2)| - 1 -- then by edge set (lexicographic), rooted
+ * height and center; the first is tm_default_tree's choice.  Writes at most
+ * max_out trees (and their looseness, when looseness is not NULL) and sets
+ * *n_out to the number of pairs.  Errors: TM_EINVAL. */
+int tm_tree_candidates(const tm_motif* mo, tm_tree* out, int64_t* looseness, int max_out, int* n_out);
+
+/* Alg. 7: the first n_c candidates' total weight W on the graph (a full
+ * weight build each, released afterwards); the smallest W wins, the earlier
+ * candidate among equals.  W_out (may be NULL) receives the min(n_c, count)
+ * values in candidate order and *n_eval (may be NULL) their number.
+ * Synchronises the stream.  Errors: as tm_weights_create. */
+int tm_choose_tree(tm_graph* g, const tm_motif* mo, int n_c, void* stream, tm_tree* best, tm_u128* W_out,
+                   int* n_eval);
+
 /* Device bytes the weight tables of (g, mo, tr) take in 64-bit (wide = 0)
  * or 128-bit (wide = 1) form: what tm_weights_info reports as device_bytes
  * after tm_weights_create builds them in that form.  tr may be NULL (the

@@ -77,6 +77,10 @@ def lib():
         L.or_prep_weights.argtypes = [vp, i32, C.c_int, vp]
         L.or_sample.argtypes = [vp, u64, u64, u64, u64, C.POINTER(Result), vp]
         L.or_derive_cnt.argtypes = [vp, vp, C.POINTER(U128)]
+        L.or_tree_candidates.argtypes = [C.POINTER(Motif), C.POINTER(Tree), C.POINTER(C.c_int64), C.c_int,
+                                         C.POINTER(C.c_int)]
+        L.or_choose_tree.argtypes = [vp, C.POINTER(Motif), C.c_int, C.POINTER(Tree), C.POINTER(U128),
+                                     C.POINTER(C.c_int)]
         L.or_prepare_light.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), C.POINTER(vp)]
         L.or_edge_weight.argtypes = [vp, C.c_int64, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(U128)]
         L.or_philox4x32_10.argtypes = [vp, vp, vp]
@@ -289,3 +293,26 @@ def philox4x32_10(ctr, key):
 
 def draw(seed, j, d, n) -> int:
     return lib().or_draw(int(seed), int(j), int(d), U128.of(int(n))).value
+
+
+def tree_candidates(mo: Motif):
+    """[(Tree, looseness)] for every (spanning tree, center) pair (Alg. 8 order)."""
+    n = C.c_int()
+    rc = lib().or_tree_candidates(C.byref(mo), None, None, 0, C.byref(n))
+    if rc != OR_OK:
+        raise OracleError(rc, "tree_candidates")
+    trees = (Tree * n.value)()
+    loose = (C.c_int64 * n.value)()
+    lib().or_tree_candidates(C.byref(mo), trees, loose, n.value, C.byref(n))
+    return [(trees[x], int(loose[x])) for x in range(n.value)]
+
+
+def choose_tree(g: "Graph", mo: Motif, n_c):
+    """(best Tree, [W per evaluated candidate]) by Alg. 7."""
+    best = Tree()
+    Ws = (U128 * max(1, n_c))()
+    ne = C.c_int()
+    rc = lib().or_choose_tree(g.h, C.byref(mo), int(n_c), C.byref(best), Ws, C.byref(ne))
+    if rc != OR_OK:
+        raise OracleError(rc, "choose_tree")
+    return best, [Ws[x].value for x in range(ne.value)]

@@ -278,6 +278,84 @@ extern "C" int or_default_tree(const or_motif* mo, or_tree* out) {
 }
 
 // ------------------------------------------------------------------------
+// Alg. 8 (constraint looseness) and Alg. 7 (choose the tree by W).
+// ------------------------------------------------------------------------
+struct OCand {
+    long loose;
+    std::vector<int> edges;
+    int height;
+    int center;
+};
+
+// Every spanning tree (edge subsets of size k-1 that connect the motif), each
+// with every choice of center.
+static std::vector<OCand> all_candidates(const or_motif* mo) {
+    std::vector<OCand> out;
+    const int need = mo->k - 1;
+    std::vector<int> idx(need);
+    for (int j = 0; j < need; ++j) idx[j] = j;
+    while (need > 0) {
+        int cur[8];
+        for (int j = 0; j < need; ++j) cur[j] = idx[j];
+        if (is_spanning_tree(mo, cur, need)) {
+            // Alg. 8 (reading: over the tree's own edges): for every vertex,
+            // every unordered pair of tree edges on it adds |pi(e1) - pi(e2)| - 1
+            long loose = 0;
+            for (int x = 0; x < mo->k; ++x)
+                for (int a = 0; a < need; ++a)
+                    for (int b = a + 1; b < need; ++b) {
+                        const bool ia = mo->src[cur[a]] == x || mo->dst[cur[a]] == x;
+                        const bool ib = mo->src[cur[b]] == x || mo->dst[cur[b]] == x;
+                        if (ia && ib) loose += std::abs(cur[a] - cur[b]) - 1;
+                    }
+            for (int j = 0; j < need; ++j) {
+                or_tree t;
+                std::memset(&t, 0, sizeof t);
+                t.n_edges = need;
+                for (int x = 0; x < need; ++x) t.edge[x] = cur[x];
+                t.center = cur[j];
+                Plan P;
+                make_plan(mo, &t, P);
+                out.push_back(OCand{loose, std::vector<int>(cur, cur + need), P.H, cur[j]});
+            }
+        }
+        int j = need - 1;
+        while (j >= 0 && idx[j] == mo->l - need + j) --j;
+        if (j < 0) break;
+        ++idx[j];
+        for (int j2 = j + 1; j2 < need; ++j2) idx[j2] = idx[j2 - 1] + 1;
+    }
+    std::stable_sort(out.begin(), out.end(), [](const OCand& a, const OCand& b) {
+        if (a.loose != b.loose) return a.loose < b.loose;
+        if (a.edges != b.edges) return a.edges < b.edges;
+        if (a.height != b.height) return a.height < b.height;
+        return a.center < b.center;
+    });
+    return out;
+}
+
+static or_tree cand_tree(const OCand& c) {
+    or_tree t;
+    std::memset(&t, 0, sizeof t);
+    t.n_edges = (int32_t)c.edges.size();
+    for (size_t x = 0; x < c.edges.size(); ++x) t.edge[x] = c.edges[x];
+    t.center = c.center;
+    return t;
+}
+
+extern "C" int or_tree_candidates(const or_motif* mo, or_tree* out, int64_t* looseness, int max_out,
+                                  int* n_out) {
+    if (!motif_ok(mo) || !n_out) return OR_EINVAL;
+    const std::vector<OCand> c = all_candidates(mo);
+    *n_out = (int)c.size();
+    for (int x = 0; x < max_out && x < (int)c.size(); ++x) {
+        out[x] = cand_tree(c[x]);
+        if (looseness) looseness[x] = c[x].loose;
+    }
+    return OR_OK;
+}
+
+// ------------------------------------------------------------------------
 // Preprocessing: Alg. 1 (intervals) and Alg. 2 (bottom-up s-weights).
 // ------------------------------------------------------------------------
 struct or_prep {
@@ -464,6 +542,33 @@ extern "C" int or_edge_weight(const or_prep* p, int64_t interval, int32_t s, int
 }
 
 extern "C" void or_prep_destroy(or_prep* p) { delete p; }
+
+// Alg. 7: W of the first n_c candidates (full preprocessing each); the
+// smallest W wins, the earlier candidate among equals.
+extern "C" int or_choose_tree(const or_graph* g, const or_motif* mo, int n_c, or_tree* best, or_u128* W_out,
+                              int* n_eval) {
+    if (!g || !best || n_c < 1 || !motif_ok(mo)) return OR_EINVAL;
+    const std::vector<OCand> c = all_candidates(mo);
+    const int n = std::min<int>(n_c, (int)c.size());
+    int arg = -1;
+    u128 bestW = 0;
+    for (int x = 0; x < n; ++x) {
+        const or_tree t = cand_tree(c[x]);
+        or_prep* p = nullptr;
+        const int rc = or_prepare(g, mo, &t, &p);
+        if (rc != OR_OK) return rc;
+        const u128 W = p->W;
+        or_prep_destroy(p);
+        if (W_out) W_out[x] = to_or(W);
+        if (arg < 0 || W < bestW) {
+            arg = x;
+            bestW = W;
+        }
+    }
+    *best = cand_tree(c[arg]);
+    if (n_eval) *n_eval = n;
+    return OR_OK;
+}
 extern "C" or_u128 or_prep_W(const or_prep* p) { return to_or(p->W); }
 extern "C" int64_t or_prep_q(const or_prep* p) { return p->q; }
 

@@ -99,6 +99,14 @@ int64_t or_graph_list(const or_graph* g, int32_t vertex, int dir, int32_t* eids,
 /* Default spanning tree and center of a motif. */
 int or_default_tree(const or_motif* mo, or_tree* out);
 
+/* ---- choosing the tree (Alg. 7 / Alg. 8) ---------------------------- */
+/* Every (spanning tree, center) pair, by looseness, then edge set, height,
+ * center; at most max_out written, *n_out = their number. */
+int or_tree_candidates(const or_motif* mo, or_tree* out, int64_t* looseness, int max_out, int* n_out);
+/* W of the first n_c candidates (or_prepare each); the smallest wins. */
+int or_choose_tree(const or_graph* g, const or_motif* mo, int n_c, or_tree* best, or_u128* W_out,
+                   int* n_eval);
+
 /* ---- preprocessing (Alg. 1 / Alg. 2) -------------------------------- */
 int or_prepare(const or_graph* g, const or_motif* mo, const or_tree* tr, or_prep** out);
 void or_prep_destroy(or_prep* p);

@@ -386,6 +386,114 @@ extern "C" int tm_graph_export(const tm_graph* g, int which, void* host_out, voi
     return TM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Choosing the spanning tree (Sec. "Choosing the Spanning Tree", Alg. 7 and 8).
+// ---------------------------------------------------------------------------
+namespace {
+struct TreeCand {
+    long loose;
+    int32_t e[8];
+    int c;
+    int H;
+    int center;
+};
+
+// Every (spanning tree, center) pair with its constraint looseness (per motif
+// vertex, over unordered pairs of tree edges incident to it, |pi(e1) - pi(e2)| - 1)
+// and rooted height; ordered by looseness, then edge set, height and center.
+int tree_cands(const tm_motif* mo, std::vector<TreeCand>& out) {
+    out.clear();
+    const int need = mo->k - 1;
+    for (uint32_t mask = 0; mask < (1u << mo->l); ++mask) {
+        if (__builtin_popcount(mask) != need) continue;
+        TreeCand t;
+        t.c = 0;
+        for (int p = 0; p < mo->l; ++p)
+            if (mask >> p & 1) t.e[t.c++] = p;
+        if (!spanning_tree_of(mo, t.e, t.c)) continue;
+        t.loose = 0;
+        for (int x = 0; x < mo->k; ++x) {
+            int inc[8], ni = 0;
+            for (int j = 0; j < t.c; ++j)
+                if (mo->src[t.e[j]] == x || mo->dst[t.e[j]] == x) inc[ni++] = t.e[j];
+            for (int a = 0; a < ni; ++a)
+                for (int b = a + 1; b < ni; ++b) t.loose += std::abs(inc[a] - inc[b]) - 1;
+        }
+        for (int j = 0; j < t.c; ++j) {
+            tm_tree tr;
+            std::memset(&tr, 0, sizeof tr);
+            tr.n_edges = t.c;
+            std::memcpy(tr.edge, t.e, sizeof(int32_t) * t.c);
+            tr.center = t.e[j];
+            HostPlan P;
+            TM_TRY(plan_build(mo, &tr, &P));
+            TreeCand u = t;
+            u.center = t.e[j];
+            u.H = P.H;
+            out.push_back(u);
+        }
+    }
+    std::stable_sort(out.begin(), out.end(), [](const TreeCand& a, const TreeCand& b) {
+        if (a.loose != b.loose) return a.loose < b.loose;
+        if (!std::equal(a.e, a.e + a.c, b.e)) return std::lexicographical_compare(a.e, a.e + a.c, b.e, b.e + b.c);
+        if (a.H != b.H) return a.H < b.H;
+        return a.center < b.center;
+    });
+    return TM_OK;
+}
+
+tm_tree to_tree(const TreeCand& t) {
+    tm_tree tr;
+    std::memset(&tr, 0, sizeof tr);
+    tr.n_edges = t.c;
+    std::memcpy(tr.edge, t.e, sizeof(int32_t) * t.c);
+    tr.center = t.center;
+    return tr;
+}
+}  // namespace
+
+extern "C" int tm_tree_candidates(const tm_motif* mo, tm_tree* out, int64_t* looseness, int max_out, int* n_out) {
+    TM_TRY(motif_check(mo));
+    if (max_out < 0 || (max_out > 0 && !out) || !n_out) return tm_fail(TM_EINVAL, "tree_candidates: bad arguments");
+    std::vector<TreeCand> c;
+    TM_TRY(tree_cands(mo, c));
+    *n_out = (int)c.size();
+    for (int x = 0; x < max_out && x < (int)c.size(); ++x) {
+        out[x] = to_tree(c[x]);
+        if (looseness) looseness[x] = c[x].loose;
+    }
+    return TM_OK;
+}
+
+extern "C" int tm_choose_tree(tm_graph* g, const tm_motif* mo, int n_c, void* stream, tm_tree* best,
+                              tm_u128* W_out, int* n_eval) {
+    if (!g || !best || n_c < 1) return tm_fail(TM_EINVAL, "choose_tree: bad arguments");
+    TM_TRY(motif_check(mo));
+    std::vector<TreeCand> c;
+    TM_TRY(tree_cands(mo, c));
+    const int n = std::min<int>(n_c, (int)c.size());
+    int arg = -1;
+    u128 bestW = 0;
+    for (int x = 0; x < n; ++x) {
+        const tm_tree tr = to_tree(c[x]);
+        tm_weights* w = nullptr;
+        TM_TRY(tm_weights_create(g, mo, &tr, stream, &w));
+        const u128 W = w->W;
+        tm_weights_destroy(w);
+        if (W_out) {
+            W_out[x].lo = (u64)W;
+            W_out[x].hi = (u64)(W >> 64);
+        }
+        if (arg < 0 || W < bestW) {
+            arg = x;
+            bestW = W;
+        }
+    }
+    *best = to_tree(c[arg]);
+    if (n_eval) *n_eval = n;
+    return TM_OK;
+}
+
 extern "C" int tm_weights_create(tm_graph* g, const tm_motif* mo, const tm_tree* tr, void* stream,
                                  tm_weights** out) {
     if (!g || !out) return tm_fail(TM_EINVAL, "weights: NULL argument");

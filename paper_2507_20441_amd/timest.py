@@ -122,6 +122,10 @@ def lib():
                                         C.POINTER(u64), C.POINTER(u64), C.c_int, vp,
                                         C.POINTER(Result)]
         L.tm_batch_config.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.tm_tree_candidates.argtypes = [C.POINTER(Motif), C.POINTER(Tree), C.POINTER(i64), C.c_int,
+                                         C.POINTER(C.c_int)]
+        L.tm_choose_tree.argtypes = [vp, C.POINTER(Motif), C.c_int, vp, C.POINTER(Tree), C.POINTER(U128),
+                                     C.POINTER(C.c_int)]
         L.tm_batch_plan_create.argtypes = [C.POINTER(vp), C.POINTER(Motif), C.POINTER(C.POINTER(Tree)),
                                            C.POINTER(u64), C.POINTER(u64), C.c_int, vp, C.POINTER(vp)]
         L.tm_batch_plan_run.argtypes = [vp, vp, C.POINTER(Result)]
@@ -450,3 +454,24 @@ class BatchPlan:
 
     def __del__(self):
         self.close()
+
+
+def tree_candidates(mo: Motif):
+    """[(Tree, looseness)] for every (spanning tree, center) pair, in the
+    library's order (tm_tree_candidates)."""
+    n = C.c_int()
+    _check(lib().tm_tree_candidates(C.byref(mo), None, None, 0, C.byref(n)), "tree_candidates")
+    trees = (Tree * n.value)()
+    loose = (C.c_int64 * n.value)()
+    _check(lib().tm_tree_candidates(C.byref(mo), trees, loose, n.value, C.byref(n)), "tree_candidates")
+    return [(trees[x], int(loose[x])) for x in range(n.value)]
+
+
+def choose_tree(g: Graph, mo: Motif, n_c):
+    """(best Tree, [W of each evaluated candidate]) by tm_choose_tree."""
+    best = Tree()
+    Ws = (U128 * max(1, n_c))()
+    ne = C.c_int()
+    _check(lib().tm_choose_tree(g.h, C.byref(mo), int(n_c), _stream(), C.byref(best), Ws, C.byref(ne)),
+           "choose_tree")
+    return best, [Ws[x].value for x in range(ne.value)]
