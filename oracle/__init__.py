@@ -15,6 +15,9 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 OR_OK, OR_EINVAL, OR_ESELFLOOP, OR_EDUP, OR_EOVERFLOW, OR_ERANGE = 0, -1, -2, -3, -4, -5
 
 
+C_EXCLUDE, C_WINDOWS, C_ALL = 1, 2, 3  # constraints 2 and 3 (constraint 1 always)
+
+
 class U128(C.Structure):
     _fields_ = [("lo", C.c_uint64), ("hi", C.c_uint64)]
 
@@ -81,6 +84,12 @@ def lib():
                                          C.POINTER(C.c_int)]
         L.or_choose_tree.argtypes = [vp, C.POINTER(Motif), C.c_int, C.POINTER(Tree), C.POINTER(U128),
                                      C.POINTER(C.c_int)]
+        L.or_prepare_ex.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), C.c_uint32, C.POINTER(vp)]
+        L.or_prepare_light_ex.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), C.c_uint32, C.POINTER(vp)]
+        L.or_brute_tree_weight_ex.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), C.c_uint32, C.POINTER(U128)]
+        L.or_brute_partial_matches_ex.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), C.c_uint32, i64, vp,
+                                                  vp, vp, vp]
+        L.or_brute_partial_matches_ex.restype = i64
         L.or_prepare_light.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), C.POINTER(vp)]
         L.or_edge_weight.argtypes = [vp, C.c_int64, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(U128)]
         L.or_philox4x32_10.argtypes = [vp, vp, vp]
@@ -182,9 +191,9 @@ class Graph:
             raise OracleError(rc, "brute_count")
         return c.value
 
-    def brute_tree_weight(self, mo: Motif, tr: Tree) -> int:
+    def brute_tree_weight(self, mo: Motif, tr: Tree, constraints=C_ALL) -> int:
         c = U128()
-        rc = lib().or_brute_tree_weight(self.h, C.byref(mo), C.byref(tr), C.byref(c))
+        rc = lib().or_brute_tree_weight_ex(self.h, C.byref(mo), C.byref(tr), int(constraints), C.byref(c))
         if rc != OR_OK:
             raise OracleError(rc, "brute_tree_weight")
         return c.value
@@ -197,17 +206,17 @@ class Graph:
             raise OracleError(rc, "brute_edge_weight")
         return c.value
 
-    def brute_partial_matches(self, mo, tr):
-        cnt = lib().or_brute_partial_matches(self.h, C.byref(mo), C.byref(tr), 0, None, None,
-                                             None, None)
+    def brute_partial_matches(self, mo, tr, constraints=C_ALL):
+        cnt = lib().or_brute_partial_matches_ex(self.h, C.byref(mo), C.byref(tr), int(constraints), 0, None,
+                                                None, None, None)
         if cnt < 0:
             raise OracleError(cnt, "brute_partial_matches")
         eids = np.empty((cnt, 8), np.int32)
         nphi = np.empty(cnt, np.uint32)
         status = np.empty(cnt, np.uint32)
         mphi = np.empty(cnt, U128_DTYPE)
-        lib().or_brute_partial_matches(self.h, C.byref(mo), C.byref(tr), cnt, _ptr(eids),
-                                       _ptr(nphi), _ptr(status), _ptr(mphi))
+        lib().or_brute_partial_matches_ex(self.h, C.byref(mo), C.byref(tr), int(constraints), cnt, _ptr(eids),
+                                          _ptr(nphi), _ptr(status), _ptr(mphi))
         return eids, nphi, status, u128_array_to_int(mphi)
 
 
@@ -215,12 +224,12 @@ class Prep:
     """Weights of one (graph, motif, tree) -- Alg. 1 / Alg. 2.  light=True
     builds no tables: only edge_weight and derive_cnt are then available."""
 
-    def __init__(self, g: Graph, mo: Motif, tr: Tree = None, light=False):
+    def __init__(self, g: Graph, mo: Motif, tr: Tree = None, light=False, constraints=C_ALL):
         self.g, self.mo = g, mo
         self.tr = tr if tr is not None else default_tree(mo)
         h = C.c_void_p()
-        fn = lib().or_prepare_light if light else lib().or_prepare
-        rc = fn(g.h, C.byref(mo), C.byref(self.tr), C.byref(h))
+        fn = lib().or_prepare_light_ex if light else lib().or_prepare_ex
+        rc = fn(g.h, C.byref(mo), C.byref(self.tr), int(constraints), C.byref(h))
         if rc != OR_OK:
             raise OracleError(rc, "prepare")
         self.h = h

@@ -163,13 +163,15 @@ struct PMCtx {
     int32_t img_v[8];
     int32_t img_e[16];
     int first;                 // index in T->order where the enumeration starts
+    bool exclude;              // constraint 2: a child shares exactly one vertex with its parent
     // collection of whole matches (optional)
     std::vector<std::vector<int32_t>>* found;
     u128 count;
 };
 
 static bool parent_child_ok(const PMCtx& C, int s, int c, const OEdge& Ep, const OEdge& Ec) {
-    if (shared_vertices(Ep, Ec) != 1) return false;
+    const int sh = shared_vertices(Ep, Ec);
+    if (C.exclude ? sh != 1 : sh < 1) return false;
     if (c > s) return Ec.t >= Ep.t && Ec.t <= Ep.t + C.delta;
     return Ec.t >= Ep.t - C.delta && Ec.t <= Ep.t;
 }
@@ -220,19 +222,33 @@ static void pm_init(PMCtx& C, const or_graph* g, const Tree* T, int64_t delta, i
     for (int z = 0; z < 8; ++z) C.img_v[z] = -1;
     for (int z = 0; z < 16; ++z) C.img_e[z] = -1;
     C.first = 0;
+    C.exclude = true;
     C.found = nullptr;
     C.count = 0;
 }
 
+// Interval unit under the constraint flags: delta with constraint 3, else one
+// interval over the whole span.
+static int64_t unit_of(const or_graph* g, const or_motif* mo, uint32_t flags) {
+    return (flags & OR_C_WINDOWS) ? mo->delta : g->T + 1;
+}
+
 extern "C" int or_brute_tree_weight(const or_graph* g, const or_motif* mo, const or_tree* tr, or_u128* W) {
+    return or_brute_tree_weight_ex(g, mo, tr, OR_C_ALL, W);
+}
+
+extern "C" int or_brute_tree_weight_ex(const or_graph* g, const or_motif* mo, const or_tree* tr, uint32_t flags,
+                                       or_u128* W) {
     if (!g || !W || !motif_basic_ok(mo)) return OR_EINVAL;
     Tree T;
     if (!build_tree(mo, tr, T)) return OR_EINVAL;
     u128 total = 0;
-    int64_t q = g->m > 0 ? g->T / mo->delta + 1 : 0;
+    const int64_t L = unit_of(g, mo, flags);
+    int64_t q = g->m > 0 ? g->T / L + 1 : 0;
     for (int64_t i = 0; i < q; ++i) {
         PMCtx C;
-        pm_init(C, g, &T, mo->delta, i * mo->delta, (i + 2) * mo->delta);
+        pm_init(C, g, &T, mo->delta, i * L, (i + 2) * L);
+        C.exclude = (flags & OR_C_EXCLUDE) != 0;
         pm_rec(C, 0);
         total += C.count;
     }
@@ -287,15 +303,23 @@ static void completion_rec(const or_graph* g, const or_motif* mo, const Tree& T,
 extern "C" int64_t or_brute_partial_matches(const or_graph* g, const or_motif* mo, const or_tree* tr,
                                             int64_t cap, int32_t* eids, uint32_t* n_phi,
                                             uint32_t* status, or_u128* m_phi_brute) {
+    return or_brute_partial_matches_ex(g, mo, tr, OR_C_ALL, cap, eids, n_phi, status, m_phi_brute);
+}
+
+extern "C" int64_t or_brute_partial_matches_ex(const or_graph* g, const or_motif* mo, const or_tree* tr,
+                                               uint32_t flags, int64_t cap, int32_t* eids, uint32_t* n_phi,
+                                               uint32_t* status, or_u128* m_phi_brute) {
     if (!g || !motif_basic_ok(mo)) return OR_EINVAL;
     Tree T;
     if (!build_tree(mo, tr, T)) return OR_EINVAL;
     std::vector<std::vector<int32_t>> found;
     PMCtx C;
     pm_init(C, g, &T, mo->delta, INT64_MIN, INT64_MAX);
+    C.exclude = (flags & OR_C_EXCLUDE) != 0;
     C.found = &found;
     pm_rec(C, 0);
-    int64_t q = g->m > 0 ? g->T / mo->delta + 1 : 0;
+    const int64_t L = unit_of(g, mo, flags);
+    int64_t q = g->m > 0 ? g->T / L + 1 : 0;
     for (int64_t a = 0; a < (int64_t)found.size() && a < cap; ++a) {
         const std::vector<int32_t>& f = found[a];
         int32_t img_e[16];
@@ -317,7 +341,7 @@ extern "C" int64_t or_brute_partial_matches(const or_graph* g, const or_motif* m
         // intervals I_i that hold every tree edge
         uint32_t np = 0;
         for (int64_t i = 0; i < q; ++i)
-            if (tmin >= i * mo->delta && tmax < (i + 2) * mo->delta) ++np;
+            if (tmin >= i * L && tmax < (i + 2) * L) ++np;
         if (n_phi) n_phi[a] = np;
         // literal validation, first failing cause
         uint32_t st = 0;

@@ -370,6 +370,13 @@ struct or_prep {
     std::vector<u128> cumW;            // cumW[i] = sum_{i'<i} W_i', q+1 entries
     std::vector<std::vector<u128>> root_cum;  // per interval: prefix of w_i(c,e) over G_i
     u128 W = 0;
+    // constraints (Sec. "A Closer Look at Preprocessing"): constraint 1 (order
+    // and delta between a tree edge and its parent) always; constraint 2
+    // (distinct end vertices of adjacent edges) when flags has OR_C_EXCLUDE;
+    // constraint 3 (the 2 delta intervals) when it has OR_C_WINDOWS, else a
+    // single interval over the whole span
+    uint32_t flags = OR_C_ALL;
+    int64_t ilen = 0;  // interval unit: delta, or T + 1 without constraint 3
 };
 
 static bool in_interval(int64_t t, int64_t i, int64_t delta) {
@@ -401,15 +408,20 @@ static void candidates(const or_prep& R, int64_t i, int s, int32_t e, int c,
     for (size_t x = first_at_or_after(G, L, wlo); x < L.size(); ++x) {
         const OEdge& F = G.e[L[x]];
         if (F.t > whi) break;
-        if (!in_interval(F.t, i, R.delta)) continue;
+        if (!in_interval(F.t, i, R.ilen)) continue;
         int32_t far = P.alpha[c] > 0 ? F.v : F.u;
-        if (far == o) continue;
+        if ((R.flags & OR_C_EXCLUDE) && far == o) continue;
         cand.push_back(L[x]);
     }
 }
 
 extern "C" int or_prepare(const or_graph* g, const or_motif* mo, const or_tree* tr, or_prep** out) {
-    if (!g || !out || !motif_ok(mo)) return OR_EINVAL;
+    return or_prepare_ex(g, mo, tr, OR_C_ALL, out);
+}
+
+extern "C" int or_prepare_ex(const or_graph* g, const or_motif* mo, const or_tree* tr, uint32_t flags,
+                             or_prep** out) {
+    if (!g || !out || !motif_ok(mo) || (flags & ~(uint32_t)OR_C_ALL)) return OR_EINVAL;
     or_tree def;
     if (!tr) {
         if (or_default_tree(mo, &def) != OR_OK) return OR_EINVAL;
@@ -420,7 +432,9 @@ extern "C" int or_prepare(const or_graph* g, const or_motif* mo, const or_tree* 
     R->g = g;
     make_plan(mo, tr, R->P);
     R->delta = mo->delta;
-    const int64_t d = R->delta;
+    R->flags = flags;
+    R->ilen = (flags & OR_C_WINDOWS) ? mo->delta : g->T + 1;
+    const int64_t d = R->ilen;
     // Alg. 1: q overlapping 2*delta intervals cover every match.
     R->q = g->m > 0 ? g->T / d + 1 : 0;
     R->lo.resize(R->q);
@@ -483,7 +497,12 @@ extern "C" int or_prepare(const or_graph* g, const or_motif* mo, const or_tree* 
 }
 
 extern "C" int or_prepare_light(const or_graph* g, const or_motif* mo, const or_tree* tr, or_prep** out) {
-    if (!g || !out || !motif_ok(mo)) return OR_EINVAL;
+    return or_prepare_light_ex(g, mo, tr, OR_C_ALL, out);
+}
+
+extern "C" int or_prepare_light_ex(const or_graph* g, const or_motif* mo, const or_tree* tr, uint32_t flags,
+                                   or_prep** out) {
+    if (!g || !out || !motif_ok(mo) || (flags & ~(uint32_t)OR_C_ALL)) return OR_EINVAL;
     or_tree def;
     if (!tr) {
         if (or_default_tree(mo, &def) != OR_OK) return OR_EINVAL;
@@ -494,7 +513,9 @@ extern "C" int or_prepare_light(const or_graph* g, const or_motif* mo, const or_
     R->g = g;
     make_plan(mo, tr, R->P);
     R->delta = mo->delta;
-    R->q = g->m > 0 ? g->T / mo->delta + 1 : 0;
+    R->flags = flags;
+    R->ilen = (flags & OR_C_WINDOWS) ? mo->delta : g->T + 1;
+    R->q = g->m > 0 ? g->T / R->ilen + 1 : 0;
     *out = R;
     return OR_OK;
 }
@@ -532,7 +553,7 @@ extern "C" int or_edge_weight(const or_prep* p, int64_t interval, int32_t s, int
                               or_u128* w) {
     if (!p || !w || eid < 0 || eid >= p->g->m || interval < 0 || interval >= p->q) return OR_EINVAL;
     if (s < 0 || s >= p->P.mo.l || !p->P.in_tree[s]) return OR_EINVAL;
-    if (!in_interval(p->g->e[eid].t, interval, p->delta)) return OR_EINVAL;
+    if (!in_interval(p->g->e[eid].t, interval, p->ilen)) return OR_EINVAL;
     uint64_t budget = work_limit;
     u128 x;
     const int rc = lazy_weight(*p, interval, s, eid, budget, &x);
@@ -580,7 +601,7 @@ extern "C" int or_prep_weights(const or_prep* p, int32_t s, int slot, or_u128* o
     if (s < 0 || s >= p->P.mo.l || !p->P.in_tree[s] || slot < 0 || slot > 1) return OR_EINVAL;
     const or_graph& G = *p->g;
     for (int64_t e = 0; e < G.m; ++e) {
-        int64_t i = G.e[e].t / p->delta - slot;
+        int64_t i = G.e[e].t / p->ilen - slot;
         if (i < 0 || i >= p->q) { out[e] = to_or(0); continue; }
         out[e] = to_or(weight(*p, i, s, (int32_t)e));
     }
@@ -713,8 +734,8 @@ static int validate_and_derive(const or_prep& R, const int32_t* img_e /* indexed
     // N_phi: the number of intervals that contain every tree edge.  Only the
     // intervals starting at or before t_min and after t_min - 2*delta can.
     uint32_t cnt = 0;
-    for (int64_t i = std::max<int64_t>(0, tmin / R.delta - 1); i <= tmin / R.delta + 1 && i < R.q; ++i)
-        if (i * R.delta <= tmin && tmax < (i + 2) * R.delta) ++cnt;
+    for (int64_t i = std::max<int64_t>(0, tmin / R.ilen - 1); i <= tmin / R.ilen + 1 && i < R.q; ++i)
+        if (i * R.ilen <= tmin && tmax < (i + 2) * R.ilen) ++cnt;
     *n_phi = cnt;
     // Alg. 5: for each non-tree motif edge, the edges of G that can match it
     // (binary search on the multi-edge list to the times any completion can

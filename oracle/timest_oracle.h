@@ -109,6 +109,15 @@ int or_choose_tree(const or_graph* g, const or_motif* mo, int n_c, or_tree* best
 
 /* ---- preprocessing (Alg. 1 / Alg. 2) -------------------------------- */
 int or_prepare(const or_graph* g, const or_motif* mo, const or_tree* tr, or_prep** out);
+/* Constraint flags (Sec. "A Closer Look at Preprocessing"; Tab. "constraints"):
+ * constraint 1 (order and delta between a tree edge and its parent) always;
+ * OR_C_EXCLUDE adds constraint 2 (a child's far endpoint differs from the
+ * parent's other endpoint); OR_C_WINDOWS adds constraint 3 (overlapping
+ * 2 delta intervals; without it one interval spans all times, N_phi = 1). */
+#define OR_C_EXCLUDE 1u
+#define OR_C_WINDOWS 2u
+#define OR_C_ALL 3u
+int or_prepare_ex(const or_graph* g, const or_motif* mo, const or_tree* tr, uint32_t flags, or_prep** out);
 void or_prep_destroy(or_prep* p);
 or_u128 or_prep_W(const or_prep* p);
 int64_t or_prep_q(const or_prep* p);
@@ -123,6 +132,8 @@ int or_prep_weights(const or_prep* p, int32_t s, int slot, or_u128* out);
  * count only.  For graphs too large for or_prepare; serves or_edge_weight
  * and or_derive_cnt (the table functions and or_sample need or_prepare). */
 int or_prepare_light(const or_graph* g, const or_motif* mo, const or_tree* tr, or_prep** out);
+int or_prepare_light_ex(const or_graph* g, const or_motif* mo, const or_tree* tr, uint32_t flags,
+                        or_prep** out);
 /* w_i(s,e) for one edge, evaluated from Claim "overall-num-matches" by
  * recursion over the candidate lists (no tables).  eid must lie in I_i.
  * OR_ERANGE when more than work_limit candidates would be visited. */
@@ -147,6 +158,8 @@ or_u128 or_draw(uint64_t seed, uint64_t j, uint32_t d, or_u128 n);
 int or_brute_count(const or_graph* g, const or_motif* mo, or_u128* C);
 /* sum over intervals i of the number of delta-partial matches of S in G_i */
 int or_brute_tree_weight(const or_graph* g, const or_motif* mo, const or_tree* tr, or_u128* W);
+int or_brute_tree_weight_ex(const or_graph* g, const or_motif* mo, const or_tree* tr, uint32_t flags,
+                            or_u128* W);
 /* number of partial matches in G_i of the subtree below tree edge s, with s
  * matched to edge eid (eid must lie in I_i) */
 int or_brute_edge_weight(const or_graph* g, const or_motif* mo, const or_tree* tr,
@@ -159,6 +172,9 @@ int or_brute_edge_weight(const or_graph* g, const or_motif* mo, const or_tree* t
 int64_t or_brute_partial_matches(const or_graph* g, const or_motif* mo, const or_tree* tr,
                                  int64_t cap, int32_t* eids, uint32_t* n_phi,
                                  uint32_t* status, or_u128* m_phi_brute);
+int64_t or_brute_partial_matches_ex(const or_graph* g, const or_motif* mo, const or_tree* tr, uint32_t flags,
+                                    int64_t cap, int32_t* eids, uint32_t* n_phi, uint32_t* status,
+                                    or_u128* m_phi_brute);
 
 #ifdef __cplusplus
 }
