@@ -51,6 +51,17 @@ enum tm_error {
 
 enum tm_ptr_kind { TM_PTR_HOST = 0, TM_PTR_DEVICE = 1 };
 
+/* Constraints on the sampled tree matches (Sec. "A Closer Look at
+ * Preprocessing"; Tab. "constraints"): constraint 1 -- order and delta
+ * between a tree edge and its parent -- always holds; TM_C_EXCLUDE adds
+ * constraint 2 (a child's far endpoint differs from the parent's other
+ * endpoint), TM_C_WINDOWS constraint 3 (the overlapping 2 delta intervals;
+ * without it one interval spans all times and N_phi = 1).  Every mode gives
+ * an unbiased estimate; the default is TM_C_ALL. */
+#define TM_C_EXCLUDE 1u
+#define TM_C_WINDOWS 2u
+#define TM_C_ALL 3u
+
 /* result flags */
 #define TM_F_W_ZERO 1u        /* no partial match exists: estimate is 0 */
 #define TM_F_SQ_SATURATED 2u  /* acc2_sq reached 2^128 - 1 and stopped */
@@ -174,6 +185,9 @@ int tm_default_tree(const tm_motif* mo, tm_tree* out);
  * TM_ERANGE (bit limits above), TM_EOVERFLOW, TM_ENOMEM, TM_EDEVICE. */
 int tm_weights_create(tm_graph* g, const tm_motif* mo, const tm_tree* tr, void* stream,
                       tm_weights** out);
+/* tm_weights_create under a subset of the constraints (TM_C_*). */
+int tm_weights_create_ex(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32_t constraints,
+                         void* stream, tm_weights** out);
 void tm_weights_destroy(tm_weights* w);
 
 /* W, the interval count q, whether 128-bit weights were needed, the device
@@ -208,6 +222,9 @@ int tm_sample(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count, uint64_
  * k), tm_weights_destroy. */
 int tm_estimate(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint64_t k,
                 uint64_t seed, void* stream, tm_result* out);
+/* tm_estimate under a subset of the constraints (TM_C_*). */
+int tm_estimate_ex(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32_t constraints, uint64_t k,
+                   uint64_t seed, void* stream, tm_result* out);
 
 /* ---- batched estimation (many jobs in one pass) -------------------------
  * Every job's samples are drawn exactly as tm_sample draws them (same seed,

@@ -496,7 +496,13 @@ extern "C" int tm_choose_tree(tm_graph* g, const tm_motif* mo, int n_c, void* st
 
 extern "C" int tm_weights_create(tm_graph* g, const tm_motif* mo, const tm_tree* tr, void* stream,
                                  tm_weights** out) {
+    return tm_weights_create_ex(g, mo, tr, TM_C_ALL, stream, out);
+}
+
+extern "C" int tm_weights_create_ex(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32_t constraints,
+                                    void* stream, tm_weights** out) {
     if (!g || !out) return tm_fail(TM_EINVAL, "weights: NULL argument");
+    if (constraints & ~(uint32_t)TM_C_ALL) return tm_fail(TM_EINVAL, "weights: constraints %u", constraints);
     TM_TRY(motif_check(mo));
     tm_tree def;
     if (!tr) {
@@ -507,6 +513,7 @@ extern "C" int tm_weights_create(tm_graph* g, const tm_motif* mo, const tm_tree*
     if (!w) return tm_fail(TM_ENOMEM, "weights: host allocation");
     w->g = g;
     w->arena.stream = as_stream(stream);
+    w->constraints = constraints;
     int rc = plan_build(mo, tr, &w->plan);
     if (rc == TM_OK) rc = weights_build(w, as_stream(stream));
     if (rc != TM_OK) {
@@ -594,7 +601,7 @@ extern "C" int tm_weights_export(const tm_weights* w, int32_t s, int32_t slot, t
         return w->wide ? v : (u128)(u64)v;
     };
     for (int64_t e = 0; e < m; ++e) {
-        const int64_t i = t[e] / P.mo.delta - slot;
+        const int64_t i = t[e] / w->ilen - slot;
         tm_u128 x = {0, 0};
         if (i >= 0 && i < w->q) {
             if (leaf) {
@@ -673,9 +680,14 @@ extern "C" int tm_sample_model_bytes(tm_weights* w, uint64_t seed, uint64_t j0, 
 
 extern "C" int tm_estimate(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint64_t k,
                            uint64_t seed, void* stream, tm_result* out) {
+    return tm_estimate_ex(g, mo, tr, TM_C_ALL, k, seed, stream, out);
+}
+
+extern "C" int tm_estimate_ex(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32_t constraints,
+                              uint64_t k, uint64_t seed, void* stream, tm_result* out) {
     if (!out) return tm_fail(TM_EINVAL, "estimate: NULL output");
     tm_weights* w = nullptr;
-    TM_TRY(tm_weights_create(g, mo, tr, stream, &w));
+    TM_TRY(tm_weights_create_ex(g, mo, tr, constraints, stream, &w));
     const int rc = tm_sample(w, seed, 0, k, k, stream, out, nullptr);
     tm_weights_destroy(w);
     return rc;

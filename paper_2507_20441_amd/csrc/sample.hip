@@ -29,6 +29,8 @@ namespace {
 struct SampleArgs {
     DevGraph G;
     int64_t delta;
+    int64_t ilen;  // interval unit (delta, or one interval over all times)
+    int exclude;   // constraint 2: candidates exclude the parent's other endpoint
     int64_t q;
     int k;
     int nt;
@@ -461,7 +463,7 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
             te[0] = G.lt[0][pos];
             ev[0] = G.lnbr[0][pos];
             eu[0] = G.src[e0];
-            const int64_t blk = te[0] / a.delta;
+            const int64_t blk = te[0] / a.ilen;
             i = (int32_t)(((blk & 1) == (int64_t)(key & 1)) ? blk : blk - 1);
             if constexpr (kCount) nb += 8 + 20;
         } else {
@@ -479,7 +481,7 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
         const int par = i & 1;
         put(img, a.esrc[0], eu[0]);
         put(img, a.edst[0], ev[0]);
-        const int64_t ilo_t = (int64_t)i * a.delta, ihi_t = ((int64_t)i + 2) * a.delta - 1;
+        const int64_t ilo_t = (int64_t)i * a.ilen, ihi_t = ((int64_t)i + 2) * a.ilen - 1;
         Bounds last;  // the previous child's window, reused by a leaf sibling with the same one
         last.p0 = last.p1 = last.q0 = last.q1 = last.a = last.b = 0;
         // draws 1..nt-1: children in pre-order
@@ -496,7 +498,8 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
             wlo = wlo > ilo_t ? wlo : ilo_t;
             whi = whi < ihi_t ? whi : ihi_t;
             const int d = a.dir[s];
-            const Bounds w = a.same_window[s] ? last : window_bounds(G, d, g, o, wlo, whi);
+            Bounds w = a.same_window[s] ? last : window_bounds(G, d, g, o, wlo, whi);
+            if (!a.exclude) w.q1 = w.q0;  // constraint 2 off: nothing excluded
             last = w;
             const bool leaf = a.leaf[s] != 0;
             const W* qt = static_cast<const W*>(a.qt[s][par]);
@@ -580,9 +583,9 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
         u128 m_phi = 0;
         if (status == 0) {
             // N_phi: intervals holding every tree edge (I_b always; I_{b-1}
-            // when the last time is still below (b+1) delta)
-            const int64_t b = tmin / a.delta;
-            n_phi = (b < a.q ? 1u : 0u) + ((b >= 1 && tmax < (b + 1) * a.delta) ? 1u : 0u);
+            // when the last time is still below (b+1) L)
+            const int64_t b = tmin / a.ilen;
+            n_phi = (b < a.q ? 1u : 0u) + ((b >= 1 && tmax < (b + 1) * a.ilen) ? 1u : 0u);
             // Alg. 5: completions over the non-tree edges
             const int64_t tfirst = pick(te, a.by_pi[0]), tlast = pick(te, a.by_pi[a.nt - 1]);
             if constexpr (kGeneral) {
@@ -766,6 +769,8 @@ void fill_args(const tm_weights* w, SampleArgs* out, size_t* lds_out) {
     std::memset(&a, 0, sizeof a);
     a.G = w->g->d;
     a.delta = P.mo.delta;
+    a.ilen = w->ilen;
+    a.exclude = (w->constraints & TM_C_EXCLUDE) ? 1 : 0;
     a.q = w->q;
     a.k = P.mo.k;
     a.nt = P.nt;

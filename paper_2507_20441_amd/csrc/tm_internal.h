@@ -124,6 +124,10 @@ struct tm_weights {
     bool wide = false;
     int64_t q = 0;
     u128 W = 0;
+    // constraints 2 (exclusion) and 3 (2 delta intervals), TM_C_*; ilen is the
+    // interval unit: delta with constraint 3, else T + 1 (one interval)
+    uint32_t constraints = TM_C_ALL;
+    int64_t ilen = 0;
     void* vals[kMaxSlots][2] = {};  // build temporaries, null afterwards
     void* qt[kMaxSlots][2] = {};
     void* qn[kMaxSlots][2] = {};

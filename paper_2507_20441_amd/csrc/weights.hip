@@ -38,6 +38,8 @@ struct ChildDesc {
 struct LevelArgs {
     DevGraph G;
     int64_t delta;
+    int64_t ilen;   // interval unit (delta, or one interval over all times)
+    int exclude;    // constraint 2: drop the run of the excluded far endpoint
     int nc;
     ChildDesc c[kMaxSlots];
     int walk;          // -1: eid order; 0 / 1: the T order of the out- / in-lists
@@ -65,7 +67,7 @@ struct Bounds3 {
 };
 
 __device__ __forceinline__ Bounds3 three_bounds(const DevGraph& G, int dir, int32_t g, int32_t o,
-                                                const int64_t (&xs)[3]) {
+                                                const int64_t (&xs)[3], bool exclude) {
     const int32_t a = G.off[dir][g], b = G.off[dir][g + 1];
     const int64_t* lt = G.lt[dir];
     const u64* nk = G.nkey[dir];
@@ -105,6 +107,7 @@ __device__ __forceinline__ Bounds3 three_bounds(const DevGraph& G, int dir, int3
         r.p[j] = a == b ? a : c[j] + (lt[c[j]] < x[j] ? 1 : 0);
         const u64 zl = nk[c[3 + j]];
         r.q[j] = a == b ? a : c[3 + j] + ((zl < kx[j] || (le[j] && zl == kx[j])) ? 1 : 0);
+        if (!exclude) r.q[j] = a;  // no excluded run
     }
     return r;
 }
@@ -121,10 +124,13 @@ __device__ __forceinline__ W window_mass(int32_t p0, int32_t p1, int32_t q0, int
 }
 
 // One thread per edge e and both intervals holding it: slot A is
-// i = floor(t / delta) = blk, slot B is i - 1.  Clipped to those intervals,
-// a child window [t - delta, t] becomes [blk delta, t] (A) and [t - delta, t]
-// (B), and [t, t + delta] becomes [t, t + delta] (A) and
-// [t, (blk + 1) delta - 1] (B): three distinct bounds per child.
+// i = floor(t / L) = blk, slot B is i - 1 (L: the interval unit).  Clipped to
+// those intervals, a child window [t - delta, t] becomes
+// [max(t - delta, blk L), t] (A) and [max(t - delta, (blk - 1) L), t] (B), and
+// [t, t + delta] becomes [t, min(t + delta, (blk + 2) L - 1)] (A) and
+// [t, min(t + delta, (blk + 1) L - 1)] (B): three distinct bounds per child
+// (with L = delta: [blk delta, t], [t - delta, t], [t, t + delta] and
+// [t, (blk + 1) delta - 1]).
 template <typename W>
 __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -133,7 +139,7 @@ __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
     const int32_t e = a.walk < 0 ? (int32_t)p : G.leid[a.walk][p];
     const int32_t u = G.src[e], v = G.dst[e];
     const int64_t t = G.t[e];
-    const int64_t blk = t / a.delta;
+    const int64_t blk = t / a.ilen;
     const bool hasB = blk >= 1;
     const int parA = (int)(blk & 1), parB = parA ^ 1;
     W prodA = 1, prodB = hasB ? (W)1 : (W)0;
@@ -156,15 +162,17 @@ __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
             //   after:  A = [x0, x1), B = [x0, x2) with x0 = t, x1 = t + delta + 1, x2 = (blk + 1) delta
             int64_t xs[3];
             if (d.beta < 0) {
-                xs[0] = blk * a.delta;
-                xs[1] = t - a.delta;
+                const int64_t lo = t - a.delta;
+                xs[0] = lo > blk * a.ilen ? lo : blk * a.ilen;
+                xs[1] = lo > (blk - 1) * a.ilen ? lo : (blk - 1) * a.ilen;
                 xs[2] = t + 1;
             } else {
+                const int64_t hi = t + a.delta;
                 xs[0] = t;
-                xs[1] = t + a.delta + 1;
-                xs[2] = (blk + 1) * a.delta;
+                xs[1] = (hi < (blk + 2) * a.ilen - 1 ? hi : (blk + 2) * a.ilen - 1) + 1;
+                xs[2] = (hi < (blk + 1) * a.ilen - 1 ? hi : (blk + 1) * a.ilen - 1) + 1;
             }
-            const Bounds3 r = three_bounds(G, d.dir, g, o, xs);
+            const Bounds3 r = three_bounds(G, d.dir, g, o, xs, a.exclude != 0);
             if (d.beta < 0) {
                 xa = window_mass<W>(r.p[0], r.p[2], r.q[0], r.q[2], d.leaf, d.qt[parA], d.qn[parA]);
                 xb = hasB ? window_mass<W>(r.p[1], r.p[2], r.q[1], r.q[2], d.leaf, d.qt[parB], d.qn[parB]) : (W)0;
@@ -297,6 +305,8 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
                 std::memset(&a, 0, sizeof a);
                 a.G = g->d;
                 a.delta = delta;
+                a.ilen = w->ilen;
+                a.exclude = (w->constraints & TM_C_EXCLUDE) ? 1 : 0;
                 a.nc = (int)cs.size();
                 for (int j = 0; j < a.nc; ++j) {
                     const int c = cs[j];
@@ -369,7 +379,7 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
     TM_TRY(arena_alloc(w->arena, &w->ilo, (size_t)w->q));
     TM_TRY(arena_alloc(w->arena, &w->ihi, (size_t)w->q));
     hipLaunchKernelGGL(interval_kernel, dim3(grid_for(w->q)), dim3(kBlock), 0, st, g->d.t, m, w->q,
-                       delta, w->ilo, w->ihi);
+                       w->ilen, w->ilo, w->ihi);
     TM_HIP(hipGetLastError());
     W* cum;
     TM_TRY(arena_alloc(w->arena, &cum, (size_t)w->q + 1));
@@ -411,10 +421,14 @@ void clear_tables(tm_weights* w) {
 
 }  // namespace
 
+int64_t interval_unit(const tm_weights* w) {
+    return (w->constraints & TM_C_WINDOWS) ? w->plan.mo.delta : w->g->T + 1;
+}
+
 int weights_build(tm_weights* w, hipStream_t st) {
     tm_graph* g = w->g;
-    const int64_t delta = w->plan.mo.delta;
-    w->q = g->m > 0 ? g->T / delta + 1 : 0;
+    w->ilen = interval_unit(w);
+    w->q = g->m > 0 ? g->T / w->ilen + 1 : 0;
     if (g->m == 0) {
         w->W = 0;
         w->wide = false;
@@ -480,7 +494,8 @@ u64 weights_build_extra(int64_t m, bool wide) {
 
 int weights_enqueue(tm_weights* w, hipStream_t st, int* ovf) {
     tm_graph* g = w->g;
-    w->q = g->m > 0 ? g->T / w->plan.mo.delta + 1 : 0;
+    w->ilen = interval_unit(w);
+    w->q = g->m > 0 ? g->T / w->ilen + 1 : 0;
     w->wide = false;
     w->W = 0;
     if (g->m == 0) return TM_OK;

@@ -18,6 +18,7 @@ TM_OK, TM_EINVAL, TM_ESELFLOOP, TM_EDUP, TM_EOVERFLOW, TM_ERANGE, TM_ENOMEM, TM_
 TM_EADMIT, TM_EAGAIN, TM_ECANCELED = -8, -9, -10
 TM_PTR_HOST, TM_PTR_DEVICE = 0, 1
 TM_F_W_ZERO, TM_F_SQ_SATURATED, TM_F_WIDE = 1, 2, 4
+TM_C_EXCLUDE, TM_C_WINDOWS, TM_C_ALL = 1, 2, 3
 ARRAYS = dict(src=0, dst=1, t=2, out_off=3, in_off=4, out_eid=5, in_eid=6, outn_eid=7, inn_eid=8)
 
 
@@ -107,6 +108,10 @@ def lib():
         L.tm_graph_export.argtypes = [vp, C.c_int, vp, vp]
         L.tm_default_tree.argtypes = [C.POINTER(Motif), C.POINTER(Tree)]
         L.tm_weights_create.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), vp, C.POINTER(vp)]
+        L.tm_weights_create_ex.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), C.c_uint32, vp,
+                                           C.POINTER(vp)]
+        L.tm_estimate_ex.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), C.c_uint32, u64, u64, vp,
+                                     C.POINTER(Result)]
         L.tm_weights_destroy.argtypes = [vp]
         L.tm_weights_destroy.restype = None
         L.tm_weights_info.argtypes = [vp, C.POINTER(U128), C.POINTER(i64), C.POINTER(i32),
@@ -244,11 +249,12 @@ class Graph:
 class Weights:
     """Resident s-weight tables of one (graph, motif, tree) (Alg. 1, Alg. 2)."""
 
-    def __init__(self, g: Graph, mo: Motif, tr: Tree = None):
+    def __init__(self, g: Graph, mo: Motif, tr: Tree = None, constraints=None):
         self.g, self.mo = g, mo
         h = C.c_void_p()
-        _check(lib().tm_weights_create(g.h, C.byref(mo), C.byref(tr) if tr is not None else None,
-                                       _stream(), C.byref(h)), "weights_create")
+        c = TM_C_ALL if constraints is None else int(constraints)
+        _check(lib().tm_weights_create_ex(g.h, C.byref(mo), C.byref(tr) if tr is not None else None, c,
+                                          _stream(), C.byref(h)), "weights_create")
         self.h = h
 
     def close(self):
@@ -300,10 +306,11 @@ class Weights:
         return res, recs
 
 
-def estimate(g: Graph, mo: Motif, k, seed, tr: Tree = None) -> Result:
+def estimate(g: Graph, mo: Motif, k, seed, tr: Tree = None, constraints=None) -> Result:
     res = Result()
-    _check(lib().tm_estimate(g.h, C.byref(mo), C.byref(tr) if tr is not None else None, int(k),
-                             int(seed), _stream(), C.byref(res)), "estimate")
+    c = TM_C_ALL if constraints is None else int(constraints)
+    _check(lib().tm_estimate_ex(g.h, C.byref(mo), C.byref(tr) if tr is not None else None, c, int(k),
+                                int(seed), _stream(), C.byref(res)), "estimate")
     return res
 
 

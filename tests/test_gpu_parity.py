@@ -102,11 +102,11 @@ def test_graph_errors_match_oracle(T):
 # ---------------------------------------------------------------------------
 # Weights and samples
 # ---------------------------------------------------------------------------
-def check_prep(T, og, tg, edges, delta, otr, seeds=(1, 2), k=3000, g=None):
+def check_prep(T, og, tg, edges, delta, otr, seeds=(1, 2), k=3000, g=None, constraints=None):
     omo, tmo = motifs_for(T, edges, delta)
     otr, ttr = trees_for(T, otr)
-    P = O.Prep(og, omo, otr)
-    Wt = T.Weights(tg, tmo, ttr)
+    P = O.Prep(og, omo, otr, constraints=O.C_ALL if constraints is None else constraints)
+    Wt = T.Weights(tg, tmo, ttr, constraints=constraints)
     info = Wt.info()
     assert info["W"] == P.W
     assert info["q"] == P.q
@@ -269,3 +269,19 @@ def test_medium_workload_full_size(T, medium, name):
     assert sum(p.acc2.value for p in pieces) == full.acc2.value
     assert sum(p.n_valid for p in pieces) == full.n_valid
     assert full.estimate == float(P.W) * (float(full.acc2.value) / (2.0 * k))
+
+
+# ---------------------------------------------------------------------------
+# Constraint ablation: every mode, bit-exact against the oracle's same mode
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", [0, 1, 2, 3], ids=["C1", "C1+2", "C1+3", "C1+2+3"])
+@pytest.mark.parametrize("name,edges,delta", MOTIF_CASES[:6], ids=[c[0] for c in MOTIF_CASES[:6]])
+def test_constraint_modes_match_oracle(T, mode, name, edges, delta):
+    say("constraints", name, mode)
+    g = W.small_graph(2500, 41, n=70, span=40 * delta)
+    og, tg = pair(T, g)
+    for otr in list(all_tree_choices(edges))[:3]:
+        check_prep(T, og, tg, edges, delta, otr, seeds=(4,), k=4000, constraints=mode)
+    # the root-sorted launch shape (2^16 samples or more)
+    check_prep(T, og, tg, edges, delta, O.default_tree(O.make_motif(edges, delta)), seeds=(5,), k=70000,
+               constraints=mode)
