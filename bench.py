@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="before timing, run a plain device copy of BYTES (3 times) so that "
                          "hardware counters can be scaled by a kernel of known traffic")
-    ap.add_argument("--workload", choices=["medium", "large", "batched", "serving", "weights"], default="medium",
+    ap.add_argument("--workload", choices=["medium", "large", "batched", "serving", "weights", "ablation"],
+                    default="medium",
                     help="medium: the single-job path (default); batched: 64 heterogeneous "
                          "jobs, one launch per job against the batched pass; serving: a Poisson "
                          "query stream against the server")
@@ -86,6 +87,8 @@ def main():
         return weights_only(args)
     if args.workload == "large":
         return large(args)
+    if args.workload == "ablation":
+        return ablation(args)
 
     import ctypes as C
 
@@ -533,6 +536,77 @@ def large(args):
                       for a, b, c, d, e, f in res],
     }
     print(json.dumps(line), flush=True)
+
+
+ABLATION_MODES = (("C1", 0), ("C1+2", 1), ("C1+3", 2), ("C1+2+3", 3))
+
+
+def ablation(args):
+    """Constraint ablation (the paper's Tab. "constraints" on synthetic data):
+    per motif and constraint mode, the invalid-sample rate by cause, the
+    valid rate, the estimate's error against the exact count (mean over five
+    seeds; exact counts stored by tests/golden/make_ablation_counts.py), the
+    95% half-width and the device time of weights + sampling; then the
+    4-cycle on the medium graph (no exact count) at 1e7 samples."""
+    import torch
+
+    from paper_2507_20441_amd import timest as T
+    from paper_2507_20441_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    torch.cuda.set_device(0)
+    exact = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "ablation_counts.txt")):
+        if line.startswith("count "):
+            _, name, c = line.split()
+            exact[name] = int(c)
+
+    def run(tg, name, delta, k, seeds, c):
+        mo = T.make_motif(W.MOTIFS[name], delta)
+        out = []
+        for seed in seeds:
+            T.profile_read(reset=True)
+            T.profile_enable(True)
+            w = T.Weights(tg, mo, constraints=c)
+            r, _ = w.sample(seed, k)
+            torch.cuda.synchronize()
+            T.profile_enable(False)
+            ms = sum(T.profile_read(reset=True)["ms"])
+            out.append((r, ms, w.W))
+            w.close()
+        return out
+
+    def row(name, label, res, k, C=None):
+        r0 = res[0][0]
+        d = dict(motif=name, mode=label, W=str(res[0][2]),
+                 invalid_vertex=r0.n_bad_vertex / k, invalid_delta=r0.n_bad_delta / k,
+                 invalid_order=r0.n_bad_order / k, valid=r0.n_valid / k,
+                 rel_ci95=(1.96 * r0.std_error / r0.estimate) if r0.estimate else None,
+                 device_ms=round(sum(x[1] for x in res) / len(res), 3))
+        if C is not None:
+            d["exact"] = C
+            d["mean_abs_rel_error"] = sum(abs(x[0].estimate - C) / C for x in res) / len(res)
+        return d
+
+    g = W.ablation_graph()
+    tg = T.Graph(g.src, g.dst, g.t, g.n)
+    k, delta = W.ABLATION["k"], W.ABLATION["delta"]
+    rows = []
+    for name in W.ABLATION["motifs"]:
+        for label, c in ABLATION_MODES:
+            rows.append(row(name, label, run(tg, name, delta, k, range(1, 6), c), k, exact[name]))
+            log(rows[-1])
+    tg.close()
+    mg = W.medium_graph()
+    tm = T.Graph(mg.src, mg.dst, mg.t, mg.n)
+    med = []
+    for label, c in ABLATION_MODES:
+        med.append(row("4cycle", label, run(tm, "4cycle", 3600, 10_000_000, (1,), c), 10_000_000))
+        log(med[-1])
+    tm.close()
+    print(json.dumps({"workload": "constraint ablation: ablation graph (n=5000, m=200000, gamma 2.1, bursty "
+                                  "over 3e6 s, delta 3600, 1e6 samples, 5 seeds) and the medium graph (4-cycle, "
+                                  "delta 3600, 1e7 samples)", "ablation": rows, "medium": med}), flush=True)
 
 
 def weights_only(args):

@@ -324,3 +324,15 @@ def serving_queries(seconds=60.0, rate=200.0, n_graphs=9, seed=3000):
         out.append(dict(at=t, graph=g, motif=names[int(rng.integers(len(names)))],
                         delta=grid[int(rng.integers(len(grid)))],
                         k=int(round(10 ** rng.uniform(5, 7))), seed=int(rng.integers(1, 2**63 - 1))))
+
+
+# ---------------------------------------------------------------------------
+# Constraint ablation (Tab. "constraints" of the paper, on a synthetic graph
+# small enough for exact counts): 5,000 vertices, 200,000 edges, gamma 2.1,
+# bursty times over 3e6 s; delta 3600; 1e6 samples per (motif, mode).
+# ---------------------------------------------------------------------------
+def ablation_graph() -> TemporalGraph:
+    return chung_lu_graph(5000, 200_000, 2.1, seed=104, times="bursty", span=3_000_000, name="ablation")
+
+
+ABLATION = dict(motifs=("3cycle", "4cycle", "6chain"), delta=3600, k=1_000_000, seed=1)

@@ -58,3 +58,19 @@ def test_constraints_shrink_the_tree_weight():
     mo = O.make_motif(W.MOTIFS["4cycle"], 500)
     w = {k: O.Prep(og, mo, constraints=v).W for k, v in MODES.items()}
     assert w["C1"] >= w["C1+2"] and w["C1+3"] >= w["C1+2+3"]
+
+
+def test_stored_ablation_counts():
+    """The exact counts the ablation benchmark compares against are the
+    oracle's brute-force counts of that workload."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ablation_counts.txt")
+    want = {}
+    for line in open(path):
+        if line.startswith("count "):
+            _, name, c = line.split()
+            want[name] = int(c)
+    g = W.ablation_graph()
+    og = O.Graph(g.src, g.dst, g.t, g.n)
+    for name in W.ABLATION["motifs"]:
+        assert og.brute_count(O.make_motif(W.MOTIFS[name], W.ABLATION["delta"])) == want[name]
