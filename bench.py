@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="before timing, run a plain device copy of BYTES (3 times) so that "
                          "hardware counters can be scaled by a kernel of known traffic")
-    ap.add_argument("--workload", choices=["medium", "large", "batched", "serving", "weights", "ablation"],
+    ap.add_argument("--workload", choices=["medium", "large", "batched", "serving", "weights", "ablation", "trees"],
                     default="medium",
                     help="medium: the single-job path (default); batched: 64 heterogeneous "
                          "jobs, one launch per job against the batched pass; serving: a Poisson "
@@ -89,6 +89,8 @@ def main():
         return large(args)
     if args.workload == "ablation":
         return ablation(args)
+    if args.workload == "trees":
+        return trees(args)
 
     import ctypes as C
 
@@ -607,6 +609,53 @@ def ablation(args):
     print(json.dumps({"workload": "constraint ablation: ablation graph (n=5000, m=200000, gamma 2.1, bursty "
                                   "over 3e6 s, delta 3600, 1e6 samples, 5 seeds) and the medium graph (4-cycle, "
                                   "delta 3600, 1e7 samples)", "ablation": rows, "medium": med}), flush=True)
+
+
+def trees(args):
+    """Tree choice (the paper's Tab. "SPTree" and Alg. 7 on synthetic data):
+    for every (spanning tree, center) candidate of each ablation motif, its
+    looseness, W, the error against the exact count (mean over five seeds)
+    and the 95% half-width at 1e6 samples; and what tm_choose_tree picks from
+    the first three candidates, with the time the choice takes."""
+    import torch
+
+    from paper_2507_20441_amd import timest as T
+    from paper_2507_20441_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    torch.cuda.set_device(0)
+    exact = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "ablation_counts.txt")):
+        if line.startswith("count "):
+            _, name, c = line.split()
+            exact[name] = int(c)
+    g = W.ablation_graph()
+    tg = T.Graph(g.src, g.dst, g.t, g.n)
+    k, delta = W.ABLATION["k"], W.ABLATION["delta"]
+    out = []
+    for name in W.ABLATION["motifs"]:
+        mo = T.make_motif(W.MOTIFS[name], delta)
+        C = exact[name]
+        cands = []
+        for tr, loose in T.tree_candidates(mo):
+            w = T.Weights(tg, mo, tr)
+            res = [w.sample(seed, k)[0] for seed in range(1, 6)]
+            cands.append(dict(tree=list(tr.edge[:tr.n_edges]), center=tr.center, looseness=loose, W=str(w.W),
+                              mean_abs_rel_error=sum(abs(r.estimate - C) / C for r in res) / len(res),
+                              rel_ci95=(1.96 * res[0].std_error / res[0].estimate) if res[0].estimate else None))
+            w.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        best, Ws = T.choose_tree(tg, mo, 3)
+        torch.cuda.synchronize()
+        choose_ms = (time.perf_counter() - t0) * 1e3
+        out.append(dict(motif=name, exact=C, candidates=cands,
+                        chosen=dict(tree=list(best.edge[:best.n_edges]), center=best.center),
+                        choose_n_c=3, choose_ms=round(choose_ms, 3)))
+        log(name, "chosen", out[-1]["chosen"], "in", round(choose_ms, 2), "ms")
+    tg.close()
+    print(json.dumps({"workload": "tree choice on the ablation graph (delta 3600, 1e6 samples, 5 seeds)",
+                      "motifs": out}), flush=True)
 
 
 def weights_only(args):
