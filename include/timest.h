@@ -275,6 +275,18 @@ void tm_batch_plan_destroy(tm_batch_plan* p);
  * values through prev_tile / prev_blocks when not NULL. */
 int tm_batch_config(int tile, int blocks, int* prev_tile, int* prev_blocks);
 
+/* Motif families (Sec. 4.3; the paper counts its 4-vertex motifs "at once",
+ * Tab. "4-vertex-runtime"): motifs whose spanning tree is w's -- the same
+ * tree edges (the same source and destination vertices, each matching one
+ * edge of the motif, in the same relative order), the same vertex count and
+ * delta -- and that differ only in their non-tree edges.  One stream of k
+ * tree samples (seed, ids 0 .. k-1) is drawn and validated once; every
+ * sample is completed for each motif.  out[f] equals tm_sample of motif f's
+ * own weights with that tree (the weights depend on the tree alone).
+ * Errors: TM_EINVAL (a motif that does not share the tree), as tm_sample. */
+int tm_sample_family(tm_weights* w, const tm_motif* motifs, int n_motifs, uint64_t seed, uint64_t k,
+                     void* stream, tm_result* out);
+
 /* Spanning-tree candidates (Sec. "Choosing the Spanning Tree", Alg. 8):
  * every (spanning tree, center) pair of the motif, ordered by constraint
  * looseness -- per motif vertex, over unordered pairs of tree edges incident

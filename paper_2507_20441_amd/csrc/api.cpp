@@ -1030,3 +1030,76 @@ extern "C" int tm_batch_plan_run(tm_batch_plan* p, void* stream, tm_result* out)
 }
 
 extern "C" void tm_batch_plan_destroy(tm_batch_plan* p) { plan_release(p); }
+
+// ---------------------------------------------------------------------------
+// Motif families (Sec. 4.3, Tab. "4-vertex-runtime"): several motifs from one
+// sample stream of a shared spanning tree.
+// ---------------------------------------------------------------------------
+// The tree of w as a tree of motif mo: the same tree edges -- the same
+// (source, destination) pairs, found once each and in the same relative
+// order -- and the same delta; the plan must have w's slot structure.
+static int family_plan(const tm_weights* w, const tm_motif* mo, HostPlan* out) {
+    TM_TRY(motif_check(mo));
+    const HostPlan& P0 = w->plan;
+    if (mo->k != P0.mo.k || mo->delta != P0.mo.delta)
+        return tm_fail(TM_EINVAL, "family: motif differs in vertex count or delta");
+    tm_tree t;
+    std::memset(&t, 0, sizeof t);
+    t.n_edges = P0.nt;
+    int prev = -1;
+    bool used[TM_MAX_L] = {false};
+    for (int x = 0; x < P0.nt; ++x) {  // tree edges in increasing pi index
+        const int s = P0.by_pi[x];
+        const int e0 = P0.edge[s];
+        int hit = -1;
+        for (int p = 0; p < mo->l; ++p)
+            if (!used[p] && mo->src[p] == P0.mo.src[e0] && mo->dst[p] == P0.mo.dst[e0]) {
+                if (hit >= 0) return tm_fail(TM_EINVAL, "family: tree edge %d matches several edges", e0);
+                hit = p;
+            }
+        if (hit < 0) return tm_fail(TM_EINVAL, "family: tree edge %d missing", e0);
+        if (hit <= prev) return tm_fail(TM_EINVAL, "family: tree edges in another order");
+        used[hit] = true;
+        prev = hit;
+        t.edge[x] = hit;
+        if (e0 == P0.tree.center) t.center = hit;
+    }
+    TM_TRY(plan_build(mo, &t, out));
+    const HostPlan& P = *out;
+    if (P.nt != P0.nt || P.H != P0.H) return tm_fail(TM_EINVAL, "family: tree shape differs");
+    for (int s = 0; s < P.nt; ++s)
+        if (P.parent[s] != P0.parent[s] || P.side[s] != P0.side[s] || P.alpha[s] != P0.alpha[s] ||
+            P.beta[s] != P0.beta[s] || P.by_pi[s] != P0.by_pi[s] ||
+            P.mo.src[P.edge[s]] != P0.mo.src[P0.edge[s]] || P.mo.dst[P.edge[s]] != P0.mo.dst[P0.edge[s]])
+            return tm_fail(TM_EINVAL, "family: tree shape differs");
+    return TM_OK;
+}
+
+extern "C" int tm_sample_family(tm_weights* w, const tm_motif* motifs, int n_motifs, uint64_t seed, uint64_t k,
+                                void* stream, tm_result* out) {
+    if (!w || !motifs || !out || n_motifs < 1 || n_motifs > 64)
+        return tm_fail(TM_EINVAL, "sample_family: bad arguments");
+    std::vector<HostPlan> plans(n_motifs);
+    for (int f = 0; f < n_motifs; ++f) TM_TRY(family_plan(w, &motifs[f], &plans[f]));
+    std::vector<JobSums> sums(n_motifs);
+    JobSums shared;
+    TM_TRY(family_run(w, plans.data(), n_motifs, seed, k, as_stream(stream), sums.data(), &shared));
+    for (int f = 0; f < n_motifs; ++f) {
+        tm_result& o = out[f];
+        std::memset(&o, 0, sizeof o);
+        o.k = k;
+        o.q = w->q;
+        o.W.lo = (u64)w->W;
+        o.W.hi = (u64)(w->W >> 64);
+        if (w->wide) o.flags |= TM_F_WIDE;
+        if (w->W == 0) o.flags |= TM_F_W_ZERO;
+        JobSums x = sums[f];
+        x.n_valid = shared.n_valid;
+        x.n_vertex = shared.n_vertex;
+        x.n_delta = shared.n_delta;
+        x.n_order = shared.n_order;
+        sums_to_result(x, &o);
+        if (o.status == TM_OK) finish_result(&o);
+    }
+    return TM_OK;
+}

@@ -434,6 +434,50 @@ __global__ void __launch_bounds__(kBlock) root_kernel(SampleArgs a, uint32_t* ke
 
 // Samples at positions x = x0, x0 + stride, ... < xend: sample offsets in
 // [0, count), or, in root-sorted order, positions of the sorted arrays.
+// M_phi of a valid tree image (Alg. 5): the completions over the non-tree
+// edges of a's motif.  img: the graph vertex of every motif vertex; te: the
+// time of every tree slot.
+template <bool kCount, bool kGeneral, int NT>
+__device__ __forceinline__ u128 completions(const SampleArgs& a, const int32_t (&img)[TM_MAX_K],
+                                            const int64_t (&te)[NT], bool& ovf, u64& nb) {
+    const DevGraph& G = a.G;
+    u128 m_phi = 0;
+    const int64_t tfirst = pick(te, a.by_pi[0]), tlast = pick(te, a.by_pi[a.nt - 1]);
+    if constexpr (kGeneral) {
+        V8 iv;
+        sfor<0, TM_MAX_K>([&](auto x) { iv.v[decltype(x)::value] = img[decltype(x)::value]; });
+        int64_t tp[TM_MAX_L], tn[TM_MAX_L];
+        for (int r2 = 0; r2 < a.n_runs; ++r2) {
+            tp[r2] = a.run_prev[r2] >= 0 ? pick(te, a.run_prev[r2]) : 0;
+            tn[r2] = a.run_next[r2] >= 0 ? pick(te, a.run_next[r2]) : 0;
+        }
+        m_phi = complete_general<kCount>(a, iv, tfirst, tlast, tp, tn, &ovf, &nb);
+    } else {
+        m_phi = 1;
+        for (int r2 = 0; r2 < a.n_runs && m_phi != 0; ++r2) {
+            const int pv = a.run_prev[r2], nx = a.run_next[r2];
+            const int f0 = a.run_first[r2], len = a.run_len[r2];
+            int64_t lo_t, hi_t;
+            if (pv >= 0 && nx >= 0) {
+                lo_t = pick(te, pv) + 1;
+                hi_t = pick(te, nx) - 1;
+            } else if (nx >= 0) {  // leading run only
+                lo_t = tlast - a.delta;
+                hi_t = tfirst - 1;
+            } else {  // trailing run only
+                lo_t = tlast + 1;
+                hi_t = tfirst + a.delta;
+            }
+            const int32_t x0 = pick(img, a.free_src[f0]), y0 = pick(img, a.free_dst[f0]);
+            const int32_t x1 = len > 1 ? pick(img, a.free_src[f0 + 1]) : 0;
+            const int32_t y1 = len > 1 ? pick(img, a.free_dst[f0 + 1]) : 0;
+            const u128 c = run_count_short<kCount>(G, x0, y0, x1, y1, len, lo_t, hi_t, nb);
+            if (!mul_ok(m_phi, c, &m_phi)) ovf = true;
+        }
+    }
+    return m_phi;
+}
+
 template <typename W, bool kCount, bool kGeneral, bool kSorted>
 __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* cum, u64 x0, u64 xend,
                                                  u64 stride, LaneAcc& L) {
@@ -587,39 +631,7 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
             const int64_t b = tmin / a.ilen;
             n_phi = (b < a.q ? 1u : 0u) + ((b >= 1 && tmax < (b + 1) * a.ilen) ? 1u : 0u);
             // Alg. 5: completions over the non-tree edges
-            const int64_t tfirst = pick(te, a.by_pi[0]), tlast = pick(te, a.by_pi[a.nt - 1]);
-            if constexpr (kGeneral) {
-                V8 iv;
-                sfor<0, TM_MAX_K>([&](auto x) { iv.v[decltype(x)::value] = img[decltype(x)::value]; });
-                int64_t tp[TM_MAX_L], tn[TM_MAX_L];
-                for (int r2 = 0; r2 < a.n_runs; ++r2) {
-                    tp[r2] = a.run_prev[r2] >= 0 ? pick(te, a.run_prev[r2]) : 0;
-                    tn[r2] = a.run_next[r2] >= 0 ? pick(te, a.run_next[r2]) : 0;
-                }
-                m_phi = complete_general<kCount>(a, iv, tfirst, tlast, tp, tn, &ovf, &nb);
-            } else {
-                m_phi = 1;
-                for (int r2 = 0; r2 < a.n_runs && m_phi != 0; ++r2) {
-                    const int pv = a.run_prev[r2], nx = a.run_next[r2];
-                    const int f0 = a.run_first[r2], len = a.run_len[r2];
-                    int64_t lo_t, hi_t;
-                    if (pv >= 0 && nx >= 0) {
-                        lo_t = pick(te, pv) + 1;
-                        hi_t = pick(te, nx) - 1;
-                    } else if (nx >= 0) {  // leading run only
-                        lo_t = tlast - a.delta;
-                        hi_t = tfirst - 1;
-                    } else {  // trailing run only
-                        lo_t = tlast + 1;
-                        hi_t = tfirst + a.delta;
-                    }
-                    const int32_t x0 = pick(img, a.free_src[f0]), y0 = pick(img, a.free_dst[f0]);
-                    const int32_t x1 = len > 1 ? pick(img, a.free_src[f0 + 1]) : 0;
-                    const int32_t y1 = len > 1 ? pick(img, a.free_dst[f0 + 1]) : 0;
-                    const u128 c = run_count_short<kCount>(G, x0, y0, x1, y1, len, lo_t, hi_t, nb);
-                    if (!mul_ok(m_phi, c, &m_phi)) ovf = true;
-                }
-            }
+            m_phi = completions<kCount, kGeneral>(a, img, te, ovf, nb);
             ++n_valid;
             if (m_phi != 0) ++n_nonzero;
             u128 term;
@@ -911,6 +923,47 @@ job_reduce_kernel(const Partial* tile_parts, const int* first, const int* count,
     const int f = first[blockIdx.x], c = count[blockIdx.x];
     for (int b = threadIdx.x; b < c; b += kBlock) combine(acc, tile_parts[f + b]);
     block_reduce_write(acc, &out[blockIdx.x]);
+}
+
+// Motif families: M_phi of every valid record for one motif whose spanning
+// tree is the sampled one (the record's tree image, this motif's non-tree
+// edges), with the per-block sums of 2 M_phi / N_phi.
+template <bool kGeneral>
+__global__ void __launch_bounds__(kBlock)
+family_kernel(SampleArgs a, const tm_sample_rec* recs, u64 count, Partial* parts, int* ovf) {
+    constexpr int NT = kMaxSlots - 1;
+    const DevGraph& G = a.G;
+    LaneAcc L = lane_zero();
+    u64 nb = 0;
+    for (u64 r = (u64)blockIdx.x * kBlock + threadIdx.x; r < count; r += (u64)gridDim.x * kBlock) {
+        const tm_sample_rec& rec = recs[r];
+        if (rec.status != 0) continue;
+        int32_t img[TM_MAX_K];
+        int64_t te[NT];
+        sfor<0, TM_MAX_K>([&](auto xx) { img[decltype(xx)::value] = -1 - decltype(xx)::value; });
+        sfor<0, NT>([&](auto xx) { te[decltype(xx)::value] = 0; });
+        sfor<0, NT>([&](auto xc) {
+            constexpr int x = decltype(xc)::value;
+            if (x >= a.nt) return;
+            const int s = a.by_pi[x];
+            const int32_t e = rec.eid[x];
+            put(te, s, G.t[e]);
+            put(img, a.esrc[s], G.src[e]);
+            put(img, a.edst[s], G.dst[e]);
+        });
+        const u128 m_phi = completions<false, kGeneral>(a, img, te, L.ovf, nb);
+        ++L.n_valid;
+        if (m_phi != 0) ++L.n_nonzero;
+        u128 term;
+        if (!mul_ok(m_phi, (u128)(2 / rec.n_phi), &term)) L.ovf = true;
+        if (!add_ok(L.acc2, term, &L.acc2)) L.flags |= 1;
+        u128 sq;
+        if (!mul_ok(term, term, &sq) || !add_ok(L.acc2_sq, sq, &L.acc2_sq)) {
+            L.acc2_sq = ~(u128)0;
+            L.flags |= 2;
+        }
+    }
+    lanes_reduce(L, &parts[blockIdx.x], ovf);
 }
 
 }  // namespace
@@ -1445,4 +1498,95 @@ void batch_capture_free(CapturedPass* P, hipStream_t st) {
     (void)sync_stream(st);
     for (Group& G : P->groups) group_free(G, st);
     delete P;
+}
+
+// ---------------------------------------------------------------------------
+// Motif families: one tree sample stream, every member's completions.
+// ---------------------------------------------------------------------------
+int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hipStream_t st, JobSums* sums,
+               JobSums* shared) {
+    for (int f = 0; f < n; ++f) sums[f] = JobSums{};
+    *shared = JobSums{};
+    if (w->W == 0 || k == 0) return TM_OK;
+    std::vector<SampleArgs> args(n);
+    for (int f = 0; f < n; ++f) {
+        size_t lds;
+        fill_args(w, &args[f], &lds);
+        const HostPlan& P = plans[f];
+        // this member's non-tree edges (its tree slots are the sampled ones)
+        args[f].n_free = P.n_free;
+        for (int x = 0; x < P.n_free; ++x) {
+            args[f].free_src[x] = P.free_src[x];
+            args[f].free_dst[x] = P.free_dst[x];
+        }
+        args[f].n_runs = P.n_runs;
+        args[f].general_runs = 0;
+        bool lead = false, trail = false;
+        for (int r = 0; r < P.n_runs; ++r) {
+            args[f].run_first[r] = P.run_first[r];
+            args[f].run_len[r] = P.run_len[r];
+            args[f].run_prev[r] = P.run_prev[r];
+            args[f].run_next[r] = P.run_next[r];
+            if (P.run_len[r] > 2) args[f].general_runs = 1;
+            lead |= P.run_prev[r] < 0;
+            trail |= P.run_next[r] < 0;
+        }
+        if (lead && trail) args[f].general_runs = 1;
+        args[f].delta = P.mo.delta;
+    }
+    const u64 chunk = std::min<u64>(k, (u64)1 << 24);
+    const int blocks = 2048;
+    tm_sample_rec* recs = nullptr;
+    Partial* parts = nullptr;
+    int* ovf = nullptr;
+    TM_HIP(dev_alloc((void**)&recs, chunk * sizeof(tm_sample_rec), st));
+    TM_HIP(dev_alloc((void**)&parts, (blocks + 1) * sizeof(Partial), st));
+    TM_HIP(dev_alloc((void**)&ovf, sizeof(int), st));
+    int rc = TM_OK;
+    for (u64 c0 = 0; c0 < k && rc == TM_OK; c0 += chunk) {
+        const u64 cnt = std::min<u64>(chunk, k - c0);
+        tm_result tree;
+        rc = sample_run(w, seed, c0, cnt, k, st, &tree, recs, nullptr);
+        if (rc != TM_OK) break;
+        JobSums t;
+        t.n_valid = tree.n_valid;
+        t.n_vertex = tree.n_bad_vertex;
+        t.n_delta = tree.n_bad_delta;
+        t.n_order = tree.n_bad_order;
+        sums_merge(*shared, t);
+        for (int f = 0; f < n && rc == TM_OK; ++f) {
+            rc = fill_u32(ovf, 1, 0u, st);
+            if (rc != TM_OK) break;
+            const dim3 grid((unsigned)std::min<u64>((cnt + kBlock - 1) / kBlock, (u64)blocks));
+            if (args[f].general_runs)
+                hipLaunchKernelGGL(family_kernel<true>, grid, dim3(kBlock), 0, st, args[f], (const tm_sample_rec*)recs,
+                                   cnt, parts, ovf);
+            else
+                hipLaunchKernelGGL(family_kernel<false>, grid, dim3(kBlock), 0, st, args[f], (const tm_sample_rec*)recs,
+                                   cnt, parts, ovf);
+            if (hipGetLastError() != hipSuccess) { rc = tm_fail(TM_EDEVICE, "family: launch"); break; }
+            hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const Partial*)parts, (int)grid.x,
+                               parts + blocks);
+            Partial h;
+            int hovf = 0;
+            if (hipMemcpyAsync(&h, parts + blocks, sizeof h, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipMemcpyAsync(&hovf, ovf, sizeof hovf, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                sync_stream(st) != hipSuccess) {
+                rc = tm_fail(TM_EDEVICE, "family: copy");
+                break;
+            }
+            JobSums x;
+            x.acc2 = h.acc2;
+            x.acc2_sq = h.acc2_sq;
+            x.n_nonzero = h.n_nonzero;
+            x.flags = h.flags & 3;
+            if (hovf & 1) x.flags |= 1;
+            sums_merge(sums[f], x);
+        }
+    }
+    (void)dev_free(recs, st);
+    (void)dev_free(parts, st);
+    (void)dev_free(ovf, st);
+    (void)sync_stream(st);
+    return rc;
 }

@@ -191,6 +191,12 @@ extern BatchConfig g_batch_config;
 int batch_sample_pass(tm_weights* const* ws, const u64* j0, const u64* count, const u64* seeds, int n,
                       hipStream_t st, JobSums* out, const BatchConfig& cfg);
 
+// Motif families: k samples of w's tree, each completed for every member
+// plan (same tree slots, own non-tree edges).  sums[f]: acc2, acc2_sq and
+// nonzero counts of member f; shared: the validation counts of the stream.
+int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hipStream_t st, JobSums* sums,
+               JobSums* shared);
+
 // The captured form of a batched pass over jobs whose 64-bit weights are
 // being built earlier on st: every launch and copy is enqueued with no host
 // synchronisation or read; W comes from each job's table and a job whose

@@ -127,6 +127,7 @@ def lib():
                                         C.POINTER(u64), C.POINTER(u64), C.c_int, vp,
                                         C.POINTER(Result)]
         L.tm_batch_config.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.tm_sample_family.argtypes = [vp, C.POINTER(Motif), C.c_int, u64, u64, vp, C.POINTER(Result)]
         L.tm_tree_candidates.argtypes = [C.POINTER(Motif), C.POINTER(Tree), C.POINTER(i64), C.c_int,
                                          C.POINTER(C.c_int)]
         L.tm_choose_tree.argtypes = [vp, C.POINTER(Motif), C.c_int, vp, C.POINTER(Tree), C.POINTER(U128),
@@ -482,3 +483,12 @@ def choose_tree(g: Graph, mo: Motif, n_c):
     _check(lib().tm_choose_tree(g.h, C.byref(mo), int(n_c), _stream(), C.byref(best), Ws, C.byref(ne)),
            "choose_tree")
     return best, [Ws[x].value for x in range(ne.value)]
+
+
+def sample_family(w: "Weights", motifs, seed, k):
+    """tm_sample_family: one tree sample stream completed for every motif."""
+    n = len(motifs)
+    mo = (Motif * n)(*motifs)
+    out = (Result * n)()
+    _check(lib().tm_sample_family(w.h, mo, n, int(seed), int(k), _stream(), out), "sample_family")
+    return list(out)
