@@ -275,6 +275,20 @@ void tm_batch_plan_destroy(tm_batch_plan* p);
  * values through prev_tile / prev_blocks when not NULL. */
 int tm_batch_config(int tile, int blocks, int* prev_tile, int* prev_blocks);
 
+/* Random instance listing (Sec. 4.3): samples j0 .. j0 + count - 1 of w's
+ * motif with the given seed (the draws of tm_sample); every valid sample with
+ * 0 < M_phi <= 2^20 lists its r-th completion, r = floor(X M_phi / 2^128)
+ * with X the 128-bit Philox block of draw 15 of the sample, completions
+ * ordered lexicographically by the eids of the motif edges in pi order (tree
+ * edges fixed).  A motif instance H whose tree image is phi is thus listed by
+ * a sample with probability (N_phi / W) / M_phi.  eids: device memory,
+ * count x 16 int32, each row the eids of the motif's edges in pi order (-1
+ * beyond l, and in rows that list nothing).  recs: NULL or device memory for
+ * count records (the samples' tree images, N_phi and M_phi).  Synchronises
+ * the stream.  Errors: TM_EINVAL, as tm_sample. */
+int tm_list_instances(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count, void* stream, int32_t* eids,
+                      tm_sample_rec* recs);
+
 /* Motif families (Sec. 4.3; the paper counts its 4-vertex motifs "at once",
  * Tab. "4-vertex-runtime"): motifs whose spanning tree is w's -- the same
  * tree edges (the same source and destination vertices, each matching one

@@ -80,6 +80,7 @@ def lib():
         L.or_prep_weights.argtypes = [vp, i32, C.c_int, vp]
         L.or_sample.argtypes = [vp, u64, u64, u64, u64, C.POINTER(Result), vp]
         L.or_derive_cnt.argtypes = [vp, vp, C.POINTER(U128)]
+        L.or_list_instance.argtypes = [vp, vp, U128, vp]
         L.or_tree_candidates.argtypes = [C.POINTER(Motif), C.POINTER(Tree), C.POINTER(C.c_int64), C.c_int,
                                          C.POINTER(C.c_int)]
         L.or_choose_tree.argtypes = [vp, C.POINTER(Motif), C.c_int, C.POINTER(Tree), C.POINTER(U128),
@@ -280,6 +281,15 @@ class Prep:
         if rc != OR_OK:
             raise OracleError(rc, "sample")
         return res, recs
+
+    def list_instance(self, eids, rank):
+        """The rank-th completion of a valid tree image: l eids in pi order."""
+        e = np.ascontiguousarray(eids, dtype=np.int32)
+        out = np.empty(self.mo.l, np.int32)
+        rc = lib().or_list_instance(self.h, _ptr(e), U128.of(int(rank)), _ptr(out))
+        if rc != OR_OK:
+            raise OracleError(rc, "list_instance")
+        return out
 
     def derive_cnt(self, eids):
         e = np.ascontiguousarray(eids, dtype=np.int32)

@@ -791,6 +791,80 @@ extern "C" int or_derive_cnt(const or_prep* p, const int32_t* eids, or_u128* m_p
 }
 
 // ------------------------------------------------------------------------
+// Random instance listing (Sec. 4.3): the r-th completion of a valid tree
+// image, completions ordered lexicographically by the eids of the motif's
+// edges in pi order (tree edges fixed).
+// ------------------------------------------------------------------------
+static bool nth_completion(const or_graph& G, const std::vector<std::vector<int32_t>>& lists, size_t p,
+                           int64_t after, int64_t t_first, int64_t delta, u128& r, std::vector<int32_t>& pick) {
+    if (p == lists.size()) {
+        if (r == 0) return true;
+        --r;
+        return false;
+    }
+    for (int32_t x : lists[p]) {
+        const int64_t tx = G.e[x].t;
+        if (tx <= after) continue;
+        const int64_t tf = p == 0 ? tx : t_first;
+        if (tx - tf > delta) continue;
+        pick[p] = x;
+        if (nth_completion(G, lists, p + 1, tx, tf, delta, r, pick)) return true;
+    }
+    return false;
+}
+
+extern "C" int or_list_instance(const or_prep* p, const int32_t* eids, or_u128 rank, int32_t* out) {
+    if (!p || !eids || !out) return OR_EINVAL;
+    const or_graph& G = *p->g;
+    const Plan& P = p->P;
+    const or_motif& M = P.mo;
+    int32_t img_e[16];
+    for (int x = 0; x < 16; ++x) img_e[x] = -1;
+    int32_t img_v[8];
+    for (int x = 0; x < 8; ++x) img_v[x] = -1;
+    for (size_t a = 0; a < P.tree_sorted.size(); ++a) {
+        if (eids[a] < 0 || eids[a] >= G.m) return OR_EINVAL;
+        const int q = P.tree_sorted[a];
+        img_e[q] = eids[a];
+        img_v[M.src[q]] = G.e[eids[a]].u;
+        img_v[M.dst[q]] = G.e[eids[a]].v;
+    }
+    uint32_t st, np;
+    u128 mp;
+    const int rc = validate_and_derive(*p, img_e, &st, &np, &mp);
+    if (rc != OR_OK) return rc;
+    u128 r = ((u128)rank.hi << 64) | rank.lo;
+    if (st != 0 || r >= mp) return OR_EINVAL;
+    int64_t tmin = 0, tmax = 0;
+    bool firstt = true;
+    for (int q : P.tree_sorted) {
+        const int64_t t = G.e[img_e[q]].t;
+        if (firstt || t < tmin) tmin = t;
+        if (firstt || t > tmax) tmax = t;
+        firstt = false;
+    }
+    // the candidate lists of Alg. 5: the tree edge itself, or the multi-edge
+    // list of the non-tree edge's images within delta of the tree times
+    std::vector<std::vector<int32_t>> lists(M.l);
+    for (int q = 0; q < M.l; ++q) {
+        if (P.in_tree[q]) {
+            lists[q].push_back(img_e[q]);
+            continue;
+        }
+        auto it = G.el.find({img_v[M.src[q]], img_v[M.dst[q]]});
+        if (it == G.el.end()) return OR_EINVAL;
+        for (size_t x = first_at_or_after(G, it->second, tmax - p->delta); x < it->second.size(); ++x) {
+            if (G.e[it->second[x]].t > tmin + p->delta) break;
+            lists[q].push_back(it->second[x]);
+        }
+    }
+    std::vector<int32_t> pick(M.l, -1);
+    if (!nth_completion(G, lists, 0, INT64_MIN, 0, p->delta, r, pick)) return OR_EINVAL;
+    for (int q = 0; q < M.l; ++q) out[q] = pick[q];
+    return OR_OK;
+}
+
+// ------------------------------------------------------------------------
 // Alg. 3 (SampleSubg) and Alg. 6 (Estimate).
 // ------------------------------------------------------------------------
 

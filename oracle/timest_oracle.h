@@ -149,6 +149,12 @@ int or_sample(const or_prep* p, uint64_t seed, uint64_t j0, uint64_t count,
  * returns OR_EINVAL if the edges do not form a valid sample. */
 int or_derive_cnt(const or_prep* p, const int32_t* eids, or_u128* m_phi);
 
+/* The rank-th (0-based) completion of a valid tree image (eids like
+ * or_derive_cnt), completions in lexicographic order of the eids of the
+ * motif edges in pi order; out: l eids.  OR_EINVAL if the image is not
+ * valid or rank >= M_phi. */
+int or_list_instance(const or_prep* p, const int32_t* eids, or_u128 rank, int32_t* out);
+
 /* ---- Philox4x32-10 and the range mapping ---------------------------- */
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 /* floor(X * n / 2^128) with X the 128-bit block of draw d of sample j */

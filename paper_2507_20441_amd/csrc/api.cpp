@@ -1103,3 +1103,10 @@ extern "C" int tm_sample_family(tm_weights* w, const tm_motif* motifs, int n_mot
     }
     return TM_OK;
 }
+
+extern "C" int tm_list_instances(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count, void* stream,
+                                 int32_t* eids, tm_sample_rec* recs) {
+    if (!w || (count > 0 && !eids)) return tm_fail(TM_EINVAL, "list_instances: NULL argument");
+    if (count > 0 && j0 + count < j0) return tm_fail(TM_EINVAL, "list_instances: id range wraps");
+    return list_run(w, seed, j0, count, as_stream(stream), eids, recs);
+}

@@ -966,6 +966,106 @@ family_kernel(SampleArgs a, const tm_sample_rec* recs, u64 count, Partial* parts
     lanes_reduce(L, &parts[blockIdx.x], ovf);
 }
 
+// Random instance listing: for every valid record with 0 < M_phi <= kListMax,
+// the r-th completion (r from draw kListDraw of the sample) by a depth-first
+// walk over the motif edges in pi order -- tree edges fixed, non-tree edges
+// over their multi-edge lists within delta of the tree times, in eid order --
+// with strictly increasing times and everything within delta of the first.
+constexpr uint32_t kListDraw = 15;
+constexpr u64 kListMax = (u64)1 << 20;
+
+struct ListArgs {
+    int l;
+    int kind[TM_MAX_L];  // motif edge in pi order: its tree slot, or -1 - (its index among the non-tree edges)
+};
+
+__global__ void __launch_bounds__(kBlock)
+list_kernel(SampleArgs a, ListArgs la, const tm_sample_rec* recs, u64 count, int32_t* out) {
+    constexpr int NT = kMaxSlots - 1;
+    const DevGraph& G = a.G;
+    const u64 tmask = tmask_of(G);
+    for (u64 r = (u64)blockIdx.x * kBlock + threadIdx.x; r < count; r += (u64)gridDim.x * kBlock) {
+        int32_t* row = out + r * TM_MAX_L;
+        for (int p = 0; p < TM_MAX_L; ++p) row[p] = -1;
+        const tm_sample_rec& rec = recs[r];
+        const u128 m = ((u128)rec.m_phi.hi << 64) | rec.m_phi.lo;
+        if (rec.status != 0 || m == 0 || m > (u128)kListMax) continue;
+        int32_t img[TM_MAX_K];
+        int64_t tslot[NT];
+        int32_t eslot[NT];
+        for (int x = 0; x < TM_MAX_K; ++x) img[x] = -1;
+        int64_t tmin = 0, tmax = 0;
+        for (int x = 0; x < a.nt; ++x) {
+            const int s = a.by_pi[x];
+            const int32_t e = rec.eid[x];
+            tslot[s] = G.t[e];
+            eslot[s] = e;
+            img[a.esrc[s]] = G.src[e];
+            img[a.edst[s]] = G.dst[e];
+            tmin = x == 0 || G.t[e] < tmin ? G.t[e] : tmin;
+            tmax = x == 0 || G.t[e] > tmax ? G.t[e] : tmax;
+        }
+        // candidate ranges: tree edges one entry, non-tree edges a run of the
+        // N order of the source's out-list
+        int32_t beg[TM_MAX_L], end[TM_MAX_L], pos[TM_MAX_L], pick_e[TM_MAX_L];
+        int64_t tt[TM_MAX_L];
+        for (int p = 0; p < la.l; ++p) {
+            if (la.kind[p] >= 0) {
+                beg[p] = 0;
+                end[p] = 1;
+            } else {
+                const int f = -1 - la.kind[p];
+                int32_t lo, hi;
+                el_run(G, img[a.free_src[f]], img[a.free_dst[f]], tmax - a.delta, tmin + a.delta, beg[p], end[p], lo,
+                       hi);
+            }
+        }
+        u128 rank = scale(draw_block(a.seed, a.j0 + r, kListDraw), m);
+        int p = 0;
+        pos[0] = beg[0];
+        bool found = false;
+        while (p >= 0) {
+            if (pos[p] >= end[p]) {
+                --p;
+                if (p >= 0) ++pos[p];
+                continue;
+            }
+            int64_t t;
+            int32_t e;
+            if (la.kind[p] >= 0) {
+                t = tslot[la.kind[p]];
+                e = eslot[la.kind[p]];
+            } else {
+                t = (int64_t)(G.nkey[0][pos[p]] & tmask);
+                e = G.neid[0][pos[p]];
+            }
+            if (p > 0 && t <= tt[p - 1]) {
+                ++pos[p];
+                continue;
+            }
+            if (p > 0 && t - tt[0] > a.delta) {
+                pos[p] = end[p];  // later entries are later in time
+                continue;
+            }
+            tt[p] = t;
+            pick_e[p] = e;
+            if (p == la.l - 1) {
+                if (rank == 0) {
+                    found = true;
+                    break;
+                }
+                --rank;
+                ++pos[p];
+                continue;
+            }
+            ++p;
+            pos[p] = beg[p];
+        }
+        if (found)
+            for (int q = 0; q < la.l; ++q) row[q] = pick_e[q];
+    }
+}
+
 }  // namespace
 
 int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStream_t st,
@@ -1588,5 +1688,40 @@ int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hip
     (void)dev_free(parts, st);
     (void)dev_free(ovf, st);
     (void)sync_stream(st);
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
+// Random instance listing.
+// ---------------------------------------------------------------------------
+int list_run(tm_weights* w, u64 seed, u64 j0, u64 count, hipStream_t st, int32_t* eids, tm_sample_rec* recs) {
+    if (count == 0) return TM_OK;
+    tm_sample_rec* own = nullptr;
+    if (!recs) TM_HIP(dev_alloc((void**)&own, count * sizeof(tm_sample_rec), st));
+    tm_sample_rec* rr = recs ? recs : own;
+    tm_result res;
+    int rc = sample_run(w, seed, j0, count, count, st, &res, rr, nullptr);
+    if (rc == TM_OK) {
+        SampleArgs a;
+        size_t lds;
+        fill_args(w, &a, &lds);
+        a.seed = seed;
+        a.j0 = j0;
+        ListArgs la;
+        const HostPlan& P = w->plan;
+        la.l = P.mo.l;
+        int nf = 0;
+        for (int p = 0; p < P.mo.l; ++p) la.kind[p] = P.slot_of_edge[p] >= 0 ? P.slot_of_edge[p] : -1 - nf++;
+        if (w->W == 0) {
+            // nothing was drawn: every row lists nothing
+            rc = fill_u32(eids, (int64_t)count * TM_MAX_L, 0xffffffffu, st);
+        } else {
+            const dim3 grid((unsigned)std::min<u64>((count + kBlock - 1) / kBlock, 4096));
+            hipLaunchKernelGGL(list_kernel, grid, dim3(kBlock), 0, st, a, la, (const tm_sample_rec*)rr, count, eids);
+            if (hipGetLastError() != hipSuccess) rc = tm_fail(TM_EDEVICE, "list: launch");
+        }
+    }
+    if (own) (void)dev_free(own, st);
+    if (sync_stream(st) != hipSuccess && rc == TM_OK) rc = tm_fail(TM_EDEVICE, "list: synchronise");
     return rc;
 }

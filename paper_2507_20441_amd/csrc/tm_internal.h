@@ -197,6 +197,10 @@ int batch_sample_pass(tm_weights* const* ws, const u64* j0, const u64* count, co
 int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hipStream_t st, JobSums* sums,
                JobSums* shared);
 
+// Random instance listing of samples j0 .. j0 + count - 1 (eids: device,
+// count x TM_MAX_L; recs: device records or NULL).
+int list_run(tm_weights* w, u64 seed, u64 j0, u64 count, hipStream_t st, int32_t* eids, tm_sample_rec* recs);
+
 // The captured form of a batched pass over jobs whose 64-bit weights are
 // being built earlier on st: every launch and copy is enqueued with no host
 // synchronisation or read; W comes from each job's table and a job whose

@@ -127,6 +127,7 @@ def lib():
                                         C.POINTER(u64), C.POINTER(u64), C.c_int, vp,
                                         C.POINTER(Result)]
         L.tm_batch_config.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.tm_list_instances.argtypes = [vp, u64, u64, u64, vp, vp, vp]
         L.tm_sample_family.argtypes = [vp, C.POINTER(Motif), C.c_int, u64, u64, vp, C.POINTER(Result)]
         L.tm_tree_candidates.argtypes = [C.POINTER(Motif), C.POINTER(Tree), C.POINTER(i64), C.c_int,
                                          C.POINTER(C.c_int)]
@@ -492,3 +493,15 @@ def sample_family(w: "Weights", motifs, seed, k):
     out = (Result * n)()
     _check(lib().tm_sample_family(w.h, mo, n, int(seed), int(k), _stream(), out), "sample_family")
     return list(out)
+
+
+def list_instances(w: "Weights", seed, count, j0=0):
+    """tm_list_instances: (eids [count x 16] int32, records) of samples
+    j0 .. j0 + count - 1."""
+    import torch
+    eids = torch.empty(max(1, count) * 16, dtype=torch.int32, device="cuda")
+    recs = torch.empty(max(1, count) * REC_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    _check(lib().tm_list_instances(w.h, int(seed), int(j0), int(count), _stream(), C.c_void_p(eids.data_ptr()),
+                                   C.c_void_p(recs.data_ptr())), "list_instances")
+    return (eids.cpu().numpy().reshape(-1, 16)[:count],
+            recs.cpu().numpy().view(REC_DTYPE)[:count])
