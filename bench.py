@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="before timing, run a plain device copy of BYTES (3 times) so that "
                          "hardware counters can be scaled by a kernel of known traffic")
-    ap.add_argument("--workload", choices=["medium", "large", "batched", "serving", "weights", "ablation", "trees"],
+    ap.add_argument("--workload", choices=["medium", "large", "batched", "serving", "weights", "ablation", "trees",
+                                           "family"],
                     default="medium",
                     help="medium: the single-job path (default); batched: 64 heterogeneous "
                          "jobs, one launch per job against the batched pass; serving: a Poisson "
@@ -91,6 +92,8 @@ def main():
         return ablation(args)
     if args.workload == "trees":
         return trees(args)
+    if args.workload == "family":
+        return family(args)
 
     import ctypes as C
 
@@ -656,6 +659,80 @@ def trees(args):
     tg.close()
     print(json.dumps({"workload": "tree choice on the ablation graph (delta 3600, 1e6 samples, 5 seeds)",
                       "motifs": out}), flush=True)
+
+
+FAMILY_TREE = ((0, 1), (1, 2), (2, 3))
+FAMILY = (((0, 1), (1, 2), (2, 3), (3, 0)), ((0, 1), (1, 2), (2, 3), (3, 1)), ((0, 1), (1, 2), (2, 0), (2, 3)),
+          ((3, 0), (0, 1), (1, 2), (2, 3)))
+
+
+def family(args):
+    """A family of four 4-vertex motifs sharing the path a->b->c->d as their
+    tree (the paper counts its 4-vertex motifs at once): one weight build and
+    one stream of 1e7 tree samples completed for all four (tm_sample_family)
+    against one tm_estimate per motif with the same tree and seed; then
+    random instance listing of 1e7 samples of the 4-cycle."""
+    import torch
+
+    from paper_2507_20441_amd import timest as T
+    from paper_2507_20441_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    torch.cuda.set_device(0)
+    mg = W.medium_graph()
+    g = T.Graph(mg.src, mg.dst, mg.t, mg.n)
+    delta, k, seed = 3600, 10_000_000, 1
+    mos = [T.make_motif(e, delta) for e in FAMILY]
+    trees = []
+    for e in FAMILY:
+        idx = [list(e).index(x) for x in FAMILY_TREE]
+        trees.append(T.make_tree(idx, idx[1]))
+    tree_motif = T.make_motif(FAMILY_TREE, delta)
+
+    def fam():
+        w = T.Weights(g, tree_motif, T.make_tree([0, 1, 2], 1))
+        out = T.sample_family(w, mos, seed, k)
+        w.close()
+        return out
+
+    def sep():
+        return [T.estimate(g, mo, k, seed, tr) for mo, tr in zip(mos, trees)]
+
+    a, b = fam(), sep()
+    same = all(x.acc2.value == y.acc2.value and x.n_valid == y.n_valid and x.estimate == y.estimate
+               for x, y in zip(a, b))
+    assert same, "family results differ from separate runs"
+    tf, ts = [], []
+    for _ in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fam()
+        torch.cuda.synchronize()
+        tf.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        sep()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    w = T.Weights(g, T.make_motif(W.MOTIFS["4cycle"], delta))
+    T.list_instances(w, seed, 1000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rows, recs = T.list_instances(w, seed, k)
+    torch.cuda.synchronize()
+    tl = time.perf_counter() - t0
+    listed = int((rows[:, 0] >= 0).sum())
+    w.close()
+    g.close()
+    line = {
+        "workload": "motif family on the medium graph: 4 motifs on the tree a->b->c->d, delta 3600, 1e7 samples",
+        "family_ms": round(min(tf) * 1e3, 3), "separate_ms": round(min(ts) * 1e3, 3),
+        "speedup": round(min(ts) / min(tf), 3), "identical": same,
+        "estimates": [dict(motif=[list(x) for x in e], estimate=r.estimate,
+                           rel_ci95=(1.96 * r.std_error / r.estimate) if r.estimate else None)
+                      for e, r in zip(FAMILY, a)],
+        "listing": {"samples": k, "listed": listed, "ms_incl_host_copy": round(tl * 1e3, 3)},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def weights_only(args):

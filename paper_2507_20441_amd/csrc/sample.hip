@@ -930,13 +930,14 @@ job_reduce_kernel(const Partial* tile_parts, const int* first, const int* count,
 // edges), with the per-block sums of 2 M_phi / N_phi.
 template <bool kGeneral>
 __global__ void __launch_bounds__(kBlock)
-family_kernel(SampleArgs a, const tm_sample_rec* recs, u64 count, Partial* parts, int* ovf) {
+family_kernel(SampleArgs a, const tm_sample_rec* recs, const uint32_t* order, u64 count, Partial* parts,
+              int* ovf) {
     constexpr int NT = kMaxSlots - 1;
     const DevGraph& G = a.G;
     LaneAcc L = lane_zero();
     u64 nb = 0;
-    for (u64 r = (u64)blockIdx.x * kBlock + threadIdx.x; r < count; r += (u64)gridDim.x * kBlock) {
-        const tm_sample_rec& rec = recs[r];
+    for (u64 x0 = (u64)blockIdx.x * kBlock + threadIdx.x; x0 < count; x0 += (u64)gridDim.x * kBlock) {
+        const tm_sample_rec& rec = recs[order[x0]];
         if (rec.status != 0) continue;
         int32_t img[TM_MAX_K];
         int64_t te[NT];
@@ -971,6 +972,18 @@ family_kernel(SampleArgs a, const tm_sample_rec* recs, u64 count, Partial* parts
 // walk over the motif edges in pi order -- tree edges fixed, non-tree edges
 // over their multi-edge lists within delta of the tree times, in eid order --
 // with strictly increasing times and everything within delta of the first.
+// Family passes visit the records in root order (as the sampler does): the
+// root's T-order position and interval parity, invalid records last.
+__global__ void __launch_bounds__(kBlock)
+family_keys_kernel(const tm_sample_rec* recs, u64 count, const int32_t* tpos0, int center_rank, uint32_t last,
+                   uint32_t* keys, uint32_t* vals) {
+    const u64 r = (u64)blockIdx.x * kBlock + threadIdx.x;
+    if (r >= count) return;
+    const tm_sample_rec& rec = recs[r];
+    keys[r] = rec.status == 0 ? (uint32_t)tpos0[rec.eid[center_rank]] * 2u + (rec.interval & 1u) : last;
+    vals[r] = (uint32_t)r;
+}
+
 constexpr uint32_t kListDraw = 15;
 constexpr u64 kListMax = (u64)1 << 20;
 
@@ -1639,14 +1652,31 @@ int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hip
     tm_sample_rec* recs = nullptr;
     Partial* parts = nullptr;
     int* ovf = nullptr;
+    uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
     TM_HIP(dev_alloc((void**)&recs, chunk * sizeof(tm_sample_rec), st));
     TM_HIP(dev_alloc((void**)&parts, (blocks + 1) * sizeof(Partial), st));
     TM_HIP(dev_alloc((void**)&ovf, sizeof(int), st));
+    TM_HIP(dev_alloc((void**)&k0, chunk * sizeof(uint32_t), st));
+    TM_HIP(dev_alloc((void**)&v0, chunk * sizeof(uint32_t), st));
+    TM_HIP(dev_alloc((void**)&k1, chunk * sizeof(uint32_t), st));
+    TM_HIP(dev_alloc((void**)&v1, chunk * sizeof(uint32_t), st));
+    int center_rank = 0;
+    for (int x = 0; x < w->plan.nt; ++x)
+        if (w->plan.by_pi[x] == 0) center_rank = x;
+    const uint32_t last = (uint32_t)(2 * (u64)w->g->m);
+    const int key_bits = bits_of(last);
     int rc = TM_OK;
     for (u64 c0 = 0; c0 < k && rc == TM_OK; c0 += chunk) {
         const u64 cnt = std::min<u64>(chunk, k - c0);
         tm_result tree;
         rc = sample_run(w, seed, c0, cnt, k, st, &tree, recs, nullptr);
+        if (rc != TM_OK) break;
+        hipLaunchKernelGGL(family_keys_kernel, dim3((unsigned)((cnt + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                           (const tm_sample_rec*)recs, cnt, (const int32_t*)w->g->d.tpos[0], center_rank, last, k0,
+                           v0);
+        uint32_t *ks, *order;
+        rc = fill_u32(ovf, 1, 0u, st);
+        if (rc == TM_OK) rc = radix_sort_pairs<uint32_t>(k0, v0, k1, v1, (int64_t)cnt, 0, key_bits, &ks, &order, ovf, st);
         if (rc != TM_OK) break;
         JobSums t;
         t.n_valid = tree.n_valid;
@@ -1660,10 +1690,10 @@ int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hip
             const dim3 grid((unsigned)std::min<u64>((cnt + kBlock - 1) / kBlock, (u64)blocks));
             if (args[f].general_runs)
                 hipLaunchKernelGGL(family_kernel<true>, grid, dim3(kBlock), 0, st, args[f], (const tm_sample_rec*)recs,
-                                   cnt, parts, ovf);
+                                   (const uint32_t*)order, cnt, parts, ovf);
             else
                 hipLaunchKernelGGL(family_kernel<false>, grid, dim3(kBlock), 0, st, args[f], (const tm_sample_rec*)recs,
-                                   cnt, parts, ovf);
+                                   (const uint32_t*)order, cnt, parts, ovf);
             if (hipGetLastError() != hipSuccess) { rc = tm_fail(TM_EDEVICE, "family: launch"); break; }
             hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const Partial*)parts, (int)grid.x,
                                parts + blocks);
@@ -1684,9 +1714,8 @@ int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hip
             sums_merge(sums[f], x);
         }
     }
-    (void)dev_free(recs, st);
-    (void)dev_free(parts, st);
-    (void)dev_free(ovf, st);
+    for (void* q : {(void*)recs, (void*)parts, (void*)ovf, (void*)k0, (void*)v0, (void*)k1, (void*)v1})
+        (void)dev_free(q, st);
     (void)sync_stream(st);
     return rc;
 }
