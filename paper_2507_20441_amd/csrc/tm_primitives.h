@@ -180,7 +180,12 @@ template <typename K>
 __global__ void __launch_bounds__(kBlock)
 radix_scatter_kernel(const K* keys, const uint32_t* vals, K* okeys, uint32_t* ovals, int64_t n,
                      int shift, int bits, const uint32_t* offs, int64_t ntiles) {
+    static_assert(kBlock == kRadix, "one thread per digit");
     __shared__ uint32_t cnt[kWaves][kRadix];
+    __shared__ uint32_t dstart[kRadix];  // tile-local start of each digit's run
+    __shared__ uint32_t gbase[kRadix];   // global start of this tile's run of each digit
+    __shared__ K skey[kSortTile];
+    __shared__ uint32_t sval[kSortTile];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int w = 0; w < kWaves; ++w) cnt[w][threadIdx.x] = 0;
     __syncthreads();
@@ -188,7 +193,8 @@ radix_scatter_kernel(const K* keys, const uint32_t* vals, K* okeys, uint32_t* ov
     const u64 lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     // wave w owns tile positions [w*64*kSortItems, (w+1)*64*kSortItems), in
     // rounds of 64 consecutive keys: the wave sees its keys in input order
-    const int64_t wbase = (int64_t)blockIdx.x * kSortTile + (int64_t)wave * 64 * kSortItems;
+    const int64_t tbase = (int64_t)blockIdx.x * kSortTile;
+    const int64_t wbase = tbase + (int64_t)wave * 64 * kSortItems;
     K key[kSortItems];
     uint32_t val[kSortItems];
     uint32_t dig[kSortItems];
@@ -213,10 +219,22 @@ radix_scatter_kernel(const K* keys, const uint32_t* vals, K* okeys, uint32_t* ov
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    // per digit: global offset of this tile, then waves in order
+    // per digit (one thread each): the tile's count, then its exclusive scan
+    // over digits (the tile-local start), and each wave's start inside it
+    const uint32_t d = threadIdx.x;
+    uint32_t total = 0;
+    for (int w = 0; w < kWaves; ++w) total += cnt[w][d];
+    dstart[d] = total;
+    gbase[d] = offs[(int64_t)d * ntiles + blockIdx.x];
+    __syncthreads();
+    for (int off = 1; off < kRadix; off <<= 1) {
+        const uint32_t x = d >= (uint32_t)off ? dstart[d - off] : 0u;
+        __syncthreads();
+        dstart[d] += x;
+        __syncthreads();
+    }
     {
-        const uint32_t d = threadIdx.x;
-        uint32_t run = offs[(int64_t)d * ntiles + blockIdx.x];
+        uint32_t run = dstart[d] - total;  // exclusive
         for (int w = 0; w < kWaves; ++w) {
             const uint32_t c = cnt[w][d];
             cnt[w][d] = run;
@@ -224,14 +242,26 @@ radix_scatter_kernel(const K* keys, const uint32_t* vals, K* okeys, uint32_t* ov
         }
     }
     __syncthreads();
+    dstart[d] = cnt[0][d];
+    // keys to their tile-local sorted places
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t i = wbase + (int64_t)k * 64 + lane;
         if (i < n) {
-            const uint32_t pos = cnt[wave][dig[k]] + rank[k];
-            okeys[pos] = key[k];
-            ovals[pos] = val[k];
+            const uint32_t lp = cnt[wave][dig[k]] + rank[k];
+            skey[lp] = key[k];
+            sval[lp] = val[k];
         }
+    }
+    __syncthreads();
+    // out in tile-local order: each digit's run goes to consecutive addresses
+    const int tn = (int)((n - tbase) < kSortTile ? (n - tbase) : kSortTile);
+    for (int p = threadIdx.x; p < tn; p += kBlock) {
+        const K kk = skey[p];
+        const uint32_t dd = (uint32_t)((kk >> shift) & mask);
+        const uint32_t gpos = gbase[dd] + ((uint32_t)p - dstart[dd]);
+        okeys[gpos] = kk;
+        ovals[gpos] = sval[p];
     }
 }
 
