@@ -144,6 +144,43 @@ __global__ void fill_n_order_kernel(const uint32_t* eids, const int64_t* t, cons
     neid[p] = (int32_t)e;
 }
 
+// The same two fills reading one packed key t << 2bn | u << bn | v per eid
+// (the canonical sort's output) instead of the separate edge arrays.
+__device__ __forceinline__ void unpack_tuv(u64 k, int bn, int64_t& t, int32_t& u, int32_t& v) {
+    const u64 mask = (1ull << bn) - 1;
+    t = (int64_t)(k >> (2 * bn));
+    u = (int32_t)((k >> bn) & mask);
+    v = (int32_t)(k & mask);
+}
+
+__global__ void fill_t_order_packed_kernel(const uint32_t* eids, const u64* pk, int bn, int dir, int64_t m,
+                                           int64_t* lt, int32_t* leid, int32_t* lnbr, int32_t* pos) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= m) return;
+    const uint32_t e = eids[p];
+    int64_t t;
+    int32_t u, v;
+    unpack_tuv(pk[e], bn, t, u, v);
+    lt[p] = t;
+    leid[p] = (int32_t)e;
+    lnbr[p] = dir == 0 ? v : u;
+    pos[e] = (int32_t)p;
+}
+
+__global__ void fill_n_order_packed_kernel(const uint32_t* eids, const u64* pk, int bn, int dir,
+                                           const int32_t* tpos, int64_t m, int bt, u64* nkey, int32_t* nxref,
+                                           int32_t* neid) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= m) return;
+    const uint32_t e = eids[p];
+    int64_t t;
+    int32_t u, v;
+    unpack_tuv(pk[e], bn, t, u, v);
+    nkey[p] = ((u64)(uint32_t)(dir == 0 ? v : u) << bt) | (u64)t;
+    nxref[p] = tpos[e];
+    neid[p] = (int32_t)e;
+}
+
 // List offsets from the owner-sorted keys: off[v] is the first position whose
 // owner is >= v.  Position p writes the offsets of the owners in
 // (key[p-1], key[p]]; the last position also closes the owners after it.
@@ -270,8 +307,12 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
     // --- per-vertex lists ---------------------------------------------------
     // dir 0: out-lists (key = source, neighbour = destination)
     // dir 1: in-lists  (key = destination, neighbour = source)
-    uint32_t* k32a = reinterpret_cast<uint32_t*>(ka);
-    uint32_t* k32b = reinterpret_cast<uint32_t*>(kb);
+    // with one packed key per edge, the sorted keys stay for the fills and
+    // the other key buffer holds both 32-bit key buffers of the list sorts
+    const bool packed = one_key && bn > 0;
+    u64* kspare = kres == ka ? kb : ka;
+    uint32_t* k32a = reinterpret_cast<uint32_t*>(packed ? kspare : ka);
+    uint32_t* k32b = packed ? k32a + m : reinterpret_cast<uint32_t*>(kb);
     int32_t* tpos[2];
     for (int dir = 0; dir < 2; ++dir) {
         const int32_t* key_by_eid = dir == 0 ? esrc : edst;
@@ -289,9 +330,13 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
         TM_HIP(hipGetLastError());
         uint32_t *kr, *vr;
         TM_TRY(radix_sort_pairs<uint32_t>(k32a, va, k32b, vb, m, 0, bn, &kr, &vr, flags + 1, st));
-        hipLaunchKernelGGL(fill_t_order_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
-                           (const uint32_t*)vr, (const int64_t*)et, nbr_by_eid, m, lt, leid, lnbr,
-                           tpos[dir]);
+        if (packed)
+            hipLaunchKernelGGL(fill_t_order_packed_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
+                               (const uint32_t*)vr, (const u64*)kres, bn, dir, m, lt, leid, lnbr, tpos[dir]);
+        else
+            hipLaunchKernelGGL(fill_t_order_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
+                               (const uint32_t*)vr, (const int64_t*)et, nbr_by_eid, m, lt, leid, lnbr,
+                               tpos[dir]);
         TM_HIP(hipGetLastError());
         hipLaunchKernelGGL(offsets_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
                            (const uint32_t*)kr, m, n, off);
@@ -319,9 +364,14 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
         TM_HIP(hipGetLastError());
         uint32_t *kr, *vr;
         TM_TRY(radix_sort_pairs<uint32_t>(k32a, va, k32b, vb, m, 0, bn, &kr, &vr, flags + 1, st));
-        hipLaunchKernelGGL(fill_n_order_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
-                           (const uint32_t*)vr, (const int64_t*)et, nbr_by_eid,
-                           (const int32_t*)tpos[dir], m, D.bt, nkey, nxref, neid);
+        if (packed)
+            hipLaunchKernelGGL(fill_n_order_packed_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
+                               (const uint32_t*)vr, (const u64*)kres, bn, dir, (const int32_t*)tpos[dir], m, D.bt,
+                               nkey, nxref, neid);
+        else
+            hipLaunchKernelGGL(fill_n_order_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
+                               (const uint32_t*)vr, (const int64_t*)et, nbr_by_eid,
+                               (const int32_t*)tpos[dir], m, D.bt, nkey, nxref, neid);
         TM_HIP(hipGetLastError());
         D.nkey[dir] = nkey;
         D.nxref[dir] = nxref;

@@ -37,7 +37,9 @@ struct SampleArgs {
     int esrc[kMaxSlots], edst[kMaxSlots];  // motif vertices of each slot's edge
     int parent[kMaxSlots], side[kMaxSlots], dir[kMaxSlots], beta[kMaxSlots], leaf[kMaxSlots];
     int new_vertex[kMaxSlots];
+    int gv[kMaxSlots], ov[kMaxSlots];  // a child's shared motif vertex and its parent's other end
     int by_pi[kMaxSlots];
+    int pi_pos[kMaxSlots];  // inverse of by_pi
     int same_window[kMaxSlots];
     const void* qt[kMaxSlots][2];
     const void* qn[kMaxSlots][2];
@@ -491,52 +493,48 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
     u64 flags = L.flags, nb = L.nb;
     bool ovf = L.ovf, bad = L.bad;
     for (u64 x = x0; x < xend; x += stride) {
-        int32_t ee[NT], eu[NT], ev[NT];
         int64_t te[NT];
         int32_t img[TM_MAX_K];
         sfor<0, TM_MAX_K>([&](auto xx) { img[decltype(xx)::value] = -1 - decltype(xx)::value; });
         u64 r;
-        int32_t i;
+        int32_t i, e0, u0, v0;
         if constexpr (kSorted) {
             // the root was drawn by root_kernel; lanes follow the sorted order
             const uint32_t key = a.skey[x] - a.key_base;
             r = a.sval[x];
             const int32_t pos = (int32_t)(key >> 1);
-            const int32_t e0 = G.leid[0][pos];
-            ee[0] = e0;
+            e0 = G.leid[0][pos];
             te[0] = G.lt[0][pos];
-            ev[0] = G.lnbr[0][pos];
-            eu[0] = G.src[e0];
+            v0 = G.lnbr[0][pos];
+            u0 = G.src[e0];
             const int64_t blk = te[0] / a.ilen;
             i = (int32_t)(((blk & 1) == (int64_t)(key & 1)) ? blk : blk - 1);
             if constexpr (kCount) nb += 8 + 20;
         } else {
             // draw 0: interval, then center edge
             r = x;
-            int32_t e0;
             if (!draw_root<W>(a, cum, Wtot, a.j0 + r, i, e0, kCount ? &nb : nullptr)) { bad = true; break; }
             if constexpr (kCount) nb += 16;
-            ee[0] = e0;
             te[0] = G.t[e0];
-            eu[0] = G.src[e0];
-            ev[0] = G.dst[e0];
+            u0 = G.src[e0];
+            v0 = G.dst[e0];
         }
         const u64 j = a.j0 + r;
         const int par = i & 1;
-        put(img, a.esrc[0], eu[0]);
-        put(img, a.edst[0], ev[0]);
+        put(img, a.esrc[0], u0);
+        put(img, a.edst[0], v0);
+        // matched eids go straight to the record, at the slot's rank in pi
+        if (a.recs) a.recs[r].eid[a.pi_pos[0]] = e0;
         const int64_t ilo_t = (int64_t)i * a.ilen, ihi_t = ((int64_t)i + 2) * a.ilen - 1;
         Bounds last;  // the previous child's window, reused by a leaf sibling with the same one
         last.p0 = last.p1 = last.q0 = last.q1 = last.a = last.b = 0;
-        // draws 1..nt-1: children in pre-order
-        sfor<1, NT>([&](auto sc) {
-            constexpr int s = decltype(sc)::value;
-            if (s >= a.nt || bad) return;
-            const int p = a.parent[s];
-            const int32_t pu = pick(eu, p), pv = pick(ev, p);
-            const int64_t pt = pick(te, p);
-            const int32_t g = a.side[s] ? pv : pu;
-            const int32_t o = a.side[s] ? pu : pv;
+        // draws 1..nt-1: children in pre-order.  A runtime loop: the slot's
+        // plan entries are read inside it rather than held for every slot.
+#pragma unroll 1
+        for (int s = 1; s < a.nt; ++s) {
+            const int64_t pt = pick(te, a.parent[s]);
+            const int32_t g = pick(img, a.gv[s]);
+            const int32_t o = pick(img, a.ov[s]);
             int64_t wlo = a.beta[s] < 0 ? pt - a.delta : pt;
             int64_t whi = a.beta[s] < 0 ? pt : pt + a.delta;
             wlo = wlo > ilo_t ? wlo : ilo_t;
@@ -557,7 +555,7 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
                 mass = (qt[w.p1] - bt0) - (qn[w.q1] - bn0);
             }
             // a child of a positive-weight match always has positive mass
-            if (mass == 0 || w.p1 <= w.p0) { bad = true; return; }
+            if (mass == 0 || w.p1 <= w.p0) { bad = true; break; }
             const W rr = scale(draw_block(a.seed, j, (uint32_t)s), mass);
             // J: excluded entries whose preceding candidate mass is <= rr
             const int32_t* xref = G.nxref[d];
@@ -592,12 +590,10 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
                 nb += 16;
             }
             const int32_t nbv = G.lnbr[d][pos];
-            ee[s] = G.leid[d][pos];
-            te[s] = G.lt[d][pos];
-            eu[s] = d == 0 ? g : nbv;
-            ev[s] = d == 0 ? nbv : g;
+            put(te, s, G.lt[d][pos]);
+            if (a.recs) a.recs[r].eid[a.pi_pos[s]] = G.leid[d][pos];
             put(img, a.new_vertex[s], nbv);
-        });
+        }
         if (bad) break;
         // Alg. 4: vertex map 1-1, then delta range, then edge order
         uint32_t status = 0;
@@ -655,9 +651,9 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
             out.status = status;
             out.n_phi = n_phi;
             out.pad = 0;
-            sfor<0, 8>([&](auto xc) {
+            sfor<1, 8>([&](auto xc) {
                 constexpr int x = decltype(xc)::value;
-                out.eid[x] = x < a.nt ? pick(ee, a.by_pi[x < NT ? x : 0]) : -1;
+                if (x >= a.nt) out.eid[x] = -1;
             });
             out.m_phi.lo = (u64)m_phi;
             out.m_phi.hi = (u64)(m_phi >> 64);
@@ -796,7 +792,13 @@ void fill_args(const tm_weights* w, SampleArgs* out, size_t* lds_out) {
         a.beta[s] = P.beta[s];
         a.leaf[s] = P.n_children[s] == 0;
         a.new_vertex[s] = P.new_vertex[s];
+        if (s > 0) {
+            const int pe = P.edge[P.parent[s]];
+            a.gv[s] = P.side[s] ? P.mo.dst[pe] : P.mo.src[pe];
+            a.ov[s] = P.side[s] ? P.mo.src[pe] : P.mo.dst[pe];
+        }
         a.by_pi[s] = P.by_pi[s];
+        a.pi_pos[P.by_pi[s]] = s;
         a.same_window[s] = P.same_window[s];
         for (int par = 0; par < 2; ++par) {
             a.qt[s][par] = w->qt[s][par];
