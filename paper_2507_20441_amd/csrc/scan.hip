@@ -1,4 +1,5 @@
-// Scan of tile sums for the device-wide exclusive scan (tm_primitives.h).
+// Scan of tile sums for the device-wide exclusive scan, and the per-digit row
+// scans of the radix sort (tm_primitives.h).
 #include <algorithm>
 
 #include "tm_primitives.h"
@@ -31,6 +32,24 @@ __global__ void __launch_bounds__(kBlock) scan_single_kernel(u128* a, int64_t n,
     if (carry) atomicOr(ovf, 1);
 }
 
+// One block per digit; each lane owns a run of consecutive tiles.
+__global__ void __launch_bounds__(kBlock) radix_rowscan_kernel(uint32_t* hist, int64_t ntiles, uint32_t* totals) {
+    __shared__ uint32_t wsum[kWaves];
+    uint32_t* row = hist + (int64_t)blockIdx.x * ntiles;
+    const int64_t per = (ntiles + kBlock - 1) / kBlock;
+    const int64_t lo = (int64_t)threadIdx.x * per;
+    const int64_t hi = lo + per < ntiles ? lo + per : ntiles;
+    uint32_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += row[i];
+    uint32_t run = block_excl_scan_256(s, wsum);
+    for (int64_t i = lo; i < hi; ++i) {
+        const uint32_t c = row[i];
+        row[i] = run;
+        run += c;
+    }
+    if (threadIdx.x == kBlock - 1) totals[blockIdx.x] = run;
+}
+
 }  // namespace
 
 __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
@@ -54,4 +73,10 @@ int scan_parts(u128* part, int64_t nb, int* ovf, hipStream_t st) {
         return TM_OK;
     }
     return device_exclusive_scan<u128>(ArrayReader128{part}, nb, part, ovf, st);
+}
+
+int radix_rowscan(uint32_t* hist, int64_t ntiles, uint32_t* totals, hipStream_t st) {
+    hipLaunchKernelGGL(radix_rowscan_kernel, dim3((unsigned)kRadix), dim3(kBlock), 0, st, hist, ntiles, totals);
+    TM_HIP(hipGetLastError());
+    return TM_OK;
 }

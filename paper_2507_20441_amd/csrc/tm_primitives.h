@@ -155,9 +155,11 @@ int device_exclusive_scan(F f, int64_t n, T* out, int* ovf, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort of (key, value) pairs, 8-bit digits.
-// Per pass: tile histograms (digit-major), their exclusive scan, then a
-// scatter in which every wave ranks its keys in input order with ballots.
+// Stable LSD radix sort of (key, value) pairs, 8-bit digits (fewer than 2^32).
+// Per pass: tile histograms (digit-major), an exclusive scan of each digit's
+// row with the digit totals, then a scatter in which every wave ranks its
+// keys in input order with ballots and each digit's start is the scan of the
+// totals.
 // ---------------------------------------------------------------------------
 template <typename K>
 __global__ void __launch_bounds__(kBlock)
@@ -176,16 +178,40 @@ radix_hist_kernel(const K* keys, int64_t n, int shift, int bits, uint32_t* hist,
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
+// Exclusive scan of v over the block's 256 threads (thread t holds entry t):
+// shuffles inside each wave, then the wave totals through LDS.
+__device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t* wsum) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += o;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) before += w < wave ? wsum[w] : 0u;
+    __syncthreads();
+    return before + inc - v;
+}
+
+// Per digit: the exclusive scan of the digit's row of tile counts
+// (hist[d * ntiles + tile]), in place, and the row's total in totals[d].
+int radix_rowscan(uint32_t* hist, int64_t ntiles, uint32_t* totals, hipStream_t st);
+
 template <typename K>
 __global__ void __launch_bounds__(kBlock)
 radix_scatter_kernel(const K* keys, const uint32_t* vals, K* okeys, uint32_t* ovals, int64_t n,
-                     int shift, int bits, const uint32_t* offs, int64_t ntiles) {
+                     int shift, int bits, const uint32_t* offs, const uint32_t* totals, int64_t ntiles) {
     static_assert(kBlock == kRadix, "one thread per digit");
     __shared__ uint32_t cnt[kWaves][kRadix];
     __shared__ uint32_t dstart[kRadix];  // tile-local start of each digit's run
     __shared__ uint32_t gbase[kRadix];   // global start of this tile's run of each digit
     __shared__ K skey[kSortTile];
     __shared__ uint32_t sval[kSortTile];
+    __shared__ uint32_t wsum[kWaves];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int w = 0; w < kWaves; ++w) cnt[w][threadIdx.x] = 0;
     __syncthreads();
@@ -224,17 +250,12 @@ radix_scatter_kernel(const K* keys, const uint32_t* vals, K* okeys, uint32_t* ov
     const uint32_t d = threadIdx.x;
     uint32_t total = 0;
     for (int w = 0; w < kWaves; ++w) total += cnt[w][d];
-    dstart[d] = total;
-    gbase[d] = offs[(int64_t)d * ntiles + blockIdx.x];
-    __syncthreads();
-    for (int off = 1; off < kRadix; off <<= 1) {
-        const uint32_t x = d >= (uint32_t)off ? dstart[d - off] : 0u;
-        __syncthreads();
-        dstart[d] += x;
-        __syncthreads();
-    }
+    // global start of this tile's run of digit d: the digit's start (scan of
+    // the digit totals) plus the earlier tiles' counts of d
+    gbase[d] = block_excl_scan_256(totals[d], wsum) + offs[(int64_t)d * ntiles + blockIdx.x];
+    const uint32_t local = block_excl_scan_256(total, wsum);
     {
-        uint32_t run = dstart[d] - total;  // exclusive
+        uint32_t run = local;  // exclusive
         for (int w = 0; w < kWaves; ++w) {
             const uint32_t c = cnt[w][d];
             cnt[w][d] = run;
@@ -283,17 +304,17 @@ int radix_sort_pairs(K* keys, uint32_t* vals, K* tkeys, uint32_t* tvals, int64_t
     if (n > 1 && nbits > 0) {
         const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
         uint32_t* hist = nullptr;
-        TM_HIP(dev_alloc((void**)&hist, (ntiles * kRadix + 1) * sizeof(uint32_t), st));
+        TM_HIP(dev_alloc((void**)&hist, (ntiles * kRadix + kRadix) * sizeof(uint32_t), st));
+        uint32_t* totals = hist + ntiles * kRadix;
         for (int shift = lo_bit; shift < nbits; shift += kRadixBits) {
             const int bits = nbits - shift < kRadixBits ? nbits - shift : kRadixBits;
             hipLaunchKernelGGL((radix_hist_kernel<K>), dim3((unsigned)ntiles), dim3(kBlock), 0, st,
                                (const K*)ka, n, shift, bits, hist, ntiles);
             TM_HIP(hipGetLastError());
-            TM_TRY(device_exclusive_scan<uint32_t>(HistReader{hist}, ntiles * kRadix, hist, ovf,
-                                                   st));
+            TM_TRY(radix_rowscan(hist, ntiles, totals, st));
             hipLaunchKernelGGL((radix_scatter_kernel<K>), dim3((unsigned)ntiles), dim3(kBlock), 0,
                                st, (const K*)ka, (const uint32_t*)va, kb, vb, n, shift, bits,
-                               (const uint32_t*)hist, ntiles);
+                               (const uint32_t*)hist, (const uint32_t*)totals, ntiles);
             TM_HIP(hipGetLastError());
             K* tk = ka; ka = kb; kb = tk;
             uint32_t* tv = va; va = vb; vb = tv;
