@@ -47,7 +47,7 @@ struct SampleArgs {
     const int32_t* ilo;
     const int32_t* ihi;
     const void* cumW;
-    const u64* guide;  // root pairs at 2^guide_bits + 1 evenly spaced draws (see weights)
+    const RootGuide* guide;  // root pairs at 2^guide_bits + 1 evenly spaced draws (see weights)
     int guide_bits;
     const void* ioff;  // per interval: cum[i] - qc[lo_i]
     // captured passes: W read from the job's table, and the job skipped when
@@ -370,25 +370,33 @@ __device__ __forceinline__ void block_reduce_write(Partial acc, Partial* out) {
 // Inconsistent tables give a harmless key and set bad.
 template <typename W>
 __device__ __forceinline__ bool draw_root(const SampleArgs& a, const W* cum, W Wtot, u64 j, int32_t& i,
-                                          int32_t& e0, u64* nb = nullptr) {
+                                          int32_t& e0, u64* nb = nullptr, uint32_t* key = nullptr) {
     const X128 X = draw_block(a.seed, j, 0);
-    const W r0 = scale(X, Wtot);
     int32_t i0 = 0, i1 = (int32_t)a.q - 1, ea = -1, eb = 0x7fffffff;
     if (a.guide) {
-        // the guide bucket of X bounds the pair between two guide entries
+        // the guide bucket of X bounds the pair between two guide entries;
+        // equal ends leave one pair (the pair is monotone in X)
         const u64 b = X.hi >> (64 - a.guide_bits);
-        const u64 g0 = a.guide[b], g1 = a.guide[b + 1];
-        i0 = (int32_t)(g0 >> 32);
-        ea = (int32_t)(uint32_t)g0;
-        i1 = (int32_t)(g1 >> 32);
-        eb = (int32_t)(uint32_t)g1;
+        const RootGuide g0 = a.guide[b], g1 = a.guide[b + 1];
+        i0 = (int32_t)(g0.pair >> 32);
+        ea = (int32_t)(uint32_t)g0.pair;
+        i1 = (int32_t)(g1.pair >> 32);
+        eb = (int32_t)(uint32_t)g1.pair;
+        if (g0.pair == g1.pair && i0 >= 0 && i0 < a.q) {
+            i = i0;
+            e0 = ea;
+            if (key) *key = (uint32_t)g0.key;
+            if (nb) *nb += 2 * sizeof(RootGuide);
+            return true;
+        }
     }
+    const W r0 = scale(X, Wtot);
     int32_t span = 0;
     const bool ok = root_pair<W>(cum, a.qc, a.ilo, a.ihi, a.q, r0, i0, i1, ea, eb, i, e0, &span,
                                  static_cast<const W*>(a.ioff));
     if (nb) {
-        if (a.ioff && i0 == i1) *nb += 16 + (1 + probes(span)) * sizeof(W);
-        else *nb += (a.guide ? 16 : 0) + (probes(i1 - i0 + 1) + 2 + probes(span)) * sizeof(W) + 8;
+        if (a.ioff && i0 == i1) *nb += 2 * sizeof(RootGuide) + (1 + probes(span)) * sizeof(W);
+        else *nb += (a.guide ? 2 * sizeof(RootGuide) : 0) + (probes(i1 - i0 + 1) + 2 + probes(span)) * sizeof(W) + 8;
     }
     return ok;
 }
@@ -401,11 +409,12 @@ __device__ __forceinline__ uint32_t root_key(const SampleArgs& a, const W* cum, 
                                              u64 r, bool& bad) {
     (void)ncum;
     int32_t i, e0;
-    if (!draw_root<W>(a, cum, Wtot, a.j0 + r, i, e0)) {
+    uint32_t key = ~0u;  // set by a one-pair guide bucket
+    if (!draw_root<W>(a, cum, Wtot, a.j0 + r, i, e0, nullptr, &key)) {
         bad = true;
         return 0u;
     }
-    return (uint32_t)a.G.tpos[0][e0] * 2u + (uint32_t)(i & 1);
+    return key != ~0u ? key : (uint32_t)a.G.tpos[0][e0] * 2u + (uint32_t)(i & 1);
 }
 
 // Draw 0 of each sample (interval, then center edge), written as a sort key:

@@ -89,6 +89,14 @@ struct X128 {
     u64 lo, hi;
 };
 
+// Root guide entry: the root pair (interval << 32 | eid) of one evenly spaced
+// draw, and that pair's sort key (T-order position of the edge * 2 + interval
+// parity).  A bucket whose two ends hold the same pair holds only that pair.
+struct alignas(16) RootGuide {
+    u64 pair;
+    u64 key;
+};
+
 __device__ __forceinline__ X128 draw_block(u64 seed, u64 j, uint32_t d) {
     Block4 b = philox10((uint32_t)j, (uint32_t)(j >> 32), d, 0u, (uint32_t)seed,
                         (uint32_t)(seed >> 32));

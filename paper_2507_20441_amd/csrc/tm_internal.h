@@ -135,10 +135,10 @@ struct tm_weights {
     int32_t* ilo = nullptr;  // [q] first eid of I_i
     int32_t* ihi = nullptr;  // [q] one past the last eid of I_i
     void* cumW = nullptr;    // [q+1] prefix of W_i
-    // root pairs (interval << 32 | eid) at the draws X = b 2^(128 - guide_bits),
-    // b = 0 .. 2^guide_bits (the last at X = 2^128 - 1): a draw in bucket b
-    // picks a pair between entries b and b + 1
-    u64* guide = nullptr;
+    // root pairs (interval << 32 | eid) and their sort keys at the draws
+    // X = b 2^(128 - guide_bits), b = 0 .. 2^guide_bits (the last at
+    // X = 2^128 - 1): a draw in bucket b picks a pair between entries b and b + 1
+    RootGuide* guide = nullptr;
     int guide_bits = 0;
     void* ioff = nullptr;    // [q] cum[i] - qc[lo_i] of the interval's parity
     DevArena arena;

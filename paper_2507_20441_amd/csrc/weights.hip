@@ -233,13 +233,14 @@ struct IntervalWeight {
 template <typename W>
 __global__ void __launch_bounds__(kBlock)
 guide_kernel(const W* cum, const void* qc0, const void* qc1, const int32_t* ilo, const int32_t* ihi, int64_t q,
-             int gb, u64* guide) {
+             const int32_t* tpos0, int gb, RootGuide* guide) {
     const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t B = (int64_t)1 << gb;
     if (b > B) return;
     const W Wt = cum[q];
     if (Wt == 0) {
-        guide[b] = 0;
+        guide[b].pair = 0;
+        guide[b].key = 0;
         return;
     }
     X128 X;
@@ -254,7 +255,8 @@ guide_kernel(const W* cum, const void* qc0, const void* qc1, const int32_t* ilo,
     const void* qc[2] = {qc0, qc1};
     int32_t i = 0, e = 0;
     if (!root_pair<W>(cum, qc, ilo, ihi, q, r, 0, (int32_t)q - 1, -1, 0x7fffffff, i, e)) i = e = 0;
-    guide[b] = ((u64)(uint32_t)i << 32) | (uint32_t)e;
+    guide[b].pair = ((u64)(uint32_t)i << 32) | (uint32_t)e;
+    guide[b].key = (u64)((uint32_t)tpos0[e] * 2u + (uint32_t)(i & 1));
 }
 
 // ioff[i] = cum[i] - qc_{i mod 2}[lo_i], modulo the word size.
@@ -399,7 +401,7 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
     const int64_t nb = ((int64_t)1 << w->guide_bits) + 1;
     TM_TRY(arena_alloc(w->arena, &w->guide, (size_t)nb));
     hipLaunchKernelGGL((guide_kernel<W>), dim3(grid_for(nb)), dim3(kBlock), 0, st, (const W*)cum, w->qc[0],
-                       w->qc[1], w->ilo, w->ihi, w->q, w->guide_bits, w->guide);
+                       w->qc[1], w->ilo, w->ihi, w->q, w->g->d.tpos[0], w->guide_bits, w->guide);
     TM_HIP(hipGetLastError());
     return TM_OK;
 }
@@ -476,7 +478,7 @@ u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide) {
     b += 2 * blk((u64)(m + 1) * wsz);                   // qc, per parity
     b += 2 * blk((u64)q * 4) + blk((u64)(q + 1) * wsz); // ilo, ihi, cumW
     b += blk((u64)q * wsz);                              // ioff
-    b += blk((((u64)1 << guide_bits_for(m)) + 1) * 8);  // root guide
+    b += blk((((u64)1 << guide_bits_for(m)) + 1) * sizeof(RootGuide));  // root guide
     return b;
 }
 
