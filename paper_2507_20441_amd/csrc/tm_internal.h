@@ -163,7 +163,7 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
 // values, per parity).
 u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide);
 u64 weights_build_extra(int64_t m, bool wide);
-// Bits of the root guide for a graph of m edges: about four (interval, edge)
+// Bits of the root guide for a graph of m edges: about two (interval, edge)
 // pairs per bucket, between 2^8 and 2^24 buckets.
 int guide_bits_for(int64_t m);
 

@@ -485,7 +485,7 @@ u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide) {
 int guide_bits_for(int64_t m) {
     int b = 0;
     while (b < 62 && ((int64_t)1 << (b + 1)) <= m) ++b;  // floor(log2 m)
-    b -= 1;                                                // ~2m pairs, ~4 per bucket
+                                                           // ~2m pairs, ~2 per bucket
     return b < 8 ? 8 : (b > 24 ? 24 : b);
 }
 
