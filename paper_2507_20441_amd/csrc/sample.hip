@@ -43,6 +43,9 @@ struct SampleArgs {
     int same_window[kMaxSlots];
     const void* qt[kMaxSlots][2];
     const void* qn[kMaxSlots][2];
+    // kept child windows (see weights): by the parent's list position, per parity
+    const int4* win[kMaxSlots][2];
+    int has_win;
     const void* qc[2];
     const int32_t* ilo;
     const int32_t* ihi;
@@ -489,9 +492,12 @@ __device__ __forceinline__ u128 completions(const SampleArgs& a, const int32_t (
     return m_phi;
 }
 
-template <typename W, bool kCount, bool kGeneral, bool kSorted>
+// kWin (root-sorted only): each child's window is read from the kept table
+// at its parent's list position instead of searched for.
+template <typename W, bool kCount, bool kGeneral, bool kSorted, bool kWin = false>
 __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* cum, u64 x0, u64 xend,
                                                  u64 stride, LaneAcc& L) {
+    static_assert(kSorted || !kWin, "windows are read by list position");
     constexpr int NT = kMaxSlots - 1;  // register slots; a.nt of them are used
     const DevGraph& G = a.G;
     const W Wtot = (W)(((u128)a.W_hi << 64) | a.W_lo);
@@ -503,6 +509,7 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
     bool ovf = L.ovf, bad = L.bad;
     for (u64 x = x0; x < xend; x += stride) {
         int64_t te[NT];
+        int32_t posv[NT];  // kWin: each slot's position in the list it was drawn from
         int32_t img[TM_MAX_K];
         sfor<0, TM_MAX_K>([&](auto xx) { img[decltype(xx)::value] = -1 - decltype(xx)::value; });
         u64 r;
@@ -512,6 +519,7 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
             const uint32_t key = a.skey[x] - a.key_base;
             r = a.sval[x];
             const int32_t pos = (int32_t)(key >> 1);
+            if constexpr (kWin) posv[0] = pos;
             e0 = G.leid[0][pos];
             te[0] = G.lt[0][pos];
             v0 = G.lnbr[0][pos];
@@ -549,7 +557,19 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
             wlo = wlo > ilo_t ? wlo : ilo_t;
             whi = whi < ihi_t ? whi : ihi_t;
             const int d = a.dir[s];
-            Bounds w = a.same_window[s] ? last : window_bounds(G, d, g, o, wlo, whi);
+            Bounds w;
+            if (a.same_window[s]) {
+                w = last;
+            } else if constexpr (kWin) {
+                const int4 b = a.win[s][par][pick(posv, a.parent[s])];
+                w.p0 = b.x;
+                w.p1 = b.y;
+                w.q0 = b.z;
+                w.q1 = b.w;
+                w.a = w.b = 0;
+            } else {
+                w = window_bounds(G, d, g, o, wlo, whi);
+            }
             if (!a.exclude) w.q1 = w.q0;  // constraint 2 off: nothing excluded
             last = w;
             const bool leaf = a.leaf[s] != 0;
@@ -592,14 +612,17 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
             }
             pos = pos < w.p0 ? w.p0 : (pos >= w.p1 ? w.p1 - 1 : pos);
             if constexpr (kCount) {
-                if (!a.same_window[s])
-                    nb += 8 + (2 * probes(w.b - w.a) + probes(w.b - w.p0) + probes(w.b - w.q0)) * 8;
+                if (!a.same_window[s]) {
+                    if constexpr (kWin) nb += sizeof(int4);
+                    else nb += 8 + (2 * probes(w.b - w.a) + probes(w.b - w.p0) + probes(w.b - w.q0)) * 8;
+                }
                 nb += probes(w.q1 - w.q0) * (4 + (leaf ? 0 : 2 * sizeof(W)));
                 if (!leaf) nb += (5 + probes(w.p1 - w.p0)) * sizeof(W);
                 nb += 16;
             }
             const int32_t nbv = G.lnbr[d][pos];
             put(te, s, G.lt[d][pos]);
+            if constexpr (kWin) put(posv, s, pos);
             if (a.recs) a.recs[r].eid[a.pi_pos[s]] = G.leid[d][pos];
             put(img, a.new_vertex[s], nbv);
         }
@@ -708,7 +731,7 @@ __device__ __forceinline__ void lanes_reduce(const LaneAcc& L, Partial* out, int
     if (L.bad) atomicOr(ovf, 2);
 }
 
-template <typename W, bool kCount, bool kGeneral, bool kSorted>
+template <typename W, bool kCount, bool kGeneral, bool kSorted, bool kWin>
 __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
     extern __shared__ unsigned char lds_raw[];
     const W* cumG = static_cast<const W*>(a.cumW);
@@ -720,7 +743,7 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
     }
     const W* cum = a.cum_in_lds ? cumL : cumG;
     LaneAcc L = lane_zero();
-    sample_positions<W, kCount, kGeneral, kSorted>(a, cum, (u64)blockIdx.x * kBlock + threadIdx.x,
+    sample_positions<W, kCount, kGeneral, kSorted, kWin>(a, cum, (u64)blockIdx.x * kBlock + threadIdx.x,
                                                    a.count, (u64)gridDim.x * kBlock, L);
     lanes_reduce(L, &a.parts[blockIdx.x], a.ovf);
 }
@@ -751,10 +774,19 @@ __global__ void fill_undrawn_kernel(tm_sample_rec* recs, u64 count) {
 
 template <typename W, bool kCount, bool kSorted>
 void launch_sample(dim3 grid, size_t lds, hipStream_t st, const SampleArgs& a) {
+    if constexpr (kSorted) {
+        if (a.has_win) {
+            if (a.general_runs)
+                hipLaunchKernelGGL((sample_kernel<W, kCount, true, true, true>), grid, dim3(kBlock), lds, st, a);
+            else
+                hipLaunchKernelGGL((sample_kernel<W, kCount, false, true, true>), grid, dim3(kBlock), lds, st, a);
+            return;
+        }
+    }
     if (a.general_runs)
-        hipLaunchKernelGGL((sample_kernel<W, kCount, true, kSorted>), grid, dim3(kBlock), lds, st, a);
+        hipLaunchKernelGGL((sample_kernel<W, kCount, true, kSorted, false>), grid, dim3(kBlock), lds, st, a);
     else
-        hipLaunchKernelGGL((sample_kernel<W, kCount, false, kSorted>), grid, dim3(kBlock), lds, st, a);
+        hipLaunchKernelGGL((sample_kernel<W, kCount, false, kSorted, false>), grid, dim3(kBlock), lds, st, a);
 }
 
 template <bool kCount>
@@ -812,8 +844,10 @@ void fill_args(const tm_weights* w, SampleArgs* out, size_t* lds_out) {
         for (int par = 0; par < 2; ++par) {
             a.qt[s][par] = w->qt[s][par];
             a.qn[s][par] = w->qn[s][par];
+            a.win[s][par] = w->win[s][par];
         }
     }
+    a.has_win = w->has_win ? 1 : 0;
     a.qc[0] = w->qc[0];
     a.qc[1] = w->qc[1];
     a.ilo = w->ilo;
@@ -916,8 +950,12 @@ batch_sample_kernel(const SampleArgs* jobs, const Tile* tiles, int n_tiles, int*
         const SampleArgs& a = jobs[T.job];
         LaneAcc L = lane_zero();
         const bool skip = (a.wflag && *a.wflag != 0) || (a.Wdev && *static_cast<const W*>(a.Wdev) == 0);
-        if (!skip)
-            sample_positions<W, false, kGeneral, true>(a, nullptr, T.begin + threadIdx.x, T.end, kBlock, L);
+        if (!skip) {
+            if (a.has_win)
+                sample_positions<W, false, kGeneral, true, true>(a, nullptr, T.begin + threadIdx.x, T.end, kBlock, L);
+            else
+                sample_positions<W, false, kGeneral, true, false>(a, nullptr, T.begin + threadIdx.x, T.end, kBlock, L);
+        }
         lanes_reduce(L, &tile_parts[t], ovf);
     }
 }

@@ -129,6 +129,12 @@ struct tm_weights {
     uint32_t constraints = TM_C_ALL;
     int64_t ilen = 0;
     void* vals[kMaxSlots][2] = {};  // build temporaries, null afterwards
+    // child windows, per non-center slot and interval parity: the slot's
+    // candidate window (p0, p1, q0, q1) for every edge its parent can match,
+    // by that edge's position in the list the parent is drawn from (the
+    // out-list T order for the center); null when not kept
+    int4* win[kMaxSlots][2] = {};
+    bool has_win = false;
     void* qt[kMaxSlots][2] = {};
     void* qn[kMaxSlots][2] = {};
     void* qc[2] = {};
@@ -162,6 +168,10 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
 // and the temporaries a build holds on top of them at its peak (one slot's
 // values, per parity).
 u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide);
+// Whether a weight set keeps its child windows: at most kWinMaxBytes of them.
+constexpr u64 kWinMaxBytes = (u64)8 << 30;
+u64 weights_window_bytes(const HostPlan& P, int64_t m);
+bool weights_keep_windows(const HostPlan& P, int64_t m);
 u64 weights_build_extra(int64_t m, bool wide);
 // Bits of the root guide for a graph of m edges: about two (interval, edge)
 // pairs per bucket, between 2^8 and 2^24 buckets.

@@ -43,6 +43,8 @@ struct LevelArgs {
     int nc;
     ChildDesc c[kMaxSlots];
     int walk;          // -1: eid order; 0 / 1: the T order of the out- / in-lists
+    int4* win[kMaxSlots][2];  // per child and parity: its windows (null: not kept)
+    int win_dir;       // the list whose T positions index the windows
     void* out[2];      // per parity: indexed by eid, or by in-list T position (out_by_pos)
     int out_by_pos;    // first of two passes: write where the second pass walks
     const void* in[2]; // second of two passes: the first pass's products, by walk position
@@ -173,6 +175,20 @@ __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
                 xs[2] = (hi < (blk + 1) * a.ilen - 1 ? hi : (blk + 1) * a.ilen - 1) + 1;
             }
             const Bounds3 r = three_bounds(G, d.dir, g, o, xs, a.exclude != 0);
+            if (a.win[c][0]) {
+                // the windows of intervals blk (parity A) and blk - 1 (B)
+                const int64_t at = G.tpos[a.win_dir][e];
+                int4 wa, wb;
+                if (d.beta < 0) {
+                    wa = make_int4(r.p[0], r.p[2], r.q[0], r.q[2]);
+                    wb = make_int4(r.p[1], r.p[2], r.q[1], r.q[2]);
+                } else {
+                    wa = make_int4(r.p[0], r.p[1], r.q[0], r.q[1]);
+                    wb = make_int4(r.p[0], r.p[2], r.q[0], r.q[2]);
+                }
+                a.win[c][parA][at] = wa;
+                a.win[c][parB][at] = hasB ? wb : make_int4(0, 0, 0, 0);
+            }
             if (d.beta < 0) {
                 xa = window_mass<W>(r.p[0], r.p[2], r.q[0], r.q[2], d.leaf, d.qt[parA], d.qn[parA]);
                 xb = hasB ? window_mass<W>(r.p[1], r.p[2], r.q[1], r.q[2], d.leaf, d.qt[parB], d.qn[parB]) : (W)0;
@@ -279,6 +295,7 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
     const HostPlan& P = w->plan;
     const int64_t m = g->m;
     const int64_t delta = P.mo.delta;
+    w->has_win = weights_keep_windows(P, m);
     // bottom-up over heights; leaves other than the center have weight 1 and
     // no table (a lone center edge gets a table of ones)
     for (int h = 0; h <= P.H; ++h) {
@@ -330,6 +347,27 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
                         d.qt[par] = w->qt[c][par];
                         d.qn[par] = w->qn[c][par];
                     }
+                }
+                if (w->has_win) {
+                    // a folded leaf shares the window of the child it joins
+                    for (int j = 0; j < a.nc; ++j) {
+                        const int c = cs[j];
+                        if (a.c[j].copies > 0) {
+                            for (int par = 0; par < 2; ++par) {
+                                TM_TRY(arena_alloc(w->arena, &w->win[c][par], (size_t)m));
+                                a.win[j][par] = w->win[c][par];
+                            }
+                        } else {
+                            for (int j2 = 0; j2 < j; ++j2) {
+                                const ChildDesc& e2 = a.c[j2];
+                                if (e2.leaf && e2.copies > 0 && e2.dir == a.c[j].dir && e2.beta == a.c[j].beta) {
+                                    for (int par = 0; par < 2; ++par) w->win[c][par] = w->win[cs[j2]][par];
+                                    break;
+                                }
+                            }
+                        }
+                    }
+                    a.win_dir = s == 0 ? 0 : (P.alpha[s] > 0 ? 0 : 1);
                 }
                 a.walk = a.nc == 0 ? -1 : side;
                 for (int par = 0; par < 2; ++par) {
@@ -412,6 +450,8 @@ void clear_tables(tm_weights* w) {
         for (void* v : vs)
             if (v) (void)dev_free(v, w->arena.stream);
     std::memset(w->vals, 0, sizeof w->vals);
+    std::memset(w->win, 0, sizeof w->win);
+    w->has_win = false;
     std::memset(w->qt, 0, sizeof w->qt);
     std::memset(w->qn, 0, sizeof w->qn);
     std::memset(w->qc, 0, sizeof w->qc);
@@ -479,7 +519,40 @@ u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide) {
     b += 2 * blk((u64)q * 4) + blk((u64)(q + 1) * wsz); // ilo, ihi, cumW
     b += blk((u64)q * wsz);                              // ioff
     b += blk((((u64)1 << guide_bits_for(m)) + 1) * sizeof(RootGuide));  // root guide
+    if (weights_keep_windows(P, m)) b += weights_window_bytes(P, m);
     return b;
+}
+
+// Child window tables of a plan: one per child that the level kernel does
+// not fold into an earlier leaf sibling (same side, direction and time side).
+static int window_tables(const HostPlan& P) {
+    int n = 0;
+    for (int s = 0; s < P.nt; ++s) {
+        for (int j = 0; j < P.n_children[s]; ++j) {
+            const int c = P.children[s][j];
+            bool folded = false;
+            for (int j2 = 0; j2 < j && P.n_children[c] == 0; ++j2) {
+                const int c2 = P.children[s][j2];
+                if (P.n_children[c2] == 0 && P.side[c2] == P.side[c] && P.alpha[c2] == P.alpha[c] &&
+                    P.beta[c2] == P.beta[c]) {
+                    folded = true;
+                    break;
+                }
+            }
+            if (!folded) ++n;
+        }
+    }
+    return n;
+}
+
+u64 weights_window_bytes(const HostPlan& P, int64_t m) {
+    if (m <= 0) return 0;
+    const u64 per = (((u64)m * sizeof(int4)) + 255) & ~(u64)255;
+    return (u64)window_tables(P) * 2 * per;
+}
+
+bool weights_keep_windows(const HostPlan& P, int64_t m) {
+    return m > 0 && weights_window_bytes(P, m) <= kWinMaxBytes;
 }
 
 int guide_bits_for(int64_t m) {
