@@ -811,6 +811,17 @@ int bits_of(u64 x) {
     return b;
 }
 
+// The lowest root-key bit the root sort looks at.  The sort only groups
+// samples by root for locality (no result depends on the order), so up to
+// six low bits (samples within 32 list positions) stay unsorted when that
+// saves a pass.
+int root_sort_lo_bit(int key_bits) {
+    const int need = key_bits > 6 ? key_bits - 6 : 0;
+    const int passes = (need + kRadixBits - 1) / kRadixBits;
+    const int lo = key_bits - passes * kRadixBits;
+    return lo > 0 ? lo : 0;
+}
+
 // Per-job kernel arguments from a weight set (everything but the sample range).
 void fill_args(const tm_weights* w, SampleArgs* out, size_t* lds_out) {
     const HostPlan& P = w->plan;
@@ -1195,7 +1206,8 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
                 hipLaunchKernelGGL(root_kernel<u64>, grid, dim3(kBlock), lds, st, a, k0, v0);
             TM_HIP(hipGetLastError());
             uint32_t *ks, *vs;
-            TM_TRY(radix_sort_pairs<uint32_t>(k0, v0, k1, v1, (int64_t)n, 0, key_bits, &ks, &vs, ovf, st));
+            TM_TRY(radix_sort_pairs<uint32_t>(k0, v0, k1, v1, (int64_t)n, root_sort_lo_bit(key_bits), key_bits, &ks,
+                                              &vs, ovf, st));
             a.skey = ks;
             a.sval = vs;
             t_roots.stop();
@@ -1326,7 +1338,7 @@ void group_prepare(tm_weights* const* ws, const std::vector<int>& act, const u64
         G.total += counts[act[y]];
     }
     G.key_bits = std::max(1, bits_of(key_space - 1));
-    G.passes = (G.key_bits + kRadixBits - 1) / kRadixBits;
+    G.passes = (G.key_bits - root_sort_lo_bit(G.key_bits) + kRadixBits - 1) / kRadixBits;
     const int tile = cfg.tile > 0 ? cfg.tile : 8192;
     int cus = 256;
     {
@@ -1444,7 +1456,8 @@ int group_launch(Group& G, hipStream_t st, bool timed) {
     }
     {
         uint32_t *ksr, *vsr;
-        TM_TRY(radix_sort_pairs<uint32_t>(G.k0, G.v0, G.k1, G.v1, (int64_t)G.total, 0, G.key_bits, &ksr, &vsr,
+        TM_TRY(radix_sort_pairs<uint32_t>(G.k0, G.v0, G.k1, G.v1, (int64_t)G.total, root_sort_lo_bit(G.key_bits),
+                                          G.key_bits, &ksr, &vsr,
                                           G.ovf, st));
         if (ksr != G.args[0].skey) return tm_fail(TM_EDEVICE, "batch: unexpected sort buffer");
     }
@@ -1725,7 +1738,9 @@ int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hip
                            v0);
         uint32_t *ks, *order;
         rc = fill_u32(ovf, 1, 0u, st);
-        if (rc == TM_OK) rc = radix_sort_pairs<uint32_t>(k0, v0, k1, v1, (int64_t)cnt, 0, key_bits, &ks, &order, ovf, st);
+        if (rc == TM_OK)
+            rc = radix_sort_pairs<uint32_t>(k0, v0, k1, v1, (int64_t)cnt, root_sort_lo_bit(key_bits), key_bits, &ks,
+                                            &order, ovf, st);
         if (rc != TM_OK) break;
         JobSums t;
         t.n_valid = tree.n_valid;
