@@ -164,20 +164,23 @@ __device__ __forceinline__ Bounds window_bounds(const DevGraph& G, int dir, int3
     return r;
 }
 
-// The multi-edge run El_{x,y} restricted to times [lo, hi]: a contiguous run
-// of x's out-list in (destination, time) order.
-__device__ __forceinline__ void el_run(const DevGraph& G, int32_t x, int32_t y, int64_t lo, int64_t hi,
-                                       int32_t& ra, int32_t& rb, int32_t& la, int32_t& lb) {
-    la = G.off[0][x];
-    lb = G.off[0][x + 1];
+// The multi-edge run El_{x,y} restricted to times [lo, hi].  It is a
+// contiguous run both of x's out-list in (destination, time) order and of y's
+// in-list in (source, time) order; [ra, rb) are its positions in list dir of
+// those two (la, lb: the list searched).
+__device__ __forceinline__ void el_run_dir(const DevGraph& G, int dir, int32_t x, int32_t y, int64_t lo, int64_t hi,
+                                           int32_t la_in, int32_t lb_in, int32_t& ra, int32_t& rb, int32_t& la,
+                                           int32_t& lb) {
+    la = la_in;
+    lb = lb_in;
     if (lo < 0) lo = 0;
     if (hi > G.T) hi = G.T;
     if (lo > hi || la == lb) {
         ra = rb = la;
         return;
     }
-    const u64* nk = G.nkey[0];
-    const u64 base = (u64)y << G.bt;
+    const u64* nk = G.nkey[dir];
+    const u64 base = (u64)(dir ? x : y) << G.bt;
     const u64 klo = base | (u64)lo, khi = base | (u64)hi;
     int32_t b0 = la, b1 = la;
     int32_t n = lb - la;
@@ -190,6 +193,17 @@ __device__ __forceinline__ void el_run(const DevGraph& G, int32_t x, int32_t y, 
     }
     ra = b0 + (nk[b0] < klo ? 1 : 0);
     rb = b1 + (nk[b1] <= khi ? 1 : 0);
+}
+
+// El_{x,y} in the shorter of the two lists that hold it; returns that list's
+// N-order keys (the run's times are their low bits).
+__device__ __forceinline__ const u64* el_run(const DevGraph& G, int32_t x, int32_t y, int64_t lo, int64_t hi,
+                                             int32_t& ra, int32_t& rb, int32_t& la, int32_t& lb) {
+    const int32_t xa = G.off[0][x], xb = G.off[0][x + 1];
+    const int32_t ya = G.off[1][y], yb = G.off[1][y + 1];
+    const int dir = (yb - ya) < (xb - xa) ? 1 : 0;
+    el_run_dir(G, dir, x, y, lo, hi, dir ? ya : xa, dir ? yb : xb, ra, rb, la, lb);
+    return G.nkey[dir];
 }
 
 __device__ __forceinline__ u64 tmask_of(const DevGraph& G) {
@@ -207,20 +221,19 @@ template <bool kCount>
 __device__ __forceinline__ u128 run_count_short(const DevGraph& G, int32_t x0, int32_t y0, int32_t x1,
                                                 int32_t y1, int len, int64_t lo, int64_t hi, u64& nb) {
     int32_t a0, b0, la0, lb0;
-    el_run(G, x0, y0, lo, hi, a0, b0, la0, lb0);
-    if constexpr (kCount) nb += 8 + 2 * probes(lb0 - la0) * 8;
+    const u64* nk0 = el_run(G, x0, y0, lo, hi, a0, b0, la0, lb0);
+    if constexpr (kCount) nb += 16 + 2 * probes(lb0 - la0) * 8;
     if (len == 1) return (u128)(b0 - a0);
     int32_t a1, b1, la1, lb1;
-    el_run(G, x1, y1, lo, hi, a1, b1, la1, lb1);
-    if constexpr (kCount) nb += 8 + 2 * probes(lb1 - la1) * 8 + (u64)(b0 - a0 + b1 - a1) * 8;
+    const u64* nk1 = el_run(G, x1, y1, lo, hi, a1, b1, la1, lb1);
+    if constexpr (kCount) nb += 16 + 2 * probes(lb1 - la1) * 8 + (u64)(b0 - a0 + b1 - a1) * 8;
     // pairs (e, f), e in the first list, f in the second, t(e) < t(f)
-    const u64* nk = G.nkey[0];
     const u64 m = tmask_of(G);
     u128 total = 0;
     int32_t p = a0;
     for (int32_t f = a1; f < b1; ++f) {
-        const u64 tf = nk[f] & m;
-        while (p < b0 && (nk[p] & m) < tf) ++p;
+        const u64 tf = nk1[f] & m;
+        while (p < b0 && (nk0[p] & m) < tf) ++p;
         total += (u128)(p - a0);
     }
     return total;
@@ -237,13 +250,13 @@ __device__ u128 chain_count_general(const DevGraph& G, const V8& img, const int*
                                     int first, int len, int64_t lo, int64_t hi, bool* ovf, u64& nb) {
     if (len == 0) return 1;
     int32_t ra[TM_MAX_L], rb[TM_MAX_L];
+    const u64* nks[TM_MAX_L];
     for (int j = 0; j < len; ++j) {
         int32_t la, lb;
-        el_run(G, img.v[fs[first + j]], img.v[fd[first + j]], lo, hi, ra[j], rb[j], la, lb);
-        if constexpr (kCount) nb += 8 + 2 * probes(lb - la) * 8 + (u64)(rb[j] - ra[j]) * 8;
+        nks[j] = el_run(G, img.v[fs[first + j]], img.v[fd[first + j]], lo, hi, ra[j], rb[j], la, lb);
+        if constexpr (kCount) nb += 16 + 2 * probes(lb - la) * 8 + (u64)(rb[j] - ra[j]) * 8;
     }
     if (len == 1) return (u128)(rb[0] - ra[0]);
-    const u64* nk = G.nkey[0];
     const u64 m = tmask_of(G);
     u128 S[TM_MAX_L];
     for (int j = 0; j < len; ++j) S[j] = 0;
@@ -252,7 +265,7 @@ __device__ u128 chain_count_general(const DevGraph& G, const V8& img, const int*
         u64 tb = 0;
         for (int j = len - 1; j >= 0; --j) {
             if (ra[j] < rb[j]) {
-                const u64 tj = nk[ra[j]] & m;
+                const u64 tj = nks[j][ra[j]] & m;
                 if (best < 0 || tj < tb) {
                     tb = tj;
                     best = j;
@@ -296,12 +309,13 @@ __device__ __noinline__ u128 complete_general(const SampleArgs& a, const V8& img
         // the trailing chain
         int32_t fa, fb, la, lb;
         const int f0 = a.run_first[lead];
-        el_run(G, img.v[a.free_src[f0]], img.v[a.free_dst[f0]], tlast - a.delta, tfirst - 1, fa, fb, la, lb);
-        if constexpr (kCount) nb += 8 + 2 * probes(lb - la) * 8 + (u64)(fb - fa) * 8;
+        const u64* nkf =
+            el_run(G, img.v[a.free_src[f0]], img.v[a.free_dst[f0]], tlast - a.delta, tfirst - 1, fa, fb, la, lb);
+        if constexpr (kCount) nb += 16 + 2 * probes(lb - la) * 8 + (u64)(fb - fa) * 8;
         const u64 m = tmask_of(G);
         u128 sum = 0;
         for (int32_t x = fa; x < fb; ++x) {
-            const int64_t tf = (int64_t)(G.nkey[0][x] & m);
+            const int64_t tf = (int64_t)(nkf[x] & m);
             const u128 lc = chain_count_general<kCount>(G, img, a.free_src, a.free_dst, f0 + 1,
                                                         a.run_len[lead] - 1, tf + 1, tfirst - 1, ovf, nb);
             if (lc == 0) continue;
@@ -1088,9 +1102,10 @@ list_kernel(SampleArgs a, ListArgs la, const tm_sample_rec* recs, u64 count, int
                 end[p] = 1;
             } else {
                 const int f = -1 - la.kind[p];
+                const int32_t x = img[a.free_src[f]], y = img[a.free_dst[f]];
                 int32_t lo, hi;
-                el_run(G, img[a.free_src[f]], img[a.free_dst[f]], tmax - a.delta, tmin + a.delta, beg[p], end[p], lo,
-                       hi);
+                el_run_dir(G, 0, x, y, tmax - a.delta, tmin + a.delta, G.off[0][x], G.off[0][x + 1], beg[p], end[p],
+                           lo, hi);
             }
         }
         u128 rank = scale(draw_block(a.seed, a.j0 + r, kListDraw), m);
