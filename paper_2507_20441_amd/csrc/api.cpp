@@ -196,6 +196,9 @@ int plan_build(const tm_motif* mo, const tm_tree* tr, HostPlan* P) {
     for (int s = 0; s < H.nt; ++s)
         H.same_window[s] = s > 1 && H.parent[s] == H.parent[s - 1] && H.side[s] == H.side[s - 1] &&
                            H.alpha[s] == H.alpha[s - 1] && H.beta[s] == H.beta[s - 1];
+    H.root_dir = H.n_children[0] > 0 ? 1 : 0;
+    for (int j = 0; j < H.n_children[0]; ++j)
+        if (H.side[H.children[0][j]] == 0) H.root_dir = 0;
     int r = 0;
     for (int p = 0; p < mo->l; ++p)
         if (H.slot_of_edge[p] >= 0) H.by_pi[r++] = H.slot_of_edge[p];

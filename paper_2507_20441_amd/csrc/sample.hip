@@ -46,6 +46,7 @@ struct SampleArgs {
     // kept child windows (see weights): by the parent's list position, per parity
     const int4* win[kMaxSlots][2];
     int has_win;
+    int root_dir;  // the list whose T positions key the root (0: out-lists, 1: in-lists)
     const void* qc[2];
     const int32_t* ilo;
     const int32_t* ihi;
@@ -431,13 +432,15 @@ __device__ __forceinline__ uint32_t root_key(const SampleArgs& a, const W* cum, 
         bad = true;
         return 0u;
     }
-    return key != ~0u ? key : (uint32_t)a.G.tpos[0][e0] * 2u + (uint32_t)(i & 1);
+    return key != ~0u ? key : (uint32_t)a.G.tpos[a.root_dir][e0] * 2u + (uint32_t)(i & 1);
 }
 
 // Draw 0 of each sample (interval, then center edge), written as a sort key:
-// the root's position in the out-list T order (grouping samples by source
-// vertex and time) and the interval's parity.  The sort that follows changes
-// only the order in which samples are processed.
+// the root's position in the T order of the root list (out-lists, or
+// in-lists when every child of the center attaches at its destination:
+// grouping samples by the vertex their first children share, then time) and
+// the interval's parity.  The sort that follows changes only the order in
+// which samples are processed.
 template <typename W>
 __global__ void __launch_bounds__(kBlock) root_kernel(SampleArgs a, uint32_t* keys, uint32_t* vals) {
     extern __shared__ unsigned char lds_raw[];
@@ -534,10 +537,13 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
             r = a.sval[x];
             const int32_t pos = (int32_t)(key >> 1);
             if constexpr (kWin) posv[0] = pos;
-            e0 = G.leid[0][pos];
-            te[0] = G.lt[0][pos];
-            v0 = G.lnbr[0][pos];
-            u0 = G.src[e0];
+            const int rd = a.root_dir;
+            e0 = G.leid[rd][pos];
+            te[0] = G.lt[rd][pos];
+            const int32_t nbr0 = G.lnbr[rd][pos];
+            const int32_t own0 = rd ? G.dst[e0] : G.src[e0];
+            u0 = rd ? nbr0 : own0;
+            v0 = rd ? own0 : nbr0;
             const int64_t blk = te[0] / a.ilen;
             i = (int32_t)(((blk & 1) == (int64_t)(key & 1)) ? blk : blk - 1);
             if constexpr (kCount) nb += 8 + 20;
@@ -873,6 +879,7 @@ void fill_args(const tm_weights* w, SampleArgs* out, size_t* lds_out) {
         }
     }
     a.has_win = w->has_win ? 1 : 0;
+    a.root_dir = P.root_dir;
     a.qc[0] = w->qc[0];
     a.qc[1] = w->qc[1];
     a.ilo = w->ilo;

@@ -90,8 +90,9 @@ struct X128 {
 };
 
 // Root guide entry: the root pair (interval << 32 | eid) of one evenly spaced
-// draw, and that pair's sort key (T-order position of the edge * 2 + interval
-// parity).  A bucket whose two ends hold the same pair holds only that pair.
+// draw, and that pair's sort key (T-order position of the edge in the root
+// list * 2 + interval parity).  A bucket whose two ends hold the same pair
+// holds only that pair.
 struct alignas(16) RootGuide {
     u64 pair;
     u64 key;

@@ -96,6 +96,9 @@ struct HostPlan {
     int children[kMaxSlots][kMaxSlots];
     int n_children[kMaxSlots];
     int by_pi[kMaxSlots];          // slots in increasing pi index
+    int root_dir;                  // the list whose T positions key the root: 1 (in-lists)
+                                   // when every child of the center attaches at its
+                                   // destination, else 0 (out-lists)
     int same_window[kMaxSlots];    // 1: same parent, side, direction and time side as
                                    // the previous slot (a leaf sibling): same window
     // non-tree edges in pi order, and maximal runs of consecutive ones
@@ -131,8 +134,8 @@ struct tm_weights {
     void* vals[kMaxSlots][2] = {};  // build temporaries, null afterwards
     // child windows, per non-center slot and interval parity: the slot's
     // candidate window (p0, p1, q0, q1) for every edge its parent can match,
-    // by that edge's position in the list the parent is drawn from (the
-    // out-list T order for the center); null when not kept
+    // by that edge's position in the list the parent is drawn from (the root
+    // list's T order for the center, see HostPlan::root_dir); null when not kept
     int4* win[kMaxSlots][2] = {};
     bool has_win = false;
     void* qt[kMaxSlots][2] = {};

@@ -45,8 +45,8 @@ struct LevelArgs {
     int walk;          // -1: eid order; 0 / 1: the T order of the out- / in-lists
     int4* win[kMaxSlots][2];  // per child and parity: its windows (null: not kept)
     int win_dir;       // the list whose T positions index the windows
-    void* out[2];      // per parity: indexed by eid, or by in-list T position (out_by_pos)
-    int out_by_pos;    // first of two passes: write where the second pass walks
+    void* out[2];      // per parity: indexed by eid, or by T position in list out_pos_dir
+    int out_pos_dir;   // first of two passes: the list the second pass walks (else -1)
     const void* in[2]; // second of two passes: the first pass's products, by walk position
     int* ovf;
 };
@@ -202,7 +202,7 @@ __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
             if (!mul_ok(prodB, xb, &prodB)) ovf = true;
         }
     });
-    const int64_t at = a.out_by_pos ? (int64_t)G.tpos[1][e] : (int64_t)e;
+    const int64_t at = a.out_pos_dir >= 0 ? (int64_t)G.tpos[a.out_pos_dir][e] : (int64_t)e;
     static_cast<W*>(a.out[parA])[at] = prodA;
     static_cast<W*>(a.out[parB])[at] = hasB ? prodB : (W)0;
     if (ovf) atomicOr(a.ovf, 4);
@@ -367,14 +367,20 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
                             }
                         }
                     }
-                    a.win_dir = s == 0 ? 0 : (P.alpha[s] > 0 ? 0 : 1);
+                    a.win_dir = s == 0 ? P.root_dir : (P.alpha[s] > 0 ? 0 : 1);
                 }
-                a.walk = a.nc == 0 ? -1 : side;
+                // the center walks the list its children attach to (the
+                // root's list too when they all attach at one end), so
+                // neighbouring lanes search one list; other slots with kept
+                // windows walk the list whose positions index those windows,
+                // so that their writes go to consecutive addresses
+                const bool by_win = w->has_win && s != 0;
+                a.walk = a.nc == 0 ? -1 : (by_win ? a.win_dir : side);
                 for (int par = 0; par < 2; ++par) {
                     a.out[par] = (two && pass == 0) ? (void*)tmp[par] : w->vals[s][par];
                     a.in[par] = (two && pass == 1) ? (const void*)tmp[par] : nullptr;
                 }
-                a.out_by_pos = two && pass == 0;
+                a.out_pos_dir = (two && pass == 0) ? (by_win ? a.win_dir : 1) : -1;
                 a.ovf = ovf;
                 hipLaunchKernelGGL((level_kernel<W>), dim3(grid_for(m)), dim3(kBlock), 0, st, a);
                 TM_HIP(hipGetLastError());
@@ -439,7 +445,7 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
     const int64_t nb = ((int64_t)1 << w->guide_bits) + 1;
     TM_TRY(arena_alloc(w->arena, &w->guide, (size_t)nb));
     hipLaunchKernelGGL((guide_kernel<W>), dim3(grid_for(nb)), dim3(kBlock), 0, st, (const W*)cum, w->qc[0],
-                       w->qc[1], w->ilo, w->ihi, w->q, w->g->d.tpos[0], w->guide_bits, w->guide);
+                       w->qc[1], w->ilo, w->ihi, w->q, w->g->d.tpos[P.root_dir], w->guide_bits, w->guide);
     TM_HIP(hipGetLastError());
     return TM_OK;
 }
@@ -487,7 +493,11 @@ int weights_build(tm_weights* w, hipStream_t st) {
         clear_tables(w);
         TM_TRY(fill_u32(ovf, 1, 0u, st));
         w->wide = wide != 0;
-        rc = wide ? build_typed<u128>(w, st, ovf) : build_typed<u64>(w, st, ovf, true);
+        // on large graphs a level costs far more than a host round trip:
+        // there the 64-bit build checks after every level and stops at the
+        // first overflow; small graphs check once, at the end
+        const bool per_level = g->m >= ((int64_t)1 << 23);
+        rc = wide ? build_typed<u128>(w, st, ovf) : build_typed<u64>(w, st, ovf, per_level);
         if (rc != TM_OK) break;
         u64 hW[2] = {0, 0};
         TM_HIP(hipMemcpyAsync(&h, ovf, sizeof(int), hipMemcpyDeviceToHost, st));
