@@ -16,9 +16,10 @@ enum : int { kBadRange = 1, kSelfLoop = 2, kDup = 4 };
 
 __device__ __forceinline__ u64 order_key(int64_t t) { return (u64)t ^ 0x8000000000000000ull; }
 
+// Per workgroup: flags and the time range of its edges, as one partial each
+// (part[3 b] = min, part[3 b + 1] = max, part[3 b + 2] = flags).
 __global__ void __launch_bounds__(kBlock)
-validate_kernel(const int32_t* src, const int32_t* dst, const int64_t* t, int64_t m, int32_t n,
-                int* flags, u64* tmin, u64* tmax) {
+validate_kernel(const int32_t* src, const int32_t* dst, const int64_t* t, int64_t m, int32_t n, u64* part) {
     u64 lo = ~0ull, hi = 0;
     int f = 0;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
@@ -36,7 +37,7 @@ validate_kernel(const int32_t* src, const int32_t* dst, const int64_t* t, int64_
         hi = b > hi ? b : hi;
         f |= __shfl_xor(f, d, 64);
     }
-    // one atomic per block: the waves meet in LDS first
+    // one partial per block: the waves meet in LDS first
     __shared__ u64 slo[kWaves], shi[kWaves];
     __shared__ int sf[kWaves];
     const int wave = threadIdx.x >> 6;
@@ -52,9 +53,46 @@ validate_kernel(const int32_t* src, const int32_t* dst, const int64_t* t, int64_
             hi = shi[w] > hi ? shi[w] : hi;
             f |= sf[w];
         }
-        atomicMin(tmin, lo);
-        atomicMax(tmax, hi);
-        if (f) atomicOr(flags, f);
+        part[3 * blockIdx.x] = lo;
+        part[3 * blockIdx.x + 1] = hi;
+        part[3 * blockIdx.x + 2] = (u64)(uint32_t)f;
+    }
+}
+
+// One workgroup: the partials of nb workgroups into *flags, *tmin, *tmax.
+__global__ void __launch_bounds__(kBlock)
+validate_reduce_kernel(const u64* part, int nb, int* flags, u64* tmin, u64* tmax) {
+    u64 lo = ~0ull, hi = 0;
+    uint32_t f = 0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+        lo = part[3 * b] < lo ? part[3 * b] : lo;
+        hi = part[3 * b + 1] > hi ? part[3 * b + 1] : hi;
+        f |= (uint32_t)part[3 * b + 2];
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        const u64 a = __shfl_xor(lo, d, 64), c = __shfl_xor(hi, d, 64);
+        lo = a < lo ? a : lo;
+        hi = c > hi ? c : hi;
+        f |= (uint32_t)__shfl_xor((int)f, d, 64);
+    }
+    __shared__ u64 slo[kWaves], shi[kWaves];
+    __shared__ uint32_t sf[kWaves];
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        slo[wave] = lo;
+        shi[wave] = hi;
+        sf[wave] = f;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kWaves; ++w) {
+            lo = slo[w] < lo ? slo[w] : lo;
+            hi = shi[w] > hi ? shi[w] : hi;
+            f |= sf[w];
+        }
+        *tmin = lo;
+        *tmax = hi;
+        *flags = (int)f;
     }
 }
 
@@ -233,14 +271,17 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
     u64* tbounds = nullptr;
     TM_HIP(dev_alloc((void**)&flags, sizeof(int) * 2, st));
     TM_HIP(dev_alloc((void**)&tbounds, sizeof(u64) * 2, st));
-    const u64 init[2] = {~0ull, 0ull};
     TM_HIP(hipMemsetAsync(flags, 0, sizeof(int) * 2, st));
-    TM_HIP(hipMemcpyAsync(tbounds, init, sizeof init, hipMemcpyHostToDevice, st));
     {
         const unsigned blocks = (unsigned)std::min<int64_t>(grid_for(m), 1024);
-        hipLaunchKernelGGL(validate_kernel, dim3(blocks), dim3(kBlock), 0, st, src, dst, t, m, n,
+        u64* part = nullptr;
+        TM_HIP(dev_alloc((void**)&part, (size_t)blocks * 3 * sizeof(u64), st));
+        hipLaunchKernelGGL(validate_kernel, dim3(blocks), dim3(kBlock), 0, st, src, dst, t, m, n, part);
+        TM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(validate_reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const u64*)part, (int)blocks,
                            flags, tbounds, tbounds + 1);
         TM_HIP(hipGetLastError());
+        TM_HIP(dev_free(part, st));
     }
     int hflags[2];
     u64 hb[2];
