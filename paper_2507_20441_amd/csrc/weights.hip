@@ -46,8 +46,9 @@ struct LevelArgs {
     int4* win[kMaxSlots][2];  // per child and parity: its windows (null: not kept)
     int win_dir;       // the list whose T positions index the windows
     void* out[2];      // per parity: indexed by eid, or by T position in list out_pos_dir
-    int out_pos_dir;   // first of two passes: the list the second pass walks (else -1)
-    const void* in[2]; // second of two passes: the first pass's products, by walk position
+    int out_pos_dir;   // first of two passes: its own walk (consecutive writes), else -1
+    const void* in[2]; // second of two passes: the first pass's products ...
+    int in_pos_dir;    // ... by T position in this list
     int* ovf;
 };
 
@@ -146,8 +147,9 @@ __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
     const int parA = (int)(blk & 1), parB = parA ^ 1;
     W prodA = 1, prodB = hasB ? (W)1 : (W)0;
     if (a.in[0]) {
-        prodA = static_cast<const W*>(a.in[parA])[p];
-        prodB = hasB ? static_cast<const W*>(a.in[parB])[p] : (W)0;
+        const int64_t ip = a.in_pos_dir == a.walk ? p : (int64_t)G.tpos[a.in_pos_dir][e];
+        prodA = static_cast<const W*>(a.in[parA])[ip];
+        prodB = hasB ? static_cast<const W*>(a.in[parB])[ip] : (W)0;
     }
     bool ovf = false;
     sfor<0, kMaxSlots>([&](auto cc) {
@@ -177,7 +179,7 @@ __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
             const Bounds3 r = three_bounds(G, d.dir, g, o, xs, a.exclude != 0);
             if (a.win[c][0]) {
                 // the windows of intervals blk (parity A) and blk - 1 (B)
-                const int64_t at = G.tpos[a.win_dir][e];
+                const int64_t at = a.win_dir == a.walk ? p : (int64_t)G.tpos[a.win_dir][e];
                 int4 wa, wb;
                 if (d.beta < 0) {
                     wa = make_int4(r.p[0], r.p[2], r.q[0], r.q[2]);
@@ -202,7 +204,7 @@ __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
             if (!mul_ok(prodB, xb, &prodB)) ovf = true;
         }
     });
-    const int64_t at = a.out_pos_dir >= 0 ? (int64_t)G.tpos[a.out_pos_dir][e] : (int64_t)e;
+    const int64_t at = a.out_pos_dir < 0 ? (int64_t)e : (a.out_pos_dir == a.walk ? p : (int64_t)G.tpos[a.out_pos_dir][e]);
     static_cast<W*>(a.out[parA])[at] = prodA;
     static_cast<W*>(a.out[parB])[at] = hasB ? prodB : (W)0;
     if (ovf) atomicOr(a.ovf, 4);
@@ -317,6 +319,7 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
             if (two)
                 for (int par = 0; par < 2; ++par)
                     TM_HIP(dev_alloc((void**)&tmp[par], ((size_t)m * sizeof(W) + 255) & ~(size_t)255, st));
+            int prev_walk = -1;
             for (int pass = 0; pass < (two ? 2 : 1); ++pass) {
                 const int side = two ? pass : (grp[0].empty() ? 1 : 0);
                 const std::vector<int>& cs = grp[side];
@@ -380,7 +383,11 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
                     a.out[par] = (two && pass == 0) ? (void*)tmp[par] : w->vals[s][par];
                     a.in[par] = (two && pass == 1) ? (const void*)tmp[par] : nullptr;
                 }
-                a.out_pos_dir = (two && pass == 0) ? (by_win ? a.win_dir : 1) : -1;
+                // the first of two passes leaves its products in its own walk
+                // order; the second gathers them
+                a.out_pos_dir = (two && pass == 0) ? a.walk : -1;
+                a.in_pos_dir = prev_walk;
+                prev_walk = a.walk;
                 a.ovf = ovf;
                 hipLaunchKernelGGL((level_kernel<W>), dim3(grid_for(m)), dim3(kBlock), 0, st, a);
                 TM_HIP(hipGetLastError());
