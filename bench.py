@@ -777,7 +777,7 @@ def weights_only(args):
 
 
 TRAFFIC_KERNELS = {
-    "sample_kernel": "sample_kernel<unsigned long long, false, false, true>",
+    "sample_kernel": "sample_kernel<unsigned long long, false, false, true, true>",
     "root_kernel": "root_kernel<unsigned long long>",
     "level_kernel": "level_kernel<unsigned long long>",
 }
