@@ -138,6 +138,7 @@ struct tm_weights {
     // list's T order for the center, see HostPlan::root_dir); null when not kept
     int4* win[kMaxSlots][2] = {};
     bool has_win = false;
+    bool allow_windows = true;  // the server builds without them (memory over speed)
     void* qt[kMaxSlots][2] = {};
     void* qn[kMaxSlots][2] = {};
     void* qc[2] = {};
@@ -170,7 +171,7 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
 // graph of m edges and q intervals, in 64-bit (wide = false) or 128-bit form,
 // and the temporaries a build holds on top of them at its peak (one slot's
 // values, per parity).
-u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide);
+u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide, bool windows = true);
 // Whether a weight set keeps its child windows: at most kWinMaxBytes of them.
 constexpr u64 kWinMaxBytes = (u64)8 << 30;
 u64 weights_window_bytes(const HostPlan& P, int64_t m);

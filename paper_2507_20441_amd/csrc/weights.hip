@@ -297,7 +297,7 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
     const HostPlan& P = w->plan;
     const int64_t m = g->m;
     const int64_t delta = P.mo.delta;
-    w->has_win = weights_keep_windows(P, m);
+    w->has_win = w->allow_windows && weights_keep_windows(P, m);
     // bottom-up over heights; leaves other than the center have weight 1 and
     // no table (a lone center edge gets a table of ones)
     for (int h = 0; h <= P.H; ++h) {
@@ -525,7 +525,7 @@ int weights_build(tm_weights* w, hipStream_t st) {
     return rc;
 }
 
-u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide) {
+u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide, bool windows) {
     if (m <= 0) return 0;
     const u64 wsz = wide ? 16 : 8;
     auto blk = [](u64 bytes) { return ((bytes ? bytes : 16) + 255) & ~(u64)255; };
@@ -536,7 +536,7 @@ u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide) {
     b += 2 * blk((u64)q * 4) + blk((u64)(q + 1) * wsz); // ilo, ihi, cumW
     b += blk((u64)q * wsz);                              // ioff
     b += blk((((u64)1 << guide_bits_for(m)) + 1) * sizeof(RootGuide));  // root guide
-    if (weights_keep_windows(P, m)) b += weights_window_bytes(P, m);
+    if (windows && weights_keep_windows(P, m)) b += weights_window_bytes(P, m);
     return b;
 }
 
