@@ -929,8 +929,9 @@ struct Tile {
 
 template <typename W>
 __global__ void __launch_bounds__(kBlock)
-batch_root_kernel(const SampleArgs* jobs, const Tile* tiles, int n_tiles, int* counter, uint32_t* keys,
-                  uint32_t* vals, int* ovf) {
+batch_root_kernel(const SampleArgs* __restrict__ jobs, const Tile* __restrict__ tiles, int n_tiles,
+                  int* __restrict__ counter, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                  int* __restrict__ ovf) {
     extern __shared__ unsigned char lds_raw[];
     __shared__ int s_tile;
     bool bad = false;
@@ -938,7 +939,7 @@ batch_root_kernel(const SampleArgs* jobs, const Tile* tiles, int n_tiles, int* c
         __syncthreads();
         if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
         __syncthreads();
-        const int t = s_tile;
+        const int t = __builtin_amdgcn_readfirstlane(s_tile);  // uniform: job fields load as scalars
         if (t >= n_tiles) break;
         const Tile T = tiles[t];
         const SampleArgs& a = jobs[T.job];
@@ -967,29 +968,46 @@ batch_root_kernel(const SampleArgs* jobs, const Tile* tiles, int n_tiles, int* c
     if (bad) atomicOr(ovf, 2);
 }
 
-template <typename W, bool kGeneral>
+// kWinMode: 0 no job kept its child windows, 1 every job did, 2 some did
+// (each path is compiled only where it can run: registers set occupancy).
+template <typename W, bool kGeneral, int kWinMode>
 __global__ void __launch_bounds__(kBlock)
-batch_sample_kernel(const SampleArgs* jobs, const Tile* tiles, int n_tiles, int* counter,
-                    Partial* tile_parts, int* ovf) {
+batch_sample_kernel(const SampleArgs* __restrict__ jobs, const Tile* __restrict__ tiles, int n_tiles,
+                    int* __restrict__ counter, Partial* __restrict__ tile_parts, int* __restrict__ ovf) {
     __shared__ int s_tile;
     while (true) {
         __syncthreads();
         if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
         __syncthreads();
-        const int t = s_tile;
+        const int t = __builtin_amdgcn_readfirstlane(s_tile);  // uniform: job fields load as scalars
         if (t >= n_tiles) break;
         const Tile T = tiles[t];
         const SampleArgs& a = jobs[T.job];
         LaneAcc L = lane_zero();
         const bool skip = (a.wflag && *a.wflag != 0) || (a.Wdev && *static_cast<const W*>(a.Wdev) == 0);
         if (!skip) {
-            if (a.has_win)
-                sample_positions<W, false, kGeneral, true, true>(a, nullptr, T.begin + threadIdx.x, T.end, kBlock, L);
+            if (kWinMode == 1 || (kWinMode == 2 && a.has_win))
+                sample_positions<W, false, kGeneral, true, kWinMode != 0>(a, nullptr, T.begin + threadIdx.x, T.end,
+                                                                          kBlock, L);
             else
                 sample_positions<W, false, kGeneral, true, false>(a, nullptr, T.begin + threadIdx.x, T.end, kBlock, L);
         }
         lanes_reduce(L, &tile_parts[t], ovf);
     }
+}
+
+template <typename W, bool kGeneral>
+void launch_batch_sample(int mode, dim3 grid, hipStream_t st, const SampleArgs* jobs, const Tile* tiles, int n_tiles,
+                         int* counter, Partial* tile_parts, int* ovf) {
+    if (mode == 0)
+        hipLaunchKernelGGL((batch_sample_kernel<W, kGeneral, 0>), grid, dim3(kBlock), 0, st, jobs, tiles, n_tiles,
+                           counter, tile_parts, ovf);
+    else if (mode == 1)
+        hipLaunchKernelGGL((batch_sample_kernel<W, kGeneral, 1>), grid, dim3(kBlock), 0, st, jobs, tiles, n_tiles,
+                           counter, tile_parts, ovf);
+    else
+        hipLaunchKernelGGL((batch_sample_kernel<W, kGeneral, 2>), grid, dim3(kBlock), 0, st, jobs, tiles, n_tiles,
+                           counter, tile_parts, ovf);
 }
 
 // One block per job: the sum of the job's tile partials.
@@ -1337,6 +1355,7 @@ struct Group {
     std::vector<SampleArgs> args;
     std::vector<Tile> rt, stt;
     std::vector<int> g_rt_first, g_st_first, jfirst, jcount;
+    int g_win[4] = {0, 0, 0, 0};  // per kernel group: the batch_sample_kernel window mode
     SampleArgs* djobs = nullptr;
     Tile *drt = nullptr, *dst = nullptr;
     uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
@@ -1393,10 +1412,12 @@ void group_prepare(tm_weights* const* ws, const std::vector<int>& act, const u64
     for (int grp = 0; grp < 4; ++grp) {
         G.g_rt_first[grp] = (int)G.rt.size();
         G.g_st_first[grp] = (int)G.stt.size();
+        int with = 0, without = 0;
         for (int y = 0; y < na; ++y) {
             const tm_weights* w = ws[act[y]];
             const int gy = (w->wide ? 2 : 0) + (G.args[y].general_runs ? 1 : 0);
             if (gy != grp) continue;
+            if (G.args[y].has_win) ++with; else ++without;
             G.jfirst[y] = (int)G.stt.size();
             const u64 cy = counts[act[y]];
             for (u64 b = 0; b < cy; b += (u64)tile) {
@@ -1406,6 +1427,7 @@ void group_prepare(tm_weights* const* ws, const std::vector<int>& act, const u64
             }
             G.jcount[y] = (int)G.stt.size() - G.jfirst[y];
         }
+        G.g_win[grp] = with == 0 ? 0 : (without == 0 ? 1 : 2);
     }
     G.g_rt_first[4] = (int)G.rt.size();
     G.g_st_first[4] = (int)G.stt.size();
@@ -1492,11 +1514,12 @@ int group_launch(Group& G, hipStream_t st, bool timed) {
         const Tile* tl = G.dst + G.g_st_first[grp];
         Partial* tp = G.tparts + G.g_st_first[grp];
         int* c = G.ctr + 4 + grp;
+        const int wm = G.g_win[grp];
         switch (grp) {
-            case 0: hipLaunchKernelGGL((batch_sample_kernel<u64, false>), grid, dim3(kBlock), 0, st, G.djobs, tl, nt, c, tp, G.ovf); break;
-            case 1: hipLaunchKernelGGL((batch_sample_kernel<u64, true>), grid, dim3(kBlock), 0, st, G.djobs, tl, nt, c, tp, G.ovf); break;
-            case 2: hipLaunchKernelGGL((batch_sample_kernel<u128, false>), grid, dim3(kBlock), 0, st, G.djobs, tl, nt, c, tp, G.ovf); break;
-            default: hipLaunchKernelGGL((batch_sample_kernel<u128, true>), grid, dim3(kBlock), 0, st, G.djobs, tl, nt, c, tp, G.ovf); break;
+            case 0: launch_batch_sample<u64, false>(wm, grid, st, G.djobs, tl, nt, c, tp, G.ovf); break;
+            case 1: launch_batch_sample<u64, true>(wm, grid, st, G.djobs, tl, nt, c, tp, G.ovf); break;
+            case 2: launch_batch_sample<u128, false>(wm, grid, st, G.djobs, tl, nt, c, tp, G.ovf); break;
+            default: launch_batch_sample<u128, true>(wm, grid, st, G.djobs, tl, nt, c, tp, G.ovf); break;
         }
         TM_HIP(hipGetLastError());
     }

@@ -234,7 +234,7 @@ void tm_server::run_builder() {
             w->arena.stream = bst;
             w->plan = qp->plan;
             // resident sets matter more here than the sampler's speed-up
-            w->allow_windows = false;
+            w->lean = true;
             rc = weights_build(w, bst);
             if (rc == TM_ENOMEM) {
                 // the device holds more than the budget counts (cached
@@ -462,7 +462,7 @@ extern "C" int tm_server_submit(tm_server* srv, int32_t gid, const tm_motif* mo,
     if (g->m > 0 && g->T / mo->delta + 1 >= ((int64_t)1 << 31))
         return tm_fail(TM_ERANGE, "server_submit: too many intervals");
     const int64_t nq = g->m > 0 ? g->T / mo->delta + 1 : 0;
-    q->est_bytes = weights_footprint(q->plan, g->m, nq, false, false);
+    q->est_bytes = weights_footprint(q->plan, g->m, nq, false, true);
     q->extra_bytes = weights_build_extra(g->m, false);
     if (q->est_bytes + q->extra_bytes > srv->budget - srv->reserve)
         return tm_fail(TM_EADMIT, "server_submit: weight set of %llu bytes (+%llu while built), budget %llu",

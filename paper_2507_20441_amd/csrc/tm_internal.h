@@ -138,7 +138,9 @@ struct tm_weights {
     // list's T order for the center, see HostPlan::root_dir); null when not kept
     int4* win[kMaxSlots][2] = {};
     bool has_win = false;
-    bool allow_windows = true;  // the server builds without them (memory over speed)
+    // a server builds its sets for memory over speed: no kept windows and a
+    // guide four times coarser
+    bool lean = false;
     void* qt[kMaxSlots][2] = {};
     void* qn[kMaxSlots][2] = {};
     void* qc[2] = {};
@@ -171,15 +173,15 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
 // graph of m edges and q intervals, in 64-bit (wide = false) or 128-bit form,
 // and the temporaries a build holds on top of them at its peak (one slot's
 // values, per parity).
-u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide, bool windows = true);
+u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide, bool lean = false);
 // Whether a weight set keeps its child windows: at most kWinMaxBytes of them.
 constexpr u64 kWinMaxBytes = (u64)8 << 30;
 u64 weights_window_bytes(const HostPlan& P, int64_t m);
 bool weights_keep_windows(const HostPlan& P, int64_t m);
 u64 weights_build_extra(int64_t m, bool wide);
 // Bits of the root guide for a graph of m edges: about two (interval, edge)
-// pairs per bucket, between 2^8 and 2^24 buckets.
-int guide_bits_for(int64_t m);
+// pairs per bucket (eight when lean), between 2^8 and 2^23 buckets.
+int guide_bits_for(int64_t m, bool lean = false);
 
 // Exact sums over a range of samples of one job.  Sums over disjoint ranges
 // add up to the sums over their union, whatever the split.

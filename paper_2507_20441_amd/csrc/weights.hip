@@ -297,7 +297,7 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
     const HostPlan& P = w->plan;
     const int64_t m = g->m;
     const int64_t delta = P.mo.delta;
-    w->has_win = w->allow_windows && weights_keep_windows(P, m);
+    w->has_win = !w->lean && weights_keep_windows(P, m);
     // bottom-up over heights; leaves other than the center have weight 1 and
     // no table (a lone center edge gets a table of ones)
     for (int h = 0; h <= P.H; ++h) {
@@ -448,7 +448,7 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
                        (const W*)w->qc[0], (const W*)w->qc[1], (const int32_t*)w->ilo, w->q, ioff);
     TM_HIP(hipGetLastError());
     w->ioff = ioff;
-    w->guide_bits = guide_bits_for(m);
+    w->guide_bits = guide_bits_for(m, w->lean);
     const int64_t nb = ((int64_t)1 << w->guide_bits) + 1;
     TM_TRY(arena_alloc(w->arena, &w->guide, (size_t)nb));
     hipLaunchKernelGGL((guide_kernel<W>), dim3(grid_for(nb)), dim3(kBlock), 0, st, (const W*)cum, w->qc[0],
@@ -500,10 +500,11 @@ int weights_build(tm_weights* w, hipStream_t st) {
         clear_tables(w);
         TM_TRY(fill_u32(ovf, 1, 0u, st));
         w->wide = wide != 0;
-        // on large graphs a level costs far more than a host round trip:
-        // there the 64-bit build checks after every level and stops at the
-        // first overflow; small graphs check once, at the end
-        const bool per_level = g->m >= ((int64_t)1 << 23);
+        // on large graphs a level costs far more than a host round trip, and
+        // a server's builder thread waits alone: there the 64-bit build
+        // checks after every level and stops at the first overflow; other
+        // builds of small graphs check once, at the end
+        const bool per_level = w->lean || g->m >= ((int64_t)1 << 23);
         rc = wide ? build_typed<u128>(w, st, ovf) : build_typed<u64>(w, st, ovf, per_level);
         if (rc != TM_OK) break;
         u64 hW[2] = {0, 0};
@@ -525,7 +526,7 @@ int weights_build(tm_weights* w, hipStream_t st) {
     return rc;
 }
 
-u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide, bool windows) {
+u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide, bool lean) {
     if (m <= 0) return 0;
     const u64 wsz = wide ? 16 : 8;
     auto blk = [](u64 bytes) { return ((bytes ? bytes : 16) + 255) & ~(u64)255; };
@@ -535,8 +536,8 @@ u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide, bool w
     b += 2 * blk((u64)(m + 1) * wsz);                   // qc, per parity
     b += 2 * blk((u64)q * 4) + blk((u64)(q + 1) * wsz); // ilo, ihi, cumW
     b += blk((u64)q * wsz);                              // ioff
-    b += blk((((u64)1 << guide_bits_for(m)) + 1) * sizeof(RootGuide));  // root guide
-    if (windows && weights_keep_windows(P, m)) b += weights_window_bytes(P, m);
+    b += blk((((u64)1 << guide_bits_for(m, lean)) + 1) * sizeof(RootGuide));  // root guide
+    if (!lean && weights_keep_windows(P, m)) b += weights_window_bytes(P, m);
     return b;
 }
 
@@ -572,11 +573,11 @@ bool weights_keep_windows(const HostPlan& P, int64_t m) {
     return m > 0 && weights_window_bytes(P, m) <= kWinMaxBytes;
 }
 
-int guide_bits_for(int64_t m) {
+int guide_bits_for(int64_t m, bool lean) {
     int b = 0;
-    while (b < 62 && ((int64_t)1 << (b + 1)) <= m) ++b;  // floor(log2 m)
-                                                           // ~2m pairs, ~2 per bucket
-    return b < 8 ? 8 : (b > 24 ? 24 : b);
+    while (b < 62 && ((int64_t)1 << (b + 1)) <= m) ++b;  // floor(log2 m): ~2m pairs, ~2 per bucket
+    if (lean) b -= 2;
+    return b < 8 ? 8 : (b > 23 ? 23 : b);
 }
 
 u64 weights_build_extra(int64_t m, bool wide) {
