@@ -836,9 +836,11 @@ int bits_of(u64 x) {
 // six low bits (samples within 32 list positions) stay unsorted when that
 // saves a pass.
 int root_sort_lo_bit(int key_bits) {
+    // whole 8-bit digits: at 1e7 keys a 9-bit digit leaves too few keys per
+    // digit in a tile for its writes to stay contiguous
     const int need = key_bits > 6 ? key_bits - 6 : 0;
-    const int passes = (need + kRadixBits - 1) / kRadixBits;
-    const int lo = key_bits - passes * kRadixBits;
+    const int passes = (need + 7) / 8;
+    const int lo = key_bits - passes * 8;
     return lo > 0 ? lo : 0;
 }
 
@@ -1379,7 +1381,7 @@ void group_prepare(tm_weights* const* ws, const std::vector<int>& act, const u64
         G.total += counts[act[y]];
     }
     G.key_bits = std::max(1, bits_of(key_space - 1));
-    G.passes = (G.key_bits - root_sort_lo_bit(G.key_bits) + kRadixBits - 1) / kRadixBits;
+    G.passes = radix_passes(G.key_bits - root_sort_lo_bit(G.key_bits));
     const int tile = cfg.tile > 0 ? cfg.tile : 8192;
     int cus = 256;
     {

@@ -75,8 +75,8 @@ int scan_parts(u128* part, int64_t nb, int* ovf, hipStream_t st) {
     return device_exclusive_scan<u128>(ArrayReader128{part}, nb, part, ovf, st);
 }
 
-int radix_rowscan(uint32_t* hist, int64_t ntiles, uint32_t* totals, hipStream_t st) {
-    hipLaunchKernelGGL(radix_rowscan_kernel, dim3((unsigned)kRadix), dim3(kBlock), 0, st, hist, ntiles, totals);
+int radix_rowscan(uint32_t* hist, int64_t ntiles, uint32_t* totals, hipStream_t st, int ndig) {
+    hipLaunchKernelGGL(radix_rowscan_kernel, dim3((unsigned)ndig), dim3(kBlock), 0, st, hist, ntiles, totals);
     TM_HIP(hipGetLastError());
     return TM_OK;
 }

@@ -9,8 +9,12 @@ constexpr int kScanItems = 8;                      // values per lane in a scan 
 constexpr int kScanTile = kBlock * kScanItems;     // 2048
 constexpr int kSortItems = 8;                      // keys per lane in a sort tile
 constexpr int kSortTile = kBlock * kSortItems;     // 2048
-constexpr int kRadixBits = 8;
-constexpr int kRadix = 1 << kRadixBits;
+constexpr int kRadixMaxBits = 9;                   // sort digits: up to 9 bits, two per thread
+constexpr int kRadixMax = 1 << kRadixMaxBits;
+
+// Radix passes over nb key bits (digits of at most kRadixMaxBits, split as
+// evenly as possible).
+inline int radix_passes(int nb) { return nb <= 0 ? 0 : (nb + kRadixMaxBits - 1) / kRadixMaxBits; }
 
 // Clearing device words with a kernel rather than a memset node, so that the
 // same code can be captured into a HIP graph.
@@ -155,7 +159,8 @@ int device_exclusive_scan(F f, int64_t n, T* out, int* ovf, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort of (key, value) pairs, 8-bit digits (fewer than 2^32).
+// Stable LSD radix sort of (key, value) pairs (fewer than 2^32), digits of up
+// to 9 bits.
 // Per pass: tile histograms (digit-major), an exclusive scan of each digit's
 // row with the digit totals, then a scatter in which every wave ranks its
 // keys in input order with ballots and each digit's start is the scan of the
@@ -164,8 +169,9 @@ int device_exclusive_scan(F f, int64_t n, T* out, int* ovf, hipStream_t st) {
 template <typename K>
 __global__ void __launch_bounds__(kBlock)
 radix_hist_kernel(const K* keys, int64_t n, int shift, int bits, uint32_t* hist, int64_t ntiles) {
-    __shared__ uint32_t h[kRadix];
+    __shared__ uint32_t h[kRadixMax];
     h[threadIdx.x] = 0;
+    h[threadIdx.x + kBlock] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     const K mask = (K)((1u << bits) - 1);
@@ -175,7 +181,7 @@ radix_hist_kernel(const K* keys, int64_t n, int shift, int bits, uint32_t* hist,
         if (i < n) atomicAdd(&h[(uint32_t)((keys[i] >> shift) & mask)], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+    for (int d = threadIdx.x; d < (1 << bits); d += kBlock) hist[(int64_t)d * ntiles + blockIdx.x] = h[d];
 }
 
 // Exclusive scan of v over the block's 256 threads (thread t holds entry t):
@@ -197,23 +203,26 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t* ws
     return before + inc - v;
 }
 
-// Per digit: the exclusive scan of the digit's row of tile counts
+// Per digit d < ndig: the exclusive scan of the digit's row of tile counts
 // (hist[d * ntiles + tile]), in place, and the row's total in totals[d].
-int radix_rowscan(uint32_t* hist, int64_t ntiles, uint32_t* totals, hipStream_t st);
+int radix_rowscan(uint32_t* hist, int64_t ntiles, uint32_t* totals, hipStream_t st, int ndig);
 
 template <typename K>
 __global__ void __launch_bounds__(kBlock)
 radix_scatter_kernel(const K* keys, const uint32_t* vals, K* okeys, uint32_t* ovals, int64_t n,
                      int shift, int bits, const uint32_t* offs, const uint32_t* totals, int64_t ntiles) {
-    static_assert(kBlock == kRadix, "one thread per digit");
-    __shared__ uint32_t cnt[kWaves][kRadix];
-    __shared__ uint32_t dstart[kRadix];  // tile-local start of each digit's run
-    __shared__ uint32_t gbase[kRadix];   // global start of this tile's run of each digit
+    static_assert(2 * kBlock == kRadixMax, "two digits per thread");
+    __shared__ uint32_t cnt[kWaves][kRadixMax];
+    __shared__ uint32_t dstart[kRadixMax];  // tile-local start of each digit's run
+    __shared__ uint32_t gbase[kRadixMax];   // global start of this tile's run of each digit
     __shared__ K skey[kSortTile];
     __shared__ uint32_t sval[kSortTile];
     __shared__ uint32_t wsum[kWaves];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int w = 0; w < kWaves; ++w) cnt[w][threadIdx.x] = 0;
+    for (int w = 0; w < kWaves; ++w) {
+        cnt[w][threadIdx.x] = 0;
+        cnt[w][threadIdx.x + kBlock] = 0;
+    }
     __syncthreads();
     const K mask = (K)((1u << bits) - 1);
     const u64 lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -245,25 +254,36 @@ radix_scatter_kernel(const K* keys, const uint32_t* vals, K* okeys, uint32_t* ov
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    // per digit (one thread each): the tile's count, then its exclusive scan
+    // per digit pair (d0, d1 = 2t, 2t + 1 for thread t, so that scans over the
+    // threads run in digit order): the tile's counts, their exclusive scan
     // over digits (the tile-local start), and each wave's start inside it
-    const uint32_t d = threadIdx.x;
-    uint32_t total = 0;
-    for (int w = 0; w < kWaves; ++w) total += cnt[w][d];
-    // global start of this tile's run of digit d: the digit's start (scan of
-    // the digit totals) plus the earlier tiles' counts of d
-    gbase[d] = block_excl_scan_256(totals[d], wsum) + offs[(int64_t)d * ntiles + blockIdx.x];
-    const uint32_t local = block_excl_scan_256(total, wsum);
+    const int ndig = 1 << bits;
+    const uint32_t d0 = 2 * threadIdx.x, d1 = d0 + 1;
+    uint32_t t0 = 0, t1 = 0;
+    for (int w = 0; w < kWaves; ++w) {
+        t0 += cnt[w][d0];
+        t1 += cnt[w][d1];
+    }
+    // global start of this tile's run of a digit: the digit's start (scan of
+    // the digit totals) plus the earlier tiles' counts of it
+    const uint32_t g0 = (int)d0 < ndig ? totals[d0] : 0u, g1 = (int)d1 < ndig ? totals[d1] : 0u;
+    const uint32_t gb = block_excl_scan_256(g0 + g1, wsum);
+    if ((int)d0 < ndig) gbase[d0] = gb + offs[(int64_t)d0 * ntiles + blockIdx.x];
+    if ((int)d1 < ndig) gbase[d1] = gb + g0 + offs[(int64_t)d1 * ntiles + blockIdx.x];
+    const uint32_t local = block_excl_scan_256(t0 + t1, wsum);
     {
-        uint32_t run = local;  // exclusive
+        uint32_t run0 = local, run1 = local + t0;  // exclusive
         for (int w = 0; w < kWaves; ++w) {
-            const uint32_t c = cnt[w][d];
-            cnt[w][d] = run;
-            run += c;
+            const uint32_t c0 = cnt[w][d0], c1 = cnt[w][d1];
+            cnt[w][d0] = run0;
+            cnt[w][d1] = run1;
+            run0 += c0;
+            run1 += c1;
         }
     }
     __syncthreads();
-    dstart[d] = cnt[0][d];
+    dstart[d0] = cnt[0][d0];
+    dstart[d1] = cnt[0][d1];
     // keys to their tile-local sorted places
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
@@ -301,23 +321,27 @@ int radix_sort_pairs(K* keys, uint32_t* vals, K* tkeys, uint32_t* tvals, int64_t
     uint32_t* va = vals;
     K* kb = tkeys;
     uint32_t* vb = tvals;
-    if (n > 1 && nbits > 0) {
+    if (n > 1 && nbits > lo_bit) {
         const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+        const int npass = radix_passes(nbits - lo_bit);
+        const int64_t maxdig = (int64_t)1 << ((nbits - lo_bit + npass - 1) / npass);
         uint32_t* hist = nullptr;
-        TM_HIP(dev_alloc((void**)&hist, (ntiles * kRadix + kRadix) * sizeof(uint32_t), st));
-        uint32_t* totals = hist + ntiles * kRadix;
-        for (int shift = lo_bit; shift < nbits; shift += kRadixBits) {
-            const int bits = nbits - shift < kRadixBits ? nbits - shift : kRadixBits;
+        TM_HIP(dev_alloc((void**)&hist, (ntiles * maxdig + maxdig) * sizeof(uint32_t), st));
+        uint32_t* totals = hist + ntiles * maxdig;
+        int shift = lo_bit;
+        for (int p = 0; p < npass; ++p) {
+            const int bits = (nbits - shift + (npass - p) - 1) / (npass - p);
             hipLaunchKernelGGL((radix_hist_kernel<K>), dim3((unsigned)ntiles), dim3(kBlock), 0, st,
                                (const K*)ka, n, shift, bits, hist, ntiles);
             TM_HIP(hipGetLastError());
-            TM_TRY(radix_rowscan(hist, ntiles, totals, st));
+            TM_TRY(radix_rowscan(hist, ntiles, totals, st, 1 << bits));
             hipLaunchKernelGGL((radix_scatter_kernel<K>), dim3((unsigned)ntiles), dim3(kBlock), 0,
                                st, (const K*)ka, (const uint32_t*)va, kb, vb, n, shift, bits,
                                (const uint32_t*)hist, (const uint32_t*)totals, ntiles);
             TM_HIP(hipGetLastError());
             K* tk = ka; ka = kb; kb = tk;
             uint32_t* tv = va; va = vb; vb = tv;
+            shift += bits;
         }
         TM_HIP(dev_free(hist, st));
     }
