@@ -151,6 +151,39 @@ def test_every_tree_and_center_small_graph(T, name, edges, delta):
         check_prep(T, og, tg, edges, delta, otr, seeds=(3,), k=2000)
 
 
+def center_children_ends(edges, otr):
+    """Whether some child of the tree's center edge touches its source, its
+    destination."""
+    ids = list(otr.edge)[: otr.n_edges]
+    cu, cv = edges[otr.center]
+    others = [edges[i] for i in ids if i != otr.center]
+    return any(cu in e for e in others), any(cv in e for e in others)
+
+
+SORTED_CASES = [c for c in MOTIF_CASES if c[0] in ("3cycle", "4cycle", "4star", "in_star", "6chain", "lead_trail")]
+
+
+@pytest.mark.parametrize("name,edges,delta", SORTED_CASES, ids=[c[0] for c in SORTED_CASES])
+def test_root_sorted_path_both_root_lists(T, name, edges, delta):
+    """k >= 2^16 takes the root-sorted sampler, which reads the kept child
+    windows; the root keys come from the in-lists when every child of the
+    center attaches at its destination, else from the out-lists.  One tree
+    of each kind per motif (where the motif has one), sample by sample
+    against the oracle."""
+    g = W.small_graph(3000, 13, n=60, span=6000)
+    og, tg = pair(T, g)
+    picked = {}
+    for otr in all_tree_choices(edges):
+        at_src, at_dst = center_children_ends(edges, otr)
+        kind = "in" if at_dst and not at_src else "out"
+        picked.setdefault(kind, otr)
+        if len(picked) == 2:
+            break
+    for kind, otr in sorted(picked.items()):
+        say(name, "root list", kind, "tree", list(otr.edge)[: otr.n_edges], "center", otr.center)
+        check_prep(T, og, tg, edges, delta, otr, seeds=(5,), k=70000)
+
+
 @pytest.mark.parametrize("name,edges,delta", MOTIF_CASES[:6], ids=[c[0] for c in MOTIF_CASES[:6]])
 def test_default_tree_multi_tile_graph(T, name, edges, delta):
     """Several scan and sort tiles with a ragged tail."""
