@@ -210,12 +210,14 @@ __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
     if (ovf) atomicOr(a.ovf, 4);
 }
 
-// Values of one parity gathered along a list order.
+// Values of one parity held in a list's T order, read in that list's N
+// order (through the N-to-T cross index, which stays inside each vertex's
+// list).
 template <typename W>
 struct ListGather {
     const W* val;
-    const int32_t* eid;
-    __device__ W operator()(int64_t p) const { return val[eid[p]]; }
+    const int32_t* at;
+    __device__ W operator()(int64_t p) const { return val[at[p]]; }
 };
 
 template <typename W>
@@ -385,7 +387,11 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
                 }
                 // the first of two passes leaves its products in its own walk
                 // order; the second gathers them
-                a.out_pos_dir = (two && pass == 0) ? a.walk : -1;
+                // a non-center slot's values land at its T-order position in
+                // the list its parent searches (that list's prefix arrays
+                // then scan them in place); the center's in eid order
+                const int own_dir = s == 0 ? -1 : (P.alpha[s] > 0 ? 0 : 1);
+                a.out_pos_dir = (two && pass == 0) ? a.walk : own_dir;
                 a.in_pos_dir = prev_walk;
                 prev_walk = a.walk;
                 a.ovf = ovf;
@@ -408,8 +414,8 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
                     TM_TRY(arena_alloc(w->arena, &qt, (size_t)m + 1));
                     TM_TRY(arena_alloc(w->arena, &qn, (size_t)m + 1));
                     const W* vp = static_cast<const W*>(w->vals[s][par]);
-                    TM_TRY(device_exclusive_scan<W>(ListGather<W>{vp, g->d.leid[dir]}, m, qt, ovf, st));
-                    TM_TRY(device_exclusive_scan<W>(ListGather<W>{vp, g->d.neid[dir]}, m, qn, ovf, st));
+                    TM_TRY(device_exclusive_scan<W>(Plain<W>{vp}, m, qt, ovf, st));
+                    TM_TRY(device_exclusive_scan<W>(ListGather<W>{vp, g->d.nxref[dir]}, m, qn, ovf, st));
                     w->qt[s][par] = qt;
                     w->qn[s][par] = qn;
                     TM_HIP(dev_free(w->vals[s][par], st));
