@@ -174,8 +174,9 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
 // and the temporaries a build holds on top of them at its peak (one slot's
 // values, per parity).
 u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide, bool lean = false);
-// Whether a weight set keeps its child windows: at most kWinMaxBytes of them.
-constexpr u64 kWinMaxBytes = (u64)8 << 30;
+// Whether a weight set keeps its child windows: at most kWinMaxBytes of them
+// (servers build lean sets without them).
+constexpr u64 kWinMaxBytes = (u64)32 << 30;
 u64 weights_window_bytes(const HostPlan& P, int64_t m);
 bool weights_keep_windows(const HostPlan& P, int64_t m);
 u64 weights_build_extra(int64_t m, bool wide);

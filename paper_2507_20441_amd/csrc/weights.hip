@@ -374,13 +374,11 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
                     }
                     a.win_dir = s == 0 ? P.root_dir : (P.alpha[s] > 0 ? 0 : 1);
                 }
-                // the center walks the list its children attach to (the
-                // root's list too when they all attach at one end), so
-                // neighbouring lanes search one list; other slots with kept
-                // windows walk the list whose positions index those windows,
-                // so that their writes go to consecutive addresses
-                const bool by_win = w->has_win && s != 0;
-                a.walk = a.nc == 0 ? -1 : (by_win ? a.win_dir : side);
+                // each pass walks the list its children attach to, so that
+                // neighbouring lanes search one list (the center's root list
+                // is that list too when all its children attach at one end);
+                // search locality outweighs scattered window writes
+                a.walk = a.nc == 0 ? -1 : side;
                 for (int par = 0; par < 2; ++par) {
                     a.out[par] = (two && pass == 0) ? (void*)tmp[par] : w->vals[s][par];
                     a.in[par] = (two && pass == 1) ? (const void*)tmp[par] : nullptr;
