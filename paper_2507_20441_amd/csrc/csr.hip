@@ -159,14 +159,16 @@ __global__ void copy_pair_kernel(const int32_t* k, const int32_t* v, int64_t m, 
 }
 
 // T-order list entries from the sorted eids.
-__global__ void fill_t_order_kernel(const uint32_t* eids, const int64_t* t, const int32_t* nbr_by_eid,
-                                    int64_t m, int64_t* lt, int32_t* leid, int32_t* lnbr, int32_t* pos) {
+__global__ void fill_t_order_kernel(const uint32_t* eids, const uint32_t* owner, const int64_t* t,
+                                    const int32_t* nbr_by_eid, int64_t m, int64_t* lt, int32_t* leid, int32_t* lnbr,
+                                    int32_t* lown, int32_t* pos) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= m) return;
     const uint32_t e = eids[p];
     lt[p] = t[e];
     leid[p] = (int32_t)e;
     lnbr[p] = nbr_by_eid[e];
+    lown[p] = (int32_t)owner[p];
     pos[e] = (int32_t)p;
 }
 
@@ -192,7 +194,7 @@ __device__ __forceinline__ void unpack_tuv(u64 k, int bn, int64_t& t, int32_t& u
 }
 
 __global__ void fill_t_order_packed_kernel(const uint32_t* eids, const u64* pk, int bn, int dir, int64_t m,
-                                           int64_t* lt, int32_t* leid, int32_t* lnbr, int32_t* pos) {
+                                           int64_t* lt, int32_t* leid, int32_t* lnbr, int32_t* lown, int32_t* pos) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= m) return;
     const uint32_t e = eids[p];
@@ -202,6 +204,7 @@ __global__ void fill_t_order_packed_kernel(const uint32_t* eids, const u64* pk, 
     lt[p] = t;
     leid[p] = (int32_t)e;
     lnbr[p] = dir == 0 ? v : u;
+    lown[p] = dir == 0 ? u : v;
     pos[e] = (int32_t)p;
 }
 
@@ -359,10 +362,11 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
         const int32_t* key_by_eid = dir == 0 ? esrc : edst;
         const int32_t* nbr_by_eid = dir == 0 ? edst : esrc;
         int64_t* lt;
-        int32_t *leid, *lnbr, *off;
+        int32_t *leid, *lnbr, *lown, *off;
         TM_TRY(arena_alloc(g->arena, &lt, m));
         TM_TRY(arena_alloc(g->arena, &leid, m));
         TM_TRY(arena_alloc(g->arena, &lnbr, m));
+        TM_TRY(arena_alloc(g->arena, &lown, m));
         TM_TRY(arena_alloc(g->arena, &off, (size_t)n + 1));
         TM_TRY(arena_alloc(g->arena, &tpos[dir], (size_t)m));
         // T order: stable sort of the eids by the list owner
@@ -373,11 +377,11 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
         TM_TRY(radix_sort_pairs<uint32_t>(k32a, va, k32b, vb, m, 0, bn, &kr, &vr, flags + 1, st));
         if (packed)
             hipLaunchKernelGGL(fill_t_order_packed_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
-                               (const uint32_t*)vr, (const u64*)kres, bn, dir, m, lt, leid, lnbr, tpos[dir]);
+                               (const uint32_t*)vr, (const u64*)kres, bn, dir, m, lt, leid, lnbr, lown, tpos[dir]);
         else
             hipLaunchKernelGGL(fill_t_order_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
-                               (const uint32_t*)vr, (const int64_t*)et, nbr_by_eid, m, lt, leid, lnbr,
-                               tpos[dir]);
+                               (const uint32_t*)vr, (const uint32_t*)kr, (const int64_t*)et, nbr_by_eid, m, lt,
+                               leid, lnbr, lown, tpos[dir]);
         TM_HIP(hipGetLastError());
         hipLaunchKernelGGL(offsets_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
                            (const uint32_t*)kr, m, n, off);
@@ -386,6 +390,7 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
         D.tpos[dir] = tpos[dir];
         D.lt[dir] = lt;
         D.leid[dir] = leid;
+        D.lown[dir] = lown;
         D.lnbr[dir] = lnbr;
     }
     // N order of dir d: the T order of the other direction (sorted by the

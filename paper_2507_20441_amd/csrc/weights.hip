@@ -139,9 +139,20 @@ __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const DevGraph& G = a.G;
     if (p >= G.m) return;
+    // the walked edge: its list's owner, neighbour and time sit at p
     const int32_t e = a.walk < 0 ? (int32_t)p : G.leid[a.walk][p];
-    const int32_t u = G.src[e], v = G.dst[e];
-    const int64_t t = G.t[e];
+    int32_t u, v;
+    int64_t t;
+    if (a.walk < 0) {
+        u = G.src[e];
+        v = G.dst[e];
+        t = G.t[e];
+    } else {
+        const int32_t own = G.lown[a.walk][p], nbr = G.lnbr[a.walk][p];
+        u = a.walk == 0 ? own : nbr;
+        v = a.walk == 0 ? nbr : own;
+        t = G.lt[a.walk][p];
+    }
     const int64_t blk = t / a.ilen;
     const bool hasB = blk >= 1;
     const int parA = (int)(blk & 1), parB = parA ^ 1;
