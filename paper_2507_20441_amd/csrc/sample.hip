@@ -1214,7 +1214,9 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
     a.key_base = 0;
     const bool sorted = count >= kSortMin;
     const u64 chunk = std::min<u64>(count, kChunk);
-    const int blocks = (int)std::min<u64>((chunk + kBlock - 1) / kBlock, 8192);
+    // grid-stride lanes: 2560 workgroups fill the chip about twice over and
+    // leave that many partials for the one-workgroup reduction
+    const int blocks = (int)std::min<u64>((chunk + kBlock - 1) / kBlock, 2560);
     const int key_bits = bits_of(2 * (u64)w->g->m - 1);
     Partial* parts = nullptr;
     int* ovf = nullptr;
@@ -1239,13 +1241,15 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
         a.count = n;
         a.recs = recs ? recs + c0 : nullptr;
         const dim3 grid((unsigned)std::min<u64>((n + kBlock - 1) / kBlock, (u64)blocks));
+        // the root draws keep a wider grid (more draws in flight)
+        const dim3 rgrid((unsigned)std::min<u64>((n + kBlock - 1) / kBlock, 8192));
         StageTimer t_roots, t_sample, t_reduce;
         if (sorted) {
             if (!model_bytes) t_roots.start(TM_STAGE_ROOTS, st);
             if (w->wide)
-                hipLaunchKernelGGL(root_kernel<u128>, grid, dim3(kBlock), lds, st, a, k0, v0);
+                hipLaunchKernelGGL(root_kernel<u128>, rgrid, dim3(kBlock), lds, st, a, k0, v0);
             else
-                hipLaunchKernelGGL(root_kernel<u64>, grid, dim3(kBlock), lds, st, a, k0, v0);
+                hipLaunchKernelGGL(root_kernel<u64>, rgrid, dim3(kBlock), lds, st, a, k0, v0);
             TM_HIP(hipGetLastError());
             uint32_t *ks, *vs;
             TM_TRY(radix_sort_pairs<uint32_t>(k0, v0, k1, v1, (int64_t)n, root_sort_lo_bit(key_bits), key_bits, &ks,
