@@ -456,10 +456,9 @@ __global__ void __launch_bounds__(kBlock) root_kernel(SampleArgs a, uint32_t* ke
     const W* cum = a.cum_in_lds ? cumL : cumG;
     bool bad = false;
     const u64 stride = (u64)gridDim.x * kBlock;
-    for (u64 r = (u64)blockIdx.x * kBlock + threadIdx.x; r < a.count; r += stride) {
+    (void)vals;  // the sort makes the sample offsets (0 .. count-1) itself
+    for (u64 r = (u64)blockIdx.x * kBlock + threadIdx.x; r < a.count; r += stride)
         keys[r] = root_key<W>(a, cum, Wtot, ncum, r, bad);
-        vals[r] = (uint32_t)r;
-    }
     if (bad) atomicOr(a.ovf, 2);
 }
 
@@ -1215,8 +1214,9 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
     const bool sorted = count >= kSortMin;
     const u64 chunk = std::min<u64>(count, kChunk);
     // grid-stride lanes: 2560 workgroups fill the chip about twice over and
-    // leave that many partials for the one-workgroup reduction
-    const int blocks = (int)std::min<u64>((chunk + kBlock - 1) / kBlock, 2560);
+    // leave that many partials for the one-workgroup reduction; runs of 2^25
+    // samples and more keep 8192 (the reduction is then negligible)
+    const int blocks = (int)std::min<u64>((chunk + kBlock - 1) / kBlock, chunk >= ((u64)1 << 25) ? 8192 : 2560);
     const int key_bits = bits_of(2 * (u64)w->g->m - 1);
     Partial* parts = nullptr;
     int* ovf = nullptr;
@@ -1253,7 +1253,7 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
             TM_HIP(hipGetLastError());
             uint32_t *ks, *vs;
             TM_TRY(radix_sort_pairs<uint32_t>(k0, v0, k1, v1, (int64_t)n, root_sort_lo_bit(key_bits), key_bits, &ks,
-                                              &vs, ovf, st));
+                                              &vs, ovf, st, true));
             a.skey = ks;
             a.sval = vs;
             t_roots.stop();

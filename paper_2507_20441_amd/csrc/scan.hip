@@ -66,6 +66,19 @@ int fill_u32(void* p, int64_t n_words, uint32_t v, hipStream_t st) {
     return TM_OK;
 }
 
+__global__ void fill_iota_kernel(uint32_t* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        p[i] = (uint32_t)i;
+}
+
+int fill_iota_u32(uint32_t* p, int64_t n, hipStream_t st) {
+    if (n <= 0) return TM_OK;
+    const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 4096);
+    hipLaunchKernelGGL(fill_iota_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, p, n);
+    TM_HIP(hipGetLastError());
+    return TM_OK;
+}
+
 int scan_parts(u128* part, int64_t nb, int* ovf, hipStream_t st) {
     if (nb <= kScanTile) {
         hipLaunchKernelGGL(scan_single_kernel, dim3(1), dim3(kBlock), 0, st, part, nb, ovf);

@@ -19,6 +19,8 @@ inline int radix_passes(int nb) { return nb <= 0 ? 0 : (nb + kRadixMaxBits - 1) 
 // Clearing device words with a kernel rather than a memset node, so that the
 // same code can be captured into a HIP graph.
 __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v);
+// p[i] = i for i < n.
+int fill_iota_u32(uint32_t* p, int64_t n, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Wave and block scans of 128-bit values (two 64-bit shuffles per step).
@@ -210,7 +212,7 @@ int radix_rowscan(uint32_t* hist, int64_t ntiles, uint32_t* totals, hipStream_t 
 template <typename K>
 __global__ void __launch_bounds__(kBlock)
 radix_scatter_kernel(const K* keys, const uint32_t* vals, K* okeys, uint32_t* ovals, int64_t n,
-                     int shift, int bits, const uint32_t* offs, const uint32_t* totals, int64_t ntiles) {
+                     int shift, int bits, const uint32_t* offs, const uint32_t* totals, int64_t ntiles, int iota) {
     static_assert(2 * kBlock == kRadixMax, "two digits per thread");
     __shared__ uint32_t cnt[kWaves][kRadixMax];
     __shared__ uint32_t dstart[kRadixMax];  // tile-local start of each digit's run
@@ -239,7 +241,7 @@ radix_scatter_kernel(const K* keys, const uint32_t* vals, K* okeys, uint32_t* ov
         const int64_t i = wbase + (int64_t)k * 64 + lane;
         const bool ok = i < n;
         key[k] = ok ? keys[i] : (K)0;
-        val[k] = ok ? vals[i] : 0u;
+        val[k] = ok ? (iota ? (uint32_t)i : vals[i]) : 0u;
         const uint32_t d = ok ? (uint32_t)((key[k] >> shift) & mask) : 0u;
         dig[k] = d;
         u64 peers = __ballot(ok);
@@ -313,10 +315,11 @@ struct HistReader {
 
 // Sorts (keys, vals) by bits [lo_bit, nbits) of the key, stably.  Buffers
 // ping-pong between (keys, vals) and (tkeys, tvals); on return *k_out / *v_out
-// point to whichever pair holds the result.
+// point to whichever pair holds the result.  iota_vals: vals holds nothing
+// yet and stands for 0 .. n-1 (the first pass makes them).
 template <typename K>
 int radix_sort_pairs(K* keys, uint32_t* vals, K* tkeys, uint32_t* tvals, int64_t n, int lo_bit,
-                     int nbits, K** k_out, uint32_t** v_out, int* ovf, hipStream_t st) {
+                     int nbits, K** k_out, uint32_t** v_out, int* ovf, hipStream_t st, bool iota_vals = false) {
     K* ka = keys;
     uint32_t* va = vals;
     K* kb = tkeys;
@@ -337,7 +340,7 @@ int radix_sort_pairs(K* keys, uint32_t* vals, K* tkeys, uint32_t* tvals, int64_t
             TM_TRY(radix_rowscan(hist, ntiles, totals, st, 1 << bits));
             hipLaunchKernelGGL((radix_scatter_kernel<K>), dim3((unsigned)ntiles), dim3(kBlock), 0,
                                st, (const K*)ka, (const uint32_t*)va, kb, vb, n, shift, bits,
-                               (const uint32_t*)hist, (const uint32_t*)totals, ntiles);
+                               (const uint32_t*)hist, (const uint32_t*)totals, ntiles, (iota_vals && p == 0) ? 1 : 0);
             TM_HIP(hipGetLastError());
             K* tk = ka; ka = kb; kb = tk;
             uint32_t* tv = va; va = vb; vb = tv;
@@ -345,6 +348,7 @@ int radix_sort_pairs(K* keys, uint32_t* vals, K* tkeys, uint32_t* tvals, int64_t
         }
         TM_HIP(dev_free(hist, st));
     }
+    if (iota_vals && !(n > 1 && nbits > lo_bit)) TM_TRY(fill_iota_u32(va, n, st));  // no pass ran
     *k_out = ka;
     *v_out = va;
     return TM_OK;
