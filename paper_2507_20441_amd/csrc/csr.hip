@@ -168,7 +168,7 @@ __global__ void fill_t_order_kernel(const uint32_t* eids, const uint32_t* owner,
     lt[p] = t[e];
     leid[p] = (int32_t)e;
     lnbr[p] = nbr_by_eid[e];
-    lown[p] = (int32_t)owner[p];
+    if (lown) lown[p] = (int32_t)owner[p];
     pos[e] = (int32_t)p;
 }
 
@@ -204,7 +204,7 @@ __global__ void fill_t_order_packed_kernel(const uint32_t* eids, const u64* pk, 
     lt[p] = t;
     leid[p] = (int32_t)e;
     lnbr[p] = dir == 0 ? v : u;
-    lown[p] = dir == 0 ? u : v;
+    if (lown) lown[p] = dir == 0 ? u : v;
     pos[e] = (int32_t)p;
 }
 
@@ -366,7 +366,8 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
         TM_TRY(arena_alloc(g->arena, &lt, m));
         TM_TRY(arena_alloc(g->arena, &leid, m));
         TM_TRY(arena_alloc(g->arena, &lnbr, m));
-        TM_TRY(arena_alloc(g->arena, &lown, m));
+        lown = nullptr;
+        if (m <= ((int64_t)1 << 28)) TM_TRY(arena_alloc(g->arena, &lown, m));
         TM_TRY(arena_alloc(g->arena, &off, (size_t)n + 1));
         TM_TRY(arena_alloc(g->arena, &tpos[dir], (size_t)m));
         // T order: stable sort of the eids by the list owner

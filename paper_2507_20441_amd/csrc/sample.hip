@@ -540,7 +540,7 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
             e0 = G.leid[rd][pos];
             te[0] = G.lt[rd][pos];
             const int32_t nbr0 = G.lnbr[rd][pos];
-            const int32_t own0 = G.lown[rd][pos];
+            const int32_t own0 = G.lown[rd] ? G.lown[rd][pos] : (rd ? G.dst[e0] : G.src[e0]);
             u0 = rd ? nbr0 : own0;
             v0 = rd ? own0 : nbr0;
             const int64_t blk = te[0] / a.ilen;

@@ -35,7 +35,8 @@ struct DevGraph {
     const int64_t* lt[2];      // T order: time
     const int32_t* leid[2];    // T order: eid
     const int32_t* lnbr[2];    // T order: neighbour
-    const int32_t* lown[2];    // T order: the list's owner (source for out-lists)
+    const int32_t* lown[2];    // T order: the list's owner (source for out-lists); null
+                               // above 2^28 edges (memory goes to weight sets there)
     const u64* nkey[2];        // N order: neighbour << bt | time
     const int32_t* nxref[2];   // N order: position of the edge in the T order
     const int32_t* neid[2];    // N order: eid

@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
     const int32_t e = a.walk < 0 ? (int32_t)p : G.leid[a.walk][p];
     int32_t u, v;
     int64_t t;
-    if (a.walk < 0) {
+    if (a.walk < 0 || !G.lown[a.walk]) {
         u = G.src[e];
         v = G.dst[e];
         t = G.t[e];
