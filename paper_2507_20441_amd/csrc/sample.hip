@@ -444,7 +444,6 @@ __device__ __forceinline__ uint32_t root_key(const SampleArgs& a, const W* cum, 
 template <typename W>
 __global__ void __launch_bounds__(kBlock) root_kernel(SampleArgs a, uint32_t* keys, uint32_t* vals) {
     extern __shared__ unsigned char lds_raw[];
-    const DevGraph& G = a.G;
     const W Wtot = (W)(((u128)a.W_hi << 64) | a.W_lo);
     const W* cumG = static_cast<const W*>(a.cumW);
     const int32_t ncum = (int32_t)a.q + 1;
@@ -517,7 +516,6 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
     constexpr int NT = kMaxSlots - 1;  // register slots; a.nt of them are used
     const DevGraph& G = a.G;
     const W Wtot = (W)(((u128)a.W_hi << 64) | a.W_lo);
-    const int32_t ncum = (int32_t)a.q + 1;
     u128 acc2 = L.acc2, acc2_sq = L.acc2_sq;
     uint32_t n_valid = L.n_valid, n_vertex = L.n_vertex, n_delta = L.n_delta, n_order = L.n_order,
              n_nonzero = L.n_nonzero;
@@ -1025,65 +1023,11 @@ job_reduce_kernel(const Partial* tile_parts, const int* first, const int* count,
     block_reduce_write(acc, &out[blockIdx.x]);
 }
 
-// Motif families: M_phi of every valid record for one motif whose spanning
-// tree is the sampled one (the record's tree image, this motif's non-tree
-// edges), with the per-block sums of 2 M_phi / N_phi.
-template <bool kGeneral>
-__global__ void __launch_bounds__(kBlock)
-family_kernel(SampleArgs a, const tm_sample_rec* recs, const uint32_t* order, u64 count, Partial* parts,
-              int* ovf) {
-    constexpr int NT = kMaxSlots - 1;
-    const DevGraph& G = a.G;
-    LaneAcc L = lane_zero();
-    u64 nb = 0;
-    for (u64 x0 = (u64)blockIdx.x * kBlock + threadIdx.x; x0 < count; x0 += (u64)gridDim.x * kBlock) {
-        const tm_sample_rec& rec = recs[order[x0]];
-        if (rec.status != 0) continue;
-        int32_t img[TM_MAX_K];
-        int64_t te[NT];
-        sfor<0, TM_MAX_K>([&](auto xx) { img[decltype(xx)::value] = -1 - decltype(xx)::value; });
-        sfor<0, NT>([&](auto xx) { te[decltype(xx)::value] = 0; });
-        sfor<0, NT>([&](auto xc) {
-            constexpr int x = decltype(xc)::value;
-            if (x >= a.nt) return;
-            const int s = a.by_pi[x];
-            const int32_t e = rec.eid[x];
-            put(te, s, G.t[e]);
-            put(img, a.esrc[s], G.src[e]);
-            put(img, a.edst[s], G.dst[e]);
-        });
-        const u128 m_phi = completions<false, kGeneral>(a, img, te, L.ovf, nb);
-        ++L.n_valid;
-        if (m_phi != 0) ++L.n_nonzero;
-        u128 term;
-        if (!mul_ok(m_phi, (u128)(2 / rec.n_phi), &term)) L.ovf = true;
-        if (!add_ok(L.acc2, term, &L.acc2)) L.flags |= 1;
-        u128 sq;
-        if (!mul_ok(term, term, &sq) || !add_ok(L.acc2_sq, sq, &L.acc2_sq)) {
-            L.acc2_sq = ~(u128)0;
-            L.flags |= 2;
-        }
-    }
-    lanes_reduce(L, &parts[blockIdx.x], ovf);
-}
-
 // Random instance listing: for every valid record with 0 < M_phi <= kListMax,
 // the r-th completion (r from draw kListDraw of the sample) by a depth-first
 // walk over the motif edges in pi order -- tree edges fixed, non-tree edges
 // over their multi-edge lists within delta of the tree times, in eid order --
 // with strictly increasing times and everything within delta of the first.
-// Family passes visit the records in root order (as the sampler does): the
-// root's T-order position and interval parity, invalid records last.
-__global__ void __launch_bounds__(kBlock)
-family_keys_kernel(const tm_sample_rec* recs, u64 count, const int32_t* tpos0, int center_rank, uint32_t last,
-                   uint32_t* keys, uint32_t* vals) {
-    const u64 r = (u64)blockIdx.x * kBlock + threadIdx.x;
-    if (r >= count) return;
-    const tm_sample_rec& rec = recs[r];
-    keys[r] = rec.status == 0 ? (uint32_t)tpos0[rec.eid[center_rank]] * 2u + (rec.interval & 1u) : last;
-    vals[r] = (uint32_t)r;
-}
-
 constexpr uint32_t kListDraw = 15;
 constexpr u64 kListMax = (u64)1 << 20;
 
@@ -1735,9 +1679,10 @@ int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hip
     *shared = JobSums{};
     if (w->W == 0 || k == 0) return TM_OK;
     std::vector<SampleArgs> args(n);
+    size_t lds = 0;
     for (int f = 0; f < n; ++f) {
-        size_t lds;
         fill_args(w, &args[f], &lds);
+        args[f].seed = seed;
         const HostPlan& P = plans[f];
         // this member's non-tree edges (its tree slots are the sampled ones)
         args[f].n_free = P.n_free;
@@ -1760,55 +1705,56 @@ int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hip
         if (lead && trail) args[f].general_runs = 1;
         args[f].delta = P.mo.delta;
     }
-    const u64 chunk = std::min<u64>(k, (u64)1 << 24);
-    const int blocks = 2048;
-    tm_sample_rec* recs = nullptr;
+    // the tree samples are the same for every member (draws keyed by sample
+    // id and slot): one root pass and sort per chunk, then one sampling pass
+    // per member over the sorted roots, completing that member's non-tree
+    // edges; the tree's validation counts come from the first member's pass
+    const u64 chunk = std::min<u64>(k, kChunk);
+    const bool sorted = chunk >= kSortMin;
+    const int blocks = (int)std::min<u64>((chunk + kBlock - 1) / kBlock, chunk >= ((u64)1 << 25) ? 8192 : 2560);
+    const int key_bits = bits_of(2 * (u64)w->g->m - 1);
     Partial* parts = nullptr;
     int* ovf = nullptr;
     uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
-    TM_HIP(dev_alloc((void**)&recs, chunk * sizeof(tm_sample_rec), st));
-    TM_HIP(dev_alloc((void**)&parts, (blocks + 1) * sizeof(Partial), st));
+    TM_HIP(dev_alloc((void**)&parts, (size_t)(blocks + 1) * sizeof(Partial), st));
     TM_HIP(dev_alloc((void**)&ovf, sizeof(int), st));
-    TM_HIP(dev_alloc((void**)&k0, chunk * sizeof(uint32_t), st));
-    TM_HIP(dev_alloc((void**)&v0, chunk * sizeof(uint32_t), st));
-    TM_HIP(dev_alloc((void**)&k1, chunk * sizeof(uint32_t), st));
-    TM_HIP(dev_alloc((void**)&v1, chunk * sizeof(uint32_t), st));
-    int center_rank = 0;
-    for (int x = 0; x < w->plan.nt; ++x)
-        if (w->plan.by_pi[x] == 0) center_rank = x;
-    const uint32_t last = (uint32_t)(2 * (u64)w->g->m);
-    const int key_bits = bits_of(last);
+    if (sorted) {
+        TM_HIP(dev_alloc((void**)&k0, chunk * sizeof(uint32_t), st));
+        TM_HIP(dev_alloc((void**)&v0, chunk * sizeof(uint32_t), st));
+        TM_HIP(dev_alloc((void**)&k1, chunk * sizeof(uint32_t), st));
+        TM_HIP(dev_alloc((void**)&v1, chunk * sizeof(uint32_t), st));
+    }
     int rc = TM_OK;
     for (u64 c0 = 0; c0 < k && rc == TM_OK; c0 += chunk) {
         const u64 cnt = std::min<u64>(chunk, k - c0);
-        tm_result tree;
-        rc = sample_run(w, seed, c0, cnt, k, st, &tree, recs, nullptr);
-        if (rc != TM_OK) break;
-        hipLaunchKernelGGL(family_keys_kernel, dim3((unsigned)((cnt + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
-                           (const tm_sample_rec*)recs, cnt, (const int32_t*)w->g->d.tpos[0], center_rank, last, k0,
-                           v0);
-        uint32_t *ks, *order;
+        for (int f = 0; f < n; ++f) {
+            args[f].j0 = c0;
+            args[f].count = cnt;
+            args[f].recs = nullptr;
+            args[f].parts = parts;
+            args[f].ovf = ovf;
+        }
         rc = fill_u32(ovf, 1, 0u, st);
-        if (rc == TM_OK)
-            rc = radix_sort_pairs<uint32_t>(k0, v0, k1, v1, (int64_t)cnt, root_sort_lo_bit(key_bits), key_bits, &ks,
-                                            &order, ovf, st);
         if (rc != TM_OK) break;
-        JobSums t;
-        t.n_valid = tree.n_valid;
-        t.n_vertex = tree.n_bad_vertex;
-        t.n_delta = tree.n_bad_delta;
-        t.n_order = tree.n_bad_order;
-        sums_merge(*shared, t);
-        for (int f = 0; f < n && rc == TM_OK; ++f) {
-            rc = fill_u32(ovf, 1, 0u, st);
-            if (rc != TM_OK) break;
-            const dim3 grid((unsigned)std::min<u64>((cnt + kBlock - 1) / kBlock, (u64)blocks));
-            if (args[f].general_runs)
-                hipLaunchKernelGGL(family_kernel<true>, grid, dim3(kBlock), 0, st, args[f], (const tm_sample_rec*)recs,
-                                   (const uint32_t*)order, cnt, parts, ovf);
+        const dim3 grid((unsigned)std::min<u64>((cnt + kBlock - 1) / kBlock, (u64)blocks));
+        if (sorted) {
+            const dim3 rgrid((unsigned)std::min<u64>((cnt + kBlock - 1) / kBlock, 8192));
+            if (w->wide)
+                hipLaunchKernelGGL(root_kernel<u128>, rgrid, dim3(kBlock), lds, st, args[0], k0, v0);
             else
-                hipLaunchKernelGGL(family_kernel<false>, grid, dim3(kBlock), 0, st, args[f], (const tm_sample_rec*)recs,
-                                   (const uint32_t*)order, cnt, parts, ovf);
+                hipLaunchKernelGGL(root_kernel<u64>, rgrid, dim3(kBlock), lds, st, args[0], k0, v0);
+            if (hipGetLastError() != hipSuccess) { rc = tm_fail(TM_EDEVICE, "family: launch"); break; }
+            uint32_t *ks, *vs;
+            rc = radix_sort_pairs<uint32_t>(k0, v0, k1, v1, (int64_t)cnt, root_sort_lo_bit(key_bits), key_bits, &ks,
+                                            &vs, ovf, st, true);
+            if (rc != TM_OK) break;
+            for (int f = 0; f < n; ++f) {
+                args[f].skey = ks;
+                args[f].sval = vs;
+            }
+        }
+        for (int f = 0; f < n && rc == TM_OK; ++f) {
+            launch_any<false>(w->wide, sorted, grid, sorted ? 0 : lds, st, args[f]);
             if (hipGetLastError() != hipSuccess) { rc = tm_fail(TM_EDEVICE, "family: launch"); break; }
             hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const Partial*)parts, (int)grid.x,
                                parts + blocks);
@@ -1820,6 +1766,10 @@ int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hip
                 rc = tm_fail(TM_EDEVICE, "family: copy");
                 break;
             }
+            if (hovf & 2) {
+                rc = tm_fail(TM_EDEVICE, "family: inconsistent weight tables");
+                break;
+            }
             JobSums x;
             x.acc2 = h.acc2;
             x.acc2_sq = h.acc2_sq;
@@ -1827,10 +1777,18 @@ int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hip
             x.flags = h.flags & 3;
             if (hovf & 1) x.flags |= 1;
             sums_merge(sums[f], x);
+            if (f == 0) {
+                JobSums t;
+                t.n_valid = h.n_valid;
+                t.n_vertex = h.n_vertex;
+                t.n_delta = h.n_delta;
+                t.n_order = h.n_order;
+                sums_merge(*shared, t);
+            }
         }
     }
-    for (void* q : {(void*)recs, (void*)parts, (void*)ovf, (void*)k0, (void*)v0, (void*)k1, (void*)v1})
-        (void)dev_free(q, st);
+    for (void* q : {(void*)parts, (void*)ovf, (void*)k0, (void*)v0, (void*)k1, (void*)v1})
+        if (q) (void)dev_free(q, st);
     (void)sync_stream(st);
     return rc;
 }
