@@ -466,15 +466,18 @@ __global__ void __launch_bounds__(kBlock) root_kernel(SampleArgs a, uint32_t* ke
 // M_phi of a valid tree image (Alg. 5): the completions over the non-tree
 // edges of a's motif.  img: the graph vertex of every motif vertex; te: the
 // time of every tree slot.
-template <bool kCount, bool kGeneral, int NT>
-__device__ __forceinline__ u128 completions(const SampleArgs& a, const int32_t (&img)[TM_MAX_K],
+template <bool kCount, bool kGeneral, int NT, int K>
+__device__ __forceinline__ u128 completions(const SampleArgs& a, const int32_t (&img)[K],
                                             const int64_t (&te)[NT], bool& ovf, u64& nb) {
     const DevGraph& G = a.G;
     u128 m_phi = 0;
     const int64_t tfirst = pick(te, a.by_pi[0]), tlast = pick(te, a.by_pi[a.nt - 1]);
     if constexpr (kGeneral) {
         V8 iv;
-        sfor<0, TM_MAX_K>([&](auto x) { iv.v[decltype(x)::value] = img[decltype(x)::value]; });
+        sfor<0, TM_MAX_K>([&](auto x) {
+            constexpr int xi = decltype(x)::value;
+            iv.v[xi] = xi < K ? img[xi < K ? xi : 0] : -1 - xi;
+        });
         int64_t tp[TM_MAX_L], tn[TM_MAX_L];
         for (int r2 = 0; r2 < a.n_runs; ++r2) {
             tp[r2] = a.run_prev[r2] >= 0 ? pick(te, a.run_prev[r2]) : 0;
@@ -509,11 +512,14 @@ __device__ __forceinline__ u128 completions(const SampleArgs& a, const int32_t (
 
 // kWin (root-sorted only): each child's window is read from the kept table
 // at its parent's list position instead of searched for.
-template <typename W, bool kCount, bool kGeneral, bool kSorted, bool kWin = false>
+// kSmall: trees of at most four edges and motifs of at most five vertices,
+// so that fewer register slots are live (more waves per SIMD).
+template <typename W, bool kCount, bool kGeneral, bool kSorted, bool kWin = false, bool kSmall = false>
 __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* cum, u64 x0, u64 xend,
                                                  u64 stride, LaneAcc& L) {
     static_assert(kSorted || !kWin, "windows are read by list position");
-    constexpr int NT = kMaxSlots - 1;  // register slots; a.nt of them are used
+    constexpr int NT = kSmall ? 4 : kMaxSlots - 1;  // register slots; a.nt of them are used
+    constexpr int K = kSmall ? 5 : TM_MAX_K;         // motif vertices held
     const DevGraph& G = a.G;
     const W Wtot = (W)(((u128)a.W_hi << 64) | a.W_lo);
     u128 acc2 = L.acc2, acc2_sq = L.acc2_sq;
@@ -524,8 +530,8 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
     for (u64 x = x0; x < xend; x += stride) {
         int64_t te[NT];
         int32_t posv[NT];  // kWin: each slot's position in the list it was drawn from
-        int32_t img[TM_MAX_K];
-        sfor<0, TM_MAX_K>([&](auto xx) { img[decltype(xx)::value] = -1 - decltype(xx)::value; });
+        int32_t img[K];
+        sfor<0, K>([&](auto xx) { img[decltype(xx)::value] = -1 - decltype(xx)::value; });
         u64 r;
         int32_t i, e0, u0, v0;
         if constexpr (kSorted) {
@@ -646,9 +652,9 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
         if (bad) break;
         // Alg. 4: vertex map 1-1, then delta range, then edge order
         uint32_t status = 0;
-        sfor<0, TM_MAX_K>([&](auto xc) {
+        sfor<0, K>([&](auto xc) {
             constexpr int x = decltype(xc)::value;
-            sfor<x + 1, TM_MAX_K>([&](auto yc) {
+            sfor<x + 1, K>([&](auto yc) {
                 constexpr int y = decltype(yc)::value;
                 if (y < a.k && img[x] == img[y]) status = 1;
             });
@@ -676,7 +682,7 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
             const int64_t b = tmin / a.ilen;
             n_phi = (b < a.q ? 1u : 0u) + ((b >= 1 && tmax < (b + 1) * a.ilen) ? 1u : 0u);
             // Alg. 5: completions over the non-tree edges
-            m_phi = completions<kCount, kGeneral>(a, img, te, ovf, nb);
+            m_phi = completions<kCount, kGeneral, NT, K>(a, img, te, ovf, nb);
             ++n_valid;
             if (m_phi != 0) ++n_nonzero;
             u128 term;
@@ -748,7 +754,7 @@ __device__ __forceinline__ void lanes_reduce(const LaneAcc& L, Partial* out, int
     if (L.bad) atomicOr(ovf, 2);
 }
 
-template <typename W, bool kCount, bool kGeneral, bool kSorted, bool kWin>
+template <typename W, bool kCount, bool kGeneral, bool kSorted, bool kWin, bool kSmall = false>
 __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
     extern __shared__ unsigned char lds_raw[];
     const W* cumG = static_cast<const W*>(a.cumW);
@@ -760,7 +766,7 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
     }
     const W* cum = a.cum_in_lds ? cumL : cumG;
     LaneAcc L = lane_zero();
-    sample_positions<W, kCount, kGeneral, kSorted, kWin>(a, cum, (u64)blockIdx.x * kBlock + threadIdx.x,
+    sample_positions<W, kCount, kGeneral, kSorted, kWin, kSmall>(a, cum, (u64)blockIdx.x * kBlock + threadIdx.x,
                                                    a.count, (u64)gridDim.x * kBlock, L);
     lanes_reduce(L, &a.parts[blockIdx.x], a.ovf);
 }
@@ -792,6 +798,10 @@ __global__ void fill_undrawn_kernel(tm_sample_rec* recs, u64 count) {
 template <typename W, bool kCount, bool kSorted>
 void launch_sample(dim3 grid, size_t lds, hipStream_t st, const SampleArgs& a) {
     if constexpr (kSorted) {
+        if (a.has_win && !a.general_runs && a.nt <= 4 && a.k <= 5) {
+            hipLaunchKernelGGL((sample_kernel<W, kCount, false, true, true, true>), grid, dim3(kBlock), lds, st, a);
+            return;
+        }
         if (a.has_win) {
             if (a.general_runs)
                 hipLaunchKernelGGL((sample_kernel<W, kCount, true, true, true>), grid, dim3(kBlock), lds, st, a);
