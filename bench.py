@@ -777,7 +777,7 @@ def weights_only(args):
 
 
 TRAFFIC_KERNELS = {
-    "sample_kernel": "sample_kernel<unsigned long long, false, false, true, true>",
+    "sample_kernel": "sample_kernel<unsigned long long, false, false, true, true",
     "root_kernel": "root_kernel<unsigned long long>",
     "level_kernel": "level_kernel<unsigned long long>",
 }
@@ -820,7 +820,8 @@ def summarize_traffic(fetch_dir, write_dir, out_path, calib_bytes):
         fv, wv = fk[fn[0]], wk[wn[0]]
         fb = statistics.mean(fv) * 1024 * f_scale
         wb = statistics.mean(wv) * 1024 * w_scale
-        kernels[key] = dict(name=fn[0].split("(")[0] if "(anonymous" not in fn[0] else pat,
+        name = fn[0].replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+        kernels[key] = dict(name=name,
                             launches=len(fv), fetch_kib_per_launch=fv, write_kib_per_launch=wv,
                             fetch_bytes_per_launch=round(fb), write_bytes_per_launch=round(wb),
                             hbm_bytes_per_launch=round(fb + wb))

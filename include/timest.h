@@ -321,7 +321,7 @@ int tm_choose_tree(tm_graph* g, const tm_motif* mo, int n_c, void* stream, tm_tr
 /* Device bytes the weight tables of (g, mo, tr) take in 64-bit (wide = 0)
  * or 128-bit (wide = 1) form: what tm_weights_info reports as device_bytes
  * after tm_weights_create builds them in that form, the kept child windows
- * included (kept when they total at most 8 GiB; a server builds its sets
+ * included (kept when they total at most 32 GiB; a server builds its sets
  * without them).  tr may be NULL (the default tree).  Errors: TM_EINVAL. */
 int tm_weights_footprint(const tm_graph* g, const tm_motif* mo, const tm_tree* tr, int32_t wide,
                          uint64_t* bytes);
