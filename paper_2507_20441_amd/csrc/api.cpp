@@ -794,11 +794,9 @@ extern "C" int tm_estimate_batch(tm_graph* const* g, const tm_motif* mo, const t
     }
     std::vector<int> hflags(n_jobs, 0);
     std::vector<u64> hW(n_jobs, 0);
-    TM_HIP(hipMemcpyAsync(hflags.data(), flags, n_jobs * sizeof(int), hipMemcpyDeviceToHost, st));
-    TM_HIP(hipMemcpyAsync(hW.data(), wdev, n_jobs * sizeof(u64), hipMemcpyDeviceToHost, st));
+    TM_HIP(read_back({{hflags.data(), flags, n_jobs * sizeof(int)}, {hW.data(), wdev, n_jobs * sizeof(u64)}}, st));
     TM_HIP(dev_free(flags, st));
     TM_HIP(dev_free(wdev, st));
-    TM_HIP(sync_stream(st));
     // jobs whose 64-bit build overflowed are rebuilt with the widening path
     for (int i = 0; i < n_jobs; ++i) {
         if (!ws[i]) continue;
@@ -1009,8 +1007,7 @@ extern "C" int tm_batch_plan_run(tm_batch_plan* p, void* stream, tm_result* out)
     TM_HIP(hipGraphLaunch(p->exec, st));
     std::vector<int> hflags(p->n);
     std::vector<u64> hW(p->n);
-    TM_HIP(hipMemcpyAsync(hflags.data(), p->flags, p->n * sizeof(int), hipMemcpyDeviceToHost, st));
-    TM_HIP(hipMemcpyAsync(hW.data(), p->wdev, p->n * sizeof(u64), hipMemcpyDeviceToHost, st));
+    TM_HIP(read_back({{hflags.data(), p->flags, p->n * sizeof(int)}, {hW.data(), p->wdev, p->n * sizeof(u64)}}, st));
     std::vector<JobSums> sums(p->n);
     TM_TRY(batch_capture_read(p->pass, st, sums.data()));
     for (int i = 0; i < p->n; ++i) {

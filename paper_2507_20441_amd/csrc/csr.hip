@@ -288,9 +288,7 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
     }
     int hflags[2];
     u64 hb[2];
-    TM_HIP(hipMemcpyAsync(hflags, flags, sizeof hflags, hipMemcpyDeviceToHost, st));
-    TM_HIP(hipMemcpyAsync(hb, tbounds, sizeof hb, hipMemcpyDeviceToHost, st));
-    TM_HIP(sync_stream(st));
+    TM_HIP(read_back({{hflags, flags, sizeof hflags}, {hb, tbounds, sizeof hb}}, st));
     if (hflags[0] & kBadRange) return tm_fail(TM_EINVAL, "graph: vertex id outside [0, %d)", n);
     if (hflags[0] & kSelfLoop) return tm_fail(TM_ESELFLOOP, "graph: self loop");
     const int64_t tmin = (int64_t)(hb[0] ^ 0x8000000000000000ull);
@@ -428,11 +426,10 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
     TM_HIP(dev_free(kb, st));
     TM_HIP(dev_free(va, st));
     TM_HIP(dev_free(vb, st));
-    TM_HIP(hipMemcpyAsync(hflags, flags, sizeof hflags, hipMemcpyDeviceToHost, st));
+    timer.stop();
+    TM_HIP(read_back({{hflags, flags, sizeof hflags}}, st));
     TM_HIP(dev_free(flags, st));
     TM_HIP(dev_free(tbounds, st));
-    timer.stop();
-    TM_HIP(sync_stream(st));
     timer.finish();
     if (hflags[0] & kDup) return tm_fail(TM_EDUP, "graph: duplicate (u, v, t) tuple");
     if (hflags[1]) return tm_fail(TM_EDEVICE, "graph: internal scan overflow");

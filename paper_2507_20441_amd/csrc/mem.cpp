@@ -7,6 +7,7 @@
 // been synchronised by the library (every entry point synchronises its stream
 // before it returns).  Memory goes back to HIP only when an allocation fails
 // (after a device synchronisation, so no queued work still uses it).
+#include <cstring>
 #include <mutex>
 #include <unordered_map>
 #include <vector>
@@ -27,6 +28,9 @@ constexpr int kMaxDevices = 64;
 std::mutex g_mu;
 std::vector<Block> g_free[kMaxDevices];
 std::unordered_map<void*, size_t> g_used;
+
+std::mutex g_stage_mu;
+std::vector<void*> g_stage_free;
 
 size_t size_class(size_t bytes) {
     if (bytes <= 4096) return (bytes + 255) & ~(size_t)255;
@@ -130,5 +134,54 @@ void dev_stream_synced(hipStream_t st) {
 hipError_t sync_stream(hipStream_t st) {
     hipError_t e = hipStreamSynchronize(st);
     if (e == hipSuccess) dev_stream_synced(st);
+    return e;
+}
+
+void* host_stage_acquire() {
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        if (!g_stage_free.empty()) {
+            void* p = g_stage_free.back();
+            g_stage_free.pop_back();
+            return p;
+        }
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, kHostStageBytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void host_stage_release(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    g_stage_free.push_back(p);
+}
+
+hipError_t read_back(const HostRead* r, int n, hipStream_t st) {
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) total += (r[i].bytes + 15) & ~(size_t)15;
+    unsigned char* stage = total <= kHostStageBytes ? static_cast<unsigned char*>(host_stage_acquire()) : nullptr;
+    hipError_t e = hipSuccess;
+    size_t off = 0;
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        if (r[i].bytes == 0) continue;
+        e = hipMemcpyAsync(stage ? stage + off : r[i].host, r[i].dev, r[i].bytes, hipMemcpyDeviceToHost, st);
+        off += (r[i].bytes + 15) & ~(size_t)15;
+    }
+    // the stream is waited for also after a failed enqueue: no copy into the
+    // staging block may still be in flight when it goes back to the list
+    const hipError_t es = sync_stream(st);
+    if (e == hipSuccess) e = es;
+    if (stage) {
+        off = 0;
+        for (int i = 0; i < n && e == hipSuccess; ++i) {
+            if (r[i].bytes) std::memcpy(r[i].host, stage + off, r[i].bytes);
+            off += (r[i].bytes + 15) & ~(size_t)15;
+        }
+        host_stage_release(stage);
+    }
     return e;
 }

@@ -1224,9 +1224,7 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
         TM_HIP(hipGetLastError());
         t_reduce.stop();
         Partial hc;
-        TM_HIP(hipMemcpyAsync(&hc, parts + blocks, sizeof hc, hipMemcpyDeviceToHost, st));
-        TM_HIP(hipMemcpyAsync(&hovf, ovf, sizeof hovf, hipMemcpyDeviceToHost, st));
-        TM_HIP(sync_stream(st));
+        TM_HIP(read_back({{&hc, parts + blocks, sizeof hc}, {&hovf, ovf, sizeof hovf}}, st));
         t_roots.finish();
         t_sample.finish();
         t_reduce.finish();
@@ -1510,9 +1508,7 @@ void group_free(Group& G, hipStream_t st) {
 int group_read(Group& G, const std::vector<int>& act, hipStream_t st, JobSums* out) {
     std::vector<Partial> hp(G.na);
     int hovf = 0;
-    TM_HIP(hipMemcpyAsync(hp.data(), G.jparts, G.na * sizeof(Partial), hipMemcpyDeviceToHost, st));
-    TM_HIP(hipMemcpyAsync(&hovf, G.ovf, sizeof(int), hipMemcpyDeviceToHost, st));
-    TM_HIP(sync_stream(st));
+    TM_HIP(read_back({{hp.data(), G.jparts, G.na * sizeof(Partial)}, {&hovf, G.ovf, sizeof(int)}}, st));
     if (hovf & 2) return tm_fail(TM_EDEVICE, "batch: inconsistent weight tables");
     for (int y = 0; y < G.na; ++y) {
         const Partial& h = hp[y];
@@ -1723,11 +1719,16 @@ int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hip
     const bool sorted = chunk >= kSortMin;
     const int blocks = (int)std::min<u64>((chunk + kBlock - 1) / kBlock, chunk >= ((u64)1 << 25) ? 8192 : 2560);
     const int key_bits = bits_of(2 * (u64)w->g->m - 1);
+    // per chunk: every member's reduced sums (after the per-block partials)
+    // and flags (ovf[0] for the shared root pass and sort, ovf[1 + f] for
+    // member f), read back together
+    std::vector<Partial> hp(n);
+    std::vector<int> hov(n + 1);
     Partial* parts = nullptr;
     int* ovf = nullptr;
     uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
-    TM_HIP(dev_alloc((void**)&parts, (size_t)(blocks + 1) * sizeof(Partial), st));
-    TM_HIP(dev_alloc((void**)&ovf, sizeof(int), st));
+    TM_HIP(dev_alloc((void**)&parts, (size_t)(blocks + n) * sizeof(Partial), st));
+    TM_HIP(dev_alloc((void**)&ovf, (size_t)(n + 1) * sizeof(int), st));
     if (sorted) {
         TM_HIP(dev_alloc((void**)&k0, chunk * sizeof(uint32_t), st));
         TM_HIP(dev_alloc((void**)&v0, chunk * sizeof(uint32_t), st));
@@ -1742,17 +1743,19 @@ int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hip
             args[f].count = cnt;
             args[f].recs = nullptr;
             args[f].parts = parts;
-            args[f].ovf = ovf;
+            args[f].ovf = ovf + 1 + f;
         }
-        rc = fill_u32(ovf, 1, 0u, st);
+        rc = fill_u32(ovf, n + 1, 0u, st);
         if (rc != TM_OK) break;
         const dim3 grid((unsigned)std::min<u64>((cnt + kBlock - 1) / kBlock, (u64)blocks));
         if (sorted) {
             const dim3 rgrid((unsigned)std::min<u64>((cnt + kBlock - 1) / kBlock, 8192));
+            SampleArgs ra = args[0];
+            ra.ovf = ovf;
             if (w->wide)
-                hipLaunchKernelGGL(root_kernel<u128>, rgrid, dim3(kBlock), lds, st, args[0], k0, v0);
+                hipLaunchKernelGGL(root_kernel<u128>, rgrid, dim3(kBlock), lds, st, ra, k0, v0);
             else
-                hipLaunchKernelGGL(root_kernel<u64>, rgrid, dim3(kBlock), lds, st, args[0], k0, v0);
+                hipLaunchKernelGGL(root_kernel<u64>, rgrid, dim3(kBlock), lds, st, ra, k0, v0);
             if (hipGetLastError() != hipSuccess) { rc = tm_fail(TM_EDEVICE, "family: launch"); break; }
             uint32_t *ks, *vs;
             rc = radix_sort_pairs<uint32_t>(k0, v0, k1, v1, (int64_t)cnt, root_sort_lo_bit(key_bits), key_bits, &ks,
@@ -1767,15 +1770,19 @@ int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hip
             launch_any<false>(w->wide, sorted, grid, sorted ? 0 : lds, st, args[f]);
             if (hipGetLastError() != hipSuccess) { rc = tm_fail(TM_EDEVICE, "family: launch"); break; }
             hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const Partial*)parts, (int)grid.x,
-                               parts + blocks);
-            Partial h;
-            int hovf = 0;
-            if (hipMemcpyAsync(&h, parts + blocks, sizeof h, hipMemcpyDeviceToHost, st) != hipSuccess ||
-                hipMemcpyAsync(&hovf, ovf, sizeof hovf, hipMemcpyDeviceToHost, st) != hipSuccess ||
-                sync_stream(st) != hipSuccess) {
-                rc = tm_fail(TM_EDEVICE, "family: copy");
-                break;
-            }
+                               parts + blocks + f);
+            if (hipGetLastError() != hipSuccess) rc = tm_fail(TM_EDEVICE, "family: launch");
+        }
+        if (rc != TM_OK) break;
+        if (read_back({{hp.data(), parts + blocks, (size_t)n * sizeof(Partial)},
+                       {hov.data(), ovf, (size_t)(n + 1) * sizeof(int)}},
+                      st) != hipSuccess) {
+            rc = tm_fail(TM_EDEVICE, "family: copy");
+            break;
+        }
+        for (int f = 0; f < n && rc == TM_OK; ++f) {
+            const Partial& h = hp[f];
+            const int hovf = hov[0] | hov[1 + f];
             if (hovf & 2) {
                 rc = tm_fail(TM_EDEVICE, "family: inconsistent weight tables");
                 break;

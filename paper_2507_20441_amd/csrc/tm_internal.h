@@ -2,6 +2,7 @@
 // error plumbing and the launchers each translation unit provides.
 #pragma once
 
+#include <initializer_list>
 #include <string>
 #include <utility>
 #include <vector>
@@ -59,6 +60,29 @@ void dev_stream_synced(hipStream_t st);
 hipError_t sync_stream(hipStream_t st);
 // Set n_words 32-bit words to v with a kernel (capturable, unlike a memset).
 int fill_u32(void* p, int64_t n_words, uint32_t v, hipStream_t st);
+
+// Pinned host blocks of kHostStageBytes for reading a few device words back.
+// A copy into pageable memory waits for the device before it returns; copies
+// into pinned memory do not, so the reads that end a call share one
+// synchronisation.  Blocks come from a process-wide list (null when pinned
+// memory cannot be had) and are never given back to HIP.
+constexpr size_t kHostStageBytes = 16384;
+void* host_stage_acquire();
+void host_stage_release(void* p);
+
+// One device-to-host copy of read_back.
+struct HostRead {
+    void* host;
+    const void* dev;
+    size_t bytes;
+};
+// The n copies, in stream order on st, then one synchronisation of st (as
+// sync_stream); through one pinned block when they fit in it, else straight
+// into the destinations.
+hipError_t read_back(const HostRead* r, int n, hipStream_t st);
+inline hipError_t read_back(std::initializer_list<HostRead> r, hipStream_t st) {
+    return read_back(r.begin(), (int)r.size(), st);
+}
 
 // ---------------------------------------------------------------------------
 // Graph handle.

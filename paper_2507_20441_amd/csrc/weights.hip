@@ -523,19 +523,17 @@ int weights_build(tm_weights* w, hipStream_t st) {
         rc = wide ? build_typed<u128>(w, st, ovf) : build_typed<u64>(w, st, ovf, per_level);
         if (rc != TM_OK) break;
         u64 hW[2] = {0, 0};
-        TM_HIP(hipMemcpyAsync(&h, ovf, sizeof(int), hipMemcpyDeviceToHost, st));
+        timer.stop();
         // a 64-bit build that stopped at an overflowing level has no W yet
-        if (w->cumW)
-            TM_HIP(hipMemcpyAsync(hW, static_cast<const unsigned char*>(w->cumW) + w->q * (wide ? 16 : 8),
-                                  wide ? 16 : 8, hipMemcpyDeviceToHost, st));
-        TM_HIP(sync_stream(st));
+        const size_t wsz = w->cumW ? (wide ? 16 : 8) : 0;
+        TM_HIP(read_back({{&h, ovf, sizeof(int)},
+                          {hW, static_cast<const unsigned char*>(w->cumW) + w->q * (wide ? 16 : 8), wsz}},
+                         st));
         w->W = ((u128)hW[1] << 64) | hW[0];
         if (h == 0) break;
         if (wide) rc = tm_fail(TM_EOVERFLOW, "weights: a weight or W reaches 2^128");
     }
     TM_HIP(dev_free(ovf, st));
-    timer.stop();
-    TM_HIP(sync_stream(st));
     timer.finish();
     if (rc != TM_OK) clear_tables(w);
     return rc;
