@@ -412,6 +412,11 @@ typedef struct {
 
 /* Turn stage timing on (1) or off (0, the default); process-wide. */
 void tm_profile_enable(int on);
+/* Which stages are timed while timing is on: bit s for stage s (default all
+ * of them; other bits are ignored).  Each timed stage records two events on
+ * its stream; timing fewer stages leaves fewer of them between the kernels.
+ * Process-wide. */
+void tm_profile_stages(uint32_t mask);
 /* Copy the accumulated times; reset = 1 clears them afterwards. */
 int tm_profile_read(tm_profile* out, int reset);
 

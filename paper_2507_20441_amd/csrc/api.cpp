@@ -23,16 +23,17 @@ int tm_fail(int code, const char* fmt, ...) {
 
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
+static uint32_t g_prof_mask = (1u << TM_N_STAGES) - 1;
 static tm_profile g_prof = {};
 
 static thread_local bool t_prof_suspended = false;
 
 void prof_suspend(bool on) { t_prof_suspended = on; }
 
-bool prof_enabled() {
-    if (t_prof_suspended) return false;
+bool prof_enabled(int stage) {
+    if (t_prof_suspended || stage < 0 || stage >= TM_N_STAGES) return false;
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    return g_prof_on;
+    return g_prof_on && ((g_prof_mask >> stage) & 1u);
 }
 
 void prof_add(int stage, double ms) {
@@ -45,6 +46,11 @@ void prof_add(int stage, double ms) {
 extern "C" void tm_profile_enable(int on) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = on != 0;
+}
+
+extern "C" void tm_profile_stages(uint32_t mask) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_mask = mask & ((1u << TM_N_STAGES) - 1);
 }
 
 extern "C" int tm_profile_read(tm_profile* out, int reset) {

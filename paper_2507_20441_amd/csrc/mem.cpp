@@ -32,6 +32,9 @@ std::unordered_map<void*, size_t> g_used;
 std::mutex g_stage_mu;
 std::vector<void*> g_stage_free;
 
+std::mutex g_ev_mu;
+std::vector<hipEvent_t> g_ev_free[kMaxDevices];
+
 size_t size_class(size_t bytes) {
     if (bytes <= 4096) return (bytes + 255) & ~(size_t)255;
     // steps of 1/8 of the enclosing power of two
@@ -184,4 +187,29 @@ hipError_t read_back(const HostRead* r, int n, hipStream_t st) {
         host_stage_release(stage);
     }
     return e;
+}
+
+hipEvent_t timing_event_acquire(int* dev) {
+    *dev = device_index();
+    {
+        std::lock_guard<std::mutex> lk(g_ev_mu);
+        std::vector<hipEvent_t>& fl = g_ev_free[*dev];
+        if (!fl.empty()) {
+            hipEvent_t e = fl.back();
+            fl.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+void timing_event_release(hipEvent_t e, int dev) {
+    if (!e) return;
+    std::lock_guard<std::mutex> lk(g_ev_mu);
+    g_ev_free[dev].push_back(e);
 }

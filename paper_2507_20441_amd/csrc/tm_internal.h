@@ -264,21 +264,34 @@ void finish_result(tm_result* r);
 // ---------------------------------------------------------------------------
 // Stage timing with HIP events on the call's stream (tm_profile_enable).
 // ---------------------------------------------------------------------------
-bool prof_enabled();
+bool prof_enabled(int stage);
 void prof_add(int stage, double ms);
 // Stage timing off on this thread (while recording a graph).
 void prof_suspend(bool on);
 
+// Timing events of the current device from a list kept per device (creating
+// and destroying two for every timed stage costs more than recording them).
+// Null when no event can be created; *dev receives the device to release on.
+hipEvent_t timing_event_acquire(int* dev);
+void timing_event_release(hipEvent_t e, int dev);
+
 struct StageTimer {
     hipEvent_t a = nullptr, b = nullptr;
     hipStream_t st = nullptr;
-    int stage = 0;
+    int stage = 0, dev = 0;
     bool on = false;
+    StageTimer() = default;
+    StageTimer(const StageTimer&) = delete;
+    StageTimer& operator=(const StageTimer&) = delete;
     void start(int stage_, hipStream_t st_) {
         stage = stage_;
         st = st_;
-        on = prof_enabled() && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
+        if (!prof_enabled(stage)) return;
+        a = timing_event_acquire(&dev);
+        b = a ? timing_event_acquire(&dev) : nullptr;
+        on = a && b;
         if (on) (void)hipEventRecord(a, st);
+        else release();
     }
     void stop() {
         if (on) (void)hipEventRecord(b, st);
@@ -289,14 +302,15 @@ struct StageTimer {
         float ms = 0.f;
         if (hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess)
             prof_add(stage, ms);
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
-        on = false;
+        release();
     }
-    ~StageTimer() {
-        if (on) {
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
-        }
+    ~StageTimer() { release(); }
+
+   private:
+    void release() {
+        if (a) timing_event_release(a, dev);
+        if (b) timing_event_release(b, dev);
+        a = b = nullptr;
+        on = false;
     }
 };

@@ -140,6 +140,8 @@ def lib():
         L.tm_batch_plan_destroy.restype = None
         L.tm_profile_enable.argtypes = [C.c_int]
         L.tm_profile_enable.restype = None
+        L.tm_profile_stages.argtypes = [C.c_uint32]
+        L.tm_profile_stages.restype = None
         L.tm_profile_read.argtypes = [C.POINTER(Profile), C.c_int]
         L.tm_sample_model_bytes.argtypes = [vp, u64, u64, u64, vp, C.POINTER(u64)]
         L.tm_weights_footprint.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), i32, C.POINTER(u64)]
@@ -415,6 +417,12 @@ class Server:
 def profile_enable(on=True):
     """Stage timing with HIP events (tm_profile_enable)."""
     lib().tm_profile_enable(1 if on else 0)
+
+
+def profile_stages(stages=None):
+    """Which stages are timed (tm_profile_stages): names from STAGES, or None for all."""
+    mask = (1 << len(STAGES)) - 1 if stages is None else sum(1 << STAGES.index(s) for s in stages)
+    lib().tm_profile_stages(mask)
 
 
 def profile_read(reset=False) -> dict:

@@ -318,3 +318,48 @@ def test_constraint_modes_match_oracle(T, mode, name, edges, delta):
     # the root-sorted launch shape (2^16 samples or more)
     check_prep(T, og, tg, edges, delta, O.default_tree(O.make_motif(edges, delta)), seeds=(5,), k=70000,
                constraints=mode)
+
+
+# ---------------------------------------------------------------------------
+# Stage timing
+# ---------------------------------------------------------------------------
+def test_stage_timing_mask(T):
+    """Only the stages selected with tm_profile_stages record time; the
+    sums are the same with timing on or off."""
+    say("stage timing mask")
+    g = W.small_graph(5000, 3, n=300, span=20000)
+    mo = T.make_motif(W.MOTIFS["4cycle"], 600)
+    k = 1 << 17  # large enough for the root-sorted path (its roots stage)
+
+    def run():
+        tg = T.Graph(g.src, g.dst, g.t, g.n)
+        w = T.Weights(tg, mo)
+        r, _ = w.sample(7, k)
+        out = (r.acc2.value, r.n_valid)
+        w.close()
+        tg.close()
+        return out
+
+    T.profile_read(reset=True)
+    try:
+        plain = run()
+        T.profile_stages(["sample"])
+        T.profile_enable(True)
+        only = run()
+        T.profile_enable(False)
+        p = dict(zip(T.STAGES, T.profile_read(reset=True)["launches"]))
+        assert p["sample"] == 1, p
+        assert all(p[s] == 0 for s in T.STAGES if s != "sample"), p
+        T.profile_stages(None)
+        T.profile_enable(True)
+        every = run()
+        T.profile_enable(False)
+        prof = T.profile_read(reset=True)
+        p = dict(zip(T.STAGES, prof["launches"]))
+        assert all(p[s] == 1 for s in T.STAGES), p
+        assert all(ms > 0 for ms in prof["ms"]), prof
+        assert plain == only == every
+    finally:
+        T.profile_enable(False)
+        T.profile_stages(None)
+        T.profile_read(reset=True)
