@@ -204,8 +204,9 @@ constexpr u64 kWinMaxBytes = (u64)32 << 30;
 u64 weights_window_bytes(const HostPlan& P, int64_t m);
 bool weights_keep_windows(const HostPlan& P, int64_t m);
 u64 weights_build_extra(int64_t m, bool wide);
-// Bits of the root guide for a graph of m edges: about two (interval, edge)
-// pairs per bucket (eight when lean), between 2^8 and 2^23 buckets.
+// Bits of the root guide for a graph of m edges: about one (interval, edge)
+// pair per bucket (lean sets: about eight), between 2^8 and 2^23 buckets.
+constexpr int kGuideExtraBits = 1;
 int guide_bits_for(int64_t m, bool lean = false);
 
 // Exact sums over a range of samples of one job.  Sums over disjoint ranges

@@ -290,6 +290,44 @@ guide_kernel(const W* cum, const void* qc0, const void* qc1, const int32_t* ilo,
     guide[b].key = (u64)((uint32_t)tpos0[e] * 2u + (uint32_t)(i & 1));
 }
 
+// The guide of gb bits in two steps: every 2^kGuideStepBits-th entry (a
+// guide of gb - kGuideStepBits bits, guide_kernel), then every entry between
+// two of those by the search they bound, as a root draw bounds its search by
+// two guide entries (the pair is monotone in the draw).
+constexpr int kGuideStepBits = 4;
+
+template <typename W>
+__global__ void __launch_bounds__(kBlock)
+guide_fill_kernel(const W* cum, const void* qc0, const void* qc1, const int32_t* ilo, const int32_t* ihi,
+                  const W* ioff, int64_t q, const int32_t* tpos0, int gb, const RootGuide* coarse,
+                  RootGuide* guide) {
+    const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t B = (int64_t)1 << gb;
+    if (b > B) return;
+    const int64_t c = b >> kGuideStepBits;
+    // entry B (the largest draw) and the multiples of the step are coarse entries
+    if ((b & ((1 << kGuideStepBits) - 1)) == 0) {
+        guide[b] = coarse[c];
+        return;
+    }
+    const RootGuide g0 = coarse[c], g1 = coarse[c + 1];
+    if (g0.pair == g1.pair) {
+        guide[b] = g0;
+        return;
+    }
+    X128 X;
+    X.lo = 0;
+    X.hi = (u64)b << (64 - gb);
+    const W r = scale(X, cum[q]);
+    const void* qc[2] = {qc0, qc1};
+    int32_t i = 0, e = 0;
+    if (!root_pair<W>(cum, qc, ilo, ihi, q, r, (int32_t)(g0.pair >> 32), (int32_t)(g1.pair >> 32),
+                      (int32_t)(uint32_t)g0.pair, (int32_t)(uint32_t)g1.pair, i, e, nullptr, ioff))
+        i = e = 0;
+    guide[b].pair = ((u64)(uint32_t)i << 32) | (uint32_t)e;
+    guide[b].key = (u64)((uint32_t)tpos0[e] * 2u + (uint32_t)(i & 1));
+}
+
 // ioff[i] = cum[i] - qc_{i mod 2}[lo_i], modulo the word size.
 template <typename W>
 __global__ void __launch_bounds__(kBlock)
@@ -464,11 +502,19 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
     TM_HIP(hipGetLastError());
     w->ioff = ioff;
     w->guide_bits = guide_bits_for(m, w->lean);
-    const int64_t nb = ((int64_t)1 << w->guide_bits) + 1;
+    const int gc = w->guide_bits - kGuideStepBits;
+    const int64_t nb = ((int64_t)1 << w->guide_bits) + 1, nc = ((int64_t)1 << gc) + 1;
     TM_TRY(arena_alloc(w->arena, &w->guide, (size_t)nb));
-    hipLaunchKernelGGL((guide_kernel<W>), dim3(grid_for(nb)), dim3(kBlock), 0, st, (const W*)cum, w->qc[0],
-                       w->qc[1], w->ilo, w->ihi, w->q, w->g->d.tpos[P.root_dir], w->guide_bits, w->guide);
+    RootGuide* coarse = nullptr;
+    TM_HIP(dev_alloc((void**)&coarse, (size_t)nc * sizeof(RootGuide), st));
+    hipLaunchKernelGGL((guide_kernel<W>), dim3(grid_for(nc)), dim3(kBlock), 0, st, (const W*)cum, w->qc[0],
+                       w->qc[1], w->ilo, w->ihi, w->q, w->g->d.tpos[P.root_dir], gc, coarse);
     TM_HIP(hipGetLastError());
+    hipLaunchKernelGGL((guide_fill_kernel<W>), dim3(grid_for(nb)), dim3(kBlock), 0, st, (const W*)cum,
+                       w->qc[0], w->qc[1], w->ilo, w->ihi, (const W*)ioff, w->q, w->g->d.tpos[P.root_dir],
+                       w->guide_bits, (const RootGuide*)coarse, w->guide);
+    TM_HIP(hipGetLastError());
+    TM_HIP(dev_free(coarse, st));
     return TM_OK;
 }
 
@@ -589,13 +635,20 @@ bool weights_keep_windows(const HostPlan& P, int64_t m) {
 int guide_bits_for(int64_t m, bool lean) {
     int b = 0;
     while (b < 62 && ((int64_t)1 << (b + 1)) <= m) ++b;  // floor(log2 m): ~2m pairs, ~2 per bucket
-    if (lean) b -= 2;
+    if (lean) {
+        b -= 2;
+        return b < 8 ? 8 : (b > 23 ? 23 : b);
+    }
+    b += kGuideExtraBits;
     return b < 8 ? 8 : (b > 23 ? 23 : b);
 }
 
 u64 weights_build_extra(int64_t m, bool wide) {
-    // one slot's values and a two-pass level's products, per parity
-    return m <= 0 ? 0 : 4 * ((((u64)m * (wide ? 16 : 8)) + 255) & ~(u64)255);
+    // one slot's values and a two-pass level's products, per parity; the
+    // coarse root guide
+    if (m <= 0) return 0;
+    const u64 coarse = (((u64)1 << (guide_bits_for(m) - kGuideStepBits)) + 1) * sizeof(RootGuide);
+    return 4 * ((((u64)m * (wide ? 16 : 8)) + 255) & ~(u64)255) + ((coarse + 255) & ~(u64)255);
 }
 
 int weights_enqueue(tm_weights* w, hipStream_t st, int* ovf) {
