@@ -20,7 +20,9 @@
 #include <algorithm>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "tm_primitives.h"
 
@@ -795,36 +797,71 @@ __global__ void fill_undrawn_kernel(tm_sample_rec* recs, u64 count) {
     out.m_phi.lo = out.m_phi.hi = 0;
 }
 
+using SampleKernel = void (*)(SampleArgs);
+
 template <typename W, bool kCount, bool kSorted>
-void launch_sample(dim3 grid, size_t lds, hipStream_t st, const SampleArgs& a) {
+SampleKernel sample_variant(const SampleArgs& a) {
     if constexpr (kSorted) {
-        if (a.has_win && !a.general_runs && a.nt <= 4 && a.k <= 5) {
-            hipLaunchKernelGGL((sample_kernel<W, kCount, false, true, true, true>), grid, dim3(kBlock), lds, st, a);
-            return;
-        }
-        if (a.has_win) {
-            if (a.general_runs)
-                hipLaunchKernelGGL((sample_kernel<W, kCount, true, true, true>), grid, dim3(kBlock), lds, st, a);
-            else
-                hipLaunchKernelGGL((sample_kernel<W, kCount, false, true, true>), grid, dim3(kBlock), lds, st, a);
-            return;
-        }
+        if (a.has_win && !a.general_runs && a.nt <= 4 && a.k <= 5)
+            return sample_kernel<W, kCount, false, true, true, true>;
+        if (a.has_win)
+            return a.general_runs ? sample_kernel<W, kCount, true, true, true>
+                                  : sample_kernel<W, kCount, false, true, true>;
     }
-    if (a.general_runs)
-        hipLaunchKernelGGL((sample_kernel<W, kCount, true, kSorted, false>), grid, dim3(kBlock), lds, st, a);
-    else
-        hipLaunchKernelGGL((sample_kernel<W, kCount, false, kSorted, false>), grid, dim3(kBlock), lds, st, a);
+    return a.general_runs ? sample_kernel<W, kCount, true, kSorted, false>
+                          : sample_kernel<W, kCount, false, kSorted, false>;
 }
 
-template <bool kCount>
-void launch_any(bool wide, bool sorted, dim3 grid, size_t lds, hipStream_t st, const SampleArgs& a) {
-    if (wide) {
-        if (sorted) launch_sample<u128, kCount, true>(grid, lds, st, a);
-        else launch_sample<u128, kCount, false>(grid, lds, st, a);
-    } else {
-        if (sorted) launch_sample<u64, kCount, true>(grid, lds, st, a);
-        else launch_sample<u64, kCount, false>(grid, lds, st, a);
+// The sampling kernel for a's plan and tables: counting variant or not,
+// 64- or 128-bit weights, root-sorted order or not.
+SampleKernel pick_sample(bool count, bool wide, bool sorted, const SampleArgs& a) {
+    if (count) {
+        if (wide) return sorted ? sample_variant<u128, true, true>(a) : sample_variant<u128, true, false>(a);
+        return sorted ? sample_variant<u64, true, true>(a) : sample_variant<u64, true, false>(a);
     }
+    if (wide) return sorted ? sample_variant<u128, false, true>(a) : sample_variant<u128, false, false>(a);
+    return sorted ? sample_variant<u64, false, true>(a) : sample_variant<u64, false, false>(a);
+}
+
+hipError_t launch_sample(SampleKernel k, dim3 grid, size_t lds, hipStream_t st, const SampleArgs& a) {
+    void* args[] = {const_cast<SampleArgs*>(&a)};
+    return hipLaunchKernel(reinterpret_cast<const void*>(k), grid, dim3(kBlock), args, lds, st);
+}
+
+// Workgroups of a grid-stride sampling launch over n samples: whole rounds of
+// the workgroups the chip holds at once for kernel k, since a partial last
+// round leaves CUs idle while the rest finish; two rounds, six for runs of
+// 2^25 samples and more (the partials' reduction is then negligible).
+unsigned sample_grid(SampleKernel k, size_t lds, u64 n) {
+    struct Occ {
+        SampleKernel k;
+        size_t lds;
+        int dev, resident;
+    };
+    static std::mutex mu;
+    static std::vector<Occ> seen;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    int resident = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (const Occ& o : seen)
+            if (o.k == k && o.lds == lds && o.dev == dev) resident = o.resident;
+    }
+    if (resident == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), kBlock, lds) !=
+                hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            per_cu = 0;
+        }
+        resident = per_cu > 0 && cus > 0 ? per_cu * cus : 1024;
+        std::lock_guard<std::mutex> lk(mu);
+        seen.push_back(Occ{k, lds, dev, resident});
+    }
+    const u64 rounds = n >= ((u64)1 << 25) ? 6 : 2;
+    return (unsigned)std::max<u64>(1, std::min<u64>((n + kBlock - 1) / kBlock, rounds * (u64)resident));
 }
 
 // Samples per chunk (sort keys and offsets are 32-bit), and the smallest
@@ -1167,10 +1204,10 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
     a.key_base = 0;
     const bool sorted = count >= kSortMin;
     const u64 chunk = std::min<u64>(count, kChunk);
-    // grid-stride lanes: 2560 workgroups fill the chip about twice over and
-    // leave that many partials for the one-workgroup reduction; runs of 2^25
-    // samples and more keep 8192 (the reduction is then negligible)
-    const int blocks = (int)std::min<u64>((chunk + kBlock - 1) / kBlock, chunk >= ((u64)1 << 25) ? 8192 : 2560);
+    // the sorted variant does not search the interval prefix (no LDS copy)
+    const SampleKernel kfn = pick_sample(model_bytes != nullptr, w->wide, sorted, a);
+    const size_t klds = sorted ? 0 : lds;
+    const int blocks = (int)sample_grid(kfn, klds, chunk);
     const int key_bits = bits_of(2 * (u64)w->g->m - 1);
     Partial* parts = nullptr;
     int* ovf = nullptr;
@@ -1213,10 +1250,7 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
             t_roots.stop();
         }
         if (!model_bytes) t_sample.start(TM_STAGE_SAMPLE, st);
-        // the sorted variant does not search the interval prefix
-        if (model_bytes) launch_any<true>(w->wide, sorted, grid, sorted ? 0 : lds, st, a);
-        else launch_any<false>(w->wide, sorted, grid, sorted ? 0 : lds, st, a);
-        TM_HIP(hipGetLastError());
+        TM_HIP(launch_sample(kfn, grid, klds, st, a));
         t_sample.stop();
         if (!model_bytes) t_reduce.start(TM_STAGE_REDUCE, st);
         hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const Partial*)parts,
@@ -1717,7 +1751,16 @@ int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hip
     // edges; the tree's validation counts come from the first member's pass
     const u64 chunk = std::min<u64>(k, kChunk);
     const bool sorted = chunk >= kSortMin;
-    const int blocks = (int)std::min<u64>((chunk + kBlock - 1) / kBlock, chunk >= ((u64)1 << 25) ? 8192 : 2560);
+    // each member's kernel and grid; the per-block partials of the widest
+    // grid come first in parts, the members' reduced sums after them
+    std::vector<SampleKernel> kfn(n);
+    std::vector<int> fblocks(n);
+    int blocks = 1;
+    for (int f = 0; f < n; ++f) {
+        kfn[f] = pick_sample(false, w->wide, sorted, args[f]);
+        fblocks[f] = (int)sample_grid(kfn[f], sorted ? 0 : lds, chunk);
+        blocks = std::max(blocks, fblocks[f]);
+    }
     const int key_bits = bits_of(2 * (u64)w->g->m - 1);
     // per chunk: every member's reduced sums (after the per-block partials)
     // and flags (ovf[0] for the shared root pass and sort, ovf[1 + f] for
@@ -1747,7 +1790,6 @@ int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hip
         }
         rc = fill_u32(ovf, n + 1, 0u, st);
         if (rc != TM_OK) break;
-        const dim3 grid((unsigned)std::min<u64>((cnt + kBlock - 1) / kBlock, (u64)blocks));
         if (sorted) {
             const dim3 rgrid((unsigned)std::min<u64>((cnt + kBlock - 1) / kBlock, 8192));
             SampleArgs ra = args[0];
@@ -1767,8 +1809,11 @@ int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hip
             }
         }
         for (int f = 0; f < n && rc == TM_OK; ++f) {
-            launch_any<false>(w->wide, sorted, grid, sorted ? 0 : lds, st, args[f]);
-            if (hipGetLastError() != hipSuccess) { rc = tm_fail(TM_EDEVICE, "family: launch"); break; }
+            const dim3 grid((unsigned)std::min<u64>((cnt + kBlock - 1) / kBlock, (u64)fblocks[f]));
+            if (launch_sample(kfn[f], grid, sorted ? 0 : lds, st, args[f]) != hipSuccess) {
+                rc = tm_fail(TM_EDEVICE, "family: launch");
+                break;
+            }
             hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const Partial*)parts, (int)grid.x,
                                parts + blocks + f);
             if (hipGetLastError() != hipSuccess) rc = tm_fail(TM_EDEVICE, "family: launch");
