@@ -389,15 +389,13 @@ __device__ __forceinline__ void block_reduce_write(Partial acc, Partial* out) {
 // the root key (T-order position of the root * 2 + interval parity).
 // Inconsistent tables give a harmless key and set bad.
 template <typename W>
-__device__ __forceinline__ bool draw_root(const SampleArgs& a, const W* cum, W Wtot, u64 j, int32_t& i,
-                                          int32_t& e0, u64* nb = nullptr, uint32_t* key = nullptr) {
-    const X128 X = draw_block(a.seed, j, 0);
+__device__ __forceinline__ bool draw_root_from(const SampleArgs& a, const W* cum, W Wtot, const X128& X,
+                                               const RootGuide& g0, const RootGuide& g1, int32_t& i,
+                                               int32_t& e0, u64* nb = nullptr, uint32_t* key = nullptr) {
     int32_t i0 = 0, i1 = (int32_t)a.q - 1, ea = -1, eb = 0x7fffffff;
     if (a.guide) {
         // the guide bucket of X bounds the pair between two guide entries;
         // equal ends leave one pair (the pair is monotone in X)
-        const u64 b = X.hi >> (64 - a.guide_bits);
-        const RootGuide g0 = a.guide[b], g1 = a.guide[b + 1];
         i0 = (int32_t)(g0.pair >> 32);
         ea = (int32_t)(uint32_t)g0.pair;
         i1 = (int32_t)(g1.pair >> 32);
@@ -421,16 +419,35 @@ __device__ __forceinline__ bool draw_root(const SampleArgs& a, const W* cum, W W
     return ok;
 }
 
+// The two guide entries around draw X (none without a guide).
+__device__ __forceinline__ void guide_pair(const SampleArgs& a, const X128& X, RootGuide& g0, RootGuide& g1) {
+    if (a.guide) {
+        const u64 b = X.hi >> (64 - a.guide_bits);
+        g0 = a.guide[b];
+        g1 = a.guide[b + 1];
+    } else {
+        g0.pair = g1.pair = g0.key = g1.key = 0;
+    }
+}
+
+template <typename W>
+__device__ __forceinline__ bool draw_root(const SampleArgs& a, const W* cum, W Wtot, u64 j, int32_t& i,
+                                          int32_t& e0, u64* nb = nullptr, uint32_t* key = nullptr) {
+    const X128 X = draw_block(a.seed, j, 0);
+    RootGuide g0, g1;
+    guide_pair(a, X, g0, g1);
+    return draw_root_from<W>(a, cum, Wtot, X, g0, g1, i, e0, nb, key);
+}
+
 // Draw 0 of sample a.j0 + r: the interval, then the center edge; returned as
 // the root key (T-order position of the root * 2 + interval parity).
 // Inconsistent tables give a harmless key and set bad.
 template <typename W>
-__device__ __forceinline__ uint32_t root_key(const SampleArgs& a, const W* cum, W Wtot, int32_t ncum,
-                                             u64 r, bool& bad) {
-    (void)ncum;
+__device__ __forceinline__ uint32_t root_key(const SampleArgs& a, const W* cum, W Wtot, const X128& X,
+                                             const RootGuide& g0, const RootGuide& g1, bool& bad) {
     int32_t i, e0;
     uint32_t key = ~0u;  // set by a one-pair guide bucket
-    if (!draw_root<W>(a, cum, Wtot, a.j0 + r, i, e0, nullptr, &key)) {
+    if (!draw_root_from<W>(a, cum, Wtot, X, g0, g1, i, e0, nullptr, &key)) {
         bad = true;
         return 0u;
     }
@@ -458,8 +475,19 @@ __global__ void __launch_bounds__(kBlock) root_kernel(SampleArgs a, uint32_t* ke
     bool bad = false;
     const u64 stride = (u64)gridDim.x * kBlock;
     (void)vals;  // the sort makes the sample offsets (0 .. count-1) itself
-    for (u64 r = (u64)blockIdx.x * kBlock + threadIdx.x; r < a.count; r += stride)
-        keys[r] = root_key<W>(a, cum, Wtot, ncum, r, bad);
+    // two draws per lane and step, both guide reads issued before either is
+    // used: the random guide reads are the kernel's latency
+    for (u64 r = (u64)blockIdx.x * kBlock + threadIdx.x; r < a.count; r += 2 * stride) {
+        const u64 r1 = r + stride;
+        const bool two = r1 < a.count;
+        const X128 X0 = draw_block(a.seed, a.j0 + r, 0);
+        const X128 X1 = draw_block(a.seed, a.j0 + (two ? r1 : r), 0);
+        RootGuide g00, g01, g10, g11;
+        guide_pair(a, X0, g00, g01);
+        guide_pair(a, X1, g10, g11);
+        keys[r] = root_key<W>(a, cum, Wtot, X0, g00, g01, bad);
+        if (two) keys[r1] = root_key<W>(a, cum, Wtot, X1, g10, g11, bad);
+    }
     if (bad) atomicOr(a.ovf, 2);
 }
 
@@ -1007,7 +1035,10 @@ batch_root_kernel(const SampleArgs* __restrict__ jobs, const Tile* __restrict__ 
         }
         const W* cum = a.cum_in_lds ? cumL : cumG;
         for (u64 r = T.begin + threadIdx.x; r < T.end; r += kBlock) {
-            keys[T.out + r] = a.key_base + root_key<W>(a, cum, Wtot, ncum, r, bad);
+            const X128 X = draw_block(a.seed, a.j0 + r, 0);
+            RootGuide g0, g1;
+            guide_pair(a, X, g0, g1);
+            keys[T.out + r] = a.key_base + root_key<W>(a, cum, Wtot, X, g0, g1, bad);
             vals[T.out + r] = (uint32_t)r;
         }
     }
