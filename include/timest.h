@@ -369,6 +369,7 @@ typedef struct {
     uint64_t cached_sets;
     double build_ms;  /* worker time in weight builds */
     double pass_ms;   /* worker time in sampling passes */
+    uint64_t pass_retries;  /* passes run again after the device ran out of memory */
 } tm_server_stats;
 
 /* Start a server on the current device.  opts may be NULL (defaults).

@@ -95,8 +95,9 @@ struct tm_server {
 
     // shared state (mu)
     std::mutex mu;
-    std::condition_variable cv_work, cv_build, cv_done;
+    std::condition_variable cv_work, cv_build, cv_done, cv_idle;
     bool stop = false;
+    bool building = false;  // the builder is inside a weight build (cv_idle when it leaves)
     std::vector<tm_graph*> graphs;
     std::deque<QueryPtr> arrivals;  // submitted, not yet looked up
     std::deque<QueryPtr> builds;    // waiting for their weight set
@@ -224,6 +225,7 @@ void tm_server::run_builder() {
         QueryPtr qp = std::move(*pick);
         builds.erase(pick);
         resident += qp->est_bytes + qp->extra_bytes;  // held while building
+        building = true;
         lk.unlock();
 
         tm_weights* w = new (std::nothrow) tm_weights();
@@ -249,6 +251,8 @@ void tm_server::run_builder() {
         }
         const std::string err = rc != TM_OK ? tm_last_error() : "";
         lk.lock();
+        building = false;
+        cv_idle.notify_all();
         resident -= qp->est_bytes + qp->extra_bytes;
         if (rc == TM_ENOMEM) {
             tm_weights_destroy(w);
@@ -329,8 +333,24 @@ void tm_server::pass() {
     }
     std::vector<JobSums> sums(pick.size());
     const Clock::time_point tp = Clock::now();
-    const int rc = batch_sample_pass(ws.data(), j0.data(), cnt.data(), seeds.data(), (int)pick.size(), st,
-                                     sums.data(), batch_config_now());
+    int rc = batch_sample_pass(ws.data(), j0.data(), cnt.data(), seeds.data(), (int)pick.size(), st, sums.data(),
+                               batch_config_now());
+    if (rc == TM_ENOMEM) {
+        // the device held more than the budget counts (a build's temporaries
+        // beyond its estimate, as in a 128-bit rebuild, or cached blocks):
+        // wait for the build in flight, give the cached blocks back and run
+        // the same pass once more
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_idle.wait(lk, [&] { return !building || stop; });
+        }
+        dev_cache_trim();
+        sums.assign(pick.size(), JobSums{});
+        rc = batch_sample_pass(ws.data(), j0.data(), cnt.data(), seeds.data(), (int)pick.size(), st, sums.data(),
+                               batch_config_now());
+        std::lock_guard<std::mutex> lk(mu);
+        ++stats.pass_retries;
+    }
     {
         std::lock_guard<std::mutex> lk(mu);
         ++stats.passes;
@@ -532,6 +552,7 @@ extern "C" void tm_server_destroy(tm_server* srv) {
     }
     srv->cv_work.notify_all();
     srv->cv_build.notify_all();
+    srv->cv_idle.notify_all();
     if (srv->builder.joinable()) srv->builder.join();
     if (srv->sampler.joinable()) srv->sampler.join();
     // everything unfinished is cancelled

@@ -68,7 +68,7 @@ class ServerStats(C.Structure):
     _fields_ = [(f, C.c_uint64) for f in (
         "submitted", "completed", "failed", "passes", "samples", "weight_builds", "weight_hits",
         "evictions", "admission_waits", "budget_bytes", "resident_bytes", "peak_bytes", "cached_sets")] + [
-        ("build_ms", C.c_double), ("pass_ms", C.c_double)]
+        ("build_ms", C.c_double), ("pass_ms", C.c_double), ("pass_retries", C.c_uint64)]
 
     def as_dict(self):
         return {f: (round(getattr(self, f), 3) if t is C.c_double else int(getattr(self, f)))
