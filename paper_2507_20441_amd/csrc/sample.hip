@@ -861,6 +861,10 @@ hipError_t launch_sample(SampleKernel k, dim3 grid, size_t lds, hipStream_t st, 
 // round leaves CUs idle while the rest finish; two rounds, six for runs of
 // 2^25 samples and more (the partials' reduction is then negligible).
 unsigned sample_grid(SampleKernel k, size_t lds, u64 n) {
+    // a grid of at most one workgroup per CU is never more than one round
+    // (the unsorted runs, below 2^16 samples, all stay there)
+    const u64 need = (n + kBlock - 1) / kBlock;
+    if (need <= 256) return (unsigned)std::max<u64>(1, need);
     struct Occ {
         SampleKernel k;
         size_t lds;
@@ -889,7 +893,7 @@ unsigned sample_grid(SampleKernel k, size_t lds, u64 n) {
         seen.push_back(Occ{k, lds, dev, resident});
     }
     const u64 rounds = n >= ((u64)1 << 25) ? 6 : 2;
-    return (unsigned)std::max<u64>(1, std::min<u64>((n + kBlock - 1) / kBlock, rounds * (u64)resident));
+    return (unsigned)std::min<u64>(need, rounds * (u64)resident);
 }
 
 // Samples per chunk (sort keys and offsets are 32-bit), and the smallest
