@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
-STAGES = ["graph", "weights", "sample", "reduce", "roots"]
+STAGES = ["graph", "weights", "sample", "reduce", "roots", "levels"]
 
 
 def log(*a):
@@ -109,7 +109,7 @@ def main():
     L.tm_profile_enable.restype = None
 
     class Profile(C.Structure):
-        _fields_ = [("ms", C.c_double * 5), ("launches", C.c_uint64 * 5)]
+        _fields_ = [("ms", C.c_double * len(STAGES)), ("launches", C.c_uint64 * len(STAGES))]
 
     L.tm_profile_read.argtypes = [C.POINTER(Profile), C.c_int]
     L.tm_sample_model_bytes.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64,
@@ -176,7 +176,8 @@ def main():
     torch.cuda.synchronize()
     L.tm_profile_enable(0)
     L.tm_profile_read(C.byref(prof), 1)
-    stage_ms = {STAGES[i]: prof.ms[i] / args.steps for i in range(5)}
+    stage_ms = {STAGES[i]: prof.ms[i] / args.steps for i in range(len(STAGES))}
+    level_launches = prof.launches[STAGES.index("levels")] / args.steps
     log("stage ms per step", stage_ms)
 
     # Access-model bytes of the sampling kernel's launches in one step
@@ -195,21 +196,32 @@ def main():
                               rel_ci95=(1.96 * se / est) if est else None, valid=nvalid, W=Wv,
                               model_bytes=b.value))
         Wt.close()
+    # ... and of the level kernels of one step's weight builds
+    level_bytes = sum(T.weights_model_bytes(Gm, mo) for _, mo in motifs)
     Gm.close()
     achieved = model_bytes / (sample_ms * 1e-3) / 1e9 if sample_ms > 0 else 0.0
     # counter-measured bytes, valid only for the kernel source they were taken on
-    traffic = None
+    traffic = level_traffic = None
     if os.path.exists(args.traffic):
         try:
             tr = json.load(open(args.traffic))
             if tr.get("source_sha") == kernel_source_sha():
                 traffic = tr.get("hbm_bytes_per_launch")
+            if tr.get("level_source_sha") == level_source_sha():
+                level_traffic = tr.get("kernels", {}).get("level_kernel", {}).get("hbm_bytes_per_launch")
         except (OSError, ValueError):
-            traffic = None
+            traffic = level_traffic = None
     roofline = dict(bound="hbm", kernel="sample_kernel", achieved=round(achieved, 2),
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 5),
                     traffic=traffic, bytes_per_launch=model_bytes / sample_launches,
                     avg_launch_ms=sample_ms / sample_launches)
+    # the weight builds' level kernels (times from the untimed stage run)
+    level_ms = stage_ms["levels"]
+    lach = level_bytes / (level_ms * 1e-3) / 1e9 if level_ms > 0 else 0.0
+    weights_roofline = dict(bound="hbm", kernel="level_kernel", achieved=round(lach, 2), peak=HBM_PEAK_GBS,
+                            unit="GB/s", frac=round(lach / HBM_PEAK_GBS, 5), traffic=level_traffic,
+                            bytes_per_launch=level_bytes / level_launches if level_launches else None,
+                            avg_launch_ms=level_ms / level_launches if level_launches else None)
 
     cpu = None
     if args.cpu_samples > 0:
@@ -237,6 +249,7 @@ def main():
         "stages_ms_per_step": {s: round(v, 3) for s, v in stage_ms.items()},
         "estimates": per_motif,
         "roofline": roofline,
+        "weights_roofline": weights_roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -547,7 +560,7 @@ def large(args):
                                "times over 3e7 s, drawn on the device), scatter-gather and 6-chain at delta "
                                "86400, 1e8 samples each; graph build + weights + sampling per step",
                    "m": int(u.numel()), "n": n, "k_per_motif": k},
-        "stages_ms_per_step": {T.STAGES[i]: round(prof["ms"][i] / args.steps, 3) for i in range(5)},
+        "stages_ms_per_step": {T.STAGES[i]: round(prof["ms"][i] / args.steps, 3) for i in range(len(T.STAGES))},
         "estimates": [dict(motif=a, estimate=b, rel_ci95=(1.96 * c / b) if b else None, valid=d, W=str(e), wide=f)
                       for a, b, c, d, e, f in res],
     }
@@ -790,7 +803,7 @@ def weights_only(args):
 TRAFFIC_KERNELS = {
     "sample_kernel": "sample_kernel<unsigned long long, false, false, true, true",
     "root_kernel": "root_kernel<unsigned long long>",
-    "level_kernel": "level_kernel<unsigned long long>",
+    "level_kernel": "level_kernel<unsigned long long, false>",
 }
 
 
@@ -839,6 +852,7 @@ def summarize_traffic(fetch_dir, write_dir, out_path, calib_bytes):
     doc = {
         "workload": "medium (bench.py defaults, one step)",
         "source_sha": kernel_source_sha(),
+        "level_source_sha": level_source_sha(),
         "copy_calibration": {"bytes": calib_bytes, "fetch_kib": f_cal, "write_kib": w_cal,
                              "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4)},
         "kernels": kernels,
@@ -856,14 +870,19 @@ def summarize_traffic(fetch_dir, write_dir, out_path, calib_bytes):
     print(json.dumps({k: v["hbm_bytes_per_launch"] for k, v in kernels.items()}))
 
 
-def kernel_source_sha():
+def kernel_source_sha(main="sample.hip"):
     """Hash of the sampling kernel's sources (the counters' validity key)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("sample.hip", "tm_common.h", "tm_primitives.h", "tm_internal.h"):
+    for f in (main, "tm_common.h", "tm_primitives.h", "tm_internal.h"):
         with open(os.path.join(ROOT, "paper_2507_20441_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def level_source_sha():
+    """Hash of the level kernel's sources (its counters' validity key)."""
+    return kernel_source_sha("weights.hip")
 
 
 def cpu_baseline(g, cfg, n_samples):

@@ -404,7 +404,8 @@ enum tm_stage {
     TM_STAGE_SAMPLE = 2,   /* the sampling kernel of tm_sample (draw, validate, complete) */
     TM_STAGE_REDUCE = 3,   /* the final reduction of tm_sample */
     TM_STAGE_ROOTS = 4,    /* tm_sample on large counts: root draws and their sort by root */
-    TM_N_STAGES = 5
+    TM_STAGE_LEVELS = 5,   /* each level kernel launch of a synchronous weight build (inside WEIGHTS) */
+    TM_N_STAGES = 6
 };
 typedef struct {
     double ms[TM_N_STAGES];          /* accumulated device milliseconds */
@@ -430,6 +431,20 @@ int tm_profile_read(tm_profile* out, int reset);
  * sampling kernel's roofline. */
 int tm_sample_model_bytes(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count,
                           void* stream, uint64_t* bytes);
+
+/* Bytes the level kernels of a weight build (Alg. 2: the s-weights of every
+ * non-leaf tree edge, level by level) request under their access model: a
+ * search over a list of L entries is charged ceil(log2 L) + 1 probes of
+ * each of its six bounds (three over the T order, three over the N order,
+ * 8 B each), every other read and write its element size (the edge, the
+ * first pass's products, the children's prefix entries, the kept windows,
+ * the products written).  The set is built as tm_weights_create_ex with
+ * constraints TM_C_ALL builds it (a counting variant of the same kernels,
+ * not timed) and then freed; a 64-bit build that overflows counts both
+ * attempts, as the TM_STAGE_LEVELS timing does.  The numerator of the level
+ * kernel's roofline.  Errors: as tm_weights_create. */
+int tm_weights_model_bytes(tm_graph* g, const tm_motif* mo, const tm_tree* tr, void* stream,
+                           uint64_t* bytes);
 
 #ifdef __cplusplus
 }

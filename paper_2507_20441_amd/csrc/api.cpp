@@ -29,6 +29,7 @@ static tm_profile g_prof = {};
 static thread_local bool t_prof_suspended = false;
 
 void prof_suspend(bool on) { t_prof_suspended = on; }
+bool prof_suspended() { return t_prof_suspended; }
 
 bool prof_enabled(int stage) {
     if (t_prof_suspended || stage < 0 || stage >= TM_N_STAGES) return false;
@@ -508,8 +509,10 @@ extern "C" int tm_weights_create(tm_graph* g, const tm_motif* mo, const tm_tree*
     return tm_weights_create_ex(g, mo, tr, TM_C_ALL, stream, out);
 }
 
-extern "C" int tm_weights_create_ex(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32_t constraints,
-                                    void* stream, tm_weights** out) {
+namespace {
+
+int weights_create(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32_t constraints, void* stream,
+                   tm_weights** out, u64* model_bytes) {
     if (!g || !out) return tm_fail(TM_EINVAL, "weights: NULL argument");
     if (constraints & ~(uint32_t)TM_C_ALL) return tm_fail(TM_EINVAL, "weights: constraints %u", constraints);
     TM_TRY(motif_check(mo));
@@ -524,13 +527,36 @@ extern "C" int tm_weights_create_ex(tm_graph* g, const tm_motif* mo, const tm_tr
     w->arena.stream = as_stream(stream);
     w->constraints = constraints;
     int rc = plan_build(mo, tr, &w->plan);
-    if (rc == TM_OK) rc = weights_build(w, as_stream(stream));
+    if (rc == TM_OK) rc = weights_build(w, as_stream(stream), model_bytes);
     if (rc != TM_OK) {
         w->arena.release();
         delete w;
         return rc;
     }
     *out = w;
+    return TM_OK;
+}
+
+}  // namespace
+
+extern "C" int tm_weights_create_ex(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32_t constraints,
+                                    void* stream, tm_weights** out) {
+    return weights_create(g, mo, tr, constraints, stream, out, nullptr);
+}
+
+extern "C" int tm_weights_model_bytes(tm_graph* g, const tm_motif* mo, const tm_tree* tr, void* stream,
+                                      uint64_t* bytes) {
+    if (!bytes) return tm_fail(TM_EINVAL, "weights_model_bytes: NULL argument");
+    // the counting pass is not a timed stage
+    const bool was = prof_suspended();
+    prof_suspend(true);
+    tm_weights* w = nullptr;
+    u64 b = 0;
+    const int rc = weights_create(g, mo, tr, TM_C_ALL, stream, &w, &b);
+    prof_suspend(was);
+    if (rc != TM_OK) return rc;
+    tm_weights_destroy(w);
+    *bytes = b;
     return TM_OK;
 }
 

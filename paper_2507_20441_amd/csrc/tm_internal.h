@@ -185,7 +185,9 @@ struct tm_weights {
 // ---------------------------------------------------------------------------
 int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64_t* t,
                 hipStream_t st);
-int weights_build(tm_weights* w, hipStream_t st);
+// model_bytes (optional): the level kernels' access-model bytes (every
+// attempt, as the level stage timing counts every attempt).
+int weights_build(tm_weights* w, hipStream_t st, u64* model_bytes = nullptr);
 // The 64-bit weight build enqueued on st with no host synchronisation; a
 // product or prefix that does not fit 64 bits sets *ovf (device).  The
 // caller reads W from cumW[q] afterwards, or rebuilds with weights_build.
@@ -269,6 +271,7 @@ bool prof_enabled(int stage);
 void prof_add(int stage, double ms);
 // Stage timing off on this thread (while recording a graph).
 void prof_suspend(bool on);
+bool prof_suspended();
 
 // Timing events of the current device from a list kept per device (creating
 // and destroying two for every timed stage costs more than recording them).

@@ -17,6 +17,7 @@
 // parity i & 1 -- one prefix array per parity serves every interval.
 #include <algorithm>
 #include <cstring>
+#include <memory>
 #include <type_traits>
 #include <vector>
 
@@ -50,6 +51,7 @@ struct LevelArgs {
     const void* in[2]; // second of two passes: the first pass's products ...
     int in_pos_dir;    // ... by T position in this list
     int* ovf;
+    unsigned long long* nbytes;  // counting variant: access-model bytes of the launch
 };
 
 template <int B, int E, typename F>
@@ -67,6 +69,7 @@ __device__ __forceinline__ void sfor(F&& f) {
 // cannot wrap even when the id and time bits fill all 64.
 struct Bounds3 {
     int32_t p[3], q[3];
+    int32_t len;  // the list's length
 };
 
 __device__ __forceinline__ Bounds3 three_bounds(const DevGraph& G, int dir, int32_t g, int32_t o,
@@ -105,6 +108,7 @@ __device__ __forceinline__ Bounds3 three_bounds(const DevGraph& G, int dir, int3
         n -= h;
     }
     Bounds3 r;
+    r.len = b - a;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         r.p[j] = a == b ? a : c[j] + (lt[c[j]] < x[j] ? 1 : 0);
@@ -134,15 +138,20 @@ __device__ __forceinline__ W window_mass(int32_t p0, int32_t p1, int32_t q0, int
 // [t, min(t + delta, (blk + 1) L - 1)] (B): three distinct bounds per child
 // (with L = delta: [blk delta, t], [t - delta, t], [t, t + delta] and
 // [t, (blk + 1) delta - 1]).
-template <typename W>
-__global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+//
+// The counting variant returns the bytes the edge's work reads and writes
+// under the access model: each read or write its element size; a list search
+// of L entries ceil(log2 L) + 1 probes of each of its six bounds (three in
+// the T order, three in the N order, 8 B each).
+template <typename W, bool kCount>
+__device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
     const DevGraph& G = a.G;
-    if (p >= G.m) return;
+    u64 nb = 0;
     // the walked edge: its list's owner, neighbour and time sit at p
     const int32_t e = a.walk < 0 ? (int32_t)p : G.leid[a.walk][p];
     int32_t u, v;
     int64_t t;
+    if constexpr (kCount) nb += 16 + (a.walk < 0 ? 0 : 4);
     if (a.walk < 0 || !G.lown[a.walk]) {
         u = G.src[e];
         v = G.dst[e];
@@ -161,6 +170,7 @@ __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
         const int64_t ip = a.in_pos_dir == a.walk ? p : (int64_t)G.tpos[a.in_pos_dir][e];
         prodA = static_cast<const W*>(a.in[parA])[ip];
         prodB = hasB ? static_cast<const W*>(a.in[parB])[ip] : (W)0;
+        if constexpr (kCount) nb += (a.in_pos_dir == a.walk ? 0 : 4) + sizeof(W) * (hasB ? 2 : 1);
     }
     bool ovf = false;
     sfor<0, kMaxSlots>([&](auto cc) {
@@ -188,6 +198,17 @@ __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
                 xs[2] = (hi < (blk + 1) * a.ilen - 1 ? hi : (blk + 1) * a.ilen - 1) + 1;
             }
             const Bounds3 r = three_bounds(G, d.dir, g, o, xs, a.exclude != 0);
+            if constexpr (kCount) {
+                int it = 0;
+                for (int32_t n = r.len; n > 1; n -= n >> 1) ++it;
+                nb += 8 + (u64)48 * it + (r.len > 0 ? 48 : 0);
+                if (a.win[c][0]) nb += 32 + (a.win_dir == a.walk ? 0 : 4);
+                if (!d.leaf) {
+                    // the prefix reads of the two windows' masses (below)
+                    const int32_t a1 = d.beta < 0 ? r.p[2] : r.p[1], b0 = d.beta < 0 ? r.p[1] : r.p[0];
+                    nb += (a1 > r.p[0] ? 4 * sizeof(W) : 0) + (hasB && r.p[2] > b0 ? 4 * sizeof(W) : 0);
+                }
+            }
             if (a.win[c][0]) {
                 // the windows of intervals blk (parity A) and blk - 1 (B)
                 const int64_t at = a.win_dir == a.walk ? p : (int64_t)G.tpos[a.win_dir][e];
@@ -218,7 +239,29 @@ __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
     const int64_t at = a.out_pos_dir < 0 ? (int64_t)e : (a.out_pos_dir == a.walk ? p : (int64_t)G.tpos[a.out_pos_dir][e]);
     static_cast<W*>(a.out[parA])[at] = prodA;
     static_cast<W*>(a.out[parB])[at] = hasB ? prodB : (W)0;
+    if constexpr (kCount) nb += 2 * sizeof(W) + (a.out_pos_dir < 0 || a.out_pos_dir == a.walk ? 0 : 4);
     if (ovf) atomicOr(a.ovf, 4);
+    return nb;
+}
+
+template <typename W, bool kCount>
+__global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    u64 nb = 0;
+    if (p < a.G.m) nb = level_edge<W, kCount>(a, p);
+    if constexpr (kCount) {
+        // one addition per workgroup
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) nb += __shfl_xor(nb, m, 64);
+        __shared__ u64 part[kBlock / 64];
+        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = nb;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            u64 sum = 0;
+            for (int w = 0; w < kBlock / 64; ++w) sum += part[w];
+            atomicAdd(a.nbytes, (unsigned long long)sum);
+        }
+    }
 }
 
 // Values of one parity held in a list's T order, read in that list's N
@@ -343,7 +386,12 @@ unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 // check_each_level: read the overflow flag after every level and stop at the
 // first overflow (the synchronous build, which then restarts in 128 bits).
 template <typename W>
-int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level = false) {
+// nbytes (optional): the level kernels' access-model bytes are added there.
+// level_timers (optional): each level launch's stage timer, for the caller to
+// finish once the stream is synchronised.
+int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level = false,
+                unsigned long long* nbytes = nullptr,
+                std::vector<std::unique_ptr<StageTimer>>* level_timers = nullptr) {
     tm_graph* g = w->g;
     const HostPlan& P = w->plan;
     const int64_t m = g->m;
@@ -442,8 +490,19 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
                 a.in_pos_dir = prev_walk;
                 prev_walk = a.walk;
                 a.ovf = ovf;
-                hipLaunchKernelGGL((level_kernel<W>), dim3(grid_for(m)), dim3(kBlock), 0, st, a);
+                a.nbytes = nbytes;
+                StageTimer* lt = nullptr;
+                if (level_timers) {
+                    level_timers->push_back(std::make_unique<StageTimer>());
+                    lt = level_timers->back().get();
+                    lt->start(TM_STAGE_LEVELS, st);
+                }
+                if (nbytes)
+                    hipLaunchKernelGGL((level_kernel<W, true>), dim3(grid_for(m)), dim3(kBlock), 0, st, a);
+                else
+                    hipLaunchKernelGGL((level_kernel<W, false>), dim3(grid_for(m)), dim3(kBlock), 0, st, a);
                 TM_HIP(hipGetLastError());
+                if (lt) lt->stop();
             }
             if (two)
                 for (int par = 0; par < 2; ++par) TM_HIP(dev_free(tmp[par], st));
@@ -541,7 +600,7 @@ int64_t interval_unit(const tm_weights* w) {
     return (w->constraints & TM_C_WINDOWS) ? w->plan.mo.delta : w->g->T + 1;
 }
 
-int weights_build(tm_weights* w, hipStream_t st) {
+int weights_build(tm_weights* w, hipStream_t st, u64* model_bytes) {
     tm_graph* g = w->g;
     w->ilen = interval_unit(w);
     w->q = g->m > 0 ? g->T / w->ilen + 1 : 0;
@@ -553,8 +612,16 @@ int weights_build(tm_weights* w, hipStream_t st) {
     if (w->q >= ((int64_t)1 << 31)) return tm_fail(TM_ERANGE, "weights: too many intervals");
     StageTimer timer;
     timer.start(TM_STAGE_WEIGHTS, st);
+    std::vector<std::unique_ptr<StageTimer>> level_timers;
     int* ovf = nullptr;
     TM_HIP(dev_alloc((void**)&ovf, sizeof(int), st));
+    // the level kernels' access-model bytes, over every attempt
+    unsigned long long* nbytes = nullptr;
+    u64 hbytes = 0;
+    if (model_bytes) {
+        TM_HIP(dev_alloc((void**)&nbytes, sizeof(u64), st));
+        TM_TRY(fill_u32(nbytes, 2, 0u, st));
+    }
     int h = 0;
     int rc = TM_OK;
     for (int wide = 0; wide < 2; ++wide) {
@@ -566,21 +633,26 @@ int weights_build(tm_weights* w, hipStream_t st) {
         // checks after every level and stops at the first overflow; other
         // builds of small graphs check once, at the end
         const bool per_level = w->lean || g->m >= ((int64_t)1 << 23);
-        rc = wide ? build_typed<u128>(w, st, ovf) : build_typed<u64>(w, st, ovf, per_level);
+        rc = wide ? build_typed<u128>(w, st, ovf, false, nbytes, &level_timers)
+                  : build_typed<u64>(w, st, ovf, per_level, nbytes, &level_timers);
         if (rc != TM_OK) break;
         u64 hW[2] = {0, 0};
         timer.stop();
         // a 64-bit build that stopped at an overflowing level has no W yet
         const size_t wsz = w->cumW ? (wide ? 16 : 8) : 0;
         TM_HIP(read_back({{&h, ovf, sizeof(int)},
-                          {hW, static_cast<const unsigned char*>(w->cumW) + w->q * (wide ? 16 : 8), wsz}},
+                          {hW, static_cast<const unsigned char*>(w->cumW) + w->q * (wide ? 16 : 8), wsz},
+                          {&hbytes, nbytes, nbytes ? sizeof(u64) : 0}},
                          st));
         w->W = ((u128)hW[1] << 64) | hW[0];
         if (h == 0) break;
         if (wide) rc = tm_fail(TM_EOVERFLOW, "weights: a weight or W reaches 2^128");
     }
     TM_HIP(dev_free(ovf, st));
+    if (nbytes) TM_HIP(dev_free(nbytes, st));
     timer.finish();
+    for (auto& t : level_timers) t->finish();
+    if (model_bytes) *model_bytes = hbytes;
     if (rc != TM_OK) clear_tables(w);
     return rc;
 }

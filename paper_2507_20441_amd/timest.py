@@ -48,10 +48,10 @@ class Result(C.Structure):
 
 
 class Profile(C.Structure):
-    _fields_ = [("ms", C.c_double * 5), ("launches", C.c_uint64 * 5)]
+    _fields_ = [("ms", C.c_double * 6), ("launches", C.c_uint64 * 6)]
 
 
-STAGES = ("graph", "weights", "sample", "reduce", "roots")
+STAGES = ("graph", "weights", "sample", "reduce", "roots", "levels")
 
 
 class ServerOpts(C.Structure):
@@ -144,6 +144,7 @@ def lib():
         L.tm_profile_stages.restype = None
         L.tm_profile_read.argtypes = [C.POINTER(Profile), C.c_int]
         L.tm_sample_model_bytes.argtypes = [vp, u64, u64, u64, vp, C.POINTER(u64)]
+        L.tm_weights_model_bytes.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), vp, C.POINTER(u64)]
         L.tm_weights_footprint.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), i32, C.POINTER(u64)]
         L.tm_server_create.argtypes = [u64, C.POINTER(ServerOpts), C.POINTER(vp)]
         L.tm_server_add_graph.argtypes = [vp, vp, C.POINTER(i32)]
@@ -436,6 +437,14 @@ def sample_model_bytes(w: "Weights", seed, count, j0=0) -> int:
     b = C.c_uint64()
     _check(lib().tm_sample_model_bytes(w.h, int(seed), int(j0), int(count), _stream(), C.byref(b)),
            "sample_model_bytes")
+    return int(b.value)
+
+
+def weights_model_bytes(g: "Graph", mo: "Motif", tr: "Tree" = None) -> int:
+    """Access-model bytes of a weight build's level kernels (tm_weights_model_bytes)."""
+    b = C.c_uint64()
+    _check(lib().tm_weights_model_bytes(g.h, C.byref(mo), C.byref(tr) if tr is not None else None, _stream(),
+                                        C.byref(b)), "weights_model_bytes")
     return int(b.value)
 
 

@@ -356,10 +356,48 @@ def test_stage_timing_mask(T):
         T.profile_enable(False)
         prof = T.profile_read(reset=True)
         p = dict(zip(T.STAGES, prof["launches"]))
-        assert all(p[s] == 1 for s in T.STAGES), p
+        # the 4-cycle's center has children at both ends: two level passes
+        assert all(p[s] == (2 if s == "levels" else 1) for s in T.STAGES), p
         assert all(ms > 0 for ms in prof["ms"]), prof
         assert plain == only == every
     finally:
         T.profile_enable(False)
         T.profile_stages(None)
         T.profile_read(reset=True)
+
+
+# ---------------------------------------------------------------------------
+# Access-model bytes of the level kernels
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("tree_edges,attach", [([0, 1], "out-list of the center's destination"),
+                                               ([0, 2], "in-list of the center's source")])
+def test_level_model_bytes_match_host_count(T, tree_edges, attach):
+    """tm_weights_model_bytes against the access model counted on the host.
+
+    3-cycle a->b, b->c, c->a with a two-edge tree centred on a->b: one level
+    launch over every edge e, whose one leaf child is searched in one list of
+    length L_e (b->c: the out-list of e's destination; c->a: the in-list of
+    e's source).  Per edge: the walked entry (owner, neighbour, time, eid:
+    20 B), the list offsets (8 B), six bounds of ceil(log2 L) + 1 probes of
+    8 B (no probes for an empty list), the two kept windows (32 B) and the
+    two products (16 B)."""
+    say("level model bytes", tree_edges)
+    g = W.small_graph(40000, 4, n=2000, span=10**6)
+    tg = T.Graph(g.src, g.dst, g.t, g.n)
+    mo = T.make_motif(W.MOTIFS["3cycle"], 3600)
+    got = T.weights_model_bytes(tg, mo, T.make_tree(tree_edges, 0))
+    assert got == T.weights_model_bytes(tg, mo, T.make_tree(tree_edges, 0))
+    src, dst = tg.export("src").astype(np.int64), tg.export("dst").astype(np.int64)
+    if tree_edges == [0, 1]:
+        L = np.bincount(src, minlength=g.n)[dst]
+    else:
+        L = np.bincount(dst, minlength=g.n)[src]
+    steps = np.zeros_like(L)
+    n = L.copy()
+    while (n > 1).any():
+        live = n > 1
+        steps[live] += 1
+        n[live] -= n[live] >> 1
+    expect = int(np.sum(20 + 8 + 48 * (steps + (L > 0)) + 32 + 16))
+    tg.close()
+    assert got == expect, (attach, got, expect)
