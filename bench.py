@@ -126,13 +126,13 @@ def main():
     torch.cuda.synchronize()
 
     def step():
+        # per motif one tm_estimate: weight build, sampling and reduction in
+        # one call
         G = T.Graph(src, dst, tt, g.n)
         out = []
         for _, mo in motifs:
-            Wt = T.Weights(G, mo)
-            res, _ = Wt.sample(seed, k)
+            res = T.estimate(G, mo, k, seed)
             out.append((res.estimate, res.std_error, res.n_valid, res.W.value))
-            Wt.close()
         G.close()
         return out
 
