@@ -718,9 +718,65 @@ extern "C" int tm_estimate(tm_graph* g, const tm_motif* mo, const tm_tree* tr, u
     return tm_estimate_ex(g, mo, tr, TM_C_ALL, k, seed, stream, out);
 }
 
+namespace {
+
+// The 64-bit weight build and the sampling enqueued together with one
+// synchronisation at the end (graphs below 2^23 edges, where a synchronous
+// build checks for overflow only at its end anyway).  *done is false when
+// the 64-bit tables overflowed: the caller then runs the synchronous path.
+int estimate_enqueued(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32_t constraints, u64 k, u64 seed,
+                      hipStream_t st, tm_result* out, bool* done) {
+    *done = false;
+    if (constraints & ~(uint32_t)TM_C_ALL) return tm_fail(TM_EINVAL, "weights: constraints %u", constraints);
+    TM_TRY(motif_check(mo));
+    tm_tree def;
+    if (!tr) {
+        TM_TRY(tm_default_tree(mo, &def));
+        tr = &def;
+    }
+    tm_weights* w = new (std::nothrow) tm_weights();
+    if (!w) return tm_fail(TM_ENOMEM, "weights: host allocation");
+    w->g = g;
+    w->arena.stream = st;
+    w->constraints = constraints;
+    int* flag = nullptr;
+    int rc = plan_build(mo, tr, &w->plan);
+    if (rc == TM_OK && dev_alloc((void**)&flag, sizeof(int), st) != hipSuccess)
+        rc = tm_fail(TM_ENOMEM, "estimate: device allocation");
+    if (rc == TM_OK) rc = fill_u32(flag, 1, 0u, st);
+    StageTimer tw;
+    std::vector<std::unique_ptr<StageTimer>> levels;
+    if (rc == TM_OK) {
+        tw.start(TM_STAGE_WEIGHTS, st);
+        rc = weights_enqueue(w, st, flag, &levels);
+        tw.stop();
+    }
+    bool overflowed = false;
+    if (rc == TM_OK) rc = sample_run(w, seed, 0, k, k, st, out, nullptr, nullptr, flag, &overflowed);
+    // sample_run synchronised the stream (on success)
+    if (sync_stream(st) != hipSuccess && rc == TM_OK) rc = tm_fail(TM_EDEVICE, "estimate: synchronise");
+    tw.finish();
+    for (auto& t : levels) t->finish();
+    if (flag) (void)dev_free(flag, st);
+    tm_weights_destroy(w);
+    if (rc == TM_OK) *done = !overflowed;
+    return rc;
+}
+
+}  // namespace
+
 extern "C" int tm_estimate_ex(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32_t constraints,
                               uint64_t k, uint64_t seed, void* stream, tm_result* out) {
     if (!out) return tm_fail(TM_EINVAL, "estimate: NULL output");
+    if (g && k > 0 && g->m > 0 && g->m < ((int64_t)1 << 23)) {
+        bool done = false;
+        TM_TRY(estimate_enqueued(g, mo, tr, constraints, k, seed, as_stream(stream), out, &done));
+        if (done) {
+            finish_result(out);
+            out->status = TM_OK;
+            return TM_OK;
+        }
+    }
     tm_weights* w = nullptr;
     TM_TRY(tm_weights_create_ex(g, mo, tr, constraints, stream, &w));
     const int rc = tm_sample(w, seed, 0, k, k, stream, out, nullptr);

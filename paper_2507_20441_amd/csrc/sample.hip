@@ -388,6 +388,20 @@ __device__ __forceinline__ void block_reduce_write(Partial acc, Partial* out) {
 // Draw 0 of sample a.j0 + r: the interval, then the center edge; returned as
 // the root key (T-order position of the root * 2 + interval parity).
 // Inconsistent tables give a harmless key and set bad.
+// The job's W: read from its table when the host has not read it yet (Wdev),
+// else from the arguments.
+template <typename W>
+__device__ __forceinline__ W job_W(const SampleArgs& a) {
+    return a.Wdev ? *static_cast<const W*>(a.Wdev) : (W)(((u128)a.W_hi << 64) | a.W_lo);
+}
+
+// A job whose 64-bit weight build overflowed (wflag set) or whose W is 0
+// draws nothing (its tables are not to be searched).
+template <typename W>
+__device__ __forceinline__ bool job_skipped(const SampleArgs& a, W Wtot) {
+    return (a.wflag && *a.wflag != 0) || Wtot == 0;
+}
+
 template <typename W>
 __device__ __forceinline__ bool draw_root_from(const SampleArgs& a, const W* cum, W Wtot, const X128& X,
                                                const RootGuide& g0, const RootGuide& g1, int32_t& i,
@@ -463,7 +477,8 @@ __device__ __forceinline__ uint32_t root_key(const SampleArgs& a, const W* cum, 
 template <typename W>
 __global__ void __launch_bounds__(kBlock) root_kernel(SampleArgs a, uint32_t* keys, uint32_t* vals) {
     extern __shared__ unsigned char lds_raw[];
-    const W Wtot = (W)(((u128)a.W_hi << 64) | a.W_lo);
+    const W Wtot = job_W<W>(a);
+    const u64 count = job_skipped<W>(a, Wtot) ? 0 : a.count;
     const W* cumG = static_cast<const W*>(a.cumW);
     const int32_t ncum = (int32_t)a.q + 1;
     W* cumL = reinterpret_cast<W*>(lds_raw);
@@ -477,9 +492,9 @@ __global__ void __launch_bounds__(kBlock) root_kernel(SampleArgs a, uint32_t* ke
     (void)vals;  // the sort makes the sample offsets (0 .. count-1) itself
     // two draws per lane and step, both guide reads issued before either is
     // used: the random guide reads are the kernel's latency
-    for (u64 r = (u64)blockIdx.x * kBlock + threadIdx.x; r < a.count; r += 2 * stride) {
+    for (u64 r = (u64)blockIdx.x * kBlock + threadIdx.x; r < count; r += 2 * stride) {
         const u64 r1 = r + stride;
-        const bool two = r1 < a.count;
+        const bool two = r1 < count;
         const X128 X0 = draw_block(a.seed, a.j0 + r, 0);
         const X128 X1 = draw_block(a.seed, a.j0 + (two ? r1 : r), 0);
         RootGuide g00, g01, g10, g11;
@@ -551,7 +566,6 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
     constexpr int NT = kSmall ? 4 : kMaxSlots - 1;  // register slots; a.nt of them are used
     constexpr int K = kSmall ? 5 : TM_MAX_K;         // motif vertices held
     const DevGraph& G = a.G;
-    const W Wtot = (W)(((u128)a.W_hi << 64) | a.W_lo);
     u128 acc2 = L.acc2, acc2_sq = L.acc2_sq;
     uint32_t n_valid = L.n_valid, n_vertex = L.n_vertex, n_delta = L.n_delta, n_order = L.n_order,
              n_nonzero = L.n_nonzero;
@@ -583,7 +597,10 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
         } else {
             // draw 0: interval, then center edge
             r = x;
-            if (!draw_root<W>(a, cum, Wtot, a.j0 + r, i, e0, kCount ? &nb : nullptr)) { bad = true; break; }
+            if (!draw_root<W>(a, cum, job_W<W>(a), a.j0 + r, i, e0, kCount ? &nb : nullptr)) {
+                bad = true;
+                break;
+            }
             if constexpr (kCount) nb += 16;
             te[0] = G.t[e0];
             u0 = G.src[e0];
@@ -796,6 +813,10 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
     }
     const W* cum = a.cum_in_lds ? cumL : cumG;
     LaneAcc L = lane_zero();
+    if (job_skipped<W>(a, job_W<W>(a))) {
+        lanes_reduce(L, &a.parts[blockIdx.x], a.ovf);  // nothing drawn
+        return;
+    }
     sample_positions<W, kCount, kGeneral, kSorted, kWin, kSmall>(a, cum, (u64)blockIdx.x * kBlock + threadIdx.x,
                                                    a.count, (u64)gridDim.x * kBlock, L);
     lanes_reduce(L, &a.parts[blockIdx.x], a.ovf);
@@ -1209,11 +1230,18 @@ list_kernel(SampleArgs a, ListArgs la, const tm_sample_rec* recs, u64 count, int
 }  // namespace
 
 int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStream_t st,
-               tm_result* out, tm_sample_rec* recs, u64* model_bytes) {
+               tm_result* out, tm_sample_rec* recs, u64* model_bytes, const int* wflag, bool* overflowed) {
     if (model_bytes) {
         *model_bytes = 0;
         recs = nullptr;
     }
+    // enqueued after a 64-bit build the host has not waited for: W is read
+    // from the table with the sums, and the kernels draw nothing when the
+    // build overflowed (*wflag) or W is 0
+    const bool deferred = wflag != nullptr;
+    if (deferred && (recs || model_bytes || count == 0 || w->wide))
+        return tm_fail(TM_EINVAL, "sample: a deferred run takes samples and nothing else");
+    if (overflowed) *overflowed = false;
     const HostPlan& P = w->plan;
     std::memset(out, 0, sizeof *out);
     out->k = k_total;
@@ -1221,7 +1249,7 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
     out->W.lo = (u64)w->W;
     out->W.hi = (u64)(w->W >> 64);
     if (w->wide) out->flags |= TM_F_WIDE;
-    if (w->W == 0 || count == 0) {
+    if (!deferred && (w->W == 0 || count == 0)) {
         if (w->W == 0) out->flags |= TM_F_W_ZERO;
         if (recs && count) {
             hipLaunchKernelGGL(fill_undrawn_kernel, dim3((unsigned)((count + kBlock - 1) / kBlock)),
@@ -1258,6 +1286,12 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
     }
     a.parts = parts;
     a.ovf = ovf;
+    u64 hW = 0;
+    int hflag = 0;
+    if (deferred) {
+        a.Wdev = static_cast<const unsigned char*>(w->cumW) + w->q * sizeof(u64);
+        a.wflag = wflag;
+    }
     Partial h;
     std::memset(&h, 0, sizeof h);
     int hovf = 0;
@@ -1293,11 +1327,16 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
         TM_HIP(hipGetLastError());
         t_reduce.stop();
         Partial hc;
-        TM_HIP(read_back({{&hc, parts + blocks, sizeof hc}, {&hovf, ovf, sizeof hovf}}, st));
+        TM_HIP(read_back({{&hc, parts + blocks, sizeof hc},
+                          {&hovf, ovf, sizeof hovf},
+                          {&hflag, wflag, deferred ? sizeof hflag : 0},
+                          {&hW, a.Wdev, deferred ? sizeof hW : 0}},
+                         st));
         t_roots.finish();
         t_sample.finish();
         t_reduce.finish();
         if (hovf) break;
+        if (deferred && (hflag || hW == 0)) break;  // nothing was drawn
         if (!add_ok(h.acc2, hc.acc2, &h.acc2)) h.flags |= 1;
         if (!add_ok(h.acc2_sq, hc.acc2_sq, &h.acc2_sq)) {
             h.acc2_sq = ~(u128)0;
@@ -1320,6 +1359,20 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
         TM_HIP(dev_free(v1, st));
     }
     if (model_bytes) *model_bytes = h.bytes;
+    if (deferred) {
+        if (hflag) {
+            // the 64-bit tables overflowed: the caller builds them again
+            if (overflowed) *overflowed = true;
+            return TM_OK;
+        }
+        w->W = hW;
+        out->W.lo = hW;
+        out->W.hi = 0;
+        if (hW == 0) {
+            out->flags |= TM_F_W_ZERO;
+            return TM_OK;
+        }
+    }
     if (hovf & 2) return tm_fail(TM_EDEVICE, "sample: inconsistent weight tables");
     if (hovf || (h.flags & 1)) return tm_fail(TM_EOVERFLOW, "sample: a count reaches 2^128");
     out->acc2.lo = (u64)h.acc2;

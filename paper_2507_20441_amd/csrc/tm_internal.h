@@ -3,6 +3,7 @@
 #pragma once
 
 #include <initializer_list>
+#include <memory>
 #include <string>
 #include <utility>
 #include <vector>
@@ -191,9 +192,18 @@ int weights_build(tm_weights* w, hipStream_t st, u64* model_bytes = nullptr);
 // The 64-bit weight build enqueued on st with no host synchronisation; a
 // product or prefix that does not fit 64 bits sets *ovf (device).  The
 // caller reads W from cumW[q] afterwards, or rebuilds with weights_build.
-int weights_enqueue(tm_weights* w, hipStream_t st, int* ovf);
+struct StageTimer;
+// level_timers (optional): each level launch's stage timer, for the caller to
+// finish once the stream is synchronised.
+int weights_enqueue(tm_weights* w, hipStream_t st, int* ovf,
+                    std::vector<std::unique_ptr<StageTimer>>* level_timers = nullptr);
+// wflag (optional): w's 64-bit build was enqueued on st with that overflow
+// flag and not waited for (weights_enqueue); W is then read with the sums,
+// *overflowed tells whether the tables overflowed (the result is then
+// unset), and only plain sampling (no records, no byte count) is allowed.
 int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStream_t st,
-               tm_result* out, tm_sample_rec* recs, u64* model_bytes);
+               tm_result* out, tm_sample_rec* recs, u64* model_bytes, const int* wflag = nullptr,
+               bool* overflowed = nullptr);
 
 // Device bytes of a weight set's tables (prefix arrays, intervals) for a
 // graph of m edges and q intervals, in 64-bit (wide = false) or 128-bit form,

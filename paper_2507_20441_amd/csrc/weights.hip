@@ -723,7 +723,8 @@ u64 weights_build_extra(int64_t m, bool wide) {
     return 4 * ((((u64)m * (wide ? 16 : 8)) + 255) & ~(u64)255) + ((coarse + 255) & ~(u64)255);
 }
 
-int weights_enqueue(tm_weights* w, hipStream_t st, int* ovf) {
+int weights_enqueue(tm_weights* w, hipStream_t st, int* ovf,
+                    std::vector<std::unique_ptr<StageTimer>>* level_timers) {
     tm_graph* g = w->g;
     w->ilen = interval_unit(w);
     w->q = g->m > 0 ? g->T / w->ilen + 1 : 0;
@@ -732,7 +733,7 @@ int weights_enqueue(tm_weights* w, hipStream_t st, int* ovf) {
     if (g->m == 0) return TM_OK;
     if (w->q >= ((int64_t)1 << 31)) return tm_fail(TM_ERANGE, "weights: too many intervals");
     clear_tables(w);
-    const int rc = build_typed<u64>(w, st, ovf);
+    const int rc = build_typed<u64>(w, st, ovf, false, nullptr, level_timers);
     if (rc != TM_OK) clear_tables(w);
     return rc;
 }

@@ -401,3 +401,67 @@ def test_level_model_bytes_match_host_count(T, tree_edges, attach):
     expect = int(np.sum(20 + 8 + 48 * (steps + (L > 0)) + 32 + 16))
     tg.close()
     assert got == expect, (attach, got, expect)
+
+
+# ---------------------------------------------------------------------------
+# tm_estimate's enqueued path (weights and sampling with one synchronisation)
+# ---------------------------------------------------------------------------
+def _same_result(a, b):
+    return (a.W.value == b.W.value and a.acc2.value == b.acc2.value and a.acc2_sq.value == b.acc2_sq.value
+            and a.n_valid == b.n_valid and a.n_bad_vertex == b.n_bad_vertex and a.n_bad_delta == b.n_bad_delta
+            and a.n_bad_order == b.n_bad_order and a.n_nonzero == b.n_nonzero and a.q == b.q and a.k == b.k
+            and a.flags == b.flags and a.estimate == b.estimate and a.std_error == b.std_error)
+
+
+@pytest.mark.parametrize("name,delta,k", [("3cycle", 3600, 5000), ("4cycle", 3600, 100000),
+                                          ("6chain", 86400, 70000), ("scatter_gather", 20000, 3000)])
+def test_estimate_equals_weights_then_sample(T, name, delta, k):
+    """tm_estimate enqueues the 64-bit build and the sampling together and
+    reads W with the sums; the result equals a separate build and tm_sample,
+    below and above the count that sorts roots."""
+    say("estimate enqueued", name, k)
+    g = W.small_graph(40000, 4, n=2000, span=10**6)
+    tg = T.Graph(g.src, g.dst, g.t, g.n)
+    mo = T.make_motif(W.MOTIFS[name], delta)
+    one = T.estimate(tg, mo, k, 11)
+    w = T.Weights(tg, mo)
+    two, _ = w.sample(11, k)
+    w.close()
+    tg.close()
+    assert _same_result(one, two)
+
+
+def test_estimate_enqueued_falls_back_to_128_bits(T):
+    """The hub graph whose weights pass 2^64: the enqueued 64-bit build
+    overflows, the kernels draw nothing, and tm_estimate runs the 128-bit
+    path; the result equals a separate build and tm_sample."""
+    say("estimate 128-bit fallback")
+    rng = np.random.default_rng(3)
+    hub_n = 1500
+    src = np.zeros(hub_n, np.int32)
+    dst = np.arange(1, hub_n + 1, dtype=np.int32)
+    t = rng.integers(0, 50, hub_n).astype(np.int64)
+    tg = T.Graph(src, dst, t, hub_n + 1)
+    mo = T.make_motif(tuple((0, j) for j in range(1, 8)), 100)
+    one = T.estimate(tg, mo, 70000, 5)
+    w = T.Weights(tg, mo)
+    assert w.info()["wide"]
+    two, _ = w.sample(5, 70000)
+    w.close()
+    tg.close()
+    assert one.W.value >= 2**64 and _same_result(one, two)
+
+
+def test_estimate_enqueued_zero_weight(T):
+    """W = 0 on a non-empty graph (every edge leaves vertex 0): the enqueued
+    path reads W = 0 with the sums and returns what tm_sample returns."""
+    g = W.TemporalGraph(np.zeros(5, np.int32), np.arange(1, 6, dtype=np.int32),
+                        np.arange(5, dtype=np.int64), 6)
+    tg = T.Graph(g.src, g.dst, g.t, g.n)
+    mo = T.make_motif(W.MOTIFS["3cycle"], 10)
+    one = T.estimate(tg, mo, 100, 1)
+    w = T.Weights(tg, mo)
+    two, _ = w.sample(1, 100)
+    w.close()
+    tg.close()
+    assert one.W.value == 0 and one.flags & T.TM_F_W_ZERO and _same_result(one, two)
