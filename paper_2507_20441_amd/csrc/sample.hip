@@ -170,10 +170,14 @@ __device__ __forceinline__ Bounds window_bounds(const DevGraph& G, int dir, int3
 // The multi-edge run El_{x,y} restricted to times [lo, hi].  It is a
 // contiguous run both of x's out-list in (destination, time) order and of y's
 // in-list in (source, time) order; [ra, rb) are its positions in list dir of
-// those two (la, lb: the list searched).
+// those two (la, lb: the list searched).  ra is searched over the list; the
+// run is short (the edges between one pair of vertices), so rb is found by
+// galloping from ra (probes at doubling distances, then a search between the
+// last two): a few probes instead of a second search of the whole list.
+// np (counting variant): the probes made are added there.
 __device__ __forceinline__ void el_run_dir(const DevGraph& G, int dir, int32_t x, int32_t y, int64_t lo, int64_t hi,
                                            int32_t la_in, int32_t lb_in, int32_t& ra, int32_t& rb, int32_t& la,
-                                           int32_t& lb) {
+                                           int32_t& lb, u64* np = nullptr) {
     la = la_in;
     lb = lb_in;
     if (lo < 0) lo = 0;
@@ -185,27 +189,47 @@ __device__ __forceinline__ void el_run_dir(const DevGraph& G, int dir, int32_t x
     const u64* nk = G.nkey[dir];
     const u64 base = (u64)(dir ? x : y) << G.bt;
     const u64 klo = base | (u64)lo, khi = base | (u64)hi;
-    int32_t b0 = la, b1 = la;
+    int32_t b0 = la;
     int32_t n = lb - la;
     while (n > 1) {
         const int32_t h = n >> 1;
-        const u64 x0 = nk[b0 + h], x1 = nk[b1 + h];
-        b0 = x0 < klo ? b0 + h : b0;
-        b1 = x1 <= khi ? b1 + h : b1;
+        b0 = nk[b0 + h] < klo ? b0 + h : b0;
         n -= h;
+        if (np) ++*np;
     }
     ra = b0 + (nk[b0] < klo ? 1 : 0);
-    rb = b1 + (nk[b1] <= khi ? 1 : 0);
+    if (np) ++*np;
+    // every key before ra is below klo <= khi: rb is the first position at
+    // or after ra whose key exceeds khi; [g0, g1] holds it
+    int32_t g0 = ra, g1 = lb, p = ra - 1;
+    for (int32_t step = 1;; step <<= 1) {
+        const int32_t q = p + step;
+        if (q >= lb) break;
+        if (np) ++*np;
+        if (nk[q] > khi) {
+            g1 = q;
+            break;
+        }
+        g0 = q + 1;
+        p = q;
+    }
+    while (g0 < g1) {
+        const int32_t mid = g0 + ((g1 - g0) >> 1);
+        if (np) ++*np;
+        if (khi < nk[mid]) g1 = mid;
+        else g0 = mid + 1;
+    }
+    rb = g0;
 }
 
 // El_{x,y} in the shorter of the two lists that hold it; returns that list's
 // N-order keys (the run's times are their low bits).
 __device__ __forceinline__ const u64* el_run(const DevGraph& G, int32_t x, int32_t y, int64_t lo, int64_t hi,
-                                             int32_t& ra, int32_t& rb, int32_t& la, int32_t& lb) {
+                                             int32_t& ra, int32_t& rb, int32_t& la, int32_t& lb, u64* np = nullptr) {
     const int32_t xa = G.off[0][x], xb = G.off[0][x + 1];
     const int32_t ya = G.off[1][y], yb = G.off[1][y + 1];
     const int dir = (yb - ya) < (xb - xa) ? 1 : 0;
-    el_run_dir(G, dir, x, y, lo, hi, dir ? ya : xa, dir ? yb : xb, ra, rb, la, lb);
+    el_run_dir(G, dir, x, y, lo, hi, dir ? ya : xa, dir ? yb : xb, ra, rb, la, lb, np);
     return G.nkey[dir];
 }
 
@@ -224,12 +248,14 @@ template <bool kCount>
 __device__ __forceinline__ u128 run_count_short(const DevGraph& G, int32_t x0, int32_t y0, int32_t x1,
                                                 int32_t y1, int len, int64_t lo, int64_t hi, u64& nb) {
     int32_t a0, b0, la0, lb0;
-    const u64* nk0 = el_run(G, x0, y0, lo, hi, a0, b0, la0, lb0);
-    if constexpr (kCount) nb += 16 + 2 * probes(lb0 - la0) * 8;
+    u64 np = 0;  // probes of the run searches (counting variant)
+    const u64* nk0 = el_run(G, x0, y0, lo, hi, a0, b0, la0, lb0, kCount ? &np : nullptr);
+    if constexpr (kCount) nb += 16 + np * 8;
     if (len == 1) return (u128)(b0 - a0);
     int32_t a1, b1, la1, lb1;
-    const u64* nk1 = el_run(G, x1, y1, lo, hi, a1, b1, la1, lb1);
-    if constexpr (kCount) nb += 16 + 2 * probes(lb1 - la1) * 8 + (u64)(b0 - a0 + b1 - a1) * 8;
+    np = 0;
+    const u64* nk1 = el_run(G, x1, y1, lo, hi, a1, b1, la1, lb1, kCount ? &np : nullptr);
+    if constexpr (kCount) nb += 16 + np * 8 + (u64)(b0 - a0 + b1 - a1) * 8;
     // pairs (e, f), e in the first list, f in the second, t(e) < t(f)
     const u64 m = tmask_of(G);
     u128 total = 0;
@@ -256,8 +282,10 @@ __device__ u128 chain_count_general(const DevGraph& G, const V8& img, const int*
     const u64* nks[TM_MAX_L];
     for (int j = 0; j < len; ++j) {
         int32_t la, lb;
-        nks[j] = el_run(G, img.v[fs[first + j]], img.v[fd[first + j]], lo, hi, ra[j], rb[j], la, lb);
-        if constexpr (kCount) nb += 16 + 2 * probes(lb - la) * 8 + (u64)(rb[j] - ra[j]) * 8;
+        u64 np = 0;
+        nks[j] = el_run(G, img.v[fs[first + j]], img.v[fd[first + j]], lo, hi, ra[j], rb[j], la, lb,
+                        kCount ? &np : nullptr);
+        if constexpr (kCount) nb += 16 + np * 8 + (u64)(rb[j] - ra[j]) * 8;
     }
     if (len == 1) return (u128)(rb[0] - ra[0]);
     const u64 m = tmask_of(G);
@@ -312,9 +340,10 @@ __device__ __noinline__ u128 complete_general(const SampleArgs& a, const V8& img
         // the trailing chain
         int32_t fa, fb, la, lb;
         const int f0 = a.run_first[lead];
-        const u64* nkf =
-            el_run(G, img.v[a.free_src[f0]], img.v[a.free_dst[f0]], tlast - a.delta, tfirst - 1, fa, fb, la, lb);
-        if constexpr (kCount) nb += 16 + 2 * probes(lb - la) * 8 + (u64)(fb - fa) * 8;
+        u64 np = 0;
+        const u64* nkf = el_run(G, img.v[a.free_src[f0]], img.v[a.free_dst[f0]], tlast - a.delta, tfirst - 1, fa,
+                                fb, la, lb, kCount ? &np : nullptr);
+        if constexpr (kCount) nb += 16 + np * 8 + (u64)(fb - fa) * 8;
         const u64 m = tmask_of(G);
         u128 sum = 0;
         for (int32_t x = fa; x < fb; ++x) {
