@@ -465,3 +465,20 @@ def test_estimate_enqueued_zero_weight(T):
     w.close()
     tg.close()
     assert one.W.value == 0 and one.flags & T.TM_F_W_ZERO and _same_result(one, two)
+
+
+def test_estimate_enqueued_two_chunks(T):
+    """More samples than one chunk (2^28): the enqueued path keeps reading W
+    from the table for the second chunk; the result equals a separate build
+    and tm_sample over the same ids."""
+    say("estimate enqueued, two chunks")
+    g = W.small_graph(5000, 3, n=300, span=20000)
+    tg = T.Graph(g.src, g.dst, g.t, g.n)
+    mo = T.make_motif(W.MOTIFS["3cycle"], 600)
+    k = (1 << 28) + 4096
+    one = T.estimate(tg, mo, k, 9)
+    w = T.Weights(tg, mo)
+    two, _ = w.sample(9, k)
+    w.close()
+    tg.close()
+    assert one.k == k and one.n_valid > 0 and _same_result(one, two)
