@@ -122,3 +122,21 @@ def test_batch_plan_replays(T, mix):
     finally:
         T.batch_config(*prev)
         plan.close()
+
+
+def test_batch_of_many_jobs_reads_back_directly(T, mix):
+    """220 jobs: their sums (over 16 KiB) are read back straight into host
+    memory instead of through the pinned staging block; each job still equals
+    its run alone."""
+    tg, jobs = mix
+    ws = [T.Weights(tg[0], T.make_motif(W.MOTIFS["3cycle"], 400)),
+          T.Weights(tg[1], T.make_motif(W.MOTIFS["4cycle"], 3000))]
+    n = 220
+    batch_ws = [ws[i % 2] for i in range(n)]
+    ks = [1000 + 37 * i for i in range(n)]
+    seeds = [1000003 * i + 17 for i in range(n)]
+    say("many jobs", n)
+    got = T.sample_batch(batch_ws, ks, seeds)
+    for i in range(n):
+        alone, _ = batch_ws[i].sample(seeds[i], ks[i])
+        assert got[i].status == 0 and same(got[i], alone), i
