@@ -482,3 +482,39 @@ def test_estimate_enqueued_two_chunks(T):
     w.close()
     tg.close()
     assert one.k == k and one.n_valid > 0 and _same_result(one, two)
+
+
+def test_level_model_bytes_two_passes(T):
+    """A level of two passes: the 4-cycle a->b, b->c, c->d, d->a on the path
+    tree centred on b->c, whose leaf children attach at both ends.  Pass 0
+    walks the out-lists (child a->b: the in-list of e's source, L0 entries);
+    pass 1 walks the in-lists (child c->d: the out-list of e's destination,
+    L1 entries), reads the first pass's products through the position index
+    (4 B, 8 B per interval of e: two unless e lies in the first block) and
+    writes its windows at out-list positions (4 B more)."""
+    say("level model bytes, two passes")
+    delta = 3600
+    g = W.small_graph(40000, 4, n=2000, span=10**6)
+    tg = T.Graph(g.src, g.dst, g.t, g.n)
+    mo = T.make_motif(W.MOTIFS["4cycle"], delta)
+    got = T.weights_model_bytes(tg, mo, T.make_tree([0, 1, 2], 1))
+    src, dst = tg.export("src").astype(np.int64), tg.export("dst").astype(np.int64)
+    t = tg.export("t")
+    tg.close()
+
+    def steps(L):
+        s = np.zeros_like(L)
+        n = L.copy()
+        while (n > 1).any():
+            live = n > 1
+            s[live] += 1
+            n[live] -= n[live] >> 1
+        return s
+
+    L0 = np.bincount(dst, minlength=g.n)[src]
+    L1 = np.bincount(src, minlength=g.n)[dst]
+    has_b = (t // delta) >= 1
+    pass0 = 20 + 8 + 48 * (steps(L0) + (L0 > 0)) + 32 + 16
+    pass1 = 20 + 4 + 8 * (1 + has_b) + 8 + 48 * (steps(L1) + (L1 > 0)) + 36 + 16
+    expect = int(np.sum(pass0 + pass1))
+    assert got == expect, (got, expect)
