@@ -97,7 +97,8 @@ typedef struct {
  * 2 * M_phi / N_phi (M_phi: motif matches completing the sampled tree match,
  * N_phi in {1, 2}: intervals holding it); estimate = W * acc2 / (2 k), each
  * 128-bit integer converted to double with round-to-nearest-even.
- * std_error = (W / 2) * sd(2 M_phi / N_phi) / sqrt(k). */
+ * std_error = (W / 2) * s / sqrt(k), s the sample standard deviation of the
+ * terms 2 M_phi / N_phi (see tm_result_finish for its exact evaluation). */
 typedef struct {
     double estimate;
     double std_error;
@@ -218,13 +219,24 @@ int tm_weights_intervals(const tm_weights* w, tm_u128* host_out, void* stream);
 int tm_sample(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count, uint64_t k_total,
               void* stream, tm_result* out, tm_sample_rec* recs);
 
-/* One whole estimate: tm_weights_create, tm_sample(j0 = 0, count = k_total =
- * k), tm_weights_destroy. */
+/* Recompute out->estimate and out->std_error from its W, acc2, acc2_sq, k
+ * and flags (Alg. 6; the standard error of Sec. 4.4): for results of
+ * sample ranges whose exact sums the caller has added up.  Host-only; no
+ * device work.  std_error = (W / 2) sqrt(D / (k^2 (k - 1))) with
+ * D = k acc2_sq - acc2^2 formed exactly in 256 bits and rounded once to
+ * double; 0 when k < 2, W = 0 or TM_F_SQ_SATURATED is set.  Errors:
+ * TM_EINVAL (NULL). */
+int tm_result_finish(tm_result* out);
+
+/* One whole estimate (Alg. 6, Estimate(M, G, k)): tm_weights_create,
+ * tm_sample(j0 = 0, count = k_total = k), tm_weights_destroy.  recs: NULL,
+ * or device memory for k records (tm_sample's).  W = 0 gives TM_OK with
+ * estimate 0 and TM_F_W_ZERO.  Errors: as tm_weights_create and tm_sample. */
 int tm_estimate(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint64_t k,
-                uint64_t seed, void* stream, tm_result* out);
+                uint64_t seed, void* stream, tm_result* out, tm_sample_rec* recs);
 /* tm_estimate under a subset of the constraints (TM_C_*). */
 int tm_estimate_ex(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32_t constraints, uint64_t k,
-                   uint64_t seed, void* stream, tm_result* out);
+                   uint64_t seed, void* stream, tm_result* out, tm_sample_rec* recs);
 
 /* ---- batched estimation (many jobs in one pass) -------------------------
  * Every job's samples are drawn exactly as tm_sample draws them (same seed,
@@ -274,6 +286,27 @@ void tm_batch_plan_destroy(tm_batch_plan* p);
  * the autotuner in the Python package searches these.  Returns the previous
  * values through prev_tile / prev_blocks when not NULL. */
 int tm_batch_config(int tile, int blocks, int* prev_tile, int* prev_blocks);
+
+/* The full schedule of the batched kernels (tm_batch_config sets the first
+ * two fields only).  Process-wide; the autotuner searches these.
+ *   tile: samples per tile, >= 256; each lane of a 256-lane workgroup takes
+ *     tile / 256 of a tile's samples (the samples per lane);
+ *   blocks: workgroups of the persistent kernels (0 = 8 per compute unit);
+ *   root_lds: LDS bytes per workgroup that stage a job's interval prefix W_i
+ *     for its root draws when it fits (jobs with a root guide read one or
+ *     two entries and stage nothing), 0 .. 65536;
+ *   group_limit: root keys (two per edge) and samples one batched pass may
+ *     hold (0 = 2^32, what 32-bit sort keys allow); a smaller value splits a
+ *     batch into more passes without changing any result.
+ * in may be NULL (read only); prev may be NULL.  Errors: TM_EINVAL. */
+typedef struct {
+    int32_t tile;
+    int32_t blocks;
+    int32_t root_lds;
+    int32_t pad;
+    uint64_t group_limit;
+} tm_batch_opts;
+int tm_batch_options(const tm_batch_opts* in, tm_batch_opts* prev);
 
 /* Random instance listing (Sec. 4.3): samples j0 .. j0 + count - 1 of w's
  * motif with the given seed (the draws of tm_sample); every valid sample with

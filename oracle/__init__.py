@@ -40,10 +40,11 @@ class Tree(C.Structure):
 
 
 class Result(C.Structure):
-    _fields_ = [("estimate", C.c_double), ("W", U128), ("acc2", U128), ("acc2_sq", U128),
-                ("k", C.c_uint64), ("n_valid", C.c_uint64), ("n_bad_vertex", C.c_uint64),
-                ("n_bad_delta", C.c_uint64), ("n_bad_order", C.c_uint64),
-                ("n_nonzero", C.c_uint64), ("q", C.c_int64), ("flags", C.c_uint32)]
+    _fields_ = [("estimate", C.c_double), ("std_error", C.c_double), ("W", U128), ("acc2", U128),
+                ("acc2_sq", U128), ("k", C.c_uint64), ("n_valid", C.c_uint64),
+                ("n_bad_vertex", C.c_uint64), ("n_bad_delta", C.c_uint64),
+                ("n_bad_order", C.c_uint64), ("n_nonzero", C.c_uint64), ("q", C.c_int64),
+                ("flags", C.c_uint32)]
 
 
 # Per-sample record, the same 64-byte layout the GPU library uses.
@@ -79,6 +80,8 @@ def lib():
         L.or_prep_interval_weights.argtypes = [vp, vp]
         L.or_prep_weights.argtypes = [vp, i32, C.c_int, vp]
         L.or_sample.argtypes = [vp, u64, u64, u64, u64, C.POINTER(Result), vp]
+        L.or_std_error.argtypes = [U128, U128, U128, u64, C.c_uint32]
+        L.or_std_error.restype = C.c_double
         L.or_derive_cnt.argtypes = [vp, vp, C.POINTER(U128)]
         L.or_list_instance.argtypes = [vp, vp, U128, vp]
         L.or_tree_candidates.argtypes = [C.POINTER(Motif), C.POINTER(Tree), C.POINTER(C.c_int64), C.c_int,
@@ -300,6 +303,11 @@ class Prep:
         if rc != OR_OK:
             raise OracleError(rc, "derive_cnt")
         return out.value
+
+
+def std_error(W, acc2, acc2_sq, k, flags=0) -> float:
+    return float(lib().or_std_error(U128.of(int(W)), U128.of(int(acc2)), U128.of(int(acc2_sq)), int(k),
+                                    int(flags)))
 
 
 def philox4x32_10(ctr, key):

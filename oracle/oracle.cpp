@@ -9,6 +9,7 @@
 #include "graph_internal.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <utility>
@@ -878,6 +879,97 @@ static size_t pick(const std::vector<u128>& wts, u128 r) {
     return wts.size();  // unreachable when r < total
 }
 
+// ------------------------------------------------------------------------
+// Standard error of the estimate (Sec. 4.4, Lemma "unbiased-estimate": the
+// estimate is (W / 2) times the mean of the per-sample terms Y = 2 M_phi /
+// N_phi, so its standard error is (W / 2) s / sqrt(k) with s^2 the unbiased
+// sample variance of Y).  s^2 = D / (k (k - 1)) with D = k sum Y^2 - (sum Y)^2,
+// an exact non-negative integer below 2^256, formed here with 32-bit limbs
+// and rounded once to the nearest double (ties to even).
+// ------------------------------------------------------------------------
+namespace {
+struct Big {  // little-endian 32-bit limbs, 256 bits
+    uint32_t d[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+};
+
+Big big_of(u128 x) {
+    Big b;
+    for (int i = 0; i < 4; ++i) b.d[i] = (uint32_t)(x >> (32 * i));
+    return b;
+}
+
+// schoolbook product; both factors below 2^128, so it fits 256 bits
+Big big_mul(const Big& a, const Big& b) {
+    uint64_t acc[16] = {0};
+    for (int i = 0; i < 8; ++i)
+        for (int j = 0; i + j < 8; ++j) {
+            uint64_t p = (uint64_t)a.d[i] * b.d[j];
+            // add p at limb i + j, carrying upward
+            int at = i + j;
+            while (p != 0 && at < 8) {
+                uint64_t s = acc[at] + (p & 0xffffffffu);
+                acc[at] = s & 0xffffffffu;
+                p = (p >> 32) + (s >> 32);
+                ++at;
+            }
+        }
+    Big r;
+    for (int i = 0; i < 8; ++i) r.d[i] = (uint32_t)acc[i];
+    return r;
+}
+
+// a - b, requires a >= b; returns false (and 0) otherwise
+bool big_sub(const Big& a, const Big& b, Big* r) {
+    int64_t borrow = 0;
+    for (int i = 0; i < 8; ++i) {
+        int64_t x = (int64_t)a.d[i] - (int64_t)b.d[i] - borrow;
+        borrow = x < 0 ? 1 : 0;
+        r->d[i] = (uint32_t)(x + (borrow << 32));
+    }
+    if (borrow) {
+        *r = Big();
+        return false;
+    }
+    return true;
+}
+
+bool big_bit(const Big& a, int i) { return (a.d[i / 32] >> (i % 32)) & 1u; }
+
+// nearest double, ties to even: the 53 bits below and at the top set bit,
+// then the next bit (half) and whether any bit below it is set (sticky)
+double big_to_double(const Big& a) {
+    int top = -1;
+    for (int i = 255; i >= 0 && top < 0; --i)
+        if (big_bit(a, i)) top = i;
+    if (top < 0) return 0.0;
+    uint64_t mant = 0;
+    const int low = top - 52;  // bit position of the mantissa's last bit
+    for (int i = top; i >= (low > 0 ? low : 0); --i) mant = (mant << 1) | (big_bit(a, i) ? 1u : 0u);
+    if (low <= 0) return std::ldexp((double)mant, low < 0 ? 0 : low);
+    const bool half = big_bit(a, low - 1);
+    bool sticky = false;
+    for (int i = low - 2; i >= 0; --i) sticky = sticky || big_bit(a, i);
+    if (half && (sticky || (mant & 1u))) ++mant;  // may carry to 2^53: still exact
+    return std::ldexp((double)mant, low);
+}
+}  // namespace
+
+static double std_error_of(u128 W, u128 acc2, u128 acc2_sq, uint64_t k, uint32_t flags) {
+    if (k < 2 || W == 0 || (flags & 2u)) return 0.0;
+    Big D;
+    if (!big_sub(big_mul(big_of((u128)k), big_of(acc2_sq)), big_mul(big_of(acc2), big_of(acc2)), &D))
+        return 0.0;  // D < 0 cannot happen for sums over at most k samples
+    const double Dd = big_to_double(D);
+    const double kd = (double)k;
+    const double km1 = (double)(k - 1);
+    const double var = Dd / (kd * km1);
+    return ((double)W / 2.0) * std::sqrt(var / kd);
+}
+
+extern "C" double or_std_error(or_u128 W, or_u128 acc2, or_u128 acc2_sq, uint64_t k, uint32_t flags) {
+    return std_error_of(from_or(W), from_or(acc2), from_or(acc2_sq), k, flags);
+}
+
 extern "C" int or_sample(const or_prep* p, uint64_t seed, uint64_t j0, uint64_t count,
                          uint64_t k_total, or_result* res, or_rec* recs) {
     if (!p || !res) return OR_EINVAL;
@@ -969,5 +1061,6 @@ extern "C" int or_sample(const or_prep* p, uint64_t seed, uint64_t j0, uint64_t 
     res->acc2_sq = to_or(acc2_sq);
     // Alg. 6: C^ = (cnt / k) * W with cnt = acc2 / 2.
     res->estimate = k_total ? (double)R.W * ((double)acc2 / (2.0 * (double)k_total)) : 0.0;
+    res->std_error = std_error_of(R.W, acc2, acc2_sq, k_total, res->flags);
     return OR_OK;
 }

@@ -62,8 +62,14 @@ typedef struct {
     int32_t center;
 } or_tree;
 
+/* std_error: the standard error of the estimate (the estimator's sample
+ * standard deviation over sqrt(k), Sec. 4.4, Lemma "unbiased-estimate"):
+ * (W / 2) * sqrt(D / (k^2 (k - 1))) with D = k * acc2_sq - acc2^2 formed
+ * exactly in 256-bit integers and rounded once to double; 0 when k < 2, when
+ * W = 0 or when acc2_sq saturated (flags bit 1). */
 typedef struct {
     double estimate;
+    double std_error;
     or_u128 W;
     or_u128 acc2;      /* sum over samples of 2*M_phi/N_phi */
     or_u128 acc2_sq;   /* sum of squares of the same terms (saturates, see flags) */
@@ -145,6 +151,8 @@ int or_edge_weight(const or_prep* p, int64_t interval, int32_t s, int32_t eid, u
  * the estimate formula.  recs may be NULL. */
 int or_sample(const or_prep* p, uint64_t seed, uint64_t j0, uint64_t count,
               uint64_t k_total, or_result* res, or_rec* recs);
+/* The std_error of a result with these sums (or_result's definition). */
+double or_std_error(or_u128 W, or_u128 acc2, or_u128 acc2_sq, uint64_t k, uint32_t flags);
 /* M_phi for a given image of the tree edges (eids indexed like or_rec.eid);
  * returns OR_EINVAL if the edges do not form a valid sample. */
 int or_derive_cnt(const or_prep* p, const int32_t* eids, or_u128* m_phi);

@@ -681,18 +681,70 @@ extern "C" int tm_weights_intervals(const tm_weights* w, tm_u128* host_out, void
 
 static double u128_to_double(tm_u128 x) { return (double)(((u128)x.hi << 64) | x.lo); }
 
+// Unsigned 256-bit value as (hi, lo) 128-bit halves.
+struct U256 {
+    u128 hi, lo;
+};
+
+// Full 128 x 128 -> 256-bit product from four 64 x 64 -> 128 partial products.
+static U256 mul_wide(u128 a, u128 b) {
+    const u64 a0 = (u64)a, a1 = (u64)(a >> 64), b0 = (u64)b, b1 = (u64)(b >> 64);
+    const u128 p00 = (u128)a0 * b0, p01 = (u128)a0 * b1, p10 = (u128)a1 * b0, p11 = (u128)a1 * b1;
+    // middle column: high half of p00 plus the low halves of the cross terms
+    const u128 mid = (p00 >> 64) + (u64)p01 + (u64)p10;
+    U256 r;
+    r.lo = (mid << 64) | (u64)p00;
+    r.hi = p11 + (p01 >> 64) + (p10 >> 64) + (mid >> 64);
+    return r;
+}
+
+// Nearest double to a 256-bit value (ties to even): shifted down to 128
+// bits with the shifted-out bits folded into bit 0 (they lie far below the
+// 53-bit rounding position, so only whether any was set matters), converted
+// by the compiler's correctly rounded u128 conversion, then scaled back by
+// an exact power of two.
+static double u256_to_double(U256 x) {
+    if (x.hi == 0) return (double)x.lo;
+    const u64 hh = (u64)(x.hi >> 64), hl = (u64)x.hi;
+    const int top = hh ? 255 - __builtin_clzll(hh) : 191 - __builtin_clzll(hl);  // top set bit
+    const int sh = top - 127;                                                     // 1 .. 128
+    const u128 low_mask = sh == 128 ? ~(u128)0 : (((u128)1 << sh) - 1);
+    const bool sticky = (x.lo & low_mask) != 0;
+    const u128 v = sh == 128 ? x.hi : ((x.hi << (128 - sh)) | (x.lo >> sh));
+    return __builtin_ldexp((double)(v | (sticky ? 1 : 0)), sh);
+}
+
+// The estimate (Alg. 6) and its standard error (Sec. 4.4, Lemma
+// "unbiased-estimate": the estimate is W / 2 times the mean of the terms
+// Y = 2 M_phi / N_phi, so its standard error is (W / 2) s / sqrt(k) with s^2
+// the unbiased sample variance).  s^2 = D / (k (k - 1)) with
+// D = k sum Y^2 - (sum Y)^2, formed exactly in 256 bits from the exact sums
+// and rounded once; 0 when k < 2, W = 0 or the sum of squares saturated.
 void finish_result(tm_result* r) {
     const double W = u128_to_double(r->W);
     const double acc2 = u128_to_double(r->acc2);
     const double k = (double)r->k;
     r->estimate = r->k ? W * (acc2 / (2.0 * k)) : 0.0;
     r->std_error = 0.0;
-    if (r->k > 1 && !(r->flags & TM_F_SQ_SATURATED)) {
-        const double mean = acc2 / k;
-        double var = (u128_to_double(r->acc2_sq) - k * mean * mean) / (k - 1.0);
-        if (var < 0) var = 0;
-        r->std_error = (W / 2.0) * __builtin_sqrt(var / k);
-    }
+    const u128 Wx = ((u128)r->W.hi << 64) | r->W.lo;
+    if (r->k < 2 || Wx == 0 || (r->flags & TM_F_SQ_SATURATED)) return;
+    const u128 s1 = ((u128)r->acc2.hi << 64) | r->acc2.lo;
+    const u128 s2 = ((u128)r->acc2_sq.hi << 64) | r->acc2_sq.lo;
+    const U256 a = mul_wide((u128)r->k, s2), b = mul_wide(s1, s1);
+    if (a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo)) return;  // not for sums over at most k samples
+    U256 D;
+    D.lo = a.lo - b.lo;
+    D.hi = a.hi - b.hi - (a.lo < b.lo ? 1 : 0);
+    const double Dd = u256_to_double(D);
+    const double km1 = (double)(r->k - 1);
+    const double var = Dd / (k * km1);
+    r->std_error = (W / 2.0) * __builtin_sqrt(var / k);
+}
+
+extern "C" int tm_result_finish(tm_result* r) {
+    if (!r) return tm_fail(TM_EINVAL, "result_finish: NULL");
+    finish_result(r);
+    return TM_OK;
 }
 
 extern "C" int tm_sample(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count,
@@ -714,8 +766,8 @@ extern "C" int tm_sample_model_bytes(tm_weights* w, uint64_t seed, uint64_t j0, 
 }
 
 extern "C" int tm_estimate(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint64_t k,
-                           uint64_t seed, void* stream, tm_result* out) {
-    return tm_estimate_ex(g, mo, tr, TM_C_ALL, k, seed, stream, out);
+                           uint64_t seed, void* stream, tm_result* out, tm_sample_rec* recs) {
+    return tm_estimate_ex(g, mo, tr, TM_C_ALL, k, seed, stream, out, recs);
 }
 
 namespace {
@@ -725,7 +777,7 @@ namespace {
 // build checks for overflow only at its end anyway).  *done is false when
 // the 64-bit tables overflowed: the caller then runs the synchronous path.
 int estimate_enqueued(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32_t constraints, u64 k, u64 seed,
-                      hipStream_t st, tm_result* out, bool* done) {
+                      hipStream_t st, tm_result* out, tm_sample_rec* recs, bool* done) {
     *done = false;
     if (constraints & ~(uint32_t)TM_C_ALL) return tm_fail(TM_EINVAL, "weights: constraints %u", constraints);
     TM_TRY(motif_check(mo));
@@ -752,7 +804,7 @@ int estimate_enqueued(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32
         tw.stop();
     }
     bool overflowed = false;
-    if (rc == TM_OK) rc = sample_run(w, seed, 0, k, k, st, out, nullptr, nullptr, flag, &overflowed);
+    if (rc == TM_OK) rc = sample_run(w, seed, 0, k, k, st, out, recs, nullptr, flag, &overflowed);
     // sample_run synchronised the stream (on success)
     if (sync_stream(st) != hipSuccess && rc == TM_OK) rc = tm_fail(TM_EDEVICE, "estimate: synchronise");
     tw.finish();
@@ -766,11 +818,11 @@ int estimate_enqueued(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32
 }  // namespace
 
 extern "C" int tm_estimate_ex(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32_t constraints,
-                              uint64_t k, uint64_t seed, void* stream, tm_result* out) {
+                              uint64_t k, uint64_t seed, void* stream, tm_result* out, tm_sample_rec* recs) {
     if (!out) return tm_fail(TM_EINVAL, "estimate: NULL output");
     if (g && k > 0 && g->m > 0 && g->m < ((int64_t)1 << 23)) {
         bool done = false;
-        TM_TRY(estimate_enqueued(g, mo, tr, constraints, k, seed, as_stream(stream), out, &done));
+        TM_TRY(estimate_enqueued(g, mo, tr, constraints, k, seed, as_stream(stream), out, recs, &done));
         if (done) {
             finish_result(out);
             out->status = TM_OK;
@@ -779,7 +831,7 @@ extern "C" int tm_estimate_ex(tm_graph* g, const tm_motif* mo, const tm_tree* tr
     }
     tm_weights* w = nullptr;
     TM_TRY(tm_weights_create_ex(g, mo, tr, constraints, stream, &w));
-    const int rc = tm_sample(w, seed, 0, k, k, stream, out, nullptr);
+    const int rc = tm_sample(w, seed, 0, k, k, stream, out, recs);
     tm_weights_destroy(w);
     return rc;
 }
@@ -796,6 +848,27 @@ extern "C" int tm_batch_config(int tile, int blocks, int* prev_tile, int* prev_b
     if (prev_blocks) *prev_blocks = g_batch_config.blocks;
     g_batch_config.tile = tile;
     g_batch_config.blocks = blocks;
+    return TM_OK;
+}
+
+extern "C" int tm_batch_options(const tm_batch_opts* in, tm_batch_opts* prev) {
+    if (in && (in->tile < 256 || in->blocks < 0 || in->root_lds < 0 || in->root_lds > 65536))
+        return tm_fail(TM_EINVAL, "batch_options: tile %d, blocks %d, root_lds %d", in->tile, in->blocks,
+                       in->root_lds);
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    if (prev) {
+        prev->tile = g_batch_config.tile;
+        prev->blocks = g_batch_config.blocks;
+        prev->root_lds = g_batch_config.root_lds;
+        prev->pad = 0;
+        prev->group_limit = g_batch_config.group_limit;
+    }
+    if (in) {
+        g_batch_config.tile = in->tile;
+        g_batch_config.blocks = in->blocks;
+        g_batch_config.root_lds = in->root_lds;
+        g_batch_config.group_limit = in->group_limit;
+    }
     return TM_OK;
 }
 
@@ -1102,7 +1175,7 @@ extern "C" int tm_batch_plan_run(tm_batch_plan* p, void* stream, tm_result* out)
         tm_result& o = out[i];
         if (hflags[i]) {
             // 64 bits do not hold this job's weights: the 128-bit path, eagerly
-            TM_TRY(tm_estimate(p->g[i], &p->mo[i], &p->tr[i], p->k[i], p->seed[i], stream, &o));
+            TM_TRY(tm_estimate(p->g[i], &p->mo[i], &p->tr[i], p->k[i], p->seed[i], stream, &o, nullptr));
             continue;
         }
         std::memset(&o, 0, sizeof o);

@@ -1420,7 +1420,7 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
 // ---------------------------------------------------------------------------
 // Host side of batched sampling.
 // ---------------------------------------------------------------------------
-BatchConfig g_batch_config = {8192, 0};
+BatchConfig g_batch_config = {8192, 0, 0, kCumLdsBytes};
 
 void sums_merge(JobSums& into, const JobSums& x) {
     if (!add_ok(into.acc2, x.acc2, &into.acc2)) into.flags |= 1;
@@ -1510,7 +1510,12 @@ void group_prepare(tm_weights* const* ws, const std::vector<int>& act, const u64
         G.args[y].key_base = key_base[y];
         G.args[y].Wdev = Wdev ? Wdev[y] : nullptr;
         G.args[y].wflag = wflag ? wflag[y] : nullptr;
-        if (G.args[y].cum_in_lds) G.root_lds = kCumLdsBytes;
+        // the root draws stage the interval prefix in LDS when it fits the
+        // configured size (jobs with a root guide read one or two entries)
+        const tm_weights* wy = ws[act[y]];
+        const size_t cum_bytes = (size_t)(wy->q + 1) * (wy->wide ? 16 : 8);
+        G.args[y].cum_in_lds = !wy->guide && cum_bytes <= (size_t)cfg.root_lds;
+        if (G.args[y].cum_in_lds) G.root_lds = (size_t)cfg.root_lds;
         base[y] = off;
         off += counts[act[y]];
     }
@@ -1708,8 +1713,10 @@ int batch_sample_pass(tm_weights* const* ws, const u64* j0s, const u64* counts, 
         if (w->W != 0 && counts[x] > 0) act.push_back(x);
     }
     // groups in job order whose key ranges (2 m per job) and sample counts
-    // each stay below 2^32; a job alone beyond that samples on its own
+    // each stay below 2^32 (or the configured smaller limit); a job of 2^32
+    // samples or more samples on its own
     const u64 lim = (u64)1 << 32;
+    const u64 glim = cfg.group_limit > 0 && cfg.group_limit < lim ? cfg.group_limit : lim;
     std::vector<int> grp;
     u64 keys = 0, cnt = 0;
     auto flush = [&]() -> int {
@@ -1741,7 +1748,7 @@ int batch_sample_pass(tm_weights* const* ws, const u64* j0s, const u64* counts, 
             h.flags = (r.flags & TM_F_SQ_SATURATED) ? 2 : 0;
             continue;
         }
-        if (keys + kx > lim || cnt + counts[x] >= lim) TM_TRY(flush());
+        if (keys + kx > glim || cnt + counts[x] >= glim) TM_TRY(flush());
         grp.push_back(x);
         keys += kx;
         cnt += counts[x];
@@ -1764,6 +1771,7 @@ int batch_capture_enqueue(tm_weights* const* ws, const int* const* wflag, const 
     if (!P) return tm_fail(TM_ENOMEM, "capture: host allocation");
     P->n = n;
     const u64 lim = (u64)1 << 32;
+    const u64 glim = cfg.group_limit > 0 && cfg.group_limit < lim ? cfg.group_limit : lim;
     std::vector<int> act;
     u64 keys = 0, cnt = 0;
     std::vector<u64> j0(n, 0);
@@ -1794,7 +1802,7 @@ int batch_capture_enqueue(tm_weights* const* ws, const int* const* wflag, const 
         if (w->plan.nt < 1 || w->plan.nt > 7) return tm_fail(TM_EINVAL, "capture: job %d tree size", x);
         if (counts[x] >= lim) return tm_fail(TM_EINVAL, "capture: job %d draws 2^32 samples or more", x);
         const u64 kx = 2 * (u64)w->g->m;
-        if (keys + kx > lim || cnt + counts[x] >= lim) {
+        if (keys + kx > glim || cnt + counts[x] >= glim) {
             const int rc = flush();
             if (rc != TM_OK) {
                 batch_capture_free(P.release(), st);

@@ -236,8 +236,10 @@ void sums_to_result(const JobSums& s, tm_result* out);
 // Batched sampling of several weight sets in one pass (tile: samples per work
 // item of the persistent kernels; blocks: their grid, 0 = 8 per CU).
 struct BatchConfig {
-    int tile;
-    int blocks;
+    int tile;          // samples per tile (each of a workgroup's lanes takes tile / kBlock)
+    int blocks;        // persistent grid (0: 8 workgroups per CU)
+    u64 group_limit;   // root keys and samples per batched pass (0: 2^32)
+    int root_lds;      // LDS bytes staging a job's interval prefix in the root draws
 };
 extern BatchConfig g_batch_config;
 // Samples j0[x] .. j0[x] + count[x] - 1 of every job x with W > 0; per-job

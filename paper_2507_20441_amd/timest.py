@@ -7,6 +7,7 @@ is missing; there is no CPU fallback.
 """
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -80,6 +81,11 @@ REC_DTYPE = np.dtype([("interval", "<u4"), ("status", "<u4"), ("n_phi", "<u4"), 
 U128_DTYPE = np.dtype([("lo", "<u8"), ("hi", "<u8")])
 
 
+class BatchOpts(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("blocks", C.c_int32), ("root_lds", C.c_int32), ("pad", C.c_int32),
+                ("group_limit", C.c_uint64)]
+
+
 class TimestError(RuntimeError):
     def __init__(self, code, what, detail):
         super().__init__(f"{what}: {detail} (code {code})")
@@ -111,7 +117,7 @@ def lib():
         L.tm_weights_create_ex.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), C.c_uint32, vp,
                                            C.POINTER(vp)]
         L.tm_estimate_ex.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), C.c_uint32, u64, u64, vp,
-                                     C.POINTER(Result)]
+                                     C.POINTER(Result), vp]
         L.tm_weights_destroy.argtypes = [vp]
         L.tm_weights_destroy.restype = None
         L.tm_weights_info.argtypes = [vp, C.POINTER(U128), C.POINTER(i64), C.POINTER(i32),
@@ -119,14 +125,16 @@ def lib():
         L.tm_weights_export.argtypes = [vp, i32, i32, vp, vp]
         L.tm_weights_intervals.argtypes = [vp, vp, vp]
         L.tm_sample.argtypes = [vp, u64, u64, u64, u64, vp, C.POINTER(Result), vp]
+        L.tm_result_finish.argtypes = [C.POINTER(Result)]
         L.tm_estimate.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), u64, u64, vp,
-                                  C.POINTER(Result)]
+                                  C.POINTER(Result), vp]
         L.tm_sample_batch.argtypes = [C.POINTER(vp), C.POINTER(u64), C.POINTER(u64), C.c_int, vp,
                                       C.POINTER(Result)]
         L.tm_estimate_batch.argtypes = [C.POINTER(vp), C.POINTER(Motif), C.POINTER(C.POINTER(Tree)),
                                         C.POINTER(u64), C.POINTER(u64), C.c_int, vp,
                                         C.POINTER(Result)]
         L.tm_batch_config.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.tm_batch_options.argtypes = [C.POINTER(BatchOpts), C.POINTER(BatchOpts)]
         L.tm_list_instances.argtypes = [vp, u64, u64, u64, vp, vp, vp]
         L.tm_sample_family.argtypes = [vp, C.POINTER(Motif), C.c_int, u64, u64, vp, C.POINTER(Result)]
         L.tm_tree_candidates.argtypes = [C.POINTER(Motif), C.POINTER(Tree), C.POINTER(i64), C.c_int,
@@ -157,6 +165,26 @@ def lib():
         L.tm_server_destroy.restype = None
         _lib = L
     return _lib
+
+
+def _release(destroy, h):
+    destroy(h)
+
+
+def _own(obj, destroy, h):
+    """Tie handle h to obj: released by obj.close(), when obj is collected, or
+    at interpreter exit (before module teardown, latest handle first) -- the
+    finalizer holds the destroy function itself, so it needs no module
+    globals then."""
+    obj.h = h
+    obj._fin = weakref.finalize(obj, _release, destroy, h)
+
+
+def _disown(obj):
+    fin = getattr(obj, "_fin", None)
+    if fin is not None:
+        fin()
+    obj.h = None
 
 
 def _check(rc, what):
@@ -227,14 +255,10 @@ class Graph:
                                        tt.ctypes.data_as(C.c_void_p), self.m, self.n, TM_PTR_HOST,
                                        _stream(), C.byref(h))
         _check(rc, "graph_create")
-        self.h = h
+        _own(self, lib().tm_graph_destroy, h)
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().tm_graph_destroy(self.h)
-            self.h = None
-
-    __del__ = close
+        _disown(self)
 
     def info(self):
         m, n, sh, sp, b = C.c_int64(), C.c_int32(), C.c_int64(), C.c_int64(), C.c_uint64()
@@ -260,14 +284,10 @@ class Weights:
         c = TM_C_ALL if constraints is None else int(constraints)
         _check(lib().tm_weights_create_ex(g.h, C.byref(mo), C.byref(tr) if tr is not None else None, c,
                                           _stream(), C.byref(h)), "weights_create")
-        self.h = h
+        _own(self, lib().tm_weights_destroy, h)
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().tm_weights_destroy(self.h)
-            self.h = None
-
-    __del__ = close
+        _disown(self)
 
     def info(self):
         W, q, wide, b, tr = U128(), C.c_int64(), C.c_int32(), C.c_uint64(), Tree()
@@ -311,11 +331,25 @@ class Weights:
         return res, recs
 
 
-def estimate(g: Graph, mo: Motif, k, seed, tr: Tree = None, constraints=None) -> Result:
+def estimate(g: Graph, mo: Motif, k, seed, tr: Tree = None, constraints=None, records=False):
+    """tm_estimate_ex: a Result, or (Result, records) when records=True."""
+    import torch
     res = Result()
     c = TM_C_ALL if constraints is None else int(constraints)
+    recs_dev, ptr = None, None
+    if records and k > 0:
+        recs_dev = torch.empty(int(k) * REC_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        ptr = C.c_void_p(recs_dev.data_ptr())
     _check(lib().tm_estimate_ex(g.h, C.byref(mo), C.byref(tr) if tr is not None else None, c, int(k),
-                                int(seed), _stream(), C.byref(res)), "estimate")
+                                int(seed), _stream(), C.byref(res), ptr), "estimate")
+    if not records:
+        return res
+    return res, (recs_dev.cpu().numpy().view(REC_DTYPE) if recs_dev is not None else np.zeros(0, REC_DTYPE))
+
+
+def result_finish(res: "Result") -> "Result":
+    """tm_result_finish: recompute estimate and std_error from the sums."""
+    _check(lib().tm_result_finish(C.byref(res)), "result_finish")
     return res
 
 
@@ -324,6 +358,21 @@ def batch_config(tile, blocks=0):
     pt, pb = C.c_int(), C.c_int()
     _check(lib().tm_batch_config(int(tile), int(blocks), C.byref(pt), C.byref(pb)), "batch_config")
     return pt.value, pb.value
+
+
+def batch_options(tile=None, blocks=None, root_lds=None, group_limit=None) -> dict:
+    """tm_batch_options: set the given fields (others unchanged); returns the
+    previous schedule as a dict (pass it back as **kwargs to restore)."""
+    prev = BatchOpts()
+    _check(lib().tm_batch_options(None, C.byref(prev)), "batch_options")
+    old = dict(tile=prev.tile, blocks=prev.blocks, root_lds=prev.root_lds, group_limit=prev.group_limit)
+    new = dict(old)
+    for k, v in (("tile", tile), ("blocks", blocks), ("root_lds", root_lds), ("group_limit", group_limit)):
+        if v is not None:
+            new[k] = int(v)
+    o = BatchOpts(new["tile"], new["blocks"], new["root_lds"], 0, new["group_limit"])
+    _check(lib().tm_batch_options(C.byref(o), None), "batch_options")
+    return old
 
 
 def sample_batch(weights, ks, seeds):
@@ -368,7 +417,7 @@ class Server:
         o = ServerOpts(int(pass_samples), int(job_chunk), int(max_jobs), 1 if fifo else 0)
         h = C.c_void_p()
         _check(lib().tm_server_create(int(budget_bytes), C.byref(o), C.byref(h)), "server_create")
-        self.h = h
+        _own(self, lib().tm_server_destroy, h)
         self._graphs = []
 
     def add_graph(self, g: Graph) -> int:
@@ -404,9 +453,7 @@ class Server:
         return st.as_dict()
 
     def close(self):
-        if self.h:
-            lib().tm_server_destroy(self.h)
-            self.h = None
+        _disown(self)
 
     def __enter__(self):
         return self
@@ -465,7 +512,7 @@ class BatchPlan:
             tr = (C.POINTER(Tree) * n)(*keep)
         h = C.c_void_p()
         _check(lib().tm_batch_plan_create(hs, mo, tr, kk, ss, n, _stream(), C.byref(h)), "batch_plan_create")
-        self.h = h
+        _own(self, lib().tm_batch_plan_destroy, h)
         self.n = n
 
     def run(self):
@@ -474,12 +521,7 @@ class BatchPlan:
         return list(out)
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().tm_batch_plan_destroy(self.h)
-            self.h = None
-
-    def __del__(self):
-        self.close()
+        _disown(self)
 
 
 def tree_candidates(mo: Motif):

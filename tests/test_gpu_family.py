@@ -53,7 +53,7 @@ def test_family_equals_separate_oracle_runs(T, k):
         assert r.acc2.value == o.acc2.value and r.acc2_sq.value == o.acc2_sq.value, name
         assert (r.n_valid, r.n_bad_vertex, r.n_bad_delta, r.n_bad_order, r.n_nonzero) == \
                (o.n_valid, o.n_bad_vertex, o.n_bad_delta, o.n_bad_order, o.n_nonzero), name
-        assert r.estimate == o.estimate, name
+        assert r.estimate == o.estimate and r.std_error == o.std_error, name
     w.close()
 
 

@@ -123,7 +123,7 @@ def check_prep(T, og, tg, edges, delta, otr, seeds=(1, 2), k=3000, g=None, const
         assert rg.acc2.value == ro.acc2.value and rg.acc2_sq.value == ro.acc2_sq.value
         assert (rg.n_valid, rg.n_bad_vertex, rg.n_bad_delta, rg.n_bad_order, rg.n_nonzero) == \
                (ro.n_valid, ro.n_bad_vertex, ro.n_bad_delta, ro.n_bad_order, ro.n_nonzero)
-        assert rg.estimate == ro.estimate
+        assert rg.estimate == ro.estimate and rg.std_error == ro.std_error
     return P, Wt
 
 
@@ -207,7 +207,7 @@ def test_tiny_workload_full_run_is_bit_identical(T):
     ro, reco = P.sample(W.TINY["seed"], W.TINY["k"], records=True)
     rg, recg = Wt.sample(W.TINY["seed"], W.TINY["k"], records=True)
     assert rec_equal(reco, recg)
-    assert rg.estimate == ro.estimate and rg.acc2.value == ro.acc2.value
+    assert rg.estimate == ro.estimate and rg.acc2.value == ro.acc2.value and rg.std_error == ro.std_error
     C = og.brute_count(omo)
     assert abs(rg.estimate - C) <= 0.05 * C, (rg.estimate, C)
 
@@ -244,6 +244,24 @@ def test_zero_weight_and_empty_graph(T):
     eg = T.Graph(e.astype(np.int32), e.astype(np.int32), e, 4)
     res = T.estimate(eg, tmo, 100, 1)
     assert res.W.value == 0 and res.estimate == 0.0
+
+
+@pytest.mark.parametrize("m,delta,k", [(3000, 300, 5000), (30000, 2000, 70000)])
+def test_estimate_records_match_oracle(T, m, delta, k):
+    """tm_estimate with records (the enqueued build-and-sample form below 2^23
+    edges; 70,000 samples take the root-sorted launch): every record and sum
+    against the oracle's run."""
+    g = W.small_graph(m, 23, n=max(60, m // 25), span=40 * delta)
+    og, tg = pair(T, g)
+    for name in ("4cycle", "lead_trail"):
+        edges = dict((c[0], c[1]) for c in MOTIF_CASES)[name]
+        omo, tmo = motifs_for(T, edges, delta)
+        say("estimate records", m, name)
+        ro, reco = O.Prep(og, omo).sample(9, k, records=True)
+        rg, recg = T.estimate(tg, tmo, k, 9, records=True)
+        assert rec_equal(reco, recg)
+        assert rg.acc2.value == ro.acc2.value and rg.acc2_sq.value == ro.acc2_sq.value
+        assert rg.estimate == ro.estimate and rg.std_error == ro.std_error
 
 
 def test_sample_ranges_compose(T):
@@ -301,7 +319,11 @@ def test_medium_workload_full_size(T, medium, name):
               ((0, 2_500_000), (2_500_000, 6_000_001), (6_000_001, k))]
     assert sum(p.acc2.value for p in pieces) == full.acc2.value
     assert sum(p.n_valid for p in pieces) == full.n_valid
+    assert sum(p.acc2_sq.value for p in pieces) == full.acc2_sq.value
     assert full.estimate == float(P.W) * (float(full.acc2.value) / (2.0 * k))
+    # the standard error of the whole run: the oracle's evaluation of the same sums
+    assert full.std_error == O.std_error(P.W, full.acc2.value, full.acc2_sq.value, k, full.flags)
+    assert 0 < full.std_error < 0.05 * full.estimate
 
 
 # ---------------------------------------------------------------------------

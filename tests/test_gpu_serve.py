@@ -126,7 +126,7 @@ def test_oracle_agrees(T, world):
             P = O.Prep(og, O.make_motif(W.MOTIFS[n], d))
             o = P.sample(s, k)[0]
             assert r.acc2.value == o.acc2.value and r.W.value == P.W and r.n_valid == o.n_valid, n
-            assert r.estimate == o.estimate
+            assert r.estimate == o.estimate and r.std_error == o.std_error
     finally:
         srv.close()
 
