@@ -32,7 +32,8 @@ class U128(C.Structure):
 
 class Motif(C.Structure):
     _fields_ = [("k", C.c_int32), ("l", C.c_int32), ("src", C.c_int32 * 16),
-                ("dst", C.c_int32 * 16), ("delta", C.c_int64)]
+                ("dst", C.c_int32 * 16), ("delta", C.c_int64), ("partial", C.c_uint32),
+                ("before", C.c_uint16 * 16)]
 
 
 class Tree(C.Structure):
@@ -120,14 +121,20 @@ def _ptr(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
 
 
-def make_motif(edges, delta, k=None) -> Motif:
-    """edges: list of (src, dst) in pi order."""
+def make_motif(edges, delta, k=None, before=None) -> Motif:
+    """edges: list of (src, dst) in pi order.  before: None for the total
+    order of the list, else a partial order as pairs (p, q), edge p strictly
+    earlier than edge q (p < q)."""
     mo = Motif()
     mo.l = len(edges)
     mo.k = k if k is not None else 1 + max(max(e) for e in edges)
     for p, (a, b) in enumerate(edges):
         mo.src[p], mo.dst[p] = a, b
     mo.delta = int(delta)
+    if before is not None:
+        mo.partial = 1
+        for p, q in before:
+            mo.before[q] |= 1 << p
     return mo
 
 

@@ -22,13 +22,75 @@ static or_u128 to_or(u128 x) { return or_u128{(uint64_t)x, (uint64_t)(x >> 64)};
 // mapped with direction, times strictly increasing in pi order, every pair of
 // times within delta.  Backtracking over the motif edges in pi order.
 // ------------------------------------------------------------------------
+// The time constraints of a motif as a relation: before_of(mo, p, q) is true
+// when edge p must be strictly earlier than edge q -- every p < q for the
+// total order of the list; for a partial order, the given pairs and every
+// pair they imply through a chain of given pairs.
+static bool before_of(const or_motif* mo, int p, int q) {
+    if (p < 0 || q < 0 || p >= mo->l || q >= mo->l || p == q) return false;
+    if (!mo->partial) return p < q;
+    // reachability from p to q along given pairs (depth-first)
+    bool seen[16] = {false};
+    int stack[16], top = 0;
+    stack[top++] = p;
+    seen[p] = true;
+    while (top > 0) {
+        const int a = stack[--top];
+        for (int b = 0; b < mo->l; ++b) {
+            if (seen[b] || !((mo->before[b] >> a) & 1u)) continue;
+            if (b == q) return true;
+            seen[b] = true;
+            stack[top++] = b;
+        }
+    }
+    return false;
+}
+
 struct CountCtx {
     const or_graph* g;
     const or_motif* mo;
     int32_t img[8];
     int64_t t0;
     u128 count;
+    int32_t eid[16];  // partial orders: the edge matched to each motif edge so far
 };
+
+// Partial orders: motif edges in list order, each over every edge of G; an
+// edge is kept when the vertex map stays consistent and 1-1, it differs from
+// the edges matched so far, every constraint with an earlier matched edge
+// holds, and all matched times stay within delta.
+static void count_po_rec(CountCtx& C, int p) {
+    const or_motif& M = *C.mo;
+    if (p == M.l) { ++C.count; return; }
+    const int x = M.src[p], y = M.dst[p];
+    for (int64_t id = 0; id < C.g->m; ++id) {
+        const OEdge& E = C.g->e[id];
+        bool ok = true;
+        for (int z = 0; z < M.k && ok; ++z) {
+            if (z == x || z == y || C.img[z] < 0) continue;
+            if (C.img[z] == E.u || C.img[z] == E.v) ok = false;
+        }
+        if (!ok) continue;
+        if (C.img[x] >= 0 && C.img[x] != E.u) continue;
+        if (C.img[y] >= 0 && C.img[y] != E.v) continue;
+        for (int q = 0; q < p && ok; ++q) {
+            const OEdge& F = C.g->e[C.eid[q]];
+            if (C.eid[q] == id) ok = false;
+            if (before_of(&M, q, p) && !(F.t < E.t)) ok = false;
+            if (before_of(&M, p, q) && !(E.t < F.t)) ok = false;
+            if (F.t - E.t > M.delta || E.t - F.t > M.delta) ok = false;
+        }
+        if (!ok) continue;
+        const int32_t sx = C.img[x], sy = C.img[y];
+        C.img[x] = E.u;
+        C.img[y] = E.v;
+        C.eid[p] = (int32_t)id;
+        count_po_rec(C, p + 1);
+        C.eid[p] = -1;
+        C.img[x] = sx;
+        C.img[y] = sy;
+    }
+}
 
 static void count_rec(CountCtx& C, int p, int64_t tprev) {
     const or_motif& M = *C.mo;
@@ -72,6 +134,15 @@ static bool motif_basic_ok(const or_motif* mo) {
         if (mo->src[p] < 0 || mo->src[p] >= mo->k || mo->dst[p] < 0 || mo->dst[p] >= mo->k ||
             mo->src[p] == mo->dst[p])
             return false;
+    if (mo->partial > 1) return false;
+    if (mo->partial) {
+        for (int q = 0; q < 16; ++q)
+            for (int p = 0; p < 16; ++p)
+                if (((mo->before[q] >> p) & 1u) && (p >= q || q >= mo->l)) return false;
+        for (int p = 0; p < mo->l; ++p)
+            for (int q = p + 1; q < mo->l; ++q)
+                if (mo->src[p] == mo->src[q] && mo->dst[p] == mo->dst[q] && !before_of(mo, p, q)) return false;
+    }
     return true;
 }
 
@@ -83,7 +154,11 @@ extern "C" int or_brute_count(const or_graph* g, const or_motif* mo, or_u128* ou
     for (int z = 0; z < 8; ++z) C.img[z] = -1;
     C.t0 = 0;
     C.count = 0;
-    count_rec(C, 0, 0);
+    for (int z = 0; z < 16; ++z) C.eid[z] = -1;
+    if (mo->partial)
+        count_po_rec(C, 0);
+    else
+        count_rec(C, 0, 0);
     *out = to_or(C.count);
     return OR_OK;
 }
@@ -172,8 +247,10 @@ struct PMCtx {
 static bool parent_child_ok(const PMCtx& C, int s, int c, const OEdge& Ep, const OEdge& Ec) {
     const int sh = shared_vertices(Ep, Ec);
     if (C.exclude ? sh != 1 : sh < 1) return false;
-    if (c > s) return Ec.t >= Ep.t && Ec.t <= Ep.t + C.delta;
-    return Ec.t >= Ep.t - C.delta && Ec.t <= Ep.t;
+    const or_motif* mo = C.T->mo;
+    if (before_of(mo, s, c)) return Ec.t >= Ep.t && Ec.t <= Ep.t + C.delta;
+    if (before_of(mo, c, s)) return Ec.t >= Ep.t - C.delta && Ec.t <= Ep.t;
+    return Ec.t >= Ep.t - C.delta && Ec.t <= Ep.t + C.delta;  // unordered pair
 }
 
 static void pm_rec(PMCtx& C, int idx) {
@@ -283,10 +360,16 @@ extern "C" int or_brute_edge_weight(const or_graph* g, const or_motif* mo, const
 static void completion_rec(const or_graph* g, const or_motif* mo, const Tree& T, int32_t* img_e,
                            const int32_t* img_v, int p, u128* count) {
     if (p == mo->l) {
-        // times strictly increasing in pi order and within delta
-        for (int a = 1; a < mo->l; ++a)
-            if (!(g->e[img_e[a - 1]].t < g->e[img_e[a]].t)) return;
-        if (g->e[img_e[mo->l - 1]].t - g->e[img_e[0]].t > mo->delta) return;
+        // every constrained pair strictly in order, distinct edges (the edge
+        // map is 1-1), every pair of times within delta
+        for (int a = 0; a < mo->l; ++a)
+            for (int b = 0; b < mo->l; ++b) {
+                if (a == b) continue;
+                if (img_e[a] == img_e[b]) return;
+                const int64_t ta = g->e[img_e[a]].t, tb = g->e[img_e[b]].t;
+                if (before_of(mo, a, b) && !(ta < tb)) return;
+                if (tb - ta > mo->delta) return;
+            }
         ++*count;
         return;
     }
@@ -349,9 +432,9 @@ extern "C" int64_t or_brute_partial_matches_ex(const or_graph* g, const or_motif
             for (int y = x + 1; y < mo->k; ++y)
                 if (img_v[x] == img_v[y]) { st = 1; break; }
         if (st == 0 && tmax - tmin > mo->delta) st = 2;
-        if (st == 0)
-            for (int b = 1; b < T.n_sorted; ++b)
-                if (!(g->e[f[b - 1]].t < g->e[f[b]].t)) { st = 3; break; }
+        for (int a2 = 0; a2 < T.n_sorted && st == 0; ++a2)
+            for (int b = 0; b < T.n_sorted; ++b)
+                if (before_of(mo, T.sorted[a2], T.sorted[b]) && !(g->e[f[a2]].t < g->e[f[b]].t)) { st = 3; break; }
         if (status) status[a] = st;
         u128 cnt = 0;
         bool injective = true;

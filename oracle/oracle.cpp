@@ -112,8 +112,42 @@ static size_t first_at_or_after(const or_graph& g, const std::vector<int32_t>& L
 // Motif and spanning tree (Def. "temporal motif", Def. "dependency list",
 // Def. "spanning tree of a temporal motif").
 // ------------------------------------------------------------------------
+// The time-order relation of the motif: R[q] holds edge p when p must be
+// strictly earlier than q.  Total order: every p < q.  Partial order: the
+// transitive closure of the given pairs (each p < q, so one pass in q order
+// closes it).
+static void order_relation(const or_motif* mo, uint16_t R[16]) {
+    for (int q = 0; q < 16; ++q) {
+        R[q] = 0;
+        if (q >= mo->l) continue;
+        if (!mo->partial) {
+            R[q] = (uint16_t)((1u << q) - 1u);
+            continue;
+        }
+        uint16_t r = mo->before[q];
+        for (int p = 0; p < q; ++p)
+            if ((mo->before[q] >> p) & 1u) r |= R[p];
+        R[q] = r;
+    }
+}
+
+static bool precedes(const uint16_t R[16], int p, int q) { return (R[q] >> p) & 1u; }
+
 static bool motif_ok(const or_motif* mo) {
     if (!mo || mo->k < 2 || mo->k > 8 || mo->l < 1 || mo->l > 16) return false;
+    if (mo->partial > 1) return false;
+    if (mo->partial) {
+        // pairs only from an earlier listed edge to a later one
+        for (int q = 0; q < 16; ++q)
+            if (mo->before[q] & (uint16_t)~((1u << (q < mo->l ? q : 0)) - 1u)) return false;
+        uint16_t R[16];
+        order_relation(mo, R);
+        // parallel motif edges must be ordered: otherwise both could take the
+        // same graph edge and the edge map would not be 1-1
+        for (int p = 0; p < mo->l; ++p)
+            for (int q = p + 1; q < mo->l; ++q)
+                if (mo->src[p] == mo->src[q] && mo->dst[p] == mo->dst[q] && !precedes(R, p, q)) return false;
+    }
     if (mo->delta < 1 || mo->delta >= kMaxSpan) return false;
     for (int p = 0; p < mo->l; ++p) {
         if (mo->src[p] < 0 || mo->src[p] >= mo->k || mo->dst[p] < 0 || mo->dst[p] >= mo->k) return false;
@@ -158,13 +192,14 @@ static bool tree_ok(const or_motif* mo, const or_tree* tr) {
 
 struct Plan {
     or_motif mo;
+    uint16_t R[16];      // time-order relation: R[q] holds p when p is strictly earlier than q
     int center = -1;
     bool in_tree[16] = {false};
     int parent[16];
     int attach[16];      // motif vertex shared with the parent edge
     int lower[16];       // v_s: the endpoint of s further from the center
     int alpha[16];       // +1: child leaves the attach vertex; -1: enters it
-    int beta[16];        // -1: child precedes its parent in pi ('<'); +1: follows ('>')
+    int beta[16];        // -1: child precedes its parent ('<'); +1: follows ('>'); 0: unordered
     int height[16];
     int H = 0;
     std::vector<int> children[16];
@@ -182,7 +217,9 @@ static void attach_children(Plan& P, int s, int z) {
         P.attach[p] = z;
         P.lower[p] = (P.mo.src[p] == z) ? P.mo.dst[p] : P.mo.src[p];
         P.alpha[p] = (P.mo.src[p] == z) ? +1 : -1;
-        P.beta[p] = (p < s) ? -1 : +1;
+        // '<' when the child must precede its parent, '>' when it must
+        // follow, '~' (0) when a partial order leaves the pair unordered
+        P.beta[p] = precedes(P.R, p, s) ? -1 : (precedes(P.R, s, p) ? +1 : 0);
         P.children[s].push_back(p);
         attach_children(P, p, P.lower[p]);
     }
@@ -202,6 +239,7 @@ static void build_preorder(Plan& P, int s) {
 
 static void make_plan(const or_motif* mo, const or_tree* tr, Plan& P) {
     P.mo = *mo;
+    order_relation(mo, P.R);
     P.center = tr->center;
     for (int p = 0; p < 16; ++p) {
         P.parent[p] = -2;
@@ -393,8 +431,10 @@ static u128 weight(const or_prep& R, int64_t i, int s, int32_t e) {
 // Candidate matches for child c of tree edge s, when s is matched to edge e
 // inside G_i (Claim "matching-edges-set"): the edges at the image g of the
 // attach vertex, leaving it (alpha=+) or entering it (alpha=-), whose time lies
-// in [t-delta, t] (beta '<') or [t, t+delta] (beta '>'), that lie in G_i, and
-// whose far endpoint is not the image o of s's other endpoint.  In eid order.
+// in [t-delta, t] (beta '<') or [t, t+delta] (beta '>') -- or, for a pair a
+// partial order leaves unordered, in [t-delta, t+delta] -- that lie in G_i,
+// and whose far endpoint is not the image o of s's other endpoint.  In eid
+// order.
 static void candidates(const or_prep& R, int64_t i, int s, int32_t e, int c,
                        std::vector<int32_t>& cand) {
     const or_graph& G = *R.g;
@@ -402,7 +442,7 @@ static void candidates(const or_prep& R, int64_t i, int s, int32_t e, int c,
     const OEdge& E = G.e[e];
     int32_t g = (P.attach[c] == P.mo.src[s]) ? E.u : E.v;
     int32_t o = (P.attach[c] == P.mo.src[s]) ? E.v : E.u;
-    int64_t wlo = P.beta[c] < 0 ? E.t - R.delta : E.t;
+    int64_t wlo = P.beta[c] > 0 ? E.t : E.t - R.delta;
     int64_t whi = P.beta[c] < 0 ? E.t : E.t + R.delta;
     const std::vector<int32_t>& L = P.alpha[c] > 0 ? G.out[g] : G.in[g];
     cand.clear();
@@ -700,6 +740,34 @@ static bool list_count(const or_graph& G, const std::vector<std::vector<int32_t>
     return true;
 }
 
+// Completions under a partial order: one edge per list, lists in motif
+// order, each choice checked against the edges chosen before it (the
+// relation's pairs and distinctness); the delta range once all are chosen.
+static bool po_enumerate(const or_graph& G, const or_motif& M, const uint16_t R[16],
+                         const std::vector<std::vector<int32_t>>& lists, int p, std::vector<int32_t>& pick,
+                         u128* count) {
+    if (p == M.l) {
+        int64_t lo = G.e[pick[0]].t, hi = lo;
+        for (int q = 1; q < M.l; ++q) {
+            lo = std::min(lo, G.e[pick[q]].t);
+            hi = std::max(hi, G.e[pick[q]].t);
+        }
+        if (hi - lo <= M.delta) return add_ok(*count, 1, count);
+        return true;
+    }
+    for (int32_t x : lists[p]) {
+        bool ok = true;
+        for (int q = 0; q < p && ok; ++q) {
+            if (pick[q] == x) ok = false;
+            if (precedes(R, q, p) && !(G.e[pick[q]].t < G.e[x].t)) ok = false;
+        }
+        if (!ok) continue;
+        pick[p] = x;
+        if (!po_enumerate(G, M, R, lists, p + 1, pick, count)) return false;
+    }
+    return true;
+}
+
 // Validate the image of the tree edges (Alg. 4: 1-1 vertex map, delta range,
 // edge order; the first failing check is the recorded cause), then count the
 // motif instances that extend it (Alg. 5).
@@ -727,11 +795,13 @@ static int validate_and_derive(const or_prep& R, const int32_t* img_e /* indexed
         firstt = false;
     }
     if (tmax - tmin > R.delta) { *status = 2; return OR_OK; }
-    for (size_t a = 1; a < P.tree_sorted.size(); ++a)
-        if (!(G.e[img_e[P.tree_sorted[a - 1]]].t < G.e[img_e[P.tree_sorted[a]]].t)) {
-            *status = 3;
-            return OR_OK;
-        }
+    // every ordered pair of tree edges strictly in order
+    for (int p : P.tree_sorted)
+        for (int q : P.tree_sorted)
+            if (precedes(P.R, p, q) && !(G.e[img_e[p]].t < G.e[img_e[q]].t)) {
+                *status = 3;
+                return OR_OK;
+            }
     // N_phi: the number of intervals that contain every tree edge.  Only the
     // intervals starting at or before t_min and after t_min - 2*delta can.
     uint32_t cnt = 0;
@@ -753,6 +823,17 @@ static int validate_and_derive(const or_prep& R, const int32_t* img_e /* indexed
             if (G.e[L[x]].t > tmin + R.delta) break;
             lists[p].push_back(L[x]);
         }
+    }
+    if (M.partial) {
+        // A partial order: the completions are counted by their definition
+        // (Def. "temporal match" with the order restricted to the given
+        // pairs): every choice of one edge per list, each pair of the
+        // relation strictly in order, distinct edges, all within delta.
+        std::vector<int32_t> pick(M.l, -1);
+        u128 total = 0;
+        if (!po_enumerate(G, M, P.R, lists, 0, pick, &total)) return OR_EOVERFLOW;
+        *m_phi = total;
+        return OR_OK;
     }
     u128 total = 0;
     for (int32_t f : lists[0]) {
@@ -815,7 +896,7 @@ static bool nth_completion(const or_graph& G, const std::vector<std::vector<int3
 }
 
 extern "C" int or_list_instance(const or_prep* p, const int32_t* eids, or_u128 rank, int32_t* out) {
-    if (!p || !eids || !out) return OR_EINVAL;
+    if (!p || !eids || !out || p->P.mo.partial) return OR_EINVAL;
     const or_graph& G = *p->g;
     const Plan& P = p->P;
     const or_motif& M = P.mo;

@@ -46,13 +46,23 @@ typedef struct or_graph or_graph;
 typedef struct or_prep or_prep;
 
 /* Motif M = (H, pi, delta): l directed edges on vertices 0..k-1, listed in
- * pi order (edge p is the p-th in time).  Def. "temporal motif". */
+ * pi order (edge p is the p-th in time).  Def. "temporal motif".
+ *
+ * Partial-order motifs (Sec. 1.1 remark and Sec. 6, "a partial order of time
+ * constraints"): with partial = 1 only the pairs of the relation `before`
+ * constrain the times -- bit p of before[q] says edge p is strictly earlier
+ * than edge q -- taken with its transitive closure; other pairs may occur in
+ * any order or at equal times.  The listing order must be a linear extension
+ * (bits p < q only), and parallel motif edges must be ordered (so that the
+ * edge map stays 1-1).  partial = 0 is the total order of the list. */
 typedef struct {
     int32_t k;
     int32_t l;
     int32_t src[16];
     int32_t dst[16];
     int64_t delta;
+    uint32_t partial;
+    uint16_t before[16];
 } or_motif;
 
 /* Spanning tree S: n_edges = k-1 motif edge indices, and the center edge. */

@@ -37,6 +37,27 @@ MOTIFS = {
 }
 
 
+# Partial-order motifs (the paper's remark on a partial order of time
+# constraints, Sec. 1.1 and Sec. 6): (edges, pairs (p, q) meaning edge p is
+# strictly earlier than edge q); pairs not implied by these are unordered.
+PO_MOTIFS = {
+    # a->b, a->c, a->d in any order (an unordered 3-leaf fan-out)
+    "po_fan3": (((0, 1), (0, 2), (0, 3)), ()),
+    # two payments a->b, b->c in any order, then the return c->a
+    "po_cycle3": (((0, 1), (1, 2), (2, 0)), ((0, 2), (1, 2))),
+    # scatter-gather with each intermediate receiving before forwarding:
+    # a->b < b->e, a->c < c->e, a->d < d->e, the three paths unordered
+    "po_sg": (((0, 1), (0, 2), (0, 3), (1, 4), (2, 4), (3, 4)), ((0, 3), (1, 4), (2, 5))),
+    # a->b < b->c, then c->a and a->c anywhere within delta (two unordered
+    # non-tree edges that may lead, trail or sit between the tree edges)
+    "po_free2": (((0, 1), (1, 2), (2, 0), (0, 2)), ((0, 1),)),
+    # two paths a->b->d and a->c->d, each in order, unordered to each other
+    "po_diamond": (((0, 1), (0, 2), (1, 3), (2, 3)), ((0, 2), (1, 3))),
+    # two ordered a->b edges and b->c unordered to both
+    "po_parallel": (((0, 1), (0, 1), (1, 2)), ((0, 1),)),
+}
+
+
 def motif_vertices(edges) -> int:
     return 1 + max(max(e) for e in edges)
 

@@ -7,7 +7,7 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def load(name):
-    fx = dict(motif=[], edges=[], tree=None, center=None)
+    fx = dict(motif=[], edges=[], tree=None, center=None, before=[])
     with open(os.path.join(GOLDEN, name)) as f:
         for line in f:
             line = line.split("#", 1)[0].strip()
@@ -19,6 +19,8 @@ def load(name):
                 fx["motif"].append(tuple(vals))
             elif key == "edge":
                 fx["edges"].append(tuple(vals))
+            elif key == "before":
+                fx["before"].append(tuple(vals))
             elif key == "tree":
                 fx["tree"] = vals
             elif key in ("delta", "center", "expect_count", "expect_weight_slot0",
