@@ -777,7 +777,7 @@ namespace {
 // build checks for overflow only at its end anyway).  *done is false when
 // the 64-bit tables overflowed: the caller then runs the synchronous path.
 int estimate_enqueued(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32_t constraints, u64 k, u64 seed,
-                      hipStream_t st, tm_result* out, tm_sample_rec* recs, bool* done) {
+                      hipStream_t st, tm_result* out, bool* done) {
     *done = false;
     if (constraints & ~(uint32_t)TM_C_ALL) return tm_fail(TM_EINVAL, "weights: constraints %u", constraints);
     TM_TRY(motif_check(mo));
@@ -804,7 +804,7 @@ int estimate_enqueued(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32
         tw.stop();
     }
     bool overflowed = false;
-    if (rc == TM_OK) rc = sample_run(w, seed, 0, k, k, st, out, recs, nullptr, flag, &overflowed);
+    if (rc == TM_OK) rc = sample_run(w, seed, 0, k, k, st, out, nullptr, nullptr, flag, &overflowed);
     // sample_run synchronised the stream (on success)
     if (sync_stream(st) != hipSuccess && rc == TM_OK) rc = tm_fail(TM_EDEVICE, "estimate: synchronise");
     tw.finish();
@@ -820,9 +820,11 @@ int estimate_enqueued(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32
 extern "C" int tm_estimate_ex(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32_t constraints,
                               uint64_t k, uint64_t seed, void* stream, tm_result* out, tm_sample_rec* recs) {
     if (!out) return tm_fail(TM_EINVAL, "estimate: NULL output");
-    if (g && k > 0 && g->m > 0 && g->m < ((int64_t)1 << 23)) {
+    // records need W on the host first (a W = 0 run writes "not drawn"
+    // records): they take the synchronous path
+    if (g && k > 0 && g->m > 0 && g->m < ((int64_t)1 << 23) && !recs) {
         bool done = false;
-        TM_TRY(estimate_enqueued(g, mo, tr, constraints, k, seed, as_stream(stream), out, recs, &done));
+        TM_TRY(estimate_enqueued(g, mo, tr, constraints, k, seed, as_stream(stream), out, &done));
         if (done) {
             finish_result(out);
             out->status = TM_OK;

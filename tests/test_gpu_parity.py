@@ -248,9 +248,9 @@ def test_zero_weight_and_empty_graph(T):
 
 @pytest.mark.parametrize("m,delta,k", [(3000, 300, 5000), (30000, 2000, 70000)])
 def test_estimate_records_match_oracle(T, m, delta, k):
-    """tm_estimate with records (the enqueued build-and-sample form below 2^23
-    edges; 70,000 samples take the root-sorted launch): every record and sum
-    against the oracle's run."""
+    """tm_estimate with records (70,000 samples take the root-sorted launch)
+    and without (the enqueued build-and-sample form below 2^23 edges): every
+    record and sum against the oracle's run."""
     g = W.small_graph(m, 23, n=max(60, m // 25), span=40 * delta)
     og, tg = pair(T, g)
     for name in ("4cycle", "lead_trail"):
@@ -260,8 +260,9 @@ def test_estimate_records_match_oracle(T, m, delta, k):
         ro, reco = O.Prep(og, omo).sample(9, k, records=True)
         rg, recg = T.estimate(tg, tmo, k, 9, records=True)
         assert rec_equal(reco, recg)
-        assert rg.acc2.value == ro.acc2.value and rg.acc2_sq.value == ro.acc2_sq.value
-        assert rg.estimate == ro.estimate and rg.std_error == ro.std_error
+        for r in (rg, T.estimate(tg, tmo, k, 9)):
+            assert r.acc2.value == ro.acc2.value and r.acc2_sq.value == ro.acc2_sq.value
+            assert r.estimate == ro.estimate and r.std_error == ro.std_error
 
 
 def test_sample_ranges_compose(T):
