@@ -75,13 +75,28 @@ typedef struct tm_weights tm_weights;
 /* Temporal motif M = (H, pi, delta) (Def. "temporal motif"): l directed edges
  * src[p] -> dst[p] over vertices 0..k-1, listed in pi order (edge p must be
  * the p-th in time).  2 <= k <= 8, 1 <= l <= 16, no self loop, weakly
- * connected, 1 <= delta < 2^62.  Parallel motif edges are allowed. */
+ * connected, 1 <= delta < 2^62.  Parallel motif edges are allowed.
+ *
+ * Partial-order motifs (the generalisation to "a partial order of time
+ * constraints", Sec. 1.1 remark and Sec. 6): partial = 1 keeps only the
+ * pairs of `before` and the pairs they imply -- bit p of before[q] says edge
+ * p must be strictly earlier than edge q -- and leaves every other pair
+ * unordered (either order, or equal times).  The list must be a linear
+ * extension (bits p < q < l only) and parallel motif edges must be ordered
+ * (else two of them could take one graph edge); an unordered pair of tree
+ * edges searches the window [t - delta, t + delta].  A relation whose
+ * closure orders every pair is the total order and runs as partial = 0.
+ * The GPU path completes at most 5 non-tree edges under a partial order
+ * (TM_EINVAL beyond); families and instance listing take total orders only.
+ * partial = 0 (zero-initialised) is the total order of the list. */
 typedef struct {
     int32_t k;
     int32_t l;
     int32_t src[TM_MAX_L];
     int32_t dst[TM_MAX_L];
     int64_t delta;
+    uint32_t partial;
+    uint16_t before[TM_MAX_L];
 } tm_motif;
 
 /* Spanning tree S of the motif (Def. "spanning tree of a temporal motif"):

@@ -90,8 +90,35 @@ void DevArena::release() {
 // ---------------------------------------------------------------------------
 // Motif and tree checks, and the rooted plan.
 // ---------------------------------------------------------------------------
+// The motif's "strictly earlier" relation: rel[q] holds p when edge p must
+// precede edge q.  The total order: every p < q; a partial order: the given
+// pairs closed under transitivity (pairs run from lower to higher index, so
+// one pass in index order closes them).
+static void order_closure(const tm_motif* mo, uint32_t rel[TM_MAX_L]) {
+    for (int q = 0; q < TM_MAX_L; ++q) {
+        if (q >= mo->l) {
+            rel[q] = 0;
+        } else if (!mo->partial) {
+            rel[q] = (1u << q) - 1u;
+        } else {
+            uint32_t r = mo->before[q];
+            for (int p = 0; p < q; ++p)
+                if ((mo->before[q] >> p) & 1u) r |= rel[p];
+            rel[q] = r;
+        }
+    }
+}
+
+// A partial order that orders every pair is the total order of the list.
+static bool order_is_total(const tm_motif* mo, const uint32_t rel[TM_MAX_L]) {
+    for (int q = 0; q < mo->l; ++q)
+        if (rel[q] != (1u << q) - 1u) return false;
+    return true;
+}
+
 int motif_check(const tm_motif* mo) {
     if (!mo) return tm_fail(TM_EINVAL, "motif: NULL");
+    if (mo->partial > 1) return tm_fail(TM_EINVAL, "motif: partial = %u (0 or 1)", mo->partial);
     if (mo->k < 2 || mo->k > TM_MAX_K) return tm_fail(TM_EINVAL, "motif: k = %d outside [2, 8]", mo->k);
     if (mo->l < 1 || mo->l > TM_MAX_L) return tm_fail(TM_EINVAL, "motif: l = %d outside [1, 16]", mo->l);
     if (mo->delta < 1 || mo->delta >= ((int64_t)1 << 62))
@@ -111,6 +138,21 @@ int motif_check(const tm_motif* mo) {
     }
     for (int x = 1; x < mo->k; ++x)
         if (find(x) != find(0)) return tm_fail(TM_EINVAL, "motif: not weakly connected");
+    if (mo->partial) {
+        for (int q = 0; q < TM_MAX_L; ++q) {
+            const uint32_t allowed = q < mo->l ? (1u << q) - 1u : 0u;
+            if (mo->before[q] & ~allowed)
+                return tm_fail(TM_EINVAL, "motif: before[%d] names an edge that is not listed earlier", q);
+        }
+        uint32_t rel[TM_MAX_L];
+        order_closure(mo, rel);
+        for (int p = 0; p < mo->l; ++p)
+            for (int q = p + 1; q < mo->l; ++q)
+                if (mo->src[p] == mo->src[q] && mo->dst[p] == mo->dst[q] && !((rel[q] >> p) & 1u))
+                    return tm_fail(TM_EINVAL, "motif: parallel edges %d and %d are unordered", p, q);
+        if (!order_is_total(mo, rel) && mo->l - (mo->k - 1) > kPoMaxFree)
+            return tm_fail(TM_EINVAL, "motif: a partial order with more than %d non-tree edges", kPoMaxFree);
+    }
     return TM_OK;
 }
 
@@ -144,6 +186,14 @@ int plan_build(const tm_motif* mo, const tm_tree* tr, HostPlan* P) {
     H = HostPlan();
     H.mo = *mo;
     H.tree = *tr;
+    uint32_t rel[TM_MAX_L];
+    order_closure(mo, rel);
+    H.po = mo->partial && !order_is_total(mo, rel);
+    if (!H.po) {  // the total order of the list, however it was given
+        H.mo.partial = 0;
+        std::memset(H.mo.before, 0, sizeof H.mo.before);
+    }
+    auto earlier = [&](int p, int q) { return ((rel[q] >> p) & 1u) != 0; };
     H.nt = tr->n_edges;
     for (int p = 0; p < TM_MAX_L; ++p) H.slot_of_edge[p] = -1;
     for (int s = 0; s < kMaxSlots; ++s) {
@@ -177,7 +227,7 @@ int plan_build(const tm_motif* mo, const tm_tree* tr, HostPlan* P) {
             else z = H.new_vertex[s];
             H.side[c] = z == mo->src[e] ? 0 : 1;
             H.alpha[c] = mo->src[p] == z ? +1 : -1;
-            H.beta[c] = p < e ? -1 : +1;
+            H.beta[c] = earlier(p, e) ? -1 : (earlier(e, p) ? +1 : 0);
             H.new_vertex[c] = mo->src[p] == z ? mo->dst[p] : mo->src[p];
             H.children[s][H.n_children[s]++] = c;
             self(self, c);
@@ -231,6 +281,25 @@ int plan_build(const tm_motif* mo, const tm_tree* tr, HostPlan* P) {
         H.run_prev[H.n_runs] = last_tree_slot;
         H.run_next[H.n_runs] = p < mo->l ? H.slot_of_edge[p] : -1;
         ++H.n_runs;
+    }
+    if (H.po) {
+        int free_edge[TM_MAX_L], nf = 0;
+        for (int p = 0; p < mo->l; ++p)
+            if (H.slot_of_edge[p] < 0) free_edge[nf++] = p;
+        for (int s = 0; s < kMaxSlots; ++s) H.po_tpred[s] = 0;
+        for (int s = 0; s < H.nt; ++s)
+            for (int s2 = 0; s2 < H.nt; ++s2)
+                if (earlier(H.edge[s2], H.edge[s])) H.po_tpred[s] |= (uint16_t)(1u << s2);
+        for (int f = 0; f < TM_MAX_L; ++f) {
+            H.po_f_tpred[f] = H.po_f_tsucc[f] = H.po_f_fpred[f] = 0;
+            if (f >= nf) continue;
+            for (int s = 0; s < H.nt; ++s) {
+                if (earlier(H.edge[s], free_edge[f])) H.po_f_tpred[f] |= (uint16_t)(1u << s);
+                if (earlier(free_edge[f], H.edge[s])) H.po_f_tsucc[f] |= (uint16_t)(1u << s);
+            }
+            for (int f2 = 0; f2 < nf; ++f2)
+                if (earlier(free_edge[f2], free_edge[f])) H.po_f_fpred[f] |= (uint16_t)(1u << f2);
+        }
     }
     return TM_OK;
 }
@@ -1204,6 +1273,7 @@ extern "C" void tm_batch_plan_destroy(tm_batch_plan* p) { plan_release(p); }
 static int family_plan(const tm_weights* w, const tm_motif* mo, HostPlan* out) {
     TM_TRY(motif_check(mo));
     const HostPlan& P0 = w->plan;
+    if (P0.po) return tm_fail(TM_EINVAL, "family: the weight set's motif has a partial order");
     if (mo->k != P0.mo.k || mo->delta != P0.mo.delta)
         return tm_fail(TM_EINVAL, "family: motif differs in vertex count or delta");
     tm_tree t;
@@ -1229,6 +1299,7 @@ static int family_plan(const tm_weights* w, const tm_motif* mo, HostPlan* out) {
     }
     TM_TRY(plan_build(mo, &t, out));
     const HostPlan& P = *out;
+    if (P.po) return tm_fail(TM_EINVAL, "family: a member motif has a partial order");
     if (P.nt != P0.nt || P.H != P0.H) return tm_fail(TM_EINVAL, "family: tree shape differs");
     for (int s = 0; s < P.nt; ++s)
         if (P.parent[s] != P0.parent[s] || P.side[s] != P0.side[s] || P.alpha[s] != P0.alpha[s] ||
@@ -1271,5 +1342,6 @@ extern "C" int tm_list_instances(tm_weights* w, uint64_t seed, uint64_t j0, uint
                                  int32_t* eids, tm_sample_rec* recs) {
     if (!w || (count > 0 && !eids)) return tm_fail(TM_EINVAL, "list_instances: NULL argument");
     if (count > 0 && j0 + count < j0) return tm_fail(TM_EINVAL, "list_instances: id range wraps");
+    if (w->plan.po) return tm_fail(TM_EINVAL, "list_instances: the motif has a partial order");
     return list_run(w, seed, j0, count, as_stream(stream), eids, recs);
 }

@@ -67,7 +67,12 @@ struct SampleArgs {
     int n_runs;
     int run_first[TM_MAX_L], run_len[TM_MAX_L], run_prev[TM_MAX_L], run_next[TM_MAX_L];
     int general_runs;  // some run needs the general chain counter (3+ lists, or a
-                       // leading and a trailing run coupled by delta)
+                       // leading and a trailing run coupled by delta), or the
+                       // motif has a partial order
+    // partial orders (po = 1): "strictly earlier" masks (see HostPlan)
+    int po;
+    uint16_t po_tpred[kMaxSlots];
+    uint16_t po_f_tpred[kPoMaxFree], po_f_tsucc[kPoMaxFree], po_f_fpred[kPoMaxFree];
     u64 seed, j0, count;
     tm_sample_rec* recs;
     struct Partial* parts;
@@ -364,6 +369,126 @@ __device__ __noinline__ u128 complete_general(const SampleArgs& a, const V8& img
 }
 
 // ---------------------------------------------------------------------------
+// Completions under a partial order.  Each non-tree edge f takes an edge of
+// its multi-edge list inside its bounds: after the tree edges that precede it
+// and before those it precedes, and within delta of every tree time.  Among
+// themselves the non-tree edges need their ordered pairs strictly in time
+// order.  The count splits by the earliest time v of the whole match: all
+// non-tree times in [t_min, t_min + delta] (the tree holds the earliest
+// time), plus, for every candidate time v < t_min, the assignments inside
+// [v, v + delta] with some non-tree edge at v.  Each part is one sweep over
+// the candidates in time order (on equal times the later-listed edge first,
+// so that an edge never follows one at its own time) with one count per set
+// of assigned non-tree edges: an edge joins a set that holds everything it
+// must follow.
+// ---------------------------------------------------------------------------
+struct PoRuns {
+    int r;
+    const u64* nk[kPoMaxFree];
+    int32_t a[kPoMaxFree], b[kPoMaxFree];
+};
+
+// Assignments with every non-tree time in [lo, hi]; must: some non-tree edge
+// at time lo exactly.
+__device__ u128 po_sweep(const SampleArgs& a, const PoRuns& R, u64 tmask, int64_t lo, int64_t hi, bool must,
+                         bool* ovf) {
+    u128 dp[1 << kPoMaxFree];
+    const int ns = 1 << R.r;
+    for (int x = 0; x < ns; ++x) dp[x] = 0;
+    dp[0] = 1;
+    int32_t pos[kPoMaxFree];
+    for (int f = 0; f < R.r; ++f) {
+        int32_t x = R.a[f];
+        while (x < R.b[f] && (int64_t)(R.nk[f][x] & tmask) < lo) ++x;
+        pos[f] = x;
+    }
+    bool dropped = !must;
+    while (true) {
+        int best = -1;
+        int64_t tb = 0;
+        for (int f = R.r - 1; f >= 0; --f) {
+            if (pos[f] >= R.b[f]) continue;
+            const int64_t tf = (int64_t)(R.nk[f][pos[f]] & tmask);
+            if (tf > hi) continue;
+            if (best < 0 || tf < tb) {
+                best = f;
+                tb = tf;
+            }
+        }
+        if (best < 0) break;
+        if (!dropped && tb > lo) {
+            dp[0] = 0;  // the sets with nothing at lo end here
+            dropped = true;
+        }
+        const uint32_t need = a.po_f_fpred[best];
+        const int bit = 1 << best;
+        for (int S = 0; S < ns; ++S) {
+            if ((S & bit) || (need & ~(uint32_t)S) || dp[S] == 0) continue;
+            if (!add_ok(dp[S | bit], dp[S], &dp[S | bit])) *ovf = true;
+        }
+        ++pos[best];
+    }
+    return dp[ns - 1];
+}
+
+template <bool kCount>
+__device__ __noinline__ u128 complete_po(const SampleArgs& a, const V8& img, const int64_t* te, bool* ovf, u64* nbp) {
+    const DevGraph& G = a.G;
+    if (a.n_free == 0) return 1;
+    int64_t tlo = te[0], thi = te[0];
+    for (int s = 1; s < a.nt; ++s) {
+        tlo = te[s] < tlo ? te[s] : tlo;
+        thi = te[s] > thi ? te[s] : thi;
+    }
+    PoRuns R;
+    R.r = a.n_free;
+    u64 nb = 0;
+    for (int f = 0; f < R.r; ++f) {
+        int64_t lo = thi - a.delta, hi = tlo + a.delta;
+        for (int s = 0; s < a.nt; ++s) {
+            if ((a.po_f_tpred[f] >> s) & 1u) lo = te[s] + 1 > lo ? te[s] + 1 : lo;
+            if ((a.po_f_tsucc[f] >> s) & 1u) hi = te[s] - 1 < hi ? te[s] - 1 : hi;
+        }
+        if (lo > hi) {
+            *nbp += nb;
+            return 0;
+        }
+        int32_t la, lb;
+        u64 np = 0;
+        R.nk[f] = el_run(G, img.v[a.free_src[f]], img.v[a.free_dst[f]], lo, hi, R.a[f], R.b[f], la, lb,
+                         kCount ? &np : nullptr);
+        if constexpr (kCount) nb += 16 + np * 8 + (u64)(R.b[f] - R.a[f]) * 8;
+        if (R.a[f] >= R.b[f]) {
+            *nbp += nb;
+            return 0;
+        }
+    }
+    const u64 tmask = tmask_of(G);
+    u128 total = po_sweep(a, R, tmask, tlo, tlo + a.delta, false, ovf);
+    // anchors: the distinct candidate times below t_min, in increasing order
+    int32_t cur[kPoMaxFree];
+    for (int f = 0; f < R.r; ++f) cur[f] = R.a[f];
+    while (true) {
+        int64_t v = -1;
+        for (int f = 0; f < R.r; ++f) {
+            if (cur[f] >= R.b[f]) continue;
+            const int64_t tf = (int64_t)(R.nk[f][cur[f]] & tmask);
+            if (v < 0 || tf < v) v = tf;
+        }
+        if (v < 0 || v >= tlo) break;
+        const u128 c = po_sweep(a, R, tmask, v, v + a.delta, true, ovf);
+        if (!add_ok(total, c, &total)) *ovf = true;
+        for (int f = 0; f < R.r; ++f)
+            while (cur[f] < R.b[f] && (int64_t)(R.nk[f][cur[f]] & tmask) == v) ++cur[f];
+        if constexpr (kCount) {
+            for (int f = 0; f < R.r; ++f) nb += (u64)(R.b[f] - R.a[f]) * 8;
+        }
+    }
+    *nbp += nb;
+    return total;
+}
+
+// ---------------------------------------------------------------------------
 // Wave and block reduction of the per-lane partial sums.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ u128 shfl_xor_u128(u128 v, int m) {
@@ -552,12 +677,21 @@ __device__ __forceinline__ u128 completions(const SampleArgs& a, const int32_t (
             constexpr int xi = decltype(x)::value;
             iv.v[xi] = xi < K ? img[xi < K ? xi : 0] : -1 - xi;
         });
-        int64_t tp[TM_MAX_L], tn[TM_MAX_L];
-        for (int r2 = 0; r2 < a.n_runs; ++r2) {
-            tp[r2] = a.run_prev[r2] >= 0 ? pick(te, a.run_prev[r2]) : 0;
-            tn[r2] = a.run_next[r2] >= 0 ? pick(te, a.run_next[r2]) : 0;
+        if (a.po) {
+            int64_t tt[kMaxSlots];
+            sfor<0, kMaxSlots>([&](auto sc) {
+                constexpr int si = decltype(sc)::value;
+                tt[si] = si < NT ? te[si < NT ? si : 0] : 0;
+            });
+            m_phi = complete_po<kCount>(a, iv, tt, &ovf, &nb);
+        } else {
+            int64_t tp[TM_MAX_L], tn[TM_MAX_L];
+            for (int r2 = 0; r2 < a.n_runs; ++r2) {
+                tp[r2] = a.run_prev[r2] >= 0 ? pick(te, a.run_prev[r2]) : 0;
+                tn[r2] = a.run_next[r2] >= 0 ? pick(te, a.run_next[r2]) : 0;
+            }
+            m_phi = complete_general<kCount>(a, iv, tfirst, tlast, tp, tn, &ovf, &nb);
         }
-        m_phi = complete_general<kCount>(a, iv, tfirst, tlast, tp, tn, &ovf, &nb);
     } else {
         m_phi = 1;
         for (int r2 = 0; r2 < a.n_runs && m_phi != 0; ++r2) {
@@ -651,7 +785,9 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
             const int64_t pt = pick(te, a.parent[s]);
             const int32_t g = pick(img, a.gv[s]);
             const int32_t o = pick(img, a.ov[s]);
-            int64_t wlo = a.beta[s] < 0 ? pt - a.delta : pt;
+            // [t - delta, t] before the parent, [t, t + delta] after it,
+            // [t - delta, t + delta] when a partial order leaves them unordered
+            int64_t wlo = a.beta[s] > 0 ? pt : pt - a.delta;
             int64_t whi = a.beta[s] < 0 ? pt : pt + a.delta;
             wlo = wlo > ilo_t ? wlo : ilo_t;
             whi = whi < ihi_t ? whi : ihi_t;
@@ -744,7 +880,19 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
             }
         });
         if (status == 0 && tmax - tmin > a.delta) status = 2;
-        if (status == 0) {
+        if constexpr (kGeneral) {
+            if (status == 0 && a.po) {
+                // a partial order: every ordered pair of tree edges in order
+                sfor<0, NT>([&](auto xc) {
+                    constexpr int x = decltype(xc)::value;
+                    sfor<0, NT>([&](auto yc) {
+                        constexpr int y = decltype(yc)::value;
+                        if (x < a.nt && y < a.nt && ((a.po_tpred[x] >> y) & 1u) && !(te[y] < te[x])) status = 3;
+                    });
+                });
+            }
+        }
+        if (status == 0 && !(kGeneral && a.po)) {
             sfor<1, NT>([&](auto xc) {
                 constexpr int x = decltype(xc)::value;
                 if (x < a.nt && !(pick(te, a.by_pi[x - 1]) < pick(te, a.by_pi[x]))) status = 3;
@@ -1040,6 +1188,17 @@ void fill_args(const tm_weights* w, SampleArgs* out, size_t* lds_out) {
         if (P.run_next[r] < 0) has_trail = true;
     }
     if (has_lead && has_trail) a.general_runs = 1;
+    if (P.po) {
+        // a partial order completes in the general variant, by its own counter
+        a.general_runs = 1;
+        a.po = 1;
+        for (int s = 0; s < kMaxSlots; ++s) a.po_tpred[s] = P.po_tpred[s];
+        for (int f = 0; f < kPoMaxFree; ++f) {
+            a.po_f_tpred[f] = P.po_f_tpred[f];
+            a.po_f_tsucc[f] = P.po_f_tsucc[f];
+            a.po_f_fpred[f] = P.po_f_fpred[f];
+        }
+    }
     *lds_out = lds;
 }
 

@@ -62,7 +62,7 @@ struct Done {
     std::string msg;
 };
 
-// Identity of a weight set: graph, motif edges and delta, tree edges and center.
+// Identity of a weight set: graph, motif edges, delta and time order, tree edges and center.
 std::string set_key(int gid, const HostPlan& P) {
     std::string k;
     auto put = [&k](int64_t v) { k.append(reinterpret_cast<const char*>(&v), sizeof v); };
@@ -76,6 +76,9 @@ std::string set_key(int gid, const HostPlan& P) {
     }
     put(P.tree.center);
     for (int e = 0; e < P.tree.n_edges; ++e) put(P.tree.edge[e]);
+    // a partial order changes the tree's windows and the completions
+    put(P.po);
+    for (int e = 0; P.po && e < P.mo.l; ++e) put(P.mo.before[e]);
     return k;
 }
 

@@ -115,7 +115,7 @@ struct HostPlan {
     int parent[kMaxSlots];         // parent slot, -1 for the center
     int side[kMaxSlots];           // 0: attaches at the parent's source, 1: at its destination
     int alpha[kMaxSlots];          // +1: child leaves the shared vertex; -1: enters it
-    int beta[kMaxSlots];           // -1: child precedes its parent in pi; +1: follows
+    int beta[kMaxSlots];           // -1: child precedes its parent; +1: follows; 0: unordered
     int height[kMaxSlots];
     int new_vertex[kMaxSlots];     // motif vertex first reached through this slot
     int children[kMaxSlots][kMaxSlots];
@@ -132,7 +132,18 @@ struct HostPlan {
     int n_runs = 0;
     int run_first[TM_MAX_L], run_len[TM_MAX_L];
     int run_prev[TM_MAX_L], run_next[TM_MAX_L];  // tree slots around a run, -1 at the ends
+    // partial-order motifs whose order is not total (po = 1): the relation
+    // "strictly earlier" as bit masks -- over tree slots for each tree slot,
+    // and for each non-tree edge (n_free index) over tree slots before it,
+    // tree slots after it and the non-tree edges before it
+    int po = 0;
+    uint16_t po_tpred[kMaxSlots];
+    uint16_t po_f_tpred[TM_MAX_L], po_f_tsucc[TM_MAX_L], po_f_fpred[TM_MAX_L];
 };
+
+// Non-tree edges a partial-order motif may have on the GPU (its completion
+// counter keeps one count per set of them).
+constexpr int kPoMaxFree = 5;
 
 int plan_build(const tm_motif* mo, const tm_tree* tr, HostPlan* out);
 int motif_check(const tm_motif* mo);

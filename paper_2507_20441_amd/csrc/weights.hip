@@ -28,7 +28,7 @@ namespace {
 struct ChildDesc {
     int side;     // 0: attaches at the source endpoint of the parent's match, 1: destination
     int dir;      // 0: child is an out-edge of the shared vertex, 1: an in-edge
-    int beta;     // -1: child precedes the parent in pi, +1: follows it
+    int beta;     // -1: child precedes the parent, +1: follows it, 0: unordered (partial orders)
     int leaf;
     int copies;   // leaf children with the same side, direction and time side share
                   // one window: the factor is raised to this power (0: folded into another)
@@ -63,57 +63,61 @@ __device__ __forceinline__ void sfor(F&& f) {
 }
 
 // The first position of a vertex's list, in T order, whose time is >= x,
-// and, in N order, whose packed key is >= (o << bt) + x, for three x at once:
-// six independent loads per halving step.  x is clipped to [0, T + 1]; the
-// key for x = T + 1 (the end of o's run) is taken as "> (o << bt) + T", which
-// cannot wrap even when the id and time bits fill all 64.
-struct Bounds3 {
-    int32_t p[3], q[3];
+// and, in N order, whose packed key is >= (o << bt) + x, for NB values of x
+// at once: 2 NB independent loads per halving step (three for a child on one
+// side of its parent in time, four for one a partial order leaves unordered).
+// x is clipped to [0, T + 1]; the key for x = T + 1 (the end of o's run) is
+// taken as "> (o << bt) + T", which cannot wrap even when the id and time
+// bits fill all 64.
+template <int NB>
+struct BoundsN {
+    int32_t p[NB], q[NB];
     int32_t len;  // the list's length
 };
 
-__device__ __forceinline__ Bounds3 three_bounds(const DevGraph& G, int dir, int32_t g, int32_t o,
-                                                const int64_t (&xs)[3], bool exclude) {
+template <int NB>
+__device__ __forceinline__ BoundsN<NB> list_bounds(const DevGraph& G, int dir, int32_t g, int32_t o,
+                                                   const int64_t (&xs)[NB], bool exclude) {
     const int32_t a = G.off[dir][g], b = G.off[dir][g + 1];
     const int64_t* lt = G.lt[dir];
     const u64* nk = G.nkey[dir];
     const u64 base = (u64)o << G.bt;
-    int64_t x[3];
-    u64 kx[3];
-    bool le[3];
-    int32_t c[6];
+    int64_t x[NB];
+    u64 kx[NB];
+    bool le[NB];
+    int32_t c[2 * NB];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
+    for (int j = 0; j < NB; ++j) {
         x[j] = xs[j] < 0 ? 0 : (xs[j] > G.T + 1 ? G.T + 1 : xs[j]);
         le[j] = x[j] > G.T;
         kx[j] = base + (u64)(le[j] ? G.T : x[j]);
         c[j] = a;
-        c[3 + j] = a;
+        c[NB + j] = a;
     }
     int32_t n = b - a;
     while (n > 1) {
         const int32_t h = n >> 1;
-        int64_t y[3];
-        u64 z[3];
+        int64_t y[NB];
+        u64 z[NB];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
+        for (int j = 0; j < NB; ++j) {
             y[j] = lt[c[j] + h];
-            z[j] = nk[c[3 + j] + h];
+            z[j] = nk[c[NB + j] + h];
         }
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
+        for (int j = 0; j < NB; ++j) {
             c[j] = y[j] < x[j] ? c[j] + h : c[j];
-            c[3 + j] = (z[j] < kx[j] || (le[j] && z[j] == kx[j])) ? c[3 + j] + h : c[3 + j];
+            c[NB + j] = (z[j] < kx[j] || (le[j] && z[j] == kx[j])) ? c[NB + j] + h : c[NB + j];
         }
         n -= h;
     }
-    Bounds3 r;
+    BoundsN<NB> r;
     r.len = b - a;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
+    for (int j = 0; j < NB; ++j) {
         r.p[j] = a == b ? a : c[j] + (lt[c[j]] < x[j] ? 1 : 0);
-        const u64 zl = nk[c[3 + j]];
-        r.q[j] = a == b ? a : c[3 + j] + ((zl < kx[j] || (le[j] && zl == kx[j])) ? 1 : 0);
+        const u64 zl = nk[c[NB + j]];
+        r.q[j] = a == b ? a : c[NB + j] + ((zl < kx[j] || (le[j] && zl == kx[j])) ? 1 : 0);
         if (!exclude) r.q[j] = a;  // no excluded run
     }
     return r;
@@ -139,11 +143,16 @@ __device__ __forceinline__ W window_mass(int32_t p0, int32_t p1, int32_t q0, int
 // (with L = delta: [blk delta, t], [t - delta, t], [t, t + delta] and
 // [t, (blk + 1) delta - 1]).
 //
+// A child that a partial order leaves unordered with its parent (kPO, beta
+// 0) has the window [t - delta, t + delta]: clipped, A = [max(t - delta,
+// blk L), min(t + delta, (blk + 2) L - 1)] and B = [max(t - delta,
+// (blk - 1) L), min(t + delta, (blk + 1) L - 1)], four distinct bounds.
+//
 // The counting variant returns the bytes the edge's work reads and writes
 // under the access model: each read or write its element size; a list search
 // of L entries ceil(log2 L) + 1 probes of each of its six bounds (three in
-// the T order, three in the N order, 8 B each).
-template <typename W, bool kCount>
+// the T order, three in the N order, 8 B each; eight for an unordered child).
+template <typename W, bool kCount, bool kPO>
 __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
     const DevGraph& G = a.G;
     u64 nb = 0;
@@ -179,7 +188,31 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
         const ChildDesc& d = a.c[c];
         if (d.copies == 0) return;
         W xa = 0, xb = 0;
-        {
+        if (kPO && d.beta == 0) {
+            const int32_t g = d.side ? v : u;
+            const int32_t o = d.side ? u : v;
+            const int64_t lo = t - a.delta, hi = t + a.delta;
+            int64_t xs[4];
+            xs[0] = lo > blk * a.ilen ? lo : blk * a.ilen;
+            xs[1] = lo > (blk - 1) * a.ilen ? lo : (blk - 1) * a.ilen;
+            xs[2] = (hi < (blk + 2) * a.ilen - 1 ? hi : (blk + 2) * a.ilen - 1) + 1;
+            xs[3] = (hi < (blk + 1) * a.ilen - 1 ? hi : (blk + 1) * a.ilen - 1) + 1;
+            const BoundsN<4> r = list_bounds<4>(G, d.dir, g, o, xs, a.exclude != 0);
+            if constexpr (kCount) {
+                int it = 0;
+                for (int32_t n = r.len; n > 1; n -= n >> 1) ++it;
+                nb += 8 + (u64)64 * it + (r.len > 0 ? 64 : 0);
+                if (a.win[c][0]) nb += 32 + (a.win_dir == a.walk ? 0 : 4);
+                if (!d.leaf) nb += (r.p[2] > r.p[0] ? 4 * sizeof(W) : 0) + (hasB && r.p[3] > r.p[1] ? 4 * sizeof(W) : 0);
+            }
+            if (a.win[c][0]) {
+                const int64_t at = a.win_dir == a.walk ? p : (int64_t)G.tpos[a.win_dir][e];
+                a.win[c][parA][at] = make_int4(r.p[0], r.p[2], r.q[0], r.q[2]);
+                a.win[c][parB][at] = hasB ? make_int4(r.p[1], r.p[3], r.q[1], r.q[3]) : make_int4(0, 0, 0, 0);
+            }
+            xa = window_mass<W>(r.p[0], r.p[2], r.q[0], r.q[2], d.leaf, d.qt[parA], d.qn[parA]);
+            xb = hasB ? window_mass<W>(r.p[1], r.p[3], r.q[1], r.q[3], d.leaf, d.qt[parB], d.qn[parB]) : (W)0;
+        } else {
             const int32_t g = d.side ? v : u;
             const int32_t o = d.side ? u : v;
             // x values (first position with time >= x):
@@ -197,7 +230,7 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
                 xs[1] = (hi < (blk + 2) * a.ilen - 1 ? hi : (blk + 2) * a.ilen - 1) + 1;
                 xs[2] = (hi < (blk + 1) * a.ilen - 1 ? hi : (blk + 1) * a.ilen - 1) + 1;
             }
-            const Bounds3 r = three_bounds(G, d.dir, g, o, xs, a.exclude != 0);
+            const BoundsN<3> r = list_bounds<3>(G, d.dir, g, o, xs, a.exclude != 0);
             if constexpr (kCount) {
                 int it = 0;
                 for (int32_t n = r.len; n > 1; n -= n >> 1) ++it;
@@ -244,11 +277,11 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
     return nb;
 }
 
-template <typename W, bool kCount>
+template <typename W, bool kCount, bool kPO>
 __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     u64 nb = 0;
-    if (p < a.G.m) nb = level_edge<W, kCount>(a, p);
+    if (p < a.G.m) nb = level_edge<W, kCount, kPO>(a, p);
     if constexpr (kCount) {
         // one addition per workgroup
 #pragma unroll
@@ -497,10 +530,20 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
                     lt = level_timers->back().get();
                     lt->start(TM_STAGE_LEVELS, st);
                 }
-                if (nbytes)
-                    hipLaunchKernelGGL((level_kernel<W, true>), dim3(grid_for(m)), dim3(kBlock), 0, st, a);
-                else
-                    hipLaunchKernelGGL((level_kernel<W, false>), dim3(grid_for(m)), dim3(kBlock), 0, st, a);
+                // children a partial order leaves unordered take the
+                // four-bound form, compiled only into its own variant
+                bool unordered = false;
+                for (int j = 0; j < a.nc; ++j) unordered = unordered || a.c[j].beta == 0;
+                if (unordered) {
+                    if (nbytes)
+                        hipLaunchKernelGGL((level_kernel<W, true, true>), dim3(grid_for(m)), dim3(kBlock), 0, st, a);
+                    else
+                        hipLaunchKernelGGL((level_kernel<W, false, true>), dim3(grid_for(m)), dim3(kBlock), 0, st, a);
+                } else if (nbytes) {
+                    hipLaunchKernelGGL((level_kernel<W, true, false>), dim3(grid_for(m)), dim3(kBlock), 0, st, a);
+                } else {
+                    hipLaunchKernelGGL((level_kernel<W, false, false>), dim3(grid_for(m)), dim3(kBlock), 0, st, a);
+                }
                 TM_HIP(hipGetLastError());
                 if (lt) lt->stop();
             }

@@ -33,7 +33,8 @@ class U128(C.Structure):
 
 class Motif(C.Structure):
     _fields_ = [("k", C.c_int32), ("l", C.c_int32), ("src", C.c_int32 * 16),
-                ("dst", C.c_int32 * 16), ("delta", C.c_int64)]
+                ("dst", C.c_int32 * 16), ("delta", C.c_int64), ("partial", C.c_uint32),
+                ("before", C.c_uint16 * 16)]
 
 
 class Tree(C.Structure):
@@ -199,13 +200,20 @@ def _stream():
     return C.c_void_p(0)
 
 
-def make_motif(edges, delta, k=None) -> Motif:
+def make_motif(edges, delta, k=None, before=None) -> Motif:
+    """edges: (src, dst) pairs in pi order; before: None for their total
+    order, else pairs (p, q), p < q, of a partial order (edge p strictly
+    earlier than edge q)."""
     mo = Motif()
     mo.l = len(edges)
     mo.k = k if k is not None else 1 + max(max(e) for e in edges)
     for p, (a, b) in enumerate(edges):
         mo.src[p], mo.dst[p] = a, b
     mo.delta = int(delta)
+    if before is not None:
+        mo.partial = 1
+        for p, q in before:
+            mo.before[q] |= 1 << p
     return mo
 
 
