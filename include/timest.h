@@ -234,6 +234,22 @@ int tm_weights_intervals(const tm_weights* w, tm_u128* host_out, void* stream);
 int tm_sample(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count, uint64_t k_total,
               void* stream, tm_result* out, tm_sample_rec* recs);
 
+/* tm_sample for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same draws, kernels and results as tm_sample, but every temporary -- the
+ * per-workgroup partial sums, a flag word, the root keys and sample offsets
+ * of the sort by root and the sort's histograms, about 36 MiB -- lives in one
+ * file-scope device array, never in hipMalloc'd memory; no hipMalloc, hipFree
+ * or other allocating routine is called.  Each device the library runs on
+ * holds its own copy of the array until the process ends.  At most 2^21
+ * samples per call (TM_EINVAL beyond: split the id range, whose sums add up
+ * exactly).  Calls that overlap on one device race on the shared array (run
+ * them one after another on a device); the caller still provides w, out and
+ * recs (NULL, or device memory for count records).  Synchronises the stream.
+ * Errors: TM_EINVAL, TM_EOVERFLOW, TM_EDEVICE. */
+int tm_sample_noalloc(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count, uint64_t k_total,
+                      void* stream, tm_result* out, tm_sample_rec* recs);
+
 /* Recompute out->estimate and out->std_error from its W, acc2, acc2_sq, k
  * and flags (Alg. 6; the standard error of Sec. 4.4): for results of
  * sample ranges whose exact sums the caller has added up.  Host-only; no

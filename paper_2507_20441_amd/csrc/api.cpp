@@ -826,6 +826,16 @@ extern "C" int tm_sample(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t cou
     return TM_OK;
 }
 
+extern "C" int tm_sample_noalloc(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count, uint64_t k_total,
+                                 void* stream, tm_result* out, tm_sample_rec* recs) {
+    if (!w || !out) return tm_fail(TM_EINVAL, "sample_noalloc: NULL argument");
+    if (count > 0 && j0 + count < j0) return tm_fail(TM_EINVAL, "sample_noalloc: id range wraps");
+    TM_TRY(sample_run_noalloc(w, seed, j0, count, k_total, as_stream(stream), out, recs));
+    finish_result(out);
+    out->status = TM_OK;
+    return TM_OK;
+}
+
 extern "C" int tm_sample_model_bytes(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count,
                                      void* stream, uint64_t* bytes) {
     if (!w || !bytes) return tm_fail(TM_EINVAL, "sample_model_bytes: NULL argument");

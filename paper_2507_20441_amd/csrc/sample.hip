@@ -2173,3 +2173,155 @@ int list_run(tm_weights* w, u64 seed, u64 j0, u64 count, hipStream_t st, int32_t
     if (sync_stream(st) != hipSuccess && rc == TM_OK) rc = tm_fail(TM_EDEVICE, "list: synchronise");
     return rc;
 }
+
+// ---------------------------------------------------------------------------
+// Sampling with no allocation.  tm_sample_noalloc runs sample_run's kernels
+// with every temporary -- the per-workgroup partial sums, the flag word, the
+// root keys and sample offsets of the sort (two buffers each) and the sort's
+// digit histograms -- carved from one file-scope device array, so it calls
+// no hipMalloc, hipFree or other allocating routine.  Each device holds its
+// own copy of the array until the process ends; its address on a device is
+// looked up once (hipGetSymbolAddress with that device current) and used
+// wherever host code needs the array: the name itself is a host-side stand-in.
+// Calls on one device share that copy: calls that overlap on a device race.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr u64 kNoAllocMaxCount = (u64)1 << 21;                  // samples per call
+constexpr int kNoAllocMaxBlocks = (int)(kNoAllocMaxCount / kBlock);  // sampling grid bound
+constexpr size_t kNoAllocParts = (size_t)(kNoAllocMaxBlocks + 1) * sizeof(Partial);
+constexpr size_t kNoAllocKeys = kNoAllocMaxCount * sizeof(uint32_t);
+constexpr size_t kNoAllocHist =
+    ((kNoAllocMaxCount + kSortTile - 1) / kSortTile + 1) * (size_t)kRadixMax * sizeof(uint32_t);
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t kScratchBytes = align256(kNoAllocParts) + 256 + 4 * align256(kNoAllocKeys) + align256(kNoAllocHist);
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// The current device's copy of scratch (looked up on the first call there).
+static int scratch_of_device(unsigned char** out) {
+    int dev = 0;
+    TM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return tm_fail(TM_EDEVICE, "sample_noalloc: device %d", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return tm_fail(TM_EDEVICE, "sample_noalloc: scratch address on device %d: %s", dev,
+                           hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return TM_OK;
+}
+
+int sample_run_noalloc(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStream_t st, tm_result* out,
+                       tm_sample_rec* recs) {
+    if (count > kNoAllocMaxCount)
+        return tm_fail(TM_EINVAL, "sample_noalloc: %llu samples, at most %llu per call (split the id range)",
+                       (unsigned long long)count, (unsigned long long)kNoAllocMaxCount);
+    unsigned char* base = nullptr;
+    TM_TRY(scratch_of_device(&base));
+    const HostPlan& P = w->plan;
+    std::memset(out, 0, sizeof *out);
+    out->k = k_total;
+    out->q = w->q;
+    out->W.lo = (u64)w->W;
+    out->W.hi = (u64)(w->W >> 64);
+    if (w->wide) out->flags |= TM_F_WIDE;
+    if (w->W == 0 || count == 0) {
+        if (w->W == 0) out->flags |= TM_F_W_ZERO;
+        if (recs && count) {
+            hipLaunchKernelGGL(fill_undrawn_kernel, dim3((unsigned)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                               st, recs, count);
+            TM_HIP(hipGetLastError());
+            TM_HIP(hipStreamSynchronize(st));
+        }
+        return TM_OK;
+    }
+    if (P.nt < 1 || P.nt > 7) return tm_fail(TM_EINVAL, "sample: tree with %d edges", P.nt);
+    SampleArgs a;
+    size_t lds = 0;
+    fill_args(w, &a, &lds);
+    a.seed = seed;
+    a.key_base = 0;
+    const bool sorted = count >= kSortMin;
+    const SampleKernel kfn = pick_sample(false, w->wide, sorted, a);
+    const size_t klds = sorted ? 0 : lds;
+    // the grid of sample_run: two rounds of the kernel's occupancy (at most
+    // one workgroup per 256 samples)
+    const u64 need = (count + kBlock - 1) / kBlock;
+    u64 blocks = need;
+    if (need > 256) {
+        int per_cu = 0, cus = 0, dev = 0;
+        TM_HIP(hipGetDevice(&dev));
+        TM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kfn), kBlock,
+                                                             klds));
+        TM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const u64 resident = per_cu > 0 && cus > 0 ? (u64)per_cu * cus : 1024;
+        blocks = std::min<u64>(need, 2 * resident);
+    }
+    blocks = std::max<u64>(1, std::min<u64>(blocks, (u64)kNoAllocMaxBlocks));
+    // carve the scratch copy: partials (blocks + 1), the flag word, four key
+    // and offset buffers, the sort's histograms
+    Partial* parts = reinterpret_cast<Partial*>(base);
+    unsigned char* at = base + align256(kNoAllocParts);
+    int* ovf = reinterpret_cast<int*>(at);
+    at += 256;
+    uint32_t* kb[4];
+    for (int x = 0; x < 4; ++x) {
+        kb[x] = reinterpret_cast<uint32_t*>(at);
+        at += align256(kNoAllocKeys);
+    }
+    uint32_t* hist = reinterpret_cast<uint32_t*>(at);
+    TM_TRY(fill_u32(ovf, 1, 0u, st));  // a fill kernel: the last call's flag is stale
+    a.parts = parts;
+    a.ovf = ovf;
+    a.j0 = j0;
+    a.count = count;
+    a.recs = recs;
+    const dim3 grid((unsigned)blocks);
+    if (sorted) {
+        const int key_bits = bits_of(2 * (u64)w->g->m - 1);
+        const dim3 rgrid((unsigned)std::min<u64>(need, 8192));
+        if (w->wide)
+            hipLaunchKernelGGL(root_kernel<u128>, rgrid, dim3(kBlock), lds, st, a, kb[0], kb[1]);
+        else
+            hipLaunchKernelGGL(root_kernel<u64>, rgrid, dim3(kBlock), lds, st, a, kb[0], kb[1]);
+        TM_HIP(hipGetLastError());
+        uint32_t *ks, *vs;
+        TM_TRY(radix_sort_pairs<uint32_t>(kb[0], kb[1], kb[2], kb[3], (int64_t)count, root_sort_lo_bit(key_bits),
+                                          key_bits, &ks, &vs, ovf, st, true, hist));
+        a.skey = ks;
+        a.sval = vs;
+    }
+    TM_HIP(launch_sample(kfn, grid, klds, st, a));
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const Partial*)parts, (int)grid.x,
+                       parts + blocks);
+    TM_HIP(hipGetLastError());
+    Partial h;
+    int hovf = 0;
+    TM_HIP(hipMemcpyAsync(&h, parts + blocks, sizeof h, hipMemcpyDeviceToHost, st));
+    TM_HIP(hipMemcpyAsync(&hovf, ovf, sizeof hovf, hipMemcpyDeviceToHost, st));
+    TM_HIP(hipStreamSynchronize(st));
+    if (hovf & 2) return tm_fail(TM_EDEVICE, "sample: inconsistent weight tables");
+    if (hovf || (h.flags & 1)) return tm_fail(TM_EOVERFLOW, "sample: a count reaches 2^128");
+    out->acc2.lo = (u64)h.acc2;
+    out->acc2.hi = (u64)(h.acc2 >> 64);
+    out->acc2_sq.lo = (u64)h.acc2_sq;
+    out->acc2_sq.hi = (u64)(h.acc2_sq >> 64);
+    out->n_valid = h.n_valid;
+    out->n_bad_vertex = h.n_vertex;
+    out->n_bad_delta = h.n_delta;
+    out->n_bad_order = h.n_order;
+    out->n_nonzero = h.n_nonzero;
+    if (h.flags & 2) out->flags |= TM_F_SQ_SATURATED;
+    return TM_OK;
+}

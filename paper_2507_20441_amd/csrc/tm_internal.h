@@ -212,6 +212,10 @@ int weights_enqueue(tm_weights* w, hipStream_t st, int* ovf,
 // flag and not waited for (weights_enqueue); W is then read with the sums,
 // *overflowed tells whether the tables overflowed (the result is then
 // unset), and only plain sampling (no records, no byte count) is allowed.
+// sample_run's non-deferred path with its temporaries in a file-scope device
+// array instead of allocations (tm_sample_noalloc).
+int sample_run_noalloc(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStream_t st, tm_result* out,
+                       tm_sample_rec* recs);
 int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStream_t st,
                tm_result* out, tm_sample_rec* recs, u64* model_bytes, const int* wflag = nullptr,
                bool* overflowed = nullptr);

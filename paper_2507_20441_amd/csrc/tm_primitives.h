@@ -319,7 +319,8 @@ struct HistReader {
 // yet and stands for 0 .. n-1 (the first pass makes them).
 template <typename K>
 int radix_sort_pairs(K* keys, uint32_t* vals, K* tkeys, uint32_t* tvals, int64_t n, int lo_bit,
-                     int nbits, K** k_out, uint32_t** v_out, int* ovf, hipStream_t st, bool iota_vals = false) {
+                     int nbits, K** k_out, uint32_t** v_out, int* ovf, hipStream_t st, bool iota_vals = false,
+                     uint32_t* hist_ext = nullptr) {
     K* ka = keys;
     uint32_t* va = vals;
     K* kb = tkeys;
@@ -328,8 +329,10 @@ int radix_sort_pairs(K* keys, uint32_t* vals, K* tkeys, uint32_t* tvals, int64_t
         const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
         const int npass = radix_passes(nbits - lo_bit);
         const int64_t maxdig = (int64_t)1 << ((nbits - lo_bit + npass - 1) / npass);
-        uint32_t* hist = nullptr;
-        TM_HIP(dev_alloc((void**)&hist, (ntiles * maxdig + maxdig) * sizeof(uint32_t), st));
+        // the digit histograms: (ntiles + 1) * maxdig words, from the caller
+        // (hist_ext, which must hold that many) or allocated here
+        uint32_t* hist = hist_ext;
+        if (!hist) TM_HIP(dev_alloc((void**)&hist, (ntiles * maxdig + maxdig) * sizeof(uint32_t), st));
         uint32_t* totals = hist + ntiles * maxdig;
         int shift = lo_bit;
         for (int p = 0; p < npass; ++p) {
@@ -346,7 +349,7 @@ int radix_sort_pairs(K* keys, uint32_t* vals, K* tkeys, uint32_t* tvals, int64_t
             uint32_t* tv = va; va = vb; vb = tv;
             shift += bits;
         }
-        TM_HIP(dev_free(hist, st));
+        if (!hist_ext) TM_HIP(dev_free(hist, st));
     }
     if (iota_vals && !(n > 1 && nbits > lo_bit)) TM_TRY(fill_iota_u32(va, n, st));  // no pass ran
     *k_out = ka;

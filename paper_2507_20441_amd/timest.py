@@ -127,6 +127,7 @@ def lib():
         L.tm_weights_intervals.argtypes = [vp, vp, vp]
         L.tm_sample.argtypes = [vp, u64, u64, u64, u64, vp, C.POINTER(Result), vp]
         L.tm_result_finish.argtypes = [C.POINTER(Result)]
+        L.tm_sample_noalloc.argtypes = [vp, u64, u64, u64, u64, vp, C.POINTER(Result), vp]
         L.tm_estimate.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), u64, u64, vp,
                                   C.POINTER(Result), vp]
         L.tm_sample_batch.argtypes = [C.POINTER(vp), C.POINTER(u64), C.POINTER(u64), C.c_int, vp,
@@ -337,6 +338,16 @@ class Weights:
             recs = (recs_dev.cpu().numpy().view(REC_DTYPE) if recs_dev is not None
                     else np.zeros(0, REC_DTYPE))
         return res, recs
+
+
+def sample_noalloc(w: "Weights", seed, count, j0=0, k_total=None, recs_ptr=None) -> "Result":
+    """tm_sample_noalloc: samples j0 .. j0 + count - 1 with no allocation in
+    the library; recs_ptr: None or a device pointer (int) to count records."""
+    res = Result()
+    k_total = count if k_total is None else k_total
+    _check(lib().tm_sample_noalloc(w.h, int(seed), int(j0), int(count), int(k_total), _stream(), C.byref(res),
+                                   C.c_void_p(recs_ptr) if recs_ptr else None), "sample_noalloc")
+    return res
 
 
 def estimate(g: Graph, mo: Motif, k, seed, tr: Tree = None, constraints=None, records=False):
