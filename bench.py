@@ -1,18 +1,22 @@
 #!/usr/bin/env python3
 """Throughput of the TIMEST hot path on one MI355X.
 
-One step is one pass of the whole path over the medium workload, starting
-from edge arrays already resident in device memory:
-  graph build (sort + lists) -> for each motif: weights -> 10^7 samples
+Default (the default line): the large workload.  One step is one pass of
+the whole path, starting from edge arrays already resident in device memory:
+  graph build (sorts + lists) -> for each motif: weights -> 10^8 samples
   (draw, validate, complete) -> reduction to the estimate.
-Workload: 100,000 vertices, 2,000,000 edges (Chung-Lu gamma = 2.1, bursty
-Pareto(1.5) per-source times over 1e7 s); 4-cycle and 4-leaf out-star at
-delta = 3,600 s; 10^7 samples per motif, seed 1.
+Workload: 2,000,000 vertices, 100,000,000 edges (90M Chung-Lu gamma 2.0 +
+10M reciprocated at +U{1..600} s, bursty Pareto(1.5) per-source times over
+3e7 s, drawn on the device); scatter-gather and 6-chain at delta 86,400 s;
+10^8 samples per motif, seed 1 (the 6-chain's weights need 128 bits).
 
-Prints one JSON line: samples/s over the timed steps, the roofline of the
-dominant kernel (bytes of its access model per launch over its average
-duration from HIP events on its stream) and the oracle's single-thread CPU
-throughput on a bounded sample of the same workload.
+The same JSON line carries: the roofline of the dominant kernel (the level
+kernels of the weight builds: their access-model bytes per launch over the
+average launch from HIP events in the timed region) and of the sampler, the
+graph build and the root draws; the oracle's single-thread CPU throughput on
+a bounded slice of the same workload; the batched-queue against one job per
+launch (64 jobs); the serving loop's p50/p99 latency on a short Poisson
+stream; and the medium workload's rate and sampler roofline.
 """
 import argparse
 import json
@@ -36,17 +40,25 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-slice-days", type=float, default=1.0,
+                    help="large: length (in delta) of the time slice the CPU baseline runs on")
     ap.add_argument("--cpu-samples", type=int, default=1_000_000,
                     help="oracle samples per motif in the CPU baseline (0: skip it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="before timing, run a plain device copy of BYTES (3 times) so that "
                          "hardware counters can be scaled by a kernel of known traffic")
     ap.add_argument("--workload", choices=["medium", "large", "batched", "serving", "weights", "ablation", "trees",
-                                           "family"],
-                    default="medium",
-                    help="medium: the single-job path (default); batched: 64 heterogeneous "
-                         "jobs, one launch per job against the batched pass; serving: a Poisson "
-                         "query stream against the server")
+                                           "family", "partial"],
+                    default="large",
+                    help="large: the 1e8-edge single-job path with every side leg (default); medium: "
+                         "the 2e6-edge path alone; batched: 64 heterogeneous jobs, one launch per job "
+                         "against the batched pass; serving: a Poisson query stream against the server; "
+                         "partial: partial-order motifs")
+    ap.add_argument("--legs", default="cpu,batched,serving,medium",
+                    help="large: side legs to run after the timed steps (comma list of cpu, batched, "
+                         "serving, medium; 'none' for profiling runs)")
+    ap.add_argument("--large-traffic", default=os.path.join(ROOT, "profiles", "large_kernel_traffic.json"),
+                    help="HBM bytes per launch of the large workload's kernels (JSON), if present")
     ap.add_argument("--weights-graph", choices=["medium", "serving"], default="serving",
                     help="weights: the medium graph, or the 5e8-edge serving graph")
     ap.add_argument("--weights-deltas", default="3600,86400")
@@ -64,7 +76,7 @@ def parse():
     ap.add_argument("--traffic-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic file (--traffic) from two rocprofv3 --pmc runs of this "
                          "bench with --copy-calibration: FETCH_SIZE, then WRITE_SIZE")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "sample_kernel_medium_traffic.json"),
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "medium_kernel_traffic.json"),
                     help="HBM bytes per launch from rocprofv3 counters (JSON), if present")
     return ap.parse_args()
 
@@ -78,8 +90,11 @@ def main():
         sys.exit(2)
 
     if args.traffic_summarize:
-        return summarize_traffic(args.traffic_summarize[0], args.traffic_summarize[1], args.traffic,
-                                 args.copy_calibration or (1 << 30))
+        out = args.large_traffic if args.workload == "large" else args.traffic
+        what = ("large (bench.py --workload large, one step)" if args.workload == "large"
+                else "medium (bench.py --workload medium, one step)")
+        return summarize_traffic(args.traffic_summarize[0], args.traffic_summarize[1], out,
+                                 args.copy_calibration or (1 << 30), what)
     if args.workload == "batched":
         return batched(args)
     if args.workload == "serving":
@@ -94,7 +109,15 @@ def main():
         return trees(args)
     if args.workload == "family":
         return family(args)
+    if args.workload == "partial":
+        return partial(args)
 
+    print(json.dumps(medium_run(args, args.steps, args.warmup, args.cpu_samples)), flush=True)
+
+
+def medium_run(args, steps, warmup, cpu_samples):
+    """The medium workload: one step is graph build + per motif weights,
+    1e7 samples and the reduction; returns the JSON line as a dict."""
     import ctypes as C
 
     import torch
@@ -144,8 +167,8 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    log(f"warmup x{args.warmup}")
-    for _ in range(args.warmup):
+    log(f"warmup x{warmup}")
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     prof = Profile()
@@ -154,30 +177,30 @@ def main():
     # (its average launch is the roofline's denominator)
     L.tm_profile_stages(1 << STAGES.index("sample"))
     L.tm_profile_enable(1)
-    log(f"timing x{args.steps}")
+    log(f"timing x{steps}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         results = step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     L.tm_profile_enable(0)
     L.tm_profile_read(C.byref(prof), 1)
-    samples = len(motifs) * k * args.steps
+    samples = len(motifs) * k * steps
     value = samples / elapsed
-    sample_ms = prof.ms[STAGES.index("sample")] / args.steps
-    sample_launches = prof.launches[STAGES.index("sample")] / args.steps
+    sample_ms = prof.ms[STAGES.index("sample")] / steps
+    sample_launches = prof.launches[STAGES.index("sample")] / steps
     # the stage breakdown: the same steps again with every stage timed
     # (outside the timed region)
     L.tm_profile_stages((1 << len(STAGES)) - 1)
     L.tm_profile_enable(1)
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
     L.tm_profile_enable(0)
     L.tm_profile_read(C.byref(prof), 1)
-    stage_ms = {STAGES[i]: prof.ms[i] / args.steps for i in range(len(STAGES))}
-    level_launches = prof.launches[STAGES.index("levels")] / args.steps
+    stage_ms = {STAGES[i]: prof.ms[i] / steps for i in range(len(STAGES))}
+    level_launches = prof.launches[STAGES.index("levels")] / steps
     log("stage ms per step", stage_ms)
 
     # Access-model bytes of the sampling kernel's launches in one step
@@ -199,42 +222,27 @@ def main():
     # ... and of the level kernels of one step's weight builds
     level_bytes = sum(T.weights_model_bytes(Gm, mo) for _, mo in motifs)
     Gm.close()
-    achieved = model_bytes / (sample_ms * 1e-3) / 1e9 if sample_ms > 0 else 0.0
     # counter-measured bytes, valid only for the kernel source they were taken on
-    traffic = level_traffic = None
-    if os.path.exists(args.traffic):
-        try:
-            tr = json.load(open(args.traffic))
-            if tr.get("source_sha") == kernel_source_sha():
-                traffic = tr.get("hbm_bytes_per_launch")
-            if tr.get("level_source_sha") == level_source_sha():
-                level_traffic = tr.get("kernels", {}).get("level_kernel", {}).get("hbm_bytes_per_launch")
-        except (OSError, ValueError):
-            traffic = level_traffic = None
-    roofline = dict(bound="hbm", kernel="sample_kernel", achieved=round(achieved, 2),
-                    peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 5),
-                    traffic=traffic, bytes_per_launch=model_bytes / sample_launches,
-                    avg_launch_ms=sample_ms / sample_launches)
+    traffic = load_traffic(args.traffic, "sample_kernel")
+    level_traffic = load_traffic(args.traffic, "level_kernel")
+    roofline = roofline_of("sample_kernel", model_bytes / sample_launches, sample_ms / sample_launches, traffic)
     # the weight builds' level kernels (times from the untimed stage run)
     level_ms = stage_ms["levels"]
-    lach = level_bytes / (level_ms * 1e-3) / 1e9 if level_ms > 0 else 0.0
-    weights_roofline = dict(bound="hbm", kernel="level_kernel", achieved=round(lach, 2), peak=HBM_PEAK_GBS,
-                            unit="GB/s", frac=round(lach / HBM_PEAK_GBS, 5), traffic=level_traffic,
-                            bytes_per_launch=level_bytes / level_launches if level_launches else None,
-                            avg_launch_ms=level_ms / level_launches if level_launches else None)
+    weights_roofline = roofline_of("level_kernel", level_bytes / level_launches if level_launches else 0,
+                                   level_ms / level_launches if level_launches else None, level_traffic)
 
     cpu = None
-    if args.cpu_samples > 0:
-        cpu = cpu_baseline(g, cfg, args.cpu_samples)
+    if cpu_samples > 0:
+        cpu = cpu_baseline(g, cfg, cpu_samples)
 
     line = {
         "metric": "samples/s at <=5% rel. err; batched-queue vs one-job-per-launch; p99 latency",
         "value": round(value, 1),
         "unit": "samples/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(elapsed * 1e3 / steps, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -252,7 +260,7 @@ def main():
         "weights_roofline": weights_roofline,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def batched(args):
@@ -510,10 +518,52 @@ def serving(args):
         g.close()
 
 
+def host_info():
+    """The host the CPU baseline ran on: logical CPUs and the CPU model."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def load_traffic(path, key):
+    """HBM bytes per launch of kernel `key` from a counter summary, or None
+    when the kernel's sources changed since the counters were taken."""
+    if not os.path.exists(path):
+        return None
+    try:
+        tr = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    k = tr.get("kernels", {}).get(key)
+    if not k or k.get("source_sha") != kernel_source_sha(k.get("source", "sample.hip")):
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def roofline_of(kernel, bytes_per_launch, avg_ms, traffic):
+    ach = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms and avg_ms > 0 else 0.0
+    out = dict(bound="hbm", kernel=kernel, achieved=round(ach, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+               frac=round(ach / HBM_PEAK_GBS, 5), traffic=traffic, bytes_per_launch=bytes_per_launch,
+               avg_launch_ms=avg_ms)
+    if traffic is not None and avg_ms:
+        # the counter-measured HBM bytes over the same launch time
+        out["traffic_frac"] = round(traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)
+    return out
+
+
 def large(args):
     """The large workload: 2e6 vertices, 1e8 edges (drawn on the device),
     scatter-gather and 6-chain at delta 86400, 1e8 samples each; a step is
-    the graph build, both weight sets, both sampling runs and reductions."""
+    the graph build, both weight sets, both sampling runs and reductions.
+    Inside the timed steps only the level kernels (the dominant stage) are
+    bracketed by HIP events; the full stage breakdown comes from a second,
+    untimed run of the same steps."""
     import torch
 
     from paper_2507_20441_amd import timest as T
@@ -521,9 +571,12 @@ def large(args):
 
     assert torch.cuda.is_available(), "bench needs a HIP device"
     torch.cuda.set_device(0)
+    legs = set() if args.legs == "none" else set(x for x in args.legs.split(",") if x)
+    log("generating the large workload on the device")
     u, v, t = W.large_graph_device()
     torch.cuda.synchronize()
     n = 2_000_000
+    m = int(u.numel())
     motifs = [(name, T.make_motif(W.MOTIFS[name], d)) for name, d in W.LARGE["motifs"]]
     k, seed = W.LARGE["k"], W.LARGE["seed"]
 
@@ -533,15 +586,27 @@ def large(args):
         for name, mo in motifs:
             w = T.Weights(g, mo)
             r, _ = w.sample(seed, k)
-            out.append((name, r.estimate, r.std_error, r.n_valid, w.W, w.info()["wide"]))
+            out.append((name, r, w.W, w.info()["wide"]))
             w.close()
         g.close()
         return out
 
+    if args.copy_calibration > 0:
+        a = torch.empty(args.copy_calibration, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    log(f"warmup x{args.warmup}")
     for _ in range(args.warmup):
         step()
+    torch.cuda.synchronize()
     T.profile_read(reset=True)
+    T.profile_stages(["levels"])
     T.profile_enable(True)
+    log(f"timing x{args.steps}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -550,6 +615,54 @@ def large(args):
     el = time.perf_counter() - t0
     T.profile_enable(False)
     prof = T.profile_read(reset=True)
+    li = T.STAGES.index("levels")
+    level_ms = prof["ms"][li] / args.steps
+    level_launches = prof["launches"][li] / args.steps
+    # the stage breakdown: the same steps again with every stage timed
+    nb = max(1, min(3, args.steps))
+    T.profile_stages(None)
+    T.profile_enable(True)
+    for _ in range(nb):
+        step()
+    torch.cuda.synchronize()
+    T.profile_enable(False)
+    bd = T.profile_read(reset=True)
+    stage_ms = {T.STAGES[i]: bd["ms"][i] / nb for i in range(len(T.STAGES))}
+    stage_n = {T.STAGES[i]: bd["launches"][i] / nb for i in range(len(T.STAGES))}
+    log("stage ms per step", {a: round(b, 3) for a, b in stage_ms.items()})
+    # access-model bytes of one step's level kernels and sampling kernels
+    # (counting variants, outside the timed region)
+    g = T.Graph(u, v, t, n)
+    level_bytes = sum(T.weights_model_bytes(g, mo) for _, mo in motifs)
+    sample_bytes = 0
+    for _, mo in motifs:
+        w = T.Weights(g, mo)
+        sample_bytes += T.sample_model_bytes(w, seed, k)
+        w.close()
+    g.close()
+    traffic = args.large_traffic
+    roof = roofline_of("level_kernel", level_bytes / level_launches if level_launches else 0,
+                       level_ms / level_launches if level_launches else None,
+                       load_traffic(traffic, "level_kernel"))
+    s_n = stage_n["sample"]
+    sample_roof = roofline_of("sample_kernel", sample_bytes / s_n if s_n else 0,
+                              stage_ms["sample"] / s_n if s_n else None, load_traffic(traffic, "sample_kernel"))
+    # graph build: the 76 B per edge the path must move (16 read: the edge;
+    # about 60 written: eid order, out- and in-lists, multi-edge runs), over
+    # the whole graph stage (its sorts are implementation bytes on top)
+    g_n = stage_n["graph"]
+    graph_roof = roofline_of("graph build (all kernels)", 76.0 * m, stage_ms["graph"] / g_n if g_n else None,
+                             load_traffic(traffic, "graph_build"))
+    graph_roof["bytes_per_edge"] = 76
+    # root draws: per draw two 16 B guide entries and the 4 B key written;
+    # the stage also holds the sort by root (reported in sort_bytes)
+    r_n = stage_n["roots"]
+    draws = len(motifs) * k
+    roots_roof = roofline_of("root draws + sort", 36.0 * draws / r_n if r_n else 0,
+                             stage_ms["roots"] / r_n if r_n else None, load_traffic(traffic, "root_kernel"))
+    roots_roof["bytes_per_draw"] = 36
+    roots_roof["root_kernel_traffic"] = roots_roof.pop("traffic")
+    roots_roof.pop("traffic_frac", None)
     total = len(motifs) * k * args.steps
     line = {
         "metric": "samples/s at <=5% rel. err; batched-queue vs one-job-per-launch; p99 latency",
@@ -558,13 +671,231 @@ def large(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "large: 2e6 vertices, 1e8 edges (90M Chung-Lu 2.0 + 10M reciprocated, bursty "
                                "times over 3e7 s, drawn on the device), scatter-gather and 6-chain at delta "
-                               "86400, 1e8 samples each; graph build + weights + sampling per step",
-                   "m": int(u.numel()), "n": n, "k_per_motif": k},
-        "stages_ms_per_step": {T.STAGES[i]: round(prof["ms"][i] / args.steps, 3) for i in range(len(T.STAGES))},
-        "estimates": [dict(motif=a, estimate=b, rel_ci95=(1.96 * c / b) if b else None, valid=d, W=str(e), wide=f)
-                      for a, b, c, d, e, f in res],
+                               "86400, 1e8 samples each, seed 1; graph build + weights + sampling + reduction "
+                               "per step",
+                   "m": m, "n": n, "k_per_motif": k},
+        "stages_ms_per_step": {a: round(b, 3) for a, b in stage_ms.items()},
+        "estimates": [dict(motif=a, estimate=r.estimate, std_error=r.std_error,
+                           rel_ci95=(1.96 * r.std_error / r.estimate) if r.estimate else None,
+                           valid=r.n_valid, W=str(Wv), wide=wide) for a, r, Wv, wide in res],
+        "roofline": roof,
+        "sample_roofline": sample_roof,
+        "graph_roofline": graph_roof,
+        "roots_roofline": roots_roof,
     }
+    cpu = None
+    if "cpu" in legs and args.cpu_samples > 0:
+        cpu = cpu_baseline_large(u, v, t, n, motifs, k, seed, args.cpu_slice_days, min(args.cpu_samples, 4000))
+    line["cpu_baseline"] = cpu
+    del u, v, t
+    torch.cuda.empty_cache()
+    if "batched" in legs:
+        line["batched"] = batched_leg(args)
+    if "serving" in legs:
+        line["serving"] = serving_leg(args)
+    if "medium" in legs:
+        med = medium_run(args, 10, 2, 0)
+        line["medium"] = {"value": med["value"], "ms_per_step": med["ms_per_step"],
+                          "stages_ms_per_step": med["stages_ms_per_step"], "roofline": med["roofline"],
+                          "weights_roofline": med["weights_roofline"],
+                          "estimates": [dict(motif=e["motif"], rel_ci95=e["rel_ci95"]) for e in med["estimates"]],
+                          "workload": med["config"]["workload"]}
     print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_large(u, v, t, n, motifs, k, seed, slice_days, n_samples):
+    """The oracle, single-threaded, on a time slice of the large graph: the
+    edges with time in [t0, t0 + slice_days * delta) (t0 at the middle of the
+    span), its graph build, the weights of both motifs and n_samples samples
+    each.  Scaled to the whole workload: the graph build by edges, the
+    weights by intervals (the slice's weights cover one interval's share; the
+    whole graph has q), the sampling by samples.  A slice's windows near its
+    end hold fewer candidates than in the whole graph, so the scaled figure
+    favours the oracle."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+
+    delta = motifs[0][1].delta
+    tmax = int(t.max().item())
+    t0 = (tmax // 2 // delta) * delta
+    t1 = t0 + int(slice_days * delta)
+    sel = (t >= t0) & (t < t1)
+    su, sv, st = (x[sel].cpu().numpy() for x in (u, v, t))
+    ms = len(su)
+    q = tmax // delta + 1
+    log(f"cpu baseline: oracle on a {slice_days}-delta slice ({ms} edges), {n_samples} samples per motif")
+    a = time.perf_counter()
+    og = O.Graph(su, sv, st, n)
+    t_graph = (time.perf_counter() - a) * (len(t) / max(1, ms))
+    total = t_graph
+    parts = []
+    for name, mo in motifs:
+        omo = O.make_motif([(mo.src[p], mo.dst[p]) for p in range(mo.l)], mo.delta)
+        a = time.perf_counter()
+        P = O.Prep(og, omo)
+        b = time.perf_counter()
+        P.sample(seed, k, j0=0, count=n_samples)
+        c = time.perf_counter()
+        # the slice's weights: one interval's share when slice_days <= 2
+        share = max(1.0, slice_days / 2.0)
+        w_est = (b - a) / share * q
+        s_est = (c - b) * (k / n_samples)
+        parts.append(dict(motif=name, weights_s_measured=round(b - a, 3), weights_s_scaled=round(w_est, 1),
+                          samples_s_measured=round(c - b, 3), samples_s_scaled=round(s_est, 1)))
+        total += w_est + s_est
+        del P
+    value = len(motifs) * k / total
+    return dict(value=round(value, 3), unit="samples/s", cores=1, kind="oracle",
+                sample=f"single-threaded oracle on the edges with time in [{t0}, {t1}) ({ms} of {len(t)} edges, "
+                       f"{slice_days} delta at mid-span): graph build, weights of both motifs, {n_samples} of "
+                       f"{k} samples each; scaled to the workload (graph by edges, weights by the {q} "
+                       "intervals, sampling by samples); favours the oracle (truncated windows at the "
+                       "slice's end)",
+                host=host_info(), parts=parts, seconds_scaled=round(total, 1))
+
+
+def batched_leg(args):
+    """The batched workload's 64 jobs (graphs drawn on the device): one
+    tm_estimate per job against the eager batch (tm_estimate_batch, autotuned
+    schedule) and the recorded pipeline's replay; identical results required."""
+    import torch
+
+    from paper_2507_20441_amd import autotune
+    from paper_2507_20441_amd import timest as T
+    from paper_2507_20441_amd import workloads as W
+
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    jobs = W.batched_jobs()
+    log(f"batched leg: {len(jobs)} graphs on the device")
+    graphs = []
+    for j in jobs:
+        uu, vv, tt = W.device_graph(j["n"], j["m"], 2.1, j["graph_seed"])
+        graphs.append(T.Graph(uu, vv, tt, j["n"]))
+        del uu, vv, tt
+    motifs = [T.make_motif(W.MOTIFS[j["motif"]], j["delta"]) for j in jobs]
+    ks = [j["k"] for j in jobs]
+    seeds = [j["seed"] for j in jobs]
+    total = sum(ks)
+    ws = [T.Weights(g, mo) for g, mo in zip(graphs, motifs)]
+    choice, times = autotune.tune(ws, ks, seeds, cus)
+    for w in ws:
+        w.close()
+    plan = T.BatchPlan(graphs, motifs, ks, seeds)
+
+    def per_job():
+        return [T.estimate(g, mo, kk, s) for g, mo, kk, s in zip(graphs, motifs, ks, seeds)]
+
+    def same_all(xs, ys):
+        return all(a.acc2.value == b.acc2.value and a.acc2_sq.value == b.acc2_sq.value and a.n_valid == b.n_valid
+                   and a.estimate == b.estimate for a, b in zip(xs, ys))
+
+    ref = per_job()
+    got = T.estimate_batch(graphs, motifs, ks, seeds)
+    rep = plan.run()
+    same = same_all(ref, got) and same_all(ref, rep)
+    tj, tb, tr = [], [], []
+    for _ in range(3):
+        for fn, acc in ((per_job, tj), (lambda: T.estimate_batch(graphs, motifs, ks, seeds), tb), (plan.run, tr)):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            acc.append(time.perf_counter() - a)
+            same = same and same_all(ref, out)
+    plan.close()
+    for g in graphs:
+        g.close()
+    rel = [1.96 * r.std_error / r.estimate for r in got if r.estimate > 0]
+    return {"workload": "batched: 64 jobs, graphs log-uniform 1e4..5e6 edges (medium shape, drawn on the device), "
+                        "motifs uniform over 5, delta log-uniform 600..86400, k log-uniform 1e5..1e7",
+            "samples_total": total, "edges_total": sum(j["m"] for j in jobs),
+            "one_job_per_launch_samples_per_s": round(total / min(tj), 1),
+            "eager_batch_samples_per_s": round(total / min(tb), 1),
+            "replay_samples_per_s": round(total / min(tr), 1),
+            "speedup_replay": round(min(tj) / min(tr), 3), "speedup_eager": round(min(tj) / min(tb), 3),
+            "ms": {"one_job_per_launch": round(min(tj) * 1e3, 3), "eager_batch": round(min(tb) * 1e3, 3),
+                   "replay": round(min(tr) * 1e3, 3)},
+            "schedule": {"tile": choice[0], "samples_per_lane": choice[0] // 256, "blocks": choice[1],
+                         "root_lds": choice[2]},
+            "identical_to_one_job_per_launch": bool(same), "rel_ci95_max": max(rel) if rel else None}
+
+
+def serving_leg(args, seconds=10.0, rate=200.0):
+    """A short open-loop stream against the server: the eight 1e6-edge
+    resident graphs of the serving workload, Poisson arrivals at `rate` for
+    `seconds`, every weight set built first; latency is measured by the
+    server from submit to result."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2507_20441_amd import timest as T
+    from paper_2507_20441_amd import workloads as W
+
+    specs = W.serving_graph_specs()[1:]
+    graphs = []
+    for sp in specs:
+        uu, vv, tt = W.device_graph(sp["n"], sp["m"], 2.1, sp["seed"])
+        graphs.append(T.Graph(uu, vv, tt, sp["n"]))
+        del uu, vv, tt
+    torch.cuda.synchronize()
+    qs = [dict(q, graph=q["graph"]) for q in W.serving_queries(seconds, rate, len(graphs))]
+    motifs = {(q["motif"], q["delta"]): T.make_motif(W.MOTIFS[q["motif"]], q["delta"]) for q in qs}
+    budget = int(torch.cuda.mem_get_info()[0] - 4 * 2**30)
+    log(f"serving leg: {len(qs)} queries over {seconds} s on {len(graphs)} graphs")
+    srv = T.Server(budget)
+    gids = [srv.add_graph(g) for g in graphs]
+    for gi, name, delta in sorted({(q["graph"], q["motif"], q["delta"]) for q in qs}):
+        srv.wait(srv.submit(gids[gi], motifs[(name, delta)], 0, 1))
+    tickets = [None] * len(qs)
+    res = [None] * len(qs)
+    ready = threading.Semaphore(0)
+
+    def collect():
+        for i in range(len(qs)):
+            ready.acquire()
+            try:
+                res[i] = srv.wait(tickets[i])
+            except T.TimestError:
+                res[i] = None
+
+    th = threading.Thread(target=collect)
+    th.start()
+    start = time.perf_counter()
+    for i, q in enumerate(qs):
+        delay = start + q["at"] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        tickets[i] = srv.submit(gids[q["graph"]], motifs[(q["motif"], q["delta"])], q["k"], q["seed"])
+        ready.release()
+    th.join()
+    wall = time.perf_counter() - start
+    st = srv.stats()
+    srv.close()
+    ok = [x for x in res if x is not None]
+    lat = np.array([info.latency_ms for _, info in ok])
+    served = sum(q["k"] for q, x in zip(qs, res) if x is not None)
+    # a few served results against the same query alone
+    same = True
+    for i in range(0, len(qs), max(1, len(qs) // 8)):
+        if res[i] is None:
+            continue
+        q = qs[i]
+        a = T.estimate(graphs[q["graph"]], motifs[(q["motif"], q["delta"])], q["k"], q["seed"])
+        same = same and a.acc2.value == res[i][0].acc2.value and a.estimate == res[i][0].estimate
+    for g in graphs:
+        g.close()
+    return {"workload": f"serving (short): the eight 1e6-edge resident graphs of the serving workload, Poisson "
+                        f"{rate}/s for {seconds} s, motif uniform over 5, delta over 8 values 600..86400, k "
+                        "log-uniform 1e5..1e7, warm weight cache",
+            "queries": len(qs), "failed": len(qs) - len(ok),
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "max": float(lat.max())},
+            "served_samples_per_s": round(served / wall, 1), "offered_samples_per_s": round(served / seconds, 1),
+            "passes": st["passes"], "identical_alone_vs_mix": bool(same)}
 
 
 ABLATION_MODES = (("C1", 0), ("C1+2", 1), ("C1+3", 2), ("C1+2+3", 3))
@@ -759,6 +1090,60 @@ def family(args):
     print(json.dumps(line), flush=True)
 
 
+def partial(args):
+    """Partial-order motifs on the medium graph (1e7 samples each, delta
+    3600): per motif, the weight build and the sampling timed with the
+    library's stage events, the samples/s of the whole estimate, the
+    sampler's access-model roofline and the 95% half-width; next to each,
+    the same edges under their listed total order."""
+    import torch
+
+    from paper_2507_20441_amd import timest as T
+    from paper_2507_20441_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    torch.cuda.set_device(0)
+    mg = W.medium_graph()
+    g = T.Graph(mg.src, mg.dst, mg.t, mg.n)
+    k, seed, delta = 10_000_000, 1, 3600
+    rows = []
+    for name in ("po_fan3", "po_cycle3", "po_sg", "po_free2", "po_diamond"):
+        edges, before = W.PO_MOTIFS[name]
+        for order, mo in (("partial", T.make_motif(edges, delta, before=before)),
+                          ("total", T.make_motif(edges, delta))):
+            for _ in range(max(1, args.warmup)):
+                T.estimate(g, mo, k, seed)
+            torch.cuda.synchronize()
+            T.profile_read(reset=True)
+            T.profile_enable(True)
+            best = None
+            for _ in range(max(1, args.steps)):
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                r = T.estimate(g, mo, k, seed)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - a
+                best = dt if best is None else min(best, dt)
+            T.profile_enable(False)
+            pr = T.profile_read(reset=True)
+            si = T.STAGES.index("sample")
+            w = T.Weights(g, mo)
+            mb = T.sample_model_bytes(w, seed, k)
+            W_ = w.W
+            w.close()
+            s_ms = pr["ms"][si] / max(1, pr["launches"][si])
+            rows.append(dict(motif=name, order=order, samples_per_s=round(k / best, 1), ms=round(best * 1e3, 3),
+                             weights_ms=round(pr["ms"][T.STAGES.index("weights")] / max(1, args.steps), 3),
+                             sample_roofline=roofline_of("sample_kernel", mb, s_ms, None),
+                             W=str(W_), valid=r.n_valid / k, estimate=r.estimate,
+                             rel_ci95=(1.96 * r.std_error / r.estimate) if r.estimate else None))
+            log(rows[-1])
+    g.close()
+    print(json.dumps({"workload": "partial-order motifs on the medium graph (delta 3600, 1e7 samples each); "
+                                  "each next to its edges under the listed total order", "motifs": rows}),
+          flush=True)
+
+
 def weights_only(args):
     """Weight builds alone (tm_weights_create) for every motif at each delta,
     timed with the library's stage events, plus 1e6 samples each as a check."""
@@ -800,17 +1185,28 @@ def weights_only(args):
     g.close()
 
 
+# Kernels whose HBM traffic the summaries record: a name test on the demangled
+# kernel name and the source file whose hash keys the figure.  Counting
+# variants (second template argument true) are left out.
+def _targs(name):
+    a = name.find("<")
+    b = name.rfind(">")
+    return [x.strip() for x in name[a + 1:b].split(",")] if a >= 0 and b > a else []
+
+
 TRAFFIC_KERNELS = {
-    "sample_kernel": "sample_kernel<unsigned long long, false, false, true, true",
-    "root_kernel": "root_kernel<unsigned long long>",
-    "level_kernel": "level_kernel<unsigned long long, false>",
+    "sample_kernel": (lambda nm: "sample_kernel<" in nm and "batch_" not in nm and _targs(nm)[1:2] == ["false"],
+                      "sample.hip"),
+    "root_kernel": (lambda nm: "root_kernel<" in nm and "batch_" not in nm, "sample.hip"),
+    "level_kernel": (lambda nm: "level_kernel<" in nm and _targs(nm)[1:2] == ["false"], "weights.hip"),
 }
 
 
-def summarize_traffic(fetch_dir, write_dir, out_path, calib_bytes):
+def summarize_traffic(fetch_dir, write_dir, out_path, calib_bytes, workload):
     """HBM bytes per launch of the main kernels from rocprofv3 counter CSVs:
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the same
-    counter reads for a device copy of calib_bytes in the same run."""
+    counter reads for a device copy of calib_bytes in the same run; a key's
+    figure is the mean over every launch of the kernels it covers."""
     import csv
     import glob
     import statistics
@@ -836,33 +1232,31 @@ def summarize_traffic(fetch_dir, write_dir, out_path, calib_bytes):
     f_scale = calib_bytes / 1024.0 / f_cal
     w_scale = calib_bytes / 1024.0 / w_cal
     kernels = {}
-    for key, pat in TRAFFIC_KERNELS.items():
-        fn = [n for n in fk if pat in n]
-        wn = [n for n in wk if pat in n]
-        if not fn or not wn:
+    for key, (test, src) in TRAFFIC_KERNELS.items():
+        fv = [x for nm, vs in fk.items() if test(nm.replace("(anonymous namespace)::", "")) for x in vs]
+        wv = [x for nm, vs in wk.items() if test(nm.replace("(anonymous namespace)::", "")) for x in vs]
+        if not fv or not wv:
             continue
-        fv, wv = fk[fn[0]], wk[wn[0]]
+        names = sorted({nm.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+                        for nm in fk if test(nm.replace("(anonymous namespace)::", ""))})
         fb = statistics.mean(fv) * 1024 * f_scale
         wb = statistics.mean(wv) * 1024 * w_scale
-        name = fn[0].replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
-        kernels[key] = dict(name=name,
-                            launches=len(fv), fetch_kib_per_launch=fv, write_kib_per_launch=wv,
+        kernels[key] = dict(names=names, source=src, source_sha=kernel_source_sha(src), launches=len(fv),
                             fetch_bytes_per_launch=round(fb), write_bytes_per_launch=round(wb),
                             hbm_bytes_per_launch=round(fb + wb))
     doc = {
-        "workload": "medium (bench.py defaults, one step)",
-        "source_sha": kernel_source_sha(),
-        "level_source_sha": level_source_sha(),
+        "workload": workload,
         "copy_calibration": {"bytes": calib_bytes, "fetch_kib": f_cal, "write_kib": w_cal,
                              "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4)},
         "kernels": kernels,
-        "hbm_bytes_per_launch": kernels.get("sample_kernel", {}).get("hbm_bytes_per_launch"),
         "commands": [
             "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d <fetch> -o fetch "
-            "-- python3 <repo>/bench.py --steps 1 --warmup 0 --cpu-samples 0 --copy-calibration 1073741824",
+            "-- python3 <repo>/bench.py --workload <w> --steps 1 --warmup 0 --cpu-samples 0 --legs none "
+            "--copy-calibration 1073741824",
             "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d <write> -o write "
-            "-- python3 <repo>/bench.py --steps 1 --warmup 0 --cpu-samples 0 --copy-calibration 1073741824",
-            "python3 bench.py --traffic-summarize <fetch> <write>",
+            "-- python3 <repo>/bench.py --workload <w> --steps 1 --warmup 0 --cpu-samples 0 --legs none "
+            "--copy-calibration 1073741824",
+            "python3 bench.py --workload <w> --traffic-summarize <fetch> <write>",
         ],
     }
     with open(out_path, "w") as f:
@@ -878,11 +1272,6 @@ def kernel_source_sha(main="sample.hip"):
         with open(os.path.join(ROOT, "paper_2507_20441_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
-
-
-def level_source_sha():
-    """Hash of the level kernel's sources (its counters' validity key)."""
-    return kernel_source_sha("weights.hip")
 
 
 def cpu_baseline(g, cfg, n_samples):

@@ -6,6 +6,7 @@ this package; the GPU library never does.
 """
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -172,11 +173,9 @@ class Graph:
         if rc != OR_OK:
             raise OracleError(rc, "graph_create")
         self.h = h
-
-    def __del__(self):
-        if getattr(self, "h", None):
-            lib().or_graph_destroy(self.h)
-            self.h = None
+        # released with the object, or at exit before module teardown (the
+        # finalizer holds the destroy function itself)
+        weakref.finalize(self, lib().or_graph_destroy, h)
 
     def edges(self):
         s = np.empty(self.m, np.int32)
@@ -244,6 +243,8 @@ class Prep:
         if rc != OR_OK:
             raise OracleError(rc, "prepare")
         self.h = h
+        self._g = g  # the graph outlives its preparations
+        weakref.finalize(self, lib().or_prep_destroy, h)
 
     def edge_weight(self, interval, s, eid, work_limit=1 << 62):
         """w_i(s, e) of one edge by the recursive rule (no tables); None when
@@ -256,10 +257,6 @@ class Prep:
             raise OracleError(rc, "edge_weight")
         return out.value
 
-    def __del__(self):
-        if getattr(self, "h", None):
-            lib().or_prep_destroy(self.h)
-            self.h = None
 
     @property
     def W(self) -> int:
