@@ -78,6 +78,16 @@ int DevArena::alloc(void** p, size_t nbytes) {
     return TM_OK;
 }
 
+void DevArena::release_one(void* p, size_t nbytes) {
+    for (size_t x = 0; x < blocks.size(); ++x) {
+        if (blocks[x] != p) continue;
+        blocks.erase(blocks.begin() + (long)x);
+        bytes -= (nbytes ? (nbytes + 255) & ~(size_t)255 : 256);
+        (void)dev_free(p, stream);
+        return;
+    }
+}
+
 // Called when no work of the library is in flight (every entry point
 // synchronises before it returns), so the blocks are free for any stream.
 void DevArena::release() {

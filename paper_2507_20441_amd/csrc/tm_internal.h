@@ -38,6 +38,8 @@ struct DevArena {
     uint64_t bytes = 0;
     hipStream_t stream = nullptr;
     int alloc(void** p, size_t nbytes);
+    // return one block (work using it must be enqueued on `stream` before)
+    void release_one(void* p, size_t nbytes);
     void release();
 };
 

@@ -416,13 +416,76 @@ ioff_kernel(const W* cum, const W* qc0, const W* qc1, const int32_t* ilo, int64_
 
 unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// A prefix array read back as its values: consecutive differences modulo
+// 2^64, which are the exact values whenever each value is below 2^64 (the
+// level kernels flag any product that is not), however the sums wrapped.
+struct WrappedDiff {
+    const u64* q;
+    __device__ u128 operator()(int64_t p) const { return (u128)(u64)(q[p + 1] - q[p]); }
+};
+
+// The center's prefix arrays in eid order from src[par] (its values), then
+// the interval bounds, the prefix of W_i, the per-interval offsets and the
+// root guide.  ovf: the flag word of these scans.
+template <typename W, typename R>
+int finish_tables(tm_weights* w, hipStream_t st, int* ovf, const R (&src)[2]) {
+    tm_graph* g = w->g;
+    const HostPlan& P = w->plan;
+    const int64_t m = g->m;
+    for (int par = 0; par < 2; ++par) {
+        W* qc;
+        TM_TRY(arena_alloc(w->arena, &qc, (size_t)m + 1));
+        TM_TRY(device_exclusive_scan<W>(src[par], m, qc, ovf, st));
+        w->qc[par] = qc;
+    }
+    // intervals and their weights
+    TM_TRY(arena_alloc(w->arena, &w->ilo, (size_t)w->q));
+    TM_TRY(arena_alloc(w->arena, &w->ihi, (size_t)w->q));
+    hipLaunchKernelGGL(interval_kernel, dim3(grid_for(w->q)), dim3(kBlock), 0, st, g->d.t, m, w->q,
+                       w->ilen, w->ilo, w->ihi);
+    TM_HIP(hipGetLastError());
+    W* cum;
+    TM_TRY(arena_alloc(w->arena, &cum, (size_t)w->q + 1));
+    TM_TRY(device_exclusive_scan<W>(
+        IntervalWeight<W>{static_cast<const W*>(w->qc[0]), static_cast<const W*>(w->qc[1]), w->ilo,
+                          w->ihi},
+        w->q, cum, ovf, st));
+    w->cumW = cum;
+    // per-interval offsets and the root guide
+    W* ioff;
+    TM_TRY(arena_alloc(w->arena, &ioff, (size_t)w->q));
+    hipLaunchKernelGGL((ioff_kernel<W>), dim3(grid_for(w->q)), dim3(kBlock), 0, st, (const W*)cum,
+                       (const W*)w->qc[0], (const W*)w->qc[1], (const int32_t*)w->ilo, w->q, ioff);
+    TM_HIP(hipGetLastError());
+    w->ioff = ioff;
+    w->guide_bits = guide_bits_for(m, w->lean);
+    const int gc = w->guide_bits - kGuideStepBits;
+    const int64_t nb = ((int64_t)1 << w->guide_bits) + 1, nc = ((int64_t)1 << gc) + 1;
+    TM_TRY(arena_alloc(w->arena, &w->guide, (size_t)nb));
+    RootGuide* coarse = nullptr;
+    TM_HIP(dev_alloc((void**)&coarse, (size_t)nc * sizeof(RootGuide), st));
+    hipLaunchKernelGGL((guide_kernel<W>), dim3(grid_for(nc)), dim3(kBlock), 0, st, (const W*)cum, w->qc[0],
+                       w->qc[1], w->ilo, w->ihi, w->q, w->g->d.tpos[P.root_dir], gc, coarse);
+    TM_HIP(hipGetLastError());
+    hipLaunchKernelGGL((guide_fill_kernel<W>), dim3(grid_for(nb)), dim3(kBlock), 0, st, (const W*)cum,
+                       w->qc[0], w->qc[1], w->ilo, w->ihi, (const W*)ioff, w->q, w->g->d.tpos[P.root_dir],
+                       w->guide_bits, (const RootGuide*)coarse, w->guide);
+    TM_HIP(hipGetLastError());
+    TM_HIP(dev_free(coarse, st));
+    return TM_OK;
+}
+
 // check_each_level: read the overflow flag after every level and stop at the
 // first overflow (the synchronous build, which then restarts in 128 bits).
+// ovf: the flag of the level kernels and of the non-center prefix sums;
+// ovf_c: the flag of the center's prefix sums and the interval totals (the
+// caller may pass ovf for both).  When only ovf_c is set, every per-edge
+// value was exact and only the totals along eid order outgrew W.
 template <typename W>
 // nbytes (optional): the level kernels' access-model bytes are added there.
 // level_timers (optional): each level launch's stage timer, for the caller to
 // finish once the stream is synchronised.
-int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level = false,
+int build_typed(tm_weights* w, hipStream_t st, int* ovf, int* ovf_c, bool check_each_level = false,
                 unsigned long long* nbytes = nullptr,
                 std::vector<std::unique_ptr<StageTimer>>* level_timers = nullptr) {
     tm_graph* g = w->g;
@@ -573,50 +636,54 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, bool check_each_level =
             }
         }
     }
-    // the center: prefix sums in eid order (slot 0 is the center)
+    // the center: prefix sums in eid order (slot 0 is the center), then the
+    // interval tables
+    {
+        const Plain<W> src[2] = {Plain<W>{static_cast<const W*>(w->vals[0][0])},
+                                 Plain<W>{static_cast<const W*>(w->vals[0][1])}};
+        TM_TRY(finish_tables<W>(w, st, ovf_c, src));
+    }
     for (int par = 0; par < 2; ++par) {
-        W* qc;
-        TM_TRY(arena_alloc(w->arena, &qc, (size_t)m + 1));
-        TM_TRY(device_exclusive_scan<W>(Plain<W>{static_cast<const W*>(w->vals[0][par])}, m, qc,
-                                        ovf, st));
-        w->qc[par] = qc;
         TM_HIP(dev_free(w->vals[0][par], st));
         w->vals[0][par] = nullptr;
     }
-    // intervals and their weights
-    TM_TRY(arena_alloc(w->arena, &w->ilo, (size_t)w->q));
-    TM_TRY(arena_alloc(w->arena, &w->ihi, (size_t)w->q));
-    hipLaunchKernelGGL(interval_kernel, dim3(grid_for(w->q)), dim3(kBlock), 0, st, g->d.t, m, w->q,
-                       w->ilen, w->ilo, w->ihi);
-    TM_HIP(hipGetLastError());
-    W* cum;
-    TM_TRY(arena_alloc(w->arena, &cum, (size_t)w->q + 1));
-    TM_TRY(device_exclusive_scan<W>(
-        IntervalWeight<W>{static_cast<const W*>(w->qc[0]), static_cast<const W*>(w->qc[1]), w->ilo,
-                          w->ihi},
-        w->q, cum, ovf, st));
-    w->cumW = cum;
-    // per-interval offsets and the root guide
-    W* ioff;
-    TM_TRY(arena_alloc(w->arena, &ioff, (size_t)w->q));
-    hipLaunchKernelGGL((ioff_kernel<W>), dim3(grid_for(w->q)), dim3(kBlock), 0, st, (const W*)cum,
-                       (const W*)w->qc[0], (const W*)w->qc[1], (const int32_t*)w->ilo, w->q, ioff);
-    TM_HIP(hipGetLastError());
-    w->ioff = ioff;
-    w->guide_bits = guide_bits_for(m, w->lean);
-    const int gc = w->guide_bits - kGuideStepBits;
-    const int64_t nb = ((int64_t)1 << w->guide_bits) + 1, nc = ((int64_t)1 << gc) + 1;
-    TM_TRY(arena_alloc(w->arena, &w->guide, (size_t)nb));
-    RootGuide* coarse = nullptr;
-    TM_HIP(dev_alloc((void**)&coarse, (size_t)nc * sizeof(RootGuide), st));
-    hipLaunchKernelGGL((guide_kernel<W>), dim3(grid_for(nc)), dim3(kBlock), 0, st, (const W*)cum, w->qc[0],
-                       w->qc[1], w->ilo, w->ihi, w->q, w->g->d.tpos[P.root_dir], gc, coarse);
-    TM_HIP(hipGetLastError());
-    hipLaunchKernelGGL((guide_fill_kernel<W>), dim3(grid_for(nb)), dim3(kBlock), 0, st, (const W*)cum,
-                       w->qc[0], w->qc[1], w->ilo, w->ihi, (const W*)ioff, w->q, w->g->d.tpos[P.root_dir],
-                       w->guide_bits, (const RootGuide*)coarse, w->guide);
-    TM_HIP(hipGetLastError());
-    TM_HIP(dev_free(coarse, st));
+    return TM_OK;
+}
+
+// The 64-bit tables made 128-bit without recomputing any level: every
+// per-edge value is exact (no product overflowed) and only prefix totals
+// outgrew 64 bits.  Each prefix array is rebuilt in 128 bits from its own
+// consecutive differences; the center's, the interval tables and the guide
+// follow.  Kept windows are positions and stay.
+int widen_tables(tm_weights* w, hipStream_t st, int* ovf) {
+    const HostPlan& P = w->plan;
+    const int64_t m = w->g->m;
+    const size_t old_bytes = (size_t)(m + 1) * sizeof(u64);
+    for (int s = 1; s < P.nt; ++s) {
+        for (int par = 0; par < 2; ++par) {
+            for (int order = 0; order < 2; ++order) {
+                void*& tab = order == 0 ? w->qt[s][par] : w->qn[s][par];
+                if (!tab) continue;
+                u128* wide;
+                TM_TRY(arena_alloc(w->arena, &wide, (size_t)m + 1));
+                TM_TRY(device_exclusive_scan<u128>(WrappedDiff{static_cast<const u64*>(tab)}, m, wide, ovf, st));
+                w->arena.release_one(tab, old_bytes);
+                tab = wide;
+            }
+        }
+    }
+    const void* qc64[2] = {w->qc[0], w->qc[1]};
+    void* old[6] = {w->qc[0], w->qc[1], w->ilo, w->ihi, w->cumW, w->ioff};
+    const size_t old_sz[6] = {old_bytes, old_bytes, (size_t)w->q * 4, (size_t)w->q * 4,
+                              (size_t)(w->q + 1) * 8, (size_t)w->q * 8};
+    void* old_guide = w->guide;
+    const size_t guide_sz = (((size_t)1 << w->guide_bits) + 1) * sizeof(RootGuide);
+    const WrappedDiff src[2] = {WrappedDiff{static_cast<const u64*>(qc64[0])},
+                                WrappedDiff{static_cast<const u64*>(qc64[1])}};
+    w->wide = true;
+    TM_TRY(finish_tables<u128>(w, st, ovf, src));
+    for (int x = 0; x < 6; ++x) w->arena.release_one(old[x], old_sz[x]);
+    w->arena.release_one(old_guide, guide_sz);
     return TM_OK;
 }
 
@@ -657,7 +724,7 @@ int weights_build(tm_weights* w, hipStream_t st, u64* model_bytes) {
     timer.start(TM_STAGE_WEIGHTS, st);
     std::vector<std::unique_ptr<StageTimer>> level_timers;
     int* ovf = nullptr;
-    TM_HIP(dev_alloc((void**)&ovf, sizeof(int), st));
+    TM_HIP(dev_alloc((void**)&ovf, 2 * sizeof(int), st));
     // the level kernels' access-model bytes, over every attempt
     unsigned long long* nbytes = nullptr;
     u64 hbytes = 0;
@@ -667,28 +734,46 @@ int weights_build(tm_weights* w, hipStream_t st, u64* model_bytes) {
     }
     int h = 0;
     int rc = TM_OK;
+    // ovf + 1: the 64-bit build's center and interval totals (see build_typed)
+    int* ovf_c = ovf + 1;
     for (int wide = 0; wide < 2; ++wide) {
         clear_tables(w);
-        TM_TRY(fill_u32(ovf, 1, 0u, st));
+        TM_TRY(fill_u32(ovf, 2, 0u, st));
         w->wide = wide != 0;
         // on large graphs a level costs far more than a host round trip, and
         // a server's builder thread waits alone: there the 64-bit build
         // checks after every level and stops at the first overflow; other
         // builds of small graphs check once, at the end
         const bool per_level = w->lean || g->m >= ((int64_t)1 << 23);
-        rc = wide ? build_typed<u128>(w, st, ovf, false, nbytes, &level_timers)
-                  : build_typed<u64>(w, st, ovf, per_level, nbytes, &level_timers);
+        rc = wide ? build_typed<u128>(w, st, ovf, ovf, false, nbytes, &level_timers)
+                  : build_typed<u64>(w, st, ovf, ovf_c, per_level, nbytes, &level_timers);
         if (rc != TM_OK) break;
+        int hc = 0;
+        if (!wide) {
+            // only totals along eid order outgrew 64 bits (no product, no
+            // other list's total): widen the tables instead of rebuilding
+            TM_HIP(read_back({{&h, ovf, sizeof(int)}, {&hc, ovf_c, sizeof(int)}}, st));
+            if (h == 0 && hc != 0 && !(hc & 1) && w->cumW) {
+                rc = widen_tables(w, st, ovf);
+                if (rc != TM_OK) break;
+            }
+        }
         u64 hW[2] = {0, 0};
         timer.stop();
         // a 64-bit build that stopped at an overflowing level has no W yet
-        const size_t wsz = w->cumW ? (wide ? 16 : 8) : 0;
+        const bool w128 = w->wide;
+        const size_t wsz = w->cumW ? (w128 ? 16 : 8) : 0;
         TM_HIP(read_back({{&h, ovf, sizeof(int)},
-                          {hW, static_cast<const unsigned char*>(w->cumW) + w->q * (wide ? 16 : 8), wsz},
+                          {hW, static_cast<const unsigned char*>(w->cumW) + w->q * (w128 ? 16 : 8), wsz},
                           {&hbytes, nbytes, nbytes ? sizeof(u64) : 0}},
                          st));
         w->W = ((u128)hW[1] << 64) | hW[0];
-        if (h == 0) break;
+        if (w128 && !wide) {
+            // widened: the 128-bit totals are exact unless they wrapped 2^128
+            if (h != 0) rc = tm_fail(TM_EOVERFLOW, "weights: a weight or W reaches 2^128");
+            break;
+        }
+        if (h == 0 && hc == 0) break;
         if (wide) rc = tm_fail(TM_EOVERFLOW, "weights: a weight or W reaches 2^128");
     }
     TM_HIP(dev_free(ovf, st));
@@ -776,7 +861,7 @@ int weights_enqueue(tm_weights* w, hipStream_t st, int* ovf,
     if (g->m == 0) return TM_OK;
     if (w->q >= ((int64_t)1 << 31)) return tm_fail(TM_ERANGE, "weights: too many intervals");
     clear_tables(w);
-    const int rc = build_typed<u64>(w, st, ovf, false, nullptr, level_timers);
+    const int rc = build_typed<u64>(w, st, ovf, ovf, false, nullptr, level_timers);
     if (rc != TM_OK) clear_tables(w);
     return rc;
 }

@@ -212,11 +212,14 @@ def test_tiny_workload_full_run_is_bit_identical(T):
     assert abs(rg.estimate - C) <= 0.05 * C, (rg.estimate, C)
 
 
-def test_wide_weights_beyond_64_bits(T):
-    """An 8-vertex out-star on a hub with 1,500 out-edges inside one window:
-    every center weight is about 1500^6 > 2^64, so the 128-bit path runs."""
+@pytest.mark.parametrize("hub_n", [1500, 3000])
+def test_wide_weights_beyond_64_bits(T, hub_n):
+    """An 8-vertex out-star on a hub with hub_n out-edges inside one window.
+    1,500: each center weight (up to about 1500^6) fits 64 bits but their
+    sum W does not, so the 64-bit tables are widened to 128 bits without
+    recomputing a level; 3,000: the weights themselves reach 2^64 and the
+    whole set is rebuilt in 128 bits."""
     rng = np.random.default_rng(3)
-    hub_n = 1500
     src = np.zeros(hub_n, np.int32)
     dst = np.arange(1, hub_n + 1, dtype=np.int32)
     t = rng.integers(0, 50, hub_n).astype(np.int64)
@@ -224,9 +227,17 @@ def test_wide_weights_beyond_64_bits(T):
     og, tg = pair(T, g)
     edges = tuple((0, j) for j in range(1, 8))
     omo, tmo = motifs_for(T, edges, 100)
-    say("wide")
+    say("wide", hub_n)
     P, Wt = check_prep(T, og, tg, edges, 100, O.default_tree(omo), seeds=(1,), k=4000)
     assert P.W >= 2**64 and Wt.info()["wide"]
+    # which path ran: one level launch (widened) or two (rebuilt)
+    T.profile_read(reset=True)
+    T.profile_enable(True)
+    again = T.Weights(tg, tmo)
+    T.profile_enable(False)
+    launches = T.profile_read(reset=True)["launches"][T.STAGES.index("levels")]
+    assert launches == (1 if hub_n == 1500 else 2), launches
+    assert again.W == P.W
 
 
 def test_zero_weight_and_empty_graph(T):
