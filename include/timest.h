@@ -15,8 +15,9 @@
  *     output handles untouched and the library usable.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
  *     on it; calls that return values to host memory synchronise it first.
- *   - Device memory is allocated by the library (hipMalloc) and owned by the
- *     handle that holds it until its destroy call.
+ *   - Device memory is allocated through the graph's or server's allocator
+ *     (tm_allocator; NULL: the library's own hipMalloc-backed block cache)
+ *     and owned by the handle that holds it until its destroy call.
  *   - Sizes: at most 2^31 - 1 edges and 2^31 - 1 vertices; the time span
  *     max(t) - min(t) and delta must stay below 2^62, and the number of bits
  *     of (n - 1) plus the number of bits of the time span must not exceed 64
@@ -25,6 +26,7 @@
 #ifndef TIMEST_H
 #define TIMEST_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -68,6 +70,24 @@ enum tm_ptr_kind { TM_PTR_HOST = 0, TM_PTR_DEVICE = 1 };
 #define TM_F_WIDE 4u          /* weights needed 128 bits (else 64) */
 
 typedef struct { uint64_t lo, hi; } tm_u128;
+
+/* A caller's device memory provider (the Python binding can pass PyTorch's
+ * caching allocator).  alloc returns at least `bytes` of device memory on the
+ * current device, first used on `stream` (a hipStream_t), or NULL when it
+ * cannot; free takes back a block alloc returned, with its size and the
+ * stream its last use was enqueued on.  Both may be called from any thread
+ * of the library (a server's workers included) and get ctx back.  A graph
+ * created with an allocator takes its tables, the tables of every weight set
+ * built on it and the temporaries of every call on them (a batch: its first
+ * job's graph's) from it; a server created with one takes its weight sets
+ * and pass buffers from it.  The functions and ctx must stay valid until
+ * every handle using them is destroyed.  tm_sample_noalloc allocates
+ * nothing, through any allocator. */
+typedef struct {
+    void* (*alloc)(void* ctx, size_t bytes, void* stream);
+    void (*free)(void* ctx, void* ptr, size_t bytes, void* stream);
+    void* ctx;
+} tm_allocator;
 
 typedef struct tm_graph tm_graph;
 typedef struct tm_weights tm_weights;
@@ -157,11 +177,13 @@ const char* tm_last_error(void);
  * multi-edge list El_{u,v} (Def. "multi-edge list") as a contiguous run.
  * src, dst, t: m entries each, host or device memory per ptr_kind; the caller
  * keeps ownership and may free them once the call returns.  n: vertex count,
- * ids in [0, n).  m = 0 gives an empty graph.  Errors: TM_EINVAL (NULL,
- * m or n out of range, id out of range), TM_ESELFLOOP, TM_ERANGE, TM_EDUP --
- * the first failing check in that order -- TM_ENOMEM, TM_EDEVICE. */
+ * ids in [0, n).  m = 0 gives an empty graph.  alloc: NULL (the library's
+ * block cache) or the allocator of the graph and of everything built on it
+ * (copied; see tm_allocator).  Errors: TM_EINVAL (NULL, m or n out of range,
+ * id out of range), TM_ESELFLOOP, TM_ERANGE, TM_EDUP -- the first failing
+ * check in that order -- TM_ENOMEM, TM_EDEVICE. */
 int tm_graph_create(const int32_t* src, const int32_t* dst, const int64_t* t, int64_t m,
-                    int32_t n, int ptr_kind, void* stream, tm_graph** out);
+                    int32_t n, int ptr_kind, const tm_allocator* alloc, void* stream, tm_graph** out);
 
 /* Frees the graph's device memory.  Weights built on it must be destroyed
  * first.  NULL is ignored. */
@@ -437,8 +459,11 @@ typedef struct {
 } tm_server_stats;
 
 /* Start a server on the current device.  opts may be NULL (defaults).
+ * alloc: NULL (the library's block cache) or the allocator of the server's
+ * weight sets and pass buffers (copied; see tm_allocator).
  * Errors: TM_EINVAL (budget below the pass reserve), TM_EDEVICE. */
-int tm_server_create(uint64_t budget_bytes, const tm_server_opts* opts, tm_server** out);
+int tm_server_create(uint64_t budget_bytes, const tm_server_opts* opts, const tm_allocator* alloc,
+                     tm_server** out);
 /* Register a built graph; it stays owned by the caller and must outlive the
  * server.  Its memory is not counted in the budget. */
 int tm_server_add_graph(tm_server* srv, tm_graph* g, int32_t* gid);

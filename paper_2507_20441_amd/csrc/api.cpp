@@ -388,7 +388,8 @@ extern "C" const char* tm_last_error(void) { return g_last_error; }
 static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 extern "C" int tm_graph_create(const int32_t* src, const int32_t* dst, const int64_t* t, int64_t m,
-                               int32_t n, int ptr_kind, void* stream, tm_graph** out) {
+                               int32_t n, int ptr_kind, const tm_allocator* alloc, void* stream,
+                               tm_graph** out) {
     if (!out) return tm_fail(TM_EINVAL, "graph: NULL output");
     if (m < 0 || m >= ((int64_t)1 << 31) || n < 0 || n == INT32_MAX)
         return tm_fail(TM_EINVAL, "graph: m = %lld or n = %d out of range", (long long)m, n);
@@ -400,6 +401,15 @@ extern "C" int tm_graph_create(const int32_t* src, const int32_t* dst, const int
     if (!g) return tm_fail(TM_ENOMEM, "graph: host allocation");
     g->m = m;
     g->n = n;
+    if (alloc) {
+        if (!alloc->alloc || !alloc->free) {
+            delete g;
+            return tm_fail(TM_EINVAL, "graph: allocator without alloc or free");
+        }
+        g->alloc = *alloc;
+        g->has_alloc = true;
+    }
+    AllocScope scope_(alloc_of(g));
     (void)hipGetDevice(&g->device);
     g->arena.stream = st;
     const int32_t *ds = src, *dd = dst;
@@ -451,6 +461,7 @@ extern "C" int tm_graph_info(const tm_graph* g, int64_t* m, int32_t* n, int64_t*
 }
 
 extern "C" int tm_graph_export(const tm_graph* g, int which, void* host_out, void* stream) {
+    AllocScope scope_(alloc_of(g));
     if (!g || !host_out) return tm_fail(TM_EINVAL, "graph_export: NULL");
     const DevGraph& D = g->d;
     const void* p = nullptr;
@@ -556,6 +567,7 @@ extern "C" int tm_tree_candidates(const tm_motif* mo, tm_tree* out, int64_t* loo
 
 extern "C" int tm_choose_tree(tm_graph* g, const tm_motif* mo, int n_c, void* stream, tm_tree* best,
                               tm_u128* W_out, int* n_eval) {
+    AllocScope scope_(alloc_of(g));
     if (!g || !best || n_c < 1) return tm_fail(TM_EINVAL, "choose_tree: bad arguments");
     TM_TRY(motif_check(mo));
     std::vector<TreeCand> c;
@@ -620,11 +632,13 @@ int weights_create(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32_t 
 
 extern "C" int tm_weights_create_ex(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32_t constraints,
                                     void* stream, tm_weights** out) {
+    AllocScope scope_(alloc_of(g));
     return weights_create(g, mo, tr, constraints, stream, out, nullptr);
 }
 
 extern "C" int tm_weights_model_bytes(tm_graph* g, const tm_motif* mo, const tm_tree* tr, void* stream,
                                       uint64_t* bytes) {
+    AllocScope scope_(alloc_of(g));
     if (!bytes) return tm_fail(TM_EINVAL, "weights_model_bytes: NULL argument");
     // the counting pass is not a timed stage
     const bool was = prof_suspended();
@@ -677,6 +691,7 @@ extern "C" int tm_weights_info(const tm_weights* w, tm_u128* W, int64_t* q, int3
 
 extern "C" int tm_weights_export(const tm_weights* w, int32_t s, int32_t slot, tm_u128* host_out,
                                  void* stream) {
+    AllocScope scope_(w ? alloc_of(w->g) : nullptr);
     if (!w || !host_out) return tm_fail(TM_EINVAL, "weights_export: NULL");
     const HostPlan& P = w->plan;
     if (s < 0 || s >= P.mo.l || P.slot_of_edge[s] < 0 || slot < 0 || slot > 1)
@@ -735,6 +750,7 @@ extern "C" int tm_weights_export(const tm_weights* w, int32_t s, int32_t slot, t
 }
 
 extern "C" int tm_weights_intervals(const tm_weights* w, tm_u128* host_out, void* stream) {
+    AllocScope scope_(w ? alloc_of(w->g) : nullptr);
     if (!w || !host_out) return tm_fail(TM_EINVAL, "weights_intervals: NULL");
     if (w->q == 0) return TM_OK;
     hipStream_t st = as_stream(stream);
@@ -828,6 +844,7 @@ extern "C" int tm_result_finish(tm_result* r) {
 
 extern "C" int tm_sample(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count,
                          uint64_t k_total, void* stream, tm_result* out, tm_sample_rec* recs) {
+    AllocScope scope_(w ? alloc_of(w->g) : nullptr);
     if (!w || !out) return tm_fail(TM_EINVAL, "sample: NULL argument");
     if (count > 0 && j0 + count < j0) return tm_fail(TM_EINVAL, "sample: id range wraps");
     TM_TRY(sample_run(w, seed, j0, count, k_total, as_stream(stream), out, recs, nullptr));
@@ -848,6 +865,7 @@ extern "C" int tm_sample_noalloc(tm_weights* w, uint64_t seed, uint64_t j0, uint
 
 extern "C" int tm_sample_model_bytes(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count,
                                      void* stream, uint64_t* bytes) {
+    AllocScope scope_(w ? alloc_of(w->g) : nullptr);
     if (!w || !bytes) return tm_fail(TM_EINVAL, "sample_model_bytes: NULL argument");
     tm_result r;
     return sample_run(w, seed, j0, count, count, as_stream(stream), &r, nullptr,
@@ -908,6 +926,7 @@ int estimate_enqueued(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32
 
 extern "C" int tm_estimate_ex(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uint32_t constraints,
                               uint64_t k, uint64_t seed, void* stream, tm_result* out, tm_sample_rec* recs) {
+    AllocScope scope_(alloc_of(g));
     if (!out) return tm_fail(TM_EINVAL, "estimate: NULL output");
     // records need W on the host first (a W = 0 run writes "not drawn"
     // records): they take the synchronous path
@@ -991,6 +1010,7 @@ int sample_batch_results(tm_weights* const* w, const uint64_t* k, const uint64_t
 
 extern "C" int tm_sample_batch(tm_weights* const* w, const uint64_t* k, const uint64_t* seed, int n_jobs,
                                void* stream, tm_result* out) {
+    AllocScope scope_(w && n_jobs > 0 && w[0] ? alloc_of(w[0]->g) : nullptr);
     if (n_jobs < 0 || (n_jobs > 0 && (!w || !k || !seed || !out)))
         return tm_fail(TM_EINVAL, "sample_batch: bad arguments");
     for (int i = 0; i < n_jobs; ++i)
@@ -1003,6 +1023,7 @@ extern "C" int tm_sample_batch(tm_weights* const* w, const uint64_t* k, const ui
 extern "C" int tm_estimate_batch(tm_graph* const* g, const tm_motif* mo, const tm_tree* const* tr,
                                  const uint64_t* k, const uint64_t* seed, int n_jobs, void* stream,
                                  tm_result* out) {
+    AllocScope scope_(g && n_jobs > 0 ? alloc_of(g[0]) : nullptr);
     if (n_jobs < 0 || (n_jobs > 0 && (!g || !mo || !k || !seed || !out)))
         return tm_fail(TM_EINVAL, "estimate_batch: bad arguments");
     if (n_jobs == 0) return TM_OK;
@@ -1141,6 +1162,7 @@ static void plan_release(tm_batch_plan* p) {
 extern "C" int tm_batch_plan_create(tm_graph* const* g, const tm_motif* mo, const tm_tree* const* tr,
                                     const uint64_t* k, const uint64_t* seed, int n_jobs, void* stream,
                                     tm_batch_plan** out) {
+    AllocScope scope_(g && n_jobs > 0 ? alloc_of(g[0]) : nullptr);
     (void)stream;
     if (!out || n_jobs < 1 || !g || !mo || !k || !seed) return tm_fail(TM_EINVAL, "batch_plan: bad arguments");
     std::unique_ptr<tm_batch_plan> P(new (std::nothrow) tm_batch_plan());
@@ -1331,6 +1353,7 @@ static int family_plan(const tm_weights* w, const tm_motif* mo, HostPlan* out) {
 
 extern "C" int tm_sample_family(tm_weights* w, const tm_motif* motifs, int n_motifs, uint64_t seed, uint64_t k,
                                 void* stream, tm_result* out) {
+    AllocScope scope_(w ? alloc_of(w->g) : nullptr);
     if (!w || !motifs || !out || n_motifs < 1 || n_motifs > 64)
         return tm_fail(TM_EINVAL, "sample_family: bad arguments");
     std::vector<HostPlan> plans(n_motifs);
@@ -1360,6 +1383,7 @@ extern "C" int tm_sample_family(tm_weights* w, const tm_motif* motifs, int n_mot
 
 extern "C" int tm_list_instances(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t count, void* stream,
                                  int32_t* eids, tm_sample_rec* recs) {
+    AllocScope scope_(w ? alloc_of(w->g) : nullptr);
     if (!w || (count > 0 && !eids)) return tm_fail(TM_EINVAL, "list_instances: NULL argument");
     if (count > 0 && j0 + count < j0) return tm_fail(TM_EINVAL, "list_instances: id range wraps");
     if (w->plan.po) return tm_fail(TM_EINVAL, "list_instances: the motif has a partial order");

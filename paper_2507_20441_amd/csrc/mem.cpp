@@ -29,6 +29,15 @@ std::mutex g_mu;
 std::vector<Block> g_free[kMaxDevices];
 std::unordered_map<void*, size_t> g_used;
 
+// Blocks from a caller's allocator (tm_allocator): returned to it, never cached.
+struct UserBlock {
+    tm_allocator a;
+    size_t bytes;
+};
+std::unordered_map<void*, UserBlock> g_user;
+
+thread_local const tm_allocator* t_alloc = nullptr;
+
 std::mutex g_stage_mu;
 std::vector<void*> g_stage_free;
 
@@ -52,8 +61,23 @@ int device_index() {
 
 }  // namespace
 
+AllocScope::AllocScope(const tm_allocator* a) : prev_(t_alloc) {
+    t_alloc = (a && a->alloc && a->free) ? a : nullptr;
+}
+AllocScope::~AllocScope() { t_alloc = prev_; }
+
 hipError_t dev_alloc(void** p, size_t bytes, hipStream_t st) {
     *p = nullptr;
+    if (t_alloc) {
+        const tm_allocator a = *t_alloc;
+        const size_t want = ((bytes ? bytes : 1) + 255) & ~(size_t)255;
+        void* q = a.alloc(a.ctx, want, st);
+        if (!q) return hipErrorOutOfMemory;
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_user[q] = UserBlock{a, want};
+        *p = q;
+        return hipSuccess;
+    }
     const size_t cls = size_class(bytes ? bytes : 1);
     const int dev = device_index();
     {
@@ -119,7 +143,15 @@ hipError_t dev_free(void* p, hipStream_t st) {
         return hipSuccess;
     }
     const int dev = device_index();
-    std::lock_guard<std::mutex> lk(g_mu);
+    std::unique_lock<std::mutex> lk(g_mu);
+    auto ut = g_user.find(p);
+    if (ut != g_user.end()) {
+        const UserBlock b = ut->second;
+        g_user.erase(ut);
+        lk.unlock();
+        b.a.free(b.a.ctx, p, b.bytes, st);
+        return hipSuccess;
+    }
     auto it = g_used.find(p);
     if (it == g_used.end()) return hipErrorInvalidValue;
     g_free[dev].push_back(Block{p, it->second, st, false});

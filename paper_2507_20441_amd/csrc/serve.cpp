@@ -93,6 +93,8 @@ struct tm_server {
     int max_jobs = 0;
     bool fifo = false;
     int device = 0;
+    tm_allocator alloc{};        // the caller's allocator (has_alloc) of weight sets and passes
+    bool has_alloc = false;
     hipStream_t st = nullptr;   // sampling passes
     hipStream_t bst = nullptr;  // weight builds
 
@@ -193,6 +195,7 @@ void tm_server::finish(QueryPtr q, int status, const char* msg) {
 }
 
 void tm_server::run_builder() {
+    AllocScope scope_(has_alloc ? &alloc : nullptr);
     (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
     while (!stop) {
@@ -383,6 +386,7 @@ void tm_server::pass() {
 }
 
 void tm_server::run_sampler() {
+    AllocScope scope_(has_alloc ? &alloc : nullptr);
     (void)hipSetDevice(device);
     while (true) {
         {
@@ -412,10 +416,16 @@ void tm_server::run_sampler() {
     }
 }
 
-extern "C" int tm_server_create(uint64_t budget_bytes, const tm_server_opts* opts, tm_server** out) {
+extern "C" int tm_server_create(uint64_t budget_bytes, const tm_server_opts* opts, const tm_allocator* alloc,
+                                tm_server** out) {
     if (!out) return tm_fail(TM_EINVAL, "server: NULL output");
+    if (alloc && (!alloc->alloc || !alloc->free)) return tm_fail(TM_EINVAL, "server: allocator without alloc or free");
     std::unique_ptr<tm_server> s(new (std::nothrow) tm_server());
     if (!s) return tm_fail(TM_ENOMEM, "server: host allocation");
+    if (alloc) {
+        s->alloc = *alloc;
+        s->has_alloc = true;
+    }
     s->pass_samples = opts && opts->pass_samples ? opts->pass_samples : ((u64)1 << 24);
     s->job_chunk = opts && opts->job_chunk ? opts->job_chunk : ((u64)1 << 22);
     s->max_jobs = opts && opts->max_jobs > 0 ? opts->max_jobs : 256;

@@ -49,6 +49,19 @@ int arena_alloc(DevArena& A, T** p, size_t count) {
 }
 
 // Device block cache (mem.cpp): stream-aware reuse of released blocks.
+// While an AllocScope with a caller's allocator is live on a thread,
+// dev_alloc takes its blocks from that allocator instead (dev_free returns
+// each block to where it came from, on any thread).
+class AllocScope {
+public:
+    explicit AllocScope(const tm_allocator* a);
+    ~AllocScope();
+    AllocScope(const AllocScope&) = delete;
+    AllocScope& operator=(const AllocScope&) = delete;
+
+private:
+    const tm_allocator* prev_;
+};
 hipError_t dev_alloc(void** p, size_t bytes, hipStream_t st);
 hipError_t dev_free(void* p, hipStream_t st);
 // Synchronise the device and return every cached block to HIP.
@@ -98,7 +111,12 @@ struct tm_graph {
     int64_t T = 0;
     int device = 0;
     DevArena arena;
+    // the caller's allocator of everything built on this graph (has_alloc)
+    tm_allocator alloc{};
+    bool has_alloc = false;
 };
+
+inline const tm_allocator* alloc_of(const tm_graph* g) { return g && g->has_alloc ? &g->alloc : nullptr; }
 
 // ---------------------------------------------------------------------------
 // Motif plan: the spanning tree rooted at its center edge (Sec. 4.1), listed

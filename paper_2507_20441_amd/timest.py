@@ -82,6 +82,54 @@ REC_DTYPE = np.dtype([("interval", "<u4"), ("status", "<u4"), ("n_phi", "<u4"), 
 U128_DTYPE = np.dtype([("lo", "<u8"), ("hi", "<u8")])
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    """tm_allocator: alloc(ctx, bytes, stream) -> device pointer or NULL;
+    free(ctx, ptr, bytes, stream)."""
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+class TorchAllocator:
+    """The library's device memory from PyTorch's caching allocator: each
+    block is a torch.cuda.caching_allocator_alloc on the stream the library
+    names, returned with caching_allocator_delete.  Counts what it served
+    (live_bytes, allocs, frees).  Pass it to Graph(..., allocator=) or
+    Server(..., allocator=); keep it alive as long as they live (they hold a
+    reference)."""
+
+    def __init__(self):
+        import torch
+        self._torch = torch
+        self.live_bytes = 0
+        self.peak_bytes = 0
+        self.allocs = 0
+        self.frees = 0
+        self._sizes = {}
+
+        def _alloc(ctx, nbytes, stream):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+            except RuntimeError:
+                return None
+            self._sizes[p] = int(nbytes)
+            self.allocs += 1
+            self.live_bytes += int(nbytes)
+            self.peak_bytes = max(self.peak_bytes, self.live_bytes)
+            return p
+
+        def _free(ctx, ptr, nbytes, stream):
+            torch.cuda.caching_allocator_delete(int(ptr))
+            self.frees += 1
+            self.live_bytes -= self._sizes.pop(int(ptr), int(nbytes))
+
+        self._fa = ALLOC_FN(_alloc)
+        self._ff = FREE_FN(_free)
+        self.struct = Allocator(self._fa, self._ff, None)
+
+
 class BatchOpts(C.Structure):
     _fields_ = [("tile", C.c_int32), ("blocks", C.c_int32), ("root_lds", C.c_int32), ("pad", C.c_int32),
                 ("group_limit", C.c_uint64)]
@@ -107,7 +155,7 @@ def lib():
         L.tm_strerror.restype = C.c_char_p
         L.tm_strerror.argtypes = [C.c_int]
         L.tm_last_error.restype = C.c_char_p
-        L.tm_graph_create.argtypes = [vp, vp, vp, i64, i32, C.c_int, vp, C.POINTER(vp)]
+        L.tm_graph_create.argtypes = [vp, vp, vp, i64, i32, C.c_int, C.POINTER(Allocator), vp, C.POINTER(vp)]
         L.tm_graph_destroy.argtypes = [vp]
         L.tm_graph_destroy.restype = None
         L.tm_graph_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i64),
@@ -156,7 +204,7 @@ def lib():
         L.tm_sample_model_bytes.argtypes = [vp, u64, u64, u64, vp, C.POINTER(u64)]
         L.tm_weights_model_bytes.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), vp, C.POINTER(u64)]
         L.tm_weights_footprint.argtypes = [vp, C.POINTER(Motif), C.POINTER(Tree), i32, C.POINTER(u64)]
-        L.tm_server_create.argtypes = [u64, C.POINTER(ServerOpts), C.POINTER(vp)]
+        L.tm_server_create.argtypes = [u64, C.POINTER(ServerOpts), C.POINTER(Allocator), C.POINTER(vp)]
         L.tm_server_add_graph.argtypes = [vp, vp, C.POINTER(i32)]
         L.tm_server_submit.argtypes = [vp, i32, C.POINTER(Motif), C.POINTER(Tree), u64, u64,
                                        C.POINTER(u64)]
@@ -241,11 +289,15 @@ class Graph:
     """A temporal graph resident in device memory.
 
     src, dst, t: numpy arrays (copied from host memory) or torch tensors on
-    the GPU (read in place on the current stream)."""
+    the GPU (read in place on the current stream).  allocator: None (the
+    library's block cache) or a TorchAllocator for the graph and everything
+    built on it."""
 
-    def __init__(self, src, dst, t, n):
+    def __init__(self, src, dst, t, n, allocator=None):
         import torch
         self.n = int(n)
+        self.allocator = allocator
+        ap = C.byref(allocator.struct) if allocator is not None else None
         h = C.c_void_p()
         if isinstance(src, torch.Tensor) and src.is_cuda:
             s = src.to(torch.int32).contiguous()
@@ -253,7 +305,7 @@ class Graph:
             tt = t.to(torch.int64).contiguous()
             self.m = int(s.numel())
             rc = lib().tm_graph_create(C.c_void_p(s.data_ptr()), C.c_void_p(d.data_ptr()),
-                                       C.c_void_p(tt.data_ptr()), self.m, self.n, TM_PTR_DEVICE,
+                                       C.c_void_p(tt.data_ptr()), self.m, self.n, TM_PTR_DEVICE, ap,
                                        _stream(), C.byref(h))
         else:
             s = np.ascontiguousarray(np.asarray(src), dtype=np.int32)
@@ -261,7 +313,7 @@ class Graph:
             tt = np.ascontiguousarray(np.asarray(t), dtype=np.int64)
             self.m = int(s.shape[0])
             rc = lib().tm_graph_create(s.ctypes.data_as(C.c_void_p), d.ctypes.data_as(C.c_void_p),
-                                       tt.ctypes.data_as(C.c_void_p), self.m, self.n, TM_PTR_HOST,
+                                       tt.ctypes.data_as(C.c_void_p), self.m, self.n, TM_PTR_HOST, ap,
                                        _stream(), C.byref(h))
         _check(rc, "graph_create")
         _own(self, lib().tm_graph_destroy, h)
@@ -432,10 +484,12 @@ class Server:
     """tm_server_*: resident graphs, a budgeted weight-set cache and
     continuous batching, driven by the library's worker thread."""
 
-    def __init__(self, budget_bytes, pass_samples=0, job_chunk=0, max_jobs=0, fifo=False):
+    def __init__(self, budget_bytes, pass_samples=0, job_chunk=0, max_jobs=0, fifo=False, allocator=None):
         o = ServerOpts(int(pass_samples), int(job_chunk), int(max_jobs), 1 if fifo else 0)
         h = C.c_void_p()
-        _check(lib().tm_server_create(int(budget_bytes), C.byref(o), C.byref(h)), "server_create")
+        self.allocator = allocator
+        ap = C.byref(allocator.struct) if allocator is not None else None
+        _check(lib().tm_server_create(int(budget_bytes), C.byref(o), ap, C.byref(h)), "server_create")
         _own(self, lib().tm_server_destroy, h)
         self._graphs = []
 

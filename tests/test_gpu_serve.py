@@ -181,3 +181,49 @@ def test_shutdown_with_pending(T, world):
     for i in range(8):
         srv.submit(gid, T.make_motif(W.MOTIFS["4star"], 40000), 200000, i + 1)
     srv.close()
+
+
+def test_torch_allocator_serves_every_device_block(T):
+    """A graph and a server given PyTorch's caching allocator (tm_allocator):
+    every device block of the graph, its weight sets, the calls' temporaries
+    and the server's sets and passes comes from it and goes back to it, and
+    every result is bit-identical to the library's own allocator."""
+    import torch
+    g = W.small_graph(20011, 71, n=400, span=20 * 20011)
+    plain = T.Graph(g.src, g.dst, g.t, g.n)
+    A = T.TorchAllocator()
+    base = torch.cuda.memory_allocated()
+    hooked = T.Graph(g.src, g.dst, g.t, g.n, allocator=A)
+    assert A.allocs > 0 and A.live_bytes > 0
+    assert torch.cuda.memory_allocated() - base >= A.live_bytes   # torch accounts for them
+    graph_bytes = A.live_bytes
+    for name in ("4cycle", "scatter_gather"):
+        mo = T.make_motif(W.MOTIFS[name], 4000)
+        for k in (5000, 70000):
+            a = T.estimate(plain, mo, k, 3)
+            b = T.estimate(hooked, mo, k, 3)
+            assert same(a, b), (name, k)
+        wa, wb = T.Weights(plain, mo), T.Weights(hooked, mo)
+        assert A.live_bytes > graph_bytes
+        assert same(wa.sample(5, 80000)[0], wb.sample(5, 80000)[0])
+        assert (wa.weights(1, 0) == wb.weights(1, 0)).all()
+        wa.close()
+        wb.close()
+    assert A.live_bytes == graph_bytes          # the weight sets gave theirs back
+    bat = T.estimate_batch([hooked, hooked], [T.make_motif(W.MOTIFS["3cycle"], 2000)] * 2, [30000, 70000], [1, 2])
+    ref = T.estimate_batch([plain, plain], [T.make_motif(W.MOTIFS["3cycle"], 2000)] * 2, [30000, 70000], [1, 2])
+    assert all(same(x, y) for x, y in zip(bat, ref))
+    # a server with its own torch allocator
+    S = T.TorchAllocator()
+    srv = T.Server(8 << 30, allocator=S)
+    gid = srv.add_graph(plain)
+    mo = T.make_motif(W.MOTIFS["4cycle"], 4000)
+    tickets = [srv.submit(gid, mo, k, s) for k, s in ((20000, 1), (300000, 2))]
+    for t, (k, s) in zip(tickets, ((20000, 1), (300000, 2))):
+        r, _ = srv.wait(t)
+        assert same(r, T.estimate(plain, mo, k, s))
+    assert S.allocs > 0
+    srv.close()
+    assert S.live_bytes == 0
+    hooked.close()
+    assert A.live_bytes == 0 and A.frees == A.allocs
