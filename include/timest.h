@@ -416,13 +416,17 @@ int tm_weights_footprint(const tm_graph* g, const tm_motif* mo, const tm_tree* t
  * A server answers estimation queries on resident graphs from a worker
  * thread with a stream of its own (default priority).
  *
- * Weight sets are cached per (graph, motif, delta, tree) and shared by the
- * queries that need them.  The budget bounds the server's device memory: the
- * resident weight sets plus a reserve for one sampling pass (24 bytes per
- * sample of pass_samples).  Admission: a query whose weight set is resident
- * is admitted at once; otherwise, in arrival order, when the set's 64-bit
- * footprint fits the budget after evicting idle sets, least recently used
- * first.  A set that turns out to need 128 bits is kept if it fits alone.
+ * Weight sets are cached per (graph, motif, delta, time order, tree) and
+ * shared by the queries that need them.  The budget bounds the server's
+ * device memory: the resident weight sets, the one set being built with its
+ * temporaries, and a reserve for one sampling pass (24 bytes per sample of
+ * pass_samples).  Admission: a query whose weight set is resident is
+ * admitted at once; otherwise, smallest set first, when the set's footprint
+ * and its build's temporaries fit the budget after evicting idle sets, least
+ * recently used first.  A set first reserves its 64-bit size; if it turns
+ * out to need 128 bits, the 64-bit attempt stops, its memory goes back to
+ * HIP and the query waits for the 128-bit reservation (every later build of
+ * that set reserves 128 bits at once; TM_EADMIT if that can never fit).
  *
  * Continuous batching: each pass draws up to job_chunk samples of every
  * admitted query (fewest remaining samples first, at most max_jobs queries

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <set>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -49,6 +50,8 @@ struct Query {
     u64 extra_bytes = 0;  // build temporaries on top of it
     Clock::time_point t_submit, t_admit;
     bool waited = false;  // found the budget full at least once
+    bool wide = false;    // its set needs 128 bits (reserve and build that)
+    int64_t nq = 0;       // intervals of its set
     CacheEntry* ce = nullptr;
     u64 next = 0;  // next sample id to draw
     JobSums sums;
@@ -108,6 +111,8 @@ struct tm_server {
     std::deque<QueryPtr> builds;    // waiting for their weight set
     std::deque<QueryPtr> ready;     // admitted by the builder, not yet sampling
     std::map<std::string, CacheEntry> cache;
+    // sets found to need 128 bits: their later builds reserve (and build) 128
+    std::set<std::string> wide_keys;
     u64 resident = 0;
     u64 releases = 0;
     std::unordered_map<u64, Done> done;
@@ -243,6 +248,10 @@ void tm_server::run_builder() {
             w->plan = qp->plan;
             // resident sets matter more here than the sampler's speed-up
             w->lean = true;
+            // the budget is a hard bound: a build stays within what it
+            // reserved, so a 64-bit build that needs 128 bits stops and the
+            // query comes back with the 128-bit reservation
+            w->width_mode = qp->wide ? 2 : 1;
             rc = weights_build(w, bst);
             if (rc == TM_ENOMEM) {
                 // the device holds more than the budget counts (cached
@@ -255,11 +264,39 @@ void tm_server::run_builder() {
                 rc = weights_build(w, bst);
             }
         }
+        const bool needs_wide = w && w->needs_wide;
+        if (needs_wide) {
+            // give the 64-bit blocks back to HIP before the larger set is built
+            tm_weights_destroy(w);
+            w = nullptr;
+            dev_cache_trim();
+        }
         const std::string err = rc != TM_OK ? tm_last_error() : "";
         lk.lock();
         building = false;
         cv_idle.notify_all();
         resident -= qp->est_bytes + qp->extra_bytes;
+        if (needs_wide) {
+            wide_keys.insert(qp->key);
+            qp->wide = true;
+            qp->est_bytes = weights_footprint(qp->plan, qp->g->m, qp->nq, true, true);
+            qp->extra_bytes = weights_build_extra(qp->g->m, true);
+            if (qp->est_bytes + qp->extra_bytes > budget - reserve) {
+                lk.unlock();
+                finish(std::move(qp), TM_EADMIT, "server: the 128-bit weight set exceeds the budget");
+                lk.lock();
+            } else {
+                // its other queries reserve the 128-bit size too
+                for (auto& b : builds)
+                    if (b->key == qp->key && !b->wide) {
+                        b->wide = true;
+                        b->est_bytes = qp->est_bytes;
+                        b->extra_bytes = qp->extra_bytes;
+                    }
+                builds.push_front(std::move(qp));
+            }
+            continue;
+        }
         if (rc == TM_ENOMEM) {
             tm_weights_destroy(w);
             bool pinned = false;
@@ -275,9 +312,6 @@ void tm_server::run_builder() {
                 continue;
             }
         }
-        if (rc == TM_OK && w->arena.bytes > budget - reserve)
-            rc = tm_fail(TM_EADMIT, "server: the 128-bit weight set takes %llu bytes",
-                         (unsigned long long)w->arena.bytes);
         if (rc != TM_OK) {
             if (rc != TM_ENOMEM) tm_weights_destroy(w);
             const std::string msg = err.empty() ? tm_last_error() : err;
@@ -286,8 +320,17 @@ void tm_server::run_builder() {
             lk.lock();
             continue;
         }
-        // a 128-bit set is larger than its estimate: make what room there is
-        if (resident + w->arena.bytes > budget - reserve) (void)make_room_locked(w->arena.bytes);
+        // the set takes what its reservation held (the footprint is exact)
+        if (resident + w->arena.bytes > budget - reserve && !make_room_locked(w->arena.bytes)) {
+            tm_weights_destroy(w);
+            if (!qp->waited) {
+                qp->waited = true;
+                ++stats.admission_waits;
+            }
+            builds.push_front(std::move(qp));
+            cv_build.wait(lk);
+            continue;
+        }
         CacheEntry& ce = cache[qp->key];
         ce.w = w;
         ce.bytes = w->arena.bytes;
@@ -495,8 +538,14 @@ extern "C" int tm_server_submit(tm_server* srv, int32_t gid, const tm_motif* mo,
     if (g->m > 0 && g->T / mo->delta + 1 >= ((int64_t)1 << 31))
         return tm_fail(TM_ERANGE, "server_submit: too many intervals");
     const int64_t nq = g->m > 0 ? g->T / mo->delta + 1 : 0;
-    q->est_bytes = weights_footprint(q->plan, g->m, nq, false, true);
-    q->extra_bytes = weights_build_extra(g->m, false);
+    q->nq = nq;
+    q->key = set_key(gid, q->plan);
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        q->wide = srv->wide_keys.count(q->key) != 0;
+    }
+    q->est_bytes = weights_footprint(q->plan, g->m, nq, q->wide, true);
+    q->extra_bytes = weights_build_extra(g->m, q->wide);
     if (q->est_bytes + q->extra_bytes > srv->budget - srv->reserve)
         return tm_fail(TM_EADMIT, "server_submit: weight set of %llu bytes (+%llu while built), budget %llu",
                        (unsigned long long)q->est_bytes, (unsigned long long)q->extra_bytes,
@@ -505,7 +554,6 @@ extern "C" int tm_server_submit(tm_server* srv, int32_t gid, const tm_motif* mo,
     q->g = g;
     q->k = k;
     q->seed = seed;
-    q->key = set_key(gid, q->plan);
     q->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> lk(srv->mu);

@@ -197,6 +197,11 @@ struct tm_weights {
     // a server builds its sets for memory over speed: no kept windows and a
     // guide four times coarser
     bool lean = false;
+    // which widths a build may use: 0 both (64 bits, widened or rebuilt in
+    // 128 when needed), 1 only 64 (a build needing more stops with
+    // TM_EOVERFLOW and needs_wide set), 2 only 128
+    int width_mode = 0;
+    bool needs_wide = false;
     void* qt[kMaxSlots][2] = {};
     void* qn[kMaxSlots][2] = {};
     void* qc[2] = {};

@@ -736,7 +736,8 @@ int weights_build(tm_weights* w, hipStream_t st, u64* model_bytes) {
     int rc = TM_OK;
     // ovf + 1: the 64-bit build's center and interval totals (see build_typed)
     int* ovf_c = ovf + 1;
-    for (int wide = 0; wide < 2; ++wide) {
+    w->needs_wide = false;
+    for (int wide = w->width_mode == 2 ? 1 : 0; wide < (w->width_mode == 1 ? 1 : 2); ++wide) {
         clear_tables(w);
         TM_TRY(fill_u32(ovf, 2, 0u, st));
         w->wide = wide != 0;
@@ -753,6 +754,12 @@ int weights_build(tm_weights* w, hipStream_t st, u64* model_bytes) {
             // only totals along eid order outgrew 64 bits (no product, no
             // other list's total): widen the tables instead of rebuilding
             TM_HIP(read_back({{&h, ovf, sizeof(int)}, {&hc, ovf_c, sizeof(int)}}, st));
+            if ((h != 0 || hc != 0) && w->width_mode == 1) {
+                // 64 bits only: the caller decides where the 128-bit set goes
+                w->needs_wide = true;
+                rc = tm_fail(TM_EOVERFLOW, "weights: the set needs 128 bits");
+                break;
+            }
             if (h == 0 && hc != 0 && !(hc & 1) && w->cumW) {
                 rc = widen_tables(w, st, ovf);
                 if (rc != TM_OK) break;

@@ -107,9 +107,15 @@ class TorchAllocator:
         self.peak_bytes = 0
         self.allocs = 0
         self.frees = 0
+        self.fail_next = 0   # tests: this many next requests fail (return NULL)
+        self.failed = 0
         self._sizes = {}
 
         def _alloc(ctx, nbytes, stream):
+            if self.fail_next > 0:
+                self.fail_next -= 1
+                self.failed += 1
+                return None
             try:
                 p = torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
             except RuntimeError:

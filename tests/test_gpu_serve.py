@@ -96,10 +96,68 @@ def test_budget_forces_eviction(T, world):
     for i, ((r, _), a) in enumerate(zip(out, alone)):
         assert r.status == 0 and same(r, a), (i, qs[i])
     assert st["evictions"] > 0 and st["admission_waits"] > 0
-    if not any(wide):
-        # a 128-bit set can exceed its 64-bit admission estimate; otherwise
-        # the budget holds
-        assert st["peak_bytes"] <= budget
+    # the budget is a hard bound, 128-bit sets included
+    assert st["peak_bytes"] <= budget
+
+
+def test_wide_set_reserves_its_128_bit_size(T):
+    """A set that needs 128 bits (an 8-vertex star on a 1,500-edge hub) in
+    a server whose budget holds it only after the 64-bit sets are evicted:
+    the 64-bit attempt stops, the query comes back with the 128-bit
+    reservation, later queries of that set reserve 128 bits at once, every
+    result equals its run alone and the budget holds throughout."""
+    rng = np.random.default_rng(3)
+    hub = 1500
+    star = W.TemporalGraph(np.zeros(hub, np.int32), np.arange(1, hub + 1, dtype=np.int32),
+                           rng.integers(0, 50, hub).astype(np.int64), hub + 1)
+    gs = T.Graph(star.src, star.dst, star.t, star.n)
+    g2 = W.small_graph(20000, 81, n=500, span=400000)
+    gt = T.Graph(g2.src, g2.dst, g2.t, g2.n)
+    smo = T.make_motif(tuple((0, j) for j in range(1, 8)), 100)
+    big = T.weights_footprint(gs, smo, wide=True) + 4 * ((hub * 16 + 255) & ~255) + (1 << 20)
+    mos = [T.make_motif(W.MOTIFS[nm], d) for nm, d in (("4cycle", 3000), ("3cycle", 2000), ("4star", 1000))]
+    small = max(T.weights_footprint(gt, mo) for mo in mos) + 4 * ((20000 * 8 + 255) & ~255) + (1 << 20)
+    reserve = 24 * (1 << 14)
+    budget = reserve + max(big, 2 * small) + small // 2
+    say("wide budget", budget, big, small)
+    srv = T.Server(budget, pass_samples=1 << 14, job_chunk=1 << 12)
+    a, b = srv.add_graph(gs), srv.add_graph(gt)
+    jobs = [(b, mos[0], 30000, 1), (a, smo, 20000, 5), (b, mos[1], 20000, 2), (b, mos[2], 10000, 3),
+            (a, smo, 7000, 6), (b, mos[0], 5000, 4)]
+    tickets = [srv.submit(g, mo, k, s) for g, mo, k, s in jobs]
+    outs = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    for (g, mo, k, s), (r, _) in zip(jobs, outs):
+        alone = T.estimate(gs if g == a else gt, mo, k, s)
+        assert r.status == 0 and same(r, alone)
+    assert outs[1][0].flags & T.TM_F_WIDE
+    assert st["peak_bytes"] <= budget and st["failed"] == 0
+
+
+def test_pass_retry_after_a_failed_allocation(T):
+    """A sampling pass whose device allocation fails (injected through the
+    server's allocator once its weight sets are resident) waits for any build
+    in flight, returns cached blocks and runs again; every result still
+    equals the same query alone."""
+    g = W.small_graph(20000, 82, n=500, span=400000)
+    tg = T.Graph(g.src, g.dst, g.t, g.n)
+    A = T.TorchAllocator()
+    srv = T.Server(4 << 30, pass_samples=1 << 16, job_chunk=1 << 14, allocator=A)
+    gid = srv.add_graph(tg)
+    mos = [T.make_motif(W.MOTIFS[nm], 3000) for nm in ("4cycle", "3cycle")]
+    for mo in mos:
+        srv.wait(srv.submit(gid, mo, 0, 1))   # sets resident
+    A.fail_next = 1                           # the next allocation fails: a pass's
+    jobs = [(mos[0], 200000, 7), (mos[1], 100000, 8)]
+    tickets = [srv.submit(gid, mo, k, s) for mo, k, s in jobs]
+    outs = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert st["pass_retries"] >= 1 and A.failed == 1
+    for (mo, k, s), (r, _) in zip(jobs, outs):
+        assert r.status == 0 and same(r, T.estimate(tg, mo, k, s))
+    assert A.live_bytes == 0
 
 
 def test_footprint_matches_build(T, world):
