@@ -123,6 +123,169 @@ __device__ __forceinline__ BoundsN<NB> list_bounds(const DevGraph& G, int dir, i
     return r;
 }
 
+// ---------------------------------------------------------------------------
+// The level kernel's window bounds.  The lanes of a wave walk consecutive
+// positions of one list order, so when they all walk one vertex's list
+// (the common case on a hub) their times -- and every window bound x, each
+// nondecreasing in the time -- rise with the lane index.  Each bound's
+// positions for the whole wave then lie between those of the first and the
+// last lane: two wave-uniform searches find that segment of the child's list,
+// the wave stages it in LDS with coalesced loads, and each lane finishes its
+// search there.  Segments longer than kSeg fall back to a per-lane search
+// inside the segment, and waves over several lists to the per-lane lockstep
+// searches.  In N order each lane's keys share its excluded neighbour, so the
+// smallest key is searched over the list and the others are reached by
+// galloping from it (they lie in that neighbour's run, a few entries on).
+// Every bound is the first position whose key is >= x, as in list_bounds.
+// ---------------------------------------------------------------------------
+constexpr int kSeg = 256;  // LDS entries per wave for a staged segment
+
+// First position in [lo, hi) with lt >= x (hi if none), by halving.
+__device__ __forceinline__ int32_t time_lower_bound(const int64_t* lt, int32_t lo, int32_t hi, int64_t x) {
+    int32_t c = lo, n = hi - lo;
+    while (n > 1) {
+        const int32_t h = n >> 1;
+        c = lt[c + h] < x ? c + h : c;
+        n -= h;
+    }
+    return hi == lo ? lo : c + (lt[c] < x ? 1 : 0);
+}
+
+// The same over an LDS copy of [0, len).
+__device__ __forceinline__ int32_t lds_lower_bound(const int64_t* seg, int32_t len, int64_t x) {
+    int32_t c = 0, n = len;
+    while (n > 1) {
+        const int32_t h = n >> 1;
+        c = seg[c + h] < x ? c + h : c;
+        n -= h;
+    }
+    return len == 0 ? 0 : c + (seg[c] < x ? 1 : 0);
+}
+
+// Keys before the bound of (kx, le): z < kx, or z == kx when x > T.
+__device__ __forceinline__ bool key_before(u64 z, u64 kx, bool le) { return z < kx || (le && z == kx); }
+
+// The bound of (kx, le) in [s, b), every position before s being before it:
+// doubling steps from s, then halving between the last two.
+__device__ __forceinline__ int32_t key_gallop(const u64* nk, int32_t s, int32_t b, u64 kx, bool le) {
+    if (s >= b || !key_before(nk[s], kx, le)) return s;
+    int32_t lo = s, step = 1, hi;
+    while (true) {
+        hi = lo + step;
+        if (hi >= b) {
+            hi = b;
+            break;
+        }
+        if (!key_before(nk[hi], kx, le)) break;
+        lo = hi;
+        step <<= 1;
+    }
+    // lo is before the bound, hi is not (or is b): the bound is in (lo, hi]
+    int32_t n = hi - lo;
+    while (n > 1) {
+        const int32_t h = n >> 1;
+        lo = key_before(nk[lo + h], kx, le) ? lo + h : lo;
+        n -= h;
+    }
+    return lo + 1;
+}
+
+// The indices of a child's bounds in nondecreasing order of x (Kind 0: a
+// child before its parent, 1: after it, 2: unordered, four bounds).
+template <int Kind>
+__device__ __forceinline__ constexpr int bound_rank(int k) {
+    return Kind == 0 ? (k == 0 ? 1 : (k == 1 ? 0 : 2)) : (Kind == 1 ? (k == 0 ? 0 : (k == 1 ? 2 : 1))
+                                                                     : (k == 0 ? 1 : (k == 1 ? 0 : (k == 2 ? 3 : 2))));
+}
+
+// seg: this wave's kSeg LDS entries.  Called by every lane of the wave with
+// the same dir.
+template <int NB, int Kind>
+__device__ __forceinline__ BoundsN<NB> level_bounds(const DevGraph& G, int dir, int32_t g, int32_t o,
+                                                    const int64_t (&xs)[NB], bool exclude, int64_t* seg) {
+    const int32_t a = G.off[dir][g], b = G.off[dir][g + 1];
+    const int64_t* lt = G.lt[dir];
+    const u64* nk = G.nkey[dir];
+    int64_t x[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) x[j] = xs[j] < 0 ? 0 : (xs[j] > G.T + 1 ? G.T + 1 : xs[j]);
+    BoundsN<NB> r;
+    r.len = b - a;
+    // --- T order
+    const int lane = threadIdx.x & 63;
+    const int32_t g0 = __builtin_amdgcn_readfirstlane(g);
+    const bool whole = __ballot(1) == ~0ull && __ballot(g != g0) == 0;
+    if (whole) {
+        const int32_t ua = __builtin_amdgcn_readfirstlane(a), ub = __builtin_amdgcn_readfirstlane(b);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int64_t xlo = __shfl(x[j], 0, 64), xhi = __shfl(x[j], 63, 64);
+            const int32_t plo = time_lower_bound(lt, ua, ub, xlo);
+            const int32_t phi = time_lower_bound(lt, plo, ub, xhi);
+            const int32_t len = phi - plo;
+            if (len <= kSeg) {
+                for (int32_t i = lane; i < len; i += 64) seg[i] = lt[plo + i];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                r.p[j] = plo + lds_lower_bound(seg, len, x[j]);
+                // every lane has read before the next bound overwrites seg
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            } else {
+                r.p[j] = time_lower_bound(lt, plo, phi, x[j]);
+            }
+        }
+    } else {
+        int32_t c[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) c[j] = a;
+        int32_t n = b - a;
+        while (n > 1) {
+            const int32_t h = n >> 1;
+            int64_t y[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) y[j] = lt[c[j] + h];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) c[j] = y[j] < x[j] ? c[j] + h : c[j];
+            n -= h;
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) r.p[j] = a == b ? a : c[j] + (lt[c[j]] < x[j] ? 1 : 0);
+    }
+    // --- N order
+    if (!exclude || a == b) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) r.q[j] = a;  // no excluded run
+        return r;
+    }
+    const u64 base = (u64)o << G.bt;
+    u64 kx[NB];
+    bool le[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        le[j] = x[j] > G.T;
+        kx[j] = base + (u64)(le[j] ? G.T : x[j]);
+    }
+    {
+        constexpr int j0 = bound_rank<Kind>(0);
+        int32_t c = a, n = b - a;
+        while (n > 1) {
+            const int32_t h = n >> 1;
+            c = key_before(nk[c + h], kx[j0], le[j0]) ? c + h : c;
+            n -= h;
+        }
+        r.q[j0] = c + (key_before(nk[c], kx[j0], le[j0]) ? 1 : 0);
+    }
+    sfor<1, NB>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int jk = bound_rank<Kind>(k), jp = bound_rank<Kind>(k - 1);
+        r.q[jk] = key_gallop(nk, r.q[jp], b, kx[jk], le[jk]);
+    });
+    return r;
+}
+
 // Sum of the child's weights over T positions [p0, p1) minus the N run [q0, q1).
 template <typename W>
 __device__ __forceinline__ W window_mass(int32_t p0, int32_t p1, int32_t q0, int32_t q1, bool leaf,
@@ -153,7 +316,7 @@ __device__ __forceinline__ W window_mass(int32_t p0, int32_t p1, int32_t q0, int
 // of L entries ceil(log2 L) + 1 probes of each of its six bounds (three in
 // the T order, three in the N order, 8 B each; eight for an unordered child).
 template <typename W, bool kCount, bool kPO>
-__device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
+__device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p, int64_t* seg) {
     const DevGraph& G = a.G;
     u64 nb = 0;
     // the walked edge: its list's owner, neighbour and time sit at p
@@ -197,7 +360,7 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
             xs[1] = lo > (blk - 1) * a.ilen ? lo : (blk - 1) * a.ilen;
             xs[2] = (hi < (blk + 2) * a.ilen - 1 ? hi : (blk + 2) * a.ilen - 1) + 1;
             xs[3] = (hi < (blk + 1) * a.ilen - 1 ? hi : (blk + 1) * a.ilen - 1) + 1;
-            const BoundsN<4> r = list_bounds<4>(G, d.dir, g, o, xs, a.exclude != 0);
+            const BoundsN<4> r = level_bounds<4, 2>(G, d.dir, g, o, xs, a.exclude != 0, seg);
             if constexpr (kCount) {
                 int it = 0;
                 for (int32_t n = r.len; n > 1; n -= n >> 1) ++it;
@@ -230,7 +393,8 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
                 xs[1] = (hi < (blk + 2) * a.ilen - 1 ? hi : (blk + 2) * a.ilen - 1) + 1;
                 xs[2] = (hi < (blk + 1) * a.ilen - 1 ? hi : (blk + 1) * a.ilen - 1) + 1;
             }
-            const BoundsN<3> r = list_bounds<3>(G, d.dir, g, o, xs, a.exclude != 0);
+            const BoundsN<3> r = d.beta < 0 ? level_bounds<3, 0>(G, d.dir, g, o, xs, a.exclude != 0, seg)
+                                            : level_bounds<3, 1>(G, d.dir, g, o, xs, a.exclude != 0, seg);
             if constexpr (kCount) {
                 int it = 0;
                 for (int32_t n = r.len; n > 1; n -= n >> 1) ++it;
@@ -280,8 +444,9 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
 template <typename W, bool kCount, bool kPO>
 __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    __shared__ int64_t segs[kWaves][kSeg];
     u64 nb = 0;
-    if (p < a.G.m) nb = level_edge<W, kCount, kPO>(a, p);
+    if (p < a.G.m) nb = level_edge<W, kCount, kPO>(a, p, segs[threadIdx.x >> 6]);
     if constexpr (kCount) {
         // one addition per workgroup
 #pragma unroll
