@@ -45,7 +45,8 @@ struct SampleArgs {
     int same_window[kMaxSlots];
     const void* qt[kMaxSlots][2];
     const void* qn[kMaxSlots][2];
-    // kept child windows (see weights): by the parent's list position, per parity
+    // kept child windows (see weights): parity par of the parent at list
+    // position x is win[s][par][2 x] (the parities interleave)
     const int4* win[kMaxSlots][2];
     int has_win;
     int root_dir;  // the list whose T positions key the root (0: out-lists, 1: in-lists)
@@ -796,7 +797,7 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
             if (a.same_window[s]) {
                 w = last;
             } else if constexpr (kWin) {
-                const int4 b = a.win[s][par][pick(posv, a.parent[s])];
+                const int4 b = a.win[s][par][2 * (int64_t)pick(posv, a.parent[s])];
                 w.p0 = b.x;
                 w.p1 = b.y;
                 w.q0 = b.z;

@@ -190,8 +190,11 @@ struct tm_weights {
     void* vals[kMaxSlots][2] = {};  // build temporaries, null afterwards
     // child windows, per non-center slot and interval parity: the slot's
     // candidate window (p0, p1, q0, q1) for every edge its parent can match,
-    // by that edge's position in the list the parent is drawn from (the root
-    // list's T order for the center, see HostPlan::root_dir); null when not kept
+    // by that edge's position x in the list the parent is drawn from (the
+    // root list's T order for the center, see HostPlan::root_dir); null when
+    // not kept.  The two parities interleave, one 32-byte record per edge:
+    // parity par's window of position x is win[s][par][2 x] (win[s][1] is
+    // win[s][0] + 1).
     int4* win[kMaxSlots][2] = {};
     bool has_win = false;
     // a server builds its sets for memory over speed: no kept windows and a

@@ -44,7 +44,7 @@ struct LevelArgs {
     int nc;
     ChildDesc c[kMaxSlots];
     int walk;          // -1: eid order; 0 / 1: the T order of the out- / in-lists
-    int4* win[kMaxSlots][2];  // per child and parity: its windows (null: not kept)
+    int4* win[kMaxSlots][2];  // per child and parity: its windows, stride 2 (null: not kept)
     int win_dir;       // the list whose T positions index the windows
     void* out[2];      // per parity: indexed by eid, or by T position in list out_pos_dir
     int out_pos_dir;   // first of two passes: its own walk (consecutive writes), else -1
@@ -124,43 +124,15 @@ __device__ __forceinline__ BoundsN<NB> list_bounds(const DevGraph& G, int dir, i
 }
 
 // ---------------------------------------------------------------------------
-// The level kernel's window bounds.  The lanes of a wave walk consecutive
-// positions of one list order, so when they all walk one vertex's list
-// (the common case on a hub) their times -- and every window bound x, each
-// nondecreasing in the time -- rise with the lane index.  Each bound's
-// positions for the whole wave then lie between those of the first and the
-// last lane: two wave-uniform searches find that segment of the child's list,
-// the wave stages it in LDS with coalesced loads, and each lane finishes its
-// search there.  Segments longer than kSeg fall back to a per-lane search
-// inside the segment, and waves over several lists to the per-lane lockstep
-// searches.  In N order each lane's keys share its excluded neighbour, so the
-// smallest key is searched over the list and the others are reached by
-// galloping from it (they lie in that neighbour's run, a few entries on).
-// Every bound is the first position whose key is >= x, as in list_bounds.
+// The level kernel's window bounds.  In T order the NB bounds are searched in
+// lockstep over the child's list (NB independent loads per halving step).  In
+// N order each lane's keys share its excluded neighbour, so the smallest key
+// is searched over the list and the others are reached by galloping from it:
+// they lie in that neighbour's run, a few entries on.  (A variant in which a
+// wave walking one list staged each bound's segment in LDS after two
+// wave-uniform searches was measured slower: see the design notes.)  Every
+// bound is the first position whose key is >= x, as in list_bounds.
 // ---------------------------------------------------------------------------
-constexpr int kSeg = 256;  // LDS entries per wave for a staged segment
-
-// First position in [lo, hi) with lt >= x (hi if none), by halving.
-__device__ __forceinline__ int32_t time_lower_bound(const int64_t* lt, int32_t lo, int32_t hi, int64_t x) {
-    int32_t c = lo, n = hi - lo;
-    while (n > 1) {
-        const int32_t h = n >> 1;
-        c = lt[c + h] < x ? c + h : c;
-        n -= h;
-    }
-    return hi == lo ? lo : c + (lt[c] < x ? 1 : 0);
-}
-
-// The same over an LDS copy of [0, len).
-__device__ __forceinline__ int32_t lds_lower_bound(const int64_t* seg, int32_t len, int64_t x) {
-    int32_t c = 0, n = len;
-    while (n > 1) {
-        const int32_t h = n >> 1;
-        c = seg[c + h] < x ? c + h : c;
-        n -= h;
-    }
-    return len == 0 ? 0 : c + (seg[c] < x ? 1 : 0);
-}
 
 // Keys before the bound of (kx, le): z < kx, or z == kx when x > T.
 __device__ __forceinline__ bool key_before(u64 z, u64 kx, bool le) { return z < kx || (le && z == kx); }
@@ -198,11 +170,9 @@ __device__ __forceinline__ constexpr int bound_rank(int k) {
                                                                      : (k == 0 ? 1 : (k == 1 ? 0 : (k == 2 ? 3 : 2))));
 }
 
-// seg: this wave's kSeg LDS entries.  Called by every lane of the wave with
-// the same dir.
 template <int NB, int Kind>
 __device__ __forceinline__ BoundsN<NB> level_bounds(const DevGraph& G, int dir, int32_t g, int32_t o,
-                                                    const int64_t (&xs)[NB], bool exclude, int64_t* seg) {
+                                                    const int64_t (&xs)[NB], bool exclude) {
     const int32_t a = G.off[dir][g], b = G.off[dir][g + 1];
     const int64_t* lt = G.lt[dir];
     const u64* nk = G.nkey[dir];
@@ -211,49 +181,23 @@ __device__ __forceinline__ BoundsN<NB> level_bounds(const DevGraph& G, int dir, 
     for (int j = 0; j < NB; ++j) x[j] = xs[j] < 0 ? 0 : (xs[j] > G.T + 1 ? G.T + 1 : xs[j]);
     BoundsN<NB> r;
     r.len = b - a;
-    // --- T order
-    const int lane = threadIdx.x & 63;
-    const int32_t g0 = __builtin_amdgcn_readfirstlane(g);
-    const bool whole = __ballot(1) == ~0ull && __ballot(g != g0) == 0;
-    if (whole) {
-        const int32_t ua = __builtin_amdgcn_readfirstlane(a), ub = __builtin_amdgcn_readfirstlane(b);
+    // --- T order: the NB bounds in lockstep (independent loads per step)
+    int32_t c[NB];
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const int64_t xlo = __shfl(x[j], 0, 64), xhi = __shfl(x[j], 63, 64);
-            const int32_t plo = time_lower_bound(lt, ua, ub, xlo);
-            const int32_t phi = time_lower_bound(lt, plo, ub, xhi);
-            const int32_t len = phi - plo;
-            if (len <= kSeg) {
-                for (int32_t i = lane; i < len; i += 64) seg[i] = lt[plo + i];
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                r.p[j] = plo + lds_lower_bound(seg, len, x[j]);
-                // every lane has read before the next bound overwrites seg
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            } else {
-                r.p[j] = time_lower_bound(lt, plo, phi, x[j]);
-            }
-        }
-    } else {
-        int32_t c[NB];
+    for (int j = 0; j < NB; ++j) c[j] = a;
+    int32_t n = b - a;
+    while (n > 1) {
+        const int32_t h = n >> 1;
+        int64_t y[NB];
 #pragma unroll
-        for (int j = 0; j < NB; ++j) c[j] = a;
-        int32_t n = b - a;
-        while (n > 1) {
-            const int32_t h = n >> 1;
-            int64_t y[NB];
+        for (int j = 0; j < NB; ++j) y[j] = lt[c[j] + h];
 #pragma unroll
-            for (int j = 0; j < NB; ++j) y[j] = lt[c[j] + h];
-#pragma unroll
-            for (int j = 0; j < NB; ++j) c[j] = y[j] < x[j] ? c[j] + h : c[j];
-            n -= h;
-        }
-#pragma unroll
-        for (int j = 0; j < NB; ++j) r.p[j] = a == b ? a : c[j] + (lt[c[j]] < x[j] ? 1 : 0);
+        for (int j = 0; j < NB; ++j) c[j] = y[j] < x[j] ? c[j] + h : c[j];
+        n -= h;
     }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) r.p[j] = a == b ? a : c[j] + (lt[c[j]] < x[j] ? 1 : 0);
+
     // --- N order
     if (!exclude || a == b) {
 #pragma unroll
@@ -270,13 +214,13 @@ __device__ __forceinline__ BoundsN<NB> level_bounds(const DevGraph& G, int dir, 
     }
     {
         constexpr int j0 = bound_rank<Kind>(0);
-        int32_t c = a, n = b - a;
-        while (n > 1) {
-            const int32_t h = n >> 1;
-            c = key_before(nk[c + h], kx[j0], le[j0]) ? c + h : c;
-            n -= h;
+        int32_t cq = a, nq = b - a;
+        while (nq > 1) {
+            const int32_t h = nq >> 1;
+            cq = key_before(nk[cq + h], kx[j0], le[j0]) ? cq + h : cq;
+            nq -= h;
         }
-        r.q[j0] = c + (key_before(nk[c], kx[j0], le[j0]) ? 1 : 0);
+        r.q[j0] = cq + (key_before(nk[cq], kx[j0], le[j0]) ? 1 : 0);
     }
     sfor<1, NB>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
@@ -316,7 +260,7 @@ __device__ __forceinline__ W window_mass(int32_t p0, int32_t p1, int32_t q0, int
 // of L entries ceil(log2 L) + 1 probes of each of its six bounds (three in
 // the T order, three in the N order, 8 B each; eight for an unordered child).
 template <typename W, bool kCount, bool kPO>
-__device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p, int64_t* seg) {
+__device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
     const DevGraph& G = a.G;
     u64 nb = 0;
     // the walked edge: its list's owner, neighbour and time sit at p
@@ -360,7 +304,7 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p, int64_t
             xs[1] = lo > (blk - 1) * a.ilen ? lo : (blk - 1) * a.ilen;
             xs[2] = (hi < (blk + 2) * a.ilen - 1 ? hi : (blk + 2) * a.ilen - 1) + 1;
             xs[3] = (hi < (blk + 1) * a.ilen - 1 ? hi : (blk + 1) * a.ilen - 1) + 1;
-            const BoundsN<4> r = level_bounds<4, 2>(G, d.dir, g, o, xs, a.exclude != 0, seg);
+            const BoundsN<4> r = level_bounds<4, 2>(G, d.dir, g, o, xs, a.exclude != 0);
             if constexpr (kCount) {
                 int it = 0;
                 for (int32_t n = r.len; n > 1; n -= n >> 1) ++it;
@@ -370,8 +314,8 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p, int64_t
             }
             if (a.win[c][0]) {
                 const int64_t at = a.win_dir == a.walk ? p : (int64_t)G.tpos[a.win_dir][e];
-                a.win[c][parA][at] = make_int4(r.p[0], r.p[2], r.q[0], r.q[2]);
-                a.win[c][parB][at] = hasB ? make_int4(r.p[1], r.p[3], r.q[1], r.q[3]) : make_int4(0, 0, 0, 0);
+                a.win[c][parA][2 * at] = make_int4(r.p[0], r.p[2], r.q[0], r.q[2]);
+                a.win[c][parB][2 * at] = hasB ? make_int4(r.p[1], r.p[3], r.q[1], r.q[3]) : make_int4(0, 0, 0, 0);
             }
             xa = window_mass<W>(r.p[0], r.p[2], r.q[0], r.q[2], d.leaf, d.qt[parA], d.qn[parA]);
             xb = hasB ? window_mass<W>(r.p[1], r.p[3], r.q[1], r.q[3], d.leaf, d.qt[parB], d.qn[parB]) : (W)0;
@@ -393,8 +337,8 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p, int64_t
                 xs[1] = (hi < (blk + 2) * a.ilen - 1 ? hi : (blk + 2) * a.ilen - 1) + 1;
                 xs[2] = (hi < (blk + 1) * a.ilen - 1 ? hi : (blk + 1) * a.ilen - 1) + 1;
             }
-            const BoundsN<3> r = d.beta < 0 ? level_bounds<3, 0>(G, d.dir, g, o, xs, a.exclude != 0, seg)
-                                            : level_bounds<3, 1>(G, d.dir, g, o, xs, a.exclude != 0, seg);
+            const BoundsN<3> r = d.beta < 0 ? level_bounds<3, 0>(G, d.dir, g, o, xs, a.exclude != 0)
+                                            : level_bounds<3, 1>(G, d.dir, g, o, xs, a.exclude != 0);
             if constexpr (kCount) {
                 int it = 0;
                 for (int32_t n = r.len; n > 1; n -= n >> 1) ++it;
@@ -417,8 +361,8 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p, int64_t
                     wa = make_int4(r.p[0], r.p[1], r.q[0], r.q[1]);
                     wb = make_int4(r.p[0], r.p[2], r.q[0], r.q[2]);
                 }
-                a.win[c][parA][at] = wa;
-                a.win[c][parB][at] = hasB ? wb : make_int4(0, 0, 0, 0);
+                a.win[c][parA][2 * at] = wa;
+                a.win[c][parB][2 * at] = hasB ? wb : make_int4(0, 0, 0, 0);
             }
             if (d.beta < 0) {
                 xa = window_mass<W>(r.p[0], r.p[2], r.q[0], r.q[2], d.leaf, d.qt[parA], d.qn[parA]);
@@ -444,9 +388,8 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p, int64_t
 template <typename W, bool kCount, bool kPO>
 __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    __shared__ int64_t segs[kWaves][kSeg];
     u64 nb = 0;
-    if (p < a.G.m) nb = level_edge<W, kCount, kPO>(a, p, segs[threadIdx.x >> 6]);
+    if (p < a.G.m) nb = level_edge<W, kCount, kPO>(a, p);
     if constexpr (kCount) {
         // one addition per workgroup
 #pragma unroll
@@ -716,10 +659,10 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, int* ovf_c, bool check_
                     for (int j = 0; j < a.nc; ++j) {
                         const int c = cs[j];
                         if (a.c[j].copies > 0) {
-                            for (int par = 0; par < 2; ++par) {
-                                TM_TRY(arena_alloc(w->arena, &w->win[c][par], (size_t)m));
-                                a.win[j][par] = w->win[c][par];
-                            }
+                            // both parities of an edge in one 32-byte record
+                            TM_TRY(arena_alloc(w->arena, &w->win[c][0], 2 * (size_t)m));
+                            w->win[c][1] = w->win[c][0] + 1;
+                            for (int par = 0; par < 2; ++par) a.win[j][par] = w->win[c][par];
                         } else {
                             for (int j2 = 0; j2 < j; ++j2) {
                                 const ChildDesc& e2 = a.c[j2];
@@ -996,8 +939,8 @@ static int window_tables(const HostPlan& P) {
 
 u64 weights_window_bytes(const HostPlan& P, int64_t m) {
     if (m <= 0) return 0;
-    const u64 per = (((u64)m * sizeof(int4)) + 255) & ~(u64)255;
-    return (u64)window_tables(P) * 2 * per;
+    const u64 per = (((u64)m * 2 * sizeof(int4)) + 255) & ~(u64)255;
+    return (u64)window_tables(P) * per;
 }
 
 bool weights_keep_windows(const HostPlan& P, int64_t m) {
