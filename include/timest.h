@@ -203,7 +203,18 @@ enum tm_graph_array {
     TM_ARR_OUT_EID = 5,  /* int32[m]  out-lists in time order (eids) */
     TM_ARR_IN_EID = 6,   /* int32[m]  in-lists in time order (eids) */
     TM_ARR_OUTN_EID = 7, /* int32[m]  out-lists in (destination, time) order */
-    TM_ARR_INN_EID = 8   /* int32[m]  in-lists in (source, time) order */
+    TM_ARR_INN_EID = 8,  /* int32[m]  in-lists in (source, time) order */
+    TM_ARR_OUT_T = 9,    /* int64[m]  out-lists in time order: times */
+    TM_ARR_IN_T = 10,    /* int64[m]  in-lists in time order: times */
+    TM_ARR_OUT_NBR = 11, /* int32[m]  out-lists in time order: destinations */
+    TM_ARR_IN_NBR = 12,  /* int32[m]  in-lists in time order: sources */
+    TM_ARR_OUT_POS = 13, /* int32[m]  by eid: the edge's position in the out-lists' time order */
+    TM_ARR_IN_POS = 14,  /* int32[m]  by eid: the edge's position in the in-lists' time order */
+    TM_ARR_OUTN_KEY = 15, /* uint64[m] out-lists in N order: destination << b | time, b the
+                           * bits of the largest shifted time (at least 1) */
+    TM_ARR_INN_KEY = 16, /* uint64[m] in-lists in N order: source << b | time */
+    TM_ARR_OUTN_POS = 17, /* int32[m] out-lists in N order: each entry's time-order position */
+    TM_ARR_INN_POS = 18  /* int32[m]  in-lists in N order: each entry's time-order position */
 };
 int tm_graph_export(const tm_graph* g, int which, void* host_out, void* stream);
 

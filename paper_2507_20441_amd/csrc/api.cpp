@@ -477,6 +477,16 @@ extern "C" int tm_graph_export(const tm_graph* g, int which, void* host_out, voi
         case TM_ARR_IN_EID: p = D.leid[1]; bytes = m * 4; break;
         case TM_ARR_OUTN_EID: p = D.neid[0]; bytes = m * 4; break;
         case TM_ARR_INN_EID: p = D.neid[1]; bytes = m * 4; break;
+        case TM_ARR_OUT_T: p = D.lt[0]; bytes = m * 8; break;
+        case TM_ARR_IN_T: p = D.lt[1]; bytes = m * 8; break;
+        case TM_ARR_OUT_NBR: p = D.lnbr[0]; bytes = m * 4; break;
+        case TM_ARR_IN_NBR: p = D.lnbr[1]; bytes = m * 4; break;
+        case TM_ARR_OUT_POS: p = D.tpos[0]; bytes = m * 4; break;
+        case TM_ARR_IN_POS: p = D.tpos[1]; bytes = m * 4; break;
+        case TM_ARR_OUTN_KEY: p = D.nkey[0]; bytes = m * 8; break;
+        case TM_ARR_INN_KEY: p = D.nkey[1]; bytes = m * 8; break;
+        case TM_ARR_OUTN_POS: p = D.nxref[0]; bytes = m * 4; break;
+        case TM_ARR_INN_POS: p = D.nxref[1]; bytes = m * 4; break;
         default: return tm_fail(TM_EINVAL, "graph_export: unknown array %d", which);
     }
     if (bytes == 0 || !p) return TM_OK;

@@ -3,7 +3,10 @@
 // The paper stores the graph as per-vertex in/out edge lists sorted by time,
 // searched by binary search (Sec. 4, storage paragraph), with timestamps
 // shifted to start at 0.  Here every list is built by stable LSD radix sorts
-// so that the order inside each list is the canonical eid order.
+// so that the order inside each list is the canonical eid order; each sort
+// carries the edge fields its lists need (time, eid, neighbour), so the list
+// arrays come out of the sorts in order and only the two inverse
+// permutations (an edge's T position) are written or read at random.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -96,43 +99,25 @@ validate_reduce_kernel(const u64* part, int nb, int* flags, u64* tmin, u64* tmax
     }
 }
 
-// Sort keys for the canonical order (t, u, v).
-__global__ void key_tuv_kernel(const int32_t* src, const int32_t* dst, const int64_t* t, int64_t m,
-                               int64_t tmin, int bn, int with_time, u64* keys, uint32_t* vals) {
+// Sort keys for the canonical order (t, u, v): one packed key t << 2bn |
+// u << bn | v when it fits 64 bits, else the key u << bn | v with the time
+// carried beside it (a second sort then orders by time).
+__global__ void canon_keys_kernel(const int32_t* src, const int32_t* dst, const int64_t* t, int64_t m, int64_t tmin,
+                                  int bn, int one_key, u64* keys, u64* times) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= m) return;
     u64 k = ((u64)(uint32_t)src[i] << bn) | (u64)(uint32_t)dst[i];
-    if (with_time) k |= (u64)(t[i] - tmin) << (2 * bn);
+    if (one_key)
+        k |= (u64)(t[i] - tmin) << (2 * bn);
+    else
+        times[i] = (u64)(t[i] - tmin);
     keys[i] = k;
-    vals[i] = (uint32_t)i;
 }
 
-__global__ void key_time_kernel(const int64_t* t, const uint32_t* perm, int64_t m, int64_t tmin,
-                                u64* keys) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < m) keys[i] = (u64)(t[perm[i]] - tmin);
-}
-
-// Edge arrays in eid order, and the duplicate check on neighbours in that order.
-__global__ void gather_edges_kernel(const int32_t* src, const int32_t* dst, const int64_t* t,
-                                    const uint32_t* perm, int64_t m, int64_t tmin, int32_t* osrc,
-                                    int32_t* odst, int64_t* ot, int* flags) {
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= m) return;
-    const uint32_t i = perm[e];
-    osrc[e] = src[i];
-    odst[e] = dst[i];
-    ot[e] = t[i] - tmin;
-    if (e > 0) {
-        const uint32_t j = perm[e - 1];
-        if (src[i] == src[j] && dst[i] == dst[j] && t[i] == t[j]) atomicOr(flags, kDup);
-    }
-}
-
-// Edge arrays straight from sorted packed keys t << 2bn | u << bn | v, and the
-// duplicate check on neighbours.
-__global__ void decode_edges_kernel(const u64* key, int64_t m, int bn, int32_t* osrc, int32_t* odst,
-                                    int64_t* ot, int* flags) {
+// Edge arrays from the sorted packed keys, and the duplicate check on
+// neighbours.
+__global__ void decode_packed_kernel(const u64* key, int64_t m, int bn, int32_t* osrc, int32_t* odst, int64_t* ot,
+                                     int* flags) {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= m) return;
     const u64 k = key[e];
@@ -143,83 +128,33 @@ __global__ void decode_edges_kernel(const u64* key, int64_t m, int bn, int32_t* 
     if (e > 0 && key[e - 1] == k) atomicOr(flags, kDup);
 }
 
-__global__ void iota_key_kernel(const int32_t* key_by_eid, int64_t m, uint32_t* keys, uint32_t* vals) {
+// Edge arrays from the sorted times and the (u, v) keys carried with them.
+__global__ void decode_split_kernel(const u64* tsorted, const u64* uv, int64_t m, int bn, int32_t* osrc,
+                                    int32_t* odst, int64_t* ot, int* flags) {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= m) return;
-    keys[e] = (uint32_t)key_by_eid[e];
-    vals[e] = (uint32_t)e;
-}
-
-__global__ void copy_pair_kernel(const int32_t* k, const int32_t* v, int64_t m, uint32_t* keys,
-                                 uint32_t* vals) {
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= m) return;
-    keys[p] = (uint32_t)k[p];
-    vals[p] = (uint32_t)v[p];
-}
-
-// T-order list entries from the sorted eids.
-__global__ void fill_t_order_kernel(const uint32_t* eids, const uint32_t* owner, const int64_t* t,
-                                    const int32_t* nbr_by_eid, int64_t m, int64_t* lt, int32_t* leid, int32_t* lnbr,
-                                    int32_t* lown, int32_t* pos) {
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= m) return;
-    const uint32_t e = eids[p];
-    lt[p] = t[e];
-    leid[p] = (int32_t)e;
-    lnbr[p] = nbr_by_eid[e];
-    if (lown) lown[p] = (int32_t)owner[p];
-    pos[e] = (int32_t)p;
-}
-
-// N-order list entries: packed (neighbour, time) key and the T-order position.
-__global__ void fill_n_order_kernel(const uint32_t* eids, const int64_t* t, const int32_t* nbr_by_eid,
-                                    const int32_t* tpos, int64_t m, int bt, u64* nkey, int32_t* nxref,
-                                    int32_t* neid) {
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= m) return;
-    const uint32_t e = eids[p];
-    nkey[p] = ((u64)(uint32_t)nbr_by_eid[e] << bt) | (u64)t[e];
-    nxref[p] = tpos[e];
-    neid[p] = (int32_t)e;
-}
-
-// The same two fills reading one packed key t << 2bn | u << bn | v per eid
-// (the canonical sort's output) instead of the separate edge arrays.
-__device__ __forceinline__ void unpack_tuv(u64 k, int bn, int64_t& t, int32_t& u, int32_t& v) {
+    const u64 k = uv[e], t = tsorted[e];
     const u64 mask = (1ull << bn) - 1;
-    t = (int64_t)(k >> (2 * bn));
-    u = (int32_t)((k >> bn) & mask);
-    v = (int32_t)(k & mask);
+    osrc[e] = (int32_t)(k >> bn);
+    odst[e] = (int32_t)(k & mask);
+    ot[e] = (int64_t)t;
+    if (e > 0 && uv[e - 1] == k && tsorted[e - 1] == t) atomicOr(flags, kDup);
 }
 
-__global__ void fill_t_order_packed_kernel(const uint32_t* eids, const u64* pk, int bn, int dir, int64_t m,
-                                           int64_t* lt, int32_t* leid, int32_t* lnbr, int32_t* lown, int32_t* pos) {
+// By eid: the edge's position in a T order (the inverse of leid).
+__global__ void tpos_kernel(const int32_t* leid, int64_t m, int32_t* pos) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= m) return;
-    const uint32_t e = eids[p];
-    int64_t t;
-    int32_t u, v;
-    unpack_tuv(pk[e], bn, t, u, v);
-    lt[p] = t;
-    leid[p] = (int32_t)e;
-    lnbr[p] = dir == 0 ? v : u;
-    if (lown) lown[p] = dir == 0 ? u : v;
-    pos[e] = (int32_t)p;
+    if (p < m && (uint32_t)leid[p] < (uint64_t)m) pos[leid[p]] = (int32_t)p;
 }
 
-__global__ void fill_n_order_packed_kernel(const uint32_t* eids, const u64* pk, int bn, int dir,
-                                           const int32_t* tpos, int64_t m, int bt, u64* nkey, int32_t* nxref,
-                                           int32_t* neid) {
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= m) return;
-    const uint32_t e = eids[p];
-    int64_t t;
-    int32_t u, v;
-    unpack_tuv(pk[e], bn, t, u, v);
-    nkey[p] = ((u64)(uint32_t)(dir == 0 ? v : u) << bt) | (u64)t;
-    nxref[p] = tpos[e];
-    neid[p] = (int32_t)e;
+// N order: the packed key from the carried neighbour and time (nkey holds the
+// time on entry), and each entry's position in this direction's T order.
+__global__ void n_order_fix_kernel(const uint32_t* nbr, const int32_t* neid, const int32_t* tpos, int64_t m, int bt,
+                                   u64* nkey, int32_t* nxref) {
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= m) return;
+    nkey[q] = ((u64)nbr[q] << bt) | nkey[q];
+    nxref[q] = (uint32_t)neid[q] < (uint64_t)m ? tpos[neid[q]] : -1;
 }
 
 // List offsets from the owner-sorted keys: off[v] is the first position whose
@@ -228,8 +163,10 @@ __global__ void fill_n_order_packed_kernel(const uint32_t* eids, const u64* pk, 
 __global__ void offsets_kernel(const uint32_t* key, int64_t m, int32_t n, int32_t* off) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= m) return;
-    const int64_t cur = key[p];
-    const int64_t prev = p == 0 ? -1 : (int64_t)key[p - 1];
+    // (owners are below n; the clamps keep a broken order from writing
+    // outside off)
+    const int64_t cur = key[p] < (uint32_t)n ? (int64_t)key[p] : (int64_t)n - 1;
+    const int64_t prev = p == 0 ? -1 : (key[p - 1] < (uint32_t)n ? (int64_t)key[p - 1] : (int64_t)n - 1);
     for (int64_t v = prev + 1; v <= cur; ++v) off[v] = (int32_t)p;
     if (p == m - 1)
         for (int64_t v = cur + 1; v <= n; ++v) off[v] = (int32_t)m;
@@ -286,16 +223,21 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
         TM_HIP(hipGetLastError());
         TM_HIP(dev_free(part, st));
     }
+    // error exits return the flag words to the cache
+    auto bail = [&](int r) {
+        (void)dev_free(flags, st);
+        (void)dev_free(tbounds, st);
+        return r;
+    };
     int hflags[2];
     u64 hb[2];
     TM_HIP(read_back({{hflags, flags, sizeof hflags}, {hb, tbounds, sizeof hb}}, st));
-    if (hflags[0] & kBadRange) return tm_fail(TM_EINVAL, "graph: vertex id outside [0, %d)", n);
-    if (hflags[0] & kSelfLoop) return tm_fail(TM_ESELFLOOP, "graph: self loop");
+    if (hflags[0] & kBadRange) return bail(tm_fail(TM_EINVAL, "graph: vertex id outside [0, %d)", n));
+    if (hflags[0] & kSelfLoop) return bail(tm_fail(TM_ESELFLOOP, "graph: self loop"));
     const int64_t tmin = (int64_t)(hb[0] ^ 0x8000000000000000ull);
     const int64_t tmax = (int64_t)(hb[1] ^ 0x8000000000000000ull);
     if ((__int128)tmax - (__int128)tmin >= ((__int128)1 << 62))
-        return tm_fail(TM_ERANGE, "graph: time span %lld..%lld too large", (long long)tmin,
-                       (long long)tmax);
+        return bail(tm_fail(TM_ERANGE, "graph: time span %lld..%lld too large", (long long)tmin, (long long)tmax));
     g->shift = tmin;
     g->T = tmax - tmin;
     D.T = g->T;
@@ -303,88 +245,127 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
     D.bt = bits_for((u64)g->T);
     if (D.bt == 0) D.bt = 1;
     if (bn + D.bt > 64)
-        return tm_fail(TM_ERANGE, "graph: %d vertex-id bits + %d time bits exceed 64", bn, D.bt);
+        return bail(tm_fail(TM_ERANGE, "graph: %d vertex-id bits + %d time bits exceed 64", bn, D.bt));
 
     // --- canonical order (t, u, v) ----------------------------------------
-    u64 *ka = nullptr, *kb = nullptr;
-    uint32_t *va = nullptr, *vb = nullptr;
-    TM_HIP(dev_alloc((void**)&ka, m * sizeof(u64), st));
-    TM_HIP(dev_alloc((void**)&kb, m * sizeof(u64), st));
-    TM_HIP(dev_alloc((void**)&va, m * sizeof(uint32_t), st));
-    TM_HIP(dev_alloc((void**)&vb, m * sizeof(uint32_t), st));
-    u64* kres;
-    uint32_t* perm;
+    // Four 64-bit work arrays serve every sort below: the canonical sorts use
+    // them whole, the list sorts as halves.
+    u64* work[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint32_t* nbr_tmp = nullptr;  // N order: the carried neighbours, when work[3] holds the owners
+    auto release = [&]() {
+        for (u64*& w : work) {
+            if (w) (void)dev_free(w, st);
+            w = nullptr;
+        }
+        if (nbr_tmp) (void)dev_free(nbr_tmp, st);
+        nbr_tmp = nullptr;
+    };
+    int rc = TM_OK;
+    for (u64*& w : work)
+        if (rc == TM_OK && dev_alloc((void**)&w, (size_t)m * sizeof(u64), st) != hipSuccess)
+            rc = tm_fail(TM_ENOMEM, "graph: work arrays");
+    if (rc != TM_OK) return bail(rc);
+    int32_t *esrc = nullptr, *edst = nullptr;
+    int64_t* et = nullptr;
+    rc = arena_alloc(g->arena, &esrc, m);
+    if (rc == TM_OK) rc = arena_alloc(g->arena, &edst, m);
+    if (rc == TM_OK) rc = arena_alloc(g->arena, &et, m);
     const bool one_key = 2 * bn + D.bt <= 64;
-    hipLaunchKernelGGL(key_tuv_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, src, dst, t, m, tmin,
-                       bn, one_key ? 1 : 0, ka, va);
-    TM_HIP(hipGetLastError());
-    if (one_key) {
-        TM_TRY(radix_sort_pairs<u64>(ka, va, kb, vb, m, 0, 2 * bn + D.bt, &kres, &perm, flags + 1, st));
-    } else {
-        TM_TRY(radix_sort_pairs<u64>(ka, va, kb, vb, m, 0, 2 * bn, &kres, &perm, flags + 1, st));
-        u64* kother = kres == ka ? kb : ka;
-        uint32_t* vother = perm == va ? vb : va;
-        hipLaunchKernelGGL(key_time_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, t, perm, m,
-                           tmin, kother);
-        TM_HIP(hipGetLastError());
-        TM_TRY(radix_sort_pairs<u64>(kother, perm, kres, vother, m, 0, D.bt, &kres, &perm, flags + 1,
-                                     st));
+    if (rc == TM_OK) {
+        hipLaunchKernelGGL(canon_keys_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, src, dst, t, m, tmin, bn,
+                           one_key ? 1 : 0, work[0], work[1]);
+        if (hipGetLastError() != hipSuccess) rc = tm_fail(TM_EDEVICE, "graph: key launch");
     }
-    int32_t *esrc, *edst;
-    int64_t* et;
-    TM_TRY(arena_alloc(g->arena, &esrc, m));
-    TM_TRY(arena_alloc(g->arena, &edst, m));
-    TM_TRY(arena_alloc(g->arena, &et, m));
-    if (one_key && bn > 0)
-        hipLaunchKernelGGL(decode_edges_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
-                           (const u64*)kres, m, bn, esrc, edst, et, flags);
-    else
-        hipLaunchKernelGGL(gather_edges_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, src, dst, t,
-                           (const uint32_t*)perm, m, tmin, esrc, edst, et, flags);
-    TM_HIP(hipGetLastError());
+    // A sort between two buffer sets: the result lands in `spare` after an
+    // odd number of passes, else back in `in`.
+    auto sort_two = [&](const auto& in, const auto& spare, int nbits, auto* res) -> int {
+        const bool odd = (std::max(1, radix_passes(nbits)) & 1) != 0;
+        *res = odd ? spare : in;
+        return sort_into(in, odd ? spare : in, odd ? in : spare, m, 0, nbits, 0, flags + 1, st);
+    };
+    if (rc == TM_OK && one_key) {
+        using S = SortSet<u64>;
+        S in, spare, res;
+        in.k = work[0];
+        spare.k = work[2];
+        rc = sort_two(in, spare, 2 * bn + D.bt, &res);
+        if (rc == TM_OK)
+            hipLaunchKernelGGL(decode_packed_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, (const u64*)res.k, m,
+                               bn, esrc, edst, et, flags);
+    } else if (rc == TM_OK) {
+        // by (u, v) with the time carried, then by time with (u, v) carried
+        using S = SortSet<u64, u64>;
+        S x, y, r1, r2;
+        x.k = work[0];
+        x.v0 = work[1];
+        y.k = work[2];
+        y.v0 = work[3];
+        rc = sort_two(x, y, 2 * bn, &r1);
+        if (rc == TM_OK) {
+            const S& o1 = r1.k == x.k ? y : x;
+            S in2, spare2;
+            in2.k = r1.v0;
+            in2.v0 = r1.k;
+            spare2.k = o1.k;
+            spare2.v0 = o1.v0;
+            rc = sort_two(in2, spare2, D.bt, &r2);
+        }
+        if (rc == TM_OK)
+            hipLaunchKernelGGL(decode_split_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, (const u64*)r2.k,
+                               (const u64*)r2.v0, m, bn, esrc, edst, et, flags);
+    }
+    if (rc == TM_OK && hipGetLastError() != hipSuccess) rc = tm_fail(TM_EDEVICE, "graph: decode launch");
+    if (rc != TM_OK) {
+        release();
+        return bail(rc);
+    }
     D.src = esrc;
     D.dst = edst;
     D.t = et;
 
     // --- per-vertex lists ---------------------------------------------------
-    // dir 0: out-lists (key = source, neighbour = destination)
-    // dir 1: in-lists  (key = destination, neighbour = source)
-    // with one packed key per edge, the sorted keys stay for the fills and
-    // the other key buffer holds both 32-bit key buffers of the list sorts
-    const bool packed = one_key && bn > 0;
-    u64* kspare = kres == ka ? kb : ka;
-    uint32_t* k32a = reinterpret_cast<uint32_t*>(packed ? kspare : ka);
-    uint32_t* k32b = packed ? k32a + m : reinterpret_cast<uint32_t*>(kb);
-    int32_t* tpos[2];
-    for (int dir = 0; dir < 2; ++dir) {
-        const int32_t* key_by_eid = dir == 0 ? esrc : edst;
-        const int32_t* nbr_by_eid = dir == 0 ? edst : esrc;
-        int64_t* lt;
-        int32_t *leid, *lnbr, *lown, *off;
-        TM_TRY(arena_alloc(g->arena, &lt, m));
-        TM_TRY(arena_alloc(g->arena, &leid, m));
-        TM_TRY(arena_alloc(g->arena, &lnbr, m));
-        lown = nullptr;
-        if (m <= ((int64_t)1 << 28)) TM_TRY(arena_alloc(g->arena, &lown, m));
-        TM_TRY(arena_alloc(g->arena, &off, (size_t)n + 1));
-        TM_TRY(arena_alloc(g->arena, &tpos[dir], (size_t)m));
-        // T order: stable sort of the eids by the list owner
-        hipLaunchKernelGGL(iota_key_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, key_by_eid, m,
-                           k32a, va);
-        TM_HIP(hipGetLastError());
-        uint32_t *kr, *vr;
-        TM_TRY(radix_sort_pairs<uint32_t>(k32a, va, k32b, vb, m, 0, bn, &kr, &vr, flags + 1, st));
-        if (packed)
-            hipLaunchKernelGGL(fill_t_order_packed_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
-                               (const uint32_t*)vr, (const u64*)kres, bn, dir, m, lt, leid, lnbr, lown, tpos[dir]);
-        else
-            hipLaunchKernelGGL(fill_t_order_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
-                               (const uint32_t*)vr, (const uint32_t*)kr, (const int64_t*)et, nbr_by_eid, m, lt,
-                               leid, lnbr, lown, tpos[dir]);
-        TM_HIP(hipGetLastError());
-        hipLaunchKernelGGL(offsets_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
-                           (const uint32_t*)kr, m, n, off);
-        TM_HIP(hipGetLastError());
+    // dir 0: out-lists (owner = source, neighbour = destination)
+    // dir 1: in-lists  (owner = destination, neighbour = source)
+    // T order: the eids stably sorted by owner, carrying time, eid and
+    // neighbour, so that every list array comes out of the sort in place.
+    using L = SortSet<uint32_t, u64, uint32_t, uint32_t>;
+    L tmp;  // the other buffer of the list sorts
+    tmp.k = reinterpret_cast<uint32_t*>(work[0]);
+    tmp.v1 = reinterpret_cast<uint32_t*>(work[0]) + m;
+    tmp.v0 = work[1];
+    tmp.v2 = reinterpret_cast<uint32_t*>(work[2]);
+    uint32_t* nkeys_out = reinterpret_cast<uint32_t*>(work[2]) + m;  // N order: its sorted keys (unused)
+    const bool keep_own = m <= ((int64_t)1 << 28);
+    uint32_t* own[2] = {nullptr, nullptr};
+    if (!keep_own && dev_alloc((void**)&nbr_tmp, (size_t)m * sizeof(uint32_t), st) != hipSuccess)
+        rc = tm_fail(TM_ENOMEM, "graph: work arrays");
+    uint32_t* nbr_carried = keep_own ? reinterpret_cast<uint32_t*>(work[3]) : nbr_tmp;
+    int32_t* tpos[2] = {nullptr, nullptr};
+    for (int dir = 0; dir < 2 && rc == TM_OK; ++dir) {
+        int64_t* lt = nullptr;
+        int32_t *leid = nullptr, *lnbr = nullptr, *lown = nullptr, *off = nullptr;
+        rc = arena_alloc(g->arena, &lt, m);
+        if (rc == TM_OK) rc = arena_alloc(g->arena, &leid, m);
+        if (rc == TM_OK) rc = arena_alloc(g->arena, &lnbr, m);
+        if (rc == TM_OK && keep_own) rc = arena_alloc(g->arena, &lown, m);
+        if (rc == TM_OK) rc = arena_alloc(g->arena, &off, (size_t)n + 1);
+        if (rc == TM_OK) rc = arena_alloc(g->arena, &tpos[dir], (size_t)m);
+        if (rc != TM_OK) break;
+        own[dir] = keep_own ? reinterpret_cast<uint32_t*>(lown) : reinterpret_cast<uint32_t*>(work[3]) + dir * m;
+        L in, out;
+        in.k = reinterpret_cast<uint32_t*>(dir == 0 ? esrc : edst);
+        in.v0 = reinterpret_cast<u64*>(et);
+        in.v2 = reinterpret_cast<uint32_t*>(dir == 0 ? edst : esrc);
+        out.k = own[dir];
+        out.v0 = reinterpret_cast<u64*>(lt);
+        out.v1 = reinterpret_cast<uint32_t*>(leid);
+        out.v2 = reinterpret_cast<uint32_t*>(lnbr);
+        rc = sort_into(in, out, tmp, m, 0, bn, 2 /* eids: 0, 1, ... */, flags + 1, st);
+        if (rc != TM_OK) break;
+        hipLaunchKernelGGL(offsets_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, (const uint32_t*)own[dir], m, n,
+                           off);
+        hipLaunchKernelGGL(tpos_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, (const int32_t*)leid, m, tpos[dir]);
+        if (hipGetLastError() != hipSuccess) rc = tm_fail(TM_EDEVICE, "graph: list launch");
         D.off[dir] = off;
         D.tpos[dir] = tpos[dir];
         D.lt[dir] = lt;
@@ -392,46 +373,43 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
         D.lown[dir] = lown;
         D.lnbr[dir] = lnbr;
     }
-    // N order of dir d: the T order of the other direction (sorted by the
-    // neighbour, then time) stably re-sorted by this direction's owner.
-    for (int dir = 0; dir < 2; ++dir) {
+    // N order of dir d: the T order of the other direction (sorted by this
+    // direction's neighbour, then time) stably re-sorted by this direction's
+    // owner, carrying time, eid and neighbour.
+    for (int dir = 0; dir < 2 && rc == TM_OK; ++dir) {
         const int other = 1 - dir;
-        const int32_t* nbr_by_eid = dir == 0 ? edst : esrc;
-        u64* nkey;
-        int32_t *nxref, *neid;
-        TM_TRY(arena_alloc(g->arena, &nkey, m));
-        TM_TRY(arena_alloc(g->arena, &nxref, m));
-        TM_TRY(arena_alloc(g->arena, &neid, m));
-        // keys: the owner of each entry of the other direction's T order,
-        // which is that entry's neighbour there
-        hipLaunchKernelGGL(copy_pair_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
-                           D.lnbr[other], D.leid[other], m, k32a, va);
-        TM_HIP(hipGetLastError());
-        uint32_t *kr, *vr;
-        TM_TRY(radix_sort_pairs<uint32_t>(k32a, va, k32b, vb, m, 0, bn, &kr, &vr, flags + 1, st));
-        if (packed)
-            hipLaunchKernelGGL(fill_n_order_packed_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
-                               (const uint32_t*)vr, (const u64*)kres, bn, dir, (const int32_t*)tpos[dir], m, D.bt,
-                               nkey, nxref, neid);
-        else
-            hipLaunchKernelGGL(fill_n_order_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
-                               (const uint32_t*)vr, (const int64_t*)et, nbr_by_eid,
-                               (const int32_t*)tpos[dir], m, D.bt, nkey, nxref, neid);
-        TM_HIP(hipGetLastError());
+        u64* nkey = nullptr;
+        int32_t *nxref = nullptr, *neid = nullptr;
+        rc = arena_alloc(g->arena, &nkey, m);
+        if (rc == TM_OK) rc = arena_alloc(g->arena, &nxref, m);
+        if (rc == TM_OK) rc = arena_alloc(g->arena, &neid, m);
+        if (rc != TM_OK) break;
+        L in, out;
+        in.k = reinterpret_cast<uint32_t*>(const_cast<int32_t*>(D.lnbr[other]));
+        in.v0 = reinterpret_cast<u64*>(const_cast<int64_t*>(D.lt[other]));
+        in.v1 = reinterpret_cast<uint32_t*>(const_cast<int32_t*>(D.leid[other]));
+        in.v2 = own[other];
+        out.k = nkeys_out;
+        out.v0 = nkey;  // the time, until the fix below packs the neighbour in
+        out.v1 = reinterpret_cast<uint32_t*>(neid);
+        out.v2 = nbr_carried;
+        rc = sort_into(in, out, tmp, m, 0, bn, 0, flags + 1, st);
+        if (rc != TM_OK) break;
+        hipLaunchKernelGGL(n_order_fix_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, (const uint32_t*)nbr_carried,
+                           (const int32_t*)neid, (const int32_t*)tpos[dir], m, D.bt, nkey, nxref);
+        if (hipGetLastError() != hipSuccess) rc = tm_fail(TM_EDEVICE, "graph: list launch");
         D.nkey[dir] = nkey;
         D.nxref[dir] = nxref;
         D.neid[dir] = neid;
     }
-    TM_HIP(dev_free(ka, st));
-    TM_HIP(dev_free(kb, st));
-    TM_HIP(dev_free(va, st));
-    TM_HIP(dev_free(vb, st));
+    release();
+    if (rc != TM_OK) return bail(rc);
     timer.stop();
     TM_HIP(read_back({{hflags, flags, sizeof hflags}}, st));
     TM_HIP(dev_free(flags, st));
     TM_HIP(dev_free(tbounds, st));
     timer.finish();
     if (hflags[0] & kDup) return tm_fail(TM_EDUP, "graph: duplicate (u, v, t) tuple");
-    if (hflags[1]) return tm_fail(TM_EDEVICE, "graph: internal scan overflow");
+    if (hflags[1]) return tm_fail(TM_EDEVICE, "graph: internal sort error (look-back stalled)");
     return TM_OK;
 }

@@ -1562,6 +1562,7 @@ int sample_run(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, hipStrea
             return TM_OK;
         }
     }
+    if (hovf & kSortStall) return tm_fail(TM_EDEVICE, "sample: root sort look-back stalled");
     if (hovf & 2) return tm_fail(TM_EDEVICE, "sample: inconsistent weight tables");
     if (hovf || (h.flags & 1)) return tm_fail(TM_EOVERFLOW, "sample: a count reaches 2^128");
     out->acc2.lo = (u64)h.acc2;
@@ -1825,6 +1826,7 @@ int group_read(Group& G, const std::vector<int>& act, hipStream_t st, JobSums* o
     std::vector<Partial> hp(G.na);
     int hovf = 0;
     TM_HIP(read_back({{hp.data(), G.jparts, G.na * sizeof(Partial)}, {&hovf, G.ovf, sizeof(int)}}, st));
+    if (hovf & kSortStall) return tm_fail(TM_EDEVICE, "batch: root sort look-back stalled");
     if (hovf & 2) return tm_fail(TM_EDEVICE, "batch: inconsistent weight tables");
     for (int y = 0; y < G.na; ++y) {
         const Partial& h = hp[y];
@@ -2113,8 +2115,9 @@ int family_run(tm_weights* w, const HostPlan* plans, int n, u64 seed, u64 k, hip
         for (int f = 0; f < n && rc == TM_OK; ++f) {
             const Partial& h = hp[f];
             const int hovf = hov[0] | hov[1 + f];
-            if (hovf & 2) {
-                rc = tm_fail(TM_EDEVICE, "family: inconsistent weight tables");
+            if (hovf & (2 | kSortStall)) {
+                rc = tm_fail(TM_EDEVICE, (hovf & kSortStall) ? "family: root sort look-back stalled"
+                                                             : "family: inconsistent weight tables");
                 break;
             }
             JobSums x;
@@ -2192,8 +2195,7 @@ constexpr u64 kNoAllocMaxCount = (u64)1 << 21;                  // samples per c
 constexpr int kNoAllocMaxBlocks = (int)(kNoAllocMaxCount / kBlock);  // sampling grid bound
 constexpr size_t kNoAllocParts = (size_t)(kNoAllocMaxBlocks + 1) * sizeof(Partial);
 constexpr size_t kNoAllocKeys = kNoAllocMaxCount * sizeof(uint32_t);
-constexpr size_t kNoAllocHist =
-    ((kNoAllocMaxCount + kSortTile - 1) / kSortTile + 1) * (size_t)kRadixMax * sizeof(uint32_t);
+constexpr size_t kNoAllocHist = sort_scratch_bytes((int64_t)kNoAllocMaxCount);
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 constexpr size_t kScratchBytes = align256(kNoAllocParts) + 256 + 4 * align256(kNoAllocKeys) + align256(kNoAllocHist);
 
@@ -2312,6 +2314,7 @@ int sample_run_noalloc(tm_weights* w, u64 seed, u64 j0, u64 count, u64 k_total, 
     TM_HIP(hipMemcpyAsync(&h, parts + blocks, sizeof h, hipMemcpyDeviceToHost, st));
     TM_HIP(hipMemcpyAsync(&hovf, ovf, sizeof hovf, hipMemcpyDeviceToHost, st));
     TM_HIP(hipStreamSynchronize(st));
+    if (hovf & kSortStall) return tm_fail(TM_EDEVICE, "sample: root sort look-back stalled");
     if (hovf & 2) return tm_fail(TM_EDEVICE, "sample: inconsistent weight tables");
     if (hovf || (h.flags & 1)) return tm_fail(TM_EOVERFLOW, "sample: a count reaches 2^128");
     out->acc2.lo = (u64)h.acc2;

@@ -1,5 +1,5 @@
-// Scan of tile sums for the device-wide exclusive scan, and the per-digit row
-// scans of the radix sort (tm_primitives.h).
+// Scan of tile sums for the device-wide exclusive scan, and the digit starts
+// of the radix sort (tm_primitives.h).
 #include <algorithm>
 
 #include "tm_primitives.h"
@@ -30,39 +30,6 @@ __global__ void __launch_bounds__(kBlock) scan_single_kernel(u128* a, int64_t n,
     }
     if (threadIdx.x == 0) a[n] = tot;
     if (carry) atomicOr(ovf, 1);
-}
-
-// One block per digit; each lane owns a run of consecutive tiles.  Rows of
-// up to kRowLds tiles go through LDS, so that the row is read and written
-// with consecutive addresses.
-constexpr int kRowLds = 8192;
-
-__global__ void __launch_bounds__(kBlock) radix_rowscan_kernel(uint32_t* hist, int64_t ntiles, uint32_t* totals) {
-    __shared__ uint32_t wsum[kWaves];
-    __shared__ uint32_t buf[kRowLds];
-    uint32_t* row = hist + (int64_t)blockIdx.x * ntiles;
-    const bool staged = ntiles <= kRowLds;
-    uint32_t* r = staged ? buf : row;
-    if (staged) {
-        for (int64_t i = threadIdx.x; i < ntiles; i += kBlock) buf[i] = row[i];
-        __syncthreads();
-    }
-    const int64_t per = (ntiles + kBlock - 1) / kBlock;
-    const int64_t lo = (int64_t)threadIdx.x * per;
-    const int64_t hi = lo + per < ntiles ? lo + per : ntiles;
-    uint32_t s = 0;
-    for (int64_t i = lo; i < hi; ++i) s += r[i];
-    uint32_t run = block_excl_scan_256(s, wsum);
-    for (int64_t i = lo; i < hi; ++i) {
-        const uint32_t c = r[i];
-        r[i] = run;
-        run += c;
-    }
-    if (threadIdx.x == kBlock - 1) totals[blockIdx.x] = run;
-    if (staged) {
-        __syncthreads();
-        for (int64_t i = threadIdx.x; i < ntiles; i += kBlock) row[i] = buf[i];
-    }
 }
 
 }  // namespace
@@ -103,8 +70,11 @@ int scan_parts(u128* part, int64_t nb, int* ovf, hipStream_t st) {
     return device_exclusive_scan<u128>(ArrayReader128{part}, nb, part, ovf, st);
 }
 
-int radix_rowscan(uint32_t* hist, int64_t ntiles, uint32_t* totals, hipStream_t st, int ndig) {
-    hipLaunchKernelGGL(radix_rowscan_kernel, dim3((unsigned)ndig), dim3(kBlock), 0, st, hist, ntiles, totals);
-    TM_HIP(hipGetLastError());
-    return TM_OK;
+__global__ void __launch_bounds__(kBlock) sort_base_kernel(uint32_t* ghist, int npass) {
+    __shared__ uint32_t wsum[kWaves];
+    for (int p = 0; p < npass; ++p) {
+        uint32_t* h = ghist + p * kSortDigits;
+        const uint32_t v = h[threadIdx.x];
+        h[threadIdx.x] = block_excl_scan_256(v, wsum);
+    }
 }

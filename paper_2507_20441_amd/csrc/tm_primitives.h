@@ -3,18 +3,23 @@
 // the translation units that use them.
 #pragma once
 
+#include <algorithm>
+#include <type_traits>
+
 #include "tm_internal.h"
 
 constexpr int kScanItems = 8;                      // values per lane in a scan tile
 constexpr int kScanTile = kBlock * kScanItems;     // 2048
-constexpr int kSortItems = 8;                      // keys per lane in a sort tile
-constexpr int kSortTile = kBlock * kSortItems;     // 2048
-constexpr int kRadixMaxBits = 9;                   // sort digits: up to 9 bits, two per thread
-constexpr int kRadixMax = 1 << kRadixMaxBits;
+constexpr int kSortBits = 8;                       // sort digits: up to 8 bits, one per lane
+constexpr int kSortDigits = 1 << kSortBits;        // 256
+constexpr int kSortItems = 16;                     // keys per lane in a sort tile
+constexpr int kSortTile = kBlock * kSortItems;     // 4096
+constexpr int kSortMaxPasses = 8;
+static_assert(kSortDigits == kBlock, "one digit per lane of a block");
 
-// Radix passes over nb key bits (digits of at most kRadixMaxBits, split as
+// Radix passes over nb key bits (digits of at most kSortBits, split as
 // evenly as possible).
-inline int radix_passes(int nb) { return nb <= 0 ? 0 : (nb + kRadixMaxBits - 1) / kRadixMaxBits; }
+inline int radix_passes(int nb) { return nb <= 0 ? 0 : (nb + kSortBits - 1) / kSortBits; }
 
 // Clearing device words with a kernel rather than a memset node, so that the
 // same code can be captured into a HIP graph.
@@ -160,32 +165,6 @@ int device_exclusive_scan(F f, int64_t n, T* out, int* ovf, hipStream_t st) {
     return rc;
 }
 
-// ---------------------------------------------------------------------------
-// Stable LSD radix sort of (key, value) pairs (fewer than 2^32), digits of up
-// to 9 bits.
-// Per pass: tile histograms (digit-major), an exclusive scan of each digit's
-// row with the digit totals, then a scatter in which every wave ranks its
-// keys in input order with ballots and each digit's start is the scan of the
-// totals.
-// ---------------------------------------------------------------------------
-template <typename K>
-__global__ void __launch_bounds__(kBlock)
-radix_hist_kernel(const K* keys, int64_t n, int shift, int bits, uint32_t* hist, int64_t ntiles) {
-    __shared__ uint32_t h[kRadixMax];
-    h[threadIdx.x] = 0;
-    h[threadIdx.x + kBlock] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    const K mask = (K)((1u << bits) - 1);
-#pragma unroll
-    for (int k = 0; k < kSortItems; ++k) {
-        const int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
-        if (i < n) atomicAdd(&h[(uint32_t)((keys[i] >> shift) & mask)], 1u);
-    }
-    __syncthreads();
-    for (int d = threadIdx.x; d < (1 << bits); d += kBlock) hist[(int64_t)d * ntiles + blockIdx.x] = h[d];
-}
-
 // Exclusive scan of v over the block's 256 threads (thread t holds entry t):
 // shuffles inside each wave, then the wave totals through LDS.
 __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t* wsum) {
@@ -205,44 +184,163 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t* ws
     return before + inc - v;
 }
 
-// Per digit d < ndig: the exclusive scan of the digit's row of tile counts
-// (hist[d * ntiles + tile]), in place, and the row's total in totals[d].
-int radix_rowscan(uint32_t* hist, int64_t ntiles, uint32_t* totals, hipStream_t st, int ndig);
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort of keys that carry up to three value arrays
+// (structure of arrays), one kernel per digit of up to 8 bits:
+//  * sort_hist_kernel counts the digits of every pass in one read of the
+//    keys, and sort_base_kernel turns those counts into each digit's first
+//    position;
+//  * sort_pass_kernel, once per pass: a block takes the next tile by ticket
+//    (so a tile only ever waits on tiles that are already running), ranks
+//    its keys by digit with wave ballots, publishes its digit counts, and
+//    finds where its run of each digit starts by adding up the counts that
+//    the tiles before it published, back to a tile that has published its
+//    inclusive total (decoupled look-back).  Keys and values then go out
+//    through LDS, each digit's run of the tile to consecutive addresses.
+// A status word holds a value (bits 0-31), a flag (bits 32-33: 1 the tile's
+// own count, 2 the total through the tile) and the pass's tag (bits 40-47).
+// The words are cleared once per sort, so a word left by an earlier pass
+// reads as not yet published.  Waits are bounded: a lane that has polled
+// kSortMaxSpins times sets kSortStall in the caller's error word and goes on
+// (the order is then wrong, and the caller reports the error).
+// ---------------------------------------------------------------------------
+struct SortNone {};  // an absent value array
+constexpr int kSortStall = 4;
+constexpr uint32_t kSortMaxSpins = 1u << 20;
+constexpr size_t kSortHeadBytes =
+    ((size_t)kSortMaxPasses * kSortDigits * sizeof(uint32_t) + kSortMaxPasses * sizeof(uint32_t) + 255) &
+    ~(size_t)255;
+
+// Scratch of a sort of n keys: per-pass digit counts and tickets, then one
+// status word per tile and digit.
+constexpr size_t sort_scratch_bytes(int64_t n) {
+    return kSortHeadBytes + (size_t)(n > 0 ? (n + kSortTile - 1) / kSortTile : 0) * kSortDigits * sizeof(u64);
+}
+
+struct SortPlan {
+    int npass;
+    int shift[kSortMaxPasses];
+    int bits[kSortMaxPasses];
+};
+
+// Digits over bits [lo_bit, nbits), as even as possible; no pass when the
+// range is empty.
+inline SortPlan sort_plan(int lo_bit, int nbits) {
+    SortPlan P{};
+    P.npass = radix_passes(nbits - lo_bit);
+    int shift = lo_bit;
+    for (int p = 0; p < P.npass; ++p) {
+        const int b = (nbits - shift + (P.npass - p) - 1) / (P.npass - p);
+        P.shift[p] = shift;
+        P.bits[p] = b;
+        shift += b;
+    }
+    return P;
+}
+
+template <typename V>
+struct SortSize {
+    static constexpr size_t value = sizeof(V);
+};
+template <>
+struct SortSize<SortNone> {
+    static constexpr size_t value = 0;
+};
+
+struct SortIO {
+    const void* in[4];  // keys, then the value arrays
+    void* out[4];
+};
 
 template <typename K>
 __global__ void __launch_bounds__(kBlock)
-radix_scatter_kernel(const K* keys, const uint32_t* vals, K* okeys, uint32_t* ovals, int64_t n,
-                     int shift, int bits, const uint32_t* offs, const uint32_t* totals, int64_t ntiles, int iota) {
-    static_assert(2 * kBlock == kRadixMax, "two digits per thread");
-    __shared__ uint32_t cnt[kWaves][kRadixMax];
-    __shared__ uint32_t dstart[kRadixMax];  // tile-local start of each digit's run
-    __shared__ uint32_t gbase[kRadixMax];   // global start of this tile's run of each digit
-    __shared__ K skey[kSortTile];
-    __shared__ uint32_t sval[kSortTile];
-    __shared__ uint32_t wsum[kWaves];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int w = 0; w < kWaves; ++w) {
-        cnt[w][threadIdx.x] = 0;
-        cnt[w][threadIdx.x + kBlock] = 0;
+sort_hist_kernel(const K* __restrict__ keys, int64_t n, SortPlan P, uint32_t* __restrict__ ghist) {
+    __shared__ uint32_t h[kSortMaxPasses][kSortDigits];
+#pragma unroll
+    for (int p = 0; p < kSortMaxPasses; ++p) h[p][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        const K k = keys[i];
+        for (int p = 0; p < P.npass; ++p)
+            atomicAdd(&h[p][(uint32_t)(k >> P.shift[p]) & ((1u << P.bits[p]) - 1u)], 1u);
     }
     __syncthreads();
-    const K mask = (K)((1u << bits) - 1);
-    const u64 lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    // wave w owns tile positions [w*64*kSortItems, (w+1)*64*kSortItems), in
-    // rounds of 64 consecutive keys: the wave sees its keys in input order
-    const int64_t tbase = (int64_t)blockIdx.x * kSortTile;
+    for (int p = 0; p < P.npass; ++p) {
+        const uint32_t c = h[p][threadIdx.x];
+        if (c) atomicAdd(&ghist[p * kSortDigits + threadIdx.x], c);
+    }
+}
+
+// Each pass's digit counts, in place, into exclusive digit starts.
+__global__ void __launch_bounds__(kBlock) sort_base_kernel(uint32_t* ghist, int npass);
+
+// One value array of a tile through LDS to the positions of its keys.
+template <typename V>
+__device__ __forceinline__ void sort_move_values(const void* vin, void* vout, bool iota, int64_t wbase, int lane,
+                                                 int64_t n, const uint32_t (&lp)[kSortItems], unsigned char* sbuf,
+                                                 const uint8_t* sdig, const uint32_t* gofs, int tn) {
+    if constexpr (!std::is_same<V, SortNone>::value) {
+        V* sv = reinterpret_cast<V*>(sbuf);
+        const V* in = static_cast<const V*>(vin);
+        V* out = static_cast<V*>(vout);
+        V x[kSortItems];
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            const int64_t i = wbase + (int64_t)k * 64 + lane;
+            x[k] = i < n ? (iota ? (V)i : in[i]) : (V)0;
+        }
+        __syncthreads();  // the buffer's previous contents have gone out
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            const int64_t i = wbase + (int64_t)k * 64 + lane;
+            if (i < n) sv[lp[k]] = x[k];
+        }
+        __syncthreads();
+        for (int p = threadIdx.x; p < tn; p += kBlock) {
+            const uint32_t g = gofs[sdig[p]] + (uint32_t)p;
+            if ((int64_t)g < n) out[g] = sv[p];
+        }
+    }
+}
+
+template <typename K, typename V0, typename V1, typename V2>
+__global__ void __launch_bounds__(kBlock)
+sort_pass_kernel(SortIO io, int64_t n, int shift, int bits, uint32_t tag, int iota, const uint32_t* __restrict__ starts,
+                 uint32_t* __restrict__ ticket, u64* __restrict__ status, int* __restrict__ err) {
+    constexpr size_t kElt = std::max(std::max(sizeof(K), SortSize<V0>::value),
+                                     std::max(SortSize<V1>::value, SortSize<V2>::value));
+    __shared__ __align__(16) unsigned char sbuf[kElt * kSortTile];
+    __shared__ uint8_t sdig[kSortTile];
+    __shared__ uint32_t cnt[kWaves][kSortDigits];
+    __shared__ uint32_t gofs[kSortDigits];  // per digit: its global position minus its tile-local one
+    __shared__ uint32_t wsum[kWaves];
+    __shared__ uint32_t s_tile;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) cnt[w][threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const int64_t tbase = (int64_t)tile * kSortTile;
+    // wave w owns tile positions [w 64 kSortItems, (w + 1) 64 kSortItems), in
+    // rounds of 64 consecutive keys: the wave ranks its keys in input order
     const int64_t wbase = tbase + (int64_t)wave * 64 * kSortItems;
+    const uint32_t mask = (1u << bits) - 1u;
+    const u64 lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const K* keys = static_cast<const K*>(io.in[0]);
     K key[kSortItems];
-    uint32_t val[kSortItems];
-    uint32_t dig[kSortItems];
-    uint32_t rank[kSortItems];
+    uint32_t dig[kSortItems], lp[kSortItems];
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t i = wbase + (int64_t)k * 64 + lane;
+        key[k] = i < n ? keys[i] : (K)0;
+    }
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t i = wbase + (int64_t)k * 64 + lane;
         const bool ok = i < n;
-        key[k] = ok ? keys[i] : (K)0;
-        val[k] = ok ? (iota ? (uint32_t)i : vals[i]) : 0u;
-        const uint32_t d = ok ? (uint32_t)((key[k] >> shift) & mask) : 0u;
+        const uint32_t d = ok ? ((uint32_t)(key[k] >> shift) & mask) : 0u;
         dig[k] = d;
         u64 peers = __ballot(ok);
         for (int b = 0; b < bits; ++b) {
@@ -250,109 +348,187 @@ radix_scatter_kernel(const K* keys, const uint32_t* vals, K* okeys, uint32_t* ov
             peers &= ((d >> b) & 1u) ? bal : ~bal;
         }
         const uint32_t before = cnt[wave][d];
-        rank[k] = before + (uint32_t)__popcll(peers & lt_mask);
+        lp[k] = before + (uint32_t)__popcll(peers & lt_mask);
         // the lowest lane of each digit group advances the wave's counter
         if (ok && (peers & lt_mask) == 0) cnt[wave][d] = before + (uint32_t)__popcll(peers);
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    // per digit pair (d0, d1 = 2t, 2t + 1 for thread t, so that scans over the
-    // threads run in digit order): the tile's counts, their exclusive scan
-    // over digits (the tile-local start), and each wave's start inside it
-    const int ndig = 1 << bits;
-    const uint32_t d0 = 2 * threadIdx.x, d1 = d0 + 1;
-    uint32_t t0 = 0, t1 = 0;
-    for (int w = 0; w < kWaves; ++w) {
-        t0 += cnt[w][d0];
-        t1 += cnt[w][d1];
-    }
-    // global start of this tile's run of a digit: the digit's start (scan of
-    // the digit totals) plus the earlier tiles' counts of it
-    const uint32_t g0 = (int)d0 < ndig ? totals[d0] : 0u, g1 = (int)d1 < ndig ? totals[d1] : 0u;
-    const uint32_t gb = block_excl_scan_256(g0 + g1, wsum);
-    if ((int)d0 < ndig) gbase[d0] = gb + offs[(int64_t)d0 * ntiles + blockIdx.x];
-    if ((int)d1 < ndig) gbase[d1] = gb + g0 + offs[(int64_t)d1 * ntiles + blockIdx.x];
-    const uint32_t local = block_excl_scan_256(t0 + t1, wsum);
+    // lane d: the tile's count of digit d, published at once (the first tile
+    // publishes it as its inclusive total)
+    const uint32_t d = threadIdx.x;
+    uint32_t tcount = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) tcount += cnt[w][d];
+    u64* my = status + (size_t)tile * kSortDigits + d;
+    const u64 tagw = (u64)tag << 40;
+    if (d <= mask)
+        __hip_atomic_store(my, tagw | ((u64)(tile == 0 ? 2 : 1) << 32) | tcount, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    // tile-local starts: of each digit, and of each wave's keys inside it
+    const uint32_t dstart = block_excl_scan_256(tcount, wsum);
     {
-        uint32_t run0 = local, run1 = local + t0;  // exclusive
+        uint32_t run = dstart;
+#pragma unroll
         for (int w = 0; w < kWaves; ++w) {
-            const uint32_t c0 = cnt[w][d0], c1 = cnt[w][d1];
-            cnt[w][d0] = run0;
-            cnt[w][d1] = run1;
-            run0 += c0;
-            run1 += c1;
+            const uint32_t c = cnt[w][d];
+            cnt[w][d] = run;
+            run += c;
         }
     }
     __syncthreads();
-    dstart[d0] = cnt[0][d0];
-    dstart[d1] = cnt[0][d1];
-    // keys to their tile-local sorted places
+    K* skey = reinterpret_cast<K*>(sbuf);
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t i = wbase + (int64_t)k * 64 + lane;
         if (i < n) {
-            const uint32_t lp = cnt[wave][dig[k]] + rank[k];
-            skey[lp] = key[k];
-            sval[lp] = val[k];
+            const uint32_t p = cnt[wave][dig[k]] + lp[k];
+            lp[k] = p;
+            skey[p] = key[k];
+            sdig[p] = (uint8_t)dig[k];
         }
+    }
+    // look-back: the digit's count over all earlier tiles
+    if (d <= mask) {
+        uint32_t excl = 0;
+        if (tile > 0) {
+            int64_t j = (int64_t)tile - 1;
+            uint32_t spins = 0;
+            while (true) {
+                const u64 s = __hip_atomic_load(status + (size_t)j * kSortDigits + d, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t f = (uint32_t)(s >> 32) & 3u;
+                if ((uint32_t)(s >> 40) == tag && f != 0) {
+                    excl += (uint32_t)s;
+                    if (f == 2 || j == 0) break;
+                    --j;
+                } else if (++spins >= kSortMaxSpins) {
+                    atomicOr(err, kSortStall);
+                    break;
+                } else {
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            __hip_atomic_store(my, tagw | ((u64)2 << 32) | (u64)(excl + tcount), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        gofs[d] = starts[d] + excl - dstart;
     }
     __syncthreads();
-    // out in tile-local order: each digit's run goes to consecutive addresses
-    const int tn = (int)((n - tbase) < kSortTile ? (n - tbase) : kSortTile);
+    const int tn = (int)(n - tbase < kSortTile ? n - tbase : kSortTile);
+    K* okeys = static_cast<K*>(io.out[0]);
+    // (positions are below n whenever the digit counts hold; the test keeps
+    // a broken invariant from writing outside the output)
     for (int p = threadIdx.x; p < tn; p += kBlock) {
-        const K kk = skey[p];
-        const uint32_t dd = (uint32_t)((kk >> shift) & mask);
-        const uint32_t gpos = gbase[dd] + ((uint32_t)p - dstart[dd]);
-        okeys[gpos] = kk;
-        ovals[gpos] = sval[p];
+        const uint32_t g = gofs[sdig[p]] + (uint32_t)p;
+        if ((int64_t)g < n) okeys[g] = skey[p];
     }
+    sort_move_values<V0>(io.in[1], io.out[1], iota & 1, wbase, lane, n, lp, sbuf, sdig, gofs, tn);
+    sort_move_values<V1>(io.in[2], io.out[2], iota & 2, wbase, lane, n, lp, sbuf, sdig, gofs, tn);
+    sort_move_values<V2>(io.in[3], io.out[3], iota & 4, wbase, lane, n, lp, sbuf, sdig, gofs, tn);
 }
 
-struct HistReader {
-    const uint32_t* h;
-    __device__ uint32_t operator()(int64_t i) const { return h[i]; }
+// A key array and up to three value arrays (null where a value is absent).
+template <typename K, typename V0 = SortNone, typename V1 = SortNone, typename V2 = SortNone>
+struct SortSet {
+    K* k = nullptr;
+    V0* v0 = nullptr;
+    V1* v1 = nullptr;
+    V2* v2 = nullptr;
 };
 
-// Sorts (keys, vals) by bits [lo_bit, nbits) of the key, stably.  Buffers
-// ping-pong between (keys, vals) and (tkeys, tvals); on return *k_out / *v_out
-// point to whichever pair holds the result.  iota_vals: vals holds nothing
-// yet and stands for 0 .. n-1 (the first pass makes them).
-template <typename K>
-int radix_sort_pairs(K* keys, uint32_t* vals, K* tkeys, uint32_t* tvals, int64_t n, int lo_bit,
-                     int nbits, K** k_out, uint32_t** v_out, int* ovf, hipStream_t st, bool iota_vals = false,
-                     uint32_t* hist_ext = nullptr) {
-    K* ka = keys;
-    uint32_t* va = vals;
-    K* kb = tkeys;
-    uint32_t* vb = tvals;
-    if (n > 1 && nbits > lo_bit) {
-        const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
-        const int npass = radix_passes(nbits - lo_bit);
-        const int64_t maxdig = (int64_t)1 << ((nbits - lo_bit + npass - 1) / npass);
-        // the digit histograms: (ntiles + 1) * maxdig words, from the caller
-        // (hist_ext, which must hold that many) or allocated here
-        uint32_t* hist = hist_ext;
-        if (!hist) TM_HIP(dev_alloc((void**)&hist, (ntiles * maxdig + maxdig) * sizeof(uint32_t), st));
-        uint32_t* totals = hist + ntiles * maxdig;
-        int shift = lo_bit;
-        for (int p = 0; p < npass; ++p) {
-            const int bits = (nbits - shift + (npass - p) - 1) / (npass - p);
-            hipLaunchKernelGGL((radix_hist_kernel<K>), dim3((unsigned)ntiles), dim3(kBlock), 0, st,
-                               (const K*)ka, n, shift, bits, hist, ntiles);
-            TM_HIP(hipGetLastError());
-            TM_TRY(radix_rowscan(hist, ntiles, totals, st, 1 << bits));
-            hipLaunchKernelGGL((radix_scatter_kernel<K>), dim3((unsigned)ntiles), dim3(kBlock), 0,
-                               st, (const K*)ka, (const uint32_t*)va, kb, vb, n, shift, bits,
-                               (const uint32_t*)hist, (const uint32_t*)totals, ntiles, (iota_vals && p == 0) ? 1 : 0);
-            TM_HIP(hipGetLastError());
-            K* tk = ka; ka = kb; kb = tk;
-            uint32_t* tv = va; va = vb; vb = tv;
-            shift += bits;
-        }
-        if (!hist_ext) TM_HIP(dev_free(hist, st));
+// Runs the plan's passes: pass p reads `in` (p = 0) or the previous pass's
+// output, and writes bufs[p & 1]; bufs[0] must not be `in` (bufs[1] may be:
+// the first pass has consumed it before the second writes).  Returns the
+// index of the buffer that holds the result.  iota: bit j set, value array j
+// holds nothing yet and stands for 0, 1, ..., n - 1.  scratch: at least
+// sort_scratch_bytes(n) bytes, or null to allocate it here.
+template <typename K, typename V0, typename V1, typename V2>
+int sort_run(const SortSet<K, V0, V1, V2>& in, const SortSet<K, V0, V1, V2> (&bufs)[2], int64_t n,
+             const SortPlan& P, int iota, int* err, hipStream_t st, void* scratch, int* result) {
+    *result = (P.npass - 1) & 1;
+    if (n <= 0 || P.npass <= 0) return TM_OK;
+    if (bufs[0].k == in.k) return tm_fail(TM_EDEVICE, "sort: the first pass would overwrite its input");
+    const size_t bytes = sort_scratch_bytes(n);
+    unsigned char* scr = static_cast<unsigned char*>(scratch);
+    if (!scr) TM_HIP(dev_alloc((void**)&scr, bytes, st));
+    uint32_t* ghist = reinterpret_cast<uint32_t*>(scr);
+    uint32_t* tickets = ghist + kSortMaxPasses * kSortDigits;
+    u64* status = reinterpret_cast<u64*>(scr + kSortHeadBytes);
+    const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+    int rc = fill_u32(scr, (int64_t)(bytes / sizeof(uint32_t)), 0u, st);
+    if (rc == TM_OK) {
+        const unsigned hb = (unsigned)std::min<int64_t>(ntiles, 1024);
+        hipLaunchKernelGGL((sort_hist_kernel<K>), dim3(hb), dim3(kBlock), 0, st, (const K*)in.k, n, P, ghist);
+        if (hipGetLastError() != hipSuccess) rc = tm_fail(TM_EDEVICE, "sort: histogram launch");
     }
-    if (iota_vals && !(n > 1 && nbits > lo_bit)) TM_TRY(fill_iota_u32(va, n, st));  // no pass ran
-    *k_out = ka;
-    *v_out = va;
+    if (rc == TM_OK) {
+        hipLaunchKernelGGL(sort_base_kernel, dim3(1), dim3(kBlock), 0, st, ghist, P.npass);
+        if (hipGetLastError() != hipSuccess) rc = tm_fail(TM_EDEVICE, "sort: digit start launch");
+    }
+    for (int p = 0; p < P.npass && rc == TM_OK; ++p) {
+        const SortSet<K, V0, V1, V2>& src = p == 0 ? in : bufs[(p - 1) & 1];
+        const SortSet<K, V0, V1, V2>& dst = bufs[p & 1];
+        SortIO io{{src.k, src.v0, src.v1, src.v2}, {dst.k, dst.v0, dst.v1, dst.v2}};
+        hipLaunchKernelGGL((sort_pass_kernel<K, V0, V1, V2>), dim3((unsigned)ntiles), dim3(kBlock), 0, st, io, n,
+                           P.shift[p], P.bits[p], (uint32_t)(p + 1), p == 0 ? iota : 0,
+                           (const uint32_t*)(ghist + p * kSortDigits), tickets + p, status, err);
+        if (hipGetLastError() != hipSuccess) rc = tm_fail(TM_EDEVICE, "sort: pass launch");
+    }
+    if (!scratch) {
+        const hipError_t e = dev_free(scr, st);
+        if (rc == TM_OK && e != hipSuccess) rc = tm_fail(TM_EDEVICE, "sort: free");
+    }
+    return rc;
+}
+
+// Sorts `in` by bits [lo_bit, nbits) of its keys into `out`, stably, with
+// `tmp` as the other buffer of the passes (`in` is left as it was unless
+// tmp is `in`, which is allowed only when an odd number of passes runs).  At
+// least one pass runs: a stable copy when no bit is sorted.
+template <typename K, typename V0, typename V1, typename V2>
+int sort_into(const SortSet<K, V0, V1, V2>& in, const SortSet<K, V0, V1, V2>& out,
+              const SortSet<K, V0, V1, V2>& tmp, int64_t n, int lo_bit, int nbits, int iota, int* err,
+              hipStream_t st) {
+    SortPlan P = sort_plan(lo_bit, nbits);
+    if (P.npass == 0) {
+        P.npass = 1;
+        P.shift[0] = 0;
+        P.bits[0] = 0;
+    }
+    const SortSet<K, V0, V1, V2> bufs[2] = {(P.npass & 1) ? out : tmp, (P.npass & 1) ? tmp : out};
+    int res = 0;
+    return sort_run(in, bufs, n, P, iota, err, st, nullptr, &res);
+}
+
+// Sorts (keys, vals) by bits [lo_bit, nbits) of the key, stably.  Buffers
+// ping-pong between (keys, vals) and (tkeys, tvals); on return *k_out /
+// *v_out point to whichever pair holds the result (the tkeys pair after an
+// odd number of passes).  iota_vals: vals holds nothing yet and stands for
+// 0 .. n-1.  scratch_ext: sort_scratch_bytes(n) bytes from the caller, or
+// null.  err: bit kSortStall is set if a look-back wait ran out.
+template <typename K>
+int radix_sort_pairs(K* keys, uint32_t* vals, K* tkeys, uint32_t* tvals, int64_t n, int lo_bit, int nbits,
+                     K** k_out, uint32_t** v_out, int* err, hipStream_t st, bool iota_vals = false,
+                     void* scratch_ext = nullptr) {
+    *k_out = keys;
+    *v_out = vals;
+    if (n > 1 && nbits > lo_bit) {
+        using S = SortSet<K, uint32_t>;
+        S in, b0, b1;
+        in.k = keys;
+        in.v0 = vals;
+        b0.k = tkeys;
+        b0.v0 = tvals;
+        b1 = in;
+        const S bufs[2] = {b0, b1};
+        const SortPlan P = sort_plan(lo_bit, nbits);
+        int res = 0;
+        TM_TRY(sort_run(in, bufs, n, P, iota_vals ? 1 : 0, err, st, scratch_ext, &res));
+        *k_out = bufs[res].k;
+        *v_out = bufs[res].v0;
+    } else if (iota_vals) {
+        TM_TRY(fill_iota_u32(vals, n, st));  // no pass ran
+    }
     return TM_OK;
 }

@@ -20,7 +20,10 @@ TM_EADMIT, TM_EAGAIN, TM_ECANCELED = -8, -9, -10
 TM_PTR_HOST, TM_PTR_DEVICE = 0, 1
 TM_F_W_ZERO, TM_F_SQ_SATURATED, TM_F_WIDE = 1, 2, 4
 TM_C_EXCLUDE, TM_C_WINDOWS, TM_C_ALL = 1, 2, 3
-ARRAYS = dict(src=0, dst=1, t=2, out_off=3, in_off=4, out_eid=5, in_eid=6, outn_eid=7, inn_eid=8)
+ARRAYS = dict(src=0, dst=1, t=2, out_off=3, in_off=4, out_eid=5, in_eid=6, outn_eid=7, inn_eid=8,
+              out_t=9, in_t=10, out_nbr=11, in_nbr=12, out_pos=13, in_pos=14, outn_key=15, inn_key=16,
+              outn_pos=17, inn_pos=18)
+ARRAY_DTYPES = dict(t="int64", out_t="int64", in_t="int64", outn_key="uint64", inn_key="uint64")
 
 
 class U128(C.Structure):
@@ -336,7 +339,7 @@ class Graph:
     def export(self, name):
         which = ARRAYS[name]
         size = self.n + 1 if name.endswith("_off") else self.m
-        out = np.empty(size, np.int64 if name == "t" else np.int32)
+        out = np.empty(size, np.dtype(ARRAY_DTYPES.get(name, "int32")))
         _check(lib().tm_graph_export(self.h, which, out.ctypes.data_as(C.c_void_p), _stream()),
                "graph_export")
         return out

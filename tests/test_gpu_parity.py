@@ -49,28 +49,46 @@ def rec_equal(a, b):
 # ---------------------------------------------------------------------------
 # CSR build
 # ---------------------------------------------------------------------------
+# the last two: 2 bn + bt > 64 (bn the vertex-id bits, bt the time bits), so
+# the canonical order takes two sorts (by (u, v), then by time), with an odd
+# and an even number of digit passes in the first
 @pytest.mark.parametrize("m,seed,n,span", [(1, 1, 2, 10), (777, 2, 40, 300), (5000, 3, 300, 20000),
-                                           (40000, 4, 2000, 10**6)])
+                                           (40000, 4, 2000, 10**6), (30000, 6, 600_000, 2**30),
+                                           (30000, 7, 3_000_000, 2**35)])
 def test_csr_matches_oracle(T, m, seed, n, span):
-    say("csr", m, seed)
+    say("csr", m, seed, n, span)
     g = W.small_graph(m, seed, n=n, span=span)
     og, tg = pair(T, g)
     s, d, t = og.edges()
     assert (tg.export("src") == s).all() and (tg.export("dst") == d).all()
     assert (tg.export("t") == t).all()
-    assert tg.info()["t_shift"] == og.shift
-    for name, direction, nbr in (("out", +1, d), ("in", -1, s)):
+    info = tg.info()
+    assert info["t_shift"] == og.shift
+    bt = max(1, int(info["t_span"]).bit_length())
+    for name, direction, own, nbr in (("out", +1, s, d), ("in", -1, d, s)):
         off = tg.export(f"{name}_off")
         teid = tg.export(f"{name}_eid")
         neid = tg.export(f"{name}n_eid")
         assert off[0] == 0 and off[-1] == g.m
-        for v in range(g.n):
-            want = og.vertex_list(v, direction)
+        # per-vertex lists: the oracle's, for every vertex that has edges
+        # (offsets are checked for all vertices through the degrees)
+        deg = np.bincount(own, minlength=g.n)
+        assert (np.diff(off) == deg).all(), name
+        for v in np.nonzero(deg)[0]:
+            want = og.vertex_list(int(v), direction)
             got = teid[off[v]:off[v + 1]]
             assert (got == want).all(), (name, v)
             # N order: the same edges by (neighbour, eid)
             order = np.lexsort((want, nbr[want]))
             assert (neid[off[v]:off[v + 1]] == want[order]).all(), (name, v)
+        # the arrays carried along with the eids
+        assert (tg.export(f"{name}_t") == t[teid]).all(), name
+        assert (tg.export(f"{name}_nbr") == nbr[teid]).all(), name
+        pos = tg.export(f"{name}_pos")
+        assert (pos[teid] == np.arange(g.m)).all(), name
+        key = tg.export(f"{name}n_key")
+        assert (key == ((nbr[neid].astype(np.uint64) << np.uint64(bt)) | t[neid].astype(np.uint64))).all(), name
+        assert (tg.export(f"{name}n_pos") == pos[neid]).all(), name
 
 
 def test_graph_from_device_tensors(T):
