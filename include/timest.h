@@ -240,7 +240,11 @@ int tm_weights_create_ex(tm_graph* g, const tm_motif* mo, const tm_tree* tr, uin
 void tm_weights_destroy(tm_weights* w);
 
 /* W, the interval count q, whether 128-bit weights were needed, the device
- * bytes held and the tree used; any output pointer may be NULL. */
+ * bytes held and the tree used; any output pointer may be NULL.  A set whose
+ * 64-bit build overflowed only in the center's totals along eid order is
+ * widened in place: its center and interval tables become 128-bit, its list
+ * tables stay 64-bit (exact), and device_bytes is then below the 128-bit
+ * footprint of tm_weights_footprint. */
 int tm_weights_info(const tm_weights* w, tm_u128* W, int64_t* q, int32_t* wide,
                     uint64_t* device_bytes, tm_tree* tree);
 
@@ -417,7 +421,8 @@ int tm_choose_tree(tm_graph* g, const tm_motif* mo, int n_c, void* stream, tm_tr
 
 /* Device bytes the weight tables of (g, mo, tr) take in 64-bit (wide = 0)
  * or 128-bit (wide = 1) form: what tm_weights_info reports as device_bytes
- * after tm_weights_create builds them in that form, the kept child windows
+ * after tm_weights_create builds them in that form (for a widened set, an
+ * upper bound: see tm_weights_info), the kept child windows
  * included (kept when they total at most 32 GiB; a server builds its sets
  * without them).  tr may be NULL (the default tree).  Errors: TM_EINVAL. */
 int tm_weights_footprint(const tm_graph* g, const tm_motif* mo, const tm_tree* tr, int32_t wide,

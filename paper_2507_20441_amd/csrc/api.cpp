@@ -713,7 +713,9 @@ extern "C" int tm_weights_export(const tm_weights* w, int32_t s, int32_t slot, t
     std::vector<int64_t> t(m);
     TM_HIP(hipMemcpyAsync(t.data(), w->g->d.t, m * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     const bool leaf = P.n_children[sl] == 0;
-    const size_t wsz = w->wide ? 16 : 8;
+    // the center's tables follow the set's width, a list table its own
+    const bool twide = sl == 0 ? w->wide : w->list_wide;
+    const size_t wsz = twide ? 16 : 8;
     // values are differences of neighbouring prefix entries: along eid order
     // for the center, along the T order of the slot's list otherwise
     std::vector<unsigned char> pre[2];
@@ -735,9 +737,9 @@ extern "C" int tm_weights_export(const tm_weights* w, int32_t s, int32_t slot, t
         const unsigned char* b = pre[par].data() + p * wsz;
         u64 lo = 0, hi = 0;
         std::memcpy(&lo, b, 8);
-        if (w->wide) std::memcpy(&hi, b + 8, 8);
+        if (twide) std::memcpy(&hi, b + 8, 8);
         const u128 v = ((u128)hi << 64) | lo;
-        return w->wide ? v : (u128)(u64)v;
+        return twide ? v : (u128)(u64)v;
     };
     for (int64_t e = 0; e < m; ++e) {
         const int64_t i = t[e] / w->ilen - slot;
@@ -749,7 +751,7 @@ extern "C" int tm_weights_export(const tm_weights* w, int32_t s, int32_t slot, t
                 const int par = (int)(i & 1);
                 const int64_t p = sl == 0 ? e : pos[e];
                 u128 d = at(par, p + 1) - at(par, p);
-                if (!w->wide) d = (u64)d;
+                if (!twide) d = (u64)d;
                 x.lo = (u64)d;
                 x.hi = (u64)(d >> 64);
             }

@@ -45,6 +45,7 @@ struct SampleArgs {
     int same_window[kMaxSlots];
     const void* qt[kMaxSlots][2];
     const void* qn[kMaxSlots][2];
+    int list_wide;  // the list tables hold 128-bit entries (else 64-bit, also under W = u128)
     // kept child windows (see weights): parity par of the parent at list
     // position x is win[s][par][2 x] (the parities interleave)
     const int4* win[kMaxSlots][2];
@@ -809,8 +810,8 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
             if (!a.exclude) w.q1 = w.q0;  // constraint 2 off: nothing excluded
             last = w;
             const bool leaf = a.leaf[s] != 0;
-            const W* qt = static_cast<const W*>(a.qt[s][par]);
-            const W* qn = static_cast<const W*>(a.qn[s][par]);
+            const ListTab<W> qt{a.qt[s][par], a.list_wide != 0};
+            const ListTab<W> qn{a.qn[s][par], a.list_wide != 0};
             W bt0 = 0, bn0 = 0, mass;
             if (leaf) {
                 mass = (W)((w.p1 - w.p0) - (w.q1 - w.q0));
@@ -844,7 +845,7 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
                 pos = w.p0 + (int32_t)rr + J;
             } else {
                 const W tgt = bt0 + rr + (qn[w.q0 + J] - bn0);
-                pos = upper_bound_bl<W>(qt, w.p0 + 1, w.p1 + 1, tgt) - 1;
+                pos = qt.upper_bound(w.p0 + 1, w.p1 + 1, tgt) - 1;
             }
             pos = pos < w.p0 ? w.p0 : (pos >= w.p1 ? w.p1 - 1 : pos);
             if constexpr (kCount) {
@@ -852,8 +853,8 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
                     if constexpr (kWin) nb += sizeof(int4);
                     else nb += 8 + (2 * probes(w.b - w.a) + probes(w.b - w.p0) + probes(w.b - w.q0)) * 8;
                 }
-                nb += probes(w.q1 - w.q0) * (4 + (leaf ? 0 : 2 * sizeof(W)));
-                if (!leaf) nb += (5 + probes(w.p1 - w.p0)) * sizeof(W);
+                nb += probes(w.q1 - w.q0) * (4 + (leaf ? 0 : 2 * qt.bytes()));
+                if (!leaf) nb += (5 + probes(w.p1 - w.p0)) * qt.bytes();
                 nb += 16;
             }
             const int32_t nbv = G.lnbr[d][pos];
@@ -1156,6 +1157,7 @@ void fill_args(const tm_weights* w, SampleArgs* out, size_t* lds_out) {
         }
     }
     a.has_win = w->has_win ? 1 : 0;
+    a.list_wide = w->list_wide ? 1 : 0;
     a.root_dir = P.root_dir;
     a.qc[0] = w->qc[0];
     a.qc[1] = w->qc[1];

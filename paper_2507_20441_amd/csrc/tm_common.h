@@ -142,6 +142,33 @@ __device__ __forceinline__ int32_t upper_bound_bl(const T* a, int32_t lo, int32_
     return b + (a[b] <= key ? 1 : 0);
 }
 
+// A list prefix table read as W: its entries are W, or 64-bit under W = u128
+// when the set was widened after a 64-bit build (every entry then fits).
+template <typename W>
+struct ListTab {
+    const void* p;
+    bool wide;
+    __device__ __forceinline__ W operator[](int64_t i) const {
+        if constexpr (sizeof(W) == 8) {
+            return static_cast<const W*>(p)[i];
+        } else {
+            return wide ? static_cast<const u128*>(p)[i] : (u128) static_cast<const u64*>(p)[i];
+        }
+    }
+    __device__ __forceinline__ int bytes() const { return sizeof(W) == 8 || wide ? (int)sizeof(W) : 8; }
+    // the first position in [lo, hi) whose entry is > key (hi if none)
+    __device__ __forceinline__ int32_t upper_bound(int32_t lo, int32_t hi, W key) const {
+        if constexpr (sizeof(W) == 8) {
+            return upper_bound_bl<W>(static_cast<const W*>(p), lo, hi, key);
+        } else {
+            if (wide) return upper_bound_bl<u128>(static_cast<const u128*>(p), lo, hi, key);
+            // the entries are below 2^64: a larger key lies past all of them
+            if (key >> 64) return hi;
+            return upper_bound_bl<u64>(static_cast<const u64*>(p), lo, hi, (u64)key);
+        }
+    }
+};
+
 // The root pair drawn by r in [0, W): over pairs (interval i, eid e in I_i)
 // in (i, eid) order weighted w_i(center, e), the pair whose cumulative range
 // holds r -- the last interval i with cum[i] <= r, then the last e of I_i

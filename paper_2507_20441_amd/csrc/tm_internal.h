@@ -205,8 +205,13 @@ struct tm_weights {
     // TM_EOVERFLOW and needs_wide set), 2 only 128
     int width_mode = 0;
     bool needs_wide = false;
+    // list prefix tables, per non-center slot and parity (T and N order):
+    // 128-bit entries only when the set was built in 128 bits; a set widened
+    // after a 64-bit build keeps its 64-bit list tables, which are exact
+    // (only center and interval totals outgrew 64 bits)
     void* qt[kMaxSlots][2] = {};
     void* qn[kMaxSlots][2] = {};
+    bool list_wide = false;
     void* qc[2] = {};
     int32_t* ilo = nullptr;  // [q] first eid of I_i
     int32_t* ihi = nullptr;  // [q] one past the last eid of I_i

@@ -759,27 +759,15 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, int* ovf_c, bool check_
 }
 
 // The 64-bit tables made 128-bit without recomputing any level: every
-// per-edge value is exact (no product overflowed) and only prefix totals
-// outgrew 64 bits.  Each prefix array is rebuilt in 128 bits from its own
-// consecutive differences; the center's, the interval tables and the guide
-// follow.  Kept windows are positions and stay.
+// per-edge value is exact (no product overflowed) and only the center's
+// totals along eid order outgrew 64 bits.  The list tables stay as they are
+// (exact in 64 bits; readers widen their entries); the center's prefix
+// arrays are rebuilt in 128 bits from their own consecutive differences, and
+// the interval tables and the guide follow.  Kept windows are positions and
+// stay.
 int widen_tables(tm_weights* w, hipStream_t st, int* ovf) {
-    const HostPlan& P = w->plan;
     const int64_t m = w->g->m;
     const size_t old_bytes = (size_t)(m + 1) * sizeof(u64);
-    for (int s = 1; s < P.nt; ++s) {
-        for (int par = 0; par < 2; ++par) {
-            for (int order = 0; order < 2; ++order) {
-                void*& tab = order == 0 ? w->qt[s][par] : w->qn[s][par];
-                if (!tab) continue;
-                u128* wide;
-                TM_TRY(arena_alloc(w->arena, &wide, (size_t)m + 1));
-                TM_TRY(device_exclusive_scan<u128>(WrappedDiff{static_cast<const u64*>(tab)}, m, wide, ovf, st));
-                w->arena.release_one(tab, old_bytes);
-                tab = wide;
-            }
-        }
-    }
     const void* qc64[2] = {w->qc[0], w->qc[1]};
     void* old[6] = {w->qc[0], w->qc[1], w->ilo, w->ihi, w->cumW, w->ioff};
     const size_t old_sz[6] = {old_bytes, old_bytes, (size_t)w->q * 4, (size_t)w->q * 4,
@@ -825,6 +813,7 @@ int weights_build(tm_weights* w, hipStream_t st, u64* model_bytes) {
     if (g->m == 0) {
         w->W = 0;
         w->wide = false;
+        w->list_wide = false;
         return TM_OK;
     }
     if (w->q >= ((int64_t)1 << 31)) return tm_fail(TM_ERANGE, "weights: too many intervals");
@@ -849,6 +838,7 @@ int weights_build(tm_weights* w, hipStream_t st, u64* model_bytes) {
         clear_tables(w);
         TM_TRY(fill_u32(ovf, 2, 0u, st));
         w->wide = wide != 0;
+        w->list_wide = w->wide;
         // on large graphs a level costs far more than a host round trip, and
         // a server's builder thread waits alone: there the 64-bit build
         // checks after every level and stops at the first overflow; other
@@ -972,6 +962,7 @@ int weights_enqueue(tm_weights* w, hipStream_t st, int* ovf,
     w->ilen = interval_unit(w);
     w->q = g->m > 0 ? g->T / w->ilen + 1 : 0;
     w->wide = false;
+    w->list_wide = false;
     w->W = 0;
     if (g->m == 0) return TM_OK;
     if (w->q >= ((int64_t)1 << 31)) return tm_fail(TM_ERANGE, "weights: too many intervals");

@@ -258,6 +258,36 @@ def test_wide_weights_beyond_64_bits(T, hub_n):
     assert again.W == P.W
 
 
+def test_widened_set_keeps_64_bit_list_tables(T):
+    """A path center -> middle -> five leaves on a hub of 5,000 out-edges:
+    the middle edge's weights (5000^5 each) and its list totals fit 64 bits,
+    the center's total W does not.  The set is widened without a second level
+    launch; its list tables stay 64-bit while the sampler runs in 128 bits,
+    and every weight, record and sum equals the oracle's."""
+    hub = 5000
+    src = np.concatenate([np.arange(10, 20), np.full(2, 1), np.full(hub, 2)]).astype(np.int32)
+    dst = np.concatenate([np.full(10, 1), np.full(2, 2), np.arange(100, 100 + hub)]).astype(np.int32)
+    t = np.concatenate([np.arange(10), 20 + np.arange(2), 30 + np.arange(hub)]).astype(np.int64)
+    g = W.TemporalGraph(src, dst, t, 100 + hub)
+    og, tg = pair(T, g)
+    edges = ((0, 1), (1, 2)) + tuple((2, j) for j in range(3, 8))
+    delta = 6000
+    otr = O.make_tree(list(range(len(edges))), 0)
+    say("widened list tables")
+    P, Wt = check_prep(T, og, tg, edges, delta, otr, seeds=(1, 2), k=4000)
+    info = Wt.info()
+    assert P.W >= 2**64 and info["wide"]
+    _, tmo = motifs_for(T, edges, delta)
+    ttr = T.make_tree(list(range(len(edges))), 0)
+    assert T.weights_footprint(tg, tmo, ttr, wide=False) < info["bytes"] < T.weights_footprint(tg, tmo, ttr, wide=True)
+    T.profile_read(reset=True)
+    T.profile_enable(True)
+    again = T.Weights(tg, tmo, ttr)
+    T.profile_enable(False)
+    launches = T.profile_read(reset=True)["launches"][T.STAGES.index("levels")]
+    assert again.W == P.W and launches == 2, launches  # one per non-leaf level, no rebuild
+
+
 def test_zero_weight_and_empty_graph(T):
     # no 2-path can exist: every edge leaves vertex 0
     g = W.TemporalGraph(np.zeros(5, np.int32), np.arange(1, 6, dtype=np.int32),

@@ -166,7 +166,12 @@ def test_footprint_matches_build(T, world):
         mo = T.make_motif(W.MOTIFS[name], delta)
         w = T.Weights(tg[gi], mo)
         info = w.info()
-        assert T.weights_footprint(tg[gi], mo, wide=info["wide"]) == info["bytes"]
+        if info["wide"]:
+            # widened after a 64-bit build: 64-bit list tables, 128-bit center
+            assert T.weights_footprint(tg[gi], mo, wide=False) < info["bytes"] <= \
+                T.weights_footprint(tg[gi], mo, wide=True)
+        else:
+            assert T.weights_footprint(tg[gi], mo, wide=False) == info["bytes"]
         w.close()
 
 
