@@ -187,7 +187,7 @@ struct tm_weights {
     // interval unit: delta with constraint 3, else T + 1 (one interval)
     uint32_t constraints = TM_C_ALL;
     int64_t ilen = 0;
-    void* vals[kMaxSlots][2] = {};  // build temporaries, null afterwards
+    void* vals[kMaxSlots][2] = {};  // build temporaries (both parities interleaved in vals[s][0]), null afterwards
     // child windows, per non-center slot and interval parity: the slot's
     // candidate window (p0, p1, q0, q1) for every edge its parent can match,
     // by that edge's position x in the list the parent is drawn from (the

@@ -165,6 +165,113 @@ int device_exclusive_scan(F f, int64_t n, T* out, int* ovf, hipStream_t st) {
     return rc;
 }
 
+// ---------------------------------------------------------------------------
+// Two exclusive scans in one pass: f(i) returns the i-th value of both
+// sequences (a Pair2), so a record holding both is read once.  Same outputs
+// and flags as two device_exclusive_scan calls.
+// ---------------------------------------------------------------------------
+template <typename V>
+struct Pair2 {
+    V a, b;
+};
+
+template <typename F>
+__global__ void __launch_bounds__(kBlock) scan2_tiles_kernel(F f, int64_t n, u128* part0, u128* part1, int* ovf) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    u128 s0 = 0, s1 = 0;
+    bool carry = false;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
+        if (i < n) {
+            const auto x = f(i);
+            const u128 y0 = s0 + to_u128(x.a), y1 = s1 + to_u128(x.b);
+            if (y0 < s0 || y1 < s1) carry = true;
+            s0 = y0;
+            s1 = y1;
+        }
+    }
+    u128 tot0, tot1;
+    block_exclusive(s0, &tot0, &carry);
+    block_exclusive(s1, &tot1, &carry);
+    if (threadIdx.x == 0) {
+        part0[blockIdx.x] = tot0;
+        part1[blockIdx.x] = tot1;
+    }
+    if (carry) atomicOr(ovf, 1);
+}
+
+template <typename T, typename F>
+__global__ void __launch_bounds__(kBlock)
+scan2_apply_kernel(F f, int64_t n, const u128* part0, const u128* part1, T* out0, T* out1, int* ovf) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    // each lane owns kScanItems consecutive values of the tile
+    const int64_t first = base + (int64_t)threadIdx.x * kScanItems;
+    u128 v0[kScanItems], v1[kScanItems];
+    u128 s0 = 0, s1 = 0;
+    bool carry = false;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = first + k;
+        v0[k] = v1[k] = 0;
+        if (i < n) {
+            const auto x = f(i);
+            v0[k] = to_u128(x.a);
+            v1[k] = to_u128(x.b);
+        }
+        const u128 y0 = s0 + v0[k], y1 = s1 + v1[k];
+        if (y0 < s0 || y1 < s1) carry = true;
+        s0 = y0;
+        s1 = y1;
+    }
+    u128 tot0, tot1;
+    u128 run0 = part0[blockIdx.x] + block_exclusive(s0, &tot0, &carry);
+    u128 run1 = part1[blockIdx.x] + block_exclusive(s1, &tot1, &carry);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = first + k;
+        if (i < n) {
+            out0[i] = (T)run0;
+            out1[i] = (T)run1;
+        }
+        const u128 y0 = run0 + v0[k], y1 = run1 + v1[k];
+        if (y0 < run0 || y1 < run1) carry = true;
+        run0 = y0;
+        run1 = y1;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        const u128 t0 = part0[gridDim.x], t1 = part1[gridDim.x];
+        out0[n] = (T)t0;
+        out1[n] = (T)t1;
+        if ((u128)(T)t0 != t0 || (u128)(T)t1 != t1) atomicOr(ovf, 2);  // a total does not fit T
+    }
+    if (carry) atomicOr(ovf, 1);
+}
+
+template <typename T, typename F>
+int device_exclusive_scan2(F f, int64_t n, T* out0, T* out1, int* ovf, hipStream_t st) {
+    if (n == 0) {
+        static_assert(sizeof(T) % 4 == 0, "scan outputs are whole words");
+        TM_TRY(fill_u32(out0, sizeof(T) / 4, 0u, st));
+        return fill_u32(out1, sizeof(T) / 4, 0u, st);
+    }
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    u128* part = nullptr;
+    TM_HIP(dev_alloc((void**)&part, 2 * (nb + 1) * sizeof(u128), st));
+    u128* part1 = part + nb + 1;
+    hipLaunchKernelGGL((scan2_tiles_kernel<F>), dim3((unsigned)nb), dim3(kBlock), 0, st, f, n, part, part1, ovf);
+    TM_HIP(hipGetLastError());
+    int rc = scan_parts(part, nb, ovf, st);
+    if (rc == TM_OK) rc = scan_parts(part1, nb, ovf, st);
+    if (rc == TM_OK) {
+        hipLaunchKernelGGL((scan2_apply_kernel<T, F>), dim3((unsigned)nb), dim3(kBlock), 0, st, f, n,
+                           (const u128*)part, (const u128*)part1, out0, out1, ovf);
+        TM_HIP(hipGetLastError());
+    }
+    TM_HIP(dev_free(part, st));
+    return rc;
+}
+
 // Exclusive scan of v over the block's 256 threads (thread t holds entry t):
 // shuffles inside each wave, then the wave totals through LDS.
 __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t* wsum) {

@@ -46,7 +46,7 @@ struct LevelArgs {
     int walk;          // -1: eid order; 0 / 1: the T order of the out- / in-lists
     int4* win[kMaxSlots][2];  // per child and parity: its windows, stride 2 (null: not kept)
     int win_dir;       // the list whose T positions index the windows
-    void* out[2];      // per parity: indexed by eid, or by T position in list out_pos_dir
+    void* out[2];      // per parity (interleaved, stride 2): by eid, or by T position in list out_pos_dir
     int out_pos_dir;   // first of two passes: its own walk (consecutive writes), else -1
     const void* in[2]; // second of two passes: the first pass's products ...
     int in_pos_dir;    // ... by T position in this list
@@ -284,8 +284,8 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
     W prodA = 1, prodB = hasB ? (W)1 : (W)0;
     if (a.in[0]) {
         const int64_t ip = a.in_pos_dir == a.walk ? p : (int64_t)G.tpos[a.in_pos_dir][e];
-        prodA = static_cast<const W*>(a.in[parA])[ip];
-        prodB = hasB ? static_cast<const W*>(a.in[parB])[ip] : (W)0;
+        prodA = static_cast<const W*>(a.in[parA])[2 * ip];
+        prodB = hasB ? static_cast<const W*>(a.in[parB])[2 * ip] : (W)0;
         if constexpr (kCount) nb += (a.in_pos_dir == a.walk ? 0 : 4) + sizeof(W) * (hasB ? 2 : 1);
     }
     bool ovf = false;
@@ -378,8 +378,8 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
         }
     });
     const int64_t at = a.out_pos_dir < 0 ? (int64_t)e : (a.out_pos_dir == a.walk ? p : (int64_t)G.tpos[a.out_pos_dir][e]);
-    static_cast<W*>(a.out[parA])[at] = prodA;
-    static_cast<W*>(a.out[parB])[at] = hasB ? prodB : (W)0;
+    static_cast<W*>(a.out[parA])[2 * at] = prodA;
+    static_cast<W*>(a.out[parB])[2 * at] = hasB ? prodB : (W)0;
     if constexpr (kCount) nb += 2 * sizeof(W) + (a.out_pos_dir < 0 || a.out_pos_dir == a.walk ? 0 : 4);
     if (ovf) atomicOr(a.ovf, 4);
     return nb;
@@ -408,17 +408,25 @@ __global__ void __launch_bounds__(kBlock) level_kernel(LevelArgs a) {
 // Values of one parity held in a list's T order, read in that list's N
 // order (through the N-to-T cross index, which stays inside each vertex's
 // list).
+// (Level values interleave their two parities, one record per position:
+// both parities' scans run together and read each record once.)
 template <typename W>
 struct ListGather {
     const W* val;
     const int32_t* at;
-    __device__ W operator()(int64_t p) const { return val[at[p]]; }
+    __device__ Pair2<W> operator()(int64_t p) const {
+        const W* r = val + 2 * (int64_t)at[p];
+        return {r[0], r[1]};
+    }
 };
 
 template <typename W>
 struct Plain {
     const W* val;
-    __device__ W operator()(int64_t p) const { return val[p]; }
+    __device__ Pair2<W> operator()(int64_t p) const {
+        const W* r = val + 2 * p;
+        return {r[0], r[1]};
+    }
 };
 
 // Interval bounds: I_i = [i delta, (i+2) delta) holds eids [lo_i, hi_i).
@@ -528,24 +536,27 @@ unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 // 2^64, which are the exact values whenever each value is below 2^64 (the
 // level kernels flag any product that is not), however the sums wrapped.
 struct WrappedDiff {
-    const u64* q;
-    __device__ u128 operator()(int64_t p) const { return (u128)(u64)(q[p + 1] - q[p]); }
+    const u64* q0;
+    const u64* q1;
+    __device__ Pair2<u128> operator()(int64_t p) const {
+        return {(u128)(u64)(q0[p + 1] - q0[p]), (u128)(u64)(q1[p + 1] - q1[p])};
+    }
 };
 
-// The center's prefix arrays in eid order from src[par] (its values), then
-// the interval bounds, the prefix of W_i, the per-interval offsets and the
-// root guide.  ovf: the flag word of these scans.
+// The center's prefix arrays in eid order from src (its values, both parities
+// in one pass), then the interval bounds, the prefix of W_i, the per-interval
+// offsets and the root guide.  ovf: the flag word of these scans.
 template <typename W, typename R>
-int finish_tables(tm_weights* w, hipStream_t st, int* ovf, const R (&src)[2]) {
+int finish_tables(tm_weights* w, hipStream_t st, int* ovf, const R& src) {
     tm_graph* g = w->g;
     const HostPlan& P = w->plan;
     const int64_t m = g->m;
+    W* qc[2];
     for (int par = 0; par < 2; ++par) {
-        W* qc;
-        TM_TRY(arena_alloc(w->arena, &qc, (size_t)m + 1));
-        TM_TRY(device_exclusive_scan<W>(src[par], m, qc, ovf, st));
-        w->qc[par] = qc;
+        TM_TRY(arena_alloc(w->arena, &qc[par], (size_t)m + 1));
+        w->qc[par] = qc[par];
     }
+    TM_TRY(device_exclusive_scan2<W>(src, m, qc[0], qc[1], ovf, st));
     // intervals and their weights
     TM_TRY(arena_alloc(w->arena, &w->ilo, (size_t)w->q));
     TM_TRY(arena_alloc(w->arena, &w->ihi, (size_t)w->q));
@@ -613,15 +624,15 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, int* ovf_c, bool check_
             std::vector<int> grp[2];
             for (int j = 0; j < P.n_children[s]; ++j) grp[P.side[P.children[s][j]]].push_back(P.children[s][j]);
             const bool two = !grp[0].empty() && !grp[1].empty();
-            for (int par = 0; par < 2; ++par) {
+            // both parities of an edge in one record: parity par of position
+            // x at [2 x + par], so a scattered write touches one line
+            {
                 W* p;
-                TM_HIP(dev_alloc((void**)&p, ((size_t)m * sizeof(W) + 255) & ~(size_t)255, st));
-                w->vals[s][par] = p;
+                TM_HIP(dev_alloc((void**)&p, ((size_t)2 * m * sizeof(W) + 255) & ~(size_t)255, st));
+                w->vals[s][0] = p;
             }
-            W* tmp[2] = {nullptr, nullptr};
-            if (two)
-                for (int par = 0; par < 2; ++par)
-                    TM_HIP(dev_alloc((void**)&tmp[par], ((size_t)m * sizeof(W) + 255) & ~(size_t)255, st));
+            W* tmp = nullptr;
+            if (two) TM_HIP(dev_alloc((void**)&tmp, ((size_t)2 * m * sizeof(W) + 255) & ~(size_t)255, st));
             int prev_walk = -1;
             for (int pass = 0; pass < (two ? 2 : 1); ++pass) {
                 const int side = two ? pass : (grp[0].empty() ? 1 : 0);
@@ -681,8 +692,8 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, int* ovf_c, bool check_
                 // search locality outweighs scattered window writes
                 a.walk = a.nc == 0 ? -1 : side;
                 for (int par = 0; par < 2; ++par) {
-                    a.out[par] = (two && pass == 0) ? (void*)tmp[par] : w->vals[s][par];
-                    a.in[par] = (two && pass == 1) ? (const void*)tmp[par] : nullptr;
+                    a.out[par] = ((two && pass == 0) ? tmp : static_cast<W*>(w->vals[s][0])) + par;
+                    a.in[par] = (two && pass == 1) ? (const void*)(tmp + par) : nullptr;
                 }
                 // the first of two passes leaves its products in its own walk
                 // order; the second gathers them
@@ -718,8 +729,7 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, int* ovf_c, bool check_
                 TM_HIP(hipGetLastError());
                 if (lt) lt->stop();
             }
-            if (two)
-                for (int par = 0; par < 2; ++par) TM_HIP(dev_free(tmp[par], st));
+            if (two) TM_HIP(dev_free(tmp, st));
             if (check_each_level && sizeof(W) == 8) {
                 int h_ovf = 0;
                 TM_HIP(hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -729,32 +739,28 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, int* ovf_c, bool check_
             // prefix sums along the lists the parent searches
             if (s != 0) {
                 const int dir = P.alpha[s] > 0 ? 0 : 1;
+                W *qt[2], *qn[2];
                 for (int par = 0; par < 2; ++par) {
-                    W *qt, *qn;
-                    TM_TRY(arena_alloc(w->arena, &qt, (size_t)m + 1));
-                    TM_TRY(arena_alloc(w->arena, &qn, (size_t)m + 1));
-                    const W* vp = static_cast<const W*>(w->vals[s][par]);
-                    TM_TRY(device_exclusive_scan<W>(Plain<W>{vp}, m, qt, ovf, st));
-                    TM_TRY(device_exclusive_scan<W>(ListGather<W>{vp, g->d.nxref[dir]}, m, qn, ovf, st));
-                    w->qt[s][par] = qt;
-                    w->qn[s][par] = qn;
-                    TM_HIP(dev_free(w->vals[s][par], st));
-                    w->vals[s][par] = nullptr;
+                    TM_TRY(arena_alloc(w->arena, &qt[par], (size_t)m + 1));
+                    TM_TRY(arena_alloc(w->arena, &qn[par], (size_t)m + 1));
+                    w->qt[s][par] = qt[par];
+                    w->qn[s][par] = qn[par];
                 }
+                const W* vp = static_cast<const W*>(w->vals[s][0]);
+                TM_TRY(device_exclusive_scan2<W>(Plain<W>{vp}, m, qt[0], qt[1], ovf, st));
+                TM_TRY(device_exclusive_scan2<W>(ListGather<W>{vp, g->d.nxref[dir]}, m, qn[0], qn[1], ovf, st));
+                TM_HIP(dev_free(w->vals[s][0], st));
+                w->vals[s][0] = nullptr;
             }
         }
     }
     // the center: prefix sums in eid order (slot 0 is the center), then the
     // interval tables
     {
-        const Plain<W> src[2] = {Plain<W>{static_cast<const W*>(w->vals[0][0])},
-                                 Plain<W>{static_cast<const W*>(w->vals[0][1])}};
-        TM_TRY(finish_tables<W>(w, st, ovf_c, src));
+        TM_TRY(finish_tables<W>(w, st, ovf_c, Plain<W>{static_cast<const W*>(w->vals[0][0])}));
     }
-    for (int par = 0; par < 2; ++par) {
-        TM_HIP(dev_free(w->vals[0][par], st));
-        w->vals[0][par] = nullptr;
-    }
+    TM_HIP(dev_free(w->vals[0][0], st));
+    w->vals[0][0] = nullptr;
     return TM_OK;
 }
 
@@ -774,8 +780,7 @@ int widen_tables(tm_weights* w, hipStream_t st, int* ovf) {
                               (size_t)(w->q + 1) * 8, (size_t)w->q * 8};
     void* old_guide = w->guide;
     const size_t guide_sz = (((size_t)1 << w->guide_bits) + 1) * sizeof(RootGuide);
-    const WrappedDiff src[2] = {WrappedDiff{static_cast<const u64*>(qc64[0])},
-                                WrappedDiff{static_cast<const u64*>(qc64[1])}};
+    const WrappedDiff src{static_cast<const u64*>(qc64[0]), static_cast<const u64*>(qc64[1])};
     w->wide = true;
     TM_TRY(finish_tables<u128>(w, st, ovf, src));
     for (int x = 0; x < 6; ++x) w->arena.release_one(old[x], old_sz[x]);
