@@ -54,9 +54,9 @@ def parse():
                          "the 2e6-edge path alone; batched: 64 heterogeneous jobs, one launch per job "
                          "against the batched pass; serving: a Poisson query stream against the server; "
                          "partial: partial-order motifs")
-    ap.add_argument("--legs", default="cpu,batched,serving,medium",
+    ap.add_argument("--legs", default="cpu,batched,serving,tiny,medium",
                     help="large: side legs to run after the timed steps (comma list of cpu, batched, "
-                         "serving, medium; 'none' for profiling runs)")
+                         "serving, tiny, medium; 'none' for profiling runs)")
     ap.add_argument("--large-traffic", default=os.path.join(ROOT, "profiles", "large_kernel_traffic.json"),
                     help="HBM bytes per launch of the large workload's kernels (JSON), if present")
     ap.add_argument("--weights-graph", choices=["medium", "serving"], default="serving",
@@ -693,6 +693,8 @@ def large(args):
         line["batched"] = batched_leg(args)
     if "serving" in legs:
         line["serving"] = serving_leg(args)
+    if "tiny" in legs:
+        line["tiny"] = tiny_leg()
     if "medium" in legs:
         med = medium_run(args, 10, 2, 0)
         line["medium"] = {"value": med["value"], "ms_per_step": med["ms_per_step"],
@@ -701,6 +703,48 @@ def large(args):
                           "estimates": [dict(motif=e["motif"], rel_ci95=e["rel_ci95"]) for e in med["estimates"]],
                           "workload": med["config"]["workload"]}
     print(json.dumps(line), flush=True)
+
+
+def tiny_leg(reps=50):
+    """The tiny configuration as a latency: one estimate call (graph build
+    from device-resident edges, weights, 1e5 samples, reduction) on 1,000
+    vertices and 20,000 edges, the 3-cycle at delta 1,000; p50/p99 over reps
+    calls after 5 warm-ups, and the samples/s that p50 gives."""
+    import numpy as np
+    import torch
+
+    from paper_2507_20441_amd import timest as T
+    from paper_2507_20441_amd import workloads as W
+
+    g = W.tiny_graph()
+    u, v, t = (torch.from_numpy(x).cuda() for x in (g.src, g.dst, g.t))
+    name, delta = W.TINY["motifs"][0]
+    mo = T.make_motif(W.MOTIFS[name], delta)
+    k, seed = W.TINY["k"], W.TINY["seed"]
+
+    def call():
+        G = T.Graph(u, v, t, g.n)
+        r = T.estimate(G, mo, k, seed)
+        G.close()
+        return r
+
+    for _ in range(5):
+        call()
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(reps):
+        a = time.perf_counter()
+        r = call()
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - a) * 1e3)
+    lat = np.array(lat)
+    p50 = float(np.percentile(lat, 50))
+    return {"workload": f"tiny: {g.n} vertices, {g.m} edges, {name} at delta {delta}, {k} samples, seed {seed}; "
+                        "graph build from device-resident edges + weights + sampling + reduction per call",
+            "latency_ms": {"p50": round(p50, 3), "p99": round(float(np.percentile(lat, 99)), 3),
+                           "calls": reps},
+            "samples_per_s_at_p50": round(k / (p50 / 1e3), 1), "estimate": r.estimate,
+            "rel_ci95": (1.96 * r.std_error / r.estimate) if r.estimate else None}
 
 
 def cpu_baseline_large(u, v, t, n, motifs, k, seed, slice_days, n_samples):
