@@ -265,7 +265,8 @@ u64 weights_window_bytes(const HostPlan& P, int64_t m);
 bool weights_keep_windows(const HostPlan& P, int64_t m);
 u64 weights_build_extra(int64_t m, bool wide);
 // Bits of the root guide for a graph of m edges: about one (interval, edge)
-// pair per bucket (lean sets: about eight), between 2^8 and 2^23 buckets.
+// pair per bucket (lean sets: about eight), between 2^8 and 2^26 buckets (lean
+// sets: 2^23).
 constexpr int kGuideExtraBits = 1;
 int guide_bits_for(int64_t m, bool lean = false);
 
