@@ -314,6 +314,7 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t* ws
 struct SortNone {};  // an absent value array
 constexpr int kSortStall = 4;
 constexpr uint32_t kSortMaxSpins = 1u << 20;
+constexpr int kSortLook = 8;  // status words a look-back step reads
 constexpr size_t kSortHeadBytes =
     ((size_t)kSortMaxPasses * kSortDigits * sizeof(uint32_t) + kSortMaxPasses * sizeof(uint32_t) + 255) &
     ~(size_t)255;
@@ -495,24 +496,42 @@ sort_pass_kernel(SortIO io, int64_t n, int shift, int bits, uint32_t tag, int io
             sdig[p] = (uint8_t)dig[k];
         }
     }
-    // look-back: the digit's count over all earlier tiles
+    // look-back: the digit's count over all earlier tiles, kSortLook status
+    // words per step (their loads in flight together), back to a tile that
+    // has published its inclusive total
     if (d <= mask) {
         uint32_t excl = 0;
         if (tile > 0) {
-            int64_t j = (int64_t)tile - 1;
+            int64_t j = (int64_t)tile - 1;  // the nearest tile not yet added
             uint32_t spins = 0;
             while (true) {
-                const u64 s = __hip_atomic_load(status + (size_t)j * kSortDigits + d, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t f = (uint32_t)(s >> 32) & 3u;
-                if ((uint32_t)(s >> 40) == tag && f != 0) {
-                    excl += (uint32_t)s;
-                    if (f == 2 || j == 0) break;
-                    --j;
-                } else if (++spins >= kSortMaxSpins) {
-                    atomicOr(err, kSortStall);
-                    break;
-                } else {
+                u64 sw[kSortLook];
+#pragma unroll
+                for (int i = 0; i < kSortLook; ++i) {
+                    const int64_t x = j - i;
+                    // before tile 0: an inclusive total of 0
+                    sw[i] = x >= 0 ? __hip_atomic_load(status + (size_t)x * kSortDigits + d, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT)
+                                   : tagw | ((u64)2 << 32);
+                }
+                int used = 0;
+                bool done = false;
+#pragma unroll
+                for (int i = 0; i < kSortLook; ++i) {
+                    if (done || used < i) continue;  // stopped before i
+                    const uint32_t f = (uint32_t)(sw[i] >> 32) & 3u;
+                    if ((uint32_t)(sw[i] >> 40) != tag || f == 0) continue;  // not published yet: poll again
+                    excl += (uint32_t)sw[i];
+                    used = i + 1;
+                    done = f == 2;
+                }
+                if (done) break;
+                j -= used;
+                if (used == 0) {
+                    if (++spins >= kSortMaxSpins) {
+                        atomicOr(err, kSortStall);
+                        break;
+                    }
                     __builtin_amdgcn_s_sleep(1);
                 }
             }
