@@ -1288,6 +1288,24 @@ def summarize_traffic(fetch_dir, write_dir, out_path, calib_bytes, workload):
         kernels[key] = dict(names=names, source=src, source_sha=kernel_source_sha(src), launches=len(fv),
                             fetch_bytes_per_launch=round(fb), write_bytes_per_launch=round(wb),
                             hbm_bytes_per_launch=round(fb + wb))
+    # the graph build as a whole: every kernel only it launches, summed over
+    # a build (builds counted by the validation kernel); the digit counts,
+    # shared with the root sorts by name, are left out (a few percent)
+    def graph_test(nm):
+        nm = nm.replace("(anonymous namespace)::", "")
+        return any(k in nm for k in ("validate_kernel(", "validate_reduce_kernel(", "canon_keys_kernel(",
+                                     "decode_packed_kernel(", "decode_split_kernel(", "tpos_kernel(",
+                                     "n_order_fix_kernel(", "offsets_kernel(")) or \
+            ("sort_pass_kernel<" in nm and "sort_pass_kernel<unsigned int, unsigned int," not in nm)
+    builds = sum(len(vs) for nm, vs in fk.items() if "validate_kernel(" in nm.replace("(anonymous namespace)::", ""))
+    if builds:
+        fb = sum(x for nm, vs in fk.items() if graph_test(nm) for x in vs) * 1024 * f_scale / builds
+        wb = sum(x for nm, vs in wk.items() if graph_test(nm) for x in vs) * 1024 * w_scale / builds
+        kernels["graph_build"] = dict(names=sorted({nm.replace("(anonymous namespace)::", "").replace("void ", "")
+                                                    .split("(")[0] for nm in fk if graph_test(nm)}),
+                                      source="csr.hip", source_sha=kernel_source_sha("csr.hip"), launches=builds,
+                                      per="build", fetch_bytes_per_launch=round(fb), write_bytes_per_launch=round(wb),
+                                      hbm_bytes_per_launch=round(fb + wb))
     doc = {
         "workload": workload,
         "copy_calibration": {"bytes": calib_bytes, "fetch_kib": f_cal, "write_kib": w_cal,
