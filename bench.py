@@ -1269,10 +1269,11 @@ def summarize_traffic(fetch_dir, write_dir, out_path, calib_bytes, workload):
     fk, wk = per_kernel(rows(fetch_dir)), per_kernel(rows(write_dir))
     copy = [n for n in fk if "copyBuffer" in n]
     assert copy, "no copy kernel: run the bench with --copy-calibration"
-    # the calibration copies are the large ones (the library's own small
-    # device copies run the same kernel)
-    f_cal = statistics.median([v for v in fk[copy[0]] if v >= 0.5 * max(fk[copy[0]])])
-    w_cal = statistics.median([v for v in wk[copy[0]] if v >= 0.5 * max(wk[copy[0]])])
+    # the calibration copies are the largest copies of the run (the library's
+    # own device copies, and PyTorch's when it draws a graph on the device,
+    # run the same kernel on fewer bytes)
+    f_cal = max(fk[copy[0]])
+    w_cal = max(wk[copy[0]])
     f_scale = calib_bytes / 1024.0 / f_cal
     w_scale = calib_bytes / 1024.0 / w_cal
     kernels = {}
