@@ -46,6 +46,7 @@ struct SampleArgs {
     const void* qt[kMaxSlots][2];
     const void* qn[kMaxSlots][2];
     int list_wide;  // the list tables hold 128-bit entries (else 64-bit, also under W = u128)
+    const void* qtc[kMaxSlots][2];  // every 2^kCoarseBits-th entry of each qt table
     // kept child windows (see weights): parity par of the parent at list
     // position x is win[s][par][2 x] (the parities interleave)
     const int4* win[kMaxSlots][2];
@@ -810,7 +811,7 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
             if (!a.exclude) w.q1 = w.q0;  // constraint 2 off: nothing excluded
             last = w;
             const bool leaf = a.leaf[s] != 0;
-            const ListTab<W> qt{a.qt[s][par], a.list_wide != 0};
+            const ListTab<W> qt{a.qt[s][par], a.list_wide != 0, a.qtc[s][par], kCoarseBits};
             const ListTab<W> qn{a.qn[s][par], a.list_wide != 0};
             W bt0 = 0, bn0 = 0, mass;
             if (leaf) {
@@ -841,11 +842,12 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
             }
             const int32_t J = jb - w.q0;
             int32_t pos;
+            uint32_t pick_probes = 0;
             if (leaf) {
                 pos = w.p0 + (int32_t)rr + J;
             } else {
                 const W tgt = bt0 + rr + (qn[w.q0 + J] - bn0);
-                pos = qt.upper_bound(w.p0 + 1, w.p1 + 1, tgt) - 1;
+                pos = qt.upper_bound_coarse(w.p0 + 1, w.p1 + 1, tgt, kCount ? &pick_probes : nullptr) - 1;
             }
             pos = pos < w.p0 ? w.p0 : (pos >= w.p1 ? w.p1 - 1 : pos);
             if constexpr (kCount) {
@@ -854,7 +856,7 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
                     else nb += 8 + (2 * probes(w.b - w.a) + probes(w.b - w.p0) + probes(w.b - w.q0)) * 8;
                 }
                 nb += probes(w.q1 - w.q0) * (4 + (leaf ? 0 : 2 * qt.bytes()));
-                if (!leaf) nb += (5 + probes(w.p1 - w.p0)) * qt.bytes();
+                if (!leaf) nb += (5 + pick_probes) * qt.bytes();
                 nb += 16;
             }
             const int32_t nbv = G.lnbr[d][pos];
@@ -1153,6 +1155,7 @@ void fill_args(const tm_weights* w, SampleArgs* out, size_t* lds_out) {
         for (int par = 0; par < 2; ++par) {
             a.qt[s][par] = w->qt[s][par];
             a.qn[s][par] = w->qn[s][par];
+            a.qtc[s][par] = w->qtc[s][par];
             a.win[s][par] = w->win[s][par];
         }
     }

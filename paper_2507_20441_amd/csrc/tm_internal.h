@@ -211,6 +211,10 @@ struct tm_weights {
     // (only center and interval totals outgrew 64 bits)
     void* qt[kMaxSlots][2] = {};
     void* qn[kMaxSlots][2] = {};
+    // every kCoarse-th entry of each qt table (m / kCoarse + 1 entries, the
+    // table's width): a search over a window goes through it first, so the
+    // probes far apart fall in a table 16 times smaller
+    void* qtc[kMaxSlots][2] = {};
     bool list_wide = false;
     void* qc[2] = {};
     int32_t* ilo = nullptr;  // [q] first eid of I_i
@@ -268,6 +272,7 @@ u64 weights_build_extra(int64_t m, bool wide);
 // pair per bucket (lean sets: about eight), between 2^8 and 2^26 buckets (lean
 // sets: 2^23).
 constexpr int kGuideExtraBits = 1;
+constexpr int kCoarseBits = 4;  // list prefix tables: one coarse entry per 2^kCoarseBits
 int guide_bits_for(int64_t m, bool lean = false);
 
 // Exact sums over a range of samples of one job.  Sums over disjoint ranges

@@ -429,6 +429,13 @@ struct Plain {
     }
 };
 
+// Every 2^kCoarseBits-th entry of a prefix table.
+template <typename W>
+__global__ void coarse_kernel(const W* q, int64_t nc, W* c) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < nc) c[i] = q[i << kCoarseBits];
+}
+
 // Interval bounds: I_i = [i delta, (i+2) delta) holds eids [lo_i, hi_i).
 __global__ void interval_kernel(const int64_t* t, int64_t m, int64_t q, int64_t delta, int32_t* lo,
                                 int32_t* hi) {
@@ -749,6 +756,15 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, int* ovf_c, bool check_
                 const W* vp = static_cast<const W*>(w->vals[s][0]);
                 TM_TRY(device_exclusive_scan2<W>(Plain<W>{vp}, m, qt[0], qt[1], ovf, st));
                 TM_TRY(device_exclusive_scan2<W>(ListGather<W>{vp, g->d.nxref[dir]}, m, qn[0], qn[1], ovf, st));
+                const int64_t nc = (m >> kCoarseBits) + 1;
+                for (int par = 0; par < 2; ++par) {
+                    W* c;
+                    TM_TRY(arena_alloc(w->arena, &c, (size_t)nc));
+                    hipLaunchKernelGGL((coarse_kernel<W>), dim3(grid_for(nc)), dim3(kBlock), 0, st,
+                                       (const W*)qt[par], nc, c);
+                    TM_HIP(hipGetLastError());
+                    w->qtc[s][par] = c;
+                }
                 TM_HIP(dev_free(w->vals[s][0], st));
                 w->vals[s][0] = nullptr;
             }
@@ -798,6 +814,7 @@ void clear_tables(tm_weights* w) {
     w->has_win = false;
     std::memset(w->qt, 0, sizeof w->qt);
     std::memset(w->qn, 0, sizeof w->qn);
+    std::memset(w->qtc, 0, sizeof w->qtc);
     std::memset(w->qc, 0, sizeof w->qc);
     w->ilo = w->ihi = nullptr;
     w->cumW = nullptr;
@@ -901,7 +918,8 @@ u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide, bool l
     auto blk = [](u64 bytes) { return ((bytes ? bytes : 16) + 255) & ~(u64)255; };
     u64 b = 0;
     for (int s = 1; s < P.nt; ++s)
-        if (P.n_children[s] > 0) b += 4 * blk((u64)(m + 1) * wsz);  // qt and qn, per parity
+        if (P.n_children[s] > 0)
+            b += 4 * blk((u64)(m + 1) * wsz) + 2 * blk((u64)((m >> kCoarseBits) + 1) * wsz);  // qt, qn, coarse qt
     b += 2 * blk((u64)(m + 1) * wsz);                   // qc, per parity
     b += 2 * blk((u64)q * 4) + blk((u64)(q + 1) * wsz); // ilo, ihi, cumW
     b += blk((u64)q * wsz);                              // ioff
