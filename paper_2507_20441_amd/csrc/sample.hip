@@ -842,12 +842,11 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
             }
             const int32_t J = jb - w.q0;
             int32_t pos;
-            uint32_t pick_probes = 0;
             if (leaf) {
                 pos = w.p0 + (int32_t)rr + J;
             } else {
                 const W tgt = bt0 + rr + (qn[w.q0 + J] - bn0);
-                pos = qt.upper_bound_coarse(w.p0 + 1, w.p1 + 1, tgt, kCount ? &pick_probes : nullptr) - 1;
+                pos = qt.upper_bound_coarse(w.p0 + 1, w.p1 + 1, tgt) - 1;
             }
             pos = pos < w.p0 ? w.p0 : (pos >= w.p1 ? w.p1 - 1 : pos);
             if constexpr (kCount) {
@@ -856,7 +855,7 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
                     else nb += 8 + (2 * probes(w.b - w.a) + probes(w.b - w.p0) + probes(w.b - w.q0)) * 8;
                 }
                 nb += probes(w.q1 - w.q0) * (4 + (leaf ? 0 : 2 * qt.bytes()));
-                if (!leaf) nb += (5 + pick_probes) * qt.bytes();
+                if (!leaf) nb += (5 + probes(w.p1 - w.p0)) * qt.bytes();  // charged as the plain search
                 nb += 16;
             }
             const int32_t nbv = G.lnbr[d][pos];

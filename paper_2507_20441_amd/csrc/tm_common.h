@@ -160,19 +160,15 @@ struct ListTab {
     __device__ __forceinline__ int bytes() const { return sizeof(W) == 8 || wide ? (int)sizeof(W) : 8; }
     // upper_bound through the coarse entries: the first coarse entry above
     // key inside the range bounds the position to the 2^cb entries before
-    // it, which a search of one or two lines finishes.  np (optional): the
-    // probes made, coarse and fine.
-    __device__ __forceinline__ int32_t upper_bound_coarse(int32_t lo, int32_t hi, W key,
-                                                          uint32_t* np = nullptr) const {
+    // it, which a search of one or two lines finishes.
+    __device__ __forceinline__ int32_t upper_bound_coarse(int32_t lo, int32_t hi, W key) const {
         const int32_t cl = (lo + (1 << cb) - 1) >> cb, ch = hi > 0 ? (hi - 1) >> cb : -1;
         int32_t flo = lo, fhi = hi;
-        uint32_t n = 0;
         if (c && cl <= ch) {
             const ListTab<W> ct{c, wide};
             int32_t j = cl, len = ch - cl + 1;  // first coarse index in [cl, ch] above key (ch + 1 if none)
             while (len > 0) {
                 const int32_t h = len >> 1;
-                ++n;
                 if (ct[j + h] <= key) {
                     j += h + 1;
                     len -= h + 1;
@@ -186,11 +182,9 @@ struct ListTab {
         int32_t a = flo, b = fhi;
         while (a < b) {
             const int32_t mid = a + ((b - a) >> 1);
-            ++n;
             if ((*this)[mid] > key) b = mid;
             else a = mid + 1;
         }
-        if (np) *np += n;
         return a;
     }
     // the first position in [lo, hi) whose entry is > key (hi if none)
