@@ -54,6 +54,14 @@ struct LevelArgs {
     unsigned long long* nbytes;  // counting variant: access-model bytes of the launch
 };
 
+// Element i (0 or 1) of a two-entry argument array, as a select: indexing
+// the kernel's argument arrays at run time had the compiler copy all of its
+// arguments to scratch in some variants.
+template <typename T>
+__device__ __forceinline__ T sel2(const T (&arr)[2], int i) {
+    return i ? arr[1] : arr[0];
+}
+
 template <int B, int E, typename F>
 __device__ __forceinline__ void sfor(F&& f) {
     if constexpr (B < E) {
@@ -62,66 +70,18 @@ __device__ __forceinline__ void sfor(F&& f) {
     }
 }
 
-// The first position of a vertex's list, in T order, whose time is >= x,
-// and, in N order, whose packed key is >= (o << bt) + x, for NB values of x
-// at once: 2 NB independent loads per halving step (three for a child on one
-// side of its parent in time, four for one a partial order leaves unordered).
-// x is clipped to [0, T + 1]; the key for x = T + 1 (the end of o's run) is
-// taken as "> (o << bt) + T", which cannot wrap even when the id and time
-// bits fill all 64.
+// NB window bounds in a vertex's list: p[j] the first position, in T order,
+// whose time is >= x_j, and q[j] the first, in N order, whose packed key is
+// >= (o << bt) + x_j (three bounds for a child on one side of its parent in
+// time, four for one a partial order leaves unordered).  x is clipped to
+// [0, T + 1]; the key for x = T + 1 (the end of o's run) is taken as
+// "> (o << bt) + T", which cannot wrap even when the id and time bits fill
+// all 64.
 template <int NB>
 struct BoundsN {
     int32_t p[NB], q[NB];
     int32_t len;  // the list's length
 };
-
-template <int NB>
-__device__ __forceinline__ BoundsN<NB> list_bounds(const DevGraph& G, int dir, int32_t g, int32_t o,
-                                                   const int64_t (&xs)[NB], bool exclude) {
-    const int32_t a = G.off[dir][g], b = G.off[dir][g + 1];
-    const int64_t* lt = G.lt[dir];
-    const u64* nk = G.nkey[dir];
-    const u64 base = (u64)o << G.bt;
-    int64_t x[NB];
-    u64 kx[NB];
-    bool le[NB];
-    int32_t c[2 * NB];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        x[j] = xs[j] < 0 ? 0 : (xs[j] > G.T + 1 ? G.T + 1 : xs[j]);
-        le[j] = x[j] > G.T;
-        kx[j] = base + (u64)(le[j] ? G.T : x[j]);
-        c[j] = a;
-        c[NB + j] = a;
-    }
-    int32_t n = b - a;
-    while (n > 1) {
-        const int32_t h = n >> 1;
-        int64_t y[NB];
-        u64 z[NB];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            y[j] = lt[c[j] + h];
-            z[j] = nk[c[NB + j] + h];
-        }
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            c[j] = y[j] < x[j] ? c[j] + h : c[j];
-            c[NB + j] = (z[j] < kx[j] || (le[j] && z[j] == kx[j])) ? c[NB + j] + h : c[NB + j];
-        }
-        n -= h;
-    }
-    BoundsN<NB> r;
-    r.len = b - a;
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        r.p[j] = a == b ? a : c[j] + (lt[c[j]] < x[j] ? 1 : 0);
-        const u64 zl = nk[c[NB + j]];
-        r.q[j] = a == b ? a : c[NB + j] + ((zl < kx[j] || (le[j] && zl == kx[j])) ? 1 : 0);
-        if (!exclude) r.q[j] = a;  // no excluded run
-    }
-    return r;
-}
 
 // ---------------------------------------------------------------------------
 // The level kernel's window bounds.  In T order the NB bounds are searched in
@@ -131,7 +91,7 @@ __device__ __forceinline__ BoundsN<NB> list_bounds(const DevGraph& G, int dir, i
 // they lie in that neighbour's run, a few entries on.  (A variant in which a
 // wave walking one list staged each bound's segment in LDS after two
 // wave-uniform searches was measured slower: see the design notes.)  Every
-// bound is the first position whose key is >= x, as in list_bounds.
+// bound is the first position whose key is >= x (BoundsN above).
 // ---------------------------------------------------------------------------
 
 // Keys before the bound of (kx, le): z < kx, or z == kx when x > T.
@@ -173,9 +133,9 @@ __device__ __forceinline__ constexpr int bound_rank(int k) {
 template <int NB, int Kind>
 __device__ __forceinline__ BoundsN<NB> level_bounds(const DevGraph& G, int dir, int32_t g, int32_t o,
                                                     const int64_t (&xs)[NB], bool exclude) {
-    const int32_t a = G.off[dir][g], b = G.off[dir][g + 1];
-    const int64_t* lt = G.lt[dir];
-    const u64* nk = G.nkey[dir];
+    const int32_t a = sel2(G.off, dir)[g], b = sel2(G.off, dir)[g + 1];
+    const int64_t* lt = sel2(G.lt, dir);
+    const u64* nk = sel2(G.nkey, dir);
     int64_t x[NB];
 #pragma unroll
     for (int j = 0; j < NB; ++j) x[j] = xs[j] < 0 ? 0 : (xs[j] > G.T + 1 ? G.T + 1 : xs[j]);
@@ -264,28 +224,28 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
     const DevGraph& G = a.G;
     u64 nb = 0;
     // the walked edge: its list's owner, neighbour and time sit at p
-    const int32_t e = a.walk < 0 ? (int32_t)p : G.leid[a.walk][p];
+    const int32_t e = a.walk < 0 ? (int32_t)p : sel2(G.leid, a.walk)[p];
     int32_t u, v;
     int64_t t;
     if constexpr (kCount) nb += 16 + (a.walk < 0 ? 0 : 4);
-    if (a.walk < 0 || !G.lown[a.walk]) {
+    if (a.walk < 0 || !sel2(G.lown, a.walk)) {
         u = G.src[e];
         v = G.dst[e];
         t = G.t[e];
     } else {
-        const int32_t own = G.lown[a.walk][p], nbr = G.lnbr[a.walk][p];
+        const int32_t own = sel2(G.lown, a.walk)[p], nbr = sel2(G.lnbr, a.walk)[p];
         u = a.walk == 0 ? own : nbr;
         v = a.walk == 0 ? nbr : own;
-        t = G.lt[a.walk][p];
+        t = sel2(G.lt, a.walk)[p];
     }
     const int64_t blk = t / a.ilen;
     const bool hasB = blk >= 1;
     const int parA = (int)(blk & 1), parB = parA ^ 1;
     W prodA = 1, prodB = hasB ? (W)1 : (W)0;
     if (a.in[0]) {
-        const int64_t ip = a.in_pos_dir == a.walk ? p : (int64_t)G.tpos[a.in_pos_dir][e];
-        prodA = static_cast<const W*>(a.in[parA])[2 * ip];
-        prodB = hasB ? static_cast<const W*>(a.in[parB])[2 * ip] : (W)0;
+        const int64_t ip = a.in_pos_dir == a.walk ? p : (int64_t)sel2(G.tpos, a.in_pos_dir)[e];
+        prodA = static_cast<const W*>(sel2(a.in, parA))[2 * ip];
+        prodB = hasB ? static_cast<const W*>(sel2(a.in, parB))[2 * ip] : (W)0;
         if constexpr (kCount) nb += (a.in_pos_dir == a.walk ? 0 : 4) + sizeof(W) * (hasB ? 2 : 1);
     }
     bool ovf = false;
@@ -294,34 +254,27 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
         if (c >= a.nc) return;
         const ChildDesc& d = a.c[c];
         if (d.copies == 0) return;
-        W xa = 0, xb = 0;
+        const int32_t g = d.side ? v : u;
+        const int32_t o = d.side ? u : v;
+        // the windows of intervals blk (parity A) and blk - 1 (B) as four
+        // bounds: A = [p0, p2), B = [p1, p3) (likewise q), whatever the
+        // child's side in time, so that one path below serves every child
+        // (separate paths had the compiler copy the arguments to scratch)
+        BoundsN<4> r;
         if (kPO && d.beta == 0) {
-            const int32_t g = d.side ? v : u;
-            const int32_t o = d.side ? u : v;
             const int64_t lo = t - a.delta, hi = t + a.delta;
             int64_t xs[4];
             xs[0] = lo > blk * a.ilen ? lo : blk * a.ilen;
             xs[1] = lo > (blk - 1) * a.ilen ? lo : (blk - 1) * a.ilen;
             xs[2] = (hi < (blk + 2) * a.ilen - 1 ? hi : (blk + 2) * a.ilen - 1) + 1;
             xs[3] = (hi < (blk + 1) * a.ilen - 1 ? hi : (blk + 1) * a.ilen - 1) + 1;
-            const BoundsN<4> r = level_bounds<4, 2>(G, d.dir, g, o, xs, a.exclude != 0);
+            r = level_bounds<4, 2>(G, d.dir, g, o, xs, a.exclude != 0);
             if constexpr (kCount) {
                 int it = 0;
                 for (int32_t n = r.len; n > 1; n -= n >> 1) ++it;
                 nb += 8 + (u64)64 * it + (r.len > 0 ? 64 : 0);
-                if (a.win[c][0]) nb += 32 + (a.win_dir == a.walk ? 0 : 4);
-                if (!d.leaf) nb += (r.p[2] > r.p[0] ? 4 * sizeof(W) : 0) + (hasB && r.p[3] > r.p[1] ? 4 * sizeof(W) : 0);
             }
-            if (a.win[c][0]) {
-                const int64_t at = a.win_dir == a.walk ? p : (int64_t)G.tpos[a.win_dir][e];
-                a.win[c][parA][2 * at] = make_int4(r.p[0], r.p[2], r.q[0], r.q[2]);
-                a.win[c][parB][2 * at] = hasB ? make_int4(r.p[1], r.p[3], r.q[1], r.q[3]) : make_int4(0, 0, 0, 0);
-            }
-            xa = window_mass<W>(r.p[0], r.p[2], r.q[0], r.q[2], d.leaf, d.qt[parA], d.qn[parA]);
-            xb = hasB ? window_mass<W>(r.p[1], r.p[3], r.q[1], r.q[3], d.leaf, d.qt[parB], d.qn[parB]) : (W)0;
         } else {
-            const int32_t g = d.side ? v : u;
-            const int32_t o = d.side ? u : v;
             // x values (first position with time >= x):
             //   before: A = [x0, x2), B = [x1, x2) with x0 = blk delta, x1 = t - delta, x2 = t + 1
             //   after:  A = [x0, x1), B = [x0, x2) with x0 = t, x1 = t + delta + 1, x2 = (blk + 1) delta
@@ -337,49 +290,45 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
                 xs[1] = (hi < (blk + 2) * a.ilen - 1 ? hi : (blk + 2) * a.ilen - 1) + 1;
                 xs[2] = (hi < (blk + 1) * a.ilen - 1 ? hi : (blk + 1) * a.ilen - 1) + 1;
             }
-            const BoundsN<3> r = d.beta < 0 ? level_bounds<3, 0>(G, d.dir, g, o, xs, a.exclude != 0)
-                                            : level_bounds<3, 1>(G, d.dir, g, o, xs, a.exclude != 0);
+            const BoundsN<3> r3 = d.beta < 0 ? level_bounds<3, 0>(G, d.dir, g, o, xs, a.exclude != 0)
+                                             : level_bounds<3, 1>(G, d.dir, g, o, xs, a.exclude != 0);
+            // before: (p0, p1, p2, p2); after: (p0, p0, p1, p2)
+            const bool bef = d.beta < 0;
+            r.p[0] = r3.p[0];
+            r.p[1] = bef ? r3.p[1] : r3.p[0];
+            r.p[2] = bef ? r3.p[2] : r3.p[1];
+            r.p[3] = r3.p[2];
+            r.q[0] = r3.q[0];
+            r.q[1] = bef ? r3.q[1] : r3.q[0];
+            r.q[2] = bef ? r3.q[2] : r3.q[1];
+            r.q[3] = r3.q[2];
+            r.len = r3.len;
             if constexpr (kCount) {
                 int it = 0;
                 for (int32_t n = r.len; n > 1; n -= n >> 1) ++it;
                 nb += 8 + (u64)48 * it + (r.len > 0 ? 48 : 0);
-                if (a.win[c][0]) nb += 32 + (a.win_dir == a.walk ? 0 : 4);
-                if (!d.leaf) {
-                    // the prefix reads of the two windows' masses (below)
-                    const int32_t a1 = d.beta < 0 ? r.p[2] : r.p[1], b0 = d.beta < 0 ? r.p[1] : r.p[0];
-                    nb += (a1 > r.p[0] ? 4 * sizeof(W) : 0) + (hasB && r.p[2] > b0 ? 4 * sizeof(W) : 0);
-                }
-            }
-            if (a.win[c][0]) {
-                // the windows of intervals blk (parity A) and blk - 1 (B)
-                const int64_t at = a.win_dir == a.walk ? p : (int64_t)G.tpos[a.win_dir][e];
-                int4 wa, wb;
-                if (d.beta < 0) {
-                    wa = make_int4(r.p[0], r.p[2], r.q[0], r.q[2]);
-                    wb = make_int4(r.p[1], r.p[2], r.q[1], r.q[2]);
-                } else {
-                    wa = make_int4(r.p[0], r.p[1], r.q[0], r.q[1]);
-                    wb = make_int4(r.p[0], r.p[2], r.q[0], r.q[2]);
-                }
-                a.win[c][parA][2 * at] = wa;
-                a.win[c][parB][2 * at] = hasB ? wb : make_int4(0, 0, 0, 0);
-            }
-            if (d.beta < 0) {
-                xa = window_mass<W>(r.p[0], r.p[2], r.q[0], r.q[2], d.leaf, d.qt[parA], d.qn[parA]);
-                xb = hasB ? window_mass<W>(r.p[1], r.p[2], r.q[1], r.q[2], d.leaf, d.qt[parB], d.qn[parB]) : (W)0;
-            } else {
-                xa = window_mass<W>(r.p[0], r.p[1], r.q[0], r.q[1], d.leaf, d.qt[parA], d.qn[parA]);
-                xb = hasB ? window_mass<W>(r.p[0], r.p[2], r.q[0], r.q[2], d.leaf, d.qt[parB], d.qn[parB]) : (W)0;
             }
         }
+        if constexpr (kCount) {
+            if (a.win[c][0]) nb += 32 + (a.win_dir == a.walk ? 0 : 4);
+            // the prefix reads of the two windows' masses (below)
+            if (!d.leaf) nb += (r.p[2] > r.p[0] ? 4 * sizeof(W) : 0) + (hasB && r.p[3] > r.p[1] ? 4 * sizeof(W) : 0);
+        }
+        if (a.win[c][0]) {
+            const int64_t at = a.win_dir == a.walk ? p : (int64_t)sel2(G.tpos, a.win_dir)[e];
+            sel2(a.win[c], parA)[2 * at] = make_int4(r.p[0], r.p[2], r.q[0], r.q[2]);
+            sel2(a.win[c], parB)[2 * at] = hasB ? make_int4(r.p[1], r.p[3], r.q[1], r.q[3]) : make_int4(0, 0, 0, 0);
+        }
+        const W xa = window_mass<W>(r.p[0], r.p[2], r.q[0], r.q[2], d.leaf, sel2(d.qt, parA), sel2(d.qn, parA));
+        const W xb = hasB ? window_mass<W>(r.p[1], r.p[3], r.q[1], r.q[3], d.leaf, sel2(d.qt, parB), sel2(d.qn, parB)) : (W)0;
         for (int r = 0; r < d.copies; ++r) {
             if (!mul_ok(prodA, xa, &prodA)) ovf = true;
             if (!mul_ok(prodB, xb, &prodB)) ovf = true;
         }
     });
-    const int64_t at = a.out_pos_dir < 0 ? (int64_t)e : (a.out_pos_dir == a.walk ? p : (int64_t)G.tpos[a.out_pos_dir][e]);
-    static_cast<W*>(a.out[parA])[2 * at] = prodA;
-    static_cast<W*>(a.out[parB])[2 * at] = hasB ? prodB : (W)0;
+    const int64_t at = a.out_pos_dir < 0 ? (int64_t)e : (a.out_pos_dir == a.walk ? p : (int64_t)sel2(G.tpos, a.out_pos_dir)[e]);
+    static_cast<W*>(sel2(a.out, parA))[2 * at] = prodA;
+    static_cast<W*>(sel2(a.out, parB))[2 * at] = hasB ? prodB : (W)0;
     if constexpr (kCount) nb += 2 * sizeof(W) + (a.out_pos_dir < 0 || a.out_pos_dir == a.walk ? 0 : 4);
     if (ovf) atomicOr(a.ovf, 4);
     return nb;
