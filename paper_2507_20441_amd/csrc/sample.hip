@@ -668,8 +668,11 @@ __global__ void __launch_bounds__(kBlock) root_kernel(SampleArgs a, uint32_t* ke
 // M_phi of a valid tree image (Alg. 5): the completions over the non-tree
 // edges of a's motif.  img: the graph vertex of every motif vertex; te: the
 // time of every tree slot.
+// ga: the same arguments where the no-inline routines read them (an LDS copy
+// in the single-job kernel, so that the kernel's arguments are never copied
+// to scratch for them).
 template <bool kCount, bool kGeneral, int NT, int K>
-__device__ __forceinline__ u128 completions(const SampleArgs& a, const int32_t (&img)[K],
+__device__ __forceinline__ u128 completions(const SampleArgs& a, const SampleArgs& ga, const int32_t (&img)[K],
                                             const int64_t (&te)[NT], bool& ovf, u64& nb) {
     const DevGraph& G = a.G;
     u128 m_phi = 0;
@@ -686,14 +689,14 @@ __device__ __forceinline__ u128 completions(const SampleArgs& a, const int32_t (
                 constexpr int si = decltype(sc)::value;
                 tt[si] = si < NT ? te[si < NT ? si : 0] : 0;
             });
-            m_phi = complete_po<kCount>(a, iv, tt, &ovf, &nb);
+            m_phi = complete_po<kCount>(ga, iv, tt, &ovf, &nb);
         } else {
             int64_t tp[TM_MAX_L], tn[TM_MAX_L];
             for (int r2 = 0; r2 < a.n_runs; ++r2) {
                 tp[r2] = a.run_prev[r2] >= 0 ? pick(te, a.run_prev[r2]) : 0;
                 tn[r2] = a.run_next[r2] >= 0 ? pick(te, a.run_next[r2]) : 0;
             }
-            m_phi = complete_general<kCount>(a, iv, tfirst, tlast, tp, tn, &ovf, &nb);
+            m_phi = complete_general<kCount>(ga, iv, tfirst, tlast, tp, tn, &ovf, &nb);
         }
     } else {
         m_phi = 1;
@@ -726,8 +729,8 @@ __device__ __forceinline__ u128 completions(const SampleArgs& a, const int32_t (
 // kSmall: trees of at most four edges and motifs of at most five vertices,
 // so that fewer register slots are live (more waves per SIMD).
 template <typename W, bool kCount, bool kGeneral, bool kSorted, bool kWin = false, bool kSmall = false>
-__device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* cum, u64 x0, u64 xend,
-                                                 u64 stride, LaneAcc& L) {
+__device__ __forceinline__ void sample_positions(const SampleArgs& a, const SampleArgs& ga, const W* cum, u64 x0,
+                                                 u64 xend, u64 stride, LaneAcc& L) {
     static_assert(kSorted || !kWin, "windows are read by list position");
     constexpr int NT = kSmall ? 4 : kMaxSlots - 1;  // register slots; a.nt of them are used
     constexpr int K = kSmall ? 5 : TM_MAX_K;         // motif vertices held
@@ -909,7 +912,7 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const W* c
             const int64_t b = tmin / a.ilen;
             n_phi = (b < a.q ? 1u : 0u) + ((b >= 1 && tmax < (b + 1) * a.ilen) ? 1u : 0u);
             // Alg. 5: completions over the non-tree edges
-            m_phi = completions<kCount, kGeneral, NT, K>(a, img, te, ovf, nb);
+            m_phi = completions<kCount, kGeneral, NT, K>(a, ga, img, te, ovf, nb);
             ++n_valid;
             if (m_phi != 0) ++n_nonzero;
             u128 term;
@@ -997,8 +1000,19 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
         lanes_reduce(L, &a.parts[blockIdx.x], a.ovf);  // nothing drawn
         return;
     }
-    sample_positions<W, kCount, kGeneral, kSorted, kWin, kSmall>(a, cum, (u64)blockIdx.x * kBlock + threadIdx.x,
-                                                   a.count, (u64)gridDim.x * kBlock, L);
+    if constexpr (kGeneral) {
+        // the general variants' no-inline completion routines read the
+        // arguments from an LDS copy (a reference to the kernel's own would
+        // make it copy them to scratch in every lane)
+        __shared__ SampleArgs s_args;
+        if (threadIdx.x == 0) s_args = a;
+        __syncthreads();
+        sample_positions<W, kCount, kGeneral, kSorted, kWin, kSmall>(
+            a, s_args, cum, (u64)blockIdx.x * kBlock + threadIdx.x, a.count, (u64)gridDim.x * kBlock, L);
+    } else {
+        sample_positions<W, kCount, kGeneral, kSorted, kWin, kSmall>(
+            a, a, cum, (u64)blockIdx.x * kBlock + threadIdx.x, a.count, (u64)gridDim.x * kBlock, L);
+    }
     lanes_reduce(L, &a.parts[blockIdx.x], a.ovf);
 }
 
@@ -1282,10 +1296,10 @@ batch_sample_kernel(const SampleArgs* __restrict__ jobs, const Tile* __restrict_
         const bool skip = (a.wflag && *a.wflag != 0) || (a.Wdev && *static_cast<const W*>(a.Wdev) == 0);
         if (!skip) {
             if (kWinMode == 1 || (kWinMode == 2 && a.has_win))
-                sample_positions<W, false, kGeneral, true, kWinMode != 0>(a, nullptr, T.begin + threadIdx.x, T.end,
-                                                                          kBlock, L);
+                sample_positions<W, false, kGeneral, true, kWinMode != 0>(a, a, nullptr, T.begin + threadIdx.x,
+                                                                          T.end, kBlock, L);
             else
-                sample_positions<W, false, kGeneral, true, false>(a, nullptr, T.begin + threadIdx.x, T.end, kBlock, L);
+                sample_positions<W, false, kGeneral, true, false>(a, a, nullptr, T.begin + threadIdx.x, T.end, kBlock, L);
         }
         lanes_reduce(L, &tile_parts[t], ovf);
     }
