@@ -71,6 +71,11 @@ def parse():
     ap.add_argument("--serve-cold", action="store_true",
                     help="serving: start the stream with an empty weight cache (default: every "
                          "(graph, motif, delta) set the stream uses is built first)")
+    ap.add_argument("--serve-rates", default="",
+                    help="serving: after the main stream, shorter open-loop streams at these rates "
+                         "(queries/s, comma-separated) on a warm cache, for the server's capacity")
+    ap.add_argument("--serve-sweep-seconds", type=float, default=10.0,
+                    help="serving: length of each --serve-rates stream")
     ap.add_argument("--serve-check", type=int, default=12,
                     help="served queries re-run alone with tm_estimate and compared")
     ap.add_argument("--traffic-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -479,6 +484,29 @@ def serving(args):
         same_open &= a.acc2.value == r.acc2.value and a.n_valid == r.n_valid and a.estimate == r.estimate
     assert same_cl and same_open, "served results differ from tm_estimate alone"
     rel = [1.96 * r.std_error / r.estimate for r, _ in ok if r.estimate > 0]
+    # capacity: the offered rate raised until the served rate falls behind it
+    sweep = []
+    for rate in [float(x) for x in args.serve_rates.split(",") if x.strip()]:
+        qs = W.serving_queries(args.serve_sweep_seconds, rate, len(graphs), seed=5000 + int(rate))
+        for q in qs:
+            key = (q["motif"], q["delta"])
+            if key not in motifs:
+                motifs[key] = T.make_motif(W.MOTIFS[q["motif"]], q["delta"])
+        log(f"capacity: {len(qs)} queries at {rate}/s for {args.serve_sweep_seconds} s")
+        s_res, s_st, s_wall = run(qs, True, warm=True)
+        s_ok = [info for r, info in s_res if r is not None]
+        s_lat = np.array([info.latency_ms for info in s_ok]) if s_ok else np.zeros(1)
+        s_total = sum(q["k"] for q, (r, _) in zip(qs, s_res) if r is not None)
+        offered = sum(q["k"] for q in qs) / args.serve_sweep_seconds
+        sweep.append({"rate_qps": rate, "queries": len(qs), "failed": len(qs) - len(s_ok),
+                      "offered_samples_per_s": round(offered, 1),
+                      "served_samples_per_s": round(s_total / s_wall, 1),
+                      "served_over_offered": round(s_total / s_wall / offered, 4) if offered else None,
+                      "latency_ms": {"p50": float(np.percentile(s_lat, 50)),
+                                     "p99": float(np.percentile(s_lat, 99)), "max": float(s_lat.max())},
+                      "passes": s_st["passes"]})
+        log(f"capacity: {json.dumps(sweep[-1])}")
+    keeping_up = [x["rate_qps"] for x in sweep if x["failed"] == 0 and (x["served_over_offered"] or 0) >= 0.95]
     line = {
         "metric": "samples/s at <=5% rel. err; batched-queue vs one-job-per-launch; p99 latency",
         "value": round(total / wall, 1),
@@ -513,6 +541,9 @@ def serving(args):
         "rel_ci95_max": max(rel) if rel else None,
         "rel_ci95_median": float(np.median(rel)) if rel else None,
     }
+    if sweep:
+        line["capacity_sweep"] = {"seconds_per_rate": args.serve_sweep_seconds, "points": sweep,
+                                  "highest_rate_kept_up_qps": max(keeping_up) if keeping_up else None}
     print(json.dumps(line), flush=True)
     for g in graphs:
         g.close()

@@ -477,8 +477,24 @@ extern "C" int tm_graph_export(const tm_graph* g, int which, void* host_out, voi
         case TM_ARR_IN_EID: p = D.leid[1]; bytes = m * 4; break;
         case TM_ARR_OUTN_EID: p = D.neid[0]; bytes = m * 4; break;
         case TM_ARR_INN_EID: p = D.neid[1]; bytes = m * 4; break;
-        case TM_ARR_OUT_T: p = D.lt[0]; bytes = m * 8; break;
-        case TM_ARR_IN_T: p = D.lt[1]; bytes = m * 8; break;
+        case TM_ARR_OUT_T:
+        case TM_ARR_IN_T: {
+            const int dir = which == TM_ARR_IN_T ? 1 : 0;
+            if (!D.lt32[dir]) {
+                p = D.lt[dir];
+                bytes = m * 8;
+                break;
+            }
+            // 32-bit lists: widened on the host
+            if (m == 0) return TM_OK;
+            std::vector<uint32_t> h32(m);
+            hipStream_t st = as_stream(stream);
+            TM_HIP(hipMemcpyAsync(h32.data(), D.lt32[dir], m * 4, hipMemcpyDeviceToHost, st));
+            TM_HIP(sync_stream(st));
+            int64_t* out = static_cast<int64_t*>(host_out);
+            for (size_t i = 0; i < m; ++i) out[i] = (int64_t)h32[i];
+            return TM_OK;
+        }
         case TM_ARR_OUT_NBR: p = D.lnbr[0]; bytes = m * 4; break;
         case TM_ARR_IN_NBR: p = D.lnbr[1]; bytes = m * 4; break;
         case TM_ARR_OUT_POS: p = D.tpos[0]; bytes = m * 4; break;

@@ -116,8 +116,9 @@ __global__ void canon_keys_kernel(const int32_t* src, const int32_t* dst, const 
 
 // Edge arrays from the sorted packed keys, and the duplicate check on
 // neighbours.
+// (ot32, when not null: the times again in 32 bits, for the list sorts)
 __global__ void decode_packed_kernel(const u64* key, int64_t m, int bn, int32_t* osrc, int32_t* odst, int64_t* ot,
-                                     int* flags) {
+                                     uint32_t* ot32, int* flags) {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= m) return;
     const u64 k = key[e];
@@ -125,12 +126,13 @@ __global__ void decode_packed_kernel(const u64* key, int64_t m, int bn, int32_t*
     osrc[e] = (int32_t)((k >> bn) & mask);
     odst[e] = (int32_t)(k & mask);
     ot[e] = (int64_t)(k >> (2 * bn));
+    if (ot32) ot32[e] = (uint32_t)(k >> (2 * bn));
     if (e > 0 && key[e - 1] == k) atomicOr(flags, kDup);
 }
 
 // Edge arrays from the sorted times and the (u, v) keys carried with them.
 __global__ void decode_split_kernel(const u64* tsorted, const u64* uv, int64_t m, int bn, int32_t* osrc,
-                                    int32_t* odst, int64_t* ot, int* flags) {
+                                    int32_t* odst, int64_t* ot, uint32_t* ot32, int* flags) {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= m) return;
     const u64 k = uv[e], t = tsorted[e];
@@ -138,6 +140,7 @@ __global__ void decode_split_kernel(const u64* tsorted, const u64* uv, int64_t m
     osrc[e] = (int32_t)(k >> bn);
     odst[e] = (int32_t)(k & mask);
     ot[e] = (int64_t)t;
+    if (ot32) ot32[e] = (uint32_t)t;
     if (e > 0 && uv[e - 1] == k && tsorted[e - 1] == t) atomicOr(flags, kDup);
 }
 
@@ -147,13 +150,15 @@ __global__ void tpos_kernel(const int32_t* leid, int64_t m, int32_t* pos) {
     if (p < m && (uint32_t)leid[p] < (uint64_t)m) pos[leid[p]] = (int32_t)p;
 }
 
-// N order: the packed key from the carried neighbour and time (nkey holds the
-// time on entry), and each entry's position in this direction's T order.
-__global__ void n_order_fix_kernel(const uint32_t* nbr, const int32_t* neid, const int32_t* tpos, int64_t m, int bt,
-                                   u64* nkey, int32_t* nxref) {
+// N order: the packed key from the carried neighbour and time (ntime: the
+// carried times, which may be nkey itself), and each entry's position in
+// this direction's T order.
+template <typename TT>
+__global__ void n_order_fix_kernel(const uint32_t* nbr, const TT* ntime, const int32_t* neid, const int32_t* tpos,
+                                   int64_t m, int bt, u64* nkey, int32_t* nxref) {
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q >= m) return;
-    nkey[q] = ((u64)nbr[q] << bt) | nkey[q];
+    nkey[q] = ((u64)nbr[q] << bt) | (u64)ntime[q];
     nxref[q] = (uint32_t)neid[q] < (uint64_t)m ? tpos[neid[q]] : -1;
 }
 
@@ -252,6 +257,10 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
     // them whole, the list sorts as halves.
     u64* work[4] = {nullptr, nullptr, nullptr, nullptr};
     uint32_t* nbr_tmp = nullptr;  // N order: the carried neighbours, when work[3] holds the owners
+    // Lists keep their times in 32 bits when every shifted time is below
+    // 2^32 - 1; t32e: those times by eid, the list sorts' input.
+    const bool narrow = g->T < (int64_t)0xFFFFFFFFll;
+    uint32_t* t32e = nullptr;
     auto release = [&]() {
         for (u64*& w : work) {
             if (w) (void)dev_free(w, st);
@@ -259,12 +268,19 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
         }
         if (nbr_tmp) (void)dev_free(nbr_tmp, st);
         nbr_tmp = nullptr;
+        if (t32e) (void)dev_free(t32e, st);
+        t32e = nullptr;
     };
     int rc = TM_OK;
     for (u64*& w : work)
         if (rc == TM_OK && dev_alloc((void**)&w, (size_t)m * sizeof(u64), st) != hipSuccess)
             rc = tm_fail(TM_ENOMEM, "graph: work arrays");
-    if (rc != TM_OK) return bail(rc);
+    if (rc == TM_OK && narrow && dev_alloc((void**)&t32e, (size_t)m * sizeof(uint32_t), st) != hipSuccess)
+        rc = tm_fail(TM_ENOMEM, "graph: work arrays");
+    if (rc != TM_OK) {
+        release();
+        return bail(rc);
+    }
     int32_t *esrc = nullptr, *edst = nullptr;
     int64_t* et = nullptr;
     rc = arena_alloc(g->arena, &esrc, m);
@@ -291,7 +307,7 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
         rc = sort_two(in, spare, 2 * bn + D.bt, &res);
         if (rc == TM_OK)
             hipLaunchKernelGGL(decode_packed_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, (const u64*)res.k, m,
-                               bn, esrc, edst, et, flags);
+                               bn, esrc, edst, et, t32e, flags);
     } else if (rc == TM_OK) {
         // by (u, v) with the time carried, then by time with (u, v) carried
         using S = SortSet<u64, u64>;
@@ -312,7 +328,7 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
         }
         if (rc == TM_OK)
             hipLaunchKernelGGL(decode_split_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, (const u64*)r2.k,
-                               (const u64*)r2.v0, m, bn, esrc, edst, et, flags);
+                               (const u64*)r2.v0, m, bn, esrc, edst, et, t32e, flags);
     }
     if (rc == TM_OK && hipGetLastError() != hipSuccess) rc = tm_fail(TM_EDEVICE, "graph: decode launch");
     if (rc != TM_OK) {
@@ -328,80 +344,96 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
     // dir 1: in-lists  (owner = destination, neighbour = source)
     // T order: the eids stably sorted by owner, carrying time, eid and
     // neighbour, so that every list array comes out of the sort in place.
-    using L = SortSet<uint32_t, u64, uint32_t, uint32_t>;
-    L tmp;  // the other buffer of the list sorts
-    tmp.k = reinterpret_cast<uint32_t*>(work[0]);
-    tmp.v1 = reinterpret_cast<uint32_t*>(work[0]) + m;
-    tmp.v0 = work[1];
-    tmp.v2 = reinterpret_cast<uint32_t*>(work[2]);
-    uint32_t* nkeys_out = reinterpret_cast<uint32_t*>(work[2]) + m;  // N order: its sorted keys (unused)
-    const bool keep_own = m <= ((int64_t)1 << 28);
-    uint32_t* own[2] = {nullptr, nullptr};
-    if (!keep_own && dev_alloc((void**)&nbr_tmp, (size_t)m * sizeof(uint32_t), st) != hipSuccess)
-        rc = tm_fail(TM_ENOMEM, "graph: work arrays");
-    uint32_t* nbr_carried = keep_own ? reinterpret_cast<uint32_t*>(work[3]) : nbr_tmp;
-    int32_t* tpos[2] = {nullptr, nullptr};
-    for (int dir = 0; dir < 2 && rc == TM_OK; ++dir) {
-        int64_t* lt = nullptr;
-        int32_t *leid = nullptr, *lnbr = nullptr, *lown = nullptr, *off = nullptr;
-        rc = arena_alloc(g->arena, &lt, m);
-        if (rc == TM_OK) rc = arena_alloc(g->arena, &leid, m);
-        if (rc == TM_OK) rc = arena_alloc(g->arena, &lnbr, m);
-        if (rc == TM_OK && keep_own) rc = arena_alloc(g->arena, &lown, m);
-        if (rc == TM_OK) rc = arena_alloc(g->arena, &off, (size_t)n + 1);
-        if (rc == TM_OK) rc = arena_alloc(g->arena, &tpos[dir], (size_t)m);
-        if (rc != TM_OK) break;
-        own[dir] = keep_own ? reinterpret_cast<uint32_t*>(lown) : reinterpret_cast<uint32_t*>(work[3]) + dir * m;
-        L in, out;
-        in.k = reinterpret_cast<uint32_t*>(dir == 0 ? esrc : edst);
-        in.v0 = reinterpret_cast<u64*>(et);
-        in.v2 = reinterpret_cast<uint32_t*>(dir == 0 ? edst : esrc);
-        out.k = own[dir];
-        out.v0 = reinterpret_cast<u64*>(lt);
-        out.v1 = reinterpret_cast<uint32_t*>(leid);
-        out.v2 = reinterpret_cast<uint32_t*>(lnbr);
-        rc = sort_into(in, out, tmp, m, 0, bn, 2 /* eids: 0, 1, ... */, flags + 1, st);
-        if (rc != TM_OK) break;
-        hipLaunchKernelGGL(offsets_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, (const uint32_t*)own[dir], m, n,
-                           off);
-        hipLaunchKernelGGL(tpos_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, (const int32_t*)leid, m, tpos[dir]);
-        if (hipGetLastError() != hipSuccess) rc = tm_fail(TM_EDEVICE, "graph: list launch");
-        D.off[dir] = off;
-        D.tpos[dir] = tpos[dir];
-        D.lt[dir] = lt;
-        D.leid[dir] = leid;
-        D.lown[dir] = lown;
-        D.lnbr[dir] = lnbr;
-    }
-    // N order of dir d: the T order of the other direction (sorted by this
-    // direction's neighbour, then time) stably re-sorted by this direction's
-    // owner, carrying time, eid and neighbour.
-    for (int dir = 0; dir < 2 && rc == TM_OK; ++dir) {
-        const int other = 1 - dir;
-        u64* nkey = nullptr;
-        int32_t *nxref = nullptr, *neid = nullptr;
-        rc = arena_alloc(g->arena, &nkey, m);
-        if (rc == TM_OK) rc = arena_alloc(g->arena, &nxref, m);
-        if (rc == TM_OK) rc = arena_alloc(g->arena, &neid, m);
-        if (rc != TM_OK) break;
-        L in, out;
-        in.k = reinterpret_cast<uint32_t*>(const_cast<int32_t*>(D.lnbr[other]));
-        in.v0 = reinterpret_cast<u64*>(const_cast<int64_t*>(D.lt[other]));
-        in.v1 = reinterpret_cast<uint32_t*>(const_cast<int32_t*>(D.leid[other]));
-        in.v2 = own[other];
-        out.k = nkeys_out;
-        out.v0 = nkey;  // the time, until the fix below packs the neighbour in
-        out.v1 = reinterpret_cast<uint32_t*>(neid);
-        out.v2 = nbr_carried;
-        rc = sort_into(in, out, tmp, m, 0, bn, 0, flags + 1, st);
-        if (rc != TM_OK) break;
-        hipLaunchKernelGGL(n_order_fix_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, (const uint32_t*)nbr_carried,
-                           (const int32_t*)neid, (const int32_t*)tpos[dir], m, D.bt, nkey, nxref);
-        if (hipGetLastError() != hipSuccess) rc = tm_fail(TM_EDEVICE, "graph: list launch");
-        D.nkey[dir] = nkey;
-        D.nxref[dir] = nxref;
-        D.neid[dir] = neid;
-    }
+    // TT: the lists' time type (uint32_t or int64_t).
+    auto build_lists = [&](auto time_tag) -> int {
+        using TT = decltype(time_tag);
+        using V = typename std::conditional<sizeof(TT) == 4, uint32_t, u64>::type;
+        using L = SortSet<uint32_t, V, uint32_t, uint32_t>;
+        L tmp;  // the other buffer of the list sorts
+        tmp.k = reinterpret_cast<uint32_t*>(work[0]);
+        tmp.v1 = reinterpret_cast<uint32_t*>(work[0]) + m;
+        tmp.v0 = reinterpret_cast<V*>(work[1]);
+        tmp.v2 = reinterpret_cast<uint32_t*>(work[2]);
+        uint32_t* nkeys_out = reinterpret_cast<uint32_t*>(work[2]) + m;  // N order: its sorted keys (unused)
+        // N order: the carried times (32-bit: the upper half of work[1]; 64-bit:
+        // the key array itself, packed in place afterwards)
+        uint32_t* ntime32 = reinterpret_cast<uint32_t*>(work[1]) + m;
+        const bool keep_own = m <= ((int64_t)1 << 28);
+        uint32_t* own[2] = {nullptr, nullptr};
+        if (!keep_own && dev_alloc((void**)&nbr_tmp, (size_t)m * sizeof(uint32_t), st) != hipSuccess)
+            return tm_fail(TM_ENOMEM, "graph: work arrays");
+        uint32_t* nbr_carried = keep_own ? reinterpret_cast<uint32_t*>(work[3]) : nbr_tmp;
+        int32_t* tpos[2] = {nullptr, nullptr};
+        TT* ltab[2] = {nullptr, nullptr};
+        for (int dir = 0; dir < 2; ++dir) {
+            TT* lt = nullptr;
+            int32_t *leid = nullptr, *lnbr = nullptr, *lown = nullptr, *off = nullptr;
+            TM_TRY(arena_alloc(g->arena, &lt, m));
+            TM_TRY(arena_alloc(g->arena, &leid, m));
+            TM_TRY(arena_alloc(g->arena, &lnbr, m));
+            if (keep_own) TM_TRY(arena_alloc(g->arena, &lown, m));
+            TM_TRY(arena_alloc(g->arena, &off, (size_t)n + 1));
+            TM_TRY(arena_alloc(g->arena, &tpos[dir], (size_t)m));
+            own[dir] = keep_own ? reinterpret_cast<uint32_t*>(lown) : reinterpret_cast<uint32_t*>(work[3]) + dir * m;
+            L in, out;
+            in.k = reinterpret_cast<uint32_t*>(dir == 0 ? esrc : edst);
+            in.v0 = sizeof(TT) == 4 ? reinterpret_cast<V*>(t32e) : reinterpret_cast<V*>(et);
+            in.v2 = reinterpret_cast<uint32_t*>(dir == 0 ? edst : esrc);
+            out.k = own[dir];
+            out.v0 = reinterpret_cast<V*>(lt);
+            out.v1 = reinterpret_cast<uint32_t*>(leid);
+            out.v2 = reinterpret_cast<uint32_t*>(lnbr);
+            TM_TRY(sort_into(in, out, tmp, m, 0, bn, 2 /* eids: 0, 1, ... */, flags + 1, st));
+            hipLaunchKernelGGL(offsets_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, (const uint32_t*)own[dir],
+                               m, n, off);
+            hipLaunchKernelGGL(tpos_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st, (const int32_t*)leid, m,
+                               tpos[dir]);
+            if (hipGetLastError() != hipSuccess) return tm_fail(TM_EDEVICE, "graph: list launch");
+            D.off[dir] = off;
+            D.tpos[dir] = tpos[dir];
+            ltab[dir] = lt;
+            if constexpr (sizeof(TT) == 4) {
+                D.lt32[dir] = reinterpret_cast<const uint32_t*>(lt);
+                D.lt[dir] = nullptr;
+            } else {
+                D.lt[dir] = reinterpret_cast<const int64_t*>(lt);
+                D.lt32[dir] = nullptr;
+            }
+            D.leid[dir] = leid;
+            D.lown[dir] = lown;
+            D.lnbr[dir] = lnbr;
+        }
+        // N order of dir d: the T order of the other direction (sorted by this
+        // direction's neighbour, then time) stably re-sorted by this
+        // direction's owner, carrying time, eid and neighbour.
+        for (int dir = 0; dir < 2; ++dir) {
+            const int other = 1 - dir;
+            u64* nkey = nullptr;
+            int32_t *nxref = nullptr, *neid = nullptr;
+            TM_TRY(arena_alloc(g->arena, &nkey, m));
+            TM_TRY(arena_alloc(g->arena, &nxref, m));
+            TM_TRY(arena_alloc(g->arena, &neid, m));
+            L in, out;
+            in.k = reinterpret_cast<uint32_t*>(const_cast<int32_t*>(D.lnbr[other]));
+            in.v0 = reinterpret_cast<V*>(ltab[other]);
+            in.v1 = reinterpret_cast<uint32_t*>(const_cast<int32_t*>(D.leid[other]));
+            in.v2 = own[other];
+            out.k = nkeys_out;
+            out.v0 = sizeof(TT) == 4 ? reinterpret_cast<V*>(ntime32) : reinterpret_cast<V*>(nkey);
+            out.v1 = reinterpret_cast<uint32_t*>(neid);
+            out.v2 = nbr_carried;
+            TM_TRY(sort_into(in, out, tmp, m, 0, bn, 0, flags + 1, st));
+            hipLaunchKernelGGL((n_order_fix_kernel<V>), dim3(grid_for(m)), dim3(kBlock), 0, st,
+                               (const uint32_t*)nbr_carried, (const V*)out.v0, (const int32_t*)neid,
+                               (const int32_t*)tpos[dir], m, D.bt, nkey, nxref);
+            if (hipGetLastError() != hipSuccess) return tm_fail(TM_EDEVICE, "graph: list launch");
+            D.nkey[dir] = nkey;
+            D.nxref[dir] = nxref;
+            D.neid[dir] = neid;
+        }
+        return TM_OK;
+    };
+    rc = narrow ? build_lists(uint32_t{}) : build_lists(int64_t{});
     release();
     if (rc != TM_OK) return bail(rc);
     timer.stop();

@@ -139,6 +139,29 @@ struct Bounds {
     int32_t a, b;    // the vertex's list
 };
 
+// The four searches of window_bounds in lockstep over a T order of time
+// type TT (wlo <= whi inside [0, T], which TT holds).
+template <typename TT>
+__device__ __forceinline__ void window_search(const TT* lt, const u64* nk, int32_t a, int32_t b, TT wlo, TT whi,
+                                              u64 klo, u64 khi, Bounds& r) {
+    int32_t b0 = a, b1 = a, b2 = a, b3 = a;
+    int32_t n = b - a;
+    while (n > 1) {
+        const int32_t h = n >> 1;
+        const TT x0 = lt[b0 + h], x1 = lt[b1 + h];
+        const u64 x2 = nk[b2 + h], x3 = nk[b3 + h];
+        b0 = x0 < wlo ? b0 + h : b0;
+        b1 = x1 <= whi ? b1 + h : b1;
+        b2 = x2 < klo ? b2 + h : b2;
+        b3 = x3 <= khi ? b3 + h : b3;
+        n -= h;
+    }
+    r.p0 = b0 + (lt[b0] < wlo ? 1 : 0);
+    r.p1 = b1 + (lt[b1] <= whi ? 1 : 0);
+    r.q0 = b2 + (nk[b2] < klo ? 1 : 0);
+    r.q1 = b3 + (nk[b3] <= khi ? 1 : 0);
+}
+
 // The child window of Claim "matching-edges-set" in list dir of vertex g with
 // time in [wlo, whi], and the run of edges whose far endpoint is o.
 __device__ __forceinline__ Bounds window_bounds(const DevGraph& G, int dir, int32_t g, int32_t o,
@@ -152,26 +175,13 @@ __device__ __forceinline__ Bounds window_bounds(const DevGraph& G, int dir, int3
         r.p0 = r.p1 = r.q0 = r.q1 = r.a;
         return r;
     }
-    const int64_t* lt = G.lt[dir];
     const u64* nk = G.nkey[dir];
     const u64 base = (u64)o << G.bt;
     const u64 klo = base | (u64)wlo, khi = base | (u64)whi;
-    int32_t b0 = r.a, b1 = r.a, b2 = r.a, b3 = r.a;
-    int32_t n = r.b - r.a;
-    while (n > 1) {
-        const int32_t h = n >> 1;
-        const int64_t x0 = lt[b0 + h], x1 = lt[b1 + h];
-        const u64 x2 = nk[b2 + h], x3 = nk[b3 + h];
-        b0 = x0 < wlo ? b0 + h : b0;
-        b1 = x1 <= whi ? b1 + h : b1;
-        b2 = x2 < klo ? b2 + h : b2;
-        b3 = x3 <= khi ? b3 + h : b3;
-        n -= h;
-    }
-    r.p0 = b0 + (lt[b0] < wlo ? 1 : 0);
-    r.p1 = b1 + (lt[b1] <= whi ? 1 : 0);
-    r.q0 = b2 + (nk[b2] < klo ? 1 : 0);
-    r.q1 = b3 + (nk[b3] <= khi ? 1 : 0);
+    if (G.lt32[dir])
+        window_search<uint32_t>(G.lt32[dir], nk, r.a, r.b, (uint32_t)wlo, (uint32_t)whi, klo, khi, r);
+    else
+        window_search<int64_t>(G.lt[dir], nk, r.a, r.b, wlo, whi, klo, khi, r);
     return r;
 }
 
@@ -755,14 +765,14 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const Samp
             if constexpr (kWin) posv[0] = pos;
             const int rd = a.root_dir;
             e0 = G.leid[rd][pos];
-            te[0] = G.lt[rd][pos];
+            te[0] = list_time(G.lt32[rd], G.lt[rd], pos);
             const int32_t nbr0 = G.lnbr[rd][pos];
             const int32_t own0 = G.lown[rd] ? G.lown[rd][pos] : (rd ? G.dst[e0] : G.src[e0]);
             u0 = rd ? nbr0 : own0;
             v0 = rd ? own0 : nbr0;
             const int64_t blk = te[0] / a.ilen;
             i = (int32_t)(((blk & 1) == (int64_t)(key & 1)) ? blk : blk - 1);
-            if constexpr (kCount) nb += 8 + 20;
+            if constexpr (kCount) nb += 8 + 12 + (G.lt32[0] ? 4 : 8);
         } else {
             // draw 0: interval, then center edge
             r = x;
@@ -855,14 +865,16 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const Samp
             if constexpr (kCount) {
                 if (!a.same_window[s]) {
                     if constexpr (kWin) nb += sizeof(int4);
-                    else nb += 8 + (2 * probes(w.b - w.a) + probes(w.b - w.p0) + probes(w.b - w.q0)) * 8;
+                    else
+                        nb += 8 + (probes(w.b - w.a) + probes(w.b - w.p0)) * (G.lt32[0] ? 4 : 8) +
+                              (probes(w.b - w.a) + probes(w.b - w.q0)) * 8;
                 }
                 nb += probes(w.q1 - w.q0) * (4 + (leaf ? 0 : 2 * qt.bytes()));
                 if (!leaf) nb += (5 + probes(w.p1 - w.p0)) * qt.bytes();  // charged as the plain search
-                nb += 16;
+                nb += 8 + (G.lt32[0] ? 4 : 8);
             }
             const int32_t nbv = G.lnbr[d][pos];
-            put(te, s, G.lt[d][pos]);
+            put(te, s, list_time(G.lt32[d], G.lt[d], pos));
             if constexpr (kWin) put(posv, s, pos);
             if (a.recs) a.recs[r].eid[a.pi_pos[s]] = G.leid[d][pos];
             put(img, a.new_vertex[s], nbv);

@@ -32,7 +32,9 @@ struct DevGraph {
     const int32_t* dst;  // [m]
     const int64_t* t;    // [m]
     const int32_t* off[2];     // [2][n+1]: 0 = out, 1 = in
-    const int64_t* lt[2];      // T order: time
+    const int64_t* lt[2];      // T order: time (null when lt32 holds it)
+    const uint32_t* lt32[2];   // T order: time in 32 bits, when every shifted time is below
+                               // 2^32 - 1 (then x + 1 of any time x fits too); else null
     const int32_t* leid[2];    // T order: eid
     const int32_t* lnbr[2];    // T order: neighbour
     const int32_t* lown[2];    // T order: the list's owner (source for out-lists); null
@@ -260,6 +262,13 @@ __device__ __forceinline__ int32_t lower_bound_pos(const T* a, int32_t lo, int32
     return lo;
 }
 
+// The time at position i of a T order, given that list's two time tables
+// (the 32-bit one is read when the graph has it).
+__device__ __forceinline__ int64_t list_time(const uint32_t* lt32, const int64_t* lt, int64_t i) {
+    if (lt32) return (int64_t)lt32[i];
+    return lt[i];
+}
+
 template <typename T>
 __device__ __forceinline__ int32_t upper_bound_pos(const T* a, int32_t lo, int32_t hi, T key) {
     while (lo < hi) {
@@ -269,33 +278,3 @@ __device__ __forceinline__ int32_t upper_bound_pos(const T* a, int32_t lo, int32
     return lo;
 }
 
-// ---------------------------------------------------------------------------
-// The candidate window of a child edge (Claim "matching-edges-set"):
-// the child's edges at the vertex g (out-list when alpha = +, in-list when
-// alpha = -) with time in [t - delta, t] (beta '<') or [t, t + delta]
-// (beta '>'), clipped to I_i = [i delta, (i+2) delta) and to [0, T]; minus
-// the edges whose far endpoint is o (a contiguous run of the N order).
-// ---------------------------------------------------------------------------
-struct Window {
-    int32_t p0, p1;  // T-order positions of the window
-    int32_t q0, q1;  // N-order positions of the excluded run
-};
-
-__device__ __forceinline__ Window find_window(const DevGraph& G, int dir, int32_t g, int32_t o,
-                                              int64_t wlo, int64_t whi) {
-    Window w;
-    const int32_t a = G.off[dir][g], b = G.off[dir][g + 1];
-    if (wlo < 0) wlo = 0;
-    if (whi > G.T) whi = G.T;
-    if (wlo > whi) {
-        w.p0 = w.p1 = a;
-        w.q0 = w.q1 = a;
-        return w;
-    }
-    w.p0 = lower_bound_pos<int64_t>(G.lt[dir], a, b, wlo);
-    w.p1 = upper_bound_pos<int64_t>(G.lt[dir], w.p0, b, whi);
-    const u64 base = (u64)o << G.bt;
-    w.q0 = lower_bound_pos<u64>(G.nkey[dir], a, b, base | (u64)wlo);
-    w.q1 = upper_bound_pos<u64>(G.nkey[dir], w.q0, b, base | (u64)whi);
-    return w;
-}

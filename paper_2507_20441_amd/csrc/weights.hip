@@ -54,12 +54,17 @@ struct LevelArgs {
     unsigned long long* nbytes;  // counting variant: access-model bytes of the launch
 };
 
-// Element i (0 or 1) of a two-entry argument array, as a select: indexing
-// the kernel's argument arrays at run time had the compiler copy all of its
-// arguments to scratch in some variants.
+// Element i (0 or 1) of a two-entry argument array, as a select between the
+// two loaded values: indexing the kernel's argument arrays at run time had
+// the compiler copy all of its arguments to scratch, and so did a plain
+// select, which the optimiser may turn back into a select of the two
+// addresses.  The empty asm statement pins both values in scalar registers
+// first (the arrays are kernel arguments: uniform across the wave).
 template <typename T>
 __device__ __forceinline__ T sel2(const T (&arr)[2], int i) {
-    return i ? arr[1] : arr[0];
+    T x0 = arr[0], x1 = arr[1];
+    asm("" : "+s"(x0), "+s"(x1));
+    return i ? x1 : x0;
 }
 
 template <int B, int E, typename F>
@@ -130,33 +135,49 @@ __device__ __forceinline__ constexpr int bound_rank(int k) {
                                                                      : (k == 0 ? 1 : (k == 1 ? 0 : (k == 2 ? 3 : 2))));
 }
 
+// The first positions in [a, b) of a T order whose time is >= x[j], for NB
+// bounds in lockstep (independent loads per step).  x[j] lies in [0, T + 1],
+// which the time type TT holds.
+template <typename TT, int NB>
+__device__ __forceinline__ void lockstep_lower(const TT* lt, int32_t a, int32_t b, const int64_t (&x)[NB],
+                                               int32_t (&p)[NB]) {
+    TT xk[NB];
+    int32_t c[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        xk[j] = (TT)x[j];
+        c[j] = a;
+    }
+    int32_t n = b - a;
+    while (n > 1) {
+        const int32_t h = n >> 1;
+        TT y[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) y[j] = lt[c[j] + h];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) c[j] = y[j] < xk[j] ? c[j] + h : c[j];
+        n -= h;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) p[j] = a == b ? a : c[j] + (lt[c[j]] < xk[j] ? 1 : 0);
+}
+
 template <int NB, int Kind>
 __device__ __forceinline__ BoundsN<NB> level_bounds(const DevGraph& G, int dir, int32_t g, int32_t o,
                                                     const int64_t (&xs)[NB], bool exclude) {
     const int32_t a = sel2(G.off, dir)[g], b = sel2(G.off, dir)[g + 1];
-    const int64_t* lt = sel2(G.lt, dir);
     const u64* nk = sel2(G.nkey, dir);
     int64_t x[NB];
 #pragma unroll
     for (int j = 0; j < NB; ++j) x[j] = xs[j] < 0 ? 0 : (xs[j] > G.T + 1 ? G.T + 1 : xs[j]);
     BoundsN<NB> r;
     r.len = b - a;
-    // --- T order: the NB bounds in lockstep (independent loads per step)
-    int32_t c[NB];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) c[j] = a;
-    int32_t n = b - a;
-    while (n > 1) {
-        const int32_t h = n >> 1;
-        int64_t y[NB];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) y[j] = lt[c[j] + h];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) c[j] = y[j] < x[j] ? c[j] + h : c[j];
-        n -= h;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) r.p[j] = a == b ? a : c[j] + (lt[c[j]] < x[j] ? 1 : 0);
+    // --- T order
+    const uint32_t* lt32 = sel2(G.lt32, dir);
+    if (lt32)
+        lockstep_lower<uint32_t, NB>(lt32, a, b, x, r.p);
+    else
+        lockstep_lower<int64_t, NB>(sel2(G.lt, dir), a, b, x, r.p);
 
     // --- N order
     if (!exclude || a == b) {
@@ -218,7 +239,8 @@ __device__ __forceinline__ W window_mass(int32_t p0, int32_t p1, int32_t q0, int
 // The counting variant returns the bytes the edge's work reads and writes
 // under the access model: each read or write its element size; a list search
 // of L entries ceil(log2 L) + 1 probes of each of its six bounds (three in
-// the T order, three in the N order, 8 B each; eight for an unordered child).
+// the T order, of the list's time size, and three 8 B keys in the N order;
+// eight bounds for an unordered child).
 template <typename W, bool kCount, bool kPO>
 __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
     const DevGraph& G = a.G;
@@ -227,7 +249,9 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
     const int32_t e = a.walk < 0 ? (int32_t)p : sel2(G.leid, a.walk)[p];
     int32_t u, v;
     int64_t t;
-    if constexpr (kCount) nb += 16 + (a.walk < 0 ? 0 : 4);
+    // T-order times in bytes (4 in 32-bit lists)
+    const u64 tsz = G.lt32[0] ? 4 : 8;
+    if constexpr (kCount) nb += a.walk < 0 ? 16 : 12 + tsz;
     if (a.walk < 0 || !sel2(G.lown, a.walk)) {
         u = G.src[e];
         v = G.dst[e];
@@ -236,7 +260,7 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
         const int32_t own = sel2(G.lown, a.walk)[p], nbr = sel2(G.lnbr, a.walk)[p];
         u = a.walk == 0 ? own : nbr;
         v = a.walk == 0 ? nbr : own;
-        t = sel2(G.lt, a.walk)[p];
+        t = list_time(sel2(G.lt32, a.walk), sel2(G.lt, a.walk), p);
     }
     const int64_t blk = t / a.ilen;
     const bool hasB = blk >= 1;
@@ -272,7 +296,7 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
             if constexpr (kCount) {
                 int it = 0;
                 for (int32_t n = r.len; n > 1; n -= n >> 1) ++it;
-                nb += 8 + (u64)64 * it + (r.len > 0 ? 64 : 0);
+                nb += 8 + (4 * tsz + 32) * (u64)(it + (r.len > 0 ? 1 : 0));
             }
         } else {
             // x values (first position with time >= x):
@@ -306,7 +330,7 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
             if constexpr (kCount) {
                 int it = 0;
                 for (int32_t n = r.len; n > 1; n -= n >> 1) ++it;
-                nb += 8 + (u64)48 * it + (r.len > 0 ? 48 : 0);
+                nb += 8 + (3 * tsz + 24) * (u64)(it + (r.len > 0 ? 1 : 0));
             }
         }
         if constexpr (kCount) {

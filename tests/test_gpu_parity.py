@@ -212,6 +212,36 @@ def test_default_tree_multi_tile_graph(T, name, edges, delta):
                k=20000)
 
 
+def stretched(g, top):
+    """g with its shifted times scaled so that the largest is exactly top."""
+    t = g.t - g.t.min()
+    scale = top // int(t.max())
+    t = t * scale
+    t[int(np.argmax(t))] = top
+    return W.TemporalGraph(g.src, g.dst, t, g.n), scale
+
+
+@pytest.mark.parametrize("top", [2**32 - 2, 2**32 - 1, 2**33 + 5], ids=["last_32_bit", "first_64_bit", "beyond"])
+def test_time_span_at_and_beyond_32_bits(T, top):
+    """Lists hold 32-bit times when every shifted time is below 2^32 - 1 and
+    64-bit ones otherwise.  A graph stretched so that its largest shifted
+    time is the last value of the 32-bit form, the first of the 64-bit one,
+    or beyond: its list times, then weights and samples of three motifs in
+    both sampler shapes (k below 2^16, and the root-sorted one reading kept
+    windows), against the oracle."""
+    g, scale = stretched(W.small_graph(3000, 13, n=60, span=6000), top)
+    og, tg = pair(T, g)
+    assert tg.info()["t_span"] == top
+    s, d, t = og.edges()
+    for name in ("out", "in"):
+        assert (tg.export(f"{name}_t") == t[tg.export(f"{name}_eid")]).all(), name
+    for name, delta in (("3cycle", 50), ("4cycle", 70), ("6chain", 70)):
+        edges = W.MOTIFS[name]
+        say("span", top, name)
+        check_prep(T, og, tg, edges, delta * scale, O.default_tree(O.make_motif(edges, 1)), seeds=(1,), k=3000)
+        check_prep(T, og, tg, edges, delta * scale, O.default_tree(O.make_motif(edges, 1)), seeds=(2,), k=70000)
+
+
 def test_tiny_workload_full_run_is_bit_identical(T):
     """The small workload in full: 1,000 vertices, 20,000 edges, 3-cycle at
     delta = 1,000, 100,000 samples, seed 1."""
@@ -451,22 +481,28 @@ def test_stage_timing_mask(T):
 # ---------------------------------------------------------------------------
 # Access-model bytes of the level kernels
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("scale", [1, 1 << 14], ids=["32_bit_times", "64_bit_times"])
 @pytest.mark.parametrize("tree_edges,attach", [([0, 1], "out-list of the center's destination"),
                                                ([0, 2], "in-list of the center's source")])
-def test_level_model_bytes_match_host_count(T, tree_edges, attach):
+def test_level_model_bytes_match_host_count(T, tree_edges, attach, scale):
     """tm_weights_model_bytes against the access model counted on the host.
 
     3-cycle a->b, b->c, c->a with a two-edge tree centred on a->b: one level
     launch over every edge e, whose one leaf child is searched in one list of
     length L_e (b->c: the out-list of e's destination; c->a: the in-list of
-    e's source).  Per edge: the walked entry (owner, neighbour, time, eid:
-    20 B), the list offsets (8 B), six bounds of ceil(log2 L) + 1 probes of
-    8 B (no probes for an empty list), the two kept windows (32 B) and the
-    two products (16 B)."""
-    say("level model bytes", tree_edges)
+    e's source).  Per edge: the walked entry (owner, neighbour, eid: 12 B,
+    and its time), the list offsets (8 B), ceil(log2 L) + 1 probes (none for
+    an empty list) of each of six bounds: three list times and three 8 B
+    keys, the two kept windows (32 B) and the two products (16 B).  A time
+    is 4 B when every shifted time is below 2^32 - 1 (the graph as drawn),
+    else 8 B (its times scaled by 2^14)."""
+    say("level model bytes", tree_edges, scale)
     g = W.small_graph(40000, 4, n=2000, span=10**6)
-    tg = T.Graph(g.src, g.dst, g.t, g.n)
-    mo = T.make_motif(W.MOTIFS["3cycle"], 3600)
+    t = (g.t - g.t.min()) * scale
+    tg = T.Graph(g.src, g.dst, t, g.n)
+    tsz = 4 if tg.info()["t_span"] < 2**32 - 1 else 8
+    assert tsz == (4 if scale == 1 else 8)
+    mo = T.make_motif(W.MOTIFS["3cycle"], 3600 * scale)
     got = T.weights_model_bytes(tg, mo, T.make_tree(tree_edges, 0))
     assert got == T.weights_model_bytes(tg, mo, T.make_tree(tree_edges, 0))
     src, dst = tg.export("src").astype(np.int64), tg.export("dst").astype(np.int64)
@@ -480,7 +516,7 @@ def test_level_model_bytes_match_host_count(T, tree_edges, attach):
         live = n > 1
         steps[live] += 1
         n[live] -= n[live] >> 1
-    expect = int(np.sum(20 + 8 + 48 * (steps + (L > 0)) + 32 + 16))
+    expect = int(np.sum(12 + tsz + 8 + (3 * tsz + 24) * (steps + (L > 0)) + 32 + 16))
     tg.close()
     assert got == expect, (attach, got, expect)
 
@@ -573,7 +609,8 @@ def test_level_model_bytes_two_passes(T):
     pass 1 walks the in-lists (child c->d: the out-list of e's destination,
     L1 entries), reads the first pass's products through the position index
     (4 B, 8 B per interval of e: two unless e lies in the first block) and
-    writes its windows at out-list positions (4 B more)."""
+    writes its windows at out-list positions (4 B more).  List times are
+    4 B here (every shifted time is below 2^32 - 1)."""
     say("level model bytes, two passes")
     delta = 3600
     g = W.small_graph(40000, 4, n=2000, span=10**6)
@@ -596,7 +633,7 @@ def test_level_model_bytes_two_passes(T):
     L0 = np.bincount(dst, minlength=g.n)[src]
     L1 = np.bincount(src, minlength=g.n)[dst]
     has_b = (t // delta) >= 1
-    pass0 = 20 + 8 + 48 * (steps(L0) + (L0 > 0)) + 32 + 16
-    pass1 = 20 + 4 + 8 * (1 + has_b) + 8 + 48 * (steps(L1) + (L1 > 0)) + 36 + 16
+    pass0 = 16 + 8 + 36 * (steps(L0) + (L0 > 0)) + 32 + 16
+    pass1 = 16 + 4 + 8 * (1 + has_b) + 8 + 36 * (steps(L1) + (L1 > 0)) + 36 + 16
     expect = int(np.sum(pass0 + pass1))
     assert got == expect, (got, expect)

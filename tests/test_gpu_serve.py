@@ -194,6 +194,31 @@ def test_oracle_agrees(T, world):
         srv.close()
 
 
+def test_oracle_agrees_beyond_32_bit_times(T):
+    """Server sets search their child windows (they keep none): on a graph
+    whose shifted times exceed 32 bits the lists hold 64-bit times, and
+    served results still equal the oracle's."""
+    g = W.small_graph(4000, 11, n=200, span=80000)
+    t = (g.t - g.t.min()) * (1 << 17)
+    og = O.Graph(g.src, g.dst, t, g.n)
+    tg = T.Graph(g.src, g.dst, t, g.n)
+    assert tg.info()["t_span"] >= 2**32
+    srv = T.Server(1 << 30, pass_samples=1 << 13, job_chunk=1 << 10)
+    try:
+        gid = srv.add_graph(tg)
+        cases = [("3cycle", 300 << 17, 5000, 3), ("4cycle", 1500 << 17, 7000, 4),
+                 ("scatter_gather", 1500 << 17, 3000, 5)]
+        tickets = [srv.submit(gid, T.make_motif(W.MOTIFS[n], d), k, s) for n, d, k, s in cases]
+        for (n, d, k, s), tk in zip(cases, tickets):
+            r, _ = srv.wait(tk)
+            P = O.Prep(og, O.make_motif(W.MOTIFS[n], d))
+            o = P.sample(s, k)[0]
+            assert r.acc2.value == o.acc2.value and r.W.value == P.W and r.n_valid == o.n_valid, n
+            assert r.estimate == o.estimate and r.std_error == o.std_error
+    finally:
+        srv.close()
+
+
 def test_concurrent_submitters(T, world):
     gs, tg, qs, alone = world
     srv = T.Server(1 << 32, pass_samples=1 << 15, job_chunk=1 << 12)
