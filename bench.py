@@ -402,6 +402,7 @@ def serving(args):
         del u, v, t
         torch.cuda.empty_cache()
         log(f"graph n={sp['n']} m={sp['m']} built, {time.perf_counter() - t0:.1f} s")
+    T.release_cached()  # the builds' temporaries go back to HIP before the budget is taken
     free = torch.cuda.mem_get_info()[0]
     budget = int(args.serve_budget_gb * 2**30) if args.serve_budget_gb > 0 else int(free - 4 * 2**30)
     queries = W.serving_queries(args.serve_seconds, args.serve_rate, len(graphs))

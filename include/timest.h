@@ -531,6 +531,14 @@ void tm_profile_stages(uint32_t mask);
 /* Copy the accumulated times; reset = 1 clears them afterwards. */
 int tm_profile_read(tm_profile* out, int reset);
 
+/* Device memory.  Blocks the library releases are kept for its later
+ * allocations on the current device (they go back to HIP by themselves only
+ * when an allocation fails); this returns every such block to HIP now, after
+ * a device synchronisation, so that other users of the device (a caching
+ * allocator, a server budget taken from the free memory) see it.  Blocks
+ * from a caller's tm_allocator are never kept.  Returns TM_OK. */
+int tm_release_cached(void);
+
 /* Bytes the sampling kernel's access model requests for samples j0 ..
  * j0 + count - 1 (a counting pass, not timed, same draws and the same kernel
  * variant as tm_sample with that count): every binary search over a range of
@@ -544,8 +552,9 @@ int tm_sample_model_bytes(tm_weights* w, uint64_t seed, uint64_t j0, uint64_t co
 /* Bytes the level kernels of a weight build (Alg. 2: the s-weights of every
  * non-leaf tree edge, level by level) request under their access model: a
  * search over a list of L entries is charged ceil(log2 L) + 1 probes of
- * each of its six bounds (three over the T order, three over the N order,
- * 8 B each), every other read and write its element size (the edge, the
+ * each of its six bounds (three over the T order, of the lists' time size:
+ * 4 B when every shifted time is below 2^32 - 1, else 8 B; three 8 B keys
+ * over the N order), every other read and write its element size (the edge, the
  * first pass's products, the children's prefix entries, the kept windows,
  * the products written).  The set is built as tm_weights_create_ex with
  * constraints TM_C_ALL builds it (a counting variant of the same kernels,

@@ -44,6 +44,11 @@ void prof_add(int stage, double ms) {
     g_prof.launches[stage] += 1;
 }
 
+extern "C" int tm_release_cached(void) {
+    dev_cache_trim();
+    return TM_OK;
+}
+
 extern "C" void tm_profile_enable(int on) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = on != 0;
@@ -495,8 +500,24 @@ extern "C" int tm_graph_export(const tm_graph* g, int which, void* host_out, voi
             for (size_t i = 0; i < m; ++i) out[i] = (int64_t)h32[i];
             return TM_OK;
         }
-        case TM_ARR_OUT_NBR: p = D.lnbr[0]; bytes = m * 4; break;
-        case TM_ARR_IN_NBR: p = D.lnbr[1]; bytes = m * 4; break;
+        case TM_ARR_OUT_NBR:
+        case TM_ARR_IN_NBR: {
+            const int dir = which == TM_ARR_IN_NBR ? 1 : 0;
+            if (!D.lnt[dir]) {
+                p = D.lnbr[dir];
+                bytes = m * 4;
+                break;
+            }
+            // (neighbour, time) records: the neighbours taken out on the host
+            if (m == 0) return TM_OK;
+            std::vector<uint2> hnt(m);
+            hipStream_t st = as_stream(stream);
+            TM_HIP(hipMemcpyAsync(hnt.data(), D.lnt[dir], m * sizeof(uint2), hipMemcpyDeviceToHost, st));
+            TM_HIP(sync_stream(st));
+            int32_t* out = static_cast<int32_t*>(host_out);
+            for (size_t i = 0; i < m; ++i) out[i] = (int32_t)hnt[i].x;
+            return TM_OK;
+        }
         case TM_ARR_OUT_POS: p = D.tpos[0]; bytes = m * 4; break;
         case TM_ARR_IN_POS: p = D.tpos[1]; bytes = m * 4; break;
         case TM_ARR_OUTN_KEY: p = D.nkey[0]; bytes = m * 8; break;

@@ -162,6 +162,12 @@ __global__ void n_order_fix_kernel(const uint32_t* nbr, const TT* ntime, const i
     nxref[q] = (uint32_t)neid[q] < (uint64_t)m ? tpos[neid[q]] : -1;
 }
 
+// (neighbour, time) records of a T order with 32-bit times.
+__global__ void pack_nt_kernel(const uint32_t* nbr, const uint32_t* t, int64_t m, uint2* nt) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p < m) nt[p] = make_uint2(nbr[p], t[p]);
+}
+
 // List offsets from the owner-sorted keys: off[v] is the first position whose
 // owner is >= v.  Position p writes the offsets of the owners in
 // (key[p-1], key[p]]; the last position also closes the owners after it.
@@ -261,7 +267,12 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
     // 2^32 - 1; t32e: those times by eid, the list sorts' input.
     const bool narrow = g->T < (int64_t)0xFFFFFFFFll;
     uint32_t* t32e = nullptr;
+    uint32_t* nbr32[2] = {nullptr, nullptr};  // 32-bit times: the T orders' neighbours until packed
     auto release = [&]() {
+        for (uint32_t*& b : nbr32) {
+            if (b) (void)dev_free(b, st);
+            b = nullptr;
+        }
         for (u64*& w : work) {
             if (w) (void)dev_free(w, st);
             w = nullptr;
@@ -365,12 +376,20 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
         uint32_t* nbr_carried = keep_own ? reinterpret_cast<uint32_t*>(work[3]) : nbr_tmp;
         int32_t* tpos[2] = {nullptr, nullptr};
         TT* ltab[2] = {nullptr, nullptr};
+        uint32_t* lnbr_of[2] = {nullptr, nullptr};  // each T order's neighbours (the N-order sorts' keys)
         for (int dir = 0; dir < 2; ++dir) {
             TT* lt = nullptr;
             int32_t *leid = nullptr, *lnbr = nullptr, *lown = nullptr, *off = nullptr;
             TM_TRY(arena_alloc(g->arena, &lt, m));
             TM_TRY(arena_alloc(g->arena, &leid, m));
-            TM_TRY(arena_alloc(g->arena, &lnbr, m));
+            if constexpr (sizeof(TT) == 4) {
+                // the neighbours end up in the (neighbour, time) records
+                if (dev_alloc((void**)&nbr32[dir], (size_t)m * sizeof(uint32_t), st) != hipSuccess)
+                    return tm_fail(TM_ENOMEM, "graph: work arrays");
+                lnbr = reinterpret_cast<int32_t*>(nbr32[dir]);
+            } else {
+                TM_TRY(arena_alloc(g->arena, &lnbr, m));
+            }
             if (keep_own) TM_TRY(arena_alloc(g->arena, &lown, m));
             TM_TRY(arena_alloc(g->arena, &off, (size_t)n + 1));
             TM_TRY(arena_alloc(g->arena, &tpos[dir], (size_t)m));
@@ -393,15 +412,24 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
             D.tpos[dir] = tpos[dir];
             ltab[dir] = lt;
             if constexpr (sizeof(TT) == 4) {
+                uint2* nt = nullptr;
+                TM_TRY(arena_alloc(g->arena, &nt, m));
+                hipLaunchKernelGGL(pack_nt_kernel, dim3(grid_for(m)), dim3(kBlock), 0, st,
+                                   (const uint32_t*)lnbr, (const uint32_t*)lt, m, nt);
+                if (hipGetLastError() != hipSuccess) return tm_fail(TM_EDEVICE, "graph: list launch");
                 D.lt32[dir] = reinterpret_cast<const uint32_t*>(lt);
                 D.lt[dir] = nullptr;
+                D.lnt[dir] = nt;
+                D.lnbr[dir] = nullptr;
             } else {
                 D.lt[dir] = reinterpret_cast<const int64_t*>(lt);
                 D.lt32[dir] = nullptr;
+                D.lnt[dir] = nullptr;
+                D.lnbr[dir] = lnbr;
             }
+            lnbr_of[dir] = reinterpret_cast<uint32_t*>(lnbr);
             D.leid[dir] = leid;
             D.lown[dir] = lown;
-            D.lnbr[dir] = lnbr;
         }
         // N order of dir d: the T order of the other direction (sorted by this
         // direction's neighbour, then time) stably re-sorted by this
@@ -414,7 +442,7 @@ int graph_build(tm_graph* g, const int32_t* src, const int32_t* dst, const int64
             TM_TRY(arena_alloc(g->arena, &nxref, m));
             TM_TRY(arena_alloc(g->arena, &neid, m));
             L in, out;
-            in.k = reinterpret_cast<uint32_t*>(const_cast<int32_t*>(D.lnbr[other]));
+            in.k = lnbr_of[other];
             in.v0 = reinterpret_cast<V*>(ltab[other]);
             in.v1 = reinterpret_cast<uint32_t*>(const_cast<int32_t*>(D.leid[other]));
             in.v2 = own[other];

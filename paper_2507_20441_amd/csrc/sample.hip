@@ -765,8 +765,8 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const Samp
             if constexpr (kWin) posv[0] = pos;
             const int rd = a.root_dir;
             e0 = G.leid[rd][pos];
-            te[0] = list_time(G.lt32[rd], G.lt[rd], pos);
-            const int32_t nbr0 = G.lnbr[rd][pos];
+            int32_t nbr0;
+            list_entry(G.lnt[rd], G.lnbr[rd], G.lt[rd], pos, nbr0, te[0]);
             const int32_t own0 = G.lown[rd] ? G.lown[rd][pos] : (rd ? G.dst[e0] : G.src[e0]);
             u0 = rd ? nbr0 : own0;
             v0 = rd ? own0 : nbr0;
@@ -873,8 +873,10 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const Samp
                 if (!leaf) nb += (5 + probes(w.p1 - w.p0)) * qt.bytes();  // charged as the plain search
                 nb += 8 + (G.lt32[0] ? 4 : 8);
             }
-            const int32_t nbv = G.lnbr[d][pos];
-            put(te, s, list_time(G.lt32[d], G.lt[d], pos));
+            int32_t nbv;
+            int64_t tv;
+            list_entry(G.lnt[d], G.lnbr[d], G.lt[d], pos, nbv, tv);
+            put(te, s, tv);
             if constexpr (kWin) put(posv, s, pos);
             if (a.recs) a.recs[r].eid[a.pi_pos[s]] = G.leid[d][pos];
             put(img, a.new_vertex[s], nbv);

@@ -36,7 +36,9 @@ struct DevGraph {
     const uint32_t* lt32[2];   // T order: time in 32 bits, when every shifted time is below
                                // 2^32 - 1 (then x + 1 of any time x fits too); else null
     const int32_t* leid[2];    // T order: eid
-    const int32_t* lnbr[2];    // T order: neighbour
+    const int32_t* lnbr[2];    // T order: neighbour (null when lnt holds it)
+    const uint2* lnt[2];       // T order, with 32-bit times: (neighbour, time) per position, one
+                               // read for both (lt32 keeps the times for searches); else null
     const int32_t* lown[2];    // T order: the list's owner (source for out-lists); null
                                // above 2^28 edges (memory goes to weight sets there)
     const u64* nkey[2];        // N order: neighbour << bt | time
@@ -262,11 +264,19 @@ __device__ __forceinline__ int32_t lower_bound_pos(const T* a, int32_t lo, int32
     return lo;
 }
 
-// The time at position i of a T order, given that list's two time tables
-// (the 32-bit one is read when the graph has it).
-__device__ __forceinline__ int64_t list_time(const uint32_t* lt32, const int64_t* lt, int64_t i) {
-    if (lt32) return (int64_t)lt32[i];
-    return lt[i];
+// The neighbour and time at position i of a T order, given that list's
+// tables: one (neighbour, time) record when the graph has 32-bit times, else
+// the neighbour and 64-bit time arrays.
+__device__ __forceinline__ void list_entry(const uint2* nt, const int32_t* nbr, const int64_t* lt, int64_t i,
+                                           int32_t& v, int64_t& t) {
+    if (nt) {
+        const uint2 x = nt[i];
+        v = (int32_t)x.x;
+        t = (int64_t)x.y;
+    } else {
+        v = nbr[i];
+        t = lt[i];
+    }
 }
 
 template <typename T>

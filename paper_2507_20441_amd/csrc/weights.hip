@@ -257,10 +257,11 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
         v = G.dst[e];
         t = G.t[e];
     } else {
-        const int32_t own = sel2(G.lown, a.walk)[p], nbr = sel2(G.lnbr, a.walk)[p];
+        const int32_t own = sel2(G.lown, a.walk)[p];
+        int32_t nbr;
+        list_entry(sel2(G.lnt, a.walk), sel2(G.lnbr, a.walk), sel2(G.lt, a.walk), p, nbr, t);
         u = a.walk == 0 ? own : nbr;
         v = a.walk == 0 ? nbr : own;
-        t = list_time(sel2(G.lt32, a.walk), sel2(G.lt, a.walk), p);
     }
     const int64_t blk = t / a.ilen;
     const bool hasB = blk >= 1;
@@ -729,8 +730,9 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, int* ovf_c, bool check_
                 const W* vp = static_cast<const W*>(w->vals[s][0]);
                 TM_TRY(device_exclusive_scan2<W>(Plain<W>{vp}, m, qt[0], qt[1], ovf, st));
                 TM_TRY(device_exclusive_scan2<W>(ListGather<W>{vp, g->d.nxref[dir]}, m, qn[0], qn[1], ovf, st));
+                // lean sets (memory over speed) search the full tables
                 const int64_t nc = (m >> kCoarseBits) + 1;
-                for (int par = 0; par < 2; ++par) {
+                for (int par = 0; par < 2 && !w->lean; ++par) {
                     W* c;
                     TM_TRY(arena_alloc(w->arena, &c, (size_t)nc));
                     hipLaunchKernelGGL((coarse_kernel<W>), dim3(grid_for(nc)), dim3(kBlock), 0, st,
@@ -892,7 +894,8 @@ u64 weights_footprint(const HostPlan& P, int64_t m, int64_t q, bool wide, bool l
     u64 b = 0;
     for (int s = 1; s < P.nt; ++s)
         if (P.n_children[s] > 0)
-            b += 4 * blk((u64)(m + 1) * wsz) + 2 * blk((u64)((m >> kCoarseBits) + 1) * wsz);  // qt, qn, coarse qt
+            b += 4 * blk((u64)(m + 1) * wsz) +
+                 (lean ? 0 : 2 * blk((u64)((m >> kCoarseBits) + 1) * wsz));  // qt, qn, coarse qt
     b += 2 * blk((u64)(m + 1) * wsz);                   // qc, per parity
     b += 2 * blk((u64)q * 4) + blk((u64)(q + 1) * wsz); // ilo, ihi, cumW
     b += blk((u64)q * wsz);                              // ioff

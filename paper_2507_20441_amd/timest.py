@@ -205,6 +205,7 @@ def lib():
         L.tm_batch_plan_run.argtypes = [vp, vp, C.POINTER(Result)]
         L.tm_batch_plan_destroy.argtypes = [vp]
         L.tm_batch_plan_destroy.restype = None
+        L.tm_release_cached.argtypes = []
         L.tm_profile_enable.argtypes = [C.c_int]
         L.tm_profile_enable.restype = None
         L.tm_profile_stages.argtypes = [C.c_uint32]
@@ -542,6 +543,11 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def release_cached():
+    """Return the library's cached device blocks to HIP (tm_release_cached)."""
+    _check(lib().tm_release_cached(), "release_cached")
 
 
 def profile_enable(on=True):

@@ -219,6 +219,24 @@ def test_oracle_agrees_beyond_32_bit_times(T):
         srv.close()
 
 
+def test_release_cached_returns_blocks(T):
+    """tm_release_cached: the blocks a graph build released go back to HIP
+    (free device memory rises), and later calls still give the same results."""
+    import torch
+    g = W.small_graph(400000, 17, n=20000, span=4000000)
+    tg = T.Graph(g.src, g.dst, g.t, g.n)
+    mo = T.make_motif(W.MOTIFS["4cycle"], 3600)
+    a = T.estimate(tg, mo, 50000, 7)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    T.release_cached()
+    free1 = torch.cuda.mem_get_info()[0]
+    assert free1 > free0, (free0, free1)
+    b = T.estimate(tg, mo, 50000, 7)
+    assert same(a, b)
+    tg.close()
+
+
 def test_concurrent_submitters(T, world):
     gs, tg, qs, alone = world
     srv = T.Server(1 << 32, pass_samples=1 << 15, job_chunk=1 << 12)
