@@ -266,10 +266,11 @@ void tm_server::run_builder() {
         }
         const bool needs_wide = w && w->needs_wide;
         if (needs_wide) {
-            // give the 64-bit blocks back to HIP before the larger set is built
+            // the 64-bit blocks go back to the block cache, which serves the
+            // larger build from them where sizes allow (and returns cached
+            // blocks to HIP by itself when an allocation fails)
             tm_weights_destroy(w);
             w = nullptr;
-            dev_cache_trim();
         }
         const std::string err = rc != TM_OK ? tm_last_error() : "";
         lk.lock();
