@@ -204,21 +204,40 @@ __global__ void __launch_bounds__(kBlock) scan2_tiles_kernel(F f, int64_t n, u12
 template <typename T, typename F>
 __global__ void __launch_bounds__(kBlock)
 scan2_apply_kernel(F f, int64_t n, const u128* part0, const u128* part1, T* out0, T* out1, int* ovf) {
+    using V = decltype(f(0).a);
+    // Values come in and results go out in rounds of kBlock consecutive
+    // entries (coalesced), through LDS; in between each lane scans a run of
+    // kScanItems consecutive entries.  Entry j of the tile sits at LDS
+    // position j + j / kScanItems, so that the lanes reading their runs do
+    // not all fall on the same banks.
+    constexpr int kPad = kScanTile + kScanTile / kScanItems;
+    constexpr size_t kElt = sizeof(V) > sizeof(T) ? sizeof(V) : sizeof(T);
+    __shared__ __align__(16) unsigned char sbuf[2 * kPad * kElt];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    // each lane owns kScanItems consecutive values of the tile
-    const int64_t first = base + (int64_t)threadIdx.x * kScanItems;
+    V* lv0 = reinterpret_cast<V*>(sbuf);
+    V* lv1 = lv0 + kPad;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int j = k * kBlock + (int)threadIdx.x;
+        const int64_t i = base + j;
+        V a = 0, b = 0;
+        if (i < n) {
+            const auto x = f(i);
+            a = x.a;
+            b = x.b;
+        }
+        lv0[j + j / kScanItems] = a;
+        lv1[j + j / kScanItems] = b;
+    }
+    __syncthreads();
     u128 v0[kScanItems], v1[kScanItems];
     u128 s0 = 0, s1 = 0;
     bool carry = false;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        const int64_t i = first + k;
-        v0[k] = v1[k] = 0;
-        if (i < n) {
-            const auto x = f(i);
-            v0[k] = to_u128(x.a);
-            v1[k] = to_u128(x.b);
-        }
+        const int j = (int)threadIdx.x * kScanItems + k;
+        v0[k] = to_u128(lv0[j + j / kScanItems]);
+        v1[k] = to_u128(lv1[j + j / kScanItems]);
         const u128 y0 = s0 + v0[k], y1 = s1 + v1[k];
         if (y0 < s0 || y1 < s1) carry = true;
         s0 = y0;
@@ -227,17 +246,28 @@ scan2_apply_kernel(F f, int64_t n, const u128* part0, const u128* part1, T* out0
     u128 tot0, tot1;
     u128 run0 = part0[blockIdx.x] + block_exclusive(s0, &tot0, &carry);
     u128 run1 = part1[blockIdx.x] + block_exclusive(s1, &tot1, &carry);
+    __syncthreads();  // every lane has read its values: the buffer takes the results
+    T* lo0 = reinterpret_cast<T*>(sbuf);
+    T* lo1 = lo0 + kPad;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        const int64_t i = first + k;
-        if (i < n) {
-            out0[i] = (T)run0;
-            out1[i] = (T)run1;
-        }
+        const int j = (int)threadIdx.x * kScanItems + k;
+        lo0[j + j / kScanItems] = (T)run0;
+        lo1[j + j / kScanItems] = (T)run1;
         const u128 y0 = run0 + v0[k], y1 = run1 + v1[k];
         if (y0 < run0 || y1 < run1) carry = true;
         run0 = y0;
         run1 = y1;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int j = k * kBlock + (int)threadIdx.x;
+        const int64_t i = base + j;
+        if (i < n) {
+            out0[i] = lo0[j + j / kScanItems];
+            out1[i] = lo1[j + j / kScanItems];
+        }
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         const u128 t0 = part0[gridDim.x], t1 = part1[gridDim.x];
