@@ -363,7 +363,7 @@ def batched(args):
         },
         "one_job_per_launch": {"ms": round(tj * 1e3, 3), "samples_per_s": round(total / tj, 1)},
         "batched": {"ms": round(tb * 1e3, 3), "samples_per_s": round(total / tb, 1),
-                    "schedule": {"tile": choice[0], "blocks": choice[1]}},
+                    "schedule": {"tile": choice[0], "blocks": choice[1], "root_lds": choice[2]}},
         "graph_replay": {"ms": round(tgr * 1e3, 3), "samples_per_s": round(total / tgr, 1),
                          "record_ms": round(record_ms, 1)},
         "speedup": round(tj / tgr, 3),
@@ -371,7 +371,7 @@ def batched(args):
         "bit_identical": same,
         "jobs_128bit": wide,
         "rel_ci95_max": max(rel) if rel else None,
-        "autotune_ms": {f"{t},{b}": round(v, 3) for (t, b), v in times.items()},
+        "autotune_ms": {",".join(str(x) for x in key): round(v, 3) for key, v in times.items()},
     }
     print(json.dumps(line), flush=True)
 
