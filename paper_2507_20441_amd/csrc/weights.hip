@@ -137,10 +137,13 @@ __device__ __forceinline__ constexpr int bound_rank(int k) {
 
 // The first positions in [a, b) of a T order whose time is >= x[j], for NB
 // bounds in lockstep (independent loads per step).  x[j] lies in [0, T + 1],
-// which the time type TT holds.
-template <typename TT, int NB>
+// which the time type TT holds.  With kN, the same halving steps also find
+// q, the bound of (kq, leq) in the N order over the same range: its probe
+// is one more independent load per step instead of a second chain of
+// dependent ones after the first.
+template <typename TT, int NB, bool kN>
 __device__ __forceinline__ void lockstep_lower(const TT* lt, int32_t a, int32_t b, const int64_t (&x)[NB],
-                                               int32_t (&p)[NB]) {
+                                               int32_t (&p)[NB], const u64* nk, u64 kq, bool leq, int32_t& q) {
     TT xk[NB];
     int32_t c[NB];
 #pragma unroll
@@ -148,18 +151,23 @@ __device__ __forceinline__ void lockstep_lower(const TT* lt, int32_t a, int32_t 
         xk[j] = (TT)x[j];
         c[j] = a;
     }
+    int32_t cq = a;
     int32_t n = b - a;
     while (n > 1) {
         const int32_t h = n >> 1;
         TT y[NB];
 #pragma unroll
         for (int j = 0; j < NB; ++j) y[j] = lt[c[j] + h];
+        u64 z = 0;
+        if constexpr (kN) z = nk[cq + h];
 #pragma unroll
         for (int j = 0; j < NB; ++j) c[j] = y[j] < xk[j] ? c[j] + h : c[j];
+        if constexpr (kN) cq = key_before(z, kq, leq) ? cq + h : cq;
         n -= h;
     }
 #pragma unroll
     for (int j = 0; j < NB; ++j) p[j] = a == b ? a : c[j] + (lt[c[j]] < xk[j] ? 1 : 0);
+    if constexpr (kN) q = a == b ? a : cq + (key_before(nk[cq], kq, leq) ? 1 : 0);
 }
 
 template <int NB, int Kind>
@@ -172,19 +180,21 @@ __device__ __forceinline__ BoundsN<NB> level_bounds(const DevGraph& G, int dir, 
     for (int j = 0; j < NB; ++j) x[j] = xs[j] < 0 ? 0 : (xs[j] > G.T + 1 ? G.T + 1 : xs[j]);
     BoundsN<NB> r;
     r.len = b - a;
-    // --- T order
     const uint32_t* lt32 = sel2(G.lt32, dir);
-    if (lt32)
-        lockstep_lower<uint32_t, NB>(lt32, a, b, x, r.p);
-    else
-        lockstep_lower<int64_t, NB>(sel2(G.lt, dir), a, b, x, r.p);
-
-    // --- N order
     if (!exclude || a == b) {
+        // T order only: no excluded run
+        int32_t unused = a;
+        if (lt32)
+            lockstep_lower<uint32_t, NB, false>(lt32, a, b, x, r.p, nk, 0, false, unused);
+        else
+            lockstep_lower<int64_t, NB, false>(sel2(G.lt, dir), a, b, x, r.p, nk, 0, false, unused);
 #pragma unroll
-        for (int j = 0; j < NB; ++j) r.q[j] = a;  // no excluded run
+        for (int j = 0; j < NB; ++j) r.q[j] = a;
         return r;
     }
+    // N order: all of the lane's keys share the excluded neighbour o; the
+    // smallest is searched together with the T-order bounds, the others are
+    // reached by galloping from it (they lie a few entries on, in o's run)
     const u64 base = (u64)o << G.bt;
     u64 kx[NB];
     bool le[NB];
@@ -193,16 +203,13 @@ __device__ __forceinline__ BoundsN<NB> level_bounds(const DevGraph& G, int dir, 
         le[j] = x[j] > G.T;
         kx[j] = base + (u64)(le[j] ? G.T : x[j]);
     }
-    {
-        constexpr int j0 = bound_rank<Kind>(0);
-        int32_t cq = a, nq = b - a;
-        while (nq > 1) {
-            const int32_t h = nq >> 1;
-            cq = key_before(nk[cq + h], kx[j0], le[j0]) ? cq + h : cq;
-            nq -= h;
-        }
-        r.q[j0] = cq + (key_before(nk[cq], kx[j0], le[j0]) ? 1 : 0);
-    }
+    constexpr int j0 = bound_rank<Kind>(0);
+    int32_t q0 = a;
+    if (lt32)
+        lockstep_lower<uint32_t, NB, true>(lt32, a, b, x, r.p, nk, kx[j0], le[j0], q0);
+    else
+        lockstep_lower<int64_t, NB, true>(sel2(G.lt, dir), a, b, x, r.p, nk, kx[j0], le[j0], q0);
+    r.q[j0] = q0;
     sfor<1, NB>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         constexpr int jk = bound_rank<Kind>(k), jp = bound_rank<Kind>(k - 1);
