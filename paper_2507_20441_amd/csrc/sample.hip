@@ -738,10 +738,17 @@ __device__ __forceinline__ u128 completions(const SampleArgs& a, const SampleArg
 // at its parent's list position instead of searched for.
 // kSmall: trees of at most four edges and motifs of at most five vertices,
 // so that fewer register slots are live (more waves per SIMD).
-template <typename W, bool kCount, bool kGeneral, bool kSorted, bool kWin = false, bool kSmall = false>
+// kNarrow (W = u128 only): a widened set whose list tables stayed 64-bit;
+// its child masses fit 64 bits, so the child picks run in 64-bit arithmetic
+// (the same draws: floor(X n / 2^128) does not depend on the width n is
+// held in), and only the root draw is 128-bit.
+template <typename W, bool kCount, bool kGeneral, bool kSorted, bool kWin = false, bool kSmall = false,
+          bool kNarrow = false>
 __device__ __forceinline__ void sample_positions(const SampleArgs& a, const SampleArgs& ga, const W* cum, u64 x0,
                                                  u64 xend, u64 stride, LaneAcc& L) {
     static_assert(kSorted || !kWin, "windows are read by list position");
+    static_assert(!kNarrow || sizeof(W) == 16, "only a 128-bit set has narrower list tables");
+    using WC = typename std::conditional<kNarrow, u64, W>::type;  // child-pick arithmetic
     constexpr int NT = kSmall ? 4 : kMaxSlots - 1;  // register slots; a.nt of them are used
     constexpr int K = kSmall ? 5 : TM_MAX_K;         // motif vertices held
     const DevGraph& G = a.G;
@@ -824,11 +831,11 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const Samp
             if (!a.exclude) w.q1 = w.q0;  // constraint 2 off: nothing excluded
             last = w;
             const bool leaf = a.leaf[s] != 0;
-            const ListTab<W> qt{a.qt[s][par], a.list_wide != 0, a.qtc[s][par], kCoarseBits};
-            const ListTab<W> qn{a.qn[s][par], a.list_wide != 0};
-            W bt0 = 0, bn0 = 0, mass;
+            const ListTab<WC> qt{a.qt[s][par], !kNarrow && a.list_wide != 0, a.qtc[s][par], kCoarseBits};
+            const ListTab<WC> qn{a.qn[s][par], !kNarrow && a.list_wide != 0};
+            WC bt0 = 0, bn0 = 0, mass;
             if (leaf) {
-                mass = (W)((w.p1 - w.p0) - (w.q1 - w.q0));
+                mass = (WC)((w.p1 - w.p0) - (w.q1 - w.q0));
             } else {
                 bt0 = qt[w.p0];
                 bn0 = qn[w.q0];
@@ -836,7 +843,7 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const Samp
             }
             // a child of a positive-weight match always has positive mass
             if (mass == 0 || w.p1 <= w.p0) { bad = true; break; }
-            const W rr = scale(draw_block(a.seed, j, (uint32_t)s), mass);
+            const WC rr = scale(draw_block(a.seed, j, (uint32_t)s), mass);
             // J: excluded entries whose preceding candidate mass is <= rr
             const int32_t* xref = G.nxref[d];
             int32_t jb = w.q0, jn = w.q1 - w.q0;
@@ -845,12 +852,12 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const Samp
                     const int32_t h = jn >> 1;
                     const int32_t mid = jb + h;
                     const int32_t xp = xref[mid];
-                    const W F = leaf ? (W)((xp - w.p0) - (mid - w.q0)) : (qt[xp] - bt0) - (qn[mid] - bn0);
+                    const WC F = leaf ? (WC)((xp - w.p0) - (mid - w.q0)) : (qt[xp] - bt0) - (qn[mid] - bn0);
                     jb = F <= rr ? mid : jb;
                     jn -= h;
                 }
                 const int32_t xp = xref[jb];
-                const W F = leaf ? (W)((xp - w.p0) - (jb - w.q0)) : (qt[xp] - bt0) - (qn[jb] - bn0);
+                const WC F = leaf ? (WC)((xp - w.p0) - (jb - w.q0)) : (qt[xp] - bt0) - (qn[jb] - bn0);
                 jb += F <= rr ? 1 : 0;
             }
             const int32_t J = jb - w.q0;
@@ -858,7 +865,7 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const Samp
             if (leaf) {
                 pos = w.p0 + (int32_t)rr + J;
             } else {
-                const W tgt = bt0 + rr + (qn[w.q0 + J] - bn0);
+                const WC tgt = bt0 + rr + (qn[w.q0 + J] - bn0);
                 pos = qt.upper_bound_coarse(w.p0 + 1, w.p1 + 1, tgt) - 1;
             }
             pos = pos < w.p0 ? w.p0 : (pos >= w.p1 ? w.p1 - 1 : pos);
@@ -998,7 +1005,7 @@ __device__ __forceinline__ void lanes_reduce(const LaneAcc& L, Partial* out, int
     if (L.bad) atomicOr(ovf, 2);
 }
 
-template <typename W, bool kCount, bool kGeneral, bool kSorted, bool kWin, bool kSmall = false>
+template <typename W, bool kCount, bool kGeneral, bool kSorted, bool kWin, bool kSmall = false, bool kNarrow = false>
 __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
     extern __shared__ unsigned char lds_raw[];
     const W* cumG = static_cast<const W*>(a.cumW);
@@ -1021,10 +1028,10 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(SampleArgs a) {
         __shared__ SampleArgs s_args;
         if (threadIdx.x == 0) s_args = a;
         __syncthreads();
-        sample_positions<W, kCount, kGeneral, kSorted, kWin, kSmall>(
+        sample_positions<W, kCount, kGeneral, kSorted, kWin, kSmall, kNarrow>(
             a, s_args, cum, (u64)blockIdx.x * kBlock + threadIdx.x, a.count, (u64)gridDim.x * kBlock, L);
     } else {
-        sample_positions<W, kCount, kGeneral, kSorted, kWin, kSmall>(
+        sample_positions<W, kCount, kGeneral, kSorted, kWin, kSmall, kNarrow>(
             a, a, cum, (u64)blockIdx.x * kBlock + threadIdx.x, a.count, (u64)gridDim.x * kBlock, L);
     }
     lanes_reduce(L, &a.parts[blockIdx.x], a.ovf);
@@ -1061,6 +1068,10 @@ SampleKernel sample_variant(const SampleArgs& a) {
     if constexpr (kSorted) {
         if (a.has_win && !a.general_runs && a.nt <= 4 && a.k <= 5)
             return sample_kernel<W, kCount, false, true, true, true>;
+        if constexpr (sizeof(W) == 16) {
+            if (a.has_win && !a.general_runs && !a.list_wide)
+                return sample_kernel<W, kCount, false, true, true, false, true>;
+        }
         if (a.has_win)
             return a.general_runs ? sample_kernel<W, kCount, true, true, true>
                                   : sample_kernel<W, kCount, false, true, true>;

@@ -292,8 +292,9 @@ def test_widened_set_keeps_64_bit_list_tables(T):
     """A path center -> middle -> five leaves on a hub of 5,000 out-edges:
     the middle edge's weights (5000^5 each) and its list totals fit 64 bits,
     the center's total W does not.  The set is widened without a second level
-    launch; its list tables stay 64-bit while the sampler runs in 128 bits,
-    and every weight, record and sum equals the oracle's."""
+    launch; its list tables stay 64-bit while the sampler draws the root in
+    128 bits (and, in the root-sorted shape, picks the children in 64), and
+    every weight, record and sum equals the oracle's."""
     hub = 5000
     src = np.concatenate([np.arange(10, 20), np.full(2, 1), np.full(hub, 2)]).astype(np.int32)
     dst = np.concatenate([np.full(10, 1), np.full(2, 2), np.arange(100, 100 + hub)]).astype(np.int32)
@@ -305,6 +306,7 @@ def test_widened_set_keeps_64_bit_list_tables(T):
     otr = O.make_tree(list(range(len(edges))), 0)
     say("widened list tables")
     P, Wt = check_prep(T, og, tg, edges, delta, otr, seeds=(1, 2), k=4000)
+    check_prep(T, og, tg, edges, delta, otr, seeds=(3,), k=70000)  # root-sorted, kept windows
     info = Wt.info()
     assert P.W >= 2**64 and info["wide"]
     _, tmo = motifs_for(T, edges, delta)
