@@ -10,8 +10,8 @@
  * All counts and weights are exact unsigned 128-bit integers; any value that
  * would reach 2^128 makes the call return OR_EOVERFLOW.
  *
- * Semantics (each reading of the paper is listed with its justification in
- * the design notes of the repository):
+ * Semantics (where the paper leaves a choice, the reading taken is stated
+ * here with the passage it rests on):
  *   - timestamps are shifted so the smallest is 0 (Sec. 4, storage paragraph);
  *   - the canonical edge id (eid) is the rank under the key (t, u, v);
  *   - intervals I_i = [i*delta, (i+2)*delta), i = 0 .. q-1, q = floor(T/delta)+1

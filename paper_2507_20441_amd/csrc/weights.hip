@@ -95,7 +95,8 @@ struct BoundsN {
 // is searched over the list and the others are reached by galloping from it:
 // they lie in that neighbour's run, a few entries on.  (A variant in which a
 // wave walking one list staged each bound's segment in LDS after two
-// wave-uniform searches was measured slower: see the design notes.)  Every
+// wave-uniform searches was measured slower than these per-lane searches,
+// which mostly hit lines their neighbours fetched.)  Every
 // bound is the first position whose key is >= x (BoundsN above).
 // ---------------------------------------------------------------------------
 
@@ -348,8 +349,21 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
         }
         if (a.win[c][0]) {
             const int64_t at = a.win_dir == a.walk ? p : (int64_t)sel2(G.tpos, a.win_dir)[e];
-            sel2(a.win[c], parA)[2 * at] = make_int4(r.p[0], r.p[2], r.q[0], r.q[2]);
-            sel2(a.win[c], parB)[2 * at] = hasB ? make_int4(r.p[1], r.p[3], r.q[1], r.q[3]) : make_int4(0, 0, 0, 0);
+            if (a.win_dir == a.walk) {
+                // consecutive lanes fill whole lines: past the caches, so that
+                // the stream of records does not evict the lines the searches
+                // reuse (scattered records stay cached writes: one by one
+                // they cost more in HBM than the eviction does)
+                typedef int v4i __attribute__((ext_vector_type(4)));
+                const v4i va = {r.p[0], r.p[2], r.q[0], r.q[2]};
+                const v4i vb = hasB ? v4i{r.p[1], r.p[3], r.q[1], r.q[3]} : v4i{0, 0, 0, 0};
+                __builtin_nontemporal_store(va, reinterpret_cast<v4i*>(sel2(a.win[c], parA) + 2 * at));
+                __builtin_nontemporal_store(vb, reinterpret_cast<v4i*>(sel2(a.win[c], parB) + 2 * at));
+            } else {
+                sel2(a.win[c], parA)[2 * at] = make_int4(r.p[0], r.p[2], r.q[0], r.q[2]);
+                sel2(a.win[c], parB)[2 * at] =
+                    hasB ? make_int4(r.p[1], r.p[3], r.q[1], r.q[3]) : make_int4(0, 0, 0, 0);
+            }
         }
         const W xa = window_mass<W>(r.p[0], r.p[2], r.q[0], r.q[2], d.leaf, sel2(d.qt, parA), sel2(d.qn, parA));
         const W xb = hasB ? window_mass<W>(r.p[1], r.p[3], r.q[1], r.q[3], d.leaf, sel2(d.qt, parB), sel2(d.qn, parB)) : (W)0;
