@@ -48,8 +48,12 @@ struct SampleArgs {
     int list_wide;  // the list tables hold 128-bit entries (else 64-bit, also under W = u128)
     const void* qtc[kMaxSlots][2];  // every 2^kCoarseBits-th entry of each qt table
     // kept child windows (see weights): parity par of the parent at list
-    // position x is win[s][par][2 x] (the parities interleave)
+    // position x is win[s][par][2 x] (the parities interleave), x the
+    // parent's position in the T order of the list slot s attaches to
+    // (side[s]); win_from[s]: the list the parent is drawn from, so that
+    // when the two differ the parent's position is looked up (leid, tpos)
     const int4* win[kMaxSlots][2];
+    int win_from[kMaxSlots];
     int has_win;
     int root_dir;  // the list whose T positions key the root (0: out-lists, 1: in-lists)
     const void* qc[2];
@@ -819,7 +823,15 @@ __device__ __forceinline__ void sample_positions(const SampleArgs& a, const Samp
             if (a.same_window[s]) {
                 w = last;
             } else if constexpr (kWin) {
-                const int4 b = a.win[s][par][2 * (int64_t)pick(posv, a.parent[s])];
+                int32_t wx = pick(posv, a.parent[s]);
+                if (a.win_from[s] != a.side[s]) {
+                    // the parent was drawn from its other list: its position
+                    // in the list the windows follow, through its eid
+                    const int32_t pe = G.leid[a.win_from[s]][wx];
+                    wx = G.tpos[a.side[s]][pe];
+                    if constexpr (kCount) nb += 8;
+                }
+                const int4 b = a.win[s][par][2 * (int64_t)wx];
                 w.p0 = b.x;
                 w.p1 = b.y;
                 w.q0 = b.z;
@@ -1196,6 +1208,8 @@ void fill_args(const tm_weights* w, SampleArgs* out, size_t* lds_out) {
             a.qtc[s][par] = w->qtc[s][par];
             a.win[s][par] = w->win[s][par];
         }
+        // the list slot s's parent is drawn from (the root list for the center)
+        if (s > 0) a.win_from[s] = P.parent[s] == 0 ? P.root_dir : (P.alpha[P.parent[s]] > 0 ? 0 : 1);
     }
     a.has_win = w->has_win ? 1 : 0;
     a.list_wide = w->list_wide ? 1 : 0;

@@ -190,9 +190,10 @@ struct tm_weights {
     void* vals[kMaxSlots][2] = {};  // build temporaries (both parities interleaved in vals[s][0]), null afterwards
     // child windows, per non-center slot and interval parity: the slot's
     // candidate window (p0, p1, q0, q1) for every edge its parent can match,
-    // by that edge's position x in the list the parent is drawn from (the
-    // root list's T order for the center, see HostPlan::root_dir); null when
-    // not kept.  The two parities interleave, one 32-byte record per edge:
+    // by that edge's position x in the T order of the list the slot attaches
+    // to (out-lists for a slot at its parent's source, in-lists at its
+    // destination: the order the level kernel walks); null when not kept.
+    // The two parities interleave, one 32-byte record per edge:
     // parity par's window of position x is win[s][par][2 x] (win[s][1] is
     // win[s][0] + 1).
     int4* win[kMaxSlots][2] = {};

@@ -44,8 +44,7 @@ struct LevelArgs {
     int nc;
     ChildDesc c[kMaxSlots];
     int walk;          // -1: eid order; 0 / 1: the T order of the out- / in-lists
-    int4* win[kMaxSlots][2];  // per child and parity: its windows, stride 2 (null: not kept)
-    int win_dir;       // the list whose T positions index the windows
+    int4* win[kMaxSlots][2];  // per child and parity: its windows, stride 2, by walk position (null: not kept)
     void* out[2];      // per parity (interleaved, stride 2): by eid, or by T position in list out_pos_dir
     int out_pos_dir;   // first of two passes: its own walk (consecutive writes), else -1
     const void* in[2]; // second of two passes: the first pass's products ...
@@ -343,27 +342,19 @@ __device__ __forceinline__ u64 level_edge(const LevelArgs& a, int64_t p) {
             }
         }
         if constexpr (kCount) {
-            if (a.win[c][0]) nb += 32 + (a.win_dir == a.walk ? 0 : 4);
+            if (a.win[c][0]) nb += 32;
             // the prefix reads of the two windows' masses (below)
             if (!d.leaf) nb += (r.p[2] > r.p[0] ? 4 * sizeof(W) : 0) + (hasB && r.p[3] > r.p[1] ? 4 * sizeof(W) : 0);
         }
         if (a.win[c][0]) {
-            const int64_t at = a.win_dir == a.walk ? p : (int64_t)sel2(G.tpos, a.win_dir)[e];
-            if (a.win_dir == a.walk) {
-                // consecutive lanes fill whole lines: past the caches, so that
-                // the stream of records does not evict the lines the searches
-                // reuse (scattered records stay cached writes: one by one
-                // they cost more in HBM than the eviction does)
-                typedef int v4i __attribute__((ext_vector_type(4)));
-                const v4i va = {r.p[0], r.p[2], r.q[0], r.q[2]};
-                const v4i vb = hasB ? v4i{r.p[1], r.p[3], r.q[1], r.q[3]} : v4i{0, 0, 0, 0};
-                __builtin_nontemporal_store(va, reinterpret_cast<v4i*>(sel2(a.win[c], parA) + 2 * at));
-                __builtin_nontemporal_store(vb, reinterpret_cast<v4i*>(sel2(a.win[c], parB) + 2 * at));
-            } else {
-                sel2(a.win[c], parA)[2 * at] = make_int4(r.p[0], r.p[2], r.q[0], r.q[2]);
-                sel2(a.win[c], parB)[2 * at] =
-                    hasB ? make_int4(r.p[1], r.p[3], r.q[1], r.q[3]) : make_int4(0, 0, 0, 0);
-            }
+            // at the parent's walk position: consecutive lanes fill whole
+            // lines, written past the caches so that the stream of records
+            // does not evict the lines the searches reuse
+            typedef int v4i __attribute__((ext_vector_type(4)));
+            const v4i va = {r.p[0], r.p[2], r.q[0], r.q[2]};
+            const v4i vb = hasB ? v4i{r.p[1], r.p[3], r.q[1], r.q[3]} : v4i{0, 0, 0, 0};
+            __builtin_nontemporal_store(va, reinterpret_cast<v4i*>(sel2(a.win[c], parA) + 2 * p));
+            __builtin_nontemporal_store(vb, reinterpret_cast<v4i*>(sel2(a.win[c], parB) + 2 * p));
         }
         const W xa = window_mass<W>(r.p[0], r.p[2], r.q[0], r.q[2], d.leaf, sel2(d.qt, parA), sel2(d.qn, parA));
         const W xb = hasB ? window_mass<W>(r.p[1], r.p[3], r.q[1], r.q[3], d.leaf, sel2(d.qt, parB), sel2(d.qn, parB)) : (W)0;
@@ -686,12 +677,13 @@ int build_typed(tm_weights* w, hipStream_t st, int* ovf, int* ovf_c, bool check_
                             }
                         }
                     }
-                    a.win_dir = s == 0 ? P.root_dir : (P.alpha[s] > 0 ? 0 : 1);
                 }
                 // each pass walks the list its children attach to, so that
                 // neighbouring lanes search one list (the center's root list
                 // is that list too when all its children attach at one end);
-                // search locality outweighs scattered window writes
+                // the kept windows are written in that walk order, and the
+                // sampler finds a parent's walk position through tpos when it
+                // drew the parent from the other list
                 a.walk = a.nc == 0 ? -1 : side;
                 for (int par = 0; par < 2; ++par) {
                     a.out[par] = ((two && pass == 0) ? tmp : static_cast<W*>(w->vals[s][0])) + par;

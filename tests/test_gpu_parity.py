@@ -609,9 +609,9 @@ def test_level_model_bytes_two_passes(T):
     tree centred on b->c, whose leaf children attach at both ends.  Pass 0
     walks the out-lists (child a->b: the in-list of e's source, L0 entries);
     pass 1 walks the in-lists (child c->d: the out-list of e's destination,
-    L1 entries), reads the first pass's products through the position index
-    (4 B, 8 B per interval of e: two unless e lies in the first block) and
-    writes its windows at out-list positions (4 B more).  List times are
+    L1 entries) and reads the first pass's products through the position
+    index (4 B, 8 B per interval of e: two unless e lies in the first
+    block); each pass writes its windows at its own walk positions.  List times are
     4 B here (every shifted time is below 2^32 - 1)."""
     say("level model bytes, two passes")
     delta = 3600
@@ -636,6 +636,6 @@ def test_level_model_bytes_two_passes(T):
     L1 = np.bincount(src, minlength=g.n)[dst]
     has_b = (t // delta) >= 1
     pass0 = 16 + 8 + 36 * (steps(L0) + (L0 > 0)) + 32 + 16
-    pass1 = 16 + 4 + 8 * (1 + has_b) + 8 + 36 * (steps(L1) + (L1 > 0)) + 36 + 16
+    pass1 = 16 + 4 + 8 * (1 + has_b) + 8 + 36 * (steps(L1) + (L1 > 0)) + 32 + 16
     expect = int(np.sum(pass0 + pass1))
     assert got == expect, (got, expect)
