@@ -8,21 +8,25 @@ it can compute one by one, and the rest is checked by properties:
 * CSR: edges in (time, src, dst) order, the same multiset as generated,
   every vertex list exactly its edges in eid order;
 * weights: w_i(s, e) only depends on G_i (every candidate of an edge in I_i
-  lies in I_i), so the oracle recomputes sampled weights on the slice G_i
-  alone (times shifted so that I_i becomes its first interval, eids offset by
-  the first eid of I_i) with its table-free recursive rule;
+  lies in I_i), so the oracle works on the slice G_i alone (times shifted so
+  that I_i becomes its first interval, eids offset by the first eid of I_i):
+  sampled weights by its table-free recursive rule, and for two whole
+  intervals its full tables against every weight of I_i;
 * interval totals W_i: exact sums of the exported center weights;
 * samples: a window of per-sample records from the root-sorted path is
   re-derived on the host from the definitions -- the root pair from Philox
   draw 0 over the (interval, eid) prefix, each child by inverse CDF over its
   candidate list (window of the shared vertex's list clipped to I_i, minus
   the excluded far endpoint) with draw index = pre-order slot -- and the
-  validation cause and N_phi recomputed; M_phi of valid samples comes from
-  the oracle on a time slice holding every edge within delta of the sample;
+  validation cause and N_phi recomputed (records of the two whole intervals
+  among them, so that their picks rest on oracle-fixed weights); M_phi of
+  valid samples comes from the oracle on a time slice holding every edge
+  within delta of the sample;
 * sums: a window's accumulators equal the sums over its records, and the
   full run equals the sum of its two halves.
 """
 import itertools
+import time
 
 import numpy as np
 import pytest
@@ -38,8 +42,11 @@ SEED = 1
 M32 = np.uint64(0xFFFFFFFF)
 
 
+_T0 = time.monotonic()
+
+
 def say(*a):
-    print("[gpu-large]", *a, flush=True)
+    print("[gpu-large] %.1fs" % (time.monotonic() - _T0), *a, flush=True)
 
 
 @pytest.fixture(scope="module")
@@ -237,7 +244,34 @@ def test_large_weights_and_samples(T, large, name):
     slot_of = {s: x for x, (s, _, _) in enumerate(slots)}
     kverts = 1 + max(max(e) for e in edges)
     lists = {0: (H["out_off"], H["out_eid"]), 1: (H["in_off"], H["in_eid"])}
+    # whole intervals: for the two intervals holding the most records of the
+    # window (slices of at most 7e5 edges), the oracle's full weight tables
+    # on G_i against every exported s-weight of I_i; the records of those
+    # intervals are then re-derived below from weights the oracle fixed
+    ivs, cnts = np.unique(recs["interval"], return_counts=True)
+    full_iv = [int(i) for i in ivs[np.argsort(-cnts, kind="stable")] if ihi[i] - ilo[i] <= 700_000][:2]
+    for i in full_iv:
+        og, e0 = slice_graph(H, i * DELTA, (i + 2) * DELTA)
+        assert e0 == ilo[i] and og.m == ihi[i] - ilo[i]
+        F = O.Prep(og, O.make_motif(edges, DELTA), O.make_tree(list(tr.edge[:tr.n_edges]), tr.center))
+        assert F.interval_weights()[0] == Wi[i], i
+        ids = np.arange(ilo[i], ihi[i])
+        # interval 0 of the slice is I_i; the oracle keeps w_0 of an edge of
+        # its block b (of its own shifted times) in slot b
+        sb = (t[ilo[i]:ihi[i]] - i * DELTA - og.shift) // DELTA
+        assert sb.min() >= 0 and sb.max() <= 1
+        for s in nonleaf:
+            o0, o1 = F.weights(s, 0), F.weights(s, 1)
+            lo, hi = slot_weights(exp[s], ids, blk, i)
+            assert np.array_equal(np.where(sb == 0, o0["lo"], o1["lo"]), lo), (i, s)
+            assert np.array_equal(np.where(sb == 0, o0["hi"], o1["hi"]), hi), (i, s)
+        del F, og
+    say(name, "intervals with every weight oracle-checked", full_iv,
+        [int(ihi[i] - ilo[i]) for i in full_iv])
+    assert len(full_iv) == 2
     pick_idx = rng.choice(CNT, size=250, replace=False)
+    in_full = np.nonzero(np.isin(recs["interval"], full_iv))[0][:200]
+    pick_idx = np.union1d(pick_idx, in_full)
     slices = {}
     n_valid_checked = 0
     for x in pick_idx:
@@ -309,5 +343,7 @@ def test_large_weights_and_samples(T, large, name):
                                          np.int32))
             assert mphi == (int(r["m_lo"]) | (int(r["m_hi"]) << 64)), j
             n_valid_checked += 1
-    say(name, "records re-derived", len(pick_idx), "valid", n_valid_checked)
+    say(name, "records re-derived", len(pick_idx), "of them in oracle-checked intervals", in_full.size,
+        "valid", n_valid_checked)
+    assert in_full.size >= 100
     w.close()
