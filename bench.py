@@ -10,10 +10,10 @@ Workload: 2,000,000 vertices, 100,000,000 edges (90M Chung-Lu gamma 2.0 +
 3e7 s, drawn on the device); scatter-gather and 6-chain at delta 86,400 s;
 10^8 samples per motif, seed 1 (the 6-chain's weights need 128 bits).
 
-The same JSON line carries: the roofline of the dominant kernel (the level
-kernels of the weight builds: their access-model bytes per launch over the
-average launch from HIP events in the timed region) and of the sampler, the
-graph build and the root draws; the oracle's single-thread CPU throughput on
+The same JSON line carries: the roofline of the dominant kernel (the
+sampler: its access-model bytes per launch over the average launch from HIP
+events in the timed region) and of the level kernels of the weight builds,
+the graph build and the root draws; the oracle's single-thread CPU throughput on
 a bounded slice of the same workload; the batched-queue against one job per
 launch (64 jobs); the serving loop's p50/p99 latency on a short Poisson
 stream; and the medium workload's rate and sampler roofline.
