@@ -423,10 +423,18 @@ __device__ __forceinline__ void sort_move_values(const void* vin, void* vout, bo
         const V* in = static_cast<const V*>(vin);
         V* out = static_cast<V*>(vout);
         V x[kSortItems];
+        const int64_t tbase = wbase - (int64_t)(threadIdx.x >> 6) * 64 * kSortItems;
+        if (!iota && tbase + kSortTile <= n) {
+            // a whole tile: one base address, the items at fixed offsets
+            const V* vp = in + wbase + lane;
 #pragma unroll
-        for (int k = 0; k < kSortItems; ++k) {
-            const int64_t i = wbase + (int64_t)k * 64 + lane;
-            x[k] = i < n ? (iota ? (V)i : in[i]) : (V)0;
+            for (int k = 0; k < kSortItems; ++k) x[k] = vp[k * 64];
+        } else {
+#pragma unroll
+            for (int k = 0; k < kSortItems; ++k) {
+                const int64_t i = wbase + (int64_t)k * 64 + lane;
+                x[k] = i < n ? (iota ? (V)i : in[i]) : (V)0;
+            }
         }
         __syncthreads();  // the buffer's previous contents have gone out
 #pragma unroll
@@ -450,7 +458,9 @@ sort_pass_kernel(SortIO io, int64_t n, int shift, int bits, uint32_t tag, int io
                                      std::max(SortSize<V1>::value, SortSize<V2>::value));
     __shared__ __align__(16) unsigned char sbuf[kElt * kSortTile];
     __shared__ uint8_t sdig[kSortTile];
-    __shared__ uint32_t cnt[kWaves][kSortDigits];
+    // per wave and digit: counts, then tile-local starts, at most kSortTile
+    // (16 bits keep a 64-bit-key pass within four workgroups' LDS per CU)
+    __shared__ uint16_t cnt[kWaves][kSortDigits];
     __shared__ uint32_t gofs[kSortDigits];  // per digit: its global position minus its tile-local one
     __shared__ uint32_t wsum[kWaves];
     __shared__ uint32_t s_tile;
@@ -468,18 +478,24 @@ sort_pass_kernel(SortIO io, int64_t n, int shift, int bits, uint32_t tag, int io
     const u64 lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const K* keys = static_cast<const K*>(io.in[0]);
     K key[kSortItems];
-    uint32_t dig[kSortItems], lp[kSortItems];
+    uint32_t lp[kSortItems];  // (the digits are recomputed from the keys: fewer registers)
+    if (tbase + kSortTile <= n) {
+        // a whole tile: one base address, the items at fixed offsets
+        const K* kp = keys + wbase + lane;
 #pragma unroll
-    for (int k = 0; k < kSortItems; ++k) {
-        const int64_t i = wbase + (int64_t)k * 64 + lane;
-        key[k] = i < n ? keys[i] : (K)0;
+        for (int k = 0; k < kSortItems; ++k) key[k] = kp[k * 64];
+    } else {
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            const int64_t i = wbase + (int64_t)k * 64 + lane;
+            key[k] = i < n ? keys[i] : (K)0;
+        }
     }
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t i = wbase + (int64_t)k * 64 + lane;
         const bool ok = i < n;
         const uint32_t d = ok ? ((uint32_t)(key[k] >> shift) & mask) : 0u;
-        dig[k] = d;
         u64 peers = __ballot(ok);
         for (int b = 0; b < bits; ++b) {
             const u64 bal = __ballot((d >> b) & 1u);
@@ -488,7 +504,7 @@ sort_pass_kernel(SortIO io, int64_t n, int shift, int bits, uint32_t tag, int io
         const uint32_t before = cnt[wave][d];
         lp[k] = before + (uint32_t)__popcll(peers & lt_mask);
         // the lowest lane of each digit group advances the wave's counter
-        if (ok && (peers & lt_mask) == 0) cnt[wave][d] = before + (uint32_t)__popcll(peers);
+        if (ok && (peers & lt_mask) == 0) cnt[wave][d] = (uint16_t)(before + (uint32_t)__popcll(peers));
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
@@ -510,7 +526,7 @@ sort_pass_kernel(SortIO io, int64_t n, int shift, int bits, uint32_t tag, int io
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) {
             const uint32_t c = cnt[w][d];
-            cnt[w][d] = run;
+            cnt[w][d] = (uint16_t)run;
             run += c;
         }
     }
@@ -520,10 +536,11 @@ sort_pass_kernel(SortIO io, int64_t n, int shift, int bits, uint32_t tag, int io
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t i = wbase + (int64_t)k * 64 + lane;
         if (i < n) {
-            const uint32_t p = cnt[wave][dig[k]] + lp[k];
+            const uint32_t dk = (uint32_t)(key[k] >> shift) & mask;  // the digit again
+            const uint32_t p = cnt[wave][dk] + lp[k];
             lp[k] = p;
             skey[p] = key[k];
-            sdig[p] = (uint8_t)dig[k];
+            sdig[p] = (uint8_t)dk;
         }
     }
     // look-back: the digit's count over all earlier tiles, kSortLook status
