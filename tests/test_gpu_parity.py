@@ -49,10 +49,12 @@ def rec_equal(a, b):
 # ---------------------------------------------------------------------------
 # CSR build
 # ---------------------------------------------------------------------------
-# the last two: 2 bn + bt > 64 (bn the vertex-id bits, bt the time bits), so
+# 4096 and 8192: whole sort tiles only (4096 keys), no ragged last tile; the
+# last two: 2 bn + bt > 64 (bn the vertex-id bits, bt the time bits), so
 # the canonical order takes two sorts (by (u, v), then by time), with an odd
 # and an even number of digit passes in the first
 @pytest.mark.parametrize("m,seed,n,span", [(1, 1, 2, 10), (777, 2, 40, 300), (5000, 3, 300, 20000),
+                                           (4096, 8, 500, 10**5), (8192, 9, 1500, 10**6),
                                            (40000, 4, 2000, 10**6), (30000, 6, 600_000, 2**30),
                                            (30000, 7, 3_000_000, 2**35)])
 def test_csr_matches_oracle(T, m, seed, n, span):
